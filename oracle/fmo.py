@@ -1,0 +1,446 @@
+"""FMO2 / FMO3 energies and the FMO2 analytic gradient (oracle).
+
+Passages followed:
+* fragment pair lists: a pair is a full SCC dimer when the closest
+  interatomic distance is below the cutoff, otherwise ES-DIM; a trimer is
+  computed when at least two of its three pairs pass the same test
+  (section "Computational Details" uses vdW-scaled radii; this build uses a
+  fixed closest-contact cutoff, 4 Angstrom by default);
+* embedding potential, eq. v_esp_matrix: each fragment sees
+  phi_s = sum_{K != I} sum_{t in K} gamma_st dq^K_t in its Fock matrix;
+* monomer self-consistency (section "FMO-xTB"): monomers are solved
+  repeatedly in the field of the others until all charges are converged
+  (Jacobi sweeps with fully converged inner SCC);
+* FMO2 energy, eq. fmo2-energy-components, with the embedding correction
+  eq. dimer_embedding_correction and the charge transfer eq. ddq_calc;
+  E_I, E_IJ are read as internal energies (embedding acts in the Fock matrix
+  only), the reading consistent with the printed Delta E^V and ES-DIM forms;
+* ES-DIM, eq. esdimer-energy: Delta E_IJ = dq^I gamma_IJ dq^J;
+* FMO3 energy, eqs. fmo3_energy, trimer_interaction_energy, trimer_embedding
+  (the embedding sum of E^V_{X,Y} read as K not in Y); an ES-DIM sub-pair
+  enters the trimer subtraction with its ES-DIM value;
+* FMO2 gradient, section "Analytic energy gradients": the explicit terms
+  eqs. pair_delta, ctij, esd_grad and the response through the Lagrangian
+  potential eq. esp_lagrangian.  The gradient is assembled from the identity
+      E = sum_I c_I E^emb_I + sum_SCC E^emb_IJ - sum_ESD dq^I gamma dq^J,
+      c_I = 1 - (number of SCC dimers containing I),
+  in which every E^emb_X is stationary in its own density, so the only
+  implicit dependence is through the monomer charges, whose energy
+  derivative is the potential v_K of eq. esp_lagrangian.  The charge response
+  is solved in shell-charge space (the shell-summed transition charges Q of
+  eq. lagrangian define the fragment susceptibility); this is equivalent to
+  the Z-vector equations eq. sczv and gives the Z-vector Z_ai, the AO
+  Z-density and the energy-weighted Z-density of eqs. Z_AO and WZ_def, which
+  enter the derivative contractions of eqs. ZxHB .. ZxG_inter and the
+  Mulliken (Lagrangian) term of eq. resp_addlag.
+"""
+
+import math
+
+import numpy as np
+
+from .xtb import (XtbSystem, coordination_numbers, cn_gradient, scc, gamma_matrix,
+                  gamma_deriv, system_gradient)
+
+
+def neumaier_sum(values):
+    s = 0.0
+    c = 0.0
+    for v in values:
+        v = float(v)
+        t = s + v
+        if abs(s) >= abs(v):
+            c += (s - t) + v
+        else:
+            c += (v - t) + s
+        s = t
+    return s + c
+
+
+# --------------------------------------------------------------------------
+# lists
+
+def fragment_atoms(frag, n_frag):
+    return [np.where(frag == I)[0] for I in range(n_frag)]
+
+
+def closest_contact_sq(xyz, atoms_i, atoms_j):
+    """Smallest squared interatomic distance between two atom sets, each term
+    formed as (dx*dx + dy*dy) + dz*dz in FP64 (no fused multiply-add)."""
+    a = xyz[atoms_i]
+    b = xyz[atoms_j]
+    dx = a[:, None, 0] - b[None, :, 0]
+    dy = a[:, None, 1] - b[None, :, 1]
+    dz = a[:, None, 2] - b[None, :, 2]
+    xx = dx * dx
+    yy = dy * dy
+    zz = dz * dz
+    d2 = xx + yy
+    d2 = d2 + zz
+    return float(d2.min())
+
+
+def build_lists(system, cutoff_bohr, order=2):
+    """SCC dimers, ES-DIM pairs (lexicographic, I < J) and, for order 3, the
+    trimers (I < J < K) with at least two SCC sub-pairs."""
+    fa = fragment_atoms(system.frag, system.n_frag)
+    F = system.n_frag
+    c2 = cutoff_bohr * cutoff_bohr
+    scc_pairs, esd_pairs = [], []
+    near = np.zeros((F, F), dtype=bool)
+    for I in range(F):
+        for J in range(I + 1, F):
+            if closest_contact_sq(system.xyz, fa[I], fa[J]) < c2:
+                scc_pairs.append((I, J))
+                near[I, J] = near[J, I] = True
+            else:
+                esd_pairs.append((I, J))
+    trimers = []
+    if order >= 3:
+        for I in range(F):
+            for J in range(I + 1, F):
+                for K in range(J + 1, F):
+                    if int(near[I, J]) + int(near[I, K]) + int(near[J, K]) >= 2:
+                        trimers.append((I, J, K))
+    return (np.array(scc_pairs, dtype=np.int32).reshape(-1, 2),
+            np.array(esd_pairs, dtype=np.int32).reshape(-1, 2),
+            np.array(trimers, dtype=np.int32).reshape(-1, 3))
+
+
+# --------------------------------------------------------------------------
+# the supersystem's shells
+
+class Shells:
+    """Global shell table: shells of atom 0, then atom 1, ...; per shell the
+    atom, its fragment and its hardness (1 + kappa) eta_A."""
+
+    def __init__(self, params, system):
+        self.p = params
+        at, eta = [], []
+        self.atom_sh0 = np.zeros(system.n_atoms + 1, dtype=np.int64)
+        for A, z in enumerate(system.Z):
+            e = params.element(int(z))
+            for sh in e["shells"]:
+                at.append(A)
+                eta.append((1.0 + sh["kappa"]) * e["eta"])
+            self.atom_sh0[A + 1] = len(at)
+        self.atom = np.array(at)
+        self.eta = np.array(eta)
+        self.frag = system.frag[self.atom]
+        self.xyz = system.xyz[self.atom]
+        self.n = len(at)
+
+    def of_atoms(self, atoms):
+        return np.concatenate([np.arange(self.atom_sh0[a], self.atom_sh0[a + 1]) for a in atoms])
+
+    def gamma_block(self, si, sj):
+        d = self.xyz[si][:, None, :] - self.xyz[sj][None, :, :]
+        R = np.sqrt(np.sum(d * d, axis=2))
+        return gamma_matrix(self.p, R, self.eta[si][:, None], self.eta[sj][None, :])
+
+    def potential(self, targets, q_all, exclude_mask_fn, chunk=4096):
+        """phi_s = sum_t gamma_st q_t over sources t allowed by the mask."""
+        out = np.zeros(len(targets))
+        src = np.arange(self.n)
+        for i0 in range(0, len(targets), chunk):
+            tg = targets[i0:i0 + chunk]
+            G = self.gamma_block(tg, src)
+            G = np.where(exclude_mask_fn(tg[:, None], src[None, :]), 0.0, G)
+            out[i0:i0 + chunk] = G @ q_all
+        return out
+
+
+def _system_for(params, system, cn, atoms, charge):
+    return XtbSystem(params, system.Z[atoms], system.xyz[atoms], cn[atoms], charge=charge)
+
+
+class FMOResult:
+    pass
+
+
+def fmo(system, params, cutoff_bohr, order=2, lists=None, scc_tol=1e-10,
+        macro_tol=1e-10, max_macro=200, verbose=False):
+    """FMO2 (order=2) or FMO3 (order=3) energy.  Returns an FMOResult with the
+    converged monomer, dimer and trimer results and the energy terms."""
+    F = system.n_frag
+    fa = fragment_atoms(system.frag, F)
+    cn = coordination_numbers(params, system.Z, system.xyz)
+    sh = Shells(params, system)
+    fsh = [sh.of_atoms(fa[I]) for I in range(F)]
+    if lists is None:
+        lists = build_lists(system, cutoff_bohr, order)
+    scc_pairs, esd_pairs, trimers = lists
+
+    mono = [_system_for(params, system, cn, fa[I], int(system.frag_charge[I])) for I in range(F)]
+    q = np.zeros(sh.n)   # superposition guess: zero shell charges
+    res = [None] * F
+    same_frag = lambda s, t: sh.frag[s] == sh.frag[t]
+    for it in range(1, max_macro + 1):
+        phi = sh.potential(np.arange(sh.n), q, same_frag)
+        qn = q.copy()
+        for I in range(F):
+            g = q[fsh[I]]
+            res[I] = scc(mono[I], phi[fsh[I]], q_guess=g, tol=scc_tol)
+            qn[fsh[I]] = res[I].q
+        delta = float(np.max(np.abs(qn - q)))
+        q = qn
+        if verbose:
+            print("macro", it, delta)
+        if delta < macro_tol:
+            break
+    out = FMOResult()
+    out.macro_iter = it
+    out.macro_converged = delta < macro_tol
+    # final embedding potential of every monomer (consistent with q)
+    phi = sh.potential(np.arange(sh.n), q, same_frag)
+    out.q = q
+    out.phi_mono = phi
+    out.cn = cn
+    out.mono = res
+    out.mono_sys = mono
+    out.frag_atoms = fa
+    out.frag_shells = fsh
+    out.shells = sh
+    out.lists = lists
+    out.E_mono = np.array([r.e_int for r in res])
+
+    def solve_cluster(frags):
+        atoms = np.concatenate([fa[I] for I in frags])
+        shl = np.concatenate([fsh[I] for I in frags])
+        inside = np.zeros(sh.n, dtype=bool)
+        inside[shl] = True
+        phiX = sh.potential(shl, np.where(inside, 0.0, q), lambda s, t: np.zeros_like(s, dtype=bool))
+        sysX = _system_for(params, system, cn, atoms,
+                           int(sum(system.frag_charge[I] for I in frags)))
+        rX = scc(sysX, phiX, q_guess=q[shl], tol=scc_tol)
+        ddq = rX.q - q[shl]
+        return sysX, rX, shl, ddq, float(ddq @ phiX)
+
+    out.dimers = []
+    dE_scc = np.zeros(len(scc_pairs))
+    for k, (I, J) in enumerate(scc_pairs):
+        sysX, rX, shl, ddq, dEV = solve_cluster((I, J))
+        dE_scc[k] = rX.e_int - res[I].e_int - res[J].e_int + dEV
+        out.dimers.append(dict(I=int(I), J=int(J), sys=sysX, res=rX, shells=shl,
+                               ddq=ddq, dEV=dEV))
+    dE_esd = np.zeros(len(esd_pairs))
+    for k, (I, J) in enumerate(esd_pairs):
+        dE_esd[k] = float(q[fsh[I]] @ sh.gamma_block(fsh[I], fsh[J]) @ q[fsh[J]])
+    out.dE_scc = dE_scc
+    out.dE_esd = dE_esd
+    out.E_fmo2 = neumaier_sum(list(out.E_mono) + list(dE_scc) + list(dE_esd))
+    out.E = out.E_fmo2
+    if order >= 3:
+        pair_dE = {}
+        for k, (I, J) in enumerate(scc_pairs):
+            pair_dE[(int(I), int(J))] = dE_scc[k]
+        for k, (I, J) in enumerate(esd_pairs):
+            pair_dE[(int(I), int(J))] = dE_esd[k]
+        out.trimers = []
+        dE_tri = np.zeros(len(trimers))
+        for k, (I, J, K) in enumerate(trimers):
+            sysX, rX, shl, ddq, dEV = solve_cluster((I, J, K))
+            dEIJK = rX.e_int - res[I].e_int - res[J].e_int - res[K].e_int + dEV
+            dE_tri[k] = dEIJK - pair_dE[(I, J)] - pair_dE[(I, K)] - pair_dE[(J, K)]
+            out.trimers.append(dict(IJK=(int(I), int(J), int(K)), res=rX, dEIJK=dEIJK))
+        out.dE_tri = dE_tri
+        out.E_fmo3 = neumaier_sum([out.E_fmo2] + list(dE_tri))
+        out.E = out.E_fmo3
+    return out
+
+
+# --------------------------------------------------------------------------
+# FMO2 gradient
+
+def _ds_matrix(sig_ao, P, Wt):
+    return 0.5 * (sig_ao[:, None] + sig_ao[None, :]) * P - Wt
+
+
+def _inter_gamma_force(sh, pair_weights, natoms):
+    """sum over listed shell pairs (s, t) of w_st d gamma_st / d R, as atom
+    forces; pair_weights: list of (si, tj, W) with W of shape (len si, len tj)."""
+    g = np.zeros((natoms, 3))
+    for si, tj, W in pair_weights:
+        d = sh.xyz[si][:, None, :] - sh.xyz[tj][None, :, :]
+        R = np.sqrt(np.sum(d * d, axis=2))
+        dg = gamma_deriv(sh.p, R, sh.eta[si][:, None], sh.eta[tj][None, :])
+        f = (W * dg / R)[:, :, None] * d          # d/dR_s of gamma_st (per pair)
+        np.add.at(g, sh.atom[si], f.sum(axis=1))
+        np.add.at(g, sh.atom[tj], -f.sum(axis=0))
+    return g
+
+
+def fmo2_gradient(system, params, res, with_response=True):
+    """Analytic FMO2 gradient (Eh/bohr, shape (natoms, 3)) for a converged
+    FMO2 result `res` (lists frozen)."""
+    sh = res.shells
+    F = system.n_frag
+    fa, fsh = res.frag_atoms, res.frag_shells
+    q = res.q
+    N = system.n_atoms
+    scc_pairs, esd_pairs, _ = res.lists
+    nscc = np.zeros(F)
+    for I, J in scc_pairs:
+        nscc[I] += 1
+        nscc[J] += 1
+    c = 1.0 - nscc
+
+    G = np.zeros((N, 3))
+    Fcn = np.zeros(N)
+    parts = {}
+
+    # explicit fragment terms: sum_X c_X g^emb_X (fixed CN), with sigma containing
+    # the embedding potential (eqs. xtb_grad, W_matrix, pair_delta)
+    gm = np.zeros((N, 3))
+    for I in range(F):
+        sx, r = res.mono_sys[I], res.mono[I]
+        DS = _ds_matrix(r.sigma[sx.ao_sh], r.P, r.Wt)
+        g, f = system_gradient(sx, r.P, DS, r.q, r.q, True)
+        gm[fa[I]] += c[I] * g
+        Fcn[fa[I]] += c[I] * f
+    for d in res.dimers:
+        sx, r = d["sys"], d["res"]
+        atoms = np.concatenate([fa[d["I"]], fa[d["J"]]])
+        DS = _ds_matrix(r.sigma[sx.ao_sh], r.P, r.Wt)
+        g, f = system_gradient(sx, r.P, DS, r.q, r.q, True)
+        gm[atoms] += g
+        Fcn[atoms] += f
+    parts["fragments"] = gm
+    G += gm
+
+    # ES-DIM (eq. esd_grad) and charge-transfer embedding (eq. ctij) terms
+    wl = []
+    for I, J in esd_pairs:
+        wl.append((fsh[I], fsh[J], np.outer(q[fsh[I]], q[fsh[J]])))
+    g_esd = _inter_gamma_force(sh, wl, N)
+    wl = []
+    for d in res.dimers:
+        I, J = d["I"], d["J"]
+        others = np.where((sh.frag != I) & (sh.frag != J))[0]
+        wl.append((d["shells"], others, np.outer(d["ddq"], q[others])))
+    g_ct = _inter_gamma_force(sh, wl, N)
+    parts["esd"] = g_esd
+    parts["ct"] = g_ct
+    G += g_esd + g_ct
+
+    if with_response:
+        g_resp, f_resp, info = _response(system, params, res, c)
+        G += g_resp
+        Fcn += f_resp
+        parts["response"] = g_resp
+        parts.update(info)
+
+    g_cn = cn_gradient(params, system.Z, system.xyz, Fcn)
+    parts["cn"] = g_cn
+    G += g_cn
+    return G, parts
+
+
+def lagrangian_potential(res):
+    """v_K on the shells of every monomer K: the potential of the charge
+    transfer of all SCC dimers not containing K (eq. esp_lagrangian)."""
+    sh = res.shells
+    v = np.zeros(sh.n)
+    for d in res.dimers:
+        I, J = d["I"], d["J"]
+        tg = np.where((sh.frag != I) & (sh.frag != J))[0]
+        v[tg] += sh.gamma_block(tg, d["shells"]) @ d["ddq"]
+    return v
+
+
+def _monomer_response_blocks(sx, r):
+    """Shell-summed transition charges Q_ai,s (eq. lagrangian), the
+    susceptibility kernel M = sum_ai Q Q^T / (eps_a - eps_i) and the charge
+    Hessian G = gamma - 2 Gamma_A dq_A (same-atom shell blocks)."""
+    occ_mask = r.occ > 1.0
+    Co = r.C[:, occ_mask]
+    Cv = r.C[:, ~occ_mask]
+    eo = r.eps[occ_mask]
+    ev = r.eps[~occ_mask]
+    SCo = sx.S @ Co
+    SCv = sx.S @ Cv
+    # per AO: C_mu,a (S C)_mu,i + C_mu,i (S C)_mu,a, summed over the AOs of a shell
+    T = Cv[:, :, None] * SCo[:, None, :] + SCv[:, :, None] * Co[:, None, :]   # (n, nv, no)
+    Q = np.zeros((sx.nsh, Cv.shape[1], Co.shape[1]))
+    np.add.at(Q, sx.ao_sh, T)
+    Q = Q.reshape(sx.nsh, -1)                                                   # (nsh, nv*no)
+    D = (ev[:, None] - eo[None, :]).reshape(-1)
+    M = (Q / D) @ Q.T
+    qa = sx.atom_sum(r.q)
+    Gm = sx.gamma.copy()
+    same = sx.sh_atom[:, None] == sx.sh_atom[None, :]
+    Gm -= np.where(same, 2.0 * (sx.at_Gamma * qa)[sx.sh_atom][:, None], 0.0)
+    return dict(Q=Q, D=D, M=M, G=Gm, Co=Co, Cv=Cv, eo=eo, ev=ev)
+
+
+def _response(system, params, res, c):
+    sh = res.shells
+    F = system.n_frag
+    fa, fsh = res.frag_atoms, res.frag_shells
+    N = system.n_atoms
+    q = res.q
+    v = lagrangian_potential(res)
+    blocks = [_monomer_response_blocks(res.mono_sys[I], res.mono[I]) for I in range(F)]
+    # susceptibility chi_K = -(1 + M G)^-1 M, block diagonal over fragments
+    ns = sh.n
+    chi = np.zeros((ns, ns))
+    for I in range(F):
+        b = blocks[I]
+        k = len(fsh[I])
+        chi[np.ix_(fsh[I], fsh[I])] = -np.linalg.solve(np.eye(k) + b["M"] @ b["G"], b["M"])
+    # inter-fragment Coulomb coupling
+    Goff = sh.gamma_block(np.arange(ns), np.arange(ns))
+    Goff[sh.frag[:, None] == sh.frag[None, :]] = 0.0
+    # adjoint of the monomer self-consistency: y = v + Goff chi y
+    y = np.linalg.solve(np.eye(ns) - Goff @ chi, v)
+    u = chi @ y
+    g = np.zeros((N, 3))
+    Fcn = np.zeros(N)
+    zinfo = []
+    for I in range(F):
+        sx, r, b = res.mono_sys[I], res.mono[I], blocks[I]
+        yI = y[fsh[I]]
+        w = np.linalg.solve(np.eye(len(yI)) + b["G"] @ b["M"], yI)
+        Z = (-2.0 * (w @ b["Q"]) / b["D"]).reshape(b["Cv"].shape[1], b["Co"].shape[1])
+        Zt = b["Cv"] @ Z @ b["Co"].T
+        Zb = 0.5 * (Zt + Zt.T)
+        WZ = b["Cv"] @ (Z * b["eo"][None, :]) @ b["Co"].T
+        WZs = 0.5 * (WZ + WZ.T)
+        QZ = np.bincount(sx.ao_sh, weights=np.sum(Zb * sx.S, axis=1), minlength=sx.nsh)
+        sig = r.sigma[sx.ao_sh]
+        wa = w[sx.ao_sh]
+        P = r.P
+        PSDP = P @ sx.S @ (wa[:, None] * P)
+        DS = (0.5 * (sig[:, None] + sig[None, :]) * Zb - WZs
+              + 0.5 * (wa[:, None] + wa[None, :]) * P - 0.25 * (PSDP + PSDP.T))
+        gI, fI = system_gradient(sx, Zb, DS, 2.0 * QZ, r.q, with_rep=False)
+        g[fa[I]] += gI
+        Fcn[fa[I]] += fI
+        zinfo.append(dict(Z=Z, w=w))
+    # inter-fragment kernel derivative with the response charges u
+    wl = []
+    for I in range(F):
+        for K in range(I + 1, F):
+            W = np.outer(u[fsh[I]], q[fsh[K]]) + np.outer(q[fsh[I]], u[fsh[K]])
+            wl.append((fsh[I], fsh[K], W))
+    g += _inter_gamma_force(sh, wl, N)
+    return g, Fcn, dict(v=v, y=y, u=u, zinfo=zinfo)
+
+
+# --------------------------------------------------------------------------
+# non-fragmented xTB of a whole system (reference for the exact special cases)
+
+def xtb_energy(system, params, tol=1e-11):
+    cn = coordination_numbers(params, system.Z, system.xyz)
+    sx = XtbSystem(params, system.Z, system.xyz, cn, charge=int(system.frag_charge.sum()))
+    r = scc(sx, tol=tol)
+    return r.e_int, sx, r
+
+
+def xtb_gradient(system, params, tol=1e-11):
+    """Analytic gradient of a non-fragmented xTB system (eq. xtb_grad)."""
+    e, sx, r = xtb_energy(system, params, tol)
+    DS = _ds_matrix(r.sigma[sx.ao_sh], r.P, r.Wt)
+    g, f = system_gradient(sx, r.P, DS, r.q, r.q, True)
+    g += cn_gradient(params, system.Z, system.xyz, f)
+    return e, g

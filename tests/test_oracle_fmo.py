@@ -1,0 +1,116 @@
+"""Pins of the oracle's FMO layer.
+
+* exact special cases of the many-body expansion (eqs. fmo2-energy-components,
+  fmo3_energy): one fragment equals non-fragmented xTB; two fragments joined by
+  an SCC dimer equal xTB of the union; three fragments with all pairs and the
+  trimer equal xTB of the union;
+* the energy identity E = sum c_I E^emb_I + sum_SCC E^emb_IJ - sum_ESD qγq
+  (the reading of E_I as an internal energy);
+* the SCC pair energy approaches its ES-DIM value as the pair separates;
+* the analytic FMO2 gradient (explicit + response) matches central finite
+  differences of the energy with the pair lists frozen, and the response term
+  matters (the paper's gradient-error table shows the same pattern);
+* the pair/trimer lists equal a brute-force classification.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import fmo as F
+import workloads as w
+
+A2B = w.ANGSTROM_TO_BOHR
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return w.water_cluster_cube()
+
+
+def test_one_fragment_is_xtb(params, c1):
+    s = c1.subset([3])
+    r = F.fmo(s, params, 4 * A2B)
+    assert abs(r.E - F.xtb_energy(s, params)[0]) < 1e-9
+
+
+def test_two_fragments_fmo2_exact(params, c1):
+    s = c1.subset([0, 1])
+    r = F.fmo(s, params, 100.0)
+    assert len(r.lists[0]) == 1
+    assert abs(r.E - F.xtb_energy(s, params)[0]) < 1e-9
+
+
+def test_three_fragments_fmo3_exact(params, c1):
+    s = c1.subset([0, 1, 2])
+    r = F.fmo(s, params, 100.0, order=3)
+    assert len(r.lists[2]) == 1
+    assert abs(r.E - F.xtb_energy(s, params)[0]) < 1e-9
+
+
+def test_energy_identity(params, c1):
+    s = c1.subset([0, 1, 2, 3, 4])
+    r = F.fmo(s, params, 4 * A2B)
+    assert len(r.lists[0]) > 0 and len(r.lists[1]) > 0
+    nscc = np.zeros(s.n_frag)
+    for I, J in r.lists[0]:
+        nscc[I] += 1
+        nscc[J] += 1
+    e = sum((1 - nscc[I]) * r.mono[I].e_emb for I in range(s.n_frag))
+    e += sum(d["res"].e_emb for d in r.dimers)
+    e -= float(np.sum(r.dE_esd))
+    assert abs(e - r.E) < 1e-10
+
+
+def test_separated_pair_limit(params):
+    diffs = []
+    for d in (4.0, 6.0, 9.0):
+        s = w.separated_water_pair(d)
+        scc = F.fmo(s, params, 1e3)   # treated as SCC dimer
+        esd = F.fmo(s, params, 0.0)   # treated as ES-DIM
+        diffs.append(abs(scc.E - esd.E))
+    assert diffs[0] > diffs[1] > diffs[2]
+    assert diffs[2] < 1e-6
+
+
+def test_lists_bruteforce(params, c1):
+    cut = 4 * A2B
+    scc, esd, tri = F.build_lists(c1, cut, order=3)
+    near = {}
+    for I in range(c1.n_frag):
+        for J in range(I + 1, c1.n_frag):
+            dmin = min(np.linalg.norm(c1.xyz[a] - c1.xyz[b])
+                       for a in np.where(c1.frag == I)[0] for b in np.where(c1.frag == J)[0])
+            near[(I, J)] = int(dmin < cut)
+    assert [tuple(p) for p in scc] == [k for k, v in near.items() if v]
+    assert [tuple(p) for p in esd] == [k for k, v in near.items() if not v]
+    exp_tri = [(I, J, K) for I in range(8) for J in range(I + 1, 8) for K in range(J + 1, 8)
+               if near[(I, J)] + near[(I, K)] + near[(J, K)] >= 2]
+    assert [tuple(t) for t in tri] == exp_tri
+
+
+def _fd(params, s, res, A, k, h=1e-4):
+    out = []
+    for sg in (+1, -1):
+        sp = w.System(s.name, s.Z, s.xyz.copy(), s.frag, s.frag_charge)
+        sp.xyz[A, k] += sg * h
+        out.append(F.fmo(sp, params, 0.0, lists=res.lists, scc_tol=1e-12, macro_tol=1e-12).E)
+    return (out[0] - out[1]) / (2 * h)
+
+
+def test_fmo2_gradient_fd(params, c1):
+    s = c1.subset([0, 1, 2, 3])
+    r = F.fmo(s, params, 4 * A2B, scc_tol=1e-12, macro_tol=1e-12)
+    assert len(r.lists[0]) > 0 and len(r.lists[1]) > 0
+    g, _ = F.fmo2_gradient(s, params, r)
+    g0, _ = F.fmo2_gradient(s, params, r, with_response=False)
+    err, err0 = [], []
+    for A in range(s.n_atoms):
+        for k in range(3):
+            fd = _fd(params, s, r, A, k)
+            err.append(fd - g[A, k])
+            err0.append(fd - g0[A, k])
+    err, err0 = np.abs(err), np.abs(err0)
+    assert err.max() < 2e-8
+    assert err0.max() > 1e-6          # the response term is needed
+    assert np.max(np.abs(g.sum(0))) < 1e-10
+    assert np.max(np.abs(np.cross(s.xyz, g).sum(0))) < 1e-9

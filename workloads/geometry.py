@@ -1,0 +1,360 @@
+"""Seeded synthetic molecular systems shaped like the paper's workloads.
+
+The paper's own structures (packmol water clusters, anthracene and pentacene
+clusters cut from crystal structures; "Computational Details") are not
+available, so these generators build stand-ins with the same composition,
+size and packing.  Every generator is deterministic in its seed
+(``numpy.random.Generator(PCG64(seed))``).  Coordinates are returned in bohr.
+Fragmentation is one molecule per fragment, as in the paper's benchmarks
+("Energy accuracy").
+"""
+
+import json
+import math
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+ANGSTROM_TO_BOHR = 1.0 / 0.529177210903
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def params_path():
+    return os.path.join(_HERE, "gfn1_like.json")
+
+
+def load_params_json(path=None):
+    with open(path or params_path()) as f:
+        return json.load(f)
+
+
+@dataclass
+class System:
+    name: str
+    Z: np.ndarray            # int32 [N] atomic numbers
+    xyz: np.ndarray          # float64 [N, 3] bohr
+    frag: np.ndarray         # int32 [N] fragment index of each atom
+    frag_charge: np.ndarray  # int32 [F] net charge of each fragment
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_atoms(self):
+        return int(self.Z.shape[0])
+
+    @property
+    def n_frag(self):
+        return int(self.frag_charge.shape[0])
+
+    def subset(self, frags):
+        """System made of the listed fragments (renumbered 0..k-1, atoms kept in
+        ascending global order)."""
+        frags = list(frags)
+        mask = np.isin(self.frag, frags)
+        remap = {f: i for i, f in enumerate(frags)}
+        return System(
+            name=f"{self.name}[{','.join(map(str, frags))}]",
+            Z=self.Z[mask].copy(), xyz=self.xyz[mask].copy(),
+            frag=np.array([remap[f] for f in self.frag[mask]], dtype=np.int32),
+            frag_charge=self.frag_charge[frags].copy(), meta=dict(self.meta))
+
+
+# --------------------------------------------------------------------------
+# small geometric helpers
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _random_rotation(rng):
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+        [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+        [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)],
+    ])
+
+
+def _axis_rotation(axis, ang):
+    axis = np.asarray(axis, float)
+    axis = axis / np.linalg.norm(axis)
+    K = np.array([[0, -axis[2], axis[1]], [axis[2], 0, -axis[0]],
+                  [-axis[1], axis[0], 0]])
+    return np.eye(3) + math.sin(ang) * K + (1 - math.cos(ang)) * (K @ K)
+
+
+def water_molecule():
+    """Rigid water in Angstrom: O at origin, O-H 0.9572, H-O-H 104.52 deg."""
+    r, th = 0.9572, math.radians(104.52)
+    return np.array([8, 1, 1], np.int32), np.array([
+        [0.0, 0.0, 0.0],
+        [r * math.sin(th / 2), 0.0, r * math.cos(th / 2)],
+        [-r * math.sin(th / 2), 0.0, r * math.cos(th / 2)],
+    ])
+
+
+def _min_d2(P, x):
+    if len(P) == 0:
+        return np.inf
+    return float(np.min(np.sum((np.asarray(P) - x) ** 2, 1)))
+
+
+def _water_ok(new, placed_O, placed_H):
+    """Contact rules: O-O >= 2.6, intermolecular H-H >= 1.5, O-H >= 1.4 (A)."""
+    O, H1, H2 = new
+    if _min_d2(placed_O, O) < 2.6 ** 2 or _min_d2(placed_H, O) < 1.4 ** 2:
+        return False
+    for h in (H1, H2):
+        if _min_d2(placed_H, h) < 1.5 ** 2 or _min_d2(placed_O, h) < 1.4 ** 2:
+            return False
+    return True
+
+
+def _place_waters(n, seed, sample_center, max_tries=2000000):
+    """Random sequential insertion with a 3.5 A spatial hash for the contact test."""
+    rng = _rng(seed)
+    Zw, Xw = water_molecule()
+    mols = []
+    cells = {}  # (i,j,k) -> list of (O or H tag, xyz)
+    tries = 0
+    cs = 3.5  # > 1.5 + 2 * 0.9572, so every possible contact is a neighbour cell
+    while len(mols) < n:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError(f"could not place {n} waters (placed {len(mols)})")
+        c = sample_center(rng)
+        R = _random_rotation(rng)
+        X = Xw @ R.T + c
+        key = tuple(np.floor(c / cs).astype(int))
+        nO, nH = [], []
+        for di in (-1, 0, 1):
+            for dj in (-1, 0, 1):
+                for dk in (-1, 0, 1):
+                    for tag, p in cells.get((key[0] + di, key[1] + dj, key[2] + dk), ()):
+                        (nO if tag == 8 else nH).append(p)
+        if not _water_ok(X, nO, nH):
+            continue
+        mols.append(X)
+        for tag, p in zip((8, 1, 1), X):
+            cells.setdefault(tuple(np.floor(c / cs).astype(int)), []).append((tag, p))
+    Z = np.tile(Zw, n).astype(np.int32)
+    xyz = np.concatenate(mols, 0)
+    frag = np.repeat(np.arange(n, dtype=np.int32), 3)
+    return Z, xyz, frag
+
+
+def water_cluster_cube(n=8, box=9.0, seed=1, name="water-cube"):
+    """n rigid waters, O uniform in a box^3 cube (Angstrom), random orientations."""
+    Z, xyz, frag = _place_waters(n, seed, lambda r: r.uniform(0.0, box, 3))
+    return System(name=f"{name}-{n}", Z=Z, xyz=xyz * ANGSTROM_TO_BOHR, frag=frag,
+                  frag_charge=np.zeros(n, np.int32),
+                  meta=dict(seed=seed, box_angstrom=box))
+
+
+def water_droplet(n=1024, radius=19.5, seed=2, name="water-droplet"):
+    """n rigid waters with O uniform inside a sphere of the given radius (A)."""
+    def sample(r):
+        while True:
+            p = r.uniform(-radius, radius, 3)
+            if p @ p <= radius * radius:
+                return p
+    Z, xyz, frag = _place_waters(n, seed, sample)
+    return System(name=f"{name}-{n}", Z=Z, xyz=xyz * ANGSTROM_TO_BOHR, frag=frag,
+                  frag_charge=np.zeros(n, np.int32),
+                  meta=dict(seed=seed, radius_angstrom=radius))
+
+
+def separated_water_pair(closest_angstrom, seed=11):
+    """Two waters whose closest interatomic distance is the given value (A)."""
+    rng = _rng(seed)
+    Zw, Xw = water_molecule()
+    A = Xw @ _random_rotation(rng).T
+    B0 = Xw @ _random_rotation(rng).T
+    d = rng.normal(size=3)
+    d /= np.linalg.norm(d)
+    # bisect the offset along d so that the closest contact equals the target
+    lo, hi = 0.0, closest_angstrom + 5.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        B = B0 + d * mid
+        dmin = np.min(np.linalg.norm(A[:, None, :] - B[None, :, :], axis=2))
+        if dmin < closest_angstrom:
+            lo = mid
+        else:
+            hi = mid
+    B = B0 + d * hi
+    Z = np.concatenate([Zw, Zw]).astype(np.int32)
+    xyz = np.concatenate([A, B]) * ANGSTROM_TO_BOHR
+    return System(name=f"water-pair-{closest_angstrom}", Z=Z, xyz=xyz,
+                  frag=np.array([0, 0, 0, 1, 1, 1], np.int32),
+                  frag_charge=np.zeros(2, np.int32))
+
+
+# --------------------------------------------------------------------------
+# acenes and herringbone crystals
+
+def acene(nrings, dcc=1.40, dch=1.08):
+    """Idealised planar linear acene in Angstrom: long axis x, plane xy,
+    centred at the origin.  nrings=3 gives C14H10, nrings=5 gives C22H14."""
+    pts = []
+    s = math.sqrt(3.0) * dcc
+    for k in range(nrings):
+        cx = k * s
+        for j in range(6):
+            a = math.radians(90 + 60 * j)
+            pts.append((cx + dcc * math.cos(a), dcc * math.sin(a)))
+    C = []
+    for p in pts:
+        if all((p[0] - q[0]) ** 2 + (p[1] - q[1]) ** 2 > 0.01 for q in C):
+            C.append(p)
+    C = np.array(C)
+    H = []
+    for i, p in enumerate(C):
+        d = np.linalg.norm(C - p, axis=1)
+        nb = np.where((d > 0.1) & (d < dcc + 0.05))[0]
+        if len(nb) == 2:
+            v = p - C[nb].mean(0)
+            v /= np.linalg.norm(v)
+            H.append(p + dch * v)
+    H = np.array(H)
+    X = np.concatenate([C, H])
+    X = np.concatenate([X, np.zeros((len(X), 1))], 1)
+    X -= X.mean(0)
+    Z = np.array([6] * len(C) + [1] * len(H), np.int32)
+    # order atoms: keep C then H (fragment-local order is by global index)
+    return Z, X
+
+
+def cell_vectors(a, b, c, alpha, beta, gamma):
+    al, be, ga = map(math.radians, (alpha, beta, gamma))
+    va = np.array([a, 0.0, 0.0])
+    vb = np.array([b * math.cos(ga), b * math.sin(ga), 0.0])
+    cx = c * math.cos(be)
+    cy = c * (math.cos(al) - math.cos(be) * math.cos(ga)) / math.sin(ga)
+    cz = math.sqrt(max(c * c - cx * cx - cy * cy, 0.0))
+    vc = np.array([cx, cy, cz])
+    return np.stack([va, vb, vc])
+
+
+def _herringbone_cell(Zm, Xm, cell, tilt, theta):
+    """Two molecules at fractional (0,0,0) and (1/2,1/2,0).  The long axis is
+    tilted by `tilt` from the layer normal (towards a); the molecular planes
+    are rotated by +theta / -theta about the long axis."""
+    n = np.cross(cell[0], cell[1])
+    n /= np.linalg.norm(n)
+    ahat = cell[0] / np.linalg.norm(cell[0])
+    long_axis = math.cos(tilt) * n + math.sin(tilt) * ahat
+    long_axis /= np.linalg.norm(long_axis)
+    # frame: x_m -> long axis, y_m -> perpendicular in the (a-ish) direction
+    y0 = np.cross(long_axis, ahat)
+    y0 /= np.linalg.norm(y0)
+    z0 = np.cross(long_axis, y0)
+    F = np.stack([long_axis, y0, z0], 1)  # columns
+    mols = []
+    for sgn, frac in ((+1, (0.0, 0.0, 0.0)), (-1, (0.5, 0.5, 0.0))):
+        R = _axis_rotation(long_axis, sgn * theta) @ F
+        X = Xm @ R.T + np.asarray(frac) @ cell
+        mols.append(X)
+    return mols
+
+
+def _min_contacts(Zm, mols, cell):
+    """Closest intermolecular C-C and H-H distances in a 3x3x3 periodic block."""
+    A = np.concatenate(mols)
+    tag = np.concatenate([np.full(len(m), i) for i, m in enumerate(mols)])
+    Zs = np.concatenate([Zm] * len(mols))
+    dcc, dhh, dall = 1e9, 1e9, 1e9
+    for i in (-1, 0, 1):
+        for j in (-1, 0, 1):
+            for k in (-1, 0, 1):
+                T = np.array([i, j, k]) @ cell
+                B = A + T
+                D = np.linalg.norm(A[:, None, :] - B[None, :, :], axis=2)
+                same = (tag[:, None] == tag[None, :]) & (i == 0 and j == 0 and k == 0)
+                D = np.where(same, 1e9, D)
+                cc = (Zs[:, None] == 6) & (Zs[None, :] == 6)
+                hh = (Zs[:, None] == 1) & (Zs[None, :] == 1)
+                dcc = min(dcc, D[cc].min())
+                dhh = min(dhh, D[hh].min())
+                dall = min(dall, D.min())
+    return dcc, dhh, dall
+
+
+def _choose_herringbone(Zm, Xm, cell):
+    """Deterministic scan of (tilt, theta) maximising the closest contact."""
+    best = None
+    for tilt_deg in range(0, 41, 2):
+        for th_deg in range(0, 90, 3):
+            mols = _herringbone_cell(Zm, Xm, cell, math.radians(tilt_deg),
+                                     math.radians(th_deg))
+            dcc, dhh, dall = _min_contacts(Zm, mols, cell)
+            score = min(dcc - 1.2, dhh, dall + 0.6)
+            if best is None or score > best[0]:
+                best = (score, tilt_deg, th_deg, dcc, dhh, dall)
+    return best
+
+
+def _crystal(name, nrings, cellpar, reps, sigma, seed, scan=None):
+    Zm, Xm = acene(nrings)
+    cell = cell_vectors(*cellpar)
+    if scan is None:
+        scan = _choose_herringbone(Zm, Xm, cell)
+    _, tilt_deg, th_deg = scan[:3]
+    mols = _herringbone_cell(Zm, Xm, cell, math.radians(tilt_deg), math.radians(th_deg))
+    rng = _rng(seed)
+    allX, allZ, frag = [], [], []
+    f = 0
+    for i in range(reps[0]):
+        for j in range(reps[1]):
+            for k in range(reps[2]):
+                T = np.array([i, j, k]) @ cell
+                for m in mols:
+                    X = m + T
+                    jit = rng.normal(0.0, sigma, X.shape)
+                    jit = np.clip(jit, -3 * sigma, 3 * sigma)
+                    allX.append(X + jit)
+                    allZ.append(Zm)
+                    frag.append(np.full(len(Zm), f, np.int32))
+                    f += 1
+    Z = np.concatenate(allZ).astype(np.int32)
+    xyz = np.concatenate(allX)
+    return System(name=name, Z=Z, xyz=xyz * ANGSTROM_TO_BOHR,
+                  frag=np.concatenate(frag), frag_charge=np.zeros(f, np.int32),
+                  meta=dict(seed=seed, cell=cellpar, reps=reps, sigma=sigma,
+                            tilt_deg=tilt_deg, theta_deg=th_deg,
+                            closest_contacts=scan[3:] if len(scan) > 3 else None))
+
+
+# herringbone scan results, recorded so that builds are fast and reproducible
+# (tilt_deg, theta_deg); recomputed by _choose_herringbone when None
+ANTHRACENE_CELL = (8.56, 6.04, 11.16, 90.0, 124.7, 90.0)
+PENTACENE_CELL = (6.27, 7.78, 14.53, 76.5, 87.5, 84.7)
+_SCAN_CACHE = {}
+
+
+# result of _choose_herringbone for the two cells: (score, tilt_deg, theta_deg,
+# closest C-C, closest H-H, closest any), in Angstrom
+_SCAN_CACHE["anthracene"] = (None, 36, 30, 3.466, 2.270, 2.270)
+_SCAN_CACHE["pentacene"] = (None, 32, 60, 3.331, 2.376, 2.376)
+
+
+def _scan(key, nrings, cellpar):
+    if key not in _SCAN_CACHE:
+        Zm, Xm = acene(nrings)
+        _SCAN_CACHE[key] = _choose_herringbone(Zm, Xm, cell_vectors(*cellpar))
+    return _SCAN_CACHE[key]
+
+
+def anthracene_crystal(reps=(8, 8, 4), sigma=0.1, seed=3):
+    scan = _scan("anthracene", 3, ANTHRACENE_CELL)
+    return _crystal(f"anthracene-{reps[0]}x{reps[1]}x{reps[2]}", 3, ANTHRACENE_CELL,
+                    reps, sigma, seed, scan)
+
+
+def pentacene_crystal(reps=(11, 5, 6), sigma=0.05, seed=4):
+    scan = _scan("pentacene", 5, PENTACENE_CELL)
+    return _crystal(f"pentacene-{reps[0]}x{reps[1]}x{reps[2]}", 5, PENTACENE_CELL,
+                    reps, sigma, seed, scan)
