@@ -1,0 +1,196 @@
+/*
+ * fmoxtb.h -- C ABI of the MI355X (gfx950) FMO-xTB library.
+ *
+ * The library computes the fragment molecular orbital energy and analytic
+ * gradient of a molecular system at the GFN1-xTB level, following the paper
+ * "FMO-xTB: Fragment molecular orbital method with GFN1-xTB":
+ *   - section "GFN1-xTB" (eqs. gfn1-energy .. gfn1_rep_energy, cn_def):
+ *     the tight-binding Hamiltonian of every fragment calculation;
+ *   - section "Fragment molecular orbital method" (eqs.
+ *     fmo2-energy-components, dimer_embedding_correction, ddq_calc,
+ *     esdimer-energy, fmo3_energy, trimer_interaction_energy,
+ *     trimer_embedding): the many-body energy;
+ *   - section "FMO-xTB" (eq. v_esp_matrix and the monomer self-consistency
+ *     it describes): the electrostatic embedding;
+ *   - section "Analytic energy gradients" (eqs. grad_decomp .. response_grad_full):
+ *     the FMO2 gradient including the response of the embedding.
+ *
+ * Conventions shared by every call
+ *   - Units: bohr for lengths, Hartree for energies, Eh/bohr for gradients.
+ *   - Charges: shell Mulliken charges dq = population - reference population
+ *     (electron excess), one value per shell, shells ordered atom by atom
+ *     (global atom order) and, within an atom, in parameter-file order.
+ *   - Fragment lists: pairs (I, J) with I < J in lexicographic order, trimers
+ *     (I, J, K) with I < J < K in lexicographic order, int32.
+ *   - All pointers in this header are HOST pointers; the library copies inputs
+ *     and results between host and its own device memory.  The caller keeps
+ *     ownership of every buffer it passes.
+ *   - Return codes: FX_OK on success, a negative FX_E_* code otherwise; the
+ *     message of the last error of a context is available from
+ *     fx_last_error().  No C++ exception crosses this boundary.
+ *   - A context is not thread-safe; independent contexts are.  Work runs on
+ *     the HIP stream given at creation; every call returns after that stream
+ *     has finished the call's work.
+ */
+#ifndef FMOXTB_H
+#define FMOXTB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  FX_OK = 0,
+  FX_E_INVALID = -1,      /* bad argument, NaN coordinate, atoms closer than 0.3 bohr */
+  FX_E_NOMEM = -2,        /* device allocation failed */
+  FX_E_DEVICE = -3,       /* HIP runtime error */
+  FX_E_NOCONV = -4,       /* an SCC or the monomer loop did not converge; results readable */
+  FX_E_STATE = -5,        /* call out of order (e.g. fx_run before fx_set_system) */
+  FX_E_UNSUPPORTED = -6   /* element or shell type missing from the parameters */
+};
+
+enum { FX_FP64 = 0, FX_MIXED = 1 };           /* precision */
+enum { FX_BATCHED = 0, FX_PLAIN_LOOP = 1 };   /* schedule of the fragment solves */
+enum { FX_GUESS_SUPERPOSITION = 0, FX_GUESS_USER = 2 };
+
+typedef struct fx_params fx_params;
+typedef struct fx_ctx fx_ctx;
+
+typedef struct fx_options {
+  int32_t order;          /* 2 (FMO2) or 3 (FMO3) */
+  double cutoff_bohr;     /* a pair is an SCC dimer when its closest interatomic
+                             distance is below this value, otherwise ES-DIM;
+                             a trimer is computed when at least two of its
+                             three pairs are SCC dimers */
+  int32_t precision;      /* FX_FP64 (FX_MIXED is reserved; FX_E_UNSUPPORTED) */
+  int32_t schedule;       /* FX_BATCHED: all fragments of a kind in one launch
+                             sequence; FX_PLAIN_LOOP: one fragment at a time */
+  int32_t guess;          /* initial monomer charges: superposition (zero) or
+                             the charges given with fx_set_guess */
+  double scc_tol;         /* SCC convergence: max |dq_out - dq_in| */
+  double energy_tol;      /* SCC convergence: |E_k - E_(k-1)| */
+  double macro_tol;       /* monomer loop: max change of any monomer charge */
+  int32_t max_iter;       /* SCC iterations per fragment solve */
+  int32_t max_macro;      /* monomer self-consistency sweeps */
+  int32_t want_gradient;  /* compute the FMO2 gradient (order 2 only) */
+  int32_t want_response;  /* include the embedding response term */
+} fx_options;
+
+typedef struct fx_counts {
+  int64_t n_scc_pairs;
+  int64_t n_esd_pairs;
+  int64_t n_trimers;
+  int32_t n_shells;       /* shells of the whole system */
+  int32_t n_fragments;
+} fx_counts;
+
+typedef struct fx_result {
+  double e_total;         /* FMO2 or FMO3 energy */
+  double e_fmo2;          /* FMO2 part of it */
+  int32_t converged;      /* 1 if every solve and the monomer loop converged */
+  int32_t macro_iter;     /* monomer self-consistency sweeps used */
+  int64_t solves_mono, solves_dimer, solves_trimer;  /* fragment SCC solves */
+  int64_t iters_mono, iters_dimer, iters_trimer;     /* SCC iterations, summed */
+  double ms_lists, ms_monomer, ms_dimer, ms_trimer, ms_energy, ms_gradient, ms_response;
+} fx_result;
+
+/* Load element constants and STO-nG basis expansions from a JSON file.
+ * *out is owned by the caller; release with fx_params_free.
+ * Errors: FX_E_INVALID (unreadable or malformed file). */
+int fx_params_load(const char* json_path, fx_params** out);
+void fx_params_free(fx_params* p);
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * (NULL: the default stream); it must outlive the context.  The parameters
+ * are copied.  Errors: FX_E_INVALID, FX_E_DEVICE. */
+int fx_ctx_create(const fx_params* p, int device, void* hip_stream, fx_ctx** out);
+void fx_ctx_destroy(fx_ctx* ctx);
+/* Message of the last error on this context ("" if none); owned by the context. */
+const char* fx_last_error(const fx_ctx* ctx);
+
+/* Fill *o with defaults: order 2, cutoff 4 Angstrom, FP64, batched,
+ * superposition guess, scc_tol 1e-10, energy_tol 1e-11, macro_tol 1e-10,
+ * max_iter 200, max_macro 200, gradient and response on. */
+int fx_default_options(fx_options* o);
+int fx_set_options(fx_ctx* ctx, const fx_options* o);
+
+/* Set the molecular system.  Z[n_atoms] atomic numbers, xyz_bohr[3*n_atoms]
+ * Cartesian coordinates, atom_frag[n_atoms] fragment index of each atom
+ * (0..n_frag-1, every fragment non-empty), frag_charge[n_frag] net charges.
+ * Fragments are molecules (one molecule per monomer, section "Energy
+ * accuracy"); no covalent bond may cross a fragment boundary.
+ * Errors: FX_E_INVALID (bad sizes, NaN, atoms closer than 0.3 bohr, empty
+ * fragment), FX_E_UNSUPPORTED (element without parameters). */
+int fx_set_system(fx_ctx* ctx, int32_t n_atoms, const int32_t* Z, const double* xyz_bohr,
+                  int32_t n_frag, const int32_t* atom_frag, const int32_t* frag_charge);
+
+/* Classify fragment pairs (and trimers for order 3) by closest contact
+ * (section "Computational Details" selection rule, fixed cutoff reading) on
+ * the GPU and report the counts.  Distances are compared as squared FP64
+ * values formed as (dx*dx + dy*dy) + dz*dz without fused multiply-add.
+ * Errors: FX_E_STATE (no system). */
+int fx_build_lists(fx_ctx* ctx, fx_counts* out);
+/* Counts of the current lists (built by fx_build_lists or by fx_run); no
+ * GPU work.  Errors: FX_E_STATE if no lists exist yet. */
+int fx_get_counts(fx_ctx* ctx, fx_counts* out);
+/* Copy the lists into caller buffers sized from fx_counts: scc_pairs[2*n_scc],
+ * esd_pairs[2*n_esd], trimers[3*n_tri] (any pointer may be NULL to skip). */
+int fx_get_lists(fx_ctx* ctx, int32_t* scc_pairs, int32_t* esd_pairs, int32_t* trimers);
+
+/* Initial monomer shell charges dq_shell[n_shells] (used with FX_GUESS_USER). */
+int fx_set_guess(fx_ctx* ctx, const double* dq_shell);
+
+/* Run the FMO calculation: lists (if not built), supersystem CN, the monomer
+ * self-consistency loop, dimer (and trimer) SCC solves in the converged
+ * embedding, ES-DIM pairs, the energy and, if requested, the FMO2 gradient.
+ * Blocks until done.  Returns FX_E_NOCONV (results still readable) when a
+ * solve hit max_iter or the monomer loop hit max_macro. */
+int fx_run(fx_ctx* ctx, fx_result* out);
+
+/* Per-fragment energies of the last run: E_mono[n_frag] internal monomer
+ * energies (embedding acts in the Fock matrix only), dE_scc[n_scc] SCC pair
+ * interaction energies Delta E_IJ (eq. fmo2-energy-components), dE_esd[n_esd]
+ * ES-DIM pair energies (eq. esdimer-energy), dE_tri[n_tri] trimer corrections
+ * Delta E_IJK - Delta E_IJ - Delta E_IK - Delta E_JK (eq. fmo3_energy).
+ * Buffers are sized from fx_get_counts after the run; NULL pointers are
+ * skipped. */
+int fx_get_energies(fx_ctx* ctx, double* E_mono, double* dE_scc, double* dE_esd, double* dE_tri);
+/* Converged monomer shell charges dq_shell[n_shells]. */
+int fx_get_charges(fx_ctx* ctx, double* dq_shell);
+/* FMO2 gradient grad[3*n_atoms] (Eh/bohr) of the last run.
+ * Errors: FX_E_STATE if the last run did not compute it. */
+int fx_get_gradient(fx_ctx* ctx, double* grad);
+
+/* ---- component entry points (single hot-path steps, for validation) ---- */
+
+/* Supersystem coordination numbers cn[n_atoms] (eq. cn_def, no cutoff). */
+int fx_compute_cn(fx_ctx* ctx, double* cn);
+
+/* Overlap S and zeroth-order Hamiltonian H0 (eq. h0_hamiltonian with
+ * eqs. xtb1_polynomial_correction, xtb1_diagonal_h0) of the cluster made of
+ * fragments frags[0..nfrag-1] (1 to 3, basis in that fragment order, atoms of
+ * a fragment in ascending global order).  S and H0 are row-major nao x nao,
+ * nao written to *nao_out; pass S = H0 = NULL to query nao only. */
+int fx_cluster_matrices(fx_ctx* ctx, int32_t nfrag, const int32_t* frags, int32_t* nao_out,
+                        double* S, double* H0);
+
+/* Electrostatic embedding field of eq. v_esp_matrix on every shell:
+ * phi[s] = sum over shells t of other fragments of gamma_st * dq[t], for the
+ * given shell charges dq[n_shells]. */
+int fx_embedding_field(fx_ctx* ctx, const double* dq, double* phi);
+
+/* Batched symmetric eigensolver used by the SCC: nmat matrices of sizes n[k]
+ * (each <= 512), packed one after another row-major in A (sum n[k]^2
+ * doubles).  Writes eigenvalues w (sum n[k], unsorted) and eigenvectors as
+ * rows of V (same packing as A: row i of matrix k is eigenvector i). */
+int fx_eigh_batched(fx_ctx* ctx, int32_t nmat, const int32_t* n, const double* A, double* w,
+                    double* V);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMOXTB_H */

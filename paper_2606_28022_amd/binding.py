@@ -1,0 +1,269 @@
+"""ctypes binding of the C ABI in include/fmoxtb.h (argument marshalling only).
+
+Names follow the C entry points.  The library is loaded from the package
+directory; a missing library raises at load time (there is no fallback).
+"""
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+FX_OK, FX_E_INVALID, FX_E_NOMEM, FX_E_DEVICE, FX_E_NOCONV, FX_E_STATE, FX_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+FX_FP64, FX_MIXED = 0, 1
+FX_BATCHED, FX_PLAIN_LOOP = 0, 1
+FX_GUESS_SUPERPOSITION, FX_GUESS_USER = 0, 2
+
+
+class FxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fmoxtb error {code}: {msg}")
+        self.code = code
+
+
+class fx_options(C.Structure):
+    _fields_ = [("order", C.c_int32), ("cutoff_bohr", C.c_double), ("precision", C.c_int32),
+                ("schedule", C.c_int32), ("guess", C.c_int32), ("scc_tol", C.c_double),
+                ("energy_tol", C.c_double), ("macro_tol", C.c_double), ("max_iter", C.c_int32),
+                ("max_macro", C.c_int32), ("want_gradient", C.c_int32), ("want_response", C.c_int32)]
+
+
+class fx_counts(C.Structure):
+    _fields_ = [("n_scc_pairs", C.c_int64), ("n_esd_pairs", C.c_int64), ("n_trimers", C.c_int64),
+                ("n_shells", C.c_int32), ("n_fragments", C.c_int32)]
+
+
+class fx_result(C.Structure):
+    _fields_ = [("e_total", C.c_double), ("e_fmo2", C.c_double), ("converged", C.c_int32),
+                ("macro_iter", C.c_int32), ("solves_mono", C.c_int64), ("solves_dimer", C.c_int64),
+                ("solves_trimer", C.c_int64), ("iters_mono", C.c_int64), ("iters_dimer", C.c_int64),
+                ("iters_trimer", C.c_int64), ("ms_lists", C.c_double), ("ms_monomer", C.c_double),
+                ("ms_dimer", C.c_double), ("ms_trimer", C.c_double), ("ms_energy", C.c_double),
+                ("ms_gradient", C.c_double), ("ms_response", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = ["fx_params_load", "fx_params_free", "fx_ctx_create", "fx_ctx_destroy", "fx_last_error",
+           "fx_default_options", "fx_set_options", "fx_set_system", "fx_build_lists", "fx_get_counts", "fx_get_lists",
+           "fx_set_guess", "fx_run", "fx_get_energies", "fx_get_charges", "fx_get_gradient",
+           "fx_compute_cn", "fx_cluster_matrices", "fx_embedding_field", "fx_eigh_batched"]
+
+_lib = None
+
+
+def lib_path():
+    return os.path.join(HERE, "libfmoxtb.so")
+
+
+def load_library():
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = lib_path()
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: build it with python -m paper_2606_28022_amd.build")
+    L = C.CDLL(path)
+    P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    pI32, pD = C.POINTER(C.c_int32), C.POINTER(C.c_double)
+    L.fx_params_load.argtypes = [C.c_char_p, C.POINTER(C.c_void_p)]
+    L.fx_params_free.argtypes = [P]
+    L.fx_params_free.restype = None
+    L.fx_ctx_create.argtypes = [P, C.c_int, P, C.POINTER(C.c_void_p)]
+    L.fx_ctx_destroy.argtypes = [P]
+    L.fx_ctx_destroy.restype = None
+    L.fx_last_error.argtypes = [P]
+    L.fx_last_error.restype = C.c_char_p
+    L.fx_default_options.argtypes = [C.POINTER(fx_options)]
+    L.fx_set_options.argtypes = [P, C.POINTER(fx_options)]
+    L.fx_set_system.argtypes = [P, I32, pI32, pD, I32, pI32, pI32]
+    L.fx_build_lists.argtypes = [P, C.POINTER(fx_counts)]
+    L.fx_get_counts.argtypes = [P, C.POINTER(fx_counts)]
+    L.fx_get_lists.argtypes = [P, pI32, pI32, pI32]
+    L.fx_set_guess.argtypes = [P, pD]
+    L.fx_run.argtypes = [P, C.POINTER(fx_result)]
+    L.fx_get_energies.argtypes = [P, pD, pD, pD, pD]
+    L.fx_get_charges.argtypes = [P, pD]
+    L.fx_get_gradient.argtypes = [P, pD]
+    L.fx_compute_cn.argtypes = [P, pD]
+    L.fx_cluster_matrices.argtypes = [P, I32, pI32, pI32, pD, pD]
+    L.fx_embedding_field.argtypes = [P, pD, pD]
+    L.fx_eigh_batched.argtypes = [P, I32, pI32, pD, pD, pD]
+    for name in ["fx_params_load", "fx_ctx_create", "fx_default_options", "fx_set_options", "fx_set_system",
+                 "fx_build_lists", "fx_get_counts", "fx_get_lists", "fx_set_guess", "fx_run", "fx_get_energies",
+                 "fx_get_charges", "fx_get_gradient", "fx_compute_cn", "fx_cluster_matrices",
+                 "fx_embedding_field", "fx_eigh_batched"]:
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _ptr(a, ctype):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def default_params_path():
+    return os.path.join(ROOT, "workloads", "gfn1_like.json")
+
+
+class FmoXtb:
+    """One library context on a HIP device; methods map 1:1 to the C ABI."""
+
+    def __init__(self, params_path=None, device=0, stream=None):
+        self.L = load_library()
+        pp = C.c_void_p()
+        rc = self.L.fx_params_load((params_path or default_params_path()).encode(), C.byref(pp))
+        if rc != FX_OK:
+            raise FxError(rc, self.L.fx_last_error(None).decode())
+        self._params = pp
+        ctx = C.c_void_p()
+        rc = self.L.fx_ctx_create(pp, device, stream, C.byref(ctx))
+        if rc != FX_OK:
+            self.L.fx_params_free(pp)
+            raise FxError(rc, "context creation failed")
+        self.ctx = ctx
+        self.opt = fx_options()
+        self.L.fx_default_options(C.byref(self.opt))
+        self.n_atoms = 0
+        self.n_shells = 0
+        self.n_frag = 0
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.L.fx_ctx_destroy(self.ctx)
+            self.ctx = None
+        if getattr(self, "_params", None):
+            self.L.fx_params_free(self._params)
+            self._params = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=()):
+        if rc != FX_OK and rc not in allow:
+            raise FxError(rc, self.L.fx_last_error(self.ctx).decode())
+        return rc
+
+    # -- options and system --------------------------------------------------
+    def set_options(self, **kw):
+        for k, v in kw.items():
+            if not hasattr(self.opt, k):
+                raise KeyError(k)
+            setattr(self.opt, k, v)
+        self._check(self.L.fx_set_options(self.ctx, C.byref(self.opt)))
+
+    def set_system(self, Z, xyz_bohr, atom_frag, frag_charge):
+        Z, xyz, fr, ch = _i32(Z), _f64(xyz_bohr).reshape(-1), _i32(atom_frag), _i32(frag_charge)
+        self._check(self.L.fx_set_system(self.ctx, len(Z), _ptr(Z, C.c_int32), _ptr(xyz, C.c_double),
+                                         len(ch), _ptr(fr, C.c_int32), _ptr(ch, C.c_int32)))
+        self.n_atoms = len(Z)
+        self.n_frag = len(ch)
+        cnt = self.build_lists_counts()
+        self.n_shells = cnt.n_shells
+
+    def build_lists_counts(self):
+        c = fx_counts()
+        self._check(self.L.fx_build_lists(self.ctx, C.byref(c)))
+        self.counts = c
+        return c
+
+    def get_counts(self):
+        c = fx_counts()
+        self._check(self.L.fx_get_counts(self.ctx, C.byref(c)))
+        self.counts = c
+        return c
+
+    def build_lists(self):
+        self.build_lists_counts()
+        c = self.get_counts()
+        scc = np.zeros((c.n_scc_pairs, 2), np.int32)
+        esd = np.zeros((c.n_esd_pairs, 2), np.int32)
+        tri = np.zeros((c.n_trimers, 3), np.int32)
+        self._check(self.L.fx_get_lists(self.ctx, _ptr(scc, C.c_int32), _ptr(esd, C.c_int32),
+                                        _ptr(tri, C.c_int32)))
+        return scc, esd, tri
+
+    def set_guess(self, dq_shell):
+        dq = _f64(dq_shell)
+        self._check(self.L.fx_set_guess(self.ctx, _ptr(dq, C.c_double)))
+
+    # -- run and results -----------------------------------------------------
+    def run(self, allow_noconv=False):
+        r = fx_result()
+        self._check(self.L.fx_run(self.ctx, C.byref(r)), allow=(FX_E_NOCONV,) if allow_noconv else ())
+        self.result = r
+        return r.as_dict()
+
+    def energies(self):
+        c = self.get_counts()
+        em = np.zeros(self.n_frag)
+        ds = np.zeros(c.n_scc_pairs)
+        de = np.zeros(c.n_esd_pairs)
+        dt = np.zeros(c.n_trimers)
+        self._check(self.L.fx_get_energies(self.ctx, _ptr(em, C.c_double), _ptr(ds, C.c_double),
+                                           _ptr(de, C.c_double), _ptr(dt, C.c_double)))
+        return em, ds, de, dt
+
+    def charges(self):
+        q = np.zeros(self.n_shells)
+        self._check(self.L.fx_get_charges(self.ctx, _ptr(q, C.c_double)))
+        return q
+
+    def gradient(self):
+        g = np.zeros((self.n_atoms, 3))
+        self._check(self.L.fx_get_gradient(self.ctx, _ptr(g, C.c_double)))
+        return g
+
+    # -- component entry points ------------------------------------------------
+    def compute_cn(self):
+        cn = np.zeros(self.n_atoms)
+        self._check(self.L.fx_compute_cn(self.ctx, _ptr(cn, C.c_double)))
+        return cn
+
+    def cluster_matrices(self, frags):
+        fr = _i32(frags)
+        n = C.c_int32()
+        self._check(self.L.fx_cluster_matrices(self.ctx, len(fr), _ptr(fr, C.c_int32), C.byref(n), None, None))
+        S = np.zeros((n.value, n.value))
+        H = np.zeros((n.value, n.value))
+        self._check(self.L.fx_cluster_matrices(self.ctx, len(fr), _ptr(fr, C.c_int32), C.byref(n),
+                                               _ptr(S, C.c_double), _ptr(H, C.c_double)))
+        return S, H
+
+    def embedding_field(self, dq):
+        dq = _f64(dq)
+        phi = np.zeros_like(dq)
+        self._check(self.L.fx_embedding_field(self.ctx, _ptr(dq, C.c_double), _ptr(phi, C.c_double)))
+        return phi
+
+    def eigh_batched(self, mats):
+        ns = _i32([m.shape[0] for m in mats])
+        A = _f64(np.concatenate([np.asarray(m, float).ravel() for m in mats]))
+        w = np.zeros(int(ns.sum()))
+        V = np.zeros_like(A)
+        self._check(self.L.fx_eigh_batched(self.ctx, len(ns), _ptr(ns, C.c_int32), _ptr(A, C.c_double),
+                                           _ptr(w, C.c_double), _ptr(V, C.c_double)))
+        out = []
+        o = ow = 0
+        for n in ns:
+            out.append((w[ow:ow + n].copy(), V[o:o + n * n].reshape(n, n).copy()))
+            o += n * n
+            ow += n
+        return out

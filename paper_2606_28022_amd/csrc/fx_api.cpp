@@ -1,0 +1,1007 @@
+// Host driver and C ABI of the FMO-xTB library.
+//
+// The driver owns the supersystem tables in device memory, builds fragment
+// batches (monomers, SCC dimers, trimers), runs the batched SCC kernels
+// until every system of a batch has converged, and assembles the FMO
+// energy.  All arithmetic of the method runs in the HIP kernels; the host
+// only builds index tables, launches kernels and reads convergence flags.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <sstream>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/fmoxtb.h"
+#include "fx_device.hpp"
+#include "fx_kernels.hpp"
+#include "fx_host.hpp"
+#include "json_mini.hpp"
+
+using namespace fx;
+
+// ---------------------------------------------------------------------------
+// parameters
+
+namespace fx {
+
+static double prim_norm(int l, double a) {
+  double n = std::pow(2.0 * a / M_PI, 0.75);
+  if (l == 1) n *= 2.0 * std::sqrt(a);
+  return n;
+}
+
+HostParams load_params(const std::string& path) {
+  std::ifstream f(path);
+  if (!f) throw FxError(FX_E_INVALID, "cannot open parameter file " + path);
+  std::stringstream ss;
+  ss << f.rdbuf();
+  JVal root = JParser(ss.str()).parse();
+  HostParams P;
+  const JVal& g = root["globals"];
+  P.g.kg = g["kg"].d();
+  P.g.kf = g["kf"].d();
+  P.g.kEN = g["kEN"].d();
+  P.g.k1 = g["k1"].d();
+  P.g.k2 = g["k2"].d();
+  for (int l = 0; l < 3; ++l) P.g.kl[l] = l < (int)g["kl"].size() ? g["kl"][l].d() : 0.0;
+  P.g.KAB = g["KAB"].d();
+  P.g.kT = g["Tel_K"].d() * g["kB_Eh_per_K"].d();
+  double a2b = g["angstrom_to_bohr"].d();
+  std::map<std::string, std::pair<std::vector<double>, std::vector<double>>> basis;
+  for (auto& kv : root["basis"].obj) {
+    const JVal& b = kv.second;
+    std::vector<double> al, co;
+    for (auto& x : b["alpha"].arr) al.push_back(x.d());
+    for (auto& x : b["coef"].arr) co.push_back(x.d());
+    if ((int)al.size() != NPRIM || (int)co.size() != NPRIM)
+      throw FxError(FX_E_UNSUPPORTED, "basis expansions must have 6 primitives");
+    basis[std::to_string(b["n"].i()) + ":" + std::to_string(b["l"].i())] = {al, co};
+  }
+  for (auto& kv : root["elements"].obj) {
+    const JVal& e = kv.second;
+    int Z = e["Z"].i();
+    if (Z < 1 || Z > 118) throw FxError(FX_E_INVALID, "bad element number");
+    DevElem el;
+    std::memset(&el, 0, sizeof(el));
+    const JVal& shells = e["shells"];
+    if ((int)shells.size() > MAXSH_EL) throw FxError(FX_E_UNSUPPORTED, "too many shells for element " + kv.first);
+    el.nsh = (int)shells.size();
+    int ao = 0;
+    for (int s = 0; s < el.nsh; ++s) {
+      const JVal& sh = shells[s];
+      int n = sh["n"].i(), l = sh["l"].i();
+      if (l > 1) throw FxError(FX_E_UNSUPPORTED, "only s and p shells are supported");
+      auto it = basis.find(std::to_string(n) + ":" + std::to_string(l));
+      if (it == basis.end()) throw FxError(FX_E_UNSUPPORTED, "no basis expansion for a shell of " + kv.first);
+      double zeta = sh["zeta"].d();
+      el.l[s] = l;
+      el.nao_sh[s] = l == 0 ? 1 : 3;
+      el.ao0[s] = ao;
+      ao += el.nao_sh[s];
+      el.level[s] = sh["level"].d();
+      el.kcn[s] = sh["kcn"].d();
+      el.kpoly[s] = sh["kpoly"].d();
+      el.eta[s] = (1.0 + sh["kappa"].d()) * e["eta"].d();
+      el.q0[s] = sh["q0"].d();
+      double norm2 = 0.0;
+      for (int i = 0; i < NPRIM; ++i) {
+        el.alpha[s][i] = it->second.first[i] * zeta * zeta;
+        el.coef[s][i] = it->second.second[i] * prim_norm(l, el.alpha[s][i]);
+      }
+      for (int i = 0; i < NPRIM; ++i)
+        for (int j = 0; j < NPRIM; ++j) {
+          double p = el.alpha[s][i] + el.alpha[s][j];
+          double v = std::pow(M_PI / p, 1.5);
+          if (l == 1) v /= 2.0 * p;
+          norm2 += el.coef[s][i] * el.coef[s][j] * v;
+        }
+      for (int i = 0; i < NPRIM; ++i) el.coef[s][i] /= std::sqrt(norm2);
+    }
+    el.nao = ao;
+    el.orth = 0;
+    if (el.nsh == 2 && el.l[0] == 0 && el.l[1] == 0) {
+      double s12 = 0.0;
+      for (int i = 0; i < NPRIM; ++i)
+        for (int j = 0; j < NPRIM; ++j)
+          s12 += el.coef[0][i] * el.coef[1][j] * std::pow(M_PI / (el.alpha[0][i] + el.alpha[1][j]), 1.5);
+      el.orth = 1;
+      el.orthS12 = s12;
+      el.orthN = 1.0 / std::sqrt(1.0 - s12 * s12);
+    }
+    el.EN = e["EN"].d();
+    el.rcov = e["rcov_angstrom"].d() * a2b;
+    el.Gamma = e["Gamma"].d();
+    el.zeff = e["zeff"].d();
+    el.arep = e["alpha_rep"].d();
+    P.elem_of_Z[Z] = (int)P.elems.size();
+    P.elems.push_back(el);
+  }
+  return P;
+}
+
+}  // namespace fx
+
+struct fx_params {
+  fx::HostParams P;
+};
+
+// ---------------------------------------------------------------------------
+// context helpers
+
+namespace fx {
+
+void Ctx::check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw FxError(FX_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void* Ctx::dmalloc(size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) throw FxError(FX_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  return p;
+}
+
+void Ctx::sync() { check(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
+
+double Ctx::now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+DevSystem Ctx::dev_system() const {
+  DevSystem s;
+  s.natoms = N;
+  s.nshells = Nsh;
+  s.nfrag = F;
+  s.xyz = d_xyz.p;
+  s.elem = d_elem.p;
+  s.frag = d_frag.p;
+  s.atom_sh0 = d_atom_sh0.p;
+  s.cn = d_cn.p;
+  s.sh_atom = d_sh_atom.p;
+  s.sh_frag = d_sh_frag.p;
+  s.sh_eta = d_sh_eta.p;
+  s.elems = d_elems.p;
+  s.g = P.g;
+  return s;
+}
+
+// Build a batch of fragment systems (each a tuple of 1..3 fragments).
+void Ctx::build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters, int nfrag_each) {
+  b = Batch();
+  const int ns = (int)clusters.size();
+  b.nsys = ns;
+  std::vector<SysDesc> desc(ns);
+  std::vector<int> atoms, atom_ao0, atom_sh0, sh_global, sh_atom, ao_sh;
+  long long mat = 0, gam = 0;
+  int sh_off = 0, ao_off = 0, atom_off = 0;
+  for (int k = 0; k < ns; ++k) {
+    SysDesc& d = desc[k];
+    d.nfrag = nfrag_each;
+    d.atom_off = atom_off;
+    d.sh_off = sh_off;
+    d.ao_off = ao_off;
+    d.mat_off = mat;
+    d.gam_off = gam;
+    int nat = 0, nsh = 0, nao = 0;
+    double nel = 0.0;
+    for (int f = 0; f < 3; ++f) d.frag[f] = -1;
+    for (int f = 0; f < nfrag_each; ++f) {
+      int I = clusters[k][f];
+      d.frag[f] = I;
+      nel -= frag_charge[I];
+      for (int ia = frag_off[I]; ia < frag_off[I + 1]; ++ia) {
+        int A = frag_atoms[ia];
+        const DevElem& el = P.elems[elem[A]];
+        atoms.push_back(A);
+        atom_ao0.push_back(nao);
+        atom_sh0.push_back(nsh);
+        for (int s = 0; s < el.nsh; ++s) {
+          sh_global.push_back(atom_sh0_g[A] + s);
+          sh_atom.push_back(nat);
+          for (int u = 0; u < el.nao_sh[s]; ++u) ao_sh.push_back(nsh);
+          nel += el.q0[s];
+          ++nsh;
+        }
+        nao += el.nao;
+        ++nat;
+      }
+    }
+    if (nao > MAXN) throw FxError(FX_E_UNSUPPORTED, "fragment system larger than 512 AOs");
+    d.nat = nat;
+    d.nsh = nsh;
+    d.nao = nao;
+    d.nel = nel;
+    atom_off += nat;
+    sh_off += nsh;
+    ao_off += nao;
+    mat += (long long)nao * nao;
+    gam += (long long)nsh * nsh;
+    b.max_nao = std::max(b.max_nao, nao);
+  }
+  b.h_desc = desc;
+  b.tot_sh = sh_off;
+  b.tot_ao = ao_off;
+  b.tot_mat = mat;
+  b.d_desc.upload(desc);
+  b.d_atoms.upload(atoms);
+  b.d_atom_ao0.upload(atom_ao0);
+  b.d_atom_sh0.upload(atom_sh0);
+  b.d_sh_global.upload(sh_global);
+  b.d_sh_atom.upload(sh_atom);
+  b.d_ao_sh.upload(ao_sh);
+  b.S.alloc(mat);
+  b.H0.alloc(mat);
+  b.Fm.alloc(mat);
+  b.Ct.alloc(mat);
+  b.Pm.alloc(mat);
+  b.Tm.alloc(mat);
+  b.gam.alloc(gam);
+  b.q_in.alloc(sh_off);
+  b.q_out.alloc(sh_off);
+  b.phi.alloc(sh_off);
+  b.sig.alloc(sh_off);
+  b.hx.alloc((long long)sh_off * HIST);
+  b.hr.alloc((long long)sh_off * HIST);
+  b.eps.alloc(ao_off);
+  b.occ.alloc(ao_off);
+  b.erep.alloc(ns);
+  b.e_int.alloc(ns);
+  b.e_prev.alloc(ns);
+  b.mts.alloc(ns);
+  b.err.alloc(ns);
+  b.status.alloc(ns);
+  b.niter.alloc(ns);
+  b.nhist.alloc(ns);
+  b.sweeps.alloc(ns);
+  std::vector<int> all(ns);
+  for (int k = 0; k < ns; ++k) all[k] = k;
+  b.d_all.upload(all);
+  check(hipMemsetAsync(b.phi.p, 0, sizeof(double) * std::max(1, sh_off), stream), "memset");
+}
+
+DevBatch Batch::dev() {
+  DevBatch d;
+  d.nsys = nsys;
+  d.desc = d_desc.p;
+  d.sys_atoms = d_atoms.p;
+  d.sys_atom_ao0 = d_atom_ao0.p;
+  d.sys_atom_sh0 = d_atom_sh0.p;
+  d.sys_sh_global = d_sh_global.p;
+  d.sys_sh_atom = d_sh_atom.p;
+  d.sys_ao_sh = d_ao_sh.p;
+  d.S = S.p;
+  d.H0 = H0.p;
+  d.F = Fm.p;
+  d.Ct = Ct.p;
+  d.P = Pm.p;
+  d.T = Tm.p;
+  d.gam = gam.p;
+  d.q_in = q_in.p;
+  d.q_out = q_out.p;
+  d.phi = phi.p;
+  d.sig = sig.p;
+  d.hx = hx.p;
+  d.hr = hr.p;
+  d.eps = eps.p;
+  d.occ = occ.p;
+  d.erep = erep.p;
+  d.e_int = e_int.p;
+  d.e_prev = e_prev.p;
+  d.mts = mts.p;
+  d.err = err.p;
+  d.status = status.p;
+  d.niter = niter.p;
+  d.nhist = nhist.p;
+  return d;
+}
+
+void Ctx::build_matrices(Batch& b) {
+  DevBatch db = b.dev();
+  hipLaunchKernelGGL(k_build_system, dim3(b.nsys), dim3(256), 0, stream, dev_system(), db, nullptr);
+  check(hipGetLastError(), "k_build_system");
+}
+
+// SCC for the systems in `list` (indices into the batch).  q_in must hold the
+// initial charges; `cold` builds the first basis from the Cholesky factor of S,
+// otherwise the eigenvectors of the previous solve are reused.
+// Returns the number of systems that failed to converge.
+int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* iters_out) {
+  if (list.empty()) return 0;
+  DevBatch db = b.dev();
+  DevSystem ds = dev_system();
+  const int nl = (int)list.size();
+  // reset per-system iteration state on the device
+  b.d_list.upload(list);
+  hipLaunchKernelGGL(k_reset_state, dim3((nl + 255) / 256), dim3(256), 0, stream, db, b.d_list.p, nl);
+  check(hipGetLastError(), "k_reset_state");
+  if (cold) {
+    hipLaunchKernelGGL(k_cholinv, dim3(nl), dim3(256), 0, stream, db, b.d_list.p);
+    check(hipGetLastError(), "k_cholinv");
+  }
+  std::vector<int> active = list;
+  std::vector<int> status(b.nsys);
+  std::vector<int> niter(b.nsys);
+  DevBuf<int> d_act;
+  for (int it = 0; it < opt.max_iter + 1 && !active.empty(); ++it) {
+    d_act.upload(active);
+    const int na = (int)active.size();
+    const int nt = (b.max_nao + 31) / 32;
+    hipLaunchKernelGGL(k_fock, dim3(na), dim3(256), 0, stream, ds, db, d_act.p);
+    hipLaunchKernelGGL(k_gemm, dim3(nt * nt, na), dim3(256), 0, stream, db, d_act.p, 0, b.Ct.p, b.Fm.p, b.Tm.p,
+                       (const double*)nullptr);
+    hipLaunchKernelGGL(k_gemm, dim3(nt * nt, na), dim3(256), 0, stream, db, d_act.p, 1, b.Tm.p, b.Ct.p, b.Fm.p,
+                       (const double*)nullptr);
+    hipLaunchKernelGGL(k_jacobi, dim3(na), dim3(256), 0, stream, db, d_act.p, jacobi_max_sweeps, jacobi_tol,
+                       b.sweeps.p);
+    hipLaunchKernelGGL(k_fermi, dim3(na), dim3(256), 0, stream, ds, db, d_act.p);
+    hipLaunchKernelGGL(k_gemm, dim3(nt * nt, na), dim3(256), 0, stream, db, d_act.p, 2, b.Ct.p, b.Ct.p, b.Pm.p,
+                       (const double*)b.occ.p);
+    hipLaunchKernelGGL(k_charges_mix, dim3(na), dim3(256), 0, stream, ds, db, d_act.p, opt.scc_tol,
+                       opt.energy_tol, opt.max_iter, mix_beta);
+    check(hipGetLastError(), "scc iteration");
+    b.status.download(status, stream);
+    sync();
+    std::vector<int> next;
+    for (int s : active)
+      if (status[s] == 0) next.push_back(s);
+    active.swap(next);
+  }
+  b.status.download(status, stream);
+  b.niter.download(niter, stream);
+  sync();
+  int failed = 0;
+  long long iters = 0;
+  for (int s : list) {
+    if (status[s] != 1) ++failed;
+    iters += niter[s];
+  }
+  if (iters_out) *iters_out += iters;
+  return failed;
+}
+
+// solve a batch either all at once or one system at a time
+int Ctx::solve_batch(Batch& b, bool cold, long long* iters_out) {
+  int failed = 0;
+  if (opt.schedule == FX_PLAIN_LOOP) {
+    for (int s = 0; s < b.nsys; ++s) failed += run_scc(b, std::vector<int>{s}, cold, iters_out);
+  } else {
+    std::vector<int> all(b.nsys);
+    for (int s = 0; s < b.nsys; ++s) all[s] = s;
+    failed += run_scc(b, all, cold, iters_out);
+  }
+  return failed;
+}
+
+void Ctx::field(const double* d_q, double* d_phi) {
+  const int nchunk = std::max(1, std::min(64, (N + 255) / 256 > 0 ? 2048 / ((N + 255) / 256) : 1));
+  if ((long long)nchunk * Nsh > field_part.n) field_part.alloc((long long)nchunk * Nsh);
+  dim3 grid((N + 255) / 256, nchunk);
+  hipLaunchKernelGGL(k_field_partial, grid, dim3(256), 0, stream, dev_system(), d_q, nchunk, field_part.p);
+  hipLaunchKernelGGL(k_field_reduce, dim3((Nsh + 255) / 256), dim3(256), 0, stream, Nsh, nchunk, field_part.p,
+                     d_phi);
+  check(hipGetLastError(), "field");
+}
+
+void Ctx::compute_cn() {
+  hipLaunchKernelGGL(k_cn, dim3((N + 255) / 256), dim3(256), 0, stream, dev_system(), d_cn.p);
+  check(hipGetLastError(), "k_cn");
+}
+
+void Ctx::build_lists_impl() {
+  const long long npair = (long long)F * (F - 1) / 2;
+  DevBuf<int8_t> flag;
+  flag.alloc(std::max(1LL, npair));
+  if (F > 1) {
+    hipLaunchKernelGGL(k_pair_contacts, dim3(F), dim3(256), 0, stream, dev_system(), d_frag_atoms.p, d_frag_off.p,
+                       opt.cutoff_bohr * opt.cutoff_bohr, flag.p);
+    check(hipGetLastError(), "k_pair_contacts");
+  }
+  std::vector<int8_t> h(npair);
+  if (npair) flag.download(h, stream);
+  sync();
+  scc_pairs.clear();
+  esd_pairs.clear();
+  trimers.clear();
+  std::vector<std::vector<int>> nb(F);
+  long long k = 0;
+  for (int I = 0; I < F; ++I)
+    for (int J = I + 1; J < F; ++J, ++k) {
+      if (h[k]) {
+        scc_pairs.push_back(I);
+        scc_pairs.push_back(J);
+        nb[I].push_back(J);
+        nb[J].push_back(I);
+      } else {
+        esd_pairs.push_back(I);
+        esd_pairs.push_back(J);
+      }
+    }
+  if (opt.order >= 3) {
+    // trimers I<J<K with at least two SCC sub-pairs: every such trimer has a
+    // fragment adjacent to both others; enumerate candidates from neighbour lists
+    std::vector<std::vector<char>> adj;
+    auto near = [&](int a, int b) {
+      const std::vector<int>& v = nb[a];
+      return std::binary_search(v.begin(), v.end(), b);
+    };
+    for (auto& v : nb) std::sort(v.begin(), v.end());
+    std::vector<std::array<int, 3>> tri;
+    for (int c = 0; c < F; ++c) {
+      const std::vector<int>& v = nb[c];
+      for (size_t x = 0; x < v.size(); ++x)
+        for (size_t y = x + 1; y < v.size(); ++y) {
+          std::array<int, 3> t = {c, v[x], v[y]};
+          std::sort(t.begin(), t.end());
+          tri.push_back(t);
+        }
+    }
+    std::sort(tri.begin(), tri.end());
+    tri.erase(std::unique(tri.begin(), tri.end()), tri.end());
+    for (auto& t : tri) {
+      int cnt = (int)near(t[0], t[1]) + (int)near(t[0], t[2]) + (int)near(t[1], t[2]);
+      if (cnt >= 2) {
+        trimers.push_back(t[0]);
+        trimers.push_back(t[1]);
+        trimers.push_back(t[2]);
+      }
+    }
+  }
+  lists_built = true;
+}
+
+void Ctx::set_system(int32_t n_atoms, const int32_t* Z, const double* xyz, int32_t n_frag, const int32_t* atom_frag,
+                     const int32_t* fchg) {
+  if (n_atoms <= 0 || n_frag <= 0 || !Z || !xyz || !atom_frag || !fchg) throw FxError(FX_E_INVALID, "bad system");
+  N = n_atoms;
+  F = n_frag;
+  elem.assign(N, 0);
+  frag.assign(atom_frag, atom_frag + N);
+  frag_charge.assign(fchg, fchg + F);
+  xyz_h.assign(xyz, xyz + 3 * N);
+  for (int A = 0; A < N; ++A) {
+    auto it = P.elem_of_Z.find(Z[A]);
+    if (it == P.elem_of_Z.end()) throw FxError(FX_E_UNSUPPORTED, "no parameters for Z=" + std::to_string(Z[A]));
+    elem[A] = it->second;
+    if (frag[A] < 0 || frag[A] >= F) throw FxError(FX_E_INVALID, "atom fragment index out of range");
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(xyz[3 * A + k])) throw FxError(FX_E_INVALID, "non-finite coordinate");
+  }
+  // atoms closer than 0.3 bohr (cell grid)
+  {
+    const double cs = 2.0;
+    std::map<std::array<long long, 3>, std::vector<int>> grid;
+    for (int A = 0; A < N; ++A) {
+      std::array<long long, 3> key = {(long long)std::floor(xyz[3 * A] / cs), (long long)std::floor(xyz[3 * A + 1] / cs),
+                                      (long long)std::floor(xyz[3 * A + 2] / cs)};
+      for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dz = -1; dz <= 1; ++dz) {
+            auto it = grid.find({key[0] + dx, key[1] + dy, key[2] + dz});
+            if (it == grid.end()) continue;
+            for (int B : it->second) {
+              double r2 = 0.0;
+              for (int k = 0; k < 3; ++k) r2 += (xyz[3 * A + k] - xyz[3 * B + k]) * (xyz[3 * A + k] - xyz[3 * B + k]);
+              if (r2 < 0.09) throw FxError(FX_E_INVALID, "atoms closer than 0.3 bohr");
+            }
+          }
+      grid[key].push_back(A);
+    }
+  }
+  // fragments: atoms in ascending order
+  frag_off.assign(F + 1, 0);
+  for (int A = 0; A < N; ++A) frag_off[frag[A] + 1]++;
+  for (int I = 0; I < F; ++I) {
+    if (frag_off[I + 1] == 0) throw FxError(FX_E_INVALID, "empty fragment");
+    frag_off[I + 1] += frag_off[I];
+  }
+  frag_atoms.assign(N, 0);
+  std::vector<int> fill(frag_off.begin(), frag_off.end() - 1);
+  for (int A = 0; A < N; ++A) frag_atoms[fill[frag[A]]++] = A;
+  // shells
+  atom_sh0_g.assign(N + 1, 0);
+  std::vector<int> sh_atom, sh_frag;
+  std::vector<double> sh_eta;
+  for (int A = 0; A < N; ++A) {
+    const DevElem& el = P.elems[elem[A]];
+    for (int s = 0; s < el.nsh; ++s) {
+      sh_atom.push_back(A);
+      sh_frag.push_back(frag[A]);
+      sh_eta.push_back(el.eta[s]);
+    }
+    atom_sh0_g[A + 1] = (int)sh_atom.size();
+  }
+  Nsh = (int)sh_atom.size();
+  d_xyz.upload(xyz_h);
+  d_elem.upload(elem);
+  d_frag.upload(frag);
+  d_atom_sh0.upload(atom_sh0_g);
+  d_sh_atom.upload(sh_atom);
+  d_sh_frag.upload(sh_frag);
+  d_sh_eta.upload(sh_eta);
+  d_frag_atoms.upload(frag_atoms);
+  d_frag_off.upload(frag_off);
+  d_cn.alloc(N);
+  d_q.alloc(Nsh);
+  d_qnew.alloc(Nsh);
+  d_phi.alloc(Nsh);
+  d_scalar.alloc(8);
+  guess.assign(Nsh, 0.0);
+  has_system = true;
+  lists_built = false;
+  has_result = false;
+  has_grad = false;
+}
+
+// ---------------------------------------------------------------------------
+
+void Ctx::run(fx_result* out) {
+  if (!has_system) throw FxError(FX_E_STATE, "no system set");
+  if (opt.precision != FX_FP64) throw FxError(FX_E_UNSUPPORTED, "only FX_FP64 is available");
+  std::memset(&res, 0, sizeof(res));
+  bool all_conv = true;
+  double t0 = now_ms();
+  if (!lists_built) build_lists_impl();
+  compute_cn();
+  sync();
+  double t1 = now_ms();
+  res.ms_lists = t1 - t0;
+
+  // ---- monomers: self-consistent embedding (Jacobi sweeps over monomers)
+  std::vector<std::array<int, 3>> mono(F);
+  for (int I = 0; I < F; ++I) mono[I] = {I, -1, -1};
+  build_batch(mb, mono, 1);
+  build_matrices(mb);
+  DevBatch dmb = mb.dev();
+  if (opt.guess == FX_GUESS_USER) d_q.upload_async(guess, stream);
+  else check(hipMemsetAsync(d_q.p, 0, sizeof(double) * Nsh, stream), "memset");
+  hipLaunchKernelGGL(k_gather_shell, dim3(mb.nsys), dim3(64), 0, stream, dmb, d_q.p, mb.q_in.p);
+  long long it_mono = 0;
+  int macro = 0;
+  double delta = 1e300;
+  bool cold = true;
+  for (macro = 1; macro <= opt.max_macro; ++macro) {
+    field(d_q.p, d_phi.p);
+    hipLaunchKernelGGL(k_gather_shell, dim3(mb.nsys), dim3(64), 0, stream, dmb, d_phi.p, mb.phi.p);
+    hipLaunchKernelGGL(k_gather_shell, dim3(mb.nsys), dim3(64), 0, stream, dmb, d_q.p, mb.q_in.p);
+    int failed = solve_batch(mb, cold, &it_mono);
+    cold = false;
+    res.solves_mono += mb.nsys;
+    if (failed) all_conv = false;
+    hipLaunchKernelGGL(k_scatter_shell, dim3(mb.nsys), dim3(64), 0, stream, dmb, mb.q_out.p, d_qnew.p);
+    hipLaunchKernelGGL(k_max_absdiff, dim3(1), dim3(256), 0, stream, d_qnew.p, d_q.p, Nsh, d_scalar.p);
+    check(hipMemcpyAsync(d_q.p, d_qnew.p, sizeof(double) * Nsh, hipMemcpyDeviceToDevice, stream), "copy");
+    std::vector<double> hs(1);
+    d_scalar.download(hs, stream, 1);
+    sync();
+    delta = hs[0];
+    if (delta < opt.macro_tol) break;
+  }
+  if (macro > opt.max_macro) {
+    all_conv = false;
+    macro = opt.max_macro;
+  }
+  res.macro_iter = macro;
+  res.iters_mono = it_mono;
+  // final embedding field of the converged charges
+  field(d_q.p, d_phi.p);
+  e_mono.alloc(F);
+  check(hipMemcpyAsync(e_mono.p, mb.e_int.p, sizeof(double) * F, hipMemcpyDeviceToDevice, stream), "copy");
+  sync();
+  double t2 = now_ms();
+  res.ms_monomer = t2 - t1;
+
+  // ---- SCC dimers (and trimers) in the converged embedding
+  const long long nscc = (long long)scc_pairs.size() / 2;
+  dE_scc.alloc(std::max(1LL, nscc));
+  dEV_scc.alloc(std::max(1LL, nscc));
+  if (nscc > 0) {
+    std::vector<std::array<int, 3>> cl(nscc);
+    for (long long k = 0; k < nscc; ++k) cl[k] = {scc_pairs[2 * k], scc_pairs[2 * k + 1], -1};
+    build_batch(db_, cl, 2);
+    build_matrices(db_);
+    DevBatch ddb = db_.dev();
+    hipLaunchKernelGGL(k_cluster_phi, dim3(db_.nsys), dim3(128), 0, stream, dev_system(), ddb, d_phi.p, d_q.p);
+    hipLaunchKernelGGL(k_gather_shell, dim3(db_.nsys), dim3(64), 0, stream, ddb, d_q.p, db_.q_in.p);
+    long long itd = 0;
+    int failed = solve_batch(db_, true, &itd);
+    if (failed) all_conv = false;
+    res.solves_dimer = nscc;
+    res.iters_dimer = itd;
+    ddq_scc.alloc(db_.tot_sh);
+    hipLaunchKernelGGL(k_cluster_terms, dim3(db_.nsys), dim3(256), 0, stream, ddb, d_q.p, e_mono.p, ddq_scc.p,
+                       dEV_scc.p, dE_scc.p);
+    check(hipGetLastError(), "k_cluster_terms");
+  }
+  sync();
+  double t3 = now_ms();
+  res.ms_dimer = t3 - t2;
+
+  const long long ntri = (long long)trimers.size() / 3;
+  dE_tri.alloc(std::max(1LL, ntri));
+  if (opt.order >= 3 && ntri > 0) {
+    std::vector<std::array<int, 3>> cl(ntri);
+    for (long long k = 0; k < ntri; ++k) cl[k] = {trimers[3 * k], trimers[3 * k + 1], trimers[3 * k + 2]};
+    build_batch(tb_, cl, 3);
+    build_matrices(tb_);
+    DevBatch dtb = tb_.dev();
+    hipLaunchKernelGGL(k_cluster_phi, dim3(tb_.nsys), dim3(128), 0, stream, dev_system(), dtb, d_phi.p, d_q.p);
+    hipLaunchKernelGGL(k_gather_shell, dim3(tb_.nsys), dim3(64), 0, stream, dtb, d_q.p, tb_.q_in.p);
+    long long itt = 0;
+    int failed = solve_batch(tb_, true, &itt);
+    if (failed) all_conv = false;
+    res.solves_trimer = ntri;
+    res.iters_trimer = itt;
+    DevBuf<double> ddq, dEV, dEX;
+    ddq.alloc(tb_.tot_sh);
+    dEV.alloc(ntri);
+    dEX.alloc(ntri);
+    hipLaunchKernelGGL(k_cluster_terms, dim3(tb_.nsys), dim3(256), 0, stream, dtb, d_q.p, e_mono.p, ddq.p, dEV.p,
+                       dEX.p);
+    trimer_dEIJK.resize(ntri);
+    dEX.download(trimer_dEIJK, stream);
+    sync();
+  }
+  double t4 = now_ms();
+  res.ms_trimer = t4 - t3;
+
+  // ---- ES-DIM pairs and the energy
+  const long long nesd = (long long)esd_pairs.size() / 2;
+  dE_esd.alloc(std::max(1LL, nesd));
+  if (nesd > 0) {
+    DevBuf<int> dp;
+    dp.upload(esd_pairs);
+    hipLaunchKernelGGL(k_esd_pairs, dim3((unsigned)((nesd + 127) / 128)), dim3(128), 0, stream, dev_system(), dp.p,
+                       nesd, d_frag_atoms.p, d_frag_off.p, d_q.p, dE_esd.p);
+    check(hipGetLastError(), "k_esd_pairs");
+    sync();
+  }
+  {
+    std::vector<const double*> arr = {e_mono.p, dE_scc.p, dE_esd.p};
+    std::vector<long long> len = {F, nscc, nesd};
+    DevBuf<const double*> da;
+    da.upload(arr);
+    DevBuf<long long> dl;
+    dl.upload(len);
+    hipLaunchKernelGGL(k_sum_neumaier, dim3(1), dim3(256), 0, stream, da.p, dl.p, 3, d_scalar.p);
+    std::vector<double> hs(1);
+    d_scalar.download(hs, stream, 1);
+    sync();
+    res.e_fmo2 = hs[0];
+    res.e_total = hs[0];
+  }
+  if (opt.order >= 3 && ntri > 0) {
+    // trimer corrections Delta E_IJK - Delta E_IJ - Delta E_IK - Delta E_JK
+    std::vector<double> h_scc(nscc), h_esd(nesd);
+    if (nscc) dE_scc.download(h_scc, stream);
+    if (nesd) dE_esd.download(h_esd, stream);
+    sync();
+    std::vector<double> corr(ntri);
+    auto pair_index = [&](int I, int J) -> long long { return (long long)I * F - (long long)I * (I + 1) / 2 + (J - I - 1); };
+    std::vector<double> pair_dE((size_t)F * (F - 1) / 2, 0.0);
+    for (long long k = 0; k < nscc; ++k) pair_dE[pair_index(scc_pairs[2 * k], scc_pairs[2 * k + 1])] = h_scc[k];
+    for (long long k = 0; k < nesd; ++k) pair_dE[pair_index(esd_pairs[2 * k], esd_pairs[2 * k + 1])] = h_esd[k];
+    for (long long k = 0; k < ntri; ++k) {
+      int I = trimers[3 * k], J = trimers[3 * k + 1], K = trimers[3 * k + 2];
+      corr[k] = trimer_dEIJK[k] - pair_dE[pair_index(I, J)] - pair_dE[pair_index(I, K)] - pair_dE[pair_index(J, K)];
+    }
+    dE_tri.upload(corr);
+    std::vector<const double*> arr = {d_scalar.p, dE_tri.p};
+    std::vector<long long> len = {1, ntri};
+    DevBuf<const double*> da;
+    da.upload(arr);
+    DevBuf<long long> dl;
+    dl.upload(len);
+    DevBuf<double> outv;
+    outv.alloc(1);
+    hipLaunchKernelGGL(k_sum_neumaier, dim3(1), dim3(256), 0, stream, da.p, dl.p, 2, outv.p);
+    std::vector<double> hs(1);
+    outv.download(hs, stream, 1);
+    sync();
+    res.e_total = hs[0];
+  }
+  double t5 = now_ms();
+  res.ms_energy = t5 - t4;
+  res.converged = all_conv ? 1 : 0;
+  has_result = true;
+  has_grad = false;
+  if (opt.want_gradient && opt.order == 2) {
+    gradient();
+    has_grad = true;
+  }
+  res.ms_gradient = now_ms() - t5;
+  if (out) *out = res;
+}
+
+}  // namespace fx
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+struct fx_ctx {
+  fx::Ctx c;
+};
+
+static thread_local std::string g_param_error;
+
+#define FX_GUARD(ctx, ...)                                   \
+  try {                                                      \
+    __VA_ARGS__;                                             \
+    (ctx)->c.last_error.clear();                             \
+    return FX_OK;                                            \
+  } catch (const fx::FxError& e) {                           \
+    (ctx)->c.last_error = e.what();                          \
+    return e.code;                                           \
+  } catch (const std::exception& e) {                        \
+    (ctx)->c.last_error = e.what();                          \
+    return FX_E_INVALID;                                     \
+  }
+
+extern "C" {
+
+int fx_params_load(const char* json_path, fx_params** out) {
+  if (!json_path || !out) return FX_E_INVALID;
+  try {
+    auto* p = new fx_params();
+    p->P = fx::load_params(json_path);
+    *out = p;
+    return FX_OK;
+  } catch (const fx::FxError& e) {
+    g_param_error = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    g_param_error = e.what();
+    return FX_E_INVALID;
+  }
+}
+
+void fx_params_free(fx_params* p) { delete p; }
+
+int fx_ctx_create(const fx_params* p, int device, void* hip_stream, fx_ctx** out) {
+  if (!p || !out) return FX_E_INVALID;
+  auto* c = new fx_ctx();
+  try {
+    c->c.P = p->P;
+    c->c.device = device;
+    fx::Ctx::check(hipSetDevice(device), "hipSetDevice");
+    c->c.stream = static_cast<hipStream_t>(hip_stream);
+    c->c.d_elems.upload(c->c.P.elems);
+    fx_default_options(&c->c.opt);
+  } catch (const fx::FxError& e) {
+    delete c;
+    return e.code;
+  }
+  *out = c;
+  return FX_OK;
+}
+
+void fx_ctx_destroy(fx_ctx* ctx) { delete ctx; }
+
+const char* fx_last_error(const fx_ctx* ctx) { return ctx ? ctx->c.last_error.c_str() : g_param_error.c_str(); }
+
+int fx_default_options(fx_options* o) {
+  if (!o) return FX_E_INVALID;
+  o->order = 2;
+  o->cutoff_bohr = 4.0 / 0.529177210903;
+  o->precision = FX_FP64;
+  o->schedule = FX_BATCHED;
+  o->guess = FX_GUESS_SUPERPOSITION;
+  o->scc_tol = 1e-10;
+  o->energy_tol = 1e-11;
+  o->macro_tol = 1e-10;
+  o->max_iter = 200;
+  o->max_macro = 200;
+  o->want_gradient = 1;
+  o->want_response = 1;
+  return FX_OK;
+}
+
+int fx_set_options(fx_ctx* ctx, const fx_options* o) {
+  if (!ctx || !o) return FX_E_INVALID;
+  FX_GUARD(ctx, {
+    if (o->order != 2 && o->order != 3) throw fx::FxError(FX_E_INVALID, "order must be 2 or 3");
+    if (!(o->cutoff_bohr >= 0.0) || !(o->scc_tol > 0.0) || !(o->macro_tol > 0.0) || o->max_iter < 1 ||
+        o->max_macro < 1)
+      throw fx::FxError(FX_E_INVALID, "bad option value");
+    if (o->precision != FX_FP64 && o->precision != FX_MIXED) throw fx::FxError(FX_E_INVALID, "bad precision");
+    bool cutoff_changed = o->cutoff_bohr != ctx->c.opt.cutoff_bohr || o->order != ctx->c.opt.order;
+    ctx->c.opt = *o;
+    if (cutoff_changed) ctx->c.lists_built = false;
+  });
+}
+
+int fx_set_system(fx_ctx* ctx, int32_t n_atoms, const int32_t* Z, const double* xyz_bohr, int32_t n_frag,
+                  const int32_t* atom_frag, const int32_t* frag_charge) {
+  if (!ctx) return FX_E_INVALID;
+  FX_GUARD(ctx, ctx->c.set_system(n_atoms, Z, xyz_bohr, n_frag, atom_frag, frag_charge));
+}
+
+int fx_build_lists(fx_ctx* ctx, fx_counts* out) {
+  if (!ctx) return FX_E_INVALID;
+  FX_GUARD(ctx, {
+    if (!ctx->c.has_system) throw fx::FxError(FX_E_STATE, "no system set");
+    ctx->c.build_lists_impl();
+    if (out) {
+      out->n_scc_pairs = (int64_t)ctx->c.scc_pairs.size() / 2;
+      out->n_esd_pairs = (int64_t)ctx->c.esd_pairs.size() / 2;
+      out->n_trimers = (int64_t)ctx->c.trimers.size() / 3;
+      out->n_shells = ctx->c.Nsh;
+      out->n_fragments = ctx->c.F;
+    }
+  });
+}
+
+int fx_get_counts(fx_ctx* ctx, fx_counts* out) {
+  if (!ctx || !out) return FX_E_INVALID;
+  FX_GUARD(ctx, {
+    if (!ctx->c.lists_built) throw fx::FxError(FX_E_STATE, "lists not built");
+    out->n_scc_pairs = (int64_t)ctx->c.scc_pairs.size() / 2;
+    out->n_esd_pairs = (int64_t)ctx->c.esd_pairs.size() / 2;
+    out->n_trimers = (int64_t)ctx->c.trimers.size() / 3;
+    out->n_shells = ctx->c.Nsh;
+    out->n_fragments = ctx->c.F;
+  });
+}
+
+int fx_get_lists(fx_ctx* ctx, int32_t* scc, int32_t* esd, int32_t* tri) {
+  if (!ctx) return FX_E_INVALID;
+  FX_GUARD(ctx, {
+    if (!ctx->c.lists_built) throw fx::FxError(FX_E_STATE, "lists not built");
+    if (scc) std::copy(ctx->c.scc_pairs.begin(), ctx->c.scc_pairs.end(), scc);
+    if (esd) std::copy(ctx->c.esd_pairs.begin(), ctx->c.esd_pairs.end(), esd);
+    if (tri) std::copy(ctx->c.trimers.begin(), ctx->c.trimers.end(), tri);
+  });
+}
+
+int fx_set_guess(fx_ctx* ctx, const double* dq) {
+  if (!ctx || !dq) return FX_E_INVALID;
+  FX_GUARD(ctx, {
+    if (!ctx->c.has_system) throw fx::FxError(FX_E_STATE, "no system set");
+    ctx->c.guess.assign(dq, dq + ctx->c.Nsh);
+  });
+}
+
+int fx_run(fx_ctx* ctx, fx_result* out) {
+  if (!ctx) return FX_E_INVALID;
+  try {
+    ctx->c.run(out);
+    ctx->c.last_error.clear();
+    if (!ctx->c.res.converged) {
+      ctx->c.last_error = "a fragment SCC or the monomer loop did not converge";
+      return FX_E_NOCONV;
+    }
+    return FX_OK;
+  } catch (const fx::FxError& e) {
+    ctx->c.last_error = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    ctx->c.last_error = e.what();
+    return FX_E_INVALID;
+  }
+}
+
+int fx_get_energies(fx_ctx* ctx, double* E_mono, double* dE_scc, double* dE_esd, double* dE_tri) {
+  if (!ctx) return FX_E_INVALID;
+  FX_GUARD(ctx, {
+    fx::Ctx& c = ctx->c;
+    if (!c.has_result) throw fx::FxError(FX_E_STATE, "no result");
+    const long long nscc = (long long)c.scc_pairs.size() / 2, nesd = (long long)c.esd_pairs.size() / 2,
+                    ntri = (long long)c.trimers.size() / 3;
+    if (E_mono) c.e_mono.download_raw(E_mono, c.F, c.stream);
+    if (dE_scc && nscc) c.dE_scc.download_raw(dE_scc, nscc, c.stream);
+    if (dE_esd && nesd) c.dE_esd.download_raw(dE_esd, nesd, c.stream);
+    if (dE_tri && ntri && c.opt.order >= 3) c.dE_tri.download_raw(dE_tri, ntri, c.stream);
+    c.sync();
+  });
+}
+
+int fx_get_charges(fx_ctx* ctx, double* dq) {
+  if (!ctx || !dq) return FX_E_INVALID;
+  FX_GUARD(ctx, {
+    if (!ctx->c.has_result) throw fx::FxError(FX_E_STATE, "no result");
+    ctx->c.d_q.download_raw(dq, ctx->c.Nsh, ctx->c.stream);
+    ctx->c.sync();
+  });
+}
+
+int fx_get_gradient(fx_ctx* ctx, double* grad) {
+  if (!ctx || !grad) return FX_E_INVALID;
+  FX_GUARD(ctx, {
+    if (!ctx->c.has_grad) throw fx::FxError(FX_E_STATE, "no gradient computed");
+    ctx->c.d_grad.download_raw(grad, 3LL * ctx->c.N, ctx->c.stream);
+    ctx->c.sync();
+  });
+}
+
+int fx_compute_cn(fx_ctx* ctx, double* cn) {
+  if (!ctx || !cn) return FX_E_INVALID;
+  FX_GUARD(ctx, {
+    if (!ctx->c.has_system) throw fx::FxError(FX_E_STATE, "no system set");
+    ctx->c.compute_cn();
+    ctx->c.d_cn.download_raw(cn, ctx->c.N, ctx->c.stream);
+    ctx->c.sync();
+  });
+}
+
+int fx_cluster_matrices(fx_ctx* ctx, int32_t nfrag, const int32_t* frags, int32_t* nao_out, double* S, double* H0) {
+  if (!ctx || !frags || nfrag < 1 || nfrag > 3) return FX_E_INVALID;
+  FX_GUARD(ctx, {
+    fx::Ctx& c = ctx->c;
+    if (!c.has_system) throw fx::FxError(FX_E_STATE, "no system set");
+    std::array<int, 3> cl = {-1, -1, -1};
+    for (int k = 0; k < nfrag; ++k) {
+      if (frags[k] < 0 || frags[k] >= c.F) throw fx::FxError(FX_E_INVALID, "fragment index out of range");
+      cl[k] = frags[k];
+    }
+    fx::Batch b;
+    c.build_batch(b, {cl}, nfrag);
+    int nao = b.h_desc[0].nao;
+    if (nao_out) *nao_out = nao;
+    if (S || H0) {
+      c.compute_cn();
+      c.build_matrices(b);
+      if (S) b.S.download_raw(S, (long long)nao * nao, c.stream);
+      if (H0) b.H0.download_raw(H0, (long long)nao * nao, c.stream);
+      c.sync();
+    }
+  });
+}
+
+int fx_embedding_field(fx_ctx* ctx, const double* dq, double* phi) {
+  if (!ctx || !dq || !phi) return FX_E_INVALID;
+  FX_GUARD(ctx, {
+    fx::Ctx& c = ctx->c;
+    if (!c.has_system) throw fx::FxError(FX_E_STATE, "no system set");
+    fx::DevBuf<double> q, p;
+    q.upload(std::vector<double>(dq, dq + c.Nsh));
+    p.alloc(c.Nsh);
+    c.field(q.p, p.p);
+    p.download_raw(phi, c.Nsh, c.stream);
+    c.sync();
+  });
+}
+
+int fx_eigh_batched(fx_ctx* ctx, int32_t nmat, const int32_t* n, const double* A, double* w, double* V) {
+  if (!ctx || nmat < 0 || !n || !A || !w || !V) return FX_E_INVALID;
+  FX_GUARD(ctx, {
+    fx::Ctx& c = ctx->c;
+    std::vector<int> nv(n, n + nmat);
+    std::vector<long long> off(nmat), woff(nmat);
+    long long tot = 0, wt = 0;
+    for (int k = 0; k < nmat; ++k) {
+      if (nv[k] < 1 || nv[k] > fx::MAXN) throw fx::FxError(FX_E_INVALID, "matrix size out of range");
+      off[k] = tot;
+      woff[k] = wt;
+      tot += (long long)nv[k] * nv[k];
+      wt += nv[k];
+    }
+    if (nmat == 0) return FX_OK;
+    fx::DevBuf<int> dn;
+    dn.upload(nv);
+    fx::DevBuf<long long> doff, dwoff;
+    doff.upload(off);
+    dwoff.upload(woff);
+    fx::DevBuf<double> dA, dV, dw;
+    dA.upload(std::vector<double>(A, A + tot));
+    dV.alloc(tot);
+    dw.alloc(wt);
+    hipLaunchKernelGGL(fx::k_eigh_batched, dim3(nmat), dim3(256), 0, c.stream, dn.p, doff.p, dA.p, dV.p, dw.p, dwoff.p,
+                       60, 1e-15);
+    fx::Ctx::check(hipGetLastError(), "k_eigh_batched");
+    dw.download_raw(w, wt, c.stream);
+    dV.download_raw(V, tot, c.stream);
+    c.sync();
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Device-side data layout shared by the HIP kernels and the host driver.
+//
+// Atoms, shells and AOs of the supersystem are stored structure-of-arrays in
+// HBM.  A "system" is one fragment calculation (monomer, dimer or trimer);
+// every system owns dense row-major nao x nao matrices in per-batch pools and
+// per-shell / per-AO vectors, located through SysDesc offsets.
+#pragma once
+
+#include <cstdint>
+
+namespace fx {
+
+constexpr int MAXSH_EL = 2;   // shells per element (minimal s/p basis)
+constexpr int NPRIM = 6;      // STO-6G
+constexpr int MAXAO_EL = 4;   // AOs per element
+constexpr int HIST = 8;       // Anderson mixing memory
+constexpr int MAXN = 512;     // largest system (AOs) handled by the SCC kernels
+
+struct DevElem {
+  int nsh, nao;
+  int l[MAXSH_EL], nao_sh[MAXSH_EL], ao0[MAXSH_EL];
+  double level[MAXSH_EL], kcn[MAXSH_EL], kpoly[MAXSH_EL], eta[MAXSH_EL], q0[MAXSH_EL];
+  double alpha[MAXSH_EL][NPRIM], coef[MAXSH_EL][NPRIM];
+  int orth;                 // second s shell orthogonalised against the first
+  double orthN, orthS12;    // |s2'> = N (|s2> - S12 |s1>)
+  double EN, rcov, Gamma, zeff, arep;
+};
+
+struct DevGlobals {
+  double kg, kf, kEN, k1, k2, kl[3], KAB, kT;
+};
+
+struct SysDesc {
+  int nat, nsh, nao, nfrag;
+  int atom_off;   // into sys_atoms / sys_atom_ao0 / sys_atom_sh0
+  int sh_off;     // into per-system shell vectors
+  int ao_off;     // into per-system AO vectors
+  int frag[3];
+  long long mat_off;  // into n x n pools
+  long long gam_off;  // into the nsh x nsh gamma pool
+  double nel;
+};
+
+// Read-only supersystem tables.
+struct DevSystem {
+  int natoms, nshells, nfrag;
+  const double* xyz;      // [3N]
+  const int* elem;        // [N] element table index
+  const int* frag;        // [N]
+  const int* atom_sh0;    // [N+1] first global shell of each atom
+  const double* cn;       // [N]
+  const int* sh_atom;     // [Nsh]
+  const int* sh_frag;     // [Nsh]
+  const double* sh_eta;   // [Nsh] (1 + kappa) eta_A
+  const DevElem* elems;
+  DevGlobals g;
+};
+
+// Per-batch tables and pools.
+struct DevBatch {
+  int nsys;
+  const SysDesc* desc;
+  const int* sys_atoms;     // global atom of each local atom
+  const int* sys_atom_ao0;  // local AO offset of each local atom
+  const int* sys_atom_sh0;  // local shell offset of each local atom
+  const int* sys_sh_global; // global shell of each local shell
+  const int* sys_sh_atom;   // local atom of each local shell
+  const int* sys_ao_sh;     // local shell of each local AO
+  double* S;
+  double* H0;
+  double* F;     // Fock matrix, then the projected matrix C^T F C
+  double* Ct;    // eigenvectors as rows
+  double* P;
+  double* T;     // GEMM scratch
+  double* gam;   // nsh x nsh gamma of the system
+  double* q_in;
+  double* q_out;
+  double* phi;   // external shell potential
+  double* sig;   // shell shift of the last Fock build
+  double* hx;    // Anderson history of inputs  [sh_off*HIST + k*nsh + s]
+  double* hr;    // Anderson history of residuals
+  double* eps;
+  double* occ;
+  double* erep;
+  double* e_int;
+  double* e_prev;
+  double* mts;   // -T S of the last density
+  double* err;   // max |q_out - q_in| of the last iteration
+  int* status;   // 0 active, 1 converged, 2 failed
+  int* niter;
+  int* nhist;
+};
+
+}  // namespace fx

@@ -1,0 +1,462 @@
+// Kernels of the FMO2 analytic gradient (section "Analytic energy gradients").
+//
+// The gradient is assembled from the energy identity
+//   E = sum_I c_I E^emb_I + sum_SCC E^emb_IJ - sum_ESD dq^I gamma dq^J,
+//   c_I = 1 - (number of SCC dimers containing I),
+// whose fragment terms are stationary in their own densities:
+//  * per fragment system: the single-system gradient of eq. xtb_grad with the
+//    W matrix of eq. W_matrix (sigma containing the embedding potential), the
+//    H0 derivative split of eq. H0_deriv and the CN sensitivity of
+//    eq. cn_factor (k_grad_contract);
+//  * inter-fragment kernel derivatives: ES-DIM (eq. esd_grad), charge-transfer
+//    embedding (eq. ctij) and the response charges (eq. ZxG_inter) in one
+//    N-body force pass over all cross-fragment shell pairs (k_force_inter)
+//    with a per-SCC-dimer correction (k_grad_pair_corr);
+//  * the CN chain of eq. cn_grad over all atoms (k_cn_grad);
+//  * the response: the Lagrangian potential of eq. esp_lagrangian, the
+//    fragment charge response built from the transition charges of
+//    eq. lagrangian, the Z-vector and its AO forms of eqs. Z_AO, WZ_def,
+//    contracted with the derivative integrals as in eqs. ZxHB .. ZxG and
+//    resp_addlag (k_resp_*).
+// Every per-atom sum is formed by one thread in a fixed order (no atomics),
+// so the gradient is bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include "fx_device.hpp"
+#include "fx_kernels.hpp"
+
+namespace fx {
+
+__device__ inline double gamma_and_deriv(const DevGlobals& g, double R, double eta_s, double eta_t, double* dg) {
+  double inv_eta = 0.5 * (1.0 / eta_s + 1.0 / eta_t);
+  if (g.kg == 2.0) {
+    double x = 1.0 / sqrt(R * R + inv_eta * inv_eta);
+    *dg = -R * x * x * x;
+    return x;
+  }
+  double base = pow(R, g.kg) + pow(inv_eta, g.kg);
+  double gam = pow(base, -1.0 / g.kg);
+  *dg = -pow(R, g.kg - 1.0) * pow(base, -1.0 / g.kg - 1.0);
+  return gam;
+}
+
+// overlap block and its derivative with respect to R = A - B
+__device__ void atom_pair_overlap_deriv(const DevElem& ea, const DevElem& eb, const double Rv[3],
+                                        double S[MAXAO_EL][MAXAO_EL], double dS[3][MAXAO_EL][MAXAO_EL]) {
+  const double PI = 3.14159265358979323846;
+  double R2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
+  for (int i = 0; i < MAXAO_EL; ++i)
+    for (int j = 0; j < MAXAO_EL; ++j) {
+      S[i][j] = 0.0;
+      for (int k = 0; k < 3; ++k) dS[k][i][j] = 0.0;
+    }
+  for (int sa = 0; sa < ea.nsh; ++sa)
+    for (int sb = 0; sb < eb.nsh; ++sb) {
+      int la = ea.l[sa], lb = eb.l[sb];
+      int oa = ea.ao0[sa], ob = eb.ao0[sb];
+      for (int i = 0; i < NPRIM; ++i) {
+        double a = ea.alpha[sa][i];
+        for (int j = 0; j < NPRIM; ++j) {
+          double b = eb.alpha[sb][j];
+          double ip = 1.0 / (a + b);
+          double mu = a * b * ip;
+          double s00 = ea.coef[sa][i] * eb.coef[sb][j] * PI * ip * sqrt(PI * ip) * exp(-mu * R2);
+          double ds00[3];
+          for (int k = 0; k < 3; ++k) ds00[k] = -2.0 * mu * Rv[k] * s00;
+          double fa = -b * ip, fb = a * ip;
+          if (la == 0 && lb == 0) {
+            S[oa][ob] += s00;
+            for (int k = 0; k < 3; ++k) dS[k][oa][ob] += ds00[k];
+          } else if (la == 1 && lb == 0) {
+            for (int u = 0; u < 3; ++u) {
+              S[oa + u][ob] += fa * Rv[u] * s00;
+              for (int k = 0; k < 3; ++k) dS[k][oa + u][ob] += (u == k ? fa * s00 : 0.0) + fa * Rv[u] * ds00[k];
+            }
+          } else if (la == 0 && lb == 1) {
+            for (int v = 0; v < 3; ++v) {
+              S[oa][ob + v] += fb * Rv[v] * s00;
+              for (int k = 0; k < 3; ++k) dS[k][oa][ob + v] += (v == k ? fb * s00 : 0.0) + fb * Rv[v] * ds00[k];
+            }
+          } else {
+            double h = 0.5 * ip;
+            for (int u = 0; u < 3; ++u)
+              for (int v = 0; v < 3; ++v) {
+                double core = fa * Rv[u] * fb * Rv[v] + (u == v ? h : 0.0);
+                S[oa + u][ob + v] += core * s00;
+                for (int k = 0; k < 3; ++k) {
+                  double dcore = (u == k ? fa * fb * Rv[v] : 0.0) + (v == k ? fa * Rv[u] * fb : 0.0);
+                  dS[k][oa + u][ob + v] += dcore * s00 + core * ds00[k];
+                }
+              }
+          }
+        }
+      }
+    }
+  if (ea.orth) {
+    int r1 = ea.ao0[0], r2 = ea.ao0[1];
+    for (int j = 0; j < eb.nao; ++j) {
+      S[r2][j] = ea.orthN * (S[r2][j] - ea.orthS12 * S[r1][j]);
+      for (int k = 0; k < 3; ++k) dS[k][r2][j] = ea.orthN * (dS[k][r2][j] - ea.orthS12 * dS[k][r1][j]);
+    }
+  }
+  if (eb.orth) {
+    int c1 = eb.ao0[0], c2 = eb.ao0[1];
+    for (int i = 0; i < ea.nao; ++i) {
+      S[i][c2] = eb.orthN * (S[i][c2] - eb.orthS12 * S[i][c1]);
+      for (int k = 0; k < 3; ++k) dS[k][i][c2] = eb.orthN * (dS[k][i][c2] - eb.orthS12 * dS[k][i][c1]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-system derivative contraction:
+//   d/dR_a [ sum D_H H0 + sum D_S S + 1/2 sum_{s,t} gx_s gamma_st gy_t + E_rep ]
+// at fixed CN, for every atom a of the system, and the CN sensitivity
+// F_a = d/dCN_a of the D_H term.  Results are multiplied by the system weight
+// and written (or added) to the per-system atom arrays.
+__global__ void k_grad_contract(DevSystem sys, DevBatch bt, const int* list, const double* DHp, const double* DSp,
+                                const double* gx, const double* gy, const double* wsys, int with_rep, int accumulate,
+                                double* g_out, double* F_out) {
+  const int si = list[blockIdx.x];
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao, nat = d.nat;
+  const double* DH = DHp + d.mat_off;
+  const double* DS = DSp + d.mat_off;
+  const int* atoms = bt.sys_atoms + d.atom_off;
+  const int* aao = bt.sys_atom_ao0 + d.atom_off;
+  const int* ash = bt.sys_atom_sh0 + d.atom_off;
+  const double cw = wsys ? wsys[si] : 1.0;
+  __shared__ double part[256][4];
+  const int nslice = nat >= (int)blockDim.x ? 1 : (int)blockDim.x / nat;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int a = threadIdx.x % nat, slice0 = threadIdx.x / nat; a < nat && slice0 < nslice; a += blockDim.x) {
+    // (for nat > blockDim each thread strides over atoms with its own accumulator slot)
+    break;
+  }
+  for (int a0 = 0; a0 < nat; a0 += (nslice == 1 ? (int)blockDim.x : nat)) {
+    int a = a0 + (nslice == 1 ? (int)threadIdx.x : (int)threadIdx.x % nat);
+    int slice = nslice == 1 ? 0 : (int)threadIdx.x / nat;
+    double g[3] = {0.0, 0.0, 0.0};
+    double Fa = 0.0;
+    bool active = a < nat && slice < nslice;
+    if (active) {
+      const int A = atoms[a];
+      const DevElem& ea = sys.elems[sys.elem[A]];
+      const double cnA = sys.cn[A];
+      const int oa = aao[a];
+      if (slice == 0) {
+        for (int s = 0; s < ea.nsh; ++s)
+          for (int u = 0; u < ea.nao_sh[s]; ++u) {
+            int mu = oa + ea.ao0[s] + u;
+            Fa += DH[(long long)mu * n + mu] * ea.level[s] * ea.kcn[s];
+          }
+      }
+      for (int b = slice; b < nat; b += nslice) {
+        if (b == a) continue;
+        const int B = atoms[b];
+        const DevElem& eb = sys.elems[sys.elem[B]];
+        const double cnB = sys.cn[B];
+        const int ob = aao[b];
+        double Rv[3] = {sys.xyz[3 * A] - sys.xyz[3 * B], sys.xyz[3 * A + 1] - sys.xyz[3 * B + 1],
+                        sys.xyz[3 * A + 2] - sys.xyz[3 * B + 2]};
+        double R = sqrt(Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2]);
+        double uR[3] = {Rv[0] / R, Rv[1] / R, Rv[2] / R};
+        double S[MAXAO_EL][MAXAO_EL], dS[3][MAXAO_EL][MAXAO_EL];
+        atom_pair_overlap_deriv(ea, eb, Rv, S, dS);
+        double den = ea.EN - eb.EN;
+        double enf = 1.0 + sys.g.kEN * den * den;
+        double rcov = ea.rcov + eb.rcov;
+        double x = sqrt(R / rcov);
+        double dx = 0.5 / sqrt(R * rcov);
+        for (int sa = 0; sa < ea.nsh; ++sa)
+          for (int sb = 0; sb < eb.nsh; ++sb) {
+            double kll = 0.5 * (sys.g.kl[ea.l[sa]] + sys.g.kl[eb.l[sb]]);
+            double ha = ea.level[sa] * (1.0 + ea.kcn[sa] * cnA);
+            double hb = eb.level[sb] * (1.0 + eb.kcn[sb] * cnB);
+            double hav = 0.5 * (ha + hb);
+            double pa = 1.0 + ea.kpoly[sa] * x, pb = 1.0 + eb.kpoly[sb] * x;
+            double Pi = pa * pb;
+            double dPi = (ea.kpoly[sa] * pb + pa * eb.kpoly[sb]) * dx;
+            double base = sys.g.KAB * kll * enf;
+            double fac = base * hav * Pi;
+            double sumDHS = 0.0;
+            for (int u = 0; u < ea.nao_sh[sa]; ++u)
+              for (int v = 0; v < eb.nao_sh[sb]; ++v) {
+                int i = ea.ao0[sa] + u, j = eb.ao0[sb] + v;
+                long long mn = (long long)(oa + i) * n + ob + j;
+                double dh = DH[mn], ds = DS[mn];
+                double w = fac * dh + ds;
+                for (int k = 0; k < 3; ++k) g[k] += 2.0 * w * dS[k][i][j];
+                sumDHS += dh * S[i][j];
+              }
+            double t = 2.0 * sumDHS * base * hav * dPi;
+            for (int k = 0; k < 3; ++k) g[k] += t * uR[k];
+            Fa += 2.0 * sumDHS * base * Pi * 0.5 * ea.level[sa] * ea.kcn[sa];
+          }
+        if (gx) {
+          int s0 = ash[a], t0 = ash[b];
+          for (int sa = 0; sa < ea.nsh; ++sa)
+            for (int sb = 0; sb < eb.nsh; ++sb) {
+              double dg;
+              gamma_and_deriv(sys.g, R, ea.eta[sa], eb.eta[sb], &dg);
+              double c = 0.5 * (gx[d.sh_off + s0 + sa] * gy[d.sh_off + t0 + sb] +
+                                gy[d.sh_off + s0 + sa] * gx[d.sh_off + t0 + sb]);
+              for (int k = 0; k < 3; ++k) g[k] += c * dg * uR[k];
+            }
+        }
+        if (with_rep) {
+          double al = sqrt(ea.arep * eb.arep);
+          double e = ea.zeff * eb.zeff / R * exp(-al * pow(R, sys.g.kf));
+          double de = e * (-1.0 / R - al * sys.g.kf * pow(R, sys.g.kf - 1.0));
+          for (int k = 0; k < 3; ++k) g[k] += de * uR[k];
+        }
+      }
+    }
+    // fixed-order reduction over slices
+    __syncthreads();
+    part[threadIdx.x][0] = g[0];
+    part[threadIdx.x][1] = g[1];
+    part[threadIdx.x][2] = g[2];
+    part[threadIdx.x][3] = Fa;
+    __syncthreads();
+    if (active && slice == 0) {
+      double t[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int sl = 0; sl < nslice; ++sl) {
+        int tid = nslice == 1 ? (int)threadIdx.x : sl * nat + (int)threadIdx.x % nat;
+        for (int k = 0; k < 4; ++k) t[k] += part[tid][k];
+      }
+      long long o = (long long)d.atom_off + a;
+      for (int k = 0; k < 3; ++k) {
+        double v = cw * t[k];
+        g_out[3 * o + k] = accumulate ? g_out[3 * o + k] + v : v;
+      }
+      F_out[o] = accumulate ? F_out[o] + cw * t[3] : cw * t[3];
+    }
+    (void)acc;
+  }
+}
+
+// For an SCC dimer (I, K): remove the cross-fragment pairs of the all-pairs
+// inter-fragment force, c_st = q_s q_t + ddq_s q_t + q_s ddq_t (added to the
+// dimer's atom arrays).
+__global__ void k_grad_pair_corr(DevSystem sys, DevBatch bt, const double* qmono, const double* ddq, double* g_out) {
+  const int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const int nat = d.nat;
+  const int* atoms = bt.sys_atoms + d.atom_off;
+  const int* ash = bt.sys_atom_sh0 + d.atom_off;
+  for (int a = threadIdx.x; a < nat; a += blockDim.x) {
+    const int A = atoms[a];
+    const DevElem& ea = sys.elems[sys.elem[A]];
+    const int fa = sys.frag[A];
+    double g[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < nat; ++b) {
+      const int B = atoms[b];
+      if (sys.frag[B] == fa) continue;
+      const DevElem& eb = sys.elems[sys.elem[B]];
+      double Rv[3] = {sys.xyz[3 * A] - sys.xyz[3 * B], sys.xyz[3 * A + 1] - sys.xyz[3 * B + 1],
+                      sys.xyz[3 * A + 2] - sys.xyz[3 * B + 2]};
+      double R = sqrt(Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2]);
+      for (int sa = 0; sa < ea.nsh; ++sa)
+        for (int sb = 0; sb < eb.nsh; ++sb) {
+          int ls = ash[a] + sa, lt = ash[b] + sb;
+          double qs = qmono[sys.atom_sh0[A] + sa], qt = qmono[sys.atom_sh0[B] + sb];
+          double c = qs * qt + ddq[d.sh_off + ls] * qt + qs * ddq[d.sh_off + lt];
+          double dg;
+          gamma_and_deriv(sys.g, R, ea.eta[sa], eb.eta[sb], &dg);
+          for (int k = 0; k < 3; ++k) g[k] -= c * dg * Rv[k] / R;
+        }
+    }
+    long long o = (long long)d.atom_off + a;
+    for (int k = 0; k < 3; ++k) g_out[3 * o + k] += g[k];
+  }
+}
+
+// All cross-fragment shell pairs: force on atom A from
+//   c_st = q_s (q_t + a_t) + a_s q_t,   s on A, t on B, frag(A) != frag(B)
+// split over source chunks (deterministic reduction afterwards).
+__global__ void k_force_inter(DevSystem sys, const double* q, const double* av, int nchunk, double* part) {
+  int A = blockIdx.x * blockDim.x + threadIdx.x;
+  int chunk = blockIdx.y;
+  int N = sys.natoms;
+  int per = (N + nchunk - 1) / nchunk;
+  int b_begin = chunk * per, b_end = min(N, b_begin + per);
+  __shared__ double sx[256], sy[256], sz[256], seta[256][MAXSH_EL], sq[256][MAXSH_EL], sa_[256][MAXSH_EL];
+  __shared__ int sf[256], sn[256];
+  double xa = 0, ya = 0, za = 0, ea[MAXSH_EL] = {1.0, 1.0}, qa[MAXSH_EL] = {0, 0}, aa[MAXSH_EL] = {0, 0};
+  int fa = -1, na = 0;
+  if (A < N) {
+    xa = sys.xyz[3 * A];
+    ya = sys.xyz[3 * A + 1];
+    za = sys.xyz[3 * A + 2];
+    fa = sys.frag[A];
+    int sh0 = sys.atom_sh0[A];
+    na = sys.atom_sh0[A + 1] - sh0;
+    for (int k = 0; k < na; ++k) {
+      ea[k] = sys.sh_eta[sh0 + k];
+      qa[k] = q[sh0 + k];
+      aa[k] = av[sh0 + k];
+    }
+  }
+  double f[3] = {0.0, 0.0, 0.0};
+  for (int b0 = b_begin; b0 < b_end; b0 += 256) {
+    int b = b0 + threadIdx.x;
+    __syncthreads();
+    if (b < b_end) {
+      sx[threadIdx.x] = sys.xyz[3 * b];
+      sy[threadIdx.x] = sys.xyz[3 * b + 1];
+      sz[threadIdx.x] = sys.xyz[3 * b + 2];
+      sf[threadIdx.x] = sys.frag[b];
+      int s0 = sys.atom_sh0[b];
+      int nsb = sys.atom_sh0[b + 1] - s0;
+      sn[threadIdx.x] = nsb;
+      for (int k = 0; k < MAXSH_EL; ++k) {
+        seta[threadIdx.x][k] = k < nsb ? sys.sh_eta[s0 + k] : 1.0;
+        sq[threadIdx.x][k] = k < nsb ? q[s0 + k] : 0.0;
+        sa_[threadIdx.x][k] = k < nsb ? av[s0 + k] : 0.0;
+      }
+    }
+    __syncthreads();
+    int nb = min(256, b_end - b0);
+    if (A < N) {
+      for (int k = 0; k < nb; ++k) {
+        if (sf[k] == fa) continue;
+        double dx = xa - sx[k], dy = ya - sy[k], dz = za - sz[k];
+        double R = sqrt(dx * dx + dy * dy + dz * dz);
+        double acc = 0.0;
+        for (int u = 0; u < na; ++u)
+          for (int v = 0; v < sn[k]; ++v) {
+            double dg;
+            gamma_and_deriv(sys.g, R, ea[u], seta[k][v], &dg);
+            acc += (qa[u] * (sq[k][v] + sa_[k][v]) + aa[u] * sq[k][v]) * dg;
+          }
+        acc /= R;
+        f[0] += acc * dx;
+        f[1] += acc * dy;
+        f[2] += acc * dz;
+      }
+    }
+  }
+  if (A < N)
+    for (int k = 0; k < 3; ++k) part[((long long)chunk * N + A) * 3 + k] = f[k];
+}
+
+__global__ void k_force_reduce(int N, int nchunk, const double* part, double* out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * N) return;
+  double acc = 0.0;
+  for (int c = 0; c < nchunk; ++c) acc += part[(long long)c * 3 * N + i];
+  out[i] = acc;
+}
+
+// CN chain: g_C = sum_{A != C} (F_A + F_C) f'(R_AC) (R_C - R_A) / R_AC
+__global__ void k_cn_grad(DevSystem sys, const double* Ftot, double* g) {
+  int C = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double sx[256], sy[256], sz[256], sr[256], sF[256];
+  double xc = 0, yc = 0, zc = 0, rc = 0, Fc = 0;
+  if (C < sys.natoms) {
+    xc = sys.xyz[3 * C];
+    yc = sys.xyz[3 * C + 1];
+    zc = sys.xyz[3 * C + 2];
+    rc = sys.elems[sys.elem[C]].rcov;
+    Fc = Ftot[C];
+  }
+  double f[3] = {0.0, 0.0, 0.0};
+  for (int b0 = 0; b0 < sys.natoms; b0 += 256) {
+    int b = b0 + threadIdx.x;
+    __syncthreads();
+    if (b < sys.natoms) {
+      sx[threadIdx.x] = sys.xyz[3 * b];
+      sy[threadIdx.x] = sys.xyz[3 * b + 1];
+      sz[threadIdx.x] = sys.xyz[3 * b + 2];
+      sr[threadIdx.x] = sys.elems[sys.elem[b]].rcov;
+      sF[threadIdx.x] = Ftot[b];
+    }
+    __syncthreads();
+    int nb = min(256, sys.natoms - b0);
+    if (C < sys.natoms) {
+      for (int k = 0; k < nb; ++k) {
+        if (b0 + k == C) continue;
+        double dx = xc - sx[k], dy = yc - sy[k], dz = zc - sz[k];
+        double R = sqrt(dx * dx + dy * dy + dz * dz);
+        double rcs = rc + sr[k];
+        double x = -sys.g.k1 * (sys.g.k2 * rcs / R - 1.0);
+        double fv = 1.0 / (1.0 + exp(x));
+        double dfdR = -fv * (1.0 - fv) * sys.g.k1 * sys.g.k2 * rcs / (R * R);
+        double w = (sF[k] + Fc) * dfdR / R;
+        f[0] += w * dx;
+        f[1] += w * dy;
+        f[2] += w * dz;
+      }
+    }
+  }
+  if (C < sys.natoms)
+    for (int k = 0; k < 3; ++k) g[3 * C + k] = f[k];
+}
+
+// Per-atom gather of the per-system contributions in a fixed order.
+// entries: CSR over atoms of (batch id, local atom offset into that batch's arrays)
+__global__ void k_gather_atoms(int N, const int* rowptr, const int* ent_batch, const long long* ent_off,
+                               const double* const* g_batches, const double* const* F_batches, double* g_tot,
+                               double* F_tot, int mode) {
+  int A = blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= N) return;
+  if (mode == 0) {
+    double F = 0.0;
+    for (int e = rowptr[A]; e < rowptr[A + 1]; ++e) F += F_batches[ent_batch[e]][ent_off[e]];
+    F_tot[A] = F;
+  } else {
+    double g[3] = {g_tot[3 * A], g_tot[3 * A + 1], g_tot[3 * A + 2]};
+    for (int e = rowptr[A]; e < rowptr[A + 1]; ++e) {
+      const double* gb = g_batches[ent_batch[e]];
+      for (int k = 0; k < 3; ++k) g[k] += gb[3 * ent_off[e] + k];
+    }
+    for (int k = 0; k < 3; ++k) g_tot[3 * A + k] = g[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// small per-system helpers
+
+// final shell shift sigma = gamma q_out - Gamma q_A^2 + phi (into sig) and the
+// weights n_i eps_i for the energy-weighted density (into wvec)
+__global__ void k_final_shift(DevSystem sys, DevBatch bt, double* wvec) {
+  const int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  __shared__ double qa[MAXN];
+  const double* q = bt.q_out + d.sh_off;
+  for (int a = threadIdx.x; a < d.nat; a += blockDim.x) {
+    int s0 = bt.sys_atom_sh0[d.atom_off + a];
+    int A = bt.sys_atoms[d.atom_off + a];
+    int nsa = sys.atom_sh0[A + 1] - sys.atom_sh0[A];
+    double v = 0.0;
+    for (int k = 0; k < nsa; ++k) v += q[s0 + k];
+    qa[a] = v;
+  }
+  __syncthreads();
+  const double* G = bt.gam + d.gam_off;
+  for (int s = threadIdx.x; s < d.nsh; s += blockDim.x) {
+    double v = 0.0;
+    for (int t = 0; t < d.nsh; ++t) v += G[(long long)s * d.nsh + t] * q[t];
+    int a = bt.sys_sh_atom[d.sh_off + s];
+    int A = bt.sys_atoms[d.atom_off + a];
+    v += -sys.elems[sys.elem[A]].Gamma * qa[a] * qa[a] + bt.phi[d.sh_off + s];
+    bt.sig[d.sh_off + s] = v;
+  }
+  for (int i = threadIdx.x; i < d.nao; i += blockDim.x) wvec[d.ao_off + i] = bt.occ[d.ao_off + i] * bt.eps[d.ao_off + i];
+}
+
+// D_S = 1/2 (sigma_mu + sigma_nu) P - W  (eq. W_matrix with the embedding in sigma)
+__global__ void k_make_DS(DevBatch bt, const double* P, const double* W, double* out) {
+  const int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao;
+  const int* aosh = bt.sys_ao_sh + d.ao_off;
+  const double* sg = bt.sig + d.sh_off;
+  for (long long idx = threadIdx.x; idx < (long long)n * n; idx += blockDim.x) {
+    int i = (int)(idx / n), j = (int)(idx % n);
+    out[d.mat_off + idx] = 0.5 * (sg[aosh[i]] + sg[aosh[j]]) * P[d.mat_off + idx] - W[d.mat_off + idx];
+  }
+}
+
+}  // namespace fx

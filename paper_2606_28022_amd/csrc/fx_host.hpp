@@ -1,0 +1,151 @@
+// Host-side classes of the library: errors, device buffers, parameters,
+// fragment batches and the context that drives a run.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/fmoxtb.h"
+#include "fx_device.hpp"
+
+namespace fx {
+
+struct FxError : std::runtime_error {
+  int code;
+  FxError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+// Owning device buffer (hipMalloc / hipFree).
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  long long n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) {
+    o.p = nullptr;
+    o.n = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      o.p = nullptr;
+      o.n = 0;
+    }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(long long count) {
+    release();
+    size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      p = nullptr;
+      throw FxError(FX_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    n = count;
+  }
+  void upload(const std::vector<T>& v) {
+    alloc((long long)v.size());
+    if (!v.empty() && hipMemcpy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) != hipSuccess)
+      throw FxError(FX_E_DEVICE, "hipMemcpy H2D failed");
+  }
+  void upload_async(const std::vector<T>& v, hipStream_t s) {
+    if ((long long)v.size() > n) alloc((long long)v.size());
+    if (!v.empty() && hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+      throw FxError(FX_E_DEVICE, "hipMemcpyAsync H2D failed");
+  }
+  void download(std::vector<T>& v, hipStream_t s, long long count = -1) const {
+    long long c = count < 0 ? n : count;
+    v.resize((size_t)c);
+    if (c > 0 && hipMemcpyAsync(v.data(), p, sizeof(T) * c, hipMemcpyDeviceToHost, s) != hipSuccess)
+      throw FxError(FX_E_DEVICE, "hipMemcpyAsync D2H failed");
+  }
+  void download_raw(T* dst, long long count, hipStream_t s) const {
+    if (count > 0 && hipMemcpyAsync(dst, p, sizeof(T) * count, hipMemcpyDeviceToHost, s) != hipSuccess)
+      throw FxError(FX_E_DEVICE, "hipMemcpyAsync D2H failed");
+  }
+};
+
+struct HostParams {
+  DevGlobals g;
+  std::vector<DevElem> elems;
+  std::map<int, int> elem_of_Z;
+};
+
+HostParams load_params(const std::string& path);
+
+struct Batch {
+  int nsys = 0;
+  int max_nao = 0;
+  int tot_sh = 0, tot_ao = 0;
+  long long tot_mat = 0;
+  std::vector<SysDesc> h_desc;
+  DevBuf<SysDesc> d_desc;
+  DevBuf<int> d_atoms, d_atom_ao0, d_atom_sh0, d_sh_global, d_sh_atom, d_ao_sh, d_all, d_list;
+  DevBuf<double> S, H0, Fm, Ct, Pm, Tm, gam, q_in, q_out, phi, sig, hx, hr, eps, occ;
+  DevBuf<double> erep, e_int, e_prev, mts, err;
+  DevBuf<int> status, niter, nhist, sweeps;
+  DevBatch dev();
+};
+
+struct Ctx {
+  HostParams P;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  fx_options opt{};
+  std::string last_error;
+  // numerical settings of the kernels
+  int jacobi_max_sweeps = 40;
+  double jacobi_tol = 1e-14;
+  double mix_beta = 0.5;
+
+  // supersystem
+  bool has_system = false, lists_built = false, has_result = false, has_grad = false;
+  int N = 0, F = 0, Nsh = 0;
+  std::vector<int> elem, frag, frag_charge, frag_off, frag_atoms, atom_sh0_g;
+  std::vector<double> xyz_h, guess;
+  DevBuf<DevElem> d_elems;
+  DevBuf<double> d_xyz, d_cn, d_sh_eta, d_q, d_qnew, d_phi, d_scalar, field_part, d_grad;
+  DevBuf<int> d_elem, d_frag, d_atom_sh0, d_sh_atom, d_sh_frag, d_frag_atoms, d_frag_off;
+
+  // lists
+  std::vector<int> scc_pairs, esd_pairs, trimers;
+
+  // batches and results
+  Batch mb, db_, tb_;
+  DevBuf<double> e_mono, dE_scc, dEV_scc, dE_esd, dE_tri, ddq_scc;
+  std::vector<double> trimer_dEIJK;
+  fx_result res{};
+
+  static void check(hipError_t e, const char* what);
+  static void* dmalloc(size_t bytes);
+  static double now_ms();
+  void sync();
+  DevSystem dev_system() const;
+  void set_system(int32_t n_atoms, const int32_t* Z, const double* xyz, int32_t n_frag, const int32_t* atom_frag,
+                  const int32_t* fchg);
+  void build_lists_impl();
+  void compute_cn();
+  void field(const double* d_q, double* d_phi);
+  void build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters, int nfrag_each);
+  void build_matrices(Batch& b);
+  int run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* iters_out);
+  int solve_batch(Batch& b, bool cold, long long* iters_out);
+  void run(fx_result* out);
+  void gradient();
+};
+
+}  // namespace fx

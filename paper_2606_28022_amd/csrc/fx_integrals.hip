@@ -1,0 +1,346 @@
+// Supersystem coordination numbers, pair classification, and the per-system
+// S / H0 / gamma / repulsion build.
+//
+// Formulas (section "GFN1-xTB"): CN of eq. cn_def without cutoff; H0 of
+// eq. h0_hamiltonian with the polynomial Pi of eq.
+// xtb1_polynomial_correction and the CN-dependent levels of eq.
+// xtb1_diagonal_h0; gamma = (R^kg + eta^-kg)^(-1/kg) with eta the harmonic
+// mean of the shell hardnesses; repulsion of eq. gfn1_rep_energy over the
+// unordered atom pairs of the system.  Overlaps of the STO-6G contracted
+// Cartesian s/p shells use the Gaussian product theorem; a second s shell on
+// an atom is orthogonalised against the first.
+#include <hip/hip_runtime.h>
+
+#include "fx_device.hpp"
+#include "fx_kernels.hpp"
+
+namespace fx {
+
+__device__ inline double gamma_fn(const DevGlobals& g, double R2, double eta_s, double eta_t) {
+  double inv_eta = 0.5 * (1.0 / eta_s + 1.0 / eta_t);   // 1 / harmonic-mean hardness
+  if (g.kg == 2.0) return 1.0 / sqrt(R2 + inv_eta * inv_eta);
+  double R = sqrt(R2);
+  return pow(pow(R, g.kg) + pow(inv_eta, g.kg), -1.0 / g.kg);
+}
+
+// ---------------------------------------------------------------------------
+// coordination numbers: one thread per atom, all partners (no cutoff)
+__global__ void k_cn(DevSystem sys, double* cn_out) {
+  int A = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double sx[256], sy[256], sz[256], sr[256];
+  double xa = 0, ya = 0, za = 0, ra = 0;
+  if (A < sys.natoms) {
+    xa = sys.xyz[3 * A];
+    ya = sys.xyz[3 * A + 1];
+    za = sys.xyz[3 * A + 2];
+    ra = sys.elems[sys.elem[A]].rcov;
+  }
+  double acc = 0.0;
+  for (int b0 = 0; b0 < sys.natoms; b0 += 256) {
+    int b = b0 + threadIdx.x;
+    __syncthreads();
+    if (b < sys.natoms) {
+      sx[threadIdx.x] = sys.xyz[3 * b];
+      sy[threadIdx.x] = sys.xyz[3 * b + 1];
+      sz[threadIdx.x] = sys.xyz[3 * b + 2];
+      sr[threadIdx.x] = sys.elems[sys.elem[b]].rcov;
+    }
+    __syncthreads();
+    int nb = min(256, sys.natoms - b0);
+    if (A < sys.natoms) {
+      for (int k = 0; k < nb; ++k) {
+        if (b0 + k == A) continue;
+        double dx = xa - sx[k], dy = ya - sy[k], dz = za - sz[k];
+        double R = sqrt(dx * dx + dy * dy + dz * dz);
+        double x = -sys.g.k1 * (sys.g.k2 * (ra + sr[k]) / R - 1.0);
+        acc += 1.0 / (1.0 + exp(x));
+      }
+    }
+  }
+  if (A < sys.natoms) cn_out[A] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// closest contact of every fragment pair (I < J), flag = d2 < cutoff^2.
+// d2 = (dx*dx + dy*dy) + dz*dz with every operation rounded separately.
+__global__ void k_pair_contacts(DevSystem sys, const int* frag_atoms, const int* frag_off,
+                                double cut2, int8_t* flag) {
+#pragma clang fp contract(off)
+  int I = blockIdx.x;
+  int F = sys.nfrag;
+  int a0 = frag_off[I], a1 = frag_off[I + 1];
+  long long base = (long long)I * F - (long long)I * (I + 1) / 2;  // index of (I, I+1)
+  for (int J = I + 1 + threadIdx.x; J < F; J += blockDim.x) {
+    int b0 = frag_off[J], b1 = frag_off[J + 1];
+    double best = 1e300;
+    for (int ia = a0; ia < a1; ++ia) {
+      int a = frag_atoms[ia];
+      double xa = sys.xyz[3 * a], ya = sys.xyz[3 * a + 1], za = sys.xyz[3 * a + 2];
+      for (int ib = b0; ib < b1; ++ib) {
+        int b = frag_atoms[ib];
+        double dx = xa - sys.xyz[3 * b];
+        double dy = ya - sys.xyz[3 * b + 1];
+        double dz = za - sys.xyz[3 * b + 2];
+        double xx = __dmul_rn(dx, dx);
+        double yy = __dmul_rn(dy, dy);
+        double zz = __dmul_rn(dz, dz);
+        double d2 = __dadd_rn(__dadd_rn(xx, yy), zz);
+        best = d2 < best ? d2 : best;
+      }
+    }
+    flag[base + (J - I - 1)] = best < cut2 ? 1 : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// overlap block between two atoms (raw contracted shells, then the on-site
+// orthogonalisation), R = A - B.  out is nao_a x nao_b, row-major, ld = 4.
+__device__ void atom_pair_overlap(const DevElem& ea, const DevElem& eb, double Rx, double Ry,
+                                  double Rz, double out[MAXAO_EL][MAXAO_EL]) {
+  const double PI = 3.14159265358979323846;
+  double R2 = Rx * Rx + Ry * Ry + Rz * Rz;
+  double Rv[3] = {Rx, Ry, Rz};
+  for (int i = 0; i < MAXAO_EL; ++i)
+    for (int j = 0; j < MAXAO_EL; ++j) out[i][j] = 0.0;
+  for (int sa = 0; sa < ea.nsh; ++sa) {
+    for (int sb = 0; sb < eb.nsh; ++sb) {
+      int la = ea.l[sa], lb = eb.l[sb];
+      int oa = ea.ao0[sa], ob = eb.ao0[sb];
+      for (int i = 0; i < NPRIM; ++i) {
+        double a = ea.alpha[sa][i];
+        for (int j = 0; j < NPRIM; ++j) {
+          double b = eb.alpha[sb][j];
+          double p = a + b;
+          double ip = 1.0 / p;
+          double mu = a * b * ip;
+          double s00 = ea.coef[sa][i] * eb.coef[sb][j] * PI * ip * sqrt(PI * ip) * exp(-mu * R2);
+          if (la == 0 && lb == 0) {
+            out[oa][ob] += s00;
+          } else if (la == 1 && lb == 0) {
+            double f = -b * ip * s00;
+            for (int k = 0; k < 3; ++k) out[oa + k][ob] += f * Rv[k];
+          } else if (la == 0 && lb == 1) {
+            double f = a * ip * s00;
+            for (int k = 0; k < 3; ++k) out[oa][ob + k] += f * Rv[k];
+          } else {
+            double fa = -b * ip, fb = a * ip, h = 0.5 * ip;
+            for (int u = 0; u < 3; ++u)
+              for (int v = 0; v < 3; ++v)
+                out[oa + u][ob + v] += (fa * Rv[u] * fb * Rv[v] + (u == v ? h : 0.0)) * s00;
+          }
+        }
+      }
+    }
+  }
+  if (ea.orth) {  // rows: second s shell of A
+    int r1 = ea.ao0[0], r2 = ea.ao0[1];
+    for (int j = 0; j < eb.nao; ++j) out[r2][j] = ea.orthN * (out[r2][j] - ea.orthS12 * out[r1][j]);
+  }
+  if (eb.orth) {
+    int c1 = eb.ao0[0], c2 = eb.ao0[1];
+    for (int i = 0; i < ea.nao; ++i) out[i][c2] = eb.orthN * (out[i][c2] - eb.orthS12 * out[i][c1]);
+  }
+}
+
+// H0 prefactor of a shell pair on different atoms (everything but S).
+__device__ inline double h0_prefactor(const DevGlobals& g, const DevElem& ea, int sa, double cna,
+                                      const DevElem& eb, int sb, double cnb, double R) {
+  double kll = 0.5 * (g.kl[ea.l[sa]] + g.kl[eb.l[sb]]);
+  double den = ea.EN - eb.EN;
+  double ha = ea.level[sa] * (1.0 + ea.kcn[sa] * cna);
+  double hb = eb.level[sb] * (1.0 + eb.kcn[sb] * cnb);
+  double x = sqrt(R / (ea.rcov + eb.rcov));
+  double Pi = (1.0 + ea.kpoly[sa] * x) * (1.0 + eb.kpoly[sb] * x);
+  return g.KAB * kll * 0.5 * (ha + hb) * (1.0 + g.kEN * den * den) * Pi;
+}
+
+// ---------------------------------------------------------------------------
+// per-system S, H0, gamma and repulsion; one work-group per system.
+__global__ void k_build_system(DevSystem sys, DevBatch bt, const int* list) {
+  int si = list ? list[blockIdx.x] : blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao;
+  double* S = bt.S + d.mat_off;
+  double* H = bt.H0 + d.mat_off;
+  const int* atoms = bt.sys_atoms + d.atom_off;
+  const int* aao = bt.sys_atom_ao0 + d.atom_off;
+  __shared__ double red[256];
+  double erep = 0.0;
+  // diagonal atom blocks
+  for (int a = threadIdx.x; a < d.nat; a += blockDim.x) {
+    int A = atoms[a];
+    const DevElem& e = sys.elems[sys.elem[A]];
+    int o = aao[a];
+    for (int i = 0; i < e.nao; ++i)
+      for (int j = 0; j < e.nao; ++j) {
+        S[(long long)(o + i) * n + o + j] = (i == j) ? 1.0 : 0.0;
+        H[(long long)(o + i) * n + o + j] = 0.0;
+      }
+    for (int s = 0; s < e.nsh; ++s) {
+      double h = e.level[s] * (1.0 + e.kcn[s] * sys.cn[A]);
+      for (int k = 0; k < e.nao_sh[s]; ++k) H[(long long)(o + e.ao0[s] + k) * n + o + e.ao0[s] + k] = h;
+    }
+  }
+  // off-diagonal atom blocks
+  const int np = d.nat * d.nat;
+  for (int idx = threadIdx.x; idx < np; idx += blockDim.x) {
+    int a = idx / d.nat, b = idx - a * d.nat;
+    if (b <= a) continue;
+    int A = atoms[a], B = atoms[b];
+    const DevElem& ea = sys.elems[sys.elem[A]];
+    const DevElem& eb = sys.elems[sys.elem[B]];
+    double Rx = sys.xyz[3 * A] - sys.xyz[3 * B];
+    double Ry = sys.xyz[3 * A + 1] - sys.xyz[3 * B + 1];
+    double Rz = sys.xyz[3 * A + 2] - sys.xyz[3 * B + 2];
+    double R = sqrt(Rx * Rx + Ry * Ry + Rz * Rz);
+    double blk[MAXAO_EL][MAXAO_EL];
+    atom_pair_overlap(ea, eb, Rx, Ry, Rz, blk);
+    int oa = aao[a], ob = aao[b];
+    for (int sa = 0; sa < ea.nsh; ++sa)
+      for (int sb = 0; sb < eb.nsh; ++sb) {
+        double f = h0_prefactor(sys.g, ea, sa, sys.cn[A], eb, sb, sys.cn[B], R);
+        for (int u = 0; u < ea.nao_sh[sa]; ++u)
+          for (int v = 0; v < eb.nao_sh[sb]; ++v) {
+            int i = ea.ao0[sa] + u, j = eb.ao0[sb] + v;
+            double sv = blk[i][j];
+            double hv = f * sv;
+            S[(long long)(oa + i) * n + ob + j] = sv;
+            S[(long long)(ob + j) * n + oa + i] = sv;
+            H[(long long)(oa + i) * n + ob + j] = hv;
+            H[(long long)(ob + j) * n + oa + i] = hv;
+          }
+      }
+    double al = sqrt(ea.arep * eb.arep);
+    erep += ea.zeff * eb.zeff / R * exp(-al * pow(R, sys.g.kf));
+  }
+  // gamma of the system's shells
+  double* G = bt.gam + d.gam_off;
+  const int* shg = bt.sys_sh_global + d.sh_off;
+  for (int idx = threadIdx.x; idx < d.nsh * d.nsh; idx += blockDim.x) {
+    int s = idx / d.nsh, t = idx - s * d.nsh;
+    int gs = shg[s], gt = shg[t];
+    int As = sys.sh_atom[gs], At = sys.sh_atom[gt];
+    double dx = sys.xyz[3 * As] - sys.xyz[3 * At];
+    double dy = sys.xyz[3 * As + 1] - sys.xyz[3 * At + 1];
+    double dz = sys.xyz[3 * As + 2] - sys.xyz[3 * At + 2];
+    G[idx] = gamma_fn(sys.g, dx * dx + dy * dy + dz * dz, sys.sh_eta[gs], sys.sh_eta[gt]);
+  }
+  // deterministic reduction of the repulsion energy
+  red[threadIdx.x] = erep;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bt.erep[si] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// Embedding field: phi_s = sum_{t in other fragments} gamma_st q_t.
+// One thread per target atom (all its shells); the source atoms are split
+// into `nchunk` slices handled by separate work-groups, whose partial sums
+// are combined in fixed order by k_field_reduce (deterministic).
+__global__ void k_field_partial(DevSystem sys, const double* q, int nchunk, double* part) {
+  int A = blockIdx.x * blockDim.x + threadIdx.x;
+  int chunk = blockIdx.y;
+  int N = sys.natoms;
+  int per = (N + nchunk - 1) / nchunk;
+  int b_begin = chunk * per, b_end = min(N, b_begin + per);
+  __shared__ double sx[256], sy[256], sz[256], seta[256][MAXSH_EL], sq[256][MAXSH_EL];
+  __shared__ int sf[256], sn[256];
+  double xa = 0, ya = 0, za = 0, ea[MAXSH_EL] = {1.0, 1.0};
+  int fa = -1, na = 0, sh0 = 0;
+  if (A < N) {
+    xa = sys.xyz[3 * A];
+    ya = sys.xyz[3 * A + 1];
+    za = sys.xyz[3 * A + 2];
+    fa = sys.frag[A];
+    sh0 = sys.atom_sh0[A];
+    na = sys.atom_sh0[A + 1] - sh0;
+    for (int k = 0; k < na; ++k) ea[k] = sys.sh_eta[sh0 + k];
+  }
+  double acc[MAXSH_EL] = {0.0, 0.0};
+  for (int b0 = b_begin; b0 < b_end; b0 += 256) {
+    int b = b0 + threadIdx.x;
+    __syncthreads();
+    if (b < b_end) {
+      sx[threadIdx.x] = sys.xyz[3 * b];
+      sy[threadIdx.x] = sys.xyz[3 * b + 1];
+      sz[threadIdx.x] = sys.xyz[3 * b + 2];
+      sf[threadIdx.x] = sys.frag[b];
+      int s0 = sys.atom_sh0[b];
+      int nsb = sys.atom_sh0[b + 1] - s0;
+      sn[threadIdx.x] = nsb;
+      for (int k = 0; k < MAXSH_EL; ++k) {
+        seta[threadIdx.x][k] = k < nsb ? sys.sh_eta[s0 + k] : 1.0;
+        sq[threadIdx.x][k] = k < nsb ? q[s0 + k] : 0.0;
+      }
+    }
+    __syncthreads();
+    int nb = min(256, b_end - b0);
+    if (A < N) {
+      for (int k = 0; k < nb; ++k) {
+        if (sf[k] == fa) continue;
+        double dx = xa - sx[k], dy = ya - sy[k], dz = za - sz[k];
+        double R2 = dx * dx + dy * dy + dz * dz;
+        for (int u = 0; u < na; ++u)
+          for (int v = 0; v < sn[k]; ++v) acc[u] += gamma_fn(sys.g, R2, ea[u], seta[k][v]) * sq[k][v];
+      }
+    }
+  }
+  if (A < N)
+    for (int u = 0; u < na; ++u) part[(long long)chunk * sys.nshells + sh0 + u] = acc[u];
+}
+
+__global__ void k_field_reduce(int nshells, int nchunk, const double* part, double* phi) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nshells) return;
+  double acc = 0.0;
+  for (int c = 0; c < nchunk; ++c) acc += part[(long long)c * nshells + s];
+  phi[s] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// cluster (dimer / trimer) embedding from the monomer field:
+// phi^X_s = Phi_s - sum_{t in X, frag(t) != frag(s)} gamma_st q_t
+__global__ void k_cluster_phi(DevSystem sys, DevBatch bt, const double* Phi, const double* qmono) {
+  int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const int* shg = bt.sys_sh_global + d.sh_off;
+  for (int s = threadIdx.x; s < d.nsh; s += blockDim.x) {
+    int gs = shg[s];
+    int fs = sys.sh_frag[gs];
+    double v = Phi[gs];
+    for (int t = 0; t < d.nsh; ++t) {
+      int gt = shg[t];
+      if (sys.sh_frag[gt] == fs) continue;
+      v -= bt.gam[d.gam_off + (long long)s * d.nsh + t] * qmono[gt];
+    }
+    bt.phi[d.sh_off + s] = v;
+  }
+}
+
+// ES-DIM pair energies dq^I gamma_IJ dq^J for a list of pairs.
+__global__ void k_esd_pairs(DevSystem sys, const int* pairs, long long npairs, const int* frag_atoms,
+                            const int* frag_off, const double* q, double* out) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= npairs) return;
+  int I = pairs[2 * k], J = pairs[2 * k + 1];
+  double acc = 0.0;
+  for (int ia = frag_off[I]; ia < frag_off[I + 1]; ++ia) {
+    int a = frag_atoms[ia];
+    double xa = sys.xyz[3 * a], ya = sys.xyz[3 * a + 1], za = sys.xyz[3 * a + 2];
+    int sa0 = sys.atom_sh0[a], sa1 = sys.atom_sh0[a + 1];
+    for (int ib = frag_off[J]; ib < frag_off[J + 1]; ++ib) {
+      int b = frag_atoms[ib];
+      double dx = xa - sys.xyz[3 * b], dy = ya - sys.xyz[3 * b + 1], dz = za - sys.xyz[3 * b + 2];
+      double R2 = dx * dx + dy * dy + dz * dz;
+      int sb0 = sys.atom_sh0[b], sb1 = sys.atom_sh0[b + 1];
+      for (int s = sa0; s < sa1; ++s)
+        for (int t = sb0; t < sb1; ++t) acc += q[s] * gamma_fn(sys.g, R2, sys.sh_eta[s], sys.sh_eta[t]) * q[t];
+    }
+  }
+  out[k] = acc;
+}
+
+}  // namespace fx

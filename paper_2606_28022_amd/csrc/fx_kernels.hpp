@@ -1,0 +1,42 @@
+// Kernel declarations shared by the kernel sources and the host driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fx_device.hpp"
+
+namespace fx {
+
+// integrals / lists / fields (fx_integrals.hip)
+__global__ void k_cn(DevSystem sys, double* cn_out);
+__global__ void k_pair_contacts(DevSystem sys, const int* frag_atoms, const int* frag_off, double cut2,
+                                int8_t* flag);
+__global__ void k_build_system(DevSystem sys, DevBatch bt, const int* list);
+__global__ void k_field_partial(DevSystem sys, const double* q, int nchunk, double* part);
+__global__ void k_field_reduce(int nshells, int nchunk, const double* part, double* phi);
+__global__ void k_cluster_phi(DevSystem sys, DevBatch bt, const double* Phi, const double* qmono);
+__global__ void k_esd_pairs(DevSystem sys, const int* pairs, long long npairs, const int* frag_atoms,
+                            const int* frag_off, const double* q, double* out);
+
+// SCC (fx_scc.hip)
+__global__ void k_reset_state(DevBatch bt, const int* list, int nl);
+__global__ void k_cholinv(DevBatch bt, const int* list);
+__global__ void k_fock(DevSystem sys, DevBatch bt, const int* list);
+__global__ void k_gemm(DevBatch bt, const int* list, int mode, const double* A, const double* B, double* C,
+                       const double* w);
+__global__ void k_jacobi(DevBatch bt, const int* list, int max_sweeps, double rel_tol, int* sweeps_out);
+__global__ void k_eigh_batched(const int* nvec, const long long* off, double* Abuf, double* Vbuf, double* wbuf,
+                               const long long* woff, int max_sweeps, double rel_tol);
+__global__ void k_fermi(DevSystem sys, DevBatch bt, const int* list);
+__global__ void k_charges_mix(DevSystem sys, DevBatch bt, const int* list, double tol, double etol, int max_iter,
+                              double beta);
+
+// FMO assembly (fx_fmo.hip)
+__global__ void k_gather_shell(DevBatch bt, const double* src_global, double* dst_local);
+__global__ void k_scatter_shell(DevBatch bt, const double* src_local, double* dst_global);
+__global__ void k_max_absdiff(const double* a, const double* b, int n, double* out);
+__global__ void k_cluster_terms(DevBatch bt, const double* qmono, const double* e_mono, double* ddq, double* dEV,
+                                double* dE);
+__global__ void k_sum_neumaier(const double* const* arrays, const long long* lens, int narrays, double* out);
+
+}  // namespace fx

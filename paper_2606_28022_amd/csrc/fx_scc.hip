@@ -1,0 +1,569 @@
+// SCC iteration kernels for batches of fragment systems (monomers, dimers,
+// trimers).  One iteration (section "GFN1-xTB"):
+//   sigma_s = sum_t gamma_st q_t - Gamma_A q_A^2 + phi_s       (k_fock)
+//   F = H0 + 1/2 S (sigma_mu + sigma_nu)                        (k_fock)
+//   A = C^T F C in the current S-orthonormal basis C            (k_gemm x2)
+//   Jacobi rotations diagonalise A and rotate C                 (k_jacobi)
+//   Fermi-Dirac occupations, eps_F by bisection                 (k_fermi)
+//   P = C diag(n) C^T                                           (k_gemm TN)
+//   Mulliken shell charges, energy, Anderson mixing, test       (k_charges_mix)
+// Because C stays S-orthonormal, the generalized problem F C = S C eps is
+// solved without refactoring S; the first basis is C = L^-T with S = L L^T
+// (k_cholinv).  C is stored transposed (eigenvectors as rows).
+#include <hip/hip_runtime.h>
+
+#include "fx_device.hpp"
+#include "fx_kernels.hpp"
+
+namespace fx {
+
+__device__ inline double block_sum(double v, double* red) {
+  __syncthreads();
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ inline double block_max(double v, double* red) {
+  __syncthreads();
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// start of a solve: clear the iteration state of the listed systems
+__global__ void k_reset_state(DevBatch bt, const int* list, int nl) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nl) return;
+  int si = list[k];
+  bt.status[si] = 0;
+  bt.niter[si] = 0;
+  bt.nhist[si] = 0;
+  bt.e_prev[si] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// C = L^-T for S = L L^T (rows of L^-1 are the first S-orthonormal basis).
+__global__ void k_cholinv(DevBatch bt, const int* list) {
+  int si = list[blockIdx.x];
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao;
+  double* L = bt.T + d.mat_off;
+  const double* S = bt.S + d.mat_off;
+  double* X = bt.Ct + d.mat_off;
+  __shared__ double piv;
+  for (long long i = threadIdx.x; i < (long long)n * n; i += blockDim.x) L[i] = S[i];
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (threadIdx.x == 0) {
+      double v = L[(long long)k * n + k];
+      piv = v > 0.0 ? sqrt(v) : -1.0;
+      if (v <= 0.0) bt.status[si] = 2;
+      L[(long long)k * n + k] = piv;
+    }
+    __syncthreads();
+    if (piv <= 0.0) return;
+    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) L[(long long)i * n + k] /= piv;
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+      int i = k + 1 + idx / m, j = k + 1 + idx % m;
+      if (j <= i) L[(long long)i * n + j] -= L[(long long)i * n + k] * L[(long long)j * n + k];
+    }
+    __syncthreads();
+  }
+  // X = L^-1 by forward substitution, one column per thread
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    for (int i = 0; i < n; ++i) {
+      if (i < j) {
+        X[(long long)i * n + j] = 0.0;
+        continue;
+      }
+      double v = (i == j) ? 1.0 : 0.0;
+      for (int k = j; k < i; ++k) v -= L[(long long)i * n + k] * X[(long long)k * n + j];
+      X[(long long)i * n + j] = v / L[(long long)i * n + i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// shell shift and Fock matrix
+__global__ void k_fock(DevSystem sys, DevBatch bt, const int* list) {
+  int si = list[blockIdx.x];
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao, ns = d.nsh;
+  __shared__ double qa_s[MAXN];
+  __shared__ double sig_s[MAXN];
+  const double* q = bt.q_in + d.sh_off;
+  // atom charges
+  for (int a = threadIdx.x; a < d.nat; a += blockDim.x) {
+    int s0 = bt.sys_atom_sh0[d.atom_off + a];
+    int A = bt.sys_atoms[d.atom_off + a];
+    int nsa = sys.atom_sh0[A + 1] - sys.atom_sh0[A];
+    double v = 0.0;
+    for (int k = 0; k < nsa; ++k) v += q[s0 + k];
+    qa_s[a] = v;
+  }
+  __syncthreads();
+  const double* G = bt.gam + d.gam_off;
+  for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+    double v = 0.0;
+    for (int t = 0; t < ns; ++t) v += G[(long long)s * ns + t] * q[t];
+    int a = bt.sys_sh_atom[d.sh_off + s];
+    int A = bt.sys_atoms[d.atom_off + a];
+    double Gam = sys.elems[sys.elem[A]].Gamma;
+    v += -Gam * qa_s[a] * qa_s[a] + bt.phi[d.sh_off + s];
+    sig_s[s] = v;
+    bt.sig[d.sh_off + s] = v;
+  }
+  __syncthreads();
+  const double* S = bt.S + d.mat_off;
+  const double* H = bt.H0 + d.mat_off;
+  double* Fm = bt.F + d.mat_off;
+  const int* aosh = bt.sys_ao_sh + d.ao_off;
+  for (long long idx = threadIdx.x; idx < (long long)n * n; idx += blockDim.x) {
+    int i = (int)(idx / n), j = (int)(idx - (long long)i * n);
+    Fm[idx] = H[idx] + 0.5 * S[idx] * (sig_s[aosh[i]] + sig_s[aosh[j]]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched dense products of the systems' n x n matrices, 32 x 32 output tile
+// per work-group (256 threads, 2 x 2 outputs each).  mode:
+//   0  C = A B          1  C = A B^T          2  C = A^T diag(w) B
+__global__ void k_gemm(DevBatch bt, const int* list, int mode, const double* Abase, const double* Bbase,
+                       double* Cbase, const double* wbase) {
+  int si = list[blockIdx.y];
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao;
+  const int nt = (n + 31) / 32;
+  if ((int)blockIdx.x >= nt * nt) return;
+  const int ti = blockIdx.x / nt, tj = blockIdx.x % nt;
+  const double* A = Abase + d.mat_off;
+  const double* B = Bbase + d.mat_off;
+  double* C = Cbase + d.mat_off;
+  const double* w = wbase ? wbase + d.ao_off : nullptr;
+  __shared__ double As[32][33];  // [k][i]
+  __shared__ double Bs[32][33];  // [k][j]
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double acc[2][2] = {{0, 0}, {0, 0}};
+  for (int k0 = 0; k0 < n; k0 += 32) {
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+      int r = e / 32, c = e % 32;
+      // A tile element (i = ti*32 + ?, k = k0 + ?)
+      double av = 0.0, bv = 0.0;
+      if (mode == 2) {
+        // A^T: As[k][i] = A[k][i] * w[k]
+        int k = k0 + r, i = ti * 32 + c;
+        if (k < n && i < n) av = A[(long long)k * n + i] * w[k];
+        int kb = k0 + r, j = tj * 32 + c;
+        if (kb < n && j < n) bv = B[(long long)kb * n + j];
+        As[r][c] = av;
+        Bs[r][c] = bv;
+      } else {
+        // A: As[k][i] = A[i][k]; read A row i = ti*32 + r, column k = k0 + c
+        int i = ti * 32 + r, k = k0 + c;
+        if (i < n && k < n) av = A[(long long)i * n + k];
+        As[c][r] = av;
+        if (mode == 0) {
+          int kb = k0 + r, j = tj * 32 + c;
+          if (kb < n && j < n) bv = B[(long long)kb * n + j];
+          Bs[r][c] = bv;
+        } else {
+          int j = tj * 32 + r, kb = k0 + c;
+          if (j < n && kb < n) bv = B[(long long)j * n + kb];
+          Bs[c][r] = bv;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int k = 0; k < 32; ++k) {
+      double a0 = As[k][ty], a1 = As[k][ty + 16];
+      double b0 = Bs[k][tx], b1 = Bs[k][tx + 16];
+      acc[0][0] += a0 * b0;
+      acc[0][1] += a0 * b1;
+      acc[1][0] += a1 * b0;
+      acc[1][1] += a1 * b1;
+    }
+    __syncthreads();
+  }
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) {
+      int i = ti * 32 + ty + 16 * u, j = tj * 32 + tx + 16 * v;
+      if (i < n && j < n) C[(long long)i * n + j] = acc[u][v];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Parallel cyclic Jacobi on the symmetric matrix A (in place), rotating the
+// rows of V.  Round-robin ordering: every step applies n/2 disjoint
+// rotations; each 2 x 2 block (pair k, pair l) is updated as J_k^T B J_l in
+// one pass.  Sweeps stop when no rotation exceeds the threshold.
+__device__ inline int rr_index(int pos, int step, int m) {
+  return pos == 0 ? 0 : 1 + (pos - 1 + step) % (m - 1);
+}
+
+__device__ void jacobi_solve(double* A, double* V, int n, int nv, int max_sweeps, double rel_tol, double* red,
+                             double* cs_c, double* cs_s, double* cs_t, int* pp, int* qq, int* nsweep_out) {
+  const int m = n + (n & 1);
+  const int nb = m / 2;
+  // scale: Frobenius norm
+  double loc = 0.0;
+  for (long long i = threadIdx.x; i < (long long)n * n; i += blockDim.x) loc += A[i] * A[i];
+  double fro = sqrt(block_sum(loc, red));
+  double thr = rel_tol * (fro > 0.0 ? fro : 1.0);
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    double maxoff = 0.0;
+    for (int step = 0; step < m - 1; ++step) {
+      for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+        int p = rr_index(k, step, m), q = rr_index(m - 1 - k, step, m);
+        if (p > q) {
+          int t = p;
+          p = q;
+          q = t;
+        }
+        double c = 1.0, s = 0.0, t = 0.0;
+        if (q < n) {
+          double apq = A[(long long)p * n + q];
+          maxoff = fmax(maxoff, fabs(apq));
+          if (fabs(apq) > thr) {
+            double app = A[(long long)p * n + p], aqq = A[(long long)q * n + q];
+            double theta = (aqq - app) / (2.0 * apq);
+            t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+          }
+        }
+        cs_c[k] = c;
+        cs_s[k] = s;
+        cs_t[k] = t;
+        pp[k] = p;
+        qq[k] = q;
+      }
+      __syncthreads();
+      // A <- J^T A J over (k <= l) blocks
+      const int nblk = nb * (nb + 1) / 2;
+      for (int idx = threadIdx.x; idx < nblk; idx += blockDim.x) {
+        // triangular index -> (k, l), k <= l
+        int k = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+        while (k * (k + 1) / 2 > idx) --k;
+        while ((k + 1) * (k + 2) / 2 <= idx) ++k;
+        int l = idx - k * (k + 1) / 2;  // l <= k
+        // use (a, b) = (l, k) with a <= b
+        int a = l, b = k;
+        int p = pp[a], q = qq[a], r = pp[b], u = qq[b];
+        double ca = cs_c[a], sa = cs_s[a], cb = cs_c[b], sb = cs_s[b];
+        if (sa == 0.0 && sb == 0.0) continue;
+        if (a == b) {
+          if (q >= n) continue;
+          double apq = A[(long long)p * n + q];
+          double t = cs_t[a];
+          A[(long long)p * n + p] -= t * apq;
+          A[(long long)q * n + q] += t * apq;
+          A[(long long)p * n + q] = 0.0;
+          A[(long long)q * n + p] = 0.0;
+          continue;
+        }
+        bool qv = q < n, uv = u < n;
+        double bpr = A[(long long)p * n + r];
+        double bpu = uv ? A[(long long)p * n + u] : 0.0;
+        double bqr = qv ? A[(long long)q * n + r] : 0.0;
+        double bqu = (qv && uv) ? A[(long long)q * n + u] : 0.0;
+        // rows: J_a^T
+        double tpr = ca * bpr - sa * bqr, tpu = ca * bpu - sa * bqu;
+        double tqr = sa * bpr + ca * bqr, tqu = sa * bpu + ca * bqu;
+        // cols: J_b
+        double npr = cb * tpr - sb * tpu, npu = sb * tpr + cb * tpu;
+        double nqr = cb * tqr - sb * tqu, nqu = sb * tqr + cb * tqu;
+        A[(long long)p * n + r] = npr;
+        A[(long long)r * n + p] = npr;
+        if (uv) {
+          A[(long long)p * n + u] = npu;
+          A[(long long)u * n + p] = npu;
+        }
+        if (qv) {
+          A[(long long)q * n + r] = nqr;
+          A[(long long)r * n + q] = nqr;
+        }
+        if (qv && uv) {
+          A[(long long)q * n + u] = nqu;
+          A[(long long)u * n + q] = nqu;
+        }
+      }
+      // eigenvector rows
+      for (int idx = threadIdx.x; idx < nb * nv; idx += blockDim.x) {
+        int k = idx / nv, j = idx - k * nv;
+        double s = cs_s[k];
+        if (s == 0.0) continue;
+        int p = pp[k], q = qq[k];
+        double c = cs_c[k];
+        double vp = V[(long long)p * nv + j], vq = V[(long long)q * nv + j];
+        V[(long long)p * nv + j] = c * vp - s * vq;
+        V[(long long)q * nv + j] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+    double mo = block_max(maxoff, red);
+    if (mo <= thr) break;
+  }
+  if (nsweep_out && threadIdx.x == 0) *nsweep_out = sweep;
+}
+
+__global__ void k_jacobi(DevBatch bt, const int* list, int max_sweeps, double rel_tol, int* sweeps_out) {
+  int si = list[blockIdx.x];
+  const SysDesc d = bt.desc[si];
+  __shared__ double red[256];
+  __shared__ double cs_c[MAXN / 2], cs_s[MAXN / 2], cs_t[MAXN / 2];
+  __shared__ int pp[MAXN / 2], qq[MAXN / 2];
+  double* A = bt.F + d.mat_off;
+  double* V = bt.Ct + d.mat_off;
+  jacobi_solve(A, V, d.nao, d.nao, max_sweeps, rel_tol, red, cs_c, cs_s, cs_t, pp, qq,
+               sweeps_out ? sweeps_out + si : nullptr);
+  __syncthreads();
+  for (int i = threadIdx.x; i < d.nao; i += blockDim.x) bt.eps[d.ao_off + i] = A[(long long)i * d.nao + i];
+}
+
+// Standalone batched eigensolver (component entry point): matrices packed in
+// Abuf with offsets off[k], eigenvectors into Vbuf (initialised to I here).
+__global__ void k_eigh_batched(const int* nvec, const long long* off, double* Abuf, double* Vbuf, double* wbuf,
+                               const long long* woff, int max_sweeps, double rel_tol) {
+  int k = blockIdx.x;
+  int n = nvec[k];
+  double* A = Abuf + off[k];
+  double* V = Vbuf + off[k];
+  __shared__ double red[256];
+  __shared__ double cs_c[MAXN / 2], cs_s[MAXN / 2], cs_t[MAXN / 2];
+  __shared__ int pp[MAXN / 2], qq[MAXN / 2];
+  for (long long i = threadIdx.x; i < (long long)n * n; i += blockDim.x) V[i] = (i / n == i % n) ? 1.0 : 0.0;
+  __syncthreads();
+  jacobi_solve(A, V, n, n, max_sweeps, rel_tol, red, cs_c, cs_s, cs_t, pp, qq, nullptr);
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) wbuf[woff[k] + i] = A[(long long)i * n + i];
+}
+
+// ---------------------------------------------------------------------------
+// Fermi-Dirac occupations n_i = 2 / (1 + exp((eps_i - eF)/kT)), eF by bisection
+// so that sum n_i = N_el; also -T S_el.
+__global__ void k_fermi(DevSystem sys, DevBatch bt, const int* list) {
+  int si = list[blockIdx.x];
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao;
+  const double kT = sys.g.kT;
+  __shared__ double red[256];
+  const double* e = bt.eps + d.ao_off;
+  double lo = 1e300, hi = -1e300;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    lo = fmin(lo, e[i]);
+    hi = fmax(hi, e[i]);
+  }
+  lo = -block_max(-lo, red) - 1.0;
+  hi = block_max(hi, red) + 1.0;
+  for (int it = 0; it < 300; ++it) {
+    double mid = 0.5 * (lo + hi);
+    double loc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) loc += 2.0 / (1.0 + exp((e[i] - mid) / kT));
+    double tot = block_sum(loc, red);
+    if (tot > d.nel) hi = mid;
+    else lo = mid;
+    if (hi - lo < 1e-15) break;
+  }
+  double ef = 0.5 * (lo + hi);
+  double ts = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double f = 1.0 / (1.0 + exp((e[i] - ef) / kT));
+    bt.occ[d.ao_off + i] = 2.0 * f;
+    double t = 0.0;
+    if (f > 0.0) t += f * log(f);
+    if (f < 1.0) t += (1.0 - f) * log(1.0 - f);
+    ts += t;
+  }
+  ts = block_sum(ts, red);
+  if (threadIdx.x == 0) bt.mts[si] = 2.0 * kT * ts;
+}
+
+// ---------------------------------------------------------------------------
+// Mulliken charges of P, energy, convergence test and Anderson mixing.
+__device__ void solve_small(double* M, double* rhs, int m) {
+  // Gaussian elimination with partial pivoting on an (m x m) system, in place
+  for (int c = 0; c < m; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < m; ++r)
+      if (fabs(M[r * m + c]) > fabs(M[piv * m + c])) piv = r;
+    if (piv != c) {
+      for (int k = 0; k < m; ++k) {
+        double t = M[c * m + k];
+        M[c * m + k] = M[piv * m + k];
+        M[piv * m + k] = t;
+      }
+      double t = rhs[c];
+      rhs[c] = rhs[piv];
+      rhs[piv] = t;
+    }
+    double dv = M[c * m + c];
+    if (fabs(dv) < 1e-300) dv = 1e-300;
+    for (int r = c + 1; r < m; ++r) {
+      double f = M[r * m + c] / dv;
+      for (int k = c; k < m; ++k) M[r * m + k] -= f * M[c * m + k];
+      rhs[r] -= f * rhs[c];
+    }
+  }
+  for (int c = m - 1; c >= 0; --c) {
+    double v = rhs[c];
+    for (int k = c + 1; k < m; ++k) v -= M[c * m + k] * rhs[k];
+    double dv = M[c * m + c];
+    rhs[c] = v / (fabs(dv) < 1e-300 ? 1e-300 : dv);
+  }
+}
+
+__global__ void k_charges_mix(DevSystem sys, DevBatch bt, const int* list, double tol, double etol, int max_iter,
+                              double beta) {
+  int si = list[blockIdx.x];
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao, ns = d.nsh;
+  __shared__ double red[256];
+  __shared__ double pop[MAXN];
+  __shared__ double qa[MAXN];
+  __shared__ double coef[HIST + 1];
+  const double* S = bt.S + d.mat_off;
+  const double* P = bt.P + d.mat_off;
+  const double* H = bt.H0 + d.mat_off;
+  // AO populations (P S)_mu,mu and Tr(P H0)
+  double eh = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double v = 0.0, h = 0.0;
+    for (int j = 0; j < n; ++j) {
+      double pij = P[(long long)i * n + j];
+      v += pij * S[(long long)i * n + j];
+      h += pij * H[(long long)i * n + j];
+    }
+    pop[i] = v;
+    eh += h;
+  }
+  eh = block_sum(eh, red);
+  // shell charges
+  double* qo = bt.q_out + d.sh_off;
+  const double* qi = bt.q_in + d.sh_off;
+  const int* aosh = bt.sys_ao_sh + d.ao_off;
+  for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+    double v = 0.0;
+    for (int i = 0; i < n; ++i)
+      if (aosh[i] == s) v += pop[i];
+    int a = bt.sys_sh_atom[d.sh_off + s];
+    int A = bt.sys_atoms[d.atom_off + a];
+    const DevElem& el = sys.elems[sys.elem[A]];
+    int ls = s - bt.sys_atom_sh0[d.atom_off + a];
+    qo[s] = v - el.q0[ls];
+  }
+  __syncthreads();
+  for (int a = threadIdx.x; a < d.nat; a += blockDim.x) {
+    int s0 = bt.sys_atom_sh0[d.atom_off + a];
+    int s1 = (a + 1 < d.nat) ? bt.sys_atom_sh0[d.atom_off + a + 1] : ns;
+    double v = 0.0;
+    for (int s = s0; s < s1; ++s) v += qo[s];
+    qa[a] = v;
+  }
+  __syncthreads();
+  // energy
+  const double* G = bt.gam + d.gam_off;
+  double e2 = 0.0, e3 = 0.0, err = 0.0;
+  for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+    double v = 0.0;
+    for (int t = 0; t < ns; ++t) v += G[(long long)s * ns + t] * qo[t];
+    e2 += 0.5 * qo[s] * v;
+    err = fmax(err, fabs(qo[s] - qi[s]));
+  }
+  for (int a = threadIdx.x; a < d.nat; a += blockDim.x) {
+    int A = bt.sys_atoms[d.atom_off + a];
+    e3 -= sys.elems[sys.elem[A]].Gamma * qa[a] * qa[a] * qa[a] / 3.0;
+  }
+  e2 = block_sum(e2, red);
+  e3 = block_sum(e3, red);
+  err = block_max(err, red);
+  double e = eh + e2 + e3 + bt.mts[si] + bt.erep[si];
+  int it = bt.niter[si] + 1;
+  double de = fabs(e - bt.e_prev[si]);
+  bool conv = (err < tol) && (de < etol) && (it > 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bt.e_int[si] = e;
+    bt.e_prev[si] = e;
+    bt.err[si] = err;
+    bt.niter[si] = it;
+    if (conv) bt.status[si] = 1;
+    else if (it >= max_iter) bt.status[si] = 2;
+  }
+  if (conv || it >= max_iter) return;
+  // Anderson mixing of the input charges
+  int nh = bt.nhist[si];
+  if (nh < 0) nh = 0;
+  double* hx = bt.hx + (long long)d.sh_off * HIST;
+  double* hr = bt.hr + (long long)d.sh_off * HIST;
+  int slot = nh % HIST;
+  for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+    hx[(long long)slot * ns + s] = qi[s];
+    hr[(long long)slot * ns + s] = qo[s] - qi[s];
+  }
+  nh += 1;
+  int m = nh < HIST ? nh : HIST;
+  __syncthreads();
+  if (m == 1) {
+    double* qn = bt.q_in + d.sh_off;
+    for (int s = threadIdx.x; s < ns; s += blockDim.x) qn[s] = qi[s] + beta * (qo[s] - qi[s]);
+  } else {
+    // B_ij = r_i . r_j (slots ordered oldest..newest)
+    __shared__ double Bm[(HIST + 1) * (HIST + 1)];
+    __shared__ double rhs[HIST + 1];
+    for (int pr = 0; pr < m * m; ++pr) {
+      int i = pr / m, j = pr % m;
+      int si_ = (nh - m + i) % HIST, sj_ = (nh - m + j) % HIST;
+      double loc = 0.0;
+      for (int s = threadIdx.x; s < ns; s += blockDim.x)
+        loc += hr[(long long)si_ * ns + s] * hr[(long long)sj_ * ns + s];
+      double v = block_sum(loc, red);
+      if (threadIdx.x == 0) Bm[i * (m + 1) + j] = v;
+    }
+    if (threadIdx.x == 0) {
+      int M = m + 1;
+      double tr = 0.0;
+      for (int i = 0; i < m; ++i) tr += Bm[i * M + i];
+      for (int i = 0; i < m; ++i) {
+        Bm[i * M + i] += 1e-14 * tr;
+        Bm[i * M + m] = 1.0;
+        Bm[m * M + i] = 1.0;
+        rhs[i] = 0.0;
+      }
+      Bm[m * M + m] = 0.0;
+      rhs[m] = 1.0;
+      solve_small(Bm, rhs, M);
+      for (int i = 0; i < m; ++i) coef[i] = rhs[i];
+    }
+    __syncthreads();
+    double* qn = bt.q_in + d.sh_off;
+    for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+      double v = 0.0;
+      for (int i = 0; i < m; ++i) {
+        int sl = (nh - m + i) % HIST;
+        v += coef[i] * (hx[(long long)sl * ns + s] + beta * hr[(long long)sl * ns + s]);
+      }
+      qn[s] = v;
+    }
+  }
+  if (threadIdx.x == 0) bt.nhist[si] = nh;
+}
+
+}  // namespace fx

@@ -1,0 +1,223 @@
+"""GPU library vs the FP64 oracle, through the C ABI.
+
+Tolerances: integer lists bit-exact; S/H0, CN and the embedding field to
+1e-12 (pure FP64 arithmetic, different summation order); fragment energies
+within 1e-8 Eh each and charges within 1e-8 e (both sides converge the SCC
+to 1e-10 in the charges, so the energies, variational in the density, agree
+to second order).
+"""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import workloads as w
+from oracle import fmo as F
+from oracle import xtb as X
+
+A2B = w.ANGSTROM_TO_BOHR
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2606_28022_amd import FmoXtb
+    return FmoXtb
+
+
+def _ctx(lib, s, **opt):
+    c = lib()
+    c.set_system(s.Z, s.xyz, s.frag, s.frag_charge)
+    if opt:
+        c.set_options(**opt)
+    return c
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return w.water_cluster_cube()
+
+
+@pytest.fixture(scope="module")
+def c4():
+    return w.pentacene_crystal()
+
+
+def test_lists_bit_exact_c1(lib, params, c1):
+    _say("lists C1")
+    c = _ctx(lib, c1, order=3)
+    scc, esd, tri = c.build_lists()
+    o_scc, o_esd, o_tri = F.build_lists(c1, 4 * A2B, order=3)
+    assert np.array_equal(scc, o_scc) and np.array_equal(esd, o_esd) and np.array_equal(tri, o_tri)
+
+
+def test_lists_bit_exact_pentacene(lib, params, c4):
+    _say("lists pentacene 23760 atoms")
+    c = _ctx(lib, c4)
+    scc, esd, _ = c.build_lists()
+    # oracle classification of every pair from its closest contact
+    o_scc, o_esd, _ = F.build_lists(c4, 4 * A2B, order=2)
+    assert np.array_equal(scc, o_scc)
+    assert np.array_equal(esd, o_esd)
+
+
+def test_cn_full_size(lib, params, c4):
+    _say("cn pentacene")
+    c = _ctx(lib, c4)
+    cn = c.compute_cn()
+    ref = X.coordination_numbers(params, c4.Z, c4.xyz)
+    assert np.max(np.abs(cn - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("frags", [(0,), (1, 2), (0, 3, 5)])
+def test_cluster_matrices_water(lib, params, c1, frags):
+    c = _ctx(lib, c1)
+    S, H = c.cluster_matrices(frags)
+    cn = X.coordination_numbers(params, c1.Z, c1.xyz)
+    atoms = np.concatenate([np.where(c1.frag == I)[0] for I in frags])
+    sx = X.XtbSystem(params, c1.Z[atoms], c1.xyz[atoms], cn[atoms])
+    assert np.max(np.abs(S - sx.S)) < 1e-13
+    assert np.max(np.abs(H - sx.H0)) < 1e-13
+
+
+def test_cluster_matrices_pentacene_dimer(lib, params, c4):
+    _say("S/H0 pentacene dimer")
+    c = _ctx(lib, c4)
+    scc, _, _ = c.build_lists()
+    I, J = scc[len(scc) // 2]
+    S, H = c.cluster_matrices((I, J))
+    cn = X.coordination_numbers(params, c4.Z, c4.xyz)
+    atoms = np.concatenate([np.where(c4.frag == I)[0], np.where(c4.frag == J)[0]])
+    sx = X.XtbSystem(params, c4.Z[atoms], c4.xyz[atoms], cn[atoms])
+    assert S.shape == (232, 232)
+    assert np.max(np.abs(S - sx.S)) < 1e-13
+    assert np.max(np.abs(H - sx.H0)) < 1e-13
+
+
+def test_embedding_field(lib, params):
+    _say("embedding field droplet")
+    s = w.water_droplet(256, radius=12.5, seed=21)
+    c = _ctx(lib, s)
+    rng = np.random.Generator(np.random.PCG64(5))
+    q = rng.normal(scale=0.3, size=c.n_shells)
+    phi = c.embedding_field(q)
+    sh = F.Shells(params, s)
+    ref = sh.potential(np.arange(sh.n), q, lambda a, b: sh.frag[a] == sh.frag[b])
+    assert np.max(np.abs(phi - ref)) < 1e-11
+
+
+@pytest.mark.parametrize("sizes", [[1, 2, 3, 8, 16], [31, 64, 76], [116, 152], [232]])
+def test_eigh_batched(lib, sizes):
+    _say(f"eigh {sizes}")
+    rng = np.random.Generator(np.random.PCG64(sum(sizes)))
+    mats = []
+    for n in sizes:
+        a = rng.normal(size=(n, n))
+        a = 0.5 * (a + a.T)
+        if n > 3:
+            a[0, 0] = a[1, 1]  # near-degenerate start
+        mats.append(a)
+    c = lib()
+    out = c.eigh_batched(mats)
+    for a, (wv, V) in zip(mats, out):
+        n = a.shape[0]
+        ref = np.linalg.eigvalsh(a)
+        assert np.max(np.abs(np.sort(wv) - ref)) < 1e-12 * max(1.0, np.abs(ref).max()) * n
+        assert np.max(np.abs(V @ V.T - np.eye(n))) < 1e-12 * n
+        assert np.max(np.abs(a @ V.T - V.T * wv)) < 1e-11 * n
+
+
+def _compare_fmo(c, r_or, nscc, tol_e=1e-8):
+    em, ds, de, dt = c.energies()
+    assert np.max(np.abs(em - r_or.E_mono)) < tol_e
+    if nscc:
+        assert np.max(np.abs(ds - r_or.dE_scc)) < tol_e
+    if len(r_or.dE_esd):
+        assert np.max(np.abs(de - r_or.dE_esd)) < tol_e
+    assert np.max(np.abs(c.charges() - r_or.q)) < 1e-8
+
+
+def test_fmo2_energy_c1_all_scc(lib, params, c1):
+    """Config: 8 waters, every pair a full SCC dimer."""
+    _say("FMO2 C1 all-SCC")
+    c = _ctx(lib, c1, cutoff_bohr=1e3, want_gradient=0)
+    r = c.run()
+    ro = F.fmo(c1, params, 1e3)
+    assert r["solves_dimer"] == 28
+    _compare_fmo(c, ro, 28)
+    assert abs(r["e_total"] - ro.E) < 1e-8
+
+
+def test_fmo2_energy_c1_mixed_pairs(lib, params, c1):
+    _say("FMO2 C1 4A cutoff")
+    c = _ctx(lib, c1, want_gradient=0)
+    r = c.run()
+    ro = F.fmo(c1, params, 4 * A2B)
+    _compare_fmo(c, ro, len(ro.lists[0]))
+    assert abs(r["e_total"] - ro.E) < 1e-8
+
+
+def test_fmo3_energy_small(lib, params, c1):
+    _say("FMO3 C1 subset")
+    s = c1.subset([0, 1, 2, 3, 4])
+    c = _ctx(lib, s, order=3, cutoff_bohr=6 * A2B, want_gradient=0)
+    r = c.run()
+    ro = F.fmo(s, params, 6 * A2B, order=3)
+    assert r["solves_trimer"] == len(ro.lists[2]) > 0
+    em, ds, de, dt = c.energies()
+    assert np.max(np.abs(dt - ro.dE_tri)) < 1e-8
+    assert abs(r["e_total"] - ro.E) < 1e-8
+
+
+def test_single_fragment_equals_xtb(lib, params, c1):
+    s = c1.subset([2])
+    c = _ctx(lib, s, want_gradient=0)
+    r = c.run()
+    assert abs(r["e_total"] - F.xtb_energy(s, params)[0]) < 1e-8
+
+
+def test_plain_loop_matches_batched(lib, params, c1):
+    _say("plain vs batched")
+    c = _ctx(lib, c1, want_gradient=0)
+    rb = c.run()
+    qb = c.charges()
+    c.set_options(schedule=1)
+    rp = c.run()
+    assert abs(rb["e_total"] - rp["e_total"]) < 1e-9
+    assert np.max(np.abs(qb - c.charges())) < 1e-9
+
+
+def test_error_paths(lib, c1):
+    from paper_2606_28022_amd.binding import FxError, FX_E_INVALID, FX_E_UNSUPPORTED, FX_E_STATE, FX_E_NOCONV
+    c = lib()
+    with pytest.raises(FxError) as e:
+        c.run()
+    assert e.value.code == FX_E_STATE
+    xyz = c1.xyz.copy()
+    xyz[3, 1] = np.nan
+    with pytest.raises(FxError) as e:
+        c.set_system(c1.Z, xyz, c1.frag, c1.frag_charge)
+    assert e.value.code == FX_E_INVALID
+    Z = c1.Z.copy()
+    Z[0] = 26
+    with pytest.raises(FxError) as e:
+        c.set_system(Z, c1.xyz, c1.frag, c1.frag_charge)
+    assert e.value.code == FX_E_UNSUPPORTED
+    xyz = c1.xyz.copy()
+    xyz[1] = xyz[0] + 0.1
+    with pytest.raises(FxError) as e:
+        c.set_system(c1.Z, xyz, c1.frag, c1.frag_charge)
+    assert e.value.code == FX_E_INVALID
+    c.set_system(c1.Z, c1.xyz, c1.frag, c1.frag_charge)
+    c.set_options(max_iter=1, want_gradient=0)
+    with pytest.raises(FxError) as e:
+        c.run()
+    assert e.value.code == FX_E_NOCONV
