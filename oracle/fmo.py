@@ -10,7 +10,8 @@ Passages followed:
   phi_s = sum_{K != I} sum_{t in K} gamma_st dq^K_t in its Fock matrix;
 * monomer self-consistency (section "FMO-xTB"): monomers are solved
   repeatedly in the field of the others until all charges are converged
-  (Jacobi sweeps with fully converged inner SCC);
+  (sweeps with fully converged inner SCC; the sweep map is driven to its
+  fixed point by Anderson mixing of the monomer charges);
 * FMO2 energy, eq. fmo2-energy-components, with the embedding correction
   eq. dimer_embedding_correction and the charge transfer eq. ddq_calc;
   E_I, E_IJ are read as internal energies (embedding acts in the Fock matrix
@@ -175,19 +176,42 @@ def fmo(system, params, cutoff_bohr, order=2, lists=None, scc_tol=1e-10,
     q = np.zeros(sh.n)   # superposition guess: zero shell charges
     res = [None] * F
     same_frag = lambda s, t: sh.frag[s] == sh.frag[t]
+    # Monomer self-consistency: every sweep solves all monomers in the field of
+    # the current charges; the sweep map q -> q_out is driven to its fixed
+    # point with Anderson (Pulay) mixing of the whole charge vector, which
+    # also converges where plain repeated sweeps oscillate.
+    X_h, R_h = [], []
+    beta = 0.5
     for it in range(1, max_macro + 1):
         phi = sh.potential(np.arange(sh.n), q, same_frag)
         qn = q.copy()
         for I in range(F):
-            g = q[fsh[I]]
+            g = res[I].q if res[I] is not None else q[fsh[I]]
             res[I] = scc(mono[I], phi[fsh[I]], q_guess=g, tol=scc_tol)
             qn[fsh[I]] = res[I].q
-        delta = float(np.max(np.abs(qn - q)))
-        q = qn
+        r = qn - q
+        delta = float(np.max(np.abs(r)))
         if verbose:
             print("macro", it, delta)
         if delta < macro_tol:
+            q = qn
             break
+        X_h.append(q.copy())
+        R_h.append(r)
+        if len(X_h) > 8:
+            X_h.pop(0)
+            R_h.pop(0)
+        m = len(X_h)
+        if m == 1:
+            q = q + beta * r
+        else:
+            M = np.zeros((m + 1, m + 1))
+            M[:m, :m] = [[R_h[i] @ R_h[j] for j in range(m)] for i in range(m)]
+            M[:m, m] = M[m, :m] = 1.0
+            rhs = np.zeros(m + 1)
+            rhs[m] = 1.0
+            c = np.linalg.lstsq(M, rhs, rcond=None)[0][:m]
+            q = sum(c[k] * (X_h[k] + beta * R_h[k]) for k in range(m))
     out = FMOResult()
     out.macro_iter = it
     out.macro_converged = delta < macro_tol

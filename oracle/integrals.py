@@ -147,14 +147,12 @@ class ElementBasis:
             self.T[s1.ao0, s2.ao0] = -N * s12
 
 
-_ebasis_cache = {}
-
-
 def element_basis(params, Z):
-    key = (id(params), int(Z))
-    if key not in _ebasis_cache:
-        _ebasis_cache[key] = ElementBasis(params, Z)
-    return _ebasis_cache[key]
+    """Element basis, cached on the parameter object."""
+    cache = params.__dict__.setdefault("_element_basis", {})
+    if int(Z) not in cache:
+        cache[int(Z)] = ElementBasis(params, Z)
+    return cache[int(Z)]
 
 
 def pair_blocks(params, ZA, ZB, R):

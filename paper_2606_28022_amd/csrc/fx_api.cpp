@@ -318,6 +318,7 @@ void Ctx::build_matrices(Batch& b) {
 // Returns the number of systems that failed to converge.
 int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* iters_out) {
   if (list.empty()) return 0;
+  const double t_start = now_ms();
   DevBatch db = b.dev();
   DevSystem ds = dev_system();
   const int nl = (int)list.size();
@@ -326,8 +327,22 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
   hipLaunchKernelGGL(k_reset_state, dim3((nl + 255) / 256), dim3(256), 0, stream, db, b.d_list.p, nl);
   check(hipGetLastError(), "k_reset_state");
   if (cold) {
-    hipLaunchKernelGGL(k_cholinv, dim3(nl), dim3(256), 0, stream, db, b.d_list.p);
-    check(hipGetLastError(), "k_cholinv");
+    const int nt = (b.max_nao + 31) / 32;
+    if (b.init_from_mono && mb.nsys > 0) {
+      // C0 = blockdiag(monomer C); G = C0^T S C0 = L L^T; C = C0 L^-T
+      hipLaunchKernelGGL(k_cluster_init_ct, dim3(nl), dim3(256), 0, stream, db, b.d_list.p, mb.dev());
+      hipLaunchKernelGGL(k_gemm, dim3(nt * nt, nl), dim3(256), 0, stream, db, b.d_list.p, 0, b.Ct.p, b.S.p, b.Tm.p,
+                         (const double*)nullptr);
+      hipLaunchKernelGGL(k_gemm, dim3(nt * nt, nl), dim3(256), 0, stream, db, b.d_list.p, 1, b.Tm.p, b.Ct.p, b.Fm.p,
+                         (const double*)nullptr);
+      hipLaunchKernelGGL(k_cholinv, dim3(nl), dim3(256), 0, stream, db, b.d_list.p, b.Fm.p, b.Tm.p, b.Pm.p);
+      hipLaunchKernelGGL(k_gemm, dim3(nt * nt, nl), dim3(256), 0, stream, db, b.d_list.p, 0, b.Pm.p, b.Ct.p, b.Tm.p,
+                         (const double*)nullptr);
+      check(hipMemcpyAsync(b.Ct.p, b.Tm.p, sizeof(double) * b.tot_mat, hipMemcpyDeviceToDevice, stream), "copy");
+    } else {
+      hipLaunchKernelGGL(k_cholinv, dim3(nl), dim3(256), 0, stream, db, b.d_list.p, b.S.p, b.Tm.p, b.Ct.p);
+    }
+    check(hipGetLastError(), "initial basis");
   }
   std::vector<int> active = list;
   std::vector<int> status(b.nsys);
@@ -343,12 +358,13 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     hipLaunchKernelGGL(k_gemm, dim3(nt * nt, na), dim3(256), 0, stream, db, d_act.p, 1, b.Tm.p, b.Ct.p, b.Fm.p,
                        (const double*)nullptr);
     hipLaunchKernelGGL(k_jacobi, dim3(na), dim3(256), 0, stream, db, d_act.p, jacobi_max_sweeps, jacobi_tol,
-                       b.sweeps.p);
+                       jacobi_thr_scale, b.sweeps.p);
     hipLaunchKernelGGL(k_fermi, dim3(na), dim3(256), 0, stream, ds, db, d_act.p);
     hipLaunchKernelGGL(k_gemm, dim3(nt * nt, na), dim3(256), 0, stream, db, d_act.p, 2, b.Ct.p, b.Ct.p, b.Pm.p,
                        (const double*)b.occ.p);
-    hipLaunchKernelGGL(k_charges_mix, dim3(na), dim3(256), 0, stream, ds, db, d_act.p, opt.scc_tol,
-                       opt.energy_tol, opt.max_iter, mix_beta);
+    hipLaunchKernelGGL(k_charges_mix, dim3(na), dim3(256), 0, stream, ds, db, d_act.p,
+                       scc_tol_cur > 0 ? scc_tol_cur : opt.scc_tol, etol_cur > 0 ? etol_cur : opt.energy_tol,
+                       opt.max_iter, mix_beta);
     check(hipGetLastError(), "scc iteration");
     b.status.download(status, stream);
     sync();
@@ -360,6 +376,16 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
   b.status.download(status, stream);
   b.niter.download(niter, stream);
   sync();
+  if (verbose) {
+    long long tot = 0;
+    int mx = 0;
+    for (int s : list) {
+      tot += niter[s];
+      mx = std::max(mx, niter[s]);
+    }
+    std::fprintf(stderr, "[fx] scc batch of %d systems (nao<=%d): %lld iterations, max %d, %.1f ms\n", nl,
+                 b.max_nao, tot, mx, now_ms() - t_start);
+  }
   int failed = 0;
   long long iters = 0;
   for (int s : list) {
@@ -570,22 +596,61 @@ void Ctx::run(fx_result* out) {
   int macro = 0;
   double delta = 1e300;
   bool cold = true;
+  // Anderson mixing of the monomer charge vector across sweeps
+  DevBuf<double> hX, hR, hB, hC;
+  hX.alloc((long long)HIST * Nsh);
+  hR.alloc((long long)HIST * Nsh);
+  hB.alloc(HIST * HIST);
+  hC.alloc(HIST);
+  std::vector<int> slots;
+  int next_slot = 0;
+  const unsigned gN = (unsigned)((Nsh + 255) / 256);
   for (macro = 1; macro <= opt.max_macro; ++macro) {
     field(d_q.p, d_phi.p);
     hipLaunchKernelGGL(k_gather_shell, dim3(mb.nsys), dim3(64), 0, stream, dmb, d_phi.p, mb.phi.p);
-    hipLaunchKernelGGL(k_gather_shell, dim3(mb.nsys), dim3(64), 0, stream, dmb, d_q.p, mb.q_in.p);
+    if (cold)
+      hipLaunchKernelGGL(k_gather_shell, dim3(mb.nsys), dim3(64), 0, stream, dmb, d_q.p, mb.q_in.p);
+    else
+      check(hipMemcpyAsync(mb.q_in.p, mb.q_out.p, sizeof(double) * mb.tot_sh, hipMemcpyDeviceToDevice, stream),
+            "copy");
+    // inner solves only as tight as the outer residual requires
+    scc_tol_cur = std::max(opt.scc_tol, std::min(1e-4, 1e-3 * delta));
+    etol_cur = std::max(opt.energy_tol, std::min(1e-4, 1e-4 * delta));
     int failed = solve_batch(mb, cold, &it_mono);
+    scc_tol_cur = etol_cur = -1.0;
     cold = false;
     res.solves_mono += mb.nsys;
-    if (failed) all_conv = false;
     hipLaunchKernelGGL(k_scatter_shell, dim3(mb.nsys), dim3(64), 0, stream, dmb, mb.q_out.p, d_qnew.p);
     hipLaunchKernelGGL(k_max_absdiff, dim3(1), dim3(256), 0, stream, d_qnew.p, d_q.p, Nsh, d_scalar.p);
-    check(hipMemcpyAsync(d_q.p, d_qnew.p, sizeof(double) * Nsh, hipMemcpyDeviceToDevice, stream), "copy");
     std::vector<double> hs(1);
     d_scalar.download(hs, stream, 1);
     sync();
     delta = hs[0];
-    if (delta < opt.macro_tol) break;
+    if (verbose) std::fprintf(stderr, "[fx] monomer sweep %d: max |dq_out - dq_in| = %.3e, %.1f ms\n", macro, delta, now_ms() - t1);
+    if (delta < opt.macro_tol) {
+      if (failed) all_conv = false;
+      check(hipMemcpyAsync(d_q.p, d_qnew.p, sizeof(double) * Nsh, hipMemcpyDeviceToDevice, stream), "copy");
+      break;
+    }
+    // history update and mixing
+    int slot;
+    if ((int)slots.size() < HIST) {
+      slot = next_slot++;
+    } else {
+      slot = slots.front();
+      slots.erase(slots.begin());
+    }
+    slots.push_back(slot);
+    hipLaunchKernelGGL(k_hist_store, dim3(gN), dim3(256), 0, stream, d_q.p, d_qnew.p, (long long)Nsh, slot, hX.p,
+                       hR.p);
+    Slots sl;
+    sl.m = (int)slots.size();
+    for (int k = 0; k < sl.m; ++k) sl.id[k] = slots[k];
+    hipLaunchKernelGGL(k_hist_gram, dim3(sl.m * sl.m), dim3(256), 0, stream, hR.p, (long long)Nsh, sl, hB.p);
+    hipLaunchKernelGGL(k_hist_coef, dim3(1), dim3(1), 0, stream, hB.p, sl, hC.p);
+    hipLaunchKernelGGL(k_hist_mix, dim3(gN), dim3(256), 0, stream, hX.p, hR.p, (long long)Nsh, sl, hC.p, macro_beta,
+                       d_q.p);
+    check(hipGetLastError(), "monomer mixing");
   }
   if (macro > opt.max_macro) {
     all_conv = false;
@@ -609,6 +674,7 @@ void Ctx::run(fx_result* out) {
     std::vector<std::array<int, 3>> cl(nscc);
     for (long long k = 0; k < nscc; ++k) cl[k] = {scc_pairs[2 * k], scc_pairs[2 * k + 1], -1};
     build_batch(db_, cl, 2);
+    db_.init_from_mono = true;
     build_matrices(db_);
     DevBatch ddb = db_.dev();
     hipLaunchKernelGGL(k_cluster_phi, dim3(db_.nsys), dim3(128), 0, stream, dev_system(), ddb, d_phi.p, d_q.p);
@@ -633,6 +699,7 @@ void Ctx::run(fx_result* out) {
     std::vector<std::array<int, 3>> cl(ntri);
     for (long long k = 0; k < ntri; ++k) cl[k] = {trimers[3 * k], trimers[3 * k + 1], trimers[3 * k + 2]};
     build_batch(tb_, cl, 3);
+    tb_.init_from_mono = true;
     build_matrices(tb_);
     DevBatch dtb = tb_.dev();
     hipLaunchKernelGGL(k_cluster_phi, dim3(tb_.nsys), dim3(128), 0, stream, dev_system(), dtb, d_phi.p, d_q.p);

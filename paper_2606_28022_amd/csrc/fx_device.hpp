@@ -41,6 +41,12 @@ struct SysDesc {
   double nel;
 };
 
+// History slots of a mixing scheme, oldest first.
+struct Slots {
+  int m;
+  int id[HIST];
+};
+
 // Read-only supersystem tables.
 struct DevSystem {
   int natoms, nshells, nfrag;

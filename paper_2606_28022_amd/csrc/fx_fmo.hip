@@ -106,4 +106,94 @@ __global__ void k_sum_neumaier(const double* const* arrays, const long long* len
   }
 }
 
+// ---------------------------------------------------------------------------
+// Anderson (Pulay) mixing of a long vector (the monomer charges of the
+// self-consistent embedding).  History slots are passed oldest first.
+// B_ij = r_i . r_j, one work-group per (i, j), fixed-order tree reduction
+__global__ void k_hist_gram(const double* R, long long n, Slots sl, double* B) {
+  int i = blockIdx.x / sl.m, j = blockIdx.x % sl.m;
+  const double* a = R + (long long)sl.id[i] * n;
+  const double* b = R + (long long)sl.id[j] * n;
+  __shared__ double red[256];
+  double v = 0.0;
+  for (long long k = threadIdx.x; k < n; k += blockDim.x) v += a[k] * b[k];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) B[i * sl.m + j] = red[0];
+}
+
+// minimise |sum c_k r_k| subject to sum c_k = 1 (bordered normal equations,
+// Gaussian elimination with partial pivoting); one thread
+__global__ void k_hist_coef(const double* B, Slots sl, double* coef) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int m = sl.m, M = m + 1;
+  double A[(HIST + 1) * (HIST + 1)], rhs[HIST + 1];
+  double tr = 0.0;
+  for (int i = 0; i < m; ++i) tr += B[i * m + i];
+  for (int i = 0; i < M; ++i) {
+    rhs[i] = (i == m) ? 1.0 : 0.0;
+    for (int j = 0; j < M; ++j) {
+      double v;
+      if (i < m && j < m) v = B[i * m + j] + (i == j ? 1e-14 * tr : 0.0);
+      else if (i == m && j == m) v = 0.0;
+      else v = 1.0;
+      A[i * M + j] = v;
+    }
+  }
+  for (int c = 0; c < M; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < M; ++r)
+      if (fabs(A[r * M + c]) > fabs(A[piv * M + c])) piv = r;
+    if (piv != c) {
+      for (int k = 0; k < M; ++k) {
+        double t = A[c * M + k];
+        A[c * M + k] = A[piv * M + k];
+        A[piv * M + k] = t;
+      }
+      double t = rhs[c];
+      rhs[c] = rhs[piv];
+      rhs[piv] = t;
+    }
+    double dv = A[c * M + c];
+    if (fabs(dv) < 1e-300) dv = 1e-300;
+    for (int r = c + 1; r < M; ++r) {
+      double f = A[r * M + c] / dv;
+      for (int k = c; k < M; ++k) A[r * M + k] -= f * A[c * M + k];
+      rhs[r] -= f * rhs[c];
+    }
+  }
+  for (int c = M - 1; c >= 0; --c) {
+    double v = rhs[c];
+    for (int k = c + 1; k < M; ++k) v -= A[c * M + k] * rhs[k];
+    double dv = A[c * M + c];
+    rhs[c] = v / (fabs(dv) < 1e-300 ? 1e-300 : dv);
+  }
+  for (int i = 0; i < m; ++i) coef[i] = rhs[i];
+}
+
+// q = sum_k c_k (x_k + beta r_k)
+__global__ void k_hist_mix(const double* X, const double* R, long long n, Slots sl, const double* coef, double beta,
+                           double* q) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double v = 0.0;
+  for (int i = 0; i < sl.m; ++i) {
+    long long o = (long long)sl.id[i] * n + k;
+    v += coef[i] * (X[o] + beta * R[o]);
+  }
+  q[k] = v;
+}
+
+// store x and r = y - x into history slot `slot`, and max |r| into *dmax
+__global__ void k_hist_store(const double* x, const double* y, long long n, int slot, double* X, double* R) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  X[(long long)slot * n + k] = x[k];
+  R[(long long)slot * n + k] = y[k] - x[k];
+}
+
 }  // namespace fx

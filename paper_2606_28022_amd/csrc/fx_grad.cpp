@@ -1,8 +1,330 @@
-// FMO2 analytic gradient driver (filled in by the gradient kernels).
+// Host driver of the FMO2 analytic gradient: explicit fragment terms, the
+// inter-fragment kernel derivatives, the response of the self-consistent
+// embedding and the CN chain (section "Analytic energy gradients").  The
+// host only builds index tables and launches kernels; per-atom sums are
+// gathered on the device in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
 #include "fx_host.hpp"
+#include "fx_kernels.hpp"
 
 namespace fx {
 
-void Ctx::gradient() { throw FxError(FX_E_UNSUPPORTED, "gradient not available in this build"); }
+__global__ void k_mo_order(DevBatch bt, const int* nocc, int* order);
+__global__ void k_resp_Q(DevSystem sys, DevBatch bt, const double* SCt, const int* order, const int* nocc,
+                         const long long* qoff, double* Q);
+__global__ void k_resp_M(DevBatch bt, const int* order, const int* nocc, const long long* qoff, const double* Q,
+                         double* M);
+__global__ void k_resp_R(DevSystem sys, DevBatch bt, const double* M, double* Wk, double* R);
+__global__ void k_resp_apply(DevBatch bt, const double* R, const double* M, const double* y, double* w, double* u);
+__global__ void k_resp_Z(DevBatch bt, const int* order, const int* nocc, const long long* qoff, const double* Q,
+                         const double* w, double* Zm, double* Ze);
+__global__ void k_rowscale(DevBatch bt, const double* wsh, const double* P, double* out);
+__global__ void k_sym_inplace(DevBatch bt, double* A);
+__global__ void k_resp_DS(DevBatch bt, const double* Zb, const double* WZ, const double* X2, const double* wsh,
+                          double* DS, double* gx);
+__global__ void k_cluster_cross(DevSystem sys, DevBatch bt, const double* x, double* out);
+__global__ void k_gather_csr(int n, const int* rowptr, const int* ent, const double* src, const double* base,
+                             double sign, double* dst);
+__global__ void k_axpy(long long n, const double* x, double a, const double* y, double* out);
+__global__ void k_grad_contract(DevSystem sys, DevBatch bt, const int* list, const double* DHp, const double* DSp,
+                                const double* gx, const double* gy, const double* wsys, int with_rep, int accumulate,
+                                double* g_out, double* F_out);
+__global__ void k_grad_pair_corr(DevSystem sys, DevBatch bt, const double* qmono, const double* ddq, double* g_out);
+__global__ void k_force_inter(DevSystem sys, const double* q, const double* av, int nchunk, double* part);
+__global__ void k_force_reduce(int N, int nchunk, const double* part, double* out);
+__global__ void k_cn_grad(DevSystem sys, const double* Ftot, double* g);
+__global__ void k_gather_atoms(int N, const int* rowptr, const int* ent_batch, const long long* ent_off,
+                               const double* const* g_batches, const double* const* F_batches, double* g_tot,
+                               double* F_tot, int mode);
+__global__ void k_final_shift(DevSystem sys, DevBatch bt, double* wvec);
+__global__ void k_make_DS(DevBatch bt, const double* P, const double* W, double* out);
+
+namespace {
+
+// explicit per-system terms of one batch into (g_sys, F_sys)
+void explicit_terms(Ctx& c, Batch& b, const double* wsys, DevBuf<double>& g_sys, DevBuf<double>& F_sys) {
+  DevBatch db = b.dev();
+  DevSystem ds = c.dev_system();
+  DevBuf<double> wvec;
+  wvec.alloc(b.tot_ao);
+  hipLaunchKernelGGL(k_final_shift, dim3(b.nsys), dim3(256), 0, c.stream, ds, db, wvec.p);
+  const int nt = (b.max_nao + 31) / 32;
+  std::vector<int> all(b.nsys);
+  for (int k = 0; k < b.nsys; ++k) all[k] = k;
+  b.d_list.upload(all);
+  // W = C diag(n eps) C^T into T, D_S into F
+  hipLaunchKernelGGL(k_gemm, dim3(nt * nt, b.nsys), dim3(256), 0, c.stream, db, b.d_list.p, 2, b.Ct.p, b.Ct.p, b.Tm.p,
+                     (const double*)wvec.p);
+  hipLaunchKernelGGL(k_make_DS, dim3(b.nsys), dim3(256), 0, c.stream, db, b.Pm.p, b.Tm.p, b.Fm.p);
+  int natot = 0;
+  for (auto& d : b.h_desc) natot += d.nat;
+  g_sys.alloc(3LL * natot);
+  F_sys.alloc(natot);
+  hipLaunchKernelGGL(k_grad_contract, dim3(b.nsys), dim3(256), 0, c.stream, ds, db, b.d_list.p, b.Pm.p, b.Fm.p,
+                     b.q_out.p, b.q_out.p, wsys, 1, 0, g_sys.p, F_sys.p);
+  Ctx::check(hipGetLastError(), "explicit gradient terms");
+}
+
+}  // namespace
+
+void Ctx::gradient() {
+  const double t0 = now_ms();
+  DevSystem ds = dev_system();
+  const long long nscc = (long long)scc_pairs.size() / 2;
+  // ---- monomer weights c_I = 1 - (number of SCC dimers containing I)
+  std::vector<double> cw(F, 1.0);
+  for (long long k = 0; k < nscc; ++k) {
+    cw[scc_pairs[2 * k]] -= 1.0;
+    cw[scc_pairs[2 * k + 1]] -= 1.0;
+  }
+  DevBuf<double> d_cw;
+  d_cw.upload(cw);
+
+  // ---- explicit fragment terms
+  DevBuf<double> gm, Fm_, gd, Fd;
+  explicit_terms(*this, mb, d_cw.p, gm, Fm_);
+  if (nscc > 0) {
+    explicit_terms(*this, db_, nullptr, gd, Fd);
+    DevBatch ddb = db_.dev();
+    hipLaunchKernelGGL(k_grad_pair_corr, dim3(db_.nsys), dim3(128), 0, stream, ds, ddb, d_q.p, ddq_scc.p, gd.p);
+    check(hipGetLastError(), "k_grad_pair_corr");
+  }
+
+  // ---- accumulated dimer charge transfer qbar and the Lagrangian potential v
+  //      v = field_excl(qbar) - sum over SCC dimers containing K of their
+  //      cross-fragment potential of ddq
+  DevBuf<double> qbar, v, u, a;
+  qbar.alloc(Nsh);
+  v.alloc(Nsh);
+  u.alloc(Nsh);
+  a.alloc(Nsh);
+  check(hipMemsetAsync(qbar.p, 0, sizeof(double) * Nsh, stream), "memset");
+  check(hipMemsetAsync(u.p, 0, sizeof(double) * Nsh, stream), "memset");
+  DevBuf<int> csr_ptr, csr_ent;
+  if (nscc > 0) {
+    // CSR: global shell -> local shell slots of the dimer batch, dimer order
+    std::vector<int> cnt(Nsh + 1, 0), ent;
+    std::vector<std::vector<int>> rows(Nsh);
+    std::vector<int> shg;
+    db_.d_sh_global.download(shg, stream);
+    sync();
+    for (int k = 0; k < (int)shg.size(); ++k) rows[shg[k]].push_back(k);
+    for (int s = 0; s < Nsh; ++s) {
+      cnt[s + 1] = cnt[s] + (int)rows[s].size();
+      for (int e : rows[s]) ent.push_back(e);
+    }
+    csr_ptr.upload(cnt);
+    csr_ent.upload(ent.empty() ? std::vector<int>{0} : ent);
+    const unsigned g = (unsigned)((Nsh + 255) / 256);
+    hipLaunchKernelGGL(k_gather_csr, dim3(g), dim3(256), 0, stream, Nsh, csr_ptr.p, csr_ent.p, ddq_scc.p,
+                       (const double*)nullptr, 1.0, qbar.p);
+    DevBuf<double> vc, fq;
+    vc.alloc(db_.tot_sh);
+    fq.alloc(Nsh);
+    DevBatch ddb = db_.dev();
+    hipLaunchKernelGGL(k_cluster_cross, dim3(db_.nsys), dim3(128), 0, stream, ds, ddb, ddq_scc.p, vc.p);
+    field(qbar.p, fq.p);
+    hipLaunchKernelGGL(k_gather_csr, dim3(g), dim3(256), 0, stream, Nsh, csr_ptr.p, csr_ent.p, vc.p, fq.p, -1.0,
+                       v.p);
+    check(hipGetLastError(), "lagrangian potential");
+  } else {
+    check(hipMemsetAsync(v.p, 0, sizeof(double) * Nsh, stream), "memset");
+  }
+
+  // ---- response of the monomer charges (adjoint of the self-consistency)
+  if (opt.want_response && nscc > 0) {
+    const double tr = now_ms();
+    Batch& b = mb;
+    DevBatch dmb = b.dev();
+    std::vector<int> nocc(b.nsys);
+    std::vector<long long> qoff(b.nsys + 1, 0);
+    for (int k = 0; k < b.nsys; ++k) {
+      const SysDesc& d = b.h_desc[k];
+      int ne = (int)std::lround(d.nel);
+      if (std::fabs(d.nel - ne) > 1e-9 || (ne & 1))
+        throw FxError(FX_E_UNSUPPORTED, "the response term needs closed-shell monomers");
+      nocc[k] = ne / 2;
+      qoff[k + 1] = qoff[k] + (long long)d.nsh * nocc[k] * (d.nao - nocc[k]);
+    }
+    DevBuf<int> d_nocc, order;
+    d_nocc.upload(nocc);
+    DevBuf<long long> d_qoff;
+    d_qoff.upload(qoff);
+    order.alloc(b.tot_ao);
+    DevBuf<double> Q, M, R, Wk, G1, G2, G3, w, y, yn, ul, gx;
+    Q.alloc(qoff[b.nsys]);
+    long long tot_gam = 0;
+    for (auto& d : b.h_desc) tot_gam += (long long)d.nsh * d.nsh;
+    M.alloc(tot_gam);
+    R.alloc(tot_gam);
+    Wk.alloc(tot_gam);
+    G1.alloc(b.tot_mat);
+    G2.alloc(b.tot_mat);
+    G3.alloc(b.tot_mat);
+    w.alloc(b.tot_sh);
+    y.alloc(b.tot_sh);
+    ul.alloc(b.tot_sh);
+    gx.alloc(b.tot_sh);
+    std::vector<int> all(b.nsys);
+    for (int k = 0; k < b.nsys; ++k) all[k] = k;
+    b.d_list.upload(all);
+    const int nt = (b.max_nao + 31) / 32;
+    hipLaunchKernelGGL(k_mo_order, dim3(b.nsys), dim3(256), 0, stream, dmb, d_nocc.p, order.p);
+    // (SC)^T = Ct S into G1
+    hipLaunchKernelGGL(k_gemm, dim3(nt * nt, b.nsys), dim3(256), 0, stream, dmb, b.d_list.p, 0, b.Ct.p, b.S.p, G1.p,
+                       (const double*)nullptr);
+    hipLaunchKernelGGL(k_resp_Q, dim3(b.nsys), dim3(256), 0, stream, ds, dmb, G1.p, order.p, d_nocc.p, d_qoff.p,
+                       Q.p);
+    hipLaunchKernelGGL(k_resp_M, dim3(b.nsys), dim3(256), 0, stream, dmb, order.p, d_nocc.p, d_qoff.p, Q.p, M.p);
+    hipLaunchKernelGGL(k_resp_R, dim3(b.nsys), dim3(256), 0, stream, ds, dmb, M.p, Wk.p, R.p);
+    check(hipGetLastError(), "response setup");
+    // adjoint sweeps y = v + field_excl(u(y)), Anderson-accelerated
+    DevBuf<double> yg, yng, hX, hR, hB, hC, fu;
+    yg.alloc(Nsh);
+    yng.alloc(Nsh);
+    fu.alloc(Nsh);
+    hX.alloc((long long)HIST * Nsh);
+    hR.alloc((long long)HIST * Nsh);
+    hB.alloc(HIST * HIST);
+    hC.alloc(HIST);
+    check(hipMemcpyAsync(yg.p, v.p, sizeof(double) * Nsh, hipMemcpyDeviceToDevice, stream), "copy");
+    std::vector<int> slots;
+    int next_slot = 0;
+    const unsigned gN = (unsigned)((Nsh + 255) / 256);
+    double delta = 1e300;
+    int it = 0;
+    for (it = 1; it <= 400; ++it) {
+      hipLaunchKernelGGL(k_gather_shell, dim3(b.nsys), dim3(64), 0, stream, dmb, yg.p, y.p);
+      hipLaunchKernelGGL(k_resp_apply, dim3(b.nsys), dim3(256), 0, stream, dmb, R.p, M.p, y.p, w.p, ul.p);
+      hipLaunchKernelGGL(k_scatter_shell, dim3(b.nsys), dim3(64), 0, stream, dmb, ul.p, u.p);
+      field(u.p, fu.p);
+      hipLaunchKernelGGL(k_axpy, dim3(gN), dim3(256), 0, stream, (long long)Nsh, v.p, 1.0, fu.p, yng.p);
+      hipLaunchKernelGGL(k_max_absdiff, dim3(1), dim3(256), 0, stream, yng.p, yg.p, Nsh, d_scalar.p);
+      std::vector<double> hs(1);
+      d_scalar.download(hs, stream, 1);
+      sync();
+      delta = hs[0];
+      if (verbose) std::fprintf(stderr, "[fx] response sweep %d: max |dy| = %.3e\n", it, delta);
+      if (delta < response_tol) break;
+      int slot;
+      if ((int)slots.size() < HIST) {
+        slot = next_slot++;
+      } else {
+        slot = slots.front();
+        slots.erase(slots.begin());
+      }
+      slots.push_back(slot);
+      hipLaunchKernelGGL(k_hist_store, dim3(gN), dim3(256), 0, stream, yg.p, yng.p, (long long)Nsh, slot, hX.p, hR.p);
+      Slots sl;
+      sl.m = (int)slots.size();
+      for (int k = 0; k < sl.m; ++k) sl.id[k] = slots[k];
+      hipLaunchKernelGGL(k_hist_gram, dim3(sl.m * sl.m), dim3(256), 0, stream, hR.p, (long long)Nsh, sl, hB.p);
+      hipLaunchKernelGGL(k_hist_coef, dim3(1), dim3(1), 0, stream, hB.p, sl, hC.p);
+      hipLaunchKernelGGL(k_hist_mix, dim3(gN), dim3(256), 0, stream, hX.p, hR.p, (long long)Nsh, sl, hC.p, 1.0,
+                         yg.p);
+      check(hipGetLastError(), "response mixing");
+    }
+    response_sweeps = it;
+    // final w, u from the converged y
+    hipLaunchKernelGGL(k_gather_shell, dim3(b.nsys), dim3(64), 0, stream, dmb, yng.p, y.p);
+    hipLaunchKernelGGL(k_resp_apply, dim3(b.nsys), dim3(256), 0, stream, dmb, R.p, M.p, y.p, w.p, ul.p);
+    hipLaunchKernelGGL(k_scatter_shell, dim3(b.nsys), dim3(64), 0, stream, dmb, ul.p, u.p);
+    // Z and its AO forms
+    hipLaunchKernelGGL(k_resp_Z, dim3(b.nsys), dim3(256), 0, stream, dmb, order.p, d_nocc.p, d_qoff.p, Q.p, w.p,
+                       G2.p, G3.p);
+    // Zt = Ct^T (Zm Ct) -> G1 ; WZ = Ct^T (Ze Ct) -> G2
+    hipLaunchKernelGGL(k_gemm, dim3(nt * nt, b.nsys), dim3(256), 0, stream, dmb, b.d_list.p, 0, G2.p, b.Ct.p, b.Tm.p,
+                       (const double*)nullptr);
+    hipLaunchKernelGGL(k_gemm, dim3(nt * nt, b.nsys), dim3(256), 0, stream, dmb, b.d_list.p, 2, b.Ct.p, b.Tm.p, G1.p,
+                       (const double*)nullptr);
+    hipLaunchKernelGGL(k_gemm, dim3(nt * nt, b.nsys), dim3(256), 0, stream, dmb, b.d_list.p, 0, G3.p, b.Ct.p, b.Tm.p,
+                       (const double*)nullptr);
+    hipLaunchKernelGGL(k_gemm, dim3(nt * nt, b.nsys), dim3(256), 0, stream, dmb, b.d_list.p, 2, b.Ct.p, b.Tm.p, G2.p,
+                       (const double*)nullptr);
+    // X2 = P S (D_w P) -> G3
+    hipLaunchKernelGGL(k_rowscale, dim3(b.nsys), dim3(256), 0, stream, dmb, w.p, b.Pm.p, b.Fm.p);
+    hipLaunchKernelGGL(k_gemm, dim3(nt * nt, b.nsys), dim3(256), 0, stream, dmb, b.d_list.p, 0, b.S.p, b.Fm.p, b.Tm.p,
+                       (const double*)nullptr);
+    hipLaunchKernelGGL(k_gemm, dim3(nt * nt, b.nsys), dim3(256), 0, stream, dmb, b.d_list.p, 0, b.Pm.p, b.Tm.p, G3.p,
+                       (const double*)nullptr);
+    hipLaunchKernelGGL(k_sym_inplace, dim3(b.nsys), dim3(256), 0, stream, dmb, G1.p);
+    hipLaunchKernelGGL(k_resp_DS, dim3(b.nsys), dim3(256), 0, stream, dmb, G1.p, G2.p, G3.p, w.p, b.Fm.p, gx.p);
+    hipLaunchKernelGGL(k_grad_contract, dim3(b.nsys), dim3(256), 0, stream, ds, dmb, b.d_list.p, G1.p, b.Fm.p, gx.p,
+                       b.q_out.p, (const double*)nullptr, 0, 1, gm.p, Fm_.p);
+    check(hipGetLastError(), "response gradient terms");
+    sync();
+    res.ms_response = now_ms() - tr;
+  }
+
+  // ---- per-atom gather: F, CN chain, inter-fragment forces, fragment terms
+  std::vector<int> rowptr(N + 1, 0), ent_b;
+  std::vector<long long> ent_o;
+  {
+    std::vector<std::vector<std::pair<int, long long>>> rows(N);
+    for (int k = 0; k < mb.nsys; ++k) {
+      const SysDesc& d = mb.h_desc[k];
+      for (int a = 0; a < d.nat; ++a) rows[frag_atoms[frag_off[d.frag[0]] + a]].push_back({0, d.atom_off + a});
+    }
+    if (nscc > 0) {
+      std::vector<int> at;
+      db_.d_atoms.download(at, stream);
+      sync();
+      for (int k = 0; k < db_.nsys; ++k) {
+        const SysDesc& d = db_.h_desc[k];
+        for (int a = 0; a < d.nat; ++a) rows[at[d.atom_off + a]].push_back({1, d.atom_off + a});
+      }
+    }
+    for (int A = 0; A < N; ++A) {
+      rowptr[A + 1] = rowptr[A] + (int)rows[A].size();
+      for (auto& e : rows[A]) {
+        ent_b.push_back(e.first);
+        ent_o.push_back(e.second);
+      }
+    }
+  }
+  DevBuf<int> d_rp, d_eb;
+  DevBuf<long long> d_eo;
+  d_rp.upload(rowptr);
+  d_eb.upload(ent_b);
+  d_eo.upload(ent_o);
+  std::vector<const double*> gb = {gm.p, nscc > 0 ? gd.p : gm.p};
+  std::vector<const double*> fb = {Fm_.p, nscc > 0 ? Fd.p : Fm_.p};
+  DevBuf<const double*> d_gb, d_fb;
+  d_gb.upload(gb);
+  d_fb.upload(fb);
+  DevBuf<double> Ftot;
+  Ftot.alloc(N);
+  d_grad.alloc(3LL * N);
+  const unsigned gA = (unsigned)((N + 255) / 256);
+  hipLaunchKernelGGL(k_gather_atoms, dim3(gA), dim3(256), 0, stream, N, d_rp.p, d_eb.p, d_eo.p, d_gb.p, d_fb.p,
+                     d_grad.p, Ftot.p, 0);
+  hipLaunchKernelGGL(k_cn_grad, dim3(gA), dim3(256), 0, stream, ds, Ftot.p, d_grad.p);
+  // inter-fragment kernel derivatives with a = qbar + u
+  hipLaunchKernelGGL(k_axpy, dim3((unsigned)((Nsh + 255) / 256)), dim3(256), 0, stream, (long long)Nsh, qbar.p, 1.0,
+                     u.p, a.p);
+  {
+    const int nchunk = std::max(1, std::min(64, 2048 / (int)gA));
+    DevBuf<double> part, fi;
+    part.alloc((long long)nchunk * 3 * N);
+    fi.alloc(3LL * N);
+    hipLaunchKernelGGL(k_force_inter, dim3(gA, nchunk), dim3(256), 0, stream, ds, d_q.p, a.p, nchunk, part.p);
+    hipLaunchKernelGGL(k_force_reduce, dim3((unsigned)((3 * N + 255) / 256)), dim3(256), 0, stream, N, nchunk, part.p,
+                       fi.p);
+    hipLaunchKernelGGL(k_axpy, dim3((unsigned)((3 * N + 255) / 256)), dim3(256), 0, stream, 3LL * N, d_grad.p, 1.0,
+                       fi.p, d_grad.p);
+  }
+  hipLaunchKernelGGL(k_gather_atoms, dim3(gA), dim3(256), 0, stream, N, d_rp.p, d_eb.p, d_eo.p, d_gb.p, d_fb.p,
+                     d_grad.p, Ftot.p, 1);
+  check(hipGetLastError(), "gradient assembly");
+  sync();
+  if (verbose) std::fprintf(stderr, "[fx] gradient: %.1f ms (response %.1f ms, %d sweeps)\n", now_ms() - t0,
+                            res.ms_response, response_sweeps);
+}
 
 }  // namespace fx

@@ -128,11 +128,6 @@ __global__ void k_grad_contract(DevSystem sys, DevBatch bt, const int* list, con
   const double cw = wsys ? wsys[si] : 1.0;
   __shared__ double part[256][4];
   const int nslice = nat >= (int)blockDim.x ? 1 : (int)blockDim.x / nat;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int a = threadIdx.x % nat, slice0 = threadIdx.x / nat; a < nat && slice0 < nslice; a += blockDim.x) {
-    // (for nat > blockDim each thread strides over atoms with its own accumulator slot)
-    break;
-  }
   for (int a0 = 0; a0 < nat; a0 += (nslice == 1 ? (int)blockDim.x : nat)) {
     int a = a0 + (nslice == 1 ? (int)threadIdx.x : (int)threadIdx.x % nat);
     int slice = nslice == 1 ? 0 : (int)threadIdx.x / nat;
@@ -232,7 +227,6 @@ __global__ void k_grad_contract(DevSystem sys, DevBatch bt, const int* list, con
       }
       F_out[o] = accumulate ? F_out[o] + cw * t[3] : cw * t[3];
     }
-    (void)acc;
   }
 }
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <cstdlib>
 #include <map>
 #include <stdexcept>
 #include <string>
@@ -90,6 +91,7 @@ HostParams load_params(const std::string& path);
 struct Batch {
   int nsys = 0;
   int max_nao = 0;
+  bool init_from_mono = false;  // first basis from the monomers' eigenvectors
   int tot_sh = 0, tot_ao = 0;
   long long tot_mat = 0;
   std::vector<SysDesc> h_desc;
@@ -110,7 +112,13 @@ struct Ctx {
   // numerical settings of the kernels
   int jacobi_max_sweeps = 40;
   double jacobi_tol = 1e-14;
+  double jacobi_thr_scale = 1e-3;
   double mix_beta = 0.5;
+  double macro_beta = 0.5;
+  double scc_tol_cur = -1.0, etol_cur = -1.0;
+  double response_tol = 1e-11;
+  int response_sweeps = 0;
+  bool verbose = std::getenv("FX_VERBOSE") != nullptr;
 
   // supersystem
   bool has_system = false, lists_built = false, has_result = false, has_grad = false;

@@ -20,11 +20,13 @@ __global__ void k_esd_pairs(DevSystem sys, const int* pairs, long long npairs, c
 
 // SCC (fx_scc.hip)
 __global__ void k_reset_state(DevBatch bt, const int* list, int nl);
-__global__ void k_cholinv(DevBatch bt, const int* list);
+__global__ void k_cholinv(DevBatch bt, const int* list, const double* Apool, double* Lpool, double* Xpool);
+__global__ void k_cluster_init_ct(DevBatch bt, const int* list, DevBatch mono);
 __global__ void k_fock(DevSystem sys, DevBatch bt, const int* list);
 __global__ void k_gemm(DevBatch bt, const int* list, int mode, const double* A, const double* B, double* C,
                        const double* w);
-__global__ void k_jacobi(DevBatch bt, const int* list, int max_sweeps, double rel_tol, int* sweeps_out);
+__global__ void k_jacobi(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale,
+                         int* sweeps_out);
 __global__ void k_eigh_batched(const int* nvec, const long long* off, double* Abuf, double* Vbuf, double* wbuf,
                                const long long* woff, int max_sweeps, double rel_tol);
 __global__ void k_fermi(DevSystem sys, DevBatch bt, const int* list);
@@ -38,5 +40,10 @@ __global__ void k_max_absdiff(const double* a, const double* b, int n, double* o
 __global__ void k_cluster_terms(DevBatch bt, const double* qmono, const double* e_mono, double* ddq, double* dEV,
                                 double* dE);
 __global__ void k_sum_neumaier(const double* const* arrays, const long long* lens, int narrays, double* out);
+__global__ void k_hist_gram(const double* R, long long n, Slots sl, double* B);
+__global__ void k_hist_coef(const double* B, Slots sl, double* coef);
+__global__ void k_hist_mix(const double* X, const double* R, long long n, Slots sl, const double* coef, double beta,
+                           double* q);
+__global__ void k_hist_store(const double* x, const double* y, long long n, int slot, double* X, double* R);
 
 }  // namespace fx

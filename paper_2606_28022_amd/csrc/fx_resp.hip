@@ -1,0 +1,320 @@
+// Response of the self-consistent embedding for the FMO2 gradient.
+//
+// The energy depends on the monomer charges q^K through the Lagrangian
+// potential v_K of eq. esp_lagrangian.  The charges respond to a geometry
+// change through each monomer's SCC response: with the shell-summed
+// occupied-virtual transition charges Q_ai,s of eq. lagrangian,
+//   M = sum_ai Q_ai Q_ai^T / (eps_a - eps_i),  G = gamma_KK - 2 Gamma_A dq_A,
+// the adjoint of the monomer self-consistency is y = v + Gamma_off chi y with
+// chi = -(1 + M G)^-1 M, solved by Anderson-accelerated sweeps (each sweep is
+// one embedding-field pass).  With w = (1 + G M)^-1 y the Z-vector is
+// Z_ai = -2 (w . Q_ai) / (eps_a - eps_i) (the solution of eq. sczv for this
+// Hamiltonian); its AO forms (eqs. Z_AO, WZ_def) and the Mulliken term of the
+// fixed-orbital charge change (eq. resp_addlag) enter the same derivative
+// contraction as the explicit gradient.
+#include <hip/hip_runtime.h>
+
+#include "fx_device.hpp"
+#include "fx_kernels.hpp"
+
+namespace fx {
+
+// order the MOs of every system: the nocc lowest eigenvalues first (ties by
+// index), then the virtuals, both ascending.
+__global__ void k_mo_order(DevBatch bt, const int* nocc, int* order) {
+  const int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const double* e = bt.eps + d.ao_off;
+  for (int i = threadIdx.x; i < d.nao; i += blockDim.x) {
+    int r = 0;
+    double ei = e[i];
+    for (int j = 0; j < d.nao; ++j) r += (e[j] < ei || (e[j] == ei && j < i)) ? 1 : 0;
+    order[d.ao_off + r] = i;
+  }
+  (void)nocc;
+}
+
+// Q[s][a'][i'] = sum_{mu in s} (C_mu,a (SC)_mu,i + C_mu,i (SC)_mu,a)
+// (Ct rows are MOs; SCt = Ct S holds (SC)^T).
+__global__ void k_resp_Q(DevSystem sys, DevBatch bt, const double* SCt, const int* order, const int* nocc,
+                         const long long* qoff, double* Q) {
+  const int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao, no = nocc[si], nv = n - no, ns = d.nsh;
+  const double* Ct = bt.Ct + d.mat_off;
+  const double* T = SCt + d.mat_off;
+  const int* ord = order + d.ao_off;
+  const long long tot = (long long)ns * nv * no;
+  for (long long idx = threadIdx.x; idx < tot; idx += blockDim.x) {
+    int s = (int)(idx / ((long long)nv * no));
+    int r = (int)(idx % ((long long)nv * no));
+    int ap = r / no, ip = r % no;
+    int a = ord[no + ap], i = ord[ip];
+    int la = bt.sys_sh_atom[d.sh_off + s];
+    int A = bt.sys_atoms[d.atom_off + la];
+    const DevElem& el = sys.elems[sys.elem[A]];
+    int ls = s - bt.sys_atom_sh0[d.atom_off + la];
+    int mu0 = bt.sys_atom_ao0[d.atom_off + la] + el.ao0[ls];
+    double v = 0.0;
+    for (int u = 0; u < el.nao_sh[ls]; ++u) {
+      int mu = mu0 + u;
+      v += Ct[(long long)a * n + mu] * T[(long long)i * n + mu] + Ct[(long long)i * n + mu] * T[(long long)a * n + mu];
+    }
+    Q[qoff[si] + idx] = v;
+  }
+}
+
+// M_st = sum_{a'i'} Q_s,a'i' Q_t,a'i' / (eps_a - eps_i)   (into the nsh^2 pool)
+__global__ void k_resp_M(DevBatch bt, const int* order, const int* nocc, const long long* qoff, const double* Q,
+                         double* M) {
+  const int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao, no = nocc[si], nv = n - no, ns = d.nsh;
+  const int* ord = order + d.ao_off;
+  const double* e = bt.eps + d.ao_off;
+  const long long K = (long long)nv * no;
+  const double* Qs = Q + qoff[si];
+  for (int idx = threadIdx.x; idx < ns * ns; idx += blockDim.x) {
+    int s = idx / ns, t = idx % ns;
+    if (t < s) continue;
+    double v = 0.0;
+    for (long long k = 0; k < K; ++k) {
+      int ap = (int)(k / no), ip = (int)(k % no);
+      double den = e[ord[no + ap]] - e[ord[ip]];
+      v += Qs[(long long)s * K + k] * Qs[(long long)t * K + k] / den;
+    }
+    M[d.gam_off + (long long)s * ns + t] = v;
+    M[d.gam_off + (long long)t * ns + s] = v;
+  }
+}
+
+// R = (1 + G M)^-1 with G = gamma - 2 Gamma_A dq_A on same-atom shell blocks
+// (Gauss-Jordan with partial pivoting on a work copy in Wk; one work-group).
+__global__ void k_resp_R(DevSystem sys, DevBatch bt, const double* M, double* Wk, double* R) {
+  const int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const int ns = d.nsh;
+  const double* G = bt.gam + d.gam_off;
+  double* A = Wk + d.gam_off;
+  double* X = R + d.gam_off;
+  __shared__ double qa[MAXN];
+  __shared__ int piv;
+  __shared__ double pv;
+  const double* q = bt.q_out + d.sh_off;
+  for (int a = threadIdx.x; a < d.nat; a += blockDim.x) {
+    int s0 = bt.sys_atom_sh0[d.atom_off + a];
+    int s1 = (a + 1 < d.nat) ? bt.sys_atom_sh0[d.atom_off + a + 1] : ns;
+    double v = 0.0;
+    for (int s = s0; s < s1; ++s) v += q[s];
+    qa[a] = v;
+  }
+  __syncthreads();
+  // A = I + G' M
+  for (int idx = threadIdx.x; idx < ns * ns; idx += blockDim.x) {
+    int s = idx / ns, t = idx % ns;
+    double v = (s == t) ? 1.0 : 0.0;
+    int as = bt.sys_sh_atom[d.sh_off + s];
+    for (int k = 0; k < ns; ++k) {
+      double g = G[(long long)s * ns + k];
+      if (bt.sys_sh_atom[d.sh_off + k] == as) {
+        int Aat = bt.sys_atoms[d.atom_off + as];
+        g -= 2.0 * sys.elems[sys.elem[Aat]].Gamma * qa[as];
+      }
+      v += g * M[d.gam_off + (long long)k * ns + t];
+    }
+    A[idx] = v;
+    X[idx] = (s == t) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int c = 0; c < ns; ++c) {
+    if (threadIdx.x == 0) {
+      int p = c;
+      double best = fabs(A[(long long)c * ns + c]);
+      for (int r = c + 1; r < ns; ++r) {
+        double v = fabs(A[(long long)r * ns + c]);
+        if (v > best) {
+          best = v;
+          p = r;
+        }
+      }
+      piv = p;
+    }
+    __syncthreads();
+    if (piv != c) {
+      for (int k = threadIdx.x; k < ns; k += blockDim.x) {
+        double t = A[(long long)c * ns + k];
+        A[(long long)c * ns + k] = A[(long long)piv * ns + k];
+        A[(long long)piv * ns + k] = t;
+        t = X[(long long)c * ns + k];
+        X[(long long)c * ns + k] = X[(long long)piv * ns + k];
+        X[(long long)piv * ns + k] = t;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) pv = A[(long long)c * ns + c];
+    __syncthreads();
+    for (int k = threadIdx.x; k < ns; k += blockDim.x) {
+      A[(long long)c * ns + k] /= pv;
+      X[(long long)c * ns + k] /= pv;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < ns * ns; idx += blockDim.x) {
+      int r = idx / ns, k = idx % ns;
+      if (r == c) continue;
+      double f = A[(long long)r * ns + c];
+      if (k == c) continue;
+      A[(long long)r * ns + k] -= f * A[(long long)c * ns + k];
+      X[(long long)r * ns + k] -= f * X[(long long)c * ns + k];
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < ns; r += blockDim.x) {
+      if (r == c) continue;
+      double f = A[(long long)r * ns + c];
+      X[(long long)r * ns + c] -= f * X[(long long)c * ns + c];
+      A[(long long)r * ns + c] = 0.0;
+    }
+    __syncthreads();
+  }
+}
+
+// w = R y,  u = -M w   (local shell vectors)
+__global__ void k_resp_apply(DevBatch bt, const double* R, const double* M, const double* y, double* w, double* u) {
+  const int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const int ns = d.nsh;
+  __shared__ double ws[MAXN];
+  for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+    double v = 0.0;
+    for (int t = 0; t < ns; ++t) v += R[d.gam_off + (long long)s * ns + t] * y[d.sh_off + t];
+    ws[s] = v;
+    w[d.sh_off + s] = v;
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+    double v = 0.0;
+    for (int t = 0; t < ns; ++t) v += M[d.gam_off + (long long)s * ns + t] * ws[t];
+    u[d.sh_off + s] = -v;
+  }
+}
+
+// Z in the MO basis: Zm[a][i] = -2 (w . Q_ai) / (eps_a - eps_i) and
+// Ze[a][i] = Zm[a][i] eps_i (zero elsewhere)
+__global__ void k_resp_Z(DevBatch bt, const int* order, const int* nocc, const long long* qoff, const double* Q,
+                         const double* w, double* Zm, double* Ze) {
+  const int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao, no = nocc[si], nv = n - no, ns = d.nsh;
+  const int* ord = order + d.ao_off;
+  const double* e = bt.eps + d.ao_off;
+  const long long K = (long long)nv * no;
+  for (long long idx = threadIdx.x; idx < (long long)n * n; idx += blockDim.x) {
+    Zm[d.mat_off + idx] = 0.0;
+    Ze[d.mat_off + idx] = 0.0;
+  }
+  __syncthreads();
+  for (long long k = threadIdx.x; k < K; k += blockDim.x) {
+    int ap = (int)(k / no), ip = (int)(k % no);
+    int a = ord[no + ap], i = ord[ip];
+    double v = 0.0;
+    for (int s = 0; s < ns; ++s) v += w[d.sh_off + s] * Q[qoff[si] + (long long)s * K + k];
+    double z = -2.0 * v / (e[a] - e[i]);
+    Zm[d.mat_off + (long long)a * n + i] = z;
+    Ze[d.mat_off + (long long)a * n + i] = z * e[i];
+  }
+}
+
+// out = diag(w_shell) P  (row scaling by the shell value of each AO)
+__global__ void k_rowscale(DevBatch bt, const double* wsh, const double* P, double* out) {
+  const int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao;
+  const int* aosh = bt.sys_ao_sh + d.ao_off;
+  for (long long idx = threadIdx.x; idx < (long long)n * n; idx += blockDim.x) {
+    int i = (int)(idx / n);
+    out[d.mat_off + idx] = wsh[d.sh_off + aosh[i]] * P[d.mat_off + idx];
+  }
+}
+
+// symmetrise a matrix pool in place: A <- (A + A^T) / 2
+__global__ void k_sym_inplace(DevBatch bt, double* A) {
+  const int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao;
+  for (long long idx = threadIdx.x; idx < (long long)n * n; idx += blockDim.x) {
+    int i = (int)(idx / n), j = (int)(idx % n);
+    if (j <= i) continue;
+    double a = A[d.mat_off + (long long)i * n + j], b = A[d.mat_off + (long long)j * n + i];
+    double m = 0.5 * (a + b);
+    A[d.mat_off + (long long)i * n + j] = m;
+    A[d.mat_off + (long long)j * n + i] = m;
+  }
+}
+
+// D_S of the response: 1/2 (sig_i + sig_j) Zb - sym(WZ) + 1/2 (w_i + w_j) P - 1/4 (X2 + X2^T)
+// and gx = 2 Q^Z with Q^Z_s = sum_{mu in s} sum_nu Zb_mu,nu S_mu,nu
+__global__ void k_resp_DS(DevBatch bt, const double* Zb, const double* WZ, const double* X2, const double* wsh,
+                          double* DS, double* gx) {
+  const int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao;
+  const int* aosh = bt.sys_ao_sh + d.ao_off;
+  const double* sg = bt.sig + d.sh_off;
+  const double* w = wsh + d.sh_off;
+  const double* P = bt.P + d.mat_off;
+  const double* S = bt.S + d.mat_off;
+  const long long o = d.mat_off;
+  for (long long idx = threadIdx.x; idx < (long long)n * n; idx += blockDim.x) {
+    int i = (int)(idx / n), j = (int)(idx % n);
+    long long ij = o + idx, ji = o + (long long)j * n + i;
+    int si_ = aosh[i], sj_ = aosh[j];
+    DS[ij] = 0.5 * (sg[si_] + sg[sj_]) * Zb[ij] - 0.5 * (WZ[ij] + WZ[ji]) + 0.5 * (w[si_] + w[sj_]) * P[idx] -
+             0.25 * (X2[ij] + X2[ji]);
+  }
+  __shared__ double pop[MAXN];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double v = 0.0;
+    for (int j = 0; j < n; ++j) v += Zb[o + (long long)i * n + j] * S[(long long)i * n + j];
+    pop[i] = v;
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < d.nsh; s += blockDim.x) {
+    double v = 0.0;
+    for (int i = 0; i < n; ++i)
+      if (aosh[i] == s) v += pop[i];
+    gx[d.sh_off + s] = 2.0 * v;
+  }
+}
+
+// per cluster system: cross-fragment potential of a local shell vector x,
+// out_s = sum_{t in X, frag(t) != frag(s)} gamma_st x_t
+__global__ void k_cluster_cross(DevSystem sys, DevBatch bt, const double* x, double* out) {
+  const int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const int* shg = bt.sys_sh_global + d.sh_off;
+  for (int s = threadIdx.x; s < d.nsh; s += blockDim.x) {
+    int fs = sys.sh_frag[shg[s]];
+    double v = 0.0;
+    for (int t = 0; t < d.nsh; ++t) {
+      if (sys.sh_frag[shg[t]] == fs) continue;
+      v += bt.gam[d.gam_off + (long long)s * d.nsh + t] * x[d.sh_off + t];
+    }
+    out[d.sh_off + s] = v;
+  }
+}
+
+// dst[s] = base[s] + sign * sum over CSR entries of src[entry] (fixed order)
+__global__ void k_gather_csr(int n, const int* rowptr, const int* ent, const double* src, const double* base,
+                             double sign, double* dst) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  double v = 0.0;
+  for (int e = rowptr[s]; e < rowptr[s + 1]; ++e) v += src[ent[e]];
+  dst[s] = (base ? base[s] : 0.0) + sign * v;
+}
+
+__global__ void k_axpy(long long n, const double* x, double a, const double* y, double* out) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = x[k] + a * y[k];
+}
+
+}  // namespace fx

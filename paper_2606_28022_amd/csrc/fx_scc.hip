@@ -53,17 +53,41 @@ __global__ void k_reset_state(DevBatch bt, const int* list, int nl) {
   bt.niter[si] = 0;
   bt.nhist[si] = 0;
   bt.e_prev[si] = 0.0;
+  bt.err[si] = 1e-2;
 }
 
-// ---------------------------------------------------------------------------
-// C = L^-T for S = L L^T (rows of L^-1 are the first S-orthonormal basis).
-__global__ void k_cholinv(DevBatch bt, const int* list) {
+// initial basis of a cluster from its monomers' eigenvectors: block-diagonal
+// rows of the monomer C^T (fragment order), later S-orthonormalised.
+__global__ void k_cluster_init_ct(DevBatch bt, const int* list, DevBatch mono) {
   int si = list[blockIdx.x];
   const SysDesc d = bt.desc[si];
   const int n = d.nao;
-  double* L = bt.T + d.mat_off;
-  const double* S = bt.S + d.mat_off;
-  double* X = bt.Ct + d.mat_off;
+  double* C = bt.Ct + d.mat_off;
+  for (long long i = threadIdx.x; i < (long long)n * n; i += blockDim.x) C[i] = 0.0;
+  __syncthreads();
+  int off = 0;
+  for (int f = 0; f < d.nfrag; ++f) {
+    const SysDesc m = mono.desc[d.frag[f]];
+    const double* Cm = mono.Ct + m.mat_off;
+    const int nm = m.nao;
+    for (long long idx = threadIdx.x; idx < (long long)nm * nm; idx += blockDim.x) {
+      int i = (int)(idx / nm), j = (int)(idx % nm);
+      C[(long long)(off + i) * n + off + j] = Cm[idx];
+    }
+    off += nm;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// X = L^-1 for an SPD matrix A = L L^T (pools: A read, L workspace, X out).
+// With A = S the rows of L^-1 are the first S-orthonormal basis C = L^-T.
+__global__ void k_cholinv(DevBatch bt, const int* list, const double* Apool, double* Lpool, double* Xpool) {
+  int si = list[blockIdx.x];
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao;
+  double* L = Lpool + d.mat_off;
+  const double* S = Apool + d.mat_off;
+  double* X = Xpool + d.mat_off;
   __shared__ double piv;
   for (long long i = threadIdx.x; i < (long long)n * n; i += blockDim.x) L[i] = S[i];
   __syncthreads();
@@ -143,7 +167,7 @@ __global__ void k_fock(DevSystem sys, DevBatch bt, const int* list) {
 // ---------------------------------------------------------------------------
 // Batched dense products of the systems' n x n matrices, 32 x 32 output tile
 // per work-group (256 threads, 2 x 2 outputs each).  mode:
-//   0  C = A B          1  C = A B^T          2  C = A^T diag(w) B
+//   0  C = A B          1  C = A B^T          2  C = A^T diag(w) B (w = 1 if null)
 __global__ void k_gemm(DevBatch bt, const int* list, int mode, const double* Abase, const double* Bbase,
                        double* Cbase, const double* wbase) {
   int si = list[blockIdx.y];
@@ -168,7 +192,7 @@ __global__ void k_gemm(DevBatch bt, const int* list, int mode, const double* Aba
       if (mode == 2) {
         // A^T: As[k][i] = A[k][i] * w[k]
         int k = k0 + r, i = ti * 32 + c;
-        if (k < n && i < n) av = A[(long long)k * n + i] * w[k];
+        if (k < n && i < n) av = A[(long long)k * n + i] * (w ? w[k] : 1.0);
         int kb = k0 + r, j = tj * 32 + c;
         if (kb < n && j < n) bv = B[(long long)kb * n + j];
         As[r][c] = av;
@@ -217,15 +241,16 @@ __device__ inline int rr_index(int pos, int step, int m) {
   return pos == 0 ? 0 : 1 + (pos - 1 + step) % (m - 1);
 }
 
-__device__ void jacobi_solve(double* A, double* V, int n, int nv, int max_sweeps, double rel_tol, double* red,
-                             double* cs_c, double* cs_s, double* cs_t, int* pp, int* qq, int* nsweep_out) {
+__device__ void jacobi_solve(double* A, double* V, int n, int nv, int max_sweeps, double rel_tol, double abs_thr,
+                             double* red, double* cs_c, double* cs_s, double* cs_t, int* pp, int* qq,
+                             int* nsweep_out) {
   const int m = n + (n & 1);
   const int nb = m / 2;
   // scale: Frobenius norm
   double loc = 0.0;
   for (long long i = threadIdx.x; i < (long long)n * n; i += blockDim.x) loc += A[i] * A[i];
   double fro = sqrt(block_sum(loc, red));
-  double thr = rel_tol * (fro > 0.0 ? fro : 1.0);
+  double thr = fmax(rel_tol * (fro > 0.0 ? fro : 1.0), abs_thr);
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
     double maxoff = 0.0;
@@ -324,7 +349,11 @@ __device__ void jacobi_solve(double* A, double* V, int n, int nv, int max_sweeps
   if (nsweep_out && threadIdx.x == 0) *nsweep_out = sweep;
 }
 
-__global__ void k_jacobi(DevBatch bt, const int* list, int max_sweeps, double rel_tol, int* sweeps_out) {
+// Rotations below max(rel_tol |A|_F, thr_scale * last SCC residual) are skipped:
+// while the charges are far from self-consistent the orbitals only need a
+// matching accuracy; the final iterations are diagonalised to rel_tol.
+__global__ void k_jacobi(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale,
+                         int* sweeps_out) {
   int si = list[blockIdx.x];
   const SysDesc d = bt.desc[si];
   __shared__ double red[256];
@@ -332,7 +361,7 @@ __global__ void k_jacobi(DevBatch bt, const int* list, int max_sweeps, double re
   __shared__ int pp[MAXN / 2], qq[MAXN / 2];
   double* A = bt.F + d.mat_off;
   double* V = bt.Ct + d.mat_off;
-  jacobi_solve(A, V, d.nao, d.nao, max_sweeps, rel_tol, red, cs_c, cs_s, cs_t, pp, qq,
+  jacobi_solve(A, V, d.nao, d.nao, max_sweeps, rel_tol, thr_scale * bt.err[si], red, cs_c, cs_s, cs_t, pp, qq,
                sweeps_out ? sweeps_out + si : nullptr);
   __syncthreads();
   for (int i = threadIdx.x; i < d.nao; i += blockDim.x) bt.eps[d.ao_off + i] = A[(long long)i * d.nao + i];
@@ -351,7 +380,7 @@ __global__ void k_eigh_batched(const int* nvec, const long long* off, double* Ab
   __shared__ int pp[MAXN / 2], qq[MAXN / 2];
   for (long long i = threadIdx.x; i < (long long)n * n; i += blockDim.x) V[i] = (i / n == i % n) ? 1.0 : 0.0;
   __syncthreads();
-  jacobi_solve(A, V, n, n, max_sweeps, rel_tol, red, cs_c, cs_s, cs_t, pp, qq, nullptr);
+  jacobi_solve(A, V, n, n, max_sweeps, rel_tol, 0.0, red, cs_c, cs_s, cs_t, pp, qq, nullptr);
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += blockDim.x) wbuf[woff[k] + i] = A[(long long)i * n + i];
 }

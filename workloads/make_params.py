@@ -126,7 +126,7 @@ def make(seed=0):
         name="gfn1-like seeded stand-in (not the fitted GFN1-xTB values)",
         seed=seed,
         globals=dict(kg=2.0, kf=1.5, kEN=-0.007, k1=16.0, k2=4.0 / 3.0,
-                     kl=[1.75, 1.75], KAB=1.0, Tel_K=300.0, VHOP=1.0e6,
+                     kl=[1.85, 2.6], KAB=1.0, Tel_K=300.0, VHOP=1.0e6,
                      kB_Eh_per_K=3.166811563e-6, angstrom_to_bohr=1.0 / 0.529177210903),
         basis=basis,
         elements=elements,
