@@ -1,0 +1,199 @@
+"""Benchmark: FMO2-xTB energy + analytic gradient of the 23,760-atom pentacene
+crystal (11 x 5 x 6 triclinic herringbone cells, 660 molecules, seeded
++-0.05 A jitter) on one MI355X.
+
+A step is one full pass of the hot path for one geometry: pair lists,
+supersystem CN, the self-consistent monomer embedding, all SCC dimers, the
+ES-DIM pairs, the energy and the FMO2 gradient including the embedding
+response.  The system is uploaded before timing (inputs resident in HBM).
+
+Prints one JSON line.  Usage:
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MI355X_FP64_PEAK_TFLOPS = 78.6
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(system, timed_result):
+    """Time the FP64 oracle on a bounded sample of the same workload and scale
+    it to seconds per step with the GPU run's solve counts."""
+    import numpy as np
+    from oracle import fmo as F
+    from oracle import xtb as X
+    from oracle.params import default_params
+
+    p = default_params()
+    A2B = 1.0 / 0.529177210903
+    # the oracle CN is an all-pairs O(N^2) sum: time it on the first 4096
+    # atoms and scale by (N / 4096)^2
+    nsub = min(4096, system.n_atoms)
+    t0 = time.time()
+    X.coordination_numbers(p, system.Z[:nsub], system.xyz[:nsub])
+    t_cn = (time.time() - t0) * (system.n_atoms / nsub) ** 2
+    cn = np.zeros(system.n_atoms)
+    fa = F.fragment_atoms(system.frag, system.n_frag)
+    # CN of the sampled fragments' atoms from their 12-molecule neighbourhood
+    near = np.concatenate([fa[k] for k in range(12)])
+    sub = system.subset(list(range(12)))
+    cn[near] = X.coordination_numbers(p, sub.Z, sub.xyz)
+    # one monomer SCC and one SCC dimer (with its gradient terms) of the crystal
+    t0 = time.time()
+    sm = X.XtbSystem(p, system.Z[fa[0]], system.xyz[fa[0]], cn[fa[0]])
+    rm = X.scc(sm)
+    t_mono = time.time() - t0
+    scc, _, _ = F.build_lists(system.subset(list(range(12))), 4.0 * A2B)
+    I, J = scc[0]
+    at = np.concatenate([fa[I], fa[J]])
+    t0 = time.time()
+    sd = X.XtbSystem(p, system.Z[at], system.xyz[at], cn[at])
+    rd = X.scc(sd, q_guess=None)
+    t_dimer = time.time() - t0
+    t0 = time.time()
+    DS = 0.5 * (rd.sigma[sd.ao_sh][:, None] + rd.sigma[sd.ao_sh][None, :]) * rd.P - rd.Wt
+    X.system_gradient(sd, rd.P, DS, rd.q, rd.q, True)
+    t_dgrad = time.time() - t0
+    n_mono_solves = timed_result["solves_mono"]
+    n_dimers = timed_result["solves_dimer"]
+    est = (t_cn + n_mono_solves * t_mono + n_dimers * (t_dimer + t_dgrad)
+           + system.n_frag * t_dgrad / 4.0)
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    return {
+        "value": est, "unit": "s/step", "cores": int(cores), "kind": "oracle",
+        "sample": (f"oracle timed on one monomer SCC ({t_mono:.2f} s), one SCC dimer "
+                   f"({t_dimer:.2f} s) plus its gradient terms ({t_dgrad:.2f} s) and the "
+                   f"supersystem CN ({t_cn:.2f} s, timed on {nsub} atoms and scaled by the square "
+                   f"of the atom ratio) of this crystal, scaled by the GPU run's "
+                   f"{n_mono_solves} monomer solves and {n_dimers} dimers"),
+    }
+
+
+def plain_vs_batched():
+    """Batched vs one-fragment-at-a-time schedule on the 1024-molecule water
+    droplet (FMO2 energy, FP64); returns (speed-up, |dE|)."""
+    from paper_2606_28022_amd import FmoXtb
+    import workloads as w
+    s = w.water_droplet()
+    c = FmoXtb()
+    c.set_system(s.Z, s.xyz, s.frag, s.frag_charge)
+    c.set_options(want_gradient=0)
+    c.run()
+    t = time.time()
+    rb = c.run()
+    tb = time.time() - t
+    c.set_options(schedule=1)
+    t = time.time()
+    rp = c.run()
+    tp = time.time() - t
+    return tp / tb, abs(rb["e_total"] - rp["e_total"]), tb, tp
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(how it would shard is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as w
+    from paper_2606_28022_amd import FmoXtb
+
+    assert torch.cuda.is_available(), "needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    s = w.pentacene_crystal()
+    log(f"system {s.name}: {s.n_atoms} atoms, {s.n_frag} fragments")
+    c = FmoXtb(device=0, stream=C_stream(stream))
+    c.set_system(s.Z, s.xyz, s.frag, s.frag_charge)
+    c.set_options(want_gradient=1, want_response=1)
+    cnt = c.get_counts()
+
+    for k in range(args.warmup):
+        r = c.run()
+        log(f"warmup {k}: {r['ms_monomer'] + r['ms_dimer'] + r['ms_gradient']:.0f} ms")
+
+    torch.cuda.synchronize()
+    times, results = [], []
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = c.run()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        results.append(r)
+        log(f"step {k}: {times[-1]:.3f} s, E = {r['e_total']:.8f}")
+    g = c.gradient()
+    sec = float(np.mean(times))
+    r = results[-1]
+    solves = r["solves_mono"] + r["solves_dimer"]
+
+    # roofline of the dominant kernel (batched Jacobi eigensolver, FP64 VALU)
+    jl = max(1, r["jacobi_launches"])
+    avg_ms = r["ms_jacobi"] / jl
+    gflop_per_launch = r["gflop_jacobi"] / jl
+    achieved = gflop_per_launch / avg_ms  # GFLOP/ms = TFLOP/s
+    roofline = {"bound": "alu", "kernel": "k_jacobi", "achieved": achieved,
+                "peak": MI355X_FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / MI355X_FP64_PEAK_TFLOPS, "traffic": None,
+                "avg_launch_ms": avg_ms, "launches": jl,
+                "share_of_step": r["ms_jacobi"] / (1000.0 * sec)}
+
+    out = {
+        "metric": "FMO2 energy+grad s/step; fragment SCC solves/s; batched vs plain @1e-6 Eh",
+        "value": sec, "unit": "s/step", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1000.0 * sec, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "pentacene 11x5x6 crystal, FMO2 energy + analytic gradient with response",
+                   "atoms": s.n_atoms, "fragments": s.n_frag, "scc_dimers": int(cnt.n_scc_pairs),
+                   "es_dim_pairs": int(cnt.n_esd_pairs), "cutoff_angstrom": 4.0, "precision": "fp64",
+                   "schedule": "batched"},
+        "scc_solves_per_s": solves / sec,
+        "energy_Eh": r["e_total"], "grad_max_Eh_per_bohr": float(np.abs(g).max()),
+        "net_force": float(np.abs(g.sum(0)).max()),
+        "phases_ms": {k: r[k] for k in ("ms_lists", "ms_monomer", "ms_dimer", "ms_energy", "ms_gradient",
+                                        "ms_response")},
+        "iterations": {"monomer": r["iters_mono"], "dimer": r["iters_dimer"], "macro": r["macro_iter"]},
+        "roofline": roofline,
+    }
+    if not args.no_plain:
+        sp, de, tb, tp = plain_vs_batched()
+        out["batched_vs_plain"] = {"workload": "water droplet 1024 molecules, FMO2 energy, fp64",
+                                   "speedup": sp, "abs_dE": de, "batched_s": tb, "plain_s": tp}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(s, r)
+    print(json.dumps(out), flush=True)
+
+
+def C_stream(stream):
+    """hipStream_t handle of a torch stream (None for the default stream)."""
+    import ctypes
+    h = stream.cuda_stream
+    return ctypes.c_void_p(h) if h else None
+
+
+if __name__ == "__main__":
+    main()

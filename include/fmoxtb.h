@@ -95,6 +95,12 @@ typedef struct fx_result {
   int64_t solves_mono, solves_dimer, solves_trimer;  /* fragment SCC solves */
   int64_t iters_mono, iters_dimer, iters_trimer;     /* SCC iterations, summed */
   double ms_lists, ms_monomer, ms_dimer, ms_trimer, ms_energy, ms_gradient, ms_response;
+  /* the batched Jacobi eigensolver kernel: summed device time of its launches
+   * (HIP events on the context stream), launch count, and algorithmic work
+   * (6 n^2 (n - 1) flop per sweep of an n x n matrix, summed over systems) */
+  double ms_jacobi;
+  int64_t jacobi_launches;
+  double gflop_jacobi;
 } fx_result;
 
 /* Load element constants and STO-nG basis expansions from a JSON file.

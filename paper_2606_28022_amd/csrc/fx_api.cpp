@@ -178,7 +178,8 @@ DevSystem Ctx::dev_system() const {
 
 // Build a batch of fragment systems (each a tuple of 1..3 fragments).
 void Ctx::build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters, int nfrag_each) {
-  b = Batch();
+  b.max_nao = 0;
+  b.init_from_mono = false;
   const int ns = (int)clusters.size();
   b.nsys = ns;
   std::vector<SysDesc> desc(ns);
@@ -345,6 +346,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     check(hipGetLastError(), "initial basis");
   }
   std::vector<int> active = list;
+  std::vector<int> sweeps(b.nsys);
   std::vector<int> status(b.nsys);
   std::vector<int> niter(b.nsys);
   DevBuf<int> d_act;
@@ -357,8 +359,14 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
                        (const double*)nullptr);
     hipLaunchKernelGGL(k_gemm, dim3(nt * nt, na), dim3(256), 0, stream, db, d_act.p, 1, b.Tm.p, b.Ct.p, b.Fm.p,
                        (const double*)nullptr);
+    if (!t_jacobi.e0) {
+      check(hipEventCreate(&t_jacobi.e0), "hipEventCreate");
+      check(hipEventCreate(&t_jacobi.e1), "hipEventCreate");
+    }
+    check(hipEventRecord(t_jacobi.e0, stream), "hipEventRecord");
     hipLaunchKernelGGL(k_jacobi, dim3(na), dim3(256), 0, stream, db, d_act.p, jacobi_max_sweeps, jacobi_tol,
                        jacobi_thr_scale, b.sweeps.p);
+    check(hipEventRecord(t_jacobi.e1, stream), "hipEventRecord");
     hipLaunchKernelGGL(k_fermi, dim3(na), dim3(256), 0, stream, ds, db, d_act.p);
     hipLaunchKernelGGL(k_gemm, dim3(nt * nt, na), dim3(256), 0, stream, db, d_act.p, 2, b.Ct.p, b.Ct.p, b.Pm.p,
                        (const double*)b.occ.p);
@@ -367,7 +375,22 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
                        opt.max_iter, mix_beta);
     check(hipGetLastError(), "scc iteration");
     b.status.download(status, stream);
+    b.sweeps.download(sweeps, stream);
     sync();
+    {
+      float ms = 0.0f;
+      check(hipEventElapsedTime(&ms, t_jacobi.e0, t_jacobi.e1), "hipEventElapsedTime");
+      t_jacobi.ms += ms;
+      t_jacobi.launches += 1;
+      // algorithmic work of a sweep over an n x n matrix: the A update
+      // (upper triangle, 2x2 block rotations) and the eigenvector rows,
+      // 6 n^2 flop per step times (n - 1) steps; the convergence check of
+      // a sweep is counted as part of the sweep
+      for (int s : active) {
+        double n = b.h_desc[s].nao;
+        t_jacobi.gflop += 1e-9 * 6.0 * n * n * (n - 1.0) * (double)sweeps[s];
+      }
+    }
     std::vector<int> next;
     for (int s : active)
       if (status[s] == 0) next.push_back(s);
@@ -575,6 +598,7 @@ void Ctx::run(fx_result* out) {
   if (!has_system) throw FxError(FX_E_STATE, "no system set");
   if (opt.precision != FX_FP64) throw FxError(FX_E_UNSUPPORTED, "only FX_FP64 is available");
   std::memset(&res, 0, sizeof(res));
+  t_jacobi.reset();
   bool all_conv = true;
   double t0 = now_ms();
   if (!lists_built) build_lists_impl();
@@ -787,6 +811,9 @@ void Ctx::run(fx_result* out) {
     has_grad = true;
   }
   res.ms_gradient = now_ms() - t5;
+  res.ms_jacobi = t_jacobi.ms;
+  res.jacobi_launches = t_jacobi.launches;
+  res.gflop_jacobi = t_jacobi.gflop;
   if (out) *out = res;
 }
 

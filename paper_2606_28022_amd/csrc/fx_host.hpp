@@ -29,17 +29,20 @@ struct DevBuf {
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) {
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), cap(o.cap) {
     o.p = nullptr;
     o.n = 0;
+    o.cap = 0;
   }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
       release();
       p = o.p;
       n = o.n;
+      cap = o.cap;
       o.p = nullptr;
       o.n = 0;
+      o.cap = 0;
     }
     return *this;
   }
@@ -48,8 +51,16 @@ struct DevBuf {
     if (p) (void)hipFree(p);
     p = nullptr;
     n = 0;
+    cap = 0;
   }
+  long long cap = 0;
+  // keeps the allocation when it is already large enough (no hipMalloc/hipFree
+  // on repeated runs of the same system)
   void alloc(long long count) {
+    if (p && count <= cap) {
+      n = count;
+      return;
+    }
     release();
     size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
     if (hipMalloc(&p, bytes) != hipSuccess) {
@@ -57,6 +68,7 @@ struct DevBuf {
       throw FxError(FX_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
     }
     n = count;
+    cap = count > 0 ? count : 1;
   }
   void upload(const std::vector<T>& v) {
     alloc((long long)v.size());
@@ -103,6 +115,19 @@ struct Batch {
   DevBatch dev();
 };
 
+// Event-timed accumulation of one kernel's launches on the context stream.
+struct KernelTimer {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double ms = 0.0;
+  long long launches = 0;
+  double gflop = 0.0;
+  void reset() {
+    ms = 0.0;
+    launches = 0;
+    gflop = 0.0;
+  }
+};
+
 struct Ctx {
   HostParams P;
   int device = 0;
@@ -137,6 +162,7 @@ struct Ctx {
   DevBuf<double> e_mono, dE_scc, dEV_scc, dE_esd, dE_tri, ddq_scc;
   std::vector<double> trimer_dEIJK;
   fx_result res{};
+  KernelTimer t_jacobi;
 
   static void check(hipError_t e, const char* what);
   static void* dmalloc(size_t bytes);

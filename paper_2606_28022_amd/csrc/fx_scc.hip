@@ -346,7 +346,7 @@ __device__ void jacobi_solve(double* A, double* V, int n, int nv, int max_sweeps
     double mo = block_max(maxoff, red);
     if (mo <= thr) break;
   }
-  if (nsweep_out && threadIdx.x == 0) *nsweep_out = sweep;
+  if (nsweep_out && threadIdx.x == 0) *nsweep_out = sweep < max_sweeps ? sweep + 1 : max_sweeps;
 }
 
 // Rotations below max(rel_tol |A|_F, thr_scale * last SCC residual) are skipped:
