@@ -101,6 +101,10 @@ typedef struct fx_result {
   double ms_jacobi;
   int64_t jacobi_launches;
   double gflop_jacobi;
+  /* the batched dense FP64 products of the SCC iterations (2 n^3 flop each) */
+  double ms_gemm;
+  int64_t gemm_launches;
+  double gflop_gemm;
 } fx_result;
 
 /* Load element constants and STO-nG basis expansions from a JSON file.

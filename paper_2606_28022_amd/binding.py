@@ -43,7 +43,8 @@ class fx_result(C.Structure):
                 ("iters_trimer", C.c_int64), ("ms_lists", C.c_double), ("ms_monomer", C.c_double),
                 ("ms_dimer", C.c_double), ("ms_trimer", C.c_double), ("ms_energy", C.c_double),
                 ("ms_gradient", C.c_double), ("ms_response", C.c_double), ("ms_jacobi", C.c_double),
-                ("jacobi_launches", C.c_int64), ("gflop_jacobi", C.c_double)]
+                ("jacobi_launches", C.c_int64), ("gflop_jacobi", C.c_double), ("ms_gemm", C.c_double),
+                ("gemm_launches", C.c_int64), ("gflop_gemm", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

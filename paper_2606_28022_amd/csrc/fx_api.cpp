@@ -346,30 +346,41 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     check(hipGetLastError(), "initial basis");
   }
   std::vector<int> active = list;
-  std::vector<int> sweeps(b.nsys);
-  std::vector<int> status(b.nsys);
-  std::vector<int> niter(b.nsys);
+  std::vector<int> sweeps(b.nsys), status(b.nsys), niter(b.nsys);
   DevBuf<int> d_act;
+  const int nt = (b.max_nao + 31) / 32;
+  // flop count of one n x n product summed over a list of systems
+  auto gemm_gflop = [&](const std::vector<int>& l) {
+    double g = 0.0;
+    for (int s : l) {
+      double n = b.h_desc[s].nao;
+      g += 2e-9 * n * n * n;
+    }
+    return g;
+  };
+  auto gemm = [&](const std::vector<int>& l, const int* dl, int mode, const double* A, const double* B, double* C,
+                  const double* w) {
+    int ev = timers.begin(stream);
+    hipLaunchKernelGGL(k_gemm, dim3(nt * nt, (unsigned)l.size()), dim3(256), 0, stream, db, dl, mode, A, B, C, w);
+    timers.end(stream, ev, &t_gemm, gemm_gflop(l));
+  };
   for (int it = 0; it < opt.max_iter + 1 && !active.empty(); ++it) {
     d_act.upload(active);
     const int na = (int)active.size();
-    const int nt = (b.max_nao + 31) / 32;
     hipLaunchKernelGGL(k_fock, dim3(na), dim3(256), 0, stream, ds, db, d_act.p);
-    hipLaunchKernelGGL(k_gemm, dim3(nt * nt, na), dim3(256), 0, stream, db, d_act.p, 0, b.Ct.p, b.Fm.p, b.Tm.p,
-                       (const double*)nullptr);
-    hipLaunchKernelGGL(k_gemm, dim3(nt * nt, na), dim3(256), 0, stream, db, d_act.p, 1, b.Tm.p, b.Ct.p, b.Fm.p,
-                       (const double*)nullptr);
-    if (!t_jacobi.e0) {
-      check(hipEventCreate(&t_jacobi.e0), "hipEventCreate");
-      check(hipEventCreate(&t_jacobi.e1), "hipEventCreate");
+    // A = C^T F C in the current basis, then Jacobi rotations
+    gemm(active, d_act.p, 0, b.Ct.p, b.Fm.p, b.Tm.p, nullptr);
+    gemm(active, d_act.p, 1, b.Tm.p, b.Ct.p, b.Fm.p, nullptr);
+    {
+      // the first iteration from the Cholesky basis is diagonalised fully
+      const double cap = (cold && it == 0 && !b.init_from_mono) ? 1e300 : jacobi_cap_err;
+      int ev = timers.begin(stream);
+      hipLaunchKernelGGL(k_jacobi, dim3(na), dim3(jacobi_threads), 0, stream, db, d_act.p, jacobi_max_sweeps, jacobi_tol,
+                         jacobi_thr_scale, cap, b.sweeps.p);
+      timers.end(stream, ev, &t_jacobi, 0.0);
     }
-    check(hipEventRecord(t_jacobi.e0, stream), "hipEventRecord");
-    hipLaunchKernelGGL(k_jacobi, dim3(na), dim3(256), 0, stream, db, d_act.p, jacobi_max_sweeps, jacobi_tol,
-                       jacobi_thr_scale, b.sweeps.p);
-    check(hipEventRecord(t_jacobi.e1, stream), "hipEventRecord");
     hipLaunchKernelGGL(k_fermi, dim3(na), dim3(256), 0, stream, ds, db, d_act.p);
-    hipLaunchKernelGGL(k_gemm, dim3(nt * nt, na), dim3(256), 0, stream, db, d_act.p, 2, b.Ct.p, b.Ct.p, b.Pm.p,
-                       (const double*)b.occ.p);
+    gemm(active, d_act.p, 2, b.Ct.p, b.Ct.p, b.Pm.p, b.occ.p);
     hipLaunchKernelGGL(k_charges_mix, dim3(na), dim3(256), 0, stream, ds, db, d_act.p,
                        scc_tol_cur > 0 ? scc_tol_cur : opt.scc_tol, etol_cur > 0 ? etol_cur : opt.energy_tol,
                        opt.max_iter, mix_beta);
@@ -377,19 +388,13 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     b.status.download(status, stream);
     b.sweeps.download(sweeps, stream);
     sync();
-    {
-      float ms = 0.0f;
-      check(hipEventElapsedTime(&ms, t_jacobi.e0, t_jacobi.e1), "hipEventElapsedTime");
-      t_jacobi.ms += ms;
-      t_jacobi.launches += 1;
-      // algorithmic work of a sweep over an n x n matrix: the A update
-      // (upper triangle, 2x2 block rotations) and the eigenvector rows,
-      // 6 n^2 flop per step times (n - 1) steps; the convergence check of
-      // a sweep is counted as part of the sweep
-      for (int s : active) {
-        double n = b.h_desc[s].nao;
-        t_jacobi.gflop += 1e-9 * 6.0 * n * n * (n - 1.0) * (double)sweeps[s];
-      }
+    timers.resolve();
+    // algorithmic work of a Jacobi sweep over an n x n matrix: the A update
+    // (upper triangle, 2x2 block rotations) and the eigenvector rows,
+    // 6 n^2 flop per step times (n - 1) steps
+    for (int s : active) {
+      double n = b.h_desc[s].nao;
+      t_jacobi.gflop += 1e-9 * 6.0 * n * n * (n - 1.0) * (double)sweeps[s];
     }
     std::vector<int> next;
     for (int s : active)
@@ -599,6 +604,7 @@ void Ctx::run(fx_result* out) {
   if (opt.precision != FX_FP64) throw FxError(FX_E_UNSUPPORTED, "only FX_FP64 is available");
   std::memset(&res, 0, sizeof(res));
   t_jacobi.reset();
+  t_gemm.reset();
   bool all_conv = true;
   double t0 = now_ms();
   if (!lists_built) build_lists_impl();
@@ -814,6 +820,9 @@ void Ctx::run(fx_result* out) {
   res.ms_jacobi = t_jacobi.ms;
   res.jacobi_launches = t_jacobi.launches;
   res.gflop_jacobi = t_jacobi.gflop;
+  res.ms_gemm = t_gemm.ms;
+  res.gemm_launches = t_gemm.launches;
+  res.gflop_gemm = t_gemm.gflop;
   if (out) *out = res;
 }
 

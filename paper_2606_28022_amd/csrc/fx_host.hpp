@@ -117,7 +117,6 @@ struct Batch {
 
 // Event-timed accumulation of one kernel's launches on the context stream.
 struct KernelTimer {
-  hipEvent_t e0 = nullptr, e1 = nullptr;
   double ms = 0.0;
   long long launches = 0;
   double gflop = 0.0;
@@ -138,6 +137,8 @@ struct Ctx {
   int jacobi_max_sweeps = 40;
   double jacobi_tol = 1e-14;
   double jacobi_thr_scale = 1e-3;
+  double jacobi_cap_err = 1e-9;
+  int jacobi_threads = std::getenv("FX_JACOBI_THREADS") ? std::atoi(std::getenv("FX_JACOBI_THREADS")) : 1024;
   double mix_beta = 0.5;
   double macro_beta = 0.5;
   double scc_tol_cur = -1.0, etol_cur = -1.0;
@@ -162,7 +163,43 @@ struct Ctx {
   DevBuf<double> e_mono, dE_scc, dEV_scc, dE_esd, dE_tri, ddq_scc;
   std::vector<double> trimer_dEIJK;
   fx_result res{};
-  KernelTimer t_jacobi;
+  KernelTimer t_jacobi, t_gemm;
+  // pool of HIP event pairs around kernel launches, resolved after a sync
+  struct EventPool {
+    std::vector<hipEvent_t> ev0, ev1;
+    std::vector<KernelTimer*> who;
+    std::vector<double> gf;
+    int used = 0;
+    int begin(hipStream_t s) {
+      if (used == (int)ev0.size()) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+          throw FxError(FX_E_DEVICE, "hipEventCreate failed");
+        ev0.push_back(a);
+        ev1.push_back(b);
+        who.push_back(nullptr);
+        gf.push_back(0.0);
+      }
+      if (hipEventRecord(ev0[used], s) != hipSuccess) throw FxError(FX_E_DEVICE, "hipEventRecord failed");
+      return used++;
+    }
+    void end(hipStream_t s, int k, KernelTimer* t, double gflop) {
+      if (hipEventRecord(ev1[k], s) != hipSuccess) throw FxError(FX_E_DEVICE, "hipEventRecord failed");
+      who[k] = t;
+      gf[k] = gflop;
+    }
+    void resolve() {
+      for (int k = 0; k < used; ++k) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ev0[k], ev1[k]) != hipSuccess) throw FxError(FX_E_DEVICE, "event time failed");
+        who[k]->ms += ms;
+        who[k]->launches += 1;
+        who[k]->gflop += gf[k];
+      }
+      used = 0;
+    }
+  } timers;
+
 
   static void check(hipError_t e, const char* what);
   static void* dmalloc(size_t bytes);

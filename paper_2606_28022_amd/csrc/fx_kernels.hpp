@@ -26,7 +26,7 @@ __global__ void k_fock(DevSystem sys, DevBatch bt, const int* list);
 __global__ void k_gemm(DevBatch bt, const int* list, int mode, const double* A, const double* B, double* C,
                        const double* w);
 __global__ void k_jacobi(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale,
-                         int* sweeps_out);
+                         double cap_err, int* sweeps_out);
 __global__ void k_eigh_batched(const int* nvec, const long long* off, double* Abuf, double* Vbuf, double* wbuf,
                                const long long* woff, int max_sweeps, double rel_tol);
 __global__ void k_fermi(DevSystem sys, DevBatch bt, const int* list);

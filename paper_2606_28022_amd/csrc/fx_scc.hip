@@ -241,21 +241,22 @@ __device__ inline int rr_index(int pos, int step, int m) {
   return pos == 0 ? 0 : 1 + (pos - 1 + step) % (m - 1);
 }
 
-__device__ void jacobi_solve(double* A, double* V, int n, int nv, int max_sweeps, double rel_tol, double abs_thr,
-                             double* red, double* cs_c, double* cs_s, double* cs_t, int* pp, int* qq,
-                             int* nsweep_out) {
+__device__ void jacobi_solve(double* __restrict__ A, double* __restrict__ V, int n, int nv, int max_sweeps,
+                             double rel_tol, double abs_thr, double* red, double* cs_c, double* cs_s, double* cs_t,
+                             int* pp, int* qq, int* nsweep_out) {
   const int m = n + (n & 1);
   const int nb = m / 2;
+  const int nt = blockDim.x;
   // scale: Frobenius norm
   double loc = 0.0;
-  for (long long i = threadIdx.x; i < (long long)n * n; i += blockDim.x) loc += A[i] * A[i];
+  for (long long i = threadIdx.x; i < (long long)n * n; i += nt) loc += A[i] * A[i];
   double fro = sqrt(block_sum(loc, red));
   double thr = fmax(rel_tol * (fro > 0.0 ? fro : 1.0), abs_thr);
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
     double maxoff = 0.0;
     for (int step = 0; step < m - 1; ++step) {
-      for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+      for (int k = threadIdx.x; k < nb; k += nt) {
         int p = rr_index(k, step, m), q = rr_index(m - 1 - k, step, m);
         if (p > q) {
           int t = p;
@@ -281,65 +282,112 @@ __device__ void jacobi_solve(double* A, double* V, int n, int nv, int max_sweeps
         qq[k] = q;
       }
       __syncthreads();
-      // A <- J^T A J over (k <= l) blocks
+      // A <- J^T A J over (a <= b) pair blocks; two blocks per thread per
+      // round with all loads issued before the stores
       const int nblk = nb * (nb + 1) / 2;
-      for (int idx = threadIdx.x; idx < nblk; idx += blockDim.x) {
-        // triangular index -> (k, l), k <= l
-        int k = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-        while (k * (k + 1) / 2 > idx) --k;
-        while ((k + 1) * (k + 2) / 2 <= idx) ++k;
-        int l = idx - k * (k + 1) / 2;  // l <= k
-        // use (a, b) = (l, k) with a <= b
-        int a = l, b = k;
-        int p = pp[a], q = qq[a], r = pp[b], u = qq[b];
-        double ca = cs_c[a], sa = cs_s[a], cb = cs_c[b], sb = cs_s[b];
-        if (sa == 0.0 && sb == 0.0) continue;
-        if (a == b) {
-          if (q >= n) continue;
-          double apq = A[(long long)p * n + q];
-          double t = cs_t[a];
-          A[(long long)p * n + p] -= t * apq;
-          A[(long long)q * n + q] += t * apq;
-          A[(long long)p * n + q] = 0.0;
-          A[(long long)q * n + p] = 0.0;
-          continue;
+      for (int base = threadIdx.x; base < nblk; base += 2 * nt) {
+        int ids[2] = {base, base + nt};
+        double v[2][4];
+        int P_[2], Q_[2], R_[2], U_[2];
+        double ca_[2], sa_[2], cb_[2], sb_[2];
+        bool act[2], diag[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          int idx = ids[h];
+          act[h] = false;
+          diag[h] = false;
+          if (idx >= nblk) continue;
+          int k = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+          while (k * (k + 1) / 2 > idx) --k;
+          while ((k + 1) * (k + 2) / 2 <= idx) ++k;
+          int a = idx - k * (k + 1) / 2, b = k;  // a <= b
+          ca_[h] = cs_c[a];
+          sa_[h] = cs_s[a];
+          cb_[h] = cs_c[b];
+          sb_[h] = cs_s[b];
+          if (sa_[h] == 0.0 && sb_[h] == 0.0) continue;
+          P_[h] = pp[a];
+          Q_[h] = qq[a];
+          R_[h] = pp[b];
+          U_[h] = qq[b];
+          act[h] = true;
+          if (a == b) {
+            diag[h] = true;
+            if (Q_[h] >= n) {
+              act[h] = false;
+              continue;
+            }
+            v[h][0] = A[(long long)P_[h] * n + Q_[h]];
+            v[h][1] = cs_t[a];
+            continue;
+          }
+          bool qv = Q_[h] < n, uv = U_[h] < n;
+          v[h][0] = A[(long long)P_[h] * n + R_[h]];
+          v[h][1] = uv ? A[(long long)P_[h] * n + U_[h]] : 0.0;
+          v[h][2] = qv ? A[(long long)Q_[h] * n + R_[h]] : 0.0;
+          v[h][3] = (qv && uv) ? A[(long long)Q_[h] * n + U_[h]] : 0.0;
         }
-        bool qv = q < n, uv = u < n;
-        double bpr = A[(long long)p * n + r];
-        double bpu = uv ? A[(long long)p * n + u] : 0.0;
-        double bqr = qv ? A[(long long)q * n + r] : 0.0;
-        double bqu = (qv && uv) ? A[(long long)q * n + u] : 0.0;
-        // rows: J_a^T
-        double tpr = ca * bpr - sa * bqr, tpu = ca * bpu - sa * bqu;
-        double tqr = sa * bpr + ca * bqr, tqu = sa * bpu + ca * bqu;
-        // cols: J_b
-        double npr = cb * tpr - sb * tpu, npu = sb * tpr + cb * tpu;
-        double nqr = cb * tqr - sb * tqu, nqu = sb * tqr + cb * tqu;
-        A[(long long)p * n + r] = npr;
-        A[(long long)r * n + p] = npr;
-        if (uv) {
-          A[(long long)p * n + u] = npu;
-          A[(long long)u * n + p] = npu;
-        }
-        if (qv) {
-          A[(long long)q * n + r] = nqr;
-          A[(long long)r * n + q] = nqr;
-        }
-        if (qv && uv) {
-          A[(long long)q * n + u] = nqu;
-          A[(long long)u * n + q] = nqu;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (!act[h]) continue;
+          int p = P_[h], q = Q_[h], r = R_[h], u = U_[h];
+          if (diag[h]) {
+            double apq = v[h][0], t = v[h][1];
+            A[(long long)p * n + p] -= t * apq;
+            A[(long long)q * n + q] += t * apq;
+            A[(long long)p * n + q] = 0.0;
+            A[(long long)q * n + p] = 0.0;
+            continue;
+          }
+          bool qv = q < n, uv = u < n;
+          double ca = ca_[h], sa = sa_[h], cb = cb_[h], sb = sb_[h];
+          double tpr = ca * v[h][0] - sa * v[h][2], tpu = ca * v[h][1] - sa * v[h][3];
+          double tqr = sa * v[h][0] + ca * v[h][2], tqu = sa * v[h][1] + ca * v[h][3];
+          double npr = cb * tpr - sb * tpu, npu = sb * tpr + cb * tpu;
+          double nqr = cb * tqr - sb * tqu, nqu = sb * tqr + cb * tqu;
+          A[(long long)p * n + r] = npr;
+          A[(long long)r * n + p] = npr;
+          if (uv) {
+            A[(long long)p * n + u] = npu;
+            A[(long long)u * n + p] = npu;
+          }
+          if (qv) {
+            A[(long long)q * n + r] = nqr;
+            A[(long long)r * n + q] = nqr;
+          }
+          if (qv && uv) {
+            A[(long long)q * n + u] = nqu;
+            A[(long long)u * n + q] = nqu;
+          }
         }
       }
-      // eigenvector rows
-      for (int idx = threadIdx.x; idx < nb * nv; idx += blockDim.x) {
-        int k = idx / nv, j = idx - k * nv;
-        double s = cs_s[k];
-        if (s == 0.0) continue;
-        int p = pp[k], q = qq[k];
-        double c = cs_c[k];
-        double vp = V[(long long)p * nv + j], vq = V[(long long)q * nv + j];
-        V[(long long)p * nv + j] = c * vp - s * vq;
-        V[(long long)q * nv + j] = s * vp + c * vq;
+      // eigenvector rows, four elements per thread per round, loads first
+      const int nvv = nb * nv;
+      for (int base = threadIdx.x; base < nvv; base += 4 * nt) {
+        double vp[4], vq[4], cc[4], ss[4];
+        long long op[4], oq[4];
+        bool go[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          int idx = base + h * nt;
+          go[h] = false;
+          if (idx >= nvv) continue;
+          int k = idx / nv, j = idx - k * nv;
+          ss[h] = cs_s[k];
+          if (ss[h] == 0.0) continue;
+          cc[h] = cs_c[k];
+          op[h] = (long long)pp[k] * nv + j;
+          oq[h] = (long long)qq[k] * nv + j;
+          vp[h] = V[op[h]];
+          vq[h] = V[oq[h]];
+          go[h] = true;
+        }
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          if (!go[h]) continue;
+          V[op[h]] = cc[h] * vp[h] - ss[h] * vq[h];
+          V[oq[h]] = ss[h] * vp[h] + cc[h] * vq[h];
+        }
       }
       __syncthreads();
     }
@@ -349,19 +397,21 @@ __device__ void jacobi_solve(double* A, double* V, int n, int nv, int max_sweeps
   if (nsweep_out && threadIdx.x == 0) *nsweep_out = sweep < max_sweeps ? sweep + 1 : max_sweeps;
 }
 
-// Rotations below max(rel_tol |A|_F, thr_scale * last SCC residual) are skipped:
-// while the charges are far from self-consistent the orbitals only need a
-// matching accuracy; the final iterations are diagonalised to rel_tol.
+// Rotations below max(rel_tol |A|_F, thr_scale * last SCC residual) are skipped,
+// and while that residual exceeds cap_err a single sweep is made per SCC
+// iteration (the warm-started basis is refined together with the charges);
+// the final iterations are diagonalised to rel_tol.
 __global__ void k_jacobi(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale,
-                         int* sweeps_out) {
+                         double cap_err, int* sweeps_out) {
   int si = list[blockIdx.x];
   const SysDesc d = bt.desc[si];
-  __shared__ double red[256];
+  __shared__ double red[1024];
   __shared__ double cs_c[MAXN / 2], cs_s[MAXN / 2], cs_t[MAXN / 2];
   __shared__ int pp[MAXN / 2], qq[MAXN / 2];
   double* A = bt.F + d.mat_off;
   double* V = bt.Ct + d.mat_off;
-  jacobi_solve(A, V, d.nao, d.nao, max_sweeps, rel_tol, thr_scale * bt.err[si], red, cs_c, cs_s, cs_t, pp, qq,
+  const int msw = bt.err[si] > cap_err ? 1 : max_sweeps;
+  jacobi_solve(A, V, d.nao, d.nao, msw, rel_tol, thr_scale * bt.err[si], red, cs_c, cs_s, cs_t, pp, qq,
                sweeps_out ? sweeps_out + si : nullptr);
   __syncthreads();
   for (int i = threadIdx.x; i < d.nao; i += blockDim.x) bt.eps[d.ao_off + i] = A[(long long)i * d.nao + i];
