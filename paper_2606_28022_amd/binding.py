@@ -135,8 +135,9 @@ class FmoXtb:
         ctx = C.c_void_p()
         rc = self.L.fx_ctx_create(pp, device, stream, C.byref(ctx))
         if rc != FX_OK:
+            self._params = None
             self.L.fx_params_free(pp)
-            raise FxError(rc, "context creation failed")
+            raise FxError(rc, "context creation failed: " + self.L.fx_last_error(None).decode())
         self.ctx = ctx
         self.opt = fx_options()
         self.L.fx_default_options(C.byref(self.opt))

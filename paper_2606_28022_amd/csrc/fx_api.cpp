@@ -307,6 +307,52 @@ DevBatch Batch::dev() {
   return d;
 }
 
+void Ctx::init_device() {
+  int v = 0;
+  check(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device), "LDS size query");
+  // dynamic LDS available to k_jacobi_lds: the per-workgroup limit minus the
+  // kernels' static LDS; raising the dynamic limit is advisory (the runtime
+  // rejects an oversized launch, which check() then reports)
+  unsigned stat = 0;
+  for (const void* k : {reinterpret_cast<const void*>(k_jacobi_lds<double>),
+                        reinterpret_cast<const void*>(k_jacobi_lds<float>)}) {
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, k) == hipSuccess) stat = std::max(stat, (unsigned)fa.sharedSizeBytes);
+  }
+  lds_max = v - (int)stat;
+  for (const void* k : {reinterpret_cast<const void*>(k_jacobi_lds<double>),
+                        reinterpret_cast<const void*>(k_jacobi_lds<float>)})
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+  (void)hipGetLastError();
+  if (verbose) std::fprintf(stderr, "[fx] LDS per workgroup %d B, static %u B\n", v, stat);
+}
+
+// Eigensolver for a batch whose largest system has n AOs: the LDS-resident
+// kernel with an FP64 working matrix if it fits with a rotation log of at
+// least 4 steps, else with an FP32 working matrix, else the global-memory
+// kernel.  Workgroup size grows with n (one V column per wave).
+JacobiPlan Ctx::jacobi_plan(int n) const {
+  JacobiPlan jp;
+  if (!jacobi_lds || n < 2 || n > MAXN) return jp;
+  int t = n <= 32 ? 64 : n <= 96 ? 256 : n <= 160 ? 512 : 1024;
+  if (const char* e = std::getenv("FX_JACOBI_LDS_THREADS")) t = std::atoi(e);
+  const int chunks[] = {16, 8, 4, 2};
+  for (int pass = 0; pass < 2; ++pass)
+    for (int elt : {8, 4})
+      for (int k : chunks) {
+        if (pass == 0 && k < 4) continue;
+        const unsigned bytes = jacobi_lds_layout(n, elt, k, t / 64).total;
+        if ((int)bytes <= lds_max) {
+          jp.elt = elt;
+          jp.chunk = k;
+          jp.threads = t;
+          jp.lds = bytes;
+          return jp;
+        }
+      }
+  return jp;
+}
+
 void Ctx::build_matrices(Batch& b) {
   DevBatch db = b.dev();
   hipLaunchKernelGGL(k_build_system, dim3(b.nsys), dim3(256), 0, stream, dev_system(), db, nullptr);
@@ -345,6 +391,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     }
     check(hipGetLastError(), "initial basis");
   }
+  const JacobiPlan jp = jacobi_plan(b.max_nao);
   std::vector<int> active = list;
   std::vector<int> sweeps(b.nsys), status(b.nsys), niter(b.nsys);
   DevBuf<int> d_act;
@@ -375,8 +422,15 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
       // the first iteration from the Cholesky basis is diagonalised fully
       const double cap = (cold && it == 0 && !b.init_from_mono) ? 1e300 : jacobi_cap_err;
       int ev = timers.begin(stream);
-      hipLaunchKernelGGL(k_jacobi, dim3(na), dim3(jacobi_threads), 0, stream, db, d_act.p, jacobi_max_sweeps, jacobi_tol,
-                         jacobi_thr_scale, cap, b.sweeps.p);
+      if (jp.elt == 8)
+        hipLaunchKernelGGL(k_jacobi_lds<double>, dim3(na), dim3(jp.threads), jp.lds, stream, db, d_act.p,
+                           jacobi_max_sweeps, jacobi_tol, jacobi_thr_scale, cap, b.sweeps.p, jp.chunk);
+      else if (jp.elt == 4)
+        hipLaunchKernelGGL(k_jacobi_lds<float>, dim3(na), dim3(jp.threads), jp.lds, stream, db, d_act.p,
+                           jacobi_max_sweeps, jacobi_tol, jacobi_thr_scale, cap, b.sweeps.p, jp.chunk);
+      else
+        hipLaunchKernelGGL(k_jacobi, dim3(na), dim3(jacobi_threads), 0, stream, db, d_act.p, jacobi_max_sweeps,
+                           jacobi_tol, jacobi_thr_scale, cap, b.sweeps.p);
       timers.end(stream, ev, &t_jacobi, 0.0);
     }
     hipLaunchKernelGGL(k_fermi, dim3(na), dim3(256), 0, stream, ds, db, d_act.p);
@@ -411,8 +465,11 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
       tot += niter[s];
       mx = std::max(mx, niter[s]);
     }
-    std::fprintf(stderr, "[fx] scc batch of %d systems (nao<=%d): %lld iterations, max %d, %.1f ms\n", nl,
-                 b.max_nao, tot, mx, now_ms() - t_start);
+    std::fprintf(stderr,
+                 "[fx] scc batch of %d systems (nao<=%d): %lld iterations, max %d, %.1f ms "
+                 "(eigensolver: %s, chunk %d, %d threads, %u B LDS)\n",
+                 nl, b.max_nao, tot, mx, now_ms() - t_start,
+                 jp.elt == 8 ? "lds-fp64" : jp.elt == 4 ? "lds-fp32" : "global", jp.chunk, jp.threads, jp.lds);
   }
   int failed = 0;
   long long iters = 0;
@@ -878,9 +935,11 @@ int fx_ctx_create(const fx_params* p, int device, void* hip_stream, fx_ctx** out
     c->c.device = device;
     fx::Ctx::check(hipSetDevice(device), "hipSetDevice");
     c->c.stream = static_cast<hipStream_t>(hip_stream);
+    c->c.init_device();
     c->c.d_elems.upload(c->c.P.elems);
     fx_default_options(&c->c.opt);
   } catch (const fx::FxError& e) {
+    g_param_error = e.what();
     delete c;
     return e.code;
   }

@@ -127,6 +127,12 @@ struct KernelTimer {
   }
 };
 
+// eigensolver choice for one batch (elt = 0: global-memory kernel)
+struct JacobiPlan {
+  int elt = 0, chunk = 0, threads = 0;
+  unsigned lds = 0;
+};
+
 struct Ctx {
   HostParams P;
   int device = 0;
@@ -139,6 +145,10 @@ struct Ctx {
   double jacobi_thr_scale = 1e-3;
   double jacobi_cap_err = 1e-9;
   int jacobi_threads = std::getenv("FX_JACOBI_THREADS") ? std::atoi(std::getenv("FX_JACOBI_THREADS")) : 1024;
+  // LDS-resident eigensolver (k_jacobi_lds) where the system fits; FX_JACOBI_LDS=0
+  // selects the global-memory kernel everywhere
+  bool jacobi_lds = !(std::getenv("FX_JACOBI_LDS") && std::atoi(std::getenv("FX_JACOBI_LDS")) == 0);
+  int lds_max = 65536;  // bytes of LDS one workgroup may allocate (queried)
   double mix_beta = 0.5;
   double macro_beta = 0.5;
   double scc_tol_cur = -1.0, etol_cur = -1.0;
@@ -213,6 +223,8 @@ struct Ctx {
   void field(const double* d_q, double* d_phi);
   void build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters, int nfrag_each);
   void build_matrices(Batch& b);
+  void init_device();
+  JacobiPlan jacobi_plan(int n) const;
   int run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* iters_out);
   int solve_batch(Batch& b, bool cold, long long* iters_out);
   void run(fx_result* out);

@@ -27,6 +27,35 @@ __global__ void k_gemm(DevBatch bt, const int* list, int mode, const double* A, 
                        const double* w);
 __global__ void k_jacobi(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale,
                          double cap_err, int* sweeps_out);
+// LDS layout of k_jacobi_lds for an n x n system: packed strict upper
+// triangle (elt bytes per element), FP64 diagonal, `chunk` steps of rotation
+// log, an nw-column tile of V and the reduction slots (16-byte aligned parts).
+struct JacobiLdsLayout {
+  unsigned ap, dg, cs, pq, vt, red, total;
+};
+__host__ __device__ inline unsigned jl_align(unsigned x) { return (x + 15u) & ~15u; }
+__host__ __device__ inline JacobiLdsLayout jacobi_lds_layout(int n, int elt, int chunk, int nw) {
+  const unsigned nb = (unsigned)(n + (n & 1)) / 2;
+  JacobiLdsLayout L;
+  unsigned o = 0;
+  L.ap = o;
+  o = jl_align(o + (unsigned)n * (unsigned)(n - 1) / 2u * (unsigned)elt);
+  L.dg = o;
+  o = jl_align(o + 8u * (unsigned)n);
+  L.cs = o;
+  o = jl_align(o + 16u * (unsigned)chunk * nb);
+  L.pq = o;
+  o = jl_align(o + 4u * (unsigned)chunk * nb);
+  L.vt = o;
+  o = jl_align(o + 8u * (unsigned)nw * (unsigned)(n + 1));
+  L.red = o;
+  o = jl_align(o + 8u * 64u);
+  L.total = o;
+  return L;
+}
+template <typename T>
+__global__ void k_jacobi_lds(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale,
+                             double cap_err, int* sweeps_out, int chunk);
 __global__ void k_eigh_batched(const int* nvec, const long long* off, double* Abuf, double* Vbuf, double* wbuf,
                                const long long* woff, int max_sweeps, double rel_tol);
 __global__ void k_fermi(DevSystem sys, DevBatch bt, const int* list);

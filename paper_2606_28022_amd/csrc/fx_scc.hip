@@ -646,3 +646,240 @@ __global__ void k_charges_mix(DevSystem sys, DevBatch bt, const int* list, doubl
 }
 
 }  // namespace fx
+
+namespace fx {
+
+// ---------------------------------------------------------------------------
+// LDS-resident parallel Jacobi (same rotations and round-robin order as
+// jacobi_solve).  The working matrix lives in LDS: its strict upper triangle
+// packed in precision T, the diagonal separately in FP64.  Rotation angles are
+// computed in FP64 from the FP64 diagonal; the rotated off-diagonal elements
+// are kept in T.  The rotations of `chunk` consecutive steps are logged in LDS
+// (FP64 c, s) and then applied to the FP64 basis rows of V in column tiles
+// streamed through LDS, so V is read and written once per chunk instead of
+// once per step.  V stays orthonormal to FP64 rounding whatever T is; with
+// T = float the off-diagonal storage error is relative to the off-diagonal
+// elements themselves, and since every SCC iteration rebuilds A = C^T F C in
+// FP64 the next iteration removes it (iterative refinement): the converged
+// eigenpairs carry FP64 accuracy.
+__device__ inline int pk_index(int i, int j) { return i < j ? j * (j - 1) / 2 + i : i * (i - 1) / 2 + j; }
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+// block reductions over per-wave partials, summed in wave order
+__device__ inline double wblock_sum(double v, double* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += red[w];
+  return r;
+}
+__device__ inline double wblock_max(double v, double* red) {
+  v = wave_max(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w]);
+  return r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+    k_jacobi_lds(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale, double cap_err,
+                 int* sweeps_out, int chunk) {
+  extern __shared__ double2 lds_raw[];
+  unsigned char* lds = reinterpret_cast<unsigned char*>(lds_raw);
+  const int si = list[blockIdx.x];
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao, nv = d.nao;
+  const int m = n + (n & 1), nb = m / 2;
+  const int nt = blockDim.x, nw = nt >> 6;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const JacobiLdsLayout L = jacobi_lds_layout(n, (int)sizeof(T), chunk, nw);
+  T* Ap = reinterpret_cast<T*>(lds + L.ap);
+  double* dg = reinterpret_cast<double*>(lds + L.dg);
+  double2* cs = reinterpret_cast<double2*>(lds + L.cs);  // [chunk][nb] (c, s)
+  int* pq = reinterpret_cast<int*>(lds + L.pq);          // [chunk][nb] p | q << 16
+  double* vt = reinterpret_cast<double*>(lds + L.vt);    // [nw][n + 1] column tile of V
+  double* red = reinterpret_cast<double*>(lds + L.red);
+  const double* __restrict__ A = bt.F + d.mat_off;
+  double* __restrict__ V = bt.Ct + d.mat_off;
+
+  // load: diagonal in FP64, strict upper triangle packed in T; |A|_F
+  double loc = 0.0;
+  for (int e = threadIdx.x; e < n * n; e += nt) {
+    const int i = e / n, j = e - i * n;
+    if (j < i) continue;
+    const double v = A[e];
+    if (i == j) {
+      dg[i] = v;
+      loc += v * v;
+    } else {
+      Ap[pk_index(i, j)] = (T)v;
+      loc += 2.0 * v * v;
+    }
+  }
+  const double fro = sqrt(wblock_sum(loc, red));
+  const double err = bt.err[si];
+  const double thr = fmax(rel_tol * (fro > 0.0 ? fro : 1.0), thr_scale * err);
+  const int msw = err > cap_err ? 1 : max_sweeps;
+  // folded enumeration of the off-diagonal pair blocks (a < b): rows a and
+  // R-1-a together hold nb blocks; the middle row (R odd) follows
+  const int R = nb - 1, hp = R / 2, rect = hp * nb, noff = nb * (nb - 1) / 2;
+  const int per = (n * nw + nt - 1) / nt;  // tile elements per thread (<= 8 for n <= 512)
+  const int ntile = (nv + nw - 1) / nw;
+  double* col = vt + (long long)wave * (n + 1);
+  int sweep = 0;
+  for (; sweep < msw; ++sweep) {
+    double maxoff = 0.0;
+    for (int s0 = 0; s0 < m - 1; s0 += chunk) {
+      const int s1 = min(m - 1, s0 + chunk);
+      int rot_local = 0;
+      for (int step = s0; step < s1; ++step) {
+        double2* csx = cs + (step - s0) * nb;
+        int* pqx = pq + (step - s0) * nb;
+        // rotation parameters; each pair's own 2x2 diagonal block is
+        // finished here (no other block of this step touches it)
+        for (int k = threadIdx.x; k < nb; k += nt) {
+          int p = rr_index(k, step, m), q = rr_index(m - 1 - k, step, m);
+          if (p > q) {
+            const int t = p;
+            p = q;
+            q = t;
+          }
+          double c = 1.0, s = 0.0;
+          if (q < n) {
+            const int ipq = pk_index(p, q);
+            const double apq = (double)Ap[ipq];
+            maxoff = fmax(maxoff, fabs(apq));
+            if (fabs(apq) > thr) {
+              const double app = dg[p], aqq = dg[q];
+              const double theta = (aqq - app) / (2.0 * apq);
+              const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+              c = 1.0 / sqrt(t * t + 1.0);
+              s = t * c;
+              dg[p] = app - t * apq;
+              dg[q] = aqq + t * apq;
+              Ap[ipq] = (T)0;
+              rot_local = 1;
+            }
+          }
+          csx[k] = make_double2(c, s);
+          pqx[k] = p | (q << 16);
+        }
+        __syncthreads();
+        // A <- J^T A J on the off-diagonal 2x2 blocks (pair a, pair b)
+        for (int idx = threadIdx.x; idx < noff; idx += nt) {
+          int a, b;
+          if (idx < rect) {
+            const int r = idx / nb, cc = idx - r * nb;
+            if (cc < R - r) {
+              a = r;
+              b = r + 1 + cc;
+            } else {
+              a = R - 1 - r;
+              b = a + 1 + (cc - (R - r));
+            }
+          } else {
+            a = hp;
+            b = hp + 1 + (idx - rect);
+          }
+          const double2 wa = csx[a], wb = csx[b];
+          if (wa.y == 0.0 && wb.y == 0.0) continue;
+          const int va = pqx[a], vb = pqx[b];
+          const int p = va & 0xffff, q = va >> 16, r = vb & 0xffff, u = vb >> 16;
+          const bool qv = q < n, uv = u < n;
+          const T ca = (T)wa.x, sa = (T)wa.y, cb = (T)wb.x, sb = (T)wb.y;
+          const int ipr = pk_index(p, r);
+          const int ipu = uv ? pk_index(p, u) : 0;
+          const int iqr = qv ? pk_index(q, r) : 0;
+          const int iqu = (qv && uv) ? pk_index(q, u) : 0;
+          const T bpr = Ap[ipr];
+          const T bpu = uv ? Ap[ipu] : (T)0;
+          const T bqr = qv ? Ap[iqr] : (T)0;
+          const T bqu = (qv && uv) ? Ap[iqu] : (T)0;
+          const T tpr = ca * bpr - sa * bqr, tpu = ca * bpu - sa * bqu;
+          const T tqr = sa * bpr + ca * bqr, tqu = sa * bpu + ca * bqu;
+          Ap[ipr] = cb * tpr - sb * tpu;
+          if (uv) Ap[ipu] = sb * tpr + cb * tpu;
+          if (qv) Ap[iqr] = cb * tqr - sb * tqu;
+          if (qv && uv) Ap[iqu] = sb * tqr + cb * tqu;
+        }
+        __syncthreads();
+      }
+      // apply the chunk's rotations to the rows of V, nw columns at a time:
+      // coalesced tile loads (next tile prefetched into registers), one
+      // column per wave, coalesced stores
+      if (__syncthreads_or(rot_local)) {
+        double rg[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int e = threadIdx.x + r * nt, i = e / nw, j = e - i * nw;
+          rg[r] = (r < per && i < n && j < nv) ? V[(long long)i * nv + j] : 0.0;
+        }
+        for (int tile = 0; tile < ntile; ++tile) {
+          const int c0 = tile * nw;
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            const int e = threadIdx.x + r * nt, i = e / nw, j = e - i * nw;
+            if (r < per && i < n) vt[(long long)j * (n + 1) + i] = rg[r];
+          }
+          __syncthreads();
+          if (tile + 1 < ntile) {
+            const int c1 = c0 + nw;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+              const int e = threadIdx.x + r * nt, i = e / nw, j = e - i * nw;
+              rg[r] = (r < per && i < n && c1 + j < nv) ? V[(long long)i * nv + c1 + j] : 0.0;
+            }
+          }
+          if (c0 + wave < nv) {
+            for (int step = s0; step < s1; ++step) {
+              const double2* csx = cs + (step - s0) * nb;
+              const int* pqx = pq + (step - s0) * nb;
+              for (int k = lane; k < nb; k += 64) {
+                const double2 w = csx[k];
+                if (w.y != 0.0) {
+                  const int v = pqx[k];
+                  const int p = v & 0xffff, q = v >> 16;
+                  const double vp = col[p], vq = col[q];
+                  col[p] = w.x * vp - w.y * vq;
+                  col[q] = w.y * vp + w.x * vq;
+                }
+              }
+              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+              __builtin_amdgcn_wave_barrier();
+              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+          }
+          __syncthreads();
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            const int e = threadIdx.x + r * nt, i = e / nw, j = e - i * nw;
+            if (r < per && i < n && c0 + j < nv) V[(long long)i * nv + c0 + j] = vt[(long long)j * (n + 1) + i];
+          }
+          __syncthreads();
+        }
+      }
+    }
+    const double mo = wblock_max(maxoff, red);
+    if (mo <= thr) break;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += nt) bt.eps[d.ao_off + i] = dg[i];
+  if (sweeps_out && threadIdx.x == 0) sweeps_out[si] = sweep < msw ? sweep + 1 : msw;
+}
+
+template __global__ void k_jacobi_lds<double>(DevBatch, const int*, int, double, double, double, int*, int);
+template __global__ void k_jacobi_lds<float>(DevBatch, const int*, int, double, double, double, int*, int);
+
+}  // namespace fx
