@@ -171,6 +171,7 @@ DevSystem Ctx::dev_system() const {
   s.sh_atom = d_sh_atom.p;
   s.sh_frag = d_sh_frag.p;
   s.sh_eta = d_sh_eta.p;
+  s.sh_ieta = d_sh_ieta.p;
   s.elems = d_elems.p;
   s.g = P.g;
   return s;
@@ -640,6 +641,9 @@ void Ctx::set_system(int32_t n_atoms, const int32_t* Z, const double* xyz, int32
   d_sh_atom.upload(sh_atom);
   d_sh_frag.upload(sh_frag);
   d_sh_eta.upload(sh_eta);
+  std::vector<double> sh_ieta(sh_eta.size());
+  for (size_t k = 0; k < sh_eta.size(); ++k) sh_ieta[k] = 0.5 / sh_eta[k];
+  d_sh_ieta.upload(sh_ieta);
   d_frag_atoms.upload(frag_atoms);
   d_frag_off.upload(frag_off);
   d_cn.alloc(N);

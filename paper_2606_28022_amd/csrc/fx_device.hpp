@@ -58,6 +58,7 @@ struct DevSystem {
   const int* sh_atom;     // [Nsh]
   const int* sh_frag;     // [Nsh]
   const double* sh_eta;   // [Nsh] (1 + kappa) eta_A
+  const double* sh_ieta;  // [Nsh] 1 / (2 (1 + kappa) eta_A): 1/eta_st = ieta_s + ieta_t
   const DevElem* elems;
   DevGlobals g;
 };

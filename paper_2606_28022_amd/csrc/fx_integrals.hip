@@ -240,15 +240,18 @@ __global__ void k_build_system(DevSystem sys, DevBatch bt, const int* list) {
 // One thread per target atom (all its shells); the source atoms are split
 // into `nchunk` slices handled by separate work-groups, whose partial sums
 // are combined in fixed order by k_field_reduce (deterministic).
-__global__ void k_field_partial(DevSystem sys, const double* q, int nchunk, double* part) {
-  int A = blockIdx.x * blockDim.x + threadIdx.x;
-  int chunk = blockIdx.y;
-  int N = sys.natoms;
-  int per = (N + nchunk - 1) / nchunk;
-  int b_begin = chunk * per, b_end = min(N, b_begin + per);
-  __shared__ double sx[256], sy[256], sz[256], seta[256][MAXSH_EL], sq[256][MAXSH_EL];
-  __shared__ int sf[256], sn[256];
-  double xa = 0, ya = 0, za = 0, ea[MAXSH_EL] = {1.0, 1.0};
+__global__ void __launch_bounds__(256) k_field_partial(DevSystem sys, const double* q, int nchunk, double* part) {
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  const int chunk = blockIdx.y;
+  const int N = sys.natoms;
+  const int per = (N + nchunk - 1) / nchunk;
+  const int b_begin = chunk * per, b_end = min(N, b_begin + per);
+  // source tile: position, fragment and up to two shells per atom (an absent
+  // second shell carries q = 0, so it adds exactly zero)
+  __shared__ double sx[256], sy[256], sz[256], si0[256], si1[256], sq0[256], sq1[256];
+  __shared__ int sf[256];
+  const bool kg2 = sys.g.kg == 2.0;
+  double xa = 0, ya = 0, za = 0, ia0 = 0.5, ia1 = 0.5, ea[MAXSH_EL] = {1.0, 1.0};
   int fa = -1, na = 0, sh0 = 0;
   if (A < N) {
     xa = sys.xyz[3 * A];
@@ -258,38 +261,54 @@ __global__ void k_field_partial(DevSystem sys, const double* q, int nchunk, doub
     sh0 = sys.atom_sh0[A];
     na = sys.atom_sh0[A + 1] - sh0;
     for (int k = 0; k < na; ++k) ea[k] = sys.sh_eta[sh0 + k];
+    ia0 = sys.sh_ieta[sh0];
+    ia1 = na > 1 ? sys.sh_ieta[sh0 + 1] : 0.5;
   }
-  double acc[MAXSH_EL] = {0.0, 0.0};
+  double acc0 = 0.0, acc1 = 0.0;
   for (int b0 = b_begin; b0 < b_end; b0 += 256) {
-    int b = b0 + threadIdx.x;
+    const int b = b0 + threadIdx.x;
     __syncthreads();
     if (b < b_end) {
       sx[threadIdx.x] = sys.xyz[3 * b];
       sy[threadIdx.x] = sys.xyz[3 * b + 1];
       sz[threadIdx.x] = sys.xyz[3 * b + 2];
       sf[threadIdx.x] = sys.frag[b];
-      int s0 = sys.atom_sh0[b];
-      int nsb = sys.atom_sh0[b + 1] - s0;
-      sn[threadIdx.x] = nsb;
-      for (int k = 0; k < MAXSH_EL; ++k) {
-        seta[threadIdx.x][k] = k < nsb ? sys.sh_eta[s0 + k] : 1.0;
-        sq[threadIdx.x][k] = k < nsb ? q[s0 + k] : 0.0;
-      }
+      const int s0 = sys.atom_sh0[b];
+      const int nsb = sys.atom_sh0[b + 1] - s0;
+      si0[threadIdx.x] = sys.sh_ieta[s0];
+      sq0[threadIdx.x] = q[s0];
+      si1[threadIdx.x] = nsb > 1 ? sys.sh_ieta[s0 + 1] : 0.5;
+      sq1[threadIdx.x] = nsb > 1 ? q[s0 + 1] : 0.0;
     }
     __syncthreads();
-    int nb = min(256, b_end - b0);
-    if (A < N) {
+    const int nb = min(256, b_end - b0);
+    if (A < N && kg2) {
+      // gamma = (R^2 + (1/eta_st)^2)^(-1/2)
       for (int k = 0; k < nb; ++k) {
         if (sf[k] == fa) continue;
-        double dx = xa - sx[k], dy = ya - sy[k], dz = za - sz[k];
-        double R2 = dx * dx + dy * dy + dz * dz;
-        for (int u = 0; u < na; ++u)
-          for (int v = 0; v < sn[k]; ++v) acc[u] += gamma_fn(sys.g, R2, ea[u], seta[k][v]) * sq[k][v];
+        const double dx = xa - sx[k], dy = ya - sy[k], dz = za - sz[k];
+        const double R2 = dx * dx + dy * dy + dz * dz;
+        const double t00 = ia0 + si0[k], t01 = ia0 + si1[k], t10 = ia1 + si0[k], t11 = ia1 + si1[k];
+        acc0 += rsqrt(R2 + t00 * t00) * sq0[k];
+        acc0 += rsqrt(R2 + t01 * t01) * sq1[k];
+        acc1 += rsqrt(R2 + t10 * t10) * sq0[k];
+        acc1 += rsqrt(R2 + t11 * t11) * sq1[k];
+      }
+    } else if (A < N) {
+      for (int k = 0; k < nb; ++k) {
+        if (sf[k] == fa) continue;
+        const double dx = xa - sx[k], dy = ya - sy[k], dz = za - sz[k];
+        const double R2 = dx * dx + dy * dy + dz * dz;
+        const double e0 = 0.5 / si0[k], e1 = 0.5 / si1[k];
+        acc0 += gamma_fn(sys.g, R2, ea[0], e0) * sq0[k] + gamma_fn(sys.g, R2, ea[0], e1) * sq1[k];
+        acc1 += gamma_fn(sys.g, R2, ea[1], e0) * sq0[k] + gamma_fn(sys.g, R2, ea[1], e1) * sq1[k];
       }
     }
   }
-  if (A < N)
-    for (int u = 0; u < na; ++u) part[(long long)chunk * sys.nshells + sh0 + u] = acc[u];
+  if (A < N) {
+    part[(long long)chunk * sys.nshells + sh0] = acc0;
+    if (na > 1) part[(long long)chunk * sys.nshells + sh0 + 1] = acc1;
+  }
 }
 
 __global__ void k_field_reduce(int nshells, int nchunk, const double* part, double* phi) {
