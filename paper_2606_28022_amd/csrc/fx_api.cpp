@@ -328,6 +328,24 @@ void Ctx::init_device() {
   if (verbose) std::fprintf(stderr, "[fx] LDS per workgroup %d B, static %u B\n", v, stat);
 }
 
+// Batched n x n products of the listed systems (first nl entries of dlist):
+// the matrix-core kernel once a system spans more than one 32 x 32 tile.
+void Ctx::gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlist, int mode, const double* A,
+                     const double* B, double* C, const double* w) {
+  if (nl <= 0) return;
+  if (b.max_nao <= 32) {
+    hipLaunchKernelGGL(k_gemm, dim3(1, nl), dim3(256), 0, stream, db, dlist, mode, A, B, C, w);
+  } else {
+    const int nt = (b.max_nao + 63) / 64;
+    const long long tiles = (long long)nl * nt * nt;
+    const long long grid = (tiles + 7) / 8 * 8;
+    if (grid > 0x7fffffffLL) throw FxError(FX_E_INVALID, "batched product grid too large");
+    hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)grid), dim3(256), 0, stream, db, dlist, nl, nt * nt, mode, A, B, C,
+                       w);
+  }
+  check(hipGetLastError(), "batched product");
+}
+
 // Eigensolver for a batch whose largest system has n AOs: the LDS-resident
 // kernel with an FP64 working matrix if it fits with a rotation log of at
 // least 4 steps, else with an FP32 working matrix, else the global-memory
@@ -379,13 +397,10 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     if (b.init_from_mono && mb.nsys > 0) {
       // C0 = blockdiag(monomer C); G = C0^T S C0 = L L^T; C = C0 L^-T
       hipLaunchKernelGGL(k_cluster_init_ct, dim3(nl), dim3(256), 0, stream, db, b.d_list.p, mb.dev());
-      hipLaunchKernelGGL(k_gemm, dim3(nt * nt, nl), dim3(256), 0, stream, db, b.d_list.p, 0, b.Ct.p, b.S.p, b.Tm.p,
-                         (const double*)nullptr);
-      hipLaunchKernelGGL(k_gemm, dim3(nt * nt, nl), dim3(256), 0, stream, db, b.d_list.p, 1, b.Tm.p, b.Ct.p, b.Fm.p,
-                         (const double*)nullptr);
+      gemm_batch(b, db, (int)nl, b.d_list.p, 0, b.Ct.p, b.S.p, b.Tm.p, (const double*)nullptr);
+      gemm_batch(b, db, (int)nl, b.d_list.p, 1, b.Tm.p, b.Ct.p, b.Fm.p, (const double*)nullptr);
       hipLaunchKernelGGL(k_cholinv, dim3(nl), dim3(256), 0, stream, db, b.d_list.p, b.Fm.p, b.Tm.p, b.Pm.p);
-      hipLaunchKernelGGL(k_gemm, dim3(nt * nt, nl), dim3(256), 0, stream, db, b.d_list.p, 0, b.Pm.p, b.Ct.p, b.Tm.p,
-                         (const double*)nullptr);
+      gemm_batch(b, db, (int)nl, b.d_list.p, 0, b.Pm.p, b.Ct.p, b.Tm.p, (const double*)nullptr);
       check(hipMemcpyAsync(b.Ct.p, b.Tm.p, sizeof(double) * b.tot_mat, hipMemcpyDeviceToDevice, stream), "copy");
     } else {
       hipLaunchKernelGGL(k_cholinv, dim3(nl), dim3(256), 0, stream, db, b.d_list.p, b.S.p, b.Tm.p, b.Ct.p);
@@ -409,7 +424,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
   auto gemm = [&](const std::vector<int>& l, const int* dl, int mode, const double* A, const double* B, double* C,
                   const double* w) {
     int ev = timers.begin(stream);
-    hipLaunchKernelGGL(k_gemm, dim3(nt * nt, (unsigned)l.size()), dim3(256), 0, stream, db, dl, mode, A, B, C, w);
+    gemm_batch(b, db, (int)l.size(), dl, mode, A, B, C, w);
     timers.end(stream, ev, &t_gemm, gemm_gflop(l));
   };
   for (int it = 0; it < opt.max_iter + 1 && !active.empty(); ++it) {

@@ -225,6 +225,8 @@ struct Ctx {
   void build_matrices(Batch& b);
   void init_device();
   JacobiPlan jacobi_plan(int n) const;
+  void gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlist, int mode, const double* A,
+                  const double* B, double* C, const double* w);
   int run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* iters_out);
   int solve_batch(Batch& b, bool cold, long long* iters_out);
   void run(fx_result* out);

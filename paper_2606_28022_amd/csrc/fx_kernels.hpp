@@ -23,6 +23,8 @@ __global__ void k_reset_state(DevBatch bt, const int* list, int nl);
 __global__ void k_cholinv(DevBatch bt, const int* list, const double* Apool, double* Lpool, double* Xpool);
 __global__ void k_cluster_init_ct(DevBatch bt, const int* list, DevBatch mono);
 __global__ void k_fock(DevSystem sys, DevBatch bt, const int* list);
+__global__ void k_gemm_mfma(DevBatch bt, const int* list, int nl, int tiles_per_sys, int mode, const double* A,
+                            const double* B, double* C, const double* w);
 __global__ void k_gemm(DevBatch bt, const int* list, int mode, const double* A, const double* B, double* C,
                        const double* w);
 __global__ void k_jacobi(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale,

@@ -233,6 +233,94 @@ __global__ void k_gemm(DevBatch bt, const int* list, int mode, const double* Aba
 }
 
 // ---------------------------------------------------------------------------
+// The same batched products on the FP64 matrix cores.  64 x 64 output tile
+// per work-group of four waves, each wave a 32 x 32 quadrant built from 2 x 2
+// v_mfma_f64_16x16x4 blocks; K staged through LDS 32 at a time.  Lane layout
+// of the 16x16x4 FP64 instruction: A[i][k] and B[k][j] from lane i + 16 k
+// (resp. j + 16 k); output element r of lane l is D[l / 16 + 4 r][l % 16].
+// Work-groups are numbered so that all tiles of one system share an XCD (the
+// dispatcher deals consecutive work-group ids to the 8 XCDs in turn), which
+// keeps each system's operand panels in one L2.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256)
+    k_gemm_mfma(DevBatch bt, const int* list, int nl, int tiles_per_sys, int mode, const double* __restrict__ Abase,
+                const double* __restrict__ Bbase, double* __restrict__ Cbase, const double* __restrict__ wbase) {
+  const int L = blockIdx.x, G = gridDim.x;  // G is a multiple of 8
+  const int logical = (L & 7) * (G >> 3) + (L >> 3);
+  const int sl = logical / tiles_per_sys, tile = logical - sl * tiles_per_sys;
+  if (sl >= nl) return;
+  const int si = list[sl];
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao;
+  const int nt = (n + 63) / 64;
+  if (tile >= nt * nt) return;
+  const int ti = tile / nt, tj = tile - ti * nt;
+  const double* A = Abase + d.mat_off;
+  const double* B = Bbase + d.mat_off;
+  double* C = Cbase + d.mat_off;
+  const double* w = wbase ? wbase + d.ao_off : nullptr;
+  constexpr int KS = 32, LD = 66;
+  __shared__ double As[KS][LD];  // [k][i]
+  __shared__ double Bs[KS][LD];  // [k][j]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int i0 = ti * 64, j0 = tj * 64;
+  v4d acc[2][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc[u][v] = (v4d){0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < n; k0 += KS) {
+    // stage A (as [k][i]) and B (as [k][j]); 2048 elements each, 8 per thread
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      const int e = threadIdx.x + 256 * h;
+      if (mode == 2) {
+        const int k = e >> 6, i = e & 63;  // A^T diag(w): rows of A are k
+        const int gk = k0 + k, gi = i0 + i;
+        As[k][i] = (gk < n && gi < n) ? A[(long long)gk * n + gi] * (w ? w[gk] : 1.0) : 0.0;
+      } else {
+        const int i = e >> 5, k = e & 31;
+        const int gi = i0 + i, gk = k0 + k;
+        As[k][i] = (gi < n && gk < n) ? A[(long long)gi * n + gk] : 0.0;
+      }
+      if (mode == 1) {
+        const int j = e >> 5, k = e & 31;  // B^T: rows of B are j
+        const int gj = j0 + j, gk = k0 + k;
+        Bs[k][j] = (gj < n && gk < n) ? B[(long long)gj * n + gk] : 0.0;
+      } else {
+        const int k = e >> 6, j = e & 63;
+        const int gk = k0 + k, gj = j0 + j;
+        Bs[k][j] = (gk < n && gj < n) ? B[(long long)gk * n + gj] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KS; kk += 4) {
+      const int kr = kk + (lane >> 4), c = lane & 15;
+      const double a0 = As[kr][wi * 32 + c], a1 = As[kr][wi * 32 + 16 + c];
+      const double b0 = Bs[kr][wj * 32 + c], b1 = Bs[kr][wj * 32 + 16 + c];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = i0 + wi * 32 + u * 16 + (lane >> 4) + 4 * r;
+        const int gj = j0 + wj * 32 + v * 16 + (lane & 15);
+        if (gi < n && gj < n) C[(long long)gi * n + gj] = acc[u][v][r];
+      }
+}
+
+// ---------------------------------------------------------------------------
 // Parallel cyclic Jacobi on the symmetric matrix A (in place), rotating the
 // rows of V.  Round-robin ordering: every step applies n/2 disjoint
 // rotations; each 2 x 2 block (pair k, pair l) is updated as J_k^T B J_l in
