@@ -87,6 +87,21 @@ typedef struct fx_counts {
   int32_t n_fragments;
 } fx_counts;
 
+/* Event-timed statistics of one kernel over a fx_run call: summed device
+ * time of its launches (HIP events recorded on the context stream around each
+ * launch), launch count and algorithmic work in GFLOP:
+ *   fx::k_jacobi_lds<float|double>, fx::k_jacobi   6 n^2 (n - 1) per sweep
+ *   fx::k_gemm_mfma, fx::k_gemm                      2 n^3 per product
+ *   fx::k_field_partial      8 per inter-fragment shell pair (one rsqrt,
+ *                            the distance shared by an atom pair's shells) */
+#define FX_MAX_KSTAT 8
+typedef struct fx_kernel_stat {
+  char name[48];          /* kernel name as rocprofv3 prints it, without arguments */
+  double ms;
+  int64_t launches;
+  double gflop;
+} fx_kernel_stat;
+
 typedef struct fx_result {
   double e_total;         /* FMO2 or FMO3 energy */
   double e_fmo2;          /* FMO2 part of it */
@@ -95,16 +110,9 @@ typedef struct fx_result {
   int64_t solves_mono, solves_dimer, solves_trimer;  /* fragment SCC solves */
   int64_t iters_mono, iters_dimer, iters_trimer;     /* SCC iterations, summed */
   double ms_lists, ms_monomer, ms_dimer, ms_trimer, ms_energy, ms_gradient, ms_response;
-  /* the batched Jacobi eigensolver kernel: summed device time of its launches
-   * (HIP events on the context stream), launch count, and algorithmic work
-   * (6 n^2 (n - 1) flop per sweep of an n x n matrix, summed over systems) */
-  double ms_jacobi;
-  int64_t jacobi_launches;
-  double gflop_jacobi;
-  /* the batched dense FP64 products of the SCC iterations (2 n^3 flop each) */
-  double ms_gemm;
-  int64_t gemm_launches;
-  double gflop_gemm;
+  /* device time of the hot kernels, largest first (see fx_kernel_stat) */
+  int32_t n_kstat;
+  fx_kernel_stat kstat[FX_MAX_KSTAT];
 } fx_result;
 
 /* Load element constants and STO-nG basis expansions from a JSON file.

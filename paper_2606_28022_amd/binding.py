@@ -36,18 +36,28 @@ class fx_counts(C.Structure):
                 ("n_shells", C.c_int32), ("n_fragments", C.c_int32)]
 
 
+FX_MAX_KSTAT = 8
+
+
+class fx_kernel_stat(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("ms", C.c_double), ("launches", C.c_int64), ("gflop", C.c_double)]
+
+
 class fx_result(C.Structure):
     _fields_ = [("e_total", C.c_double), ("e_fmo2", C.c_double), ("converged", C.c_int32),
                 ("macro_iter", C.c_int32), ("solves_mono", C.c_int64), ("solves_dimer", C.c_int64),
                 ("solves_trimer", C.c_int64), ("iters_mono", C.c_int64), ("iters_dimer", C.c_int64),
                 ("iters_trimer", C.c_int64), ("ms_lists", C.c_double), ("ms_monomer", C.c_double),
                 ("ms_dimer", C.c_double), ("ms_trimer", C.c_double), ("ms_energy", C.c_double),
-                ("ms_gradient", C.c_double), ("ms_response", C.c_double), ("ms_jacobi", C.c_double),
-                ("jacobi_launches", C.c_int64), ("gflop_jacobi", C.c_double), ("ms_gemm", C.c_double),
-                ("gemm_launches", C.c_int64), ("gflop_gemm", C.c_double)]
+                ("ms_gradient", C.c_double), ("ms_response", C.c_double), ("n_kstat", C.c_int32),
+                ("kstat", fx_kernel_stat * FX_MAX_KSTAT)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("kstat", "n_kstat")}
+        d["kernels"] = [{"name": self.kstat[i].name.decode(), "ms": self.kstat[i].ms,
+                         "launches": self.kstat[i].launches, "gflop": self.kstat[i].gflop}
+                        for i in range(self.n_kstat)]
+        return d
 
 
 EXPORTS = ["fx_params_load", "fx_params_free", "fx_ctx_create", "fx_ctx_destroy", "fx_last_error",

@@ -331,17 +331,21 @@ void Ctx::init_device() {
 // Batched n x n products of the listed systems (first nl entries of dlist):
 // the matrix-core kernel once a system spans more than one 32 x 32 tile.
 void Ctx::gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlist, int mode, const double* A,
-                     const double* B, double* C, const double* w) {
+                     const double* B, double* C, const double* w, double gflop) {
   if (nl <= 0) return;
   if (b.max_nao <= 32) {
+    const int ev = timers.begin(stream);
     hipLaunchKernelGGL(k_gemm, dim3(1, nl), dim3(256), 0, stream, db, dlist, mode, A, B, C, w);
+    timers.end(stream, ev, kt("fx::k_gemm"), gflop);
   } else {
     const int nt = (b.max_nao + 63) / 64;
     const long long tiles = (long long)nl * nt * nt;
     const long long grid = (tiles + 7) / 8 * 8;
     if (grid > 0x7fffffffLL) throw FxError(FX_E_INVALID, "batched product grid too large");
+    const int ev = timers.begin(stream);
     hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)grid), dim3(256), 0, stream, db, dlist, nl, nt * nt, mode, A, B, C,
                        w);
+    timers.end(stream, ev, kt("fx::k_gemm_mfma"), gflop);
   }
   check(hipGetLastError(), "batched product");
 }
@@ -397,10 +401,10 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     if (b.init_from_mono && mb.nsys > 0) {
       // C0 = blockdiag(monomer C); G = C0^T S C0 = L L^T; C = C0 L^-T
       hipLaunchKernelGGL(k_cluster_init_ct, dim3(nl), dim3(256), 0, stream, db, b.d_list.p, mb.dev());
-      gemm_batch(b, db, (int)nl, b.d_list.p, 0, b.Ct.p, b.S.p, b.Tm.p, (const double*)nullptr);
-      gemm_batch(b, db, (int)nl, b.d_list.p, 1, b.Tm.p, b.Ct.p, b.Fm.p, (const double*)nullptr);
+      gemm_batch(b, db, (int)nl, b.d_list.p, 0, b.Ct.p, b.S.p, b.Tm.p, (const double*)nullptr, b.gemm_gflop(list));
+      gemm_batch(b, db, (int)nl, b.d_list.p, 1, b.Tm.p, b.Ct.p, b.Fm.p, (const double*)nullptr, b.gemm_gflop(list));
       hipLaunchKernelGGL(k_cholinv, dim3(nl), dim3(256), 0, stream, db, b.d_list.p, b.Fm.p, b.Tm.p, b.Pm.p);
-      gemm_batch(b, db, (int)nl, b.d_list.p, 0, b.Pm.p, b.Ct.p, b.Tm.p, (const double*)nullptr);
+      gemm_batch(b, db, (int)nl, b.d_list.p, 0, b.Pm.p, b.Ct.p, b.Tm.p, (const double*)nullptr, b.gemm_gflop(list));
       check(hipMemcpyAsync(b.Ct.p, b.Tm.p, sizeof(double) * b.tot_mat, hipMemcpyDeviceToDevice, stream), "copy");
     } else {
       hipLaunchKernelGGL(k_cholinv, dim3(nl), dim3(256), 0, stream, db, b.d_list.p, b.S.p, b.Tm.p, b.Ct.p);
@@ -412,21 +416,10 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
   std::vector<int> sweeps(b.nsys), status(b.nsys), niter(b.nsys);
   DevBuf<int> d_act;
   const int nt = (b.max_nao + 31) / 32;
-  // flop count of one n x n product summed over a list of systems
-  auto gemm_gflop = [&](const std::vector<int>& l) {
-    double g = 0.0;
-    for (int s : l) {
-      double n = b.h_desc[s].nao;
-      g += 2e-9 * n * n * n;
-    }
-    return g;
-  };
   auto gemm = [&](const std::vector<int>& l, const int* dl, int mode, const double* A, const double* B, double* C,
-                  const double* w) {
-    int ev = timers.begin(stream);
-    gemm_batch(b, db, (int)l.size(), dl, mode, A, B, C, w);
-    timers.end(stream, ev, &t_gemm, gemm_gflop(l));
-  };
+                  const double* w) { gemm_batch(b, db, (int)l.size(), dl, mode, A, B, C, w, b.gemm_gflop(l)); };
+  KernelTimer* kt_jac = kt(jp.elt == 8 ? "fx::k_jacobi_lds<double>" : jp.elt == 4 ? "fx::k_jacobi_lds<float>"
+                                                                                   : "fx::k_jacobi");
   for (int it = 0; it < opt.max_iter + 1 && !active.empty(); ++it) {
     d_act.upload(active);
     const int na = (int)active.size();
@@ -447,7 +440,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
       else
         hipLaunchKernelGGL(k_jacobi, dim3(na), dim3(jacobi_threads), 0, stream, db, d_act.p, jacobi_max_sweeps,
                            jacobi_tol, jacobi_thr_scale, cap, b.sweeps.p);
-      timers.end(stream, ev, &t_jacobi, 0.0);
+      timers.end(stream, ev, kt_jac, 0.0);
     }
     hipLaunchKernelGGL(k_fermi, dim3(na), dim3(256), 0, stream, ds, db, d_act.p);
     gemm(active, d_act.p, 2, b.Ct.p, b.Ct.p, b.Pm.p, b.occ.p);
@@ -464,7 +457,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     // 6 n^2 flop per step times (n - 1) steps
     for (int s : active) {
       double n = b.h_desc[s].nao;
-      t_jacobi.gflop += 1e-9 * 6.0 * n * n * (n - 1.0) * (double)sweeps[s];
+      kt_jac->gflop += 1e-9 * 6.0 * n * n * (n - 1.0) * (double)sweeps[s];
     }
     std::vector<int> next;
     for (int s : active)
@@ -514,7 +507,9 @@ void Ctx::field(const double* d_q, double* d_phi) {
   const int nchunk = std::max(1, std::min(64, (N + 255) / 256 > 0 ? 2048 / ((N + 255) / 256) : 1));
   if ((long long)nchunk * Nsh > field_part.n) field_part.alloc((long long)nchunk * Nsh);
   dim3 grid((N + 255) / 256, nchunk);
+  const int ev = timers.begin(stream);
   hipLaunchKernelGGL(k_field_partial, grid, dim3(256), 0, stream, dev_system(), d_q, nchunk, field_part.p);
+  timers.end(stream, ev, kt("fx::k_field_partial"), 8e-9 * field_pairs);
   hipLaunchKernelGGL(k_field_reduce, dim3((Nsh + 255) / 256), dim3(256), 0, stream, Nsh, nchunk, field_part.p,
                      d_phi);
   check(hipGetLastError(), "field");
@@ -649,6 +644,12 @@ void Ctx::set_system(int32_t n_atoms, const int32_t* Z, const double* xyz, int32
     atom_sh0_g[A + 1] = (int)sh_atom.size();
   }
   Nsh = (int)sh_atom.size();
+  {
+    std::vector<double> nsh_f(F, 0.0);
+    for (int A = 0; A < N; ++A) nsh_f[frag[A]] += atom_sh0_g[A + 1] - atom_sh0_g[A];
+    field_pairs = (double)Nsh * Nsh;
+    for (double v : nsh_f) field_pairs -= v * v;
+  }
   d_xyz.upload(xyz_h);
   d_elem.upload(elem);
   d_frag.upload(frag);
@@ -679,8 +680,7 @@ void Ctx::run(fx_result* out) {
   if (!has_system) throw FxError(FX_E_STATE, "no system set");
   if (opt.precision != FX_FP64) throw FxError(FX_E_UNSUPPORTED, "only FX_FP64 is available");
   std::memset(&res, 0, sizeof(res));
-  t_jacobi.reset();
-  t_gemm.reset();
+  ktimers.clear();
   bool all_conv = true;
   double t0 = now_ms();
   if (!lists_built) build_lists_impl();
@@ -893,12 +893,20 @@ void Ctx::run(fx_result* out) {
     has_grad = true;
   }
   res.ms_gradient = now_ms() - t5;
-  res.ms_jacobi = t_jacobi.ms;
-  res.jacobi_launches = t_jacobi.launches;
-  res.gflop_jacobi = t_jacobi.gflop;
-  res.ms_gemm = t_gemm.ms;
-  res.gemm_launches = t_gemm.launches;
-  res.gflop_gemm = t_gemm.gflop;
+  {
+    sync();
+    timers.resolve();
+    std::vector<const KernelTimer*> ks;
+    for (const auto& t : ktimers) ks.push_back(&t);
+    std::stable_sort(ks.begin(), ks.end(), [](const KernelTimer* a, const KernelTimer* b) { return a->ms > b->ms; });
+    res.n_kstat = (int)std::min<size_t>(ks.size(), FX_MAX_KSTAT);
+    for (int k = 0; k < res.n_kstat; ++k) {
+      std::snprintf(res.kstat[k].name, sizeof(res.kstat[k].name), "%s", ks[k]->name.c_str());
+      res.kstat[k].ms = ks[k]->ms;
+      res.kstat[k].launches = ks[k]->launches;
+      res.kstat[k].gflop = ks[k]->gflop;
+    }
+  }
   if (out) *out = res;
 }
 

@@ -59,7 +59,7 @@ void explicit_terms(Ctx& c, Batch& b, const double* wsys, DevBuf<double>& g_sys,
   for (int k = 0; k < b.nsys; ++k) all[k] = k;
   b.d_list.upload(all);
   // W = C diag(n eps) C^T into T, D_S into F
-  c.gemm_batch(b, db, (int)b.nsys, b.d_list.p, 2, b.Ct.p, b.Ct.p, b.Tm.p, (const double*)wvec.p);
+  c.gemm_batch(b, db, (int)b.nsys, b.d_list.p, 2, b.Ct.p, b.Ct.p, b.Tm.p, (const double*)wvec.p, b.gemm_gflop_all());
   hipLaunchKernelGGL(k_make_DS, dim3(b.nsys), dim3(256), 0, c.stream, db, b.Pm.p, b.Tm.p, b.Fm.p);
   int natot = 0;
   for (auto& d : b.h_desc) natot += d.nat;
@@ -176,7 +176,7 @@ void Ctx::gradient() {
     const int nt = (b.max_nao + 31) / 32;
     hipLaunchKernelGGL(k_mo_order, dim3(b.nsys), dim3(256), 0, stream, dmb, d_nocc.p, order.p);
     // (SC)^T = Ct S into G1
-    gemm_batch(b, dmb, (int)b.nsys, b.d_list.p, 0, b.Ct.p, b.S.p, G1.p, (const double*)nullptr);
+    gemm_batch(b, dmb, (int)b.nsys, b.d_list.p, 0, b.Ct.p, b.S.p, G1.p, (const double*)nullptr, b.gemm_gflop_all());
     hipLaunchKernelGGL(k_resp_Q, dim3(b.nsys), dim3(256), 0, stream, ds, dmb, G1.p, order.p, d_nocc.p, d_qoff.p,
                        Q.p);
     hipLaunchKernelGGL(k_resp_M, dim3(b.nsys), dim3(256), 0, stream, dmb, order.p, d_nocc.p, d_qoff.p, Q.p, M.p);
@@ -237,14 +237,14 @@ void Ctx::gradient() {
     hipLaunchKernelGGL(k_resp_Z, dim3(b.nsys), dim3(256), 0, stream, dmb, order.p, d_nocc.p, d_qoff.p, Q.p, w.p,
                        G2.p, G3.p);
     // Zt = Ct^T (Zm Ct) -> G1 ; WZ = Ct^T (Ze Ct) -> G2
-    gemm_batch(b, dmb, (int)b.nsys, b.d_list.p, 0, G2.p, b.Ct.p, b.Tm.p, (const double*)nullptr);
-    gemm_batch(b, dmb, (int)b.nsys, b.d_list.p, 2, b.Ct.p, b.Tm.p, G1.p, (const double*)nullptr);
-    gemm_batch(b, dmb, (int)b.nsys, b.d_list.p, 0, G3.p, b.Ct.p, b.Tm.p, (const double*)nullptr);
-    gemm_batch(b, dmb, (int)b.nsys, b.d_list.p, 2, b.Ct.p, b.Tm.p, G2.p, (const double*)nullptr);
+    gemm_batch(b, dmb, (int)b.nsys, b.d_list.p, 0, G2.p, b.Ct.p, b.Tm.p, (const double*)nullptr, b.gemm_gflop_all());
+    gemm_batch(b, dmb, (int)b.nsys, b.d_list.p, 2, b.Ct.p, b.Tm.p, G1.p, (const double*)nullptr, b.gemm_gflop_all());
+    gemm_batch(b, dmb, (int)b.nsys, b.d_list.p, 0, G3.p, b.Ct.p, b.Tm.p, (const double*)nullptr, b.gemm_gflop_all());
+    gemm_batch(b, dmb, (int)b.nsys, b.d_list.p, 2, b.Ct.p, b.Tm.p, G2.p, (const double*)nullptr, b.gemm_gflop_all());
     // X2 = P S (D_w P) -> G3
     hipLaunchKernelGGL(k_rowscale, dim3(b.nsys), dim3(256), 0, stream, dmb, w.p, b.Pm.p, b.Fm.p);
-    gemm_batch(b, dmb, (int)b.nsys, b.d_list.p, 0, b.S.p, b.Fm.p, b.Tm.p, (const double*)nullptr);
-    gemm_batch(b, dmb, (int)b.nsys, b.d_list.p, 0, b.Pm.p, b.Tm.p, G3.p, (const double*)nullptr);
+    gemm_batch(b, dmb, (int)b.nsys, b.d_list.p, 0, b.S.p, b.Fm.p, b.Tm.p, (const double*)nullptr, b.gemm_gflop_all());
+    gemm_batch(b, dmb, (int)b.nsys, b.d_list.p, 0, b.Pm.p, b.Tm.p, G3.p, (const double*)nullptr, b.gemm_gflop_all());
     hipLaunchKernelGGL(k_sym_inplace, dim3(b.nsys), dim3(256), 0, stream, dmb, G1.p);
     hipLaunchKernelGGL(k_resp_DS, dim3(b.nsys), dim3(256), 0, stream, dmb, G1.p, G2.p, G3.p, w.p, b.Fm.p, gx.p);
     hipLaunchKernelGGL(k_grad_contract, dim3(b.nsys), dim3(256), 0, stream, ds, dmb, b.d_list.p, G1.p, b.Fm.p, gx.p,

@@ -5,7 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <cmath>
 #include <cstdlib>
+#include <deque>
 #include <map>
 #include <stdexcept>
 #include <string>
@@ -113,10 +115,22 @@ struct Batch {
   DevBuf<double> erep, e_int, e_prev, mts, err;
   DevBuf<int> status, niter, nhist, sweeps;
   DevBatch dev();
+  // algorithmic work of one n x n product (2 n^3) summed over listed systems
+  double gemm_gflop(const std::vector<int>& l) const {
+    double g = 0.0;
+    for (int s : l) g += 2e-9 * std::pow((double)h_desc[s].nao, 3);
+    return g;
+  }
+  double gemm_gflop_all() const {
+    double g = 0.0;
+    for (const auto& d : h_desc) g += 2e-9 * std::pow((double)d.nao, 3);
+    return g;
+  }
 };
 
 // Event-timed accumulation of one kernel's launches on the context stream.
 struct KernelTimer {
+  std::string name;
   double ms = 0.0;
   long long launches = 0;
   double gflop = 0.0;
@@ -159,6 +173,7 @@ struct Ctx {
   // supersystem
   bool has_system = false, lists_built = false, has_result = false, has_grad = false;
   int N = 0, F = 0, Nsh = 0;
+  double field_pairs = 0.0;  // inter-fragment shell pairs of one field pass
   std::vector<int> elem, frag, frag_charge, frag_off, frag_atoms, atom_sh0_g;
   std::vector<double> xyz_h, guess;
   DevBuf<DevElem> d_elems;
@@ -173,7 +188,14 @@ struct Ctx {
   DevBuf<double> e_mono, dE_scc, dEV_scc, dE_esd, dE_tri, ddq_scc;
   std::vector<double> trimer_dEIJK;
   fx_result res{};
-  KernelTimer t_jacobi, t_gemm;
+  std::deque<KernelTimer> ktimers;  // stable addresses
+  KernelTimer* kt(const char* name) {
+    for (auto& t : ktimers)
+      if (t.name == name) return &t;
+    ktimers.emplace_back();
+    ktimers.back().name = name;
+    return &ktimers.back();
+  }
   // pool of HIP event pairs around kernel launches, resolved after a sync
   struct EventPool {
     std::vector<hipEvent_t> ev0, ev1;
@@ -226,7 +248,7 @@ struct Ctx {
   void init_device();
   JacobiPlan jacobi_plan(int n) const;
   void gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlist, int mode, const double* A,
-                  const double* B, double* C, const double* w);
+                  const double* B, double* C, const double* w, double gflop);
   int run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* iters_out);
   int solve_batch(Batch& b, bool cold, long long* iters_out);
   void run(fx_result* out);

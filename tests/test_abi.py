@@ -40,3 +40,31 @@ def test_library_exports_every_declared_symbol():
 def test_binding_names_match_header():
     from paper_2606_28022_amd import binding
     assert sorted(binding.EXPORTS) == declared()
+
+
+def test_struct_layouts_match_binding(tmp_path):
+    """sizeof and field offsets of the ABI structs, compiled from the header
+    with the host C compiler, equal those of the ctypes mirrors."""
+    from paper_2606_28022_amd import binding as B
+    structs = {"fx_options": B.fx_options, "fx_counts": B.fx_counts, "fx_result": B.fx_result,
+               "fx_kernel_stat": B.fx_kernel_stat}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fmoxtb.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("  return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line.strip():
+            parts = line.split()
+            got[(parts[0], parts[1])] = int(parts[2])
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got[(name, f)] == getattr(cls, f).offset, (name, f)
