@@ -235,6 +235,8 @@ void Ctx::build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters,
   b.tot_sh = sh_off;
   b.tot_ao = ao_off;
   b.tot_mat = mat;
+  b.tot_gam = gam;
+  b.has_pre = false;
   b.d_desc.upload(desc);
   b.d_atoms.upload(atoms);
   b.d_atom_ao0.upload(atom_ao0);
@@ -293,6 +295,7 @@ DevBatch Batch::dev() {
   d.q_out = q_out.p;
   d.phi = phi.p;
   d.sig = sig.p;
+  d.pre = has_pre ? pre.p : nullptr;
   d.hx = hx.p;
   d.hr = hr.p;
   d.eps = eps.p;
@@ -324,6 +327,8 @@ void Ctx::init_device() {
   for (const void* k : {reinterpret_cast<const void*>(k_jacobi_lds<double>),
                         reinterpret_cast<const void*>(k_jacobi_lds<float>)})
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_precond_build),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_max - 16384);
   (void)hipGetLastError();
   if (verbose) std::fprintf(stderr, "[fx] LDS per workgroup %d B, static %u B\n", v, stat);
 }
@@ -348,6 +353,68 @@ void Ctx::gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlis
     timers.end(stream, ev, kt("fx::k_gemm_mfma"), gflop);
   }
   check(hipGetLastError(), "batched product");
+}
+
+// Charge susceptibilities of the monomers from their current orbitals
+// (shell-summed transition charges Q and M = sum_ai Q Q^T / (eps_a - eps_i));
+// closed-shell monomers only (returns false otherwise).
+bool Ctx::monomer_response_setup() {
+  resp_ok = false;
+  Batch& b = mb;
+  if (b.nsys == 0) return false;
+  std::vector<int> nocc(b.nsys);
+  std::vector<long long> qoff(b.nsys + 1, 0);
+  for (int k = 0; k < b.nsys; ++k) {
+    const SysDesc& d = b.h_desc[k];
+    const int ne = (int)std::lround(d.nel);
+    if (std::fabs(d.nel - ne) > 1e-9 || (ne & 1) || ne / 2 >= d.nao || ne <= 0) return false;
+    nocc[k] = ne / 2;
+    qoff[k + 1] = qoff[k] + (long long)d.nsh * nocc[k] * (d.nao - nocc[k]);
+  }
+  DevBatch dmb = b.dev();
+  resp_nocc.upload(nocc);
+  resp_qoff.upload(qoff);
+  resp_order.alloc(b.tot_ao);
+  resp_Q.alloc(std::max(1LL, qoff[b.nsys]));
+  resp_M.alloc(std::max(1LL, b.tot_gam));
+  std::vector<int> all(b.nsys);
+  for (int k = 0; k < b.nsys; ++k) all[k] = k;
+  b.d_list.upload(all);
+  hipLaunchKernelGGL(k_mo_order, dim3(b.nsys), dim3(256), 0, stream, dmb, resp_nocc.p, resp_order.p);
+  // (S C)^T = Ct S into the GEMM scratch
+  gemm_batch(b, dmb, b.nsys, b.d_list.p, 0, b.Ct.p, b.S.p, b.Tm.p, (const double*)nullptr, b.gemm_gflop_all());
+  hipLaunchKernelGGL(k_resp_Q, dim3(b.nsys), dim3(256), 0, stream, dev_system(), dmb, b.Tm.p, resp_order.p,
+                     resp_nocc.p, resp_qoff.p, resp_Q.p);
+  hipLaunchKernelGGL(k_resp_M, dim3(b.nsys), dim3(256), 0, stream, dmb, resp_order.p, resp_nocc.p, resp_qoff.p,
+                     resp_Q.p, resp_M.p);
+  check(hipGetLastError(), "monomer susceptibilities");
+  resp_ok = true;
+  return true;
+}
+
+// Newton preconditioners of the mixer for every system of the batch, from
+// the monomer susceptibilities and the systems' current input charges.
+void Ctx::build_precond(Batch& b) {
+  b.has_pre = false;
+  if (!precond || !resp_ok || b.nsys == 0) return;
+  int nsmax = 0;
+  for (const auto& d : b.h_desc) nsmax = std::max(nsmax, d.nsh);
+  const unsigned bytes = (unsigned)nsmax * (unsigned)nsmax * 4u;
+  if ((int)bytes > lds_max - 16384 || nsmax > MAXN) return;
+  b.pre.alloc(std::max(1LL, b.tot_gam));
+  DevBuf<int> ok;
+  ok.alloc(b.nsys);
+  DevBatch db = b.dev();
+  hipLaunchKernelGGL(k_precond_build, dim3(b.nsys), dim3(256), bytes, stream, dev_system(), db, b.d_all.p, mb.dev(),
+                     (const double*)resp_M.p, b.pre.p, ok.p);
+  check(hipGetLastError(), "k_precond_build");
+  std::vector<int> h;
+  ok.download(h, stream);
+  sync();
+  int bad = 0;
+  for (int v : h) bad += v == 0;
+  if (verbose) std::fprintf(stderr, "[fx] mixing preconditioner for %d systems (%d singular)\n", b.nsys, bad);
+  b.has_pre = true;
 }
 
 // Eigensolver for a batch whose largest system has n AOs: the LDS-resident
@@ -386,7 +453,9 @@ void Ctx::build_matrices(Batch& b) {
 // initial charges; `cold` builds the first basis from the Cholesky factor of S,
 // otherwise the eigenvectors of the previous solve are reused.
 // Returns the number of systems that failed to converge.
-int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* iters_out) {
+// single: exactly one iteration (no mixing, no convergence test), used by
+// the fused monomer loop; the previous residual is kept for the eigensolver.
+int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* iters_out, bool single) {
   if (list.empty()) return 0;
   const double t_start = now_ms();
   DevBatch db = b.dev();
@@ -394,7 +463,8 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
   const int nl = (int)list.size();
   // reset per-system iteration state on the device
   b.d_list.upload(list);
-  hipLaunchKernelGGL(k_reset_state, dim3((nl + 255) / 256), dim3(256), 0, stream, db, b.d_list.p, nl);
+  hipLaunchKernelGGL(k_reset_state, dim3((nl + 255) / 256), dim3(256), 0, stream, db, b.d_list.p, nl,
+                     single ? 1 : 0);
   check(hipGetLastError(), "k_reset_state");
   if (cold) {
     const int nt = (b.max_nao + 31) / 32;
@@ -420,7 +490,8 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
                   const double* w) { gemm_batch(b, db, (int)l.size(), dl, mode, A, B, C, w, b.gemm_gflop(l)); };
   KernelTimer* kt_jac = kt(jp.elt == 8 ? "fx::k_jacobi_lds<double>" : jp.elt == 4 ? "fx::k_jacobi_lds<float>"
                                                                                    : "fx::k_jacobi");
-  for (int it = 0; it < opt.max_iter + 1 && !active.empty(); ++it) {
+  const int max_it = single ? 1 : opt.max_iter + 1;
+  for (int it = 0; it < max_it && !active.empty(); ++it) {
     d_act.upload(active);
     const int na = (int)active.size();
     hipLaunchKernelGGL(k_fock, dim3(na), dim3(256), 0, stream, ds, db, d_act.p);
@@ -446,7 +517,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     gemm(active, d_act.p, 2, b.Ct.p, b.Ct.p, b.Pm.p, b.occ.p);
     hipLaunchKernelGGL(k_charges_mix, dim3(na), dim3(256), 0, stream, ds, db, d_act.p,
                        scc_tol_cur > 0 ? scc_tol_cur : opt.scc_tol, etol_cur > 0 ? etol_cur : opt.energy_tol,
-                       opt.max_iter, mix_beta);
+                       single ? 1 : opt.max_iter, b.has_pre ? precond_beta : mix_beta);
     check(hipGetLastError(), "scc iteration");
     b.status.download(status, stream);
     b.sweeps.download(sweeps, stream);
@@ -487,7 +558,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     iters += niter[s];
   }
   if (iters_out) *iters_out += iters;
-  return failed;
+  return single ? 0 : failed;
 }
 
 // solve a batch either all at once or one system at a time
@@ -711,19 +782,34 @@ void Ctx::run(fx_result* out) {
   std::vector<int> slots;
   int next_slot = 0;
   const unsigned gN = (unsigned)((Nsh + 255) / 256);
+  mono_tmp.alloc(Nsh);
+  DevBuf<double> d_tmp_local;
+  d_tmp_local.alloc(mb.tot_sh);
+  std::vector<int> all_mono(mb.nsys);
+  for (int k = 0; k < mb.nsys; ++k) all_mono[k] = k;
+  bool fused_mode = false;
   for (macro = 1; macro <= opt.max_macro; ++macro) {
     field(d_q.p, d_phi.p);
     hipLaunchKernelGGL(k_gather_shell, dim3(mb.nsys), dim3(64), 0, stream, dmb, d_phi.p, mb.phi.p);
-    if (cold)
+    int failed = 0;
+    if (fused_mode) {
+      // one SCC iteration of every monomer at the globally mixed charges
       hipLaunchKernelGGL(k_gather_shell, dim3(mb.nsys), dim3(64), 0, stream, dmb, d_q.p, mb.q_in.p);
-    else
-      check(hipMemcpyAsync(mb.q_in.p, mb.q_out.p, sizeof(double) * mb.tot_sh, hipMemcpyDeviceToDevice, stream),
-            "copy");
-    // inner solves only as tight as the outer residual requires
-    scc_tol_cur = std::max(opt.scc_tol, std::min(1e-4, 1e-3 * delta));
-    etol_cur = std::max(opt.energy_tol, std::min(1e-4, 1e-4 * delta));
-    int failed = solve_batch(mb, cold, &it_mono);
-    scc_tol_cur = etol_cur = -1.0;
+      run_scc(mb, all_mono, false, &it_mono, true);
+    } else {
+      if (cold)
+        hipLaunchKernelGGL(k_gather_shell, dim3(mb.nsys), dim3(64), 0, stream, dmb, d_q.p, mb.q_in.p);
+      else
+        check(hipMemcpyAsync(mb.q_in.p, mb.q_out.p, sizeof(double) * mb.tot_sh, hipMemcpyDeviceToDevice, stream),
+              "copy");
+      // inner solves only as tight as the outer residual requires
+      scc_tol_cur = std::max(opt.scc_tol, std::min(1e-4, 1e-3 * delta));
+      etol_cur = std::max(opt.energy_tol, std::min(1e-4, 1e-4 * delta));
+      failed = solve_batch(mb, cold, &it_mono);
+      scc_tol_cur = etol_cur = -1.0;
+      if (cold && precond && monomer_response_setup()) build_precond(mb);
+    }
+    const bool was_cold = cold;
     cold = false;
     res.solves_mono += mb.nsys;
     hipLaunchKernelGGL(k_scatter_shell, dim3(mb.nsys), dim3(64), 0, stream, dmb, mb.q_out.p, d_qnew.p);
@@ -732,13 +818,30 @@ void Ctx::run(fx_result* out) {
     d_scalar.download(hs, stream, 1);
     sync();
     delta = hs[0];
-    if (verbose) std::fprintf(stderr, "[fx] monomer sweep %d: max |dq_out - dq_in| = %.3e, %.1f ms\n", macro, delta, now_ms() - t1);
+    if (verbose)
+      std::fprintf(stderr, "[fx] monomer %s %d: max |dq_out - dq_in| = %.3e, %.1f ms\n",
+                   fused_mode ? "step" : "sweep", macro, delta, now_ms() - t1);
     if (delta < opt.macro_tol) {
       if (failed) all_conv = false;
       check(hipMemcpyAsync(d_q.p, d_qnew.p, sizeof(double) * Nsh, hipMemcpyDeviceToDevice, stream), "copy");
       break;
     }
-    // history update and mixing
+    if (was_cold && fused && mb.has_pre) {
+      // switch to the fused loop from the charges of the first full solve
+      check(hipMemcpyAsync(d_q.p, d_qnew.p, sizeof(double) * Nsh, hipMemcpyDeviceToDevice, stream), "copy");
+      fused_mode = true;
+      slots.clear();
+      next_slot = 0;
+      continue;
+    }
+    // history update and mixing; in the fused loop the residual is the
+    // monomer-block Newton step (1 + M_I G_I)^-1 (q_out - q_in)
+    const double* target = d_qnew.p;
+    if (fused_mode) {
+      hipLaunchKernelGGL(k_precond_step, dim3(mb.nsys), dim3(128), 0, stream, mb.dev(), d_tmp_local.p);
+      hipLaunchKernelGGL(k_scatter_shell, dim3(mb.nsys), dim3(64), 0, stream, dmb, d_tmp_local.p, mono_tmp.p);
+      target = mono_tmp.p;
+    }
     int slot;
     if ((int)slots.size() < HIST) {
       slot = next_slot++;
@@ -747,15 +850,15 @@ void Ctx::run(fx_result* out) {
       slots.erase(slots.begin());
     }
     slots.push_back(slot);
-    hipLaunchKernelGGL(k_hist_store, dim3(gN), dim3(256), 0, stream, d_q.p, d_qnew.p, (long long)Nsh, slot, hX.p,
+    hipLaunchKernelGGL(k_hist_store, dim3(gN), dim3(256), 0, stream, d_q.p, target, (long long)Nsh, slot, hX.p,
                        hR.p);
     Slots sl;
     sl.m = (int)slots.size();
     for (int k = 0; k < sl.m; ++k) sl.id[k] = slots[k];
     hipLaunchKernelGGL(k_hist_gram, dim3(sl.m * sl.m), dim3(256), 0, stream, hR.p, (long long)Nsh, sl, hB.p);
     hipLaunchKernelGGL(k_hist_coef, dim3(1), dim3(1), 0, stream, hB.p, sl, hC.p);
-    hipLaunchKernelGGL(k_hist_mix, dim3(gN), dim3(256), 0, stream, hX.p, hR.p, (long long)Nsh, sl, hC.p, macro_beta,
-                       d_q.p);
+    hipLaunchKernelGGL(k_hist_mix, dim3(gN), dim3(256), 0, stream, hX.p, hR.p, (long long)Nsh, sl, hC.p,
+                       fused_mode ? fused_beta : macro_beta, d_q.p);
     check(hipGetLastError(), "monomer mixing");
   }
   if (macro > opt.max_macro) {
@@ -764,6 +867,7 @@ void Ctx::run(fx_result* out) {
   }
   res.macro_iter = macro;
   res.iters_mono = it_mono;
+  if (precond) monomer_response_setup();
   // final embedding field of the converged charges
   field(d_q.p, d_phi.p);
   e_mono.alloc(F);
@@ -785,6 +889,7 @@ void Ctx::run(fx_result* out) {
     DevBatch ddb = db_.dev();
     hipLaunchKernelGGL(k_cluster_phi, dim3(db_.nsys), dim3(128), 0, stream, dev_system(), ddb, d_phi.p, d_q.p);
     hipLaunchKernelGGL(k_gather_shell, dim3(db_.nsys), dim3(64), 0, stream, ddb, d_q.p, db_.q_in.p);
+    build_precond(db_);
     long long itd = 0;
     int failed = solve_batch(db_, true, &itd);
     if (failed) all_conv = false;
@@ -810,6 +915,7 @@ void Ctx::run(fx_result* out) {
     DevBatch dtb = tb_.dev();
     hipLaunchKernelGGL(k_cluster_phi, dim3(tb_.nsys), dim3(128), 0, stream, dev_system(), dtb, d_phi.p, d_q.p);
     hipLaunchKernelGGL(k_gather_shell, dim3(tb_.nsys), dim3(64), 0, stream, dtb, d_q.p, tb_.q_in.p);
+    build_precond(tb_);
     long long itt = 0;
     int failed = solve_batch(tb_, true, &itt);
     if (failed) all_conv = false;

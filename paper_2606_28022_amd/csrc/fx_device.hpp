@@ -84,6 +84,7 @@ struct DevBatch {
   double* q_out;
   double* phi;   // external shell potential
   double* sig;   // shell shift of the last Fock build
+  const float* pre;  // nsh x nsh mixing preconditioner per system (gam layout) or null
   double* hx;    // Anderson history of inputs  [sh_off*HIST + k*nsh + s]
   double* hr;    // Anderson history of residuals
   double* eps;

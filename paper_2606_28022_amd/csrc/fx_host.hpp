@@ -114,6 +114,11 @@ struct Batch {
   DevBuf<double> S, H0, Fm, Ct, Pm, Tm, gam, q_in, q_out, phi, sig, hx, hr, eps, occ;
   DevBuf<double> erep, e_int, e_prev, mts, err;
   DevBuf<int> status, niter, nhist, sweeps;
+  // Newton preconditioner (1 + M G)^-1 of the Anderson residuals (FP32,
+  // gam layout); used by the mixer when has_pre is set
+  DevBuf<float> pre;
+  bool has_pre = false;
+  long long tot_gam = 0;
   DevBatch dev();
   // algorithmic work of one n x n product (2 n^3) summed over listed systems
   double gemm_gflop(const std::vector<int>& l) const {
@@ -188,6 +193,21 @@ struct Ctx {
   DevBuf<double> e_mono, dE_scc, dEV_scc, dE_esd, dE_tri, ddq_scc;
   std::vector<double> trimer_dEIJK;
   fx_result res{};
+  // monomer susceptibility blocks (shell-summed transition charges Q and
+  // M = sum_ai Q Q^T / (eps_a - eps_i)) of the current monomer orbitals
+  DevBuf<int> resp_nocc, resp_order;
+  DevBuf<long long> resp_qoff;
+  DevBuf<double> resp_Q, resp_M;
+  bool resp_ok = false;
+  bool precond = !(std::getenv("FX_PRECOND") && std::atoi(std::getenv("FX_PRECOND")) == 0);
+  double precond_beta = 1.0;
+  // monomer loop: after the first full solve, one SCC iteration per monomer
+  // per step with global (preconditioned) mixing of all monomer charges
+  bool fused = !(std::getenv("FX_FUSED") && std::atoi(std::getenv("FX_FUSED")) == 0);
+  double fused_beta = std::getenv("FX_FUSED_BETA") ? std::atof(std::getenv("FX_FUSED_BETA")) : 1.0;
+  DevBuf<double> mono_tmp;
+  bool monomer_response_setup();
+  void build_precond(Batch& b);
   std::deque<KernelTimer> ktimers;  // stable addresses
   KernelTimer* kt(const char* name) {
     for (auto& t : ktimers)
@@ -249,7 +269,7 @@ struct Ctx {
   JacobiPlan jacobi_plan(int n) const;
   void gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlist, int mode, const double* A,
                   const double* B, double* C, const double* w, double gflop);
-  int run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* iters_out);
+  int run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* iters_out, bool single = false);
   int solve_batch(Batch& b, bool cold, long long* iters_out);
   void run(fx_result* out);
   void gradient();

@@ -19,10 +19,13 @@ __global__ void k_esd_pairs(DevSystem sys, const int* pairs, long long npairs, c
                             const int* frag_off, const double* q, double* out);
 
 // SCC (fx_scc.hip)
-__global__ void k_reset_state(DevBatch bt, const int* list, int nl);
+__global__ void k_reset_state(DevBatch bt, const int* list, int nl, int keep_err);
+__global__ void k_precond_step(DevBatch bt, double* out);
 __global__ void k_cholinv(DevBatch bt, const int* list, const double* Apool, double* Lpool, double* Xpool);
 __global__ void k_cluster_init_ct(DevBatch bt, const int* list, DevBatch mono);
 __global__ void k_fock(DevSystem sys, DevBatch bt, const int* list);
+__global__ void k_precond_build(DevSystem sys, DevBatch bt, const int* list, DevBatch mono, const double* Mmono,
+                                float* pre, int* ok);
 __global__ void k_gemm_mfma(DevBatch bt, const int* list, int nl, int tiles_per_sys, int mode, const double* A,
                             const double* B, double* C, const double* w);
 __global__ void k_gemm(DevBatch bt, const int* list, int mode, const double* A, const double* B, double* C,
@@ -76,5 +79,36 @@ __global__ void k_hist_coef(const double* B, Slots sl, double* coef);
 __global__ void k_hist_mix(const double* X, const double* R, long long n, Slots sl, const double* coef, double beta,
                            double* q);
 __global__ void k_hist_store(const double* x, const double* y, long long n, int slot, double* X, double* R);
+
+// response and gradient kernels
+__global__ void k_mo_order(DevBatch bt, const int* nocc, int* order);
+__global__ void k_resp_Q(DevSystem sys, DevBatch bt, const double* SCt, const int* order, const int* nocc,
+                         const long long* qoff, double* Q);
+__global__ void k_resp_M(DevBatch bt, const int* order, const int* nocc, const long long* qoff, const double* Q,
+                         double* M);
+__global__ void k_resp_R(DevSystem sys, DevBatch bt, const double* M, double* Wk, double* R);
+__global__ void k_resp_apply(DevBatch bt, const double* R, const double* M, const double* y, double* w, double* u);
+__global__ void k_resp_Z(DevBatch bt, const int* order, const int* nocc, const long long* qoff, const double* Q,
+                         const double* w, double* Zm, double* Ze);
+__global__ void k_rowscale(DevBatch bt, const double* wsh, const double* P, double* out);
+__global__ void k_sym_inplace(DevBatch bt, double* A);
+__global__ void k_resp_DS(DevBatch bt, const double* Zb, const double* WZ, const double* X2, const double* wsh,
+                          double* DS, double* gx);
+__global__ void k_cluster_cross(DevSystem sys, DevBatch bt, const double* x, double* out);
+__global__ void k_gather_csr(int n, const int* rowptr, const int* ent, const double* src, const double* base,
+                             double sign, double* dst);
+__global__ void k_axpy(long long n, const double* x, double a, const double* y, double* out);
+__global__ void k_grad_contract(DevSystem sys, DevBatch bt, const int* list, const double* DHp, const double* DSp,
+                                const double* gx, const double* gy, const double* wsys, int with_rep, int accumulate,
+                                double* g_out, double* F_out);
+__global__ void k_grad_pair_corr(DevSystem sys, DevBatch bt, const double* qmono, const double* ddq, double* g_out);
+__global__ void k_force_inter(DevSystem sys, const double* q, const double* av, int nchunk, double* part);
+__global__ void k_force_reduce(int N, int nchunk, const double* part, double* out);
+__global__ void k_cn_grad(DevSystem sys, const double* Ftot, double* g);
+__global__ void k_gather_atoms(int N, const int* rowptr, const int* ent_batch, const long long* ent_off,
+                               const double* const* g_batches, const double* const* F_batches, double* g_tot,
+                               double* F_tot, int mode);
+__global__ void k_final_shift(DevSystem sys, DevBatch bt, double* wvec);
+__global__ void k_make_DS(DevBatch bt, const double* P, const double* W, double* out);
 
 }  // namespace fx

@@ -74,17 +74,35 @@ __global__ void k_resp_M(DevBatch bt, const int* order, const int* nocc, const l
   const double* e = bt.eps + d.ao_off;
   const long long K = (long long)nv * no;
   const double* Qs = Q + qoff[si];
-  for (int idx = threadIdx.x; idx < ns * ns; idx += blockDim.x) {
-    int s = idx / ns, t = idx % ns;
-    if (t < s) continue;
-    double v = 0.0;
-    for (long long k = 0; k < K; ++k) {
-      int ap = (int)(k / no), ip = (int)(k % no);
-      double den = e[ord[no + ap]] - e[ord[ip]];
-      v += Qs[(long long)s * K + k] * Qs[(long long)t * K + k] / den;
+  // inverse orbital-energy gaps of a chunk of (a, i) pairs staged in LDS;
+  // M accumulated chunk by chunk in fixed order
+  constexpr int CH = 2048;
+  __shared__ double idn[CH];
+  double* Mo = M + d.gam_off;
+  for (int idx = threadIdx.x; idx < ns * ns; idx += blockDim.x) Mo[idx] = 0.0;
+  for (long long k0 = 0; k0 < K; k0 += CH) {
+    const int kn = (int)((K - k0) < CH ? (K - k0) : CH);
+    __syncthreads();
+    for (int k = threadIdx.x; k < kn; k += blockDim.x) {
+      const long long kk = k0 + k;
+      const int ap = (int)(kk / no), ip = (int)(kk - (long long)ap * no);
+      idn[k] = 1.0 / (e[ord[no + ap]] - e[ord[ip]]);
     }
-    M[d.gam_off + (long long)s * ns + t] = v;
-    M[d.gam_off + (long long)t * ns + s] = v;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < ns * ns; idx += blockDim.x) {
+      const int s = idx / ns, t = idx - s * ns;
+      if (t < s) continue;
+      const double* qs = Qs + (long long)s * K + k0;
+      const double* qt = Qs + (long long)t * K + k0;
+      double v = 0.0;
+      for (int k = 0; k < kn; ++k) v += qs[k] * qt[k] * idn[k];
+      Mo[idx] += v;
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < ns * ns; idx += blockDim.x) {
+    const int s = idx / ns, t = idx - s * ns;
+    if (t < s) Mo[idx] = Mo[(long long)t * ns + s];
   }
 }
 

@@ -45,7 +45,9 @@ __device__ inline double block_max(double v, double* red) {
 
 // ---------------------------------------------------------------------------
 // start of a solve: clear the iteration state of the listed systems
-__global__ void k_reset_state(DevBatch bt, const int* list, int nl) {
+// (keep_err: the residual of the previous pass stays, so the eigensolver's
+// rotation threshold follows the outer iteration)
+__global__ void k_reset_state(DevBatch bt, const int* list, int nl, int keep_err) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nl) return;
   int si = list[k];
@@ -53,7 +55,26 @@ __global__ void k_reset_state(DevBatch bt, const int* list, int nl) {
   bt.niter[si] = 0;
   bt.nhist[si] = 0;
   bt.e_prev[si] = 0.0;
-  bt.err[si] = 1e-2;
+  if (!keep_err) bt.err[si] = 1e-2;
+}
+
+// Preconditioned monomer step of the fused embedding loop, per system:
+// out = q_in + (1 + M G)^-1 (q_out - q_in) (local shell vectors)
+__global__ void k_precond_step(DevBatch bt, double* out) {
+  const int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const int ns = d.nsh;
+  __shared__ double r[MAXN];
+  const double* qi = bt.q_in + d.sh_off;
+  const double* qo = bt.q_out + d.sh_off;
+  for (int s = threadIdx.x; s < ns; s += blockDim.x) r[s] = qo[s] - qi[s];
+  __syncthreads();
+  const float* Pr = bt.pre + d.gam_off;
+  for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+    double v = 0.0;
+    for (int t = 0; t < ns; ++t) v += (double)Pr[(long long)s * ns + t] * r[t];
+    out[d.sh_off + s] = qi[s] + v;
+  }
 }
 
 // initial basis of a cluster from its monomers' eigenvectors: block-diagonal
@@ -681,9 +702,24 @@ __global__ void k_charges_mix(DevSystem sys, DevBatch bt, const int* list, doubl
   double* hx = bt.hx + (long long)d.sh_off * HIST;
   double* hr = bt.hr + (long long)d.sh_off * HIST;
   int slot = nh % HIST;
-  for (int s = threadIdx.x; s < ns; s += blockDim.x) {
-    hx[(long long)slot * ns + s] = qi[s];
-    hr[(long long)slot * ns + s] = qo[s] - qi[s];
+  if (bt.pre) {
+    // Newton step direction (1 + M G)^-1 r: the residual map of the SCC has
+    // Jacobian -(1 + M G) with M the charge susceptibility, G the Coulomb
+    // and third-order kernel; M and G are frozen at the start of the solve
+    const float* Pr = bt.pre + d.gam_off;
+    for (int s = threadIdx.x; s < ns; s += blockDim.x) pop[s] = qo[s] - qi[s];
+    __syncthreads();
+    for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+      double v = 0.0;
+      for (int t = 0; t < ns; ++t) v += (double)Pr[(long long)s * ns + t] * pop[t];
+      hx[(long long)slot * ns + s] = qi[s];
+      hr[(long long)slot * ns + s] = v;
+    }
+  } else {
+    for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+      hx[(long long)slot * ns + s] = qi[s];
+      hr[(long long)slot * ns + s] = qo[s] - qi[s];
+    }
   }
   nh += 1;
   int m = nh < HIST ? nh : HIST;
@@ -969,5 +1005,145 @@ __global__ void __launch_bounds__(1024)
 
 template __global__ void k_jacobi_lds<double>(DevBatch, const int*, int, double, double, double, int*, int);
 template __global__ void k_jacobi_lds<float>(DevBatch, const int*, int, double, double, double, int*, int);
+
+}  // namespace fx
+
+namespace fx {
+
+// ---------------------------------------------------------------------------
+// Mixing preconditioner of a cluster system X (1 to 3 fragments): the inverse
+// of K = 1 + M_X G_X, where M_X is block diagonal with the monomers' charge
+// susceptibilities M_I = sum_ai Q_ai Q_ai^T / (eps_a - eps_i) (the orbital
+// response of the response section, shell-summed) and G_X = gamma_XX minus
+// 2 Gamma_A dq_A on same-atom shell blocks at the system's input charges.
+// Gauss-Jordan inversion in place, in FP32 in LDS (the preconditioner only
+// steers the mixer; the fixed point does not depend on it).  ok[si] = 0 and
+// the identity are written when a pivot vanishes.
+__global__ void __launch_bounds__(256)
+    k_precond_build(DevSystem sys, DevBatch bt, const int* list, DevBatch mono, const double* Mmono, float* pre,
+                    int* ok) {
+  extern __shared__ float Kf[];  // ns x ns
+  __shared__ double qa[MAXN];
+  __shared__ float fcol[MAXN];
+  __shared__ int perm[MAXN];
+  __shared__ int comp_off[4], comp_frag[3];
+  __shared__ int pivrow;
+  __shared__ float redv[256];
+  __shared__ int redi[256];
+  const int si = list[blockIdx.x];
+  const SysDesc d = bt.desc[si];
+  const int ns = d.nsh;
+  const double* G = bt.gam + d.gam_off;
+  const double* q = bt.q_in + d.sh_off;
+  if (threadIdx.x == 0) {
+    int off = 0;
+    for (int c = 0; c < d.nfrag; ++c) {
+      comp_frag[c] = d.frag[c];
+      comp_off[c] = off;
+      off += mono.desc[d.frag[c]].nsh;
+    }
+    comp_off[d.nfrag] = off;
+  }
+  for (int a = threadIdx.x; a < d.nat; a += blockDim.x) {
+    const int s0 = bt.sys_atom_sh0[d.atom_off + a];
+    const int s1 = (a + 1 < d.nat) ? bt.sys_atom_sh0[d.atom_off + a + 1] : ns;
+    double v = 0.0;
+    for (int s = s0; s < s1; ++s) v += q[s];
+    qa[a] = v;
+  }
+  __syncthreads();
+  // K = 1 + M G'
+  for (int idx = threadIdx.x; idx < ns * ns; idx += blockDim.x) {
+    const int s = idx / ns, t = idx - s * ns;
+    int c = 0;
+    while (c + 1 < d.nfrag && s >= comp_off[c + 1]) ++c;
+    const int k0 = comp_off[c], k1 = comp_off[c + 1], nsf = k1 - k0;
+    const SysDesc md = mono.desc[comp_frag[c]];
+    const double* Mr = Mmono + md.gam_off + (long long)(s - k0) * nsf;
+    const int at = bt.sys_sh_atom[d.sh_off + t];
+    const int Aat = bt.sys_atoms[d.atom_off + at];
+    const double g3 = 2.0 * sys.elems[sys.elem[Aat]].Gamma * qa[at];
+    double v = (s == t) ? 1.0 : 0.0;
+    for (int k = k0; k < k1; ++k) {
+      double g = G[(long long)k * ns + t];
+      if (bt.sys_sh_atom[d.sh_off + k] == at) g -= g3;
+      v += Mr[k - k0] * g;
+    }
+    Kf[idx] = (float)v;
+  }
+  __syncthreads();
+  bool good = true;
+  for (int k = 0; k < ns; ++k) {
+    // pivot: largest |K[i][k]|, i >= k (lowest index on ties)
+    float best = -1.0f;
+    int bi = k;
+    for (int i = k + threadIdx.x; i < ns; i += blockDim.x) {
+      const float v = fabsf(Kf[i * ns + k]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    redv[threadIdx.x] = best;
+    redi[threadIdx.x] = bi;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) {
+        const float o = redv[threadIdx.x + w];
+        const int oi = redi[threadIdx.x + w];
+        if (o > redv[threadIdx.x] || (o == redv[threadIdx.x] && oi < redi[threadIdx.x])) {
+          redv[threadIdx.x] = o;
+          redi[threadIdx.x] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      pivrow = redi[0];
+      perm[k] = redi[0];
+    }
+    __syncthreads();
+    const int p = pivrow;
+    if (redv[0] < 1e-20f) {
+      good = false;
+      break;
+    }
+    if (p != k)
+      for (int j = threadIdx.x; j < ns; j += blockDim.x) {
+        const float t = Kf[k * ns + j];
+        Kf[k * ns + j] = Kf[p * ns + j];
+        Kf[p * ns + j] = t;
+      }
+    __syncthreads();
+    const float piv = Kf[k * ns + k];
+    for (int i = threadIdx.x; i < ns; i += blockDim.x) fcol[i] = (i == k) ? 0.0f : Kf[i * ns + k];
+    __syncthreads();
+    for (int j = threadIdx.x; j < ns; j += blockDim.x) Kf[k * ns + j] = (j == k ? 1.0f : Kf[k * ns + j]) / piv;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < ns * ns; idx += blockDim.x) {
+      const int i = idx / ns, j = idx - i * ns;
+      if (i == k) continue;
+      Kf[idx] = (j == k ? 0.0f : Kf[idx]) - fcol[i] * Kf[k * ns + j];
+    }
+    __syncthreads();
+  }
+  if (good) {
+    // undo the row interchanges as column interchanges, last first
+    for (int k = ns - 1; k >= 0; --k) {
+      const int p = perm[k];
+      if (p != k)
+        for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+          const float t = Kf[i * ns + k];
+          Kf[i * ns + k] = Kf[i * ns + p];
+          Kf[i * ns + p] = t;
+        }
+      __syncthreads();
+    }
+  }
+  float* out = pre + d.gam_off;
+  for (int idx = threadIdx.x; idx < ns * ns; idx += blockDim.x)
+    out[idx] = good ? Kf[idx] : ((idx / ns == idx % ns) ? 1.0f : 0.0f);
+  if (threadIdx.x == 0) ok[si] = good ? 1 : 0;
+}
 
 }  // namespace fx
