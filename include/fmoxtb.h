@@ -138,12 +138,25 @@ int fx_set_options(fx_ctx* ctx, const fx_options* o);
 /* Set the molecular system.  Z[n_atoms] atomic numbers, xyz_bohr[3*n_atoms]
  * Cartesian coordinates, atom_frag[n_atoms] fragment index of each atom
  * (0..n_frag-1, every fragment non-empty), frag_charge[n_frag] net charges.
- * Fragments are molecules (one molecule per monomer, section "Energy
- * accuracy"); no covalent bond may cross a fragment boundary.
+ * Fragments are molecules (section "Energy accuracy") or pieces of a
+ * covalent chain: bonds[2*n_bonds] lists the covalent bonds cut by the
+ * fragmentation as (detached atom, attached atom) pairs (section "Covalent
+ * bond fragmentation"): the detached atom keeps its fragment and gives one
+ * electron to the bond; a ghost copy of it joins the attached atom's fragment
+ * with one electron; hybrid-orbital projectors (V_HOP) constrain both sides.
+ * n_bonds = 0 (bonds may be NULL) for molecular fragments.  The detached atom
+ * must have one s and one p shell.  Inputs are copied.
+ * With cut bonds the shell vectors of fx_get_charges / fx_set_guess hold the
+ * ghost shells after those of the real atoms (one ghost per bond, in bond
+ * order); the gradient is not available (FX_E_UNSUPPORTED from fx_run when
+ * want_gradient is set).
  * Errors: FX_E_INVALID (bad sizes, NaN, atoms closer than 0.3 bohr, empty
- * fragment), FX_E_UNSUPPORTED (element without parameters). */
+ * fragment, bond index out of range or inside one fragment),
+ * FX_E_UNSUPPORTED (element without parameters, detached atom without s and
+ * p shells). */
 int fx_set_system(fx_ctx* ctx, int32_t n_atoms, const int32_t* Z, const double* xyz_bohr,
-                  int32_t n_frag, const int32_t* atom_frag, const int32_t* frag_charge);
+                  int32_t n_frag, const int32_t* atom_frag, const int32_t* frag_charge,
+                  int32_t n_bonds, const int32_t* bonds);
 
 /* Classify fragment pairs (and trimers for order 3) by closest contact
  * (section "Computational Details" selection rule, fixed cutoff reading) on

@@ -111,9 +111,60 @@ def build_lists(system, cutoff_bohr, order=2):
 # --------------------------------------------------------------------------
 # the supersystem's shells
 
+class ExtendedAtoms:
+    """The supersystem's atoms followed by one ghost atom per cut covalent bond
+    (section "Covalent bond fragmentation"): a copy of the detached atom (same
+    element, position and supersystem CN) that belongs to the attached atom's
+    fragment.  Without cut bonds this is the system itself."""
+
+    def __init__(self, system, cn):
+        b = np.asarray(system.bonds, dtype=np.int64).reshape(-1, 2)
+        self.N = system.n_atoms
+        self.bonds = b
+        self.Z = np.concatenate([system.Z, system.Z[b[:, 0]]])
+        self.xyz = np.concatenate([system.xyz, system.xyz[b[:, 0]]])
+        self.frag = np.concatenate([system.frag, system.frag[b[:, 1]]]).astype(np.int64)
+        self.cn = np.concatenate([cn, cn[b[:, 0]]])
+        self.n_atoms = len(self.Z)
+        self.frag_charge = system.frag_charge
+        self.real_atoms = fragment_atoms(system.frag, system.n_frag)
+
+    def bond_vector(self, k):
+        a, b = self.bonds[k]
+        v = self.xyz[b] - self.xyz[a]
+        return v / np.linalg.norm(v)
+
+    def layout(self, frags):
+        """Atoms (extended indices) of the system made of `frags`, in basis
+        order: per fragment its real atoms, then the ghosts of its cut bonds
+        whose detached atom lies outside; the covalent-boundary list of that
+        system; and the ghosts of bonds healed inside it (present in the
+        monomers only)."""
+        fs = set(int(f) for f in frags)
+        fr = self.frag
+        atoms = []
+        for f in frags:
+            atoms.extend(int(a) for a in self.real_atoms[f])
+            for k, (a, b) in enumerate(self.bonds):
+                if fr[b] == f and fr[a] not in fs:
+                    atoms.append(self.N + k)
+        pos = {a: i for i, a in enumerate(atoms)}
+        hop, healed = [], []
+        for k, (a, b) in enumerate(self.bonds):
+            ina, inb = fr[a] in fs, fr[b] in fs
+            if ina and not inb:
+                hop.append((pos[int(a)], "bda", self.bond_vector(k)))
+            elif inb and not ina:
+                hop.append((pos[self.N + k], "ghost", self.bond_vector(k)))
+            elif ina and inb:
+                healed.append(self.N + k)
+        return np.array(atoms, dtype=np.int64), hop, np.array(healed, dtype=np.int64)
+
+
 class Shells:
-    """Global shell table: shells of atom 0, then atom 1, ...; per shell the
-    atom, its fragment and its hardness (1 + kappa) eta_A."""
+    """Global shell table: shells of atom 0, then atom 1, ... (ghost atoms
+    after the real ones); per shell the atom, its fragment and its hardness
+    (1 + kappa) eta_A."""
 
     def __init__(self, params, system):
         self.p = params
@@ -151,8 +202,8 @@ class Shells:
         return out
 
 
-def _system_for(params, system, cn, atoms, charge):
-    return XtbSystem(params, system.Z[atoms], system.xyz[atoms], cn[atoms], charge=charge)
+def _system_for(params, ext, atoms, charge, hop=None):
+    return XtbSystem(params, ext.Z[atoms], ext.xyz[atoms], ext.cn[atoms], charge=charge, hop=hop)
 
 
 class FMOResult:
@@ -164,15 +215,17 @@ def fmo(system, params, cutoff_bohr, order=2, lists=None, scc_tol=1e-10,
     """FMO2 (order=2) or FMO3 (order=3) energy.  Returns an FMOResult with the
     converged monomer, dimer and trimer results and the energy terms."""
     F = system.n_frag
-    fa = fragment_atoms(system.frag, F)
     cn = coordination_numbers(params, system.Z, system.xyz)
-    sh = Shells(params, system)
+    ext = ExtendedAtoms(system, cn)
+    lay = [ext.layout((I,)) for I in range(F)]
+    fa = [l[0] for l in lay]
+    sh = Shells(params, ext)
     fsh = [sh.of_atoms(fa[I]) for I in range(F)]
     if lists is None:
         lists = build_lists(system, cutoff_bohr, order)
     scc_pairs, esd_pairs, trimers = lists
 
-    mono = [_system_for(params, system, cn, fa[I], int(system.frag_charge[I])) for I in range(F)]
+    mono = [_system_for(params, ext, fa[I], int(system.frag_charge[I]), lay[I][1]) for I in range(F)]
     q = np.zeros(sh.n)   # superposition guess: zero shell charges
     res = [None] * F
     same_frag = lambda s, t: sh.frag[s] == sh.frag[t]
@@ -220,6 +273,7 @@ def fmo(system, params, cutoff_bohr, order=2, lists=None, scc_tol=1e-10,
     out.q = q
     out.phi_mono = phi
     out.cn = cn
+    out.ext = ext
     out.mono = res
     out.mono_sys = mono
     out.frag_atoms = fa
@@ -229,16 +283,22 @@ def fmo(system, params, cutoff_bohr, order=2, lists=None, scc_tol=1e-10,
     out.E_mono = np.array([r.e_int for r in res])
 
     def solve_cluster(frags):
-        atoms = np.concatenate([fa[I] for I in frags])
-        shl = np.concatenate([fsh[I] for I in frags])
-        inside = np.zeros(sh.n, dtype=bool)
-        inside[shl] = True
-        phiX = sh.potential(shl, np.where(inside, 0.0, q), lambda s, t: np.zeros_like(s, dtype=bool))
-        sysX = _system_for(params, system, cn, atoms,
-                           int(sum(system.frag_charge[I] for I in frags)))
+        atoms, hop, healed = ext.layout(frags)
+        shl = sh.of_atoms(atoms)
+        inside = np.isin(sh.frag, np.asarray(frags))
+        no_mask = lambda s, t: np.zeros_like(s, dtype=bool)
+        q_out = np.where(inside, 0.0, q)
+        phiX = sh.potential(shl, q_out, no_mask)
+        sysX = _system_for(params, ext, atoms, int(sum(system.frag_charge[I] for I in frags)), hop)
         rX = scc(sysX, phiX, q_guess=q[shl], tol=scc_tol)
         ddq = rX.q - q[shl]
-        return sysX, rX, shl, ddq, float(ddq @ phiX)
+        dEV = float(ddq @ phiX)
+        if len(healed):
+            # ghosts of bonds healed inside the cluster: their monomer charge is
+            # the charge transfer, with the opposite sign (eq. ctij_ghost)
+            hs = sh.of_atoms(healed)
+            dEV += float(-q[hs] @ sh.potential(hs, q_out, no_mask))
+        return sysX, rX, shl, ddq, dEV
 
     out.dimers = []
     dE_scc = np.zeros(len(scc_pairs))
@@ -296,7 +356,10 @@ def _inter_gamma_force(sh, pair_weights, natoms):
 
 def fmo2_gradient(system, params, res, with_response=True):
     """Analytic FMO2 gradient (Eh/bohr, shape (natoms, 3)) for a converged
-    FMO2 result `res` (lists frozen)."""
+    FMO2 result `res` (lists frozen).  Systems with cut covalent bonds are not
+    covered (the HOP gradient is not part of this build)."""
+    if len(getattr(system, "bonds", ())):
+        raise NotImplementedError("FMO2 gradient with covalent boundaries")
     sh = res.shells
     F = system.n_frag
     fa, fsh = res.frag_atoms, res.frag_shells

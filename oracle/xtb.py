@@ -79,7 +79,14 @@ class XtbSystem:
     computed in the whole supersystem (FMO reads CN at supersystem level,
     section "Explicit FMO-xTB gradient", coordination number correction)."""
 
-    def __init__(self, params, Z, xyz, cn, charge=0):
+    def __init__(self, params, Z, xyz, cn, charge=0, hop=None):
+        """hop: covalent boundary atoms of this system (section "Covalent bond
+        fragmentation"), a list of (atom, kind, b) with kind "bda" (a
+        detached atom whose partner is outside: it gives up one electron and
+        its bond-pointing hybrid is projected out) or "ghost" (a copy of the
+        detached atom of a bond whose attached atom is inside: one electron,
+        everything but the bond-pointing hybrid projected out); b is the unit
+        vector from the detached to the attached atom."""
         self.p = params
         self.Z = np.asarray(Z, dtype=np.int64)
         self.xyz = np.asarray(xyz, dtype=float)
@@ -123,8 +130,11 @@ class XtbSystem:
         self.at_zeff = np.array([params.element(int(z))["zeff"] for z in self.Z])
         self.at_arep = np.array([params.element(int(z))["arep"] for z in self.Z])
         self.sh_h = self.sh_level * (1.0 + self.sh_kcn * self.cn[self.sh_atom])
+        self.hop = list(hop or [])
+        self._apply_hop_references()
         self.nel = float(self.sh_q0.sum()) - charge
         self._build()
+        self._build_hop()
 
     # -- integrals -----------------------------------------------------------
     def _pairs(self):
@@ -202,6 +212,62 @@ class XtbSystem:
             self.erep += (self.at_zeff[a] * self.at_zeff[b] / R
                           * math.exp(-math.sqrt(self.at_arep[a] * self.at_arep[b]) * R ** p.kf))
 
+    # -- covalent boundaries (HOP) --------------------------------------------
+    def _hop_atom_layout(self, A):
+        """(s shell, p shell) of a boundary atom; it must have exactly one s
+        and one p shell (4 AOs)."""
+        shells = list(range(self.atom_sh0[A], self.atom_sh0[A + 1]))
+        ls = [int(self.sh_l[t]) for t in shells]
+        if ls != [0, 1]:
+            raise ValueError("a covalent boundary atom needs one s and one p shell")
+        return shells[0], shells[1]
+
+    def _apply_hop_references(self):
+        """Reference populations and repulsion charges of boundary atoms: the
+        detached atom gives one electron to the bond, taken 1/4 from s and 3/4
+        from p (sp3 hybrid weights); the ghost carries 1/4 s + 3/4 p.  The
+        repulsion charge is scaled by (v - 1)/v and 1/v (v = valence electrons
+        of the element)."""
+        for A, kind, _ in self.hop:
+            s_sh, p_sh = self._hop_atom_layout(A)
+            v = float(self.sh_q0[s_sh] + self.sh_q0[p_sh])
+            if kind == "bda":
+                self.sh_q0[s_sh] -= 0.25
+                self.sh_q0[p_sh] -= 0.75
+                self.at_zeff[A] *= (v - 1.0) / v
+            elif kind == "ghost":
+                self.sh_q0[s_sh] = 0.25
+                self.sh_q0[p_sh] = 0.75
+                self.at_zeff[A] *= 1.0 / v
+            else:
+                raise ValueError(kind)
+
+    def hybrid(self, A, b):
+        """AO coefficients of the sp3 hybrid 1/2 s + sqrt(3)/2 (b . p) on atom A
+        (eq. hybrid), as a length-nao vector."""
+        s_sh, p_sh = self._hop_atom_layout(A)
+        h = np.zeros(self.nao)
+        h[self.sh_ao0[s_sh]] = 0.5
+        h[self.sh_ao0[p_sh]:self.sh_ao0[p_sh] + 3] = 0.5 * math.sqrt(3.0) * np.asarray(b, float)
+        return h
+
+    def _build_hop(self):
+        """V^HOP = S D S (eq. vhop), D = V h h^T on a detached atom (eq. dd_bda)
+        and V (1_sp - h h^T) on a ghost (eq. dd_ghost)."""
+        n = self.nao
+        D = np.zeros((n, n))
+        for A, kind, b in self.hop:
+            h = self.hybrid(A, b)
+            blk = slice(self.ao_off[A], self.ao_off[A + 1])
+            if kind == "bda":
+                D += self.p.VHOP * np.outer(h, h)
+            else:
+                one = np.zeros((n, n))
+                one[blk, blk] = np.eye(self.ao_off[A + 1] - self.ao_off[A])
+                D += self.p.VHOP * (one - np.outer(h, h))
+        self.D_hop = D
+        self.V_hop = self.S @ D @ self.S if self.hop else np.zeros((n, n))
+
     # -- Mulliken charges and energy -----------------------------------------
     def shell_charges(self, P):
         pop_ao = np.sum(P * self.S, axis=1)
@@ -216,12 +282,16 @@ class XtbSystem:
         return self.gamma @ q - (self.at_Gamma * qa * qa)[self.sh_atom] + phi
 
     def fock(self, q, phi):
+        """F = H0 + 1/2 S (sigma_mu + sigma_nu), plus V^HOP at covalent
+        boundaries (eq. fock_hop)."""
         sig = self.shift(q, phi)[self.ao_sh]
-        return self.H0 + 0.5 * self.S * (sig[:, None] + sig[None, :])
+        F = self.H0 + 0.5 * self.S * (sig[:, None] + sig[None, :])
+        return F + self.V_hop if self.hop else F
 
     def energy_internal(self, P, q, occ):
         """E'_X of the system without the embedding term (eq. gfn1_energy_2 plus
-        the repulsion)."""
+        the repulsion); a HOP projector is a constraint and not part of it
+        (section "FMO-xTB HOP energy")."""
         qa = self.atom_sum(q)
         e = float(np.sum(P * self.H0))
         e += 0.5 * float(q @ self.gamma @ q)

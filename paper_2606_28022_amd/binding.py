@@ -92,7 +92,7 @@ def load_library():
     L.fx_last_error.restype = C.c_char_p
     L.fx_default_options.argtypes = [C.POINTER(fx_options)]
     L.fx_set_options.argtypes = [P, C.POINTER(fx_options)]
-    L.fx_set_system.argtypes = [P, I32, pI32, pD, I32, pI32, pI32]
+    L.fx_set_system.argtypes = [P, I32, pI32, pD, I32, pI32, pI32, I32, pI32]
     L.fx_build_lists.argtypes = [P, C.POINTER(fx_counts)]
     L.fx_get_counts.argtypes = [P, C.POINTER(fx_counts)]
     L.fx_get_lists.argtypes = [P, pI32, pI32, pI32]
@@ -182,10 +182,13 @@ class FmoXtb:
             setattr(self.opt, k, v)
         self._check(self.L.fx_set_options(self.ctx, C.byref(self.opt)))
 
-    def set_system(self, Z, xyz_bohr, atom_frag, frag_charge):
+    def set_system(self, Z, xyz_bohr, atom_frag, frag_charge, bonds=None):
         Z, xyz, fr, ch = _i32(Z), _f64(xyz_bohr).reshape(-1), _i32(atom_frag), _i32(frag_charge)
+        bd = _i32(np.zeros((0, 2)) if bonds is None else np.asarray(bonds).reshape(-1, 2)).reshape(-1)
+        nb = len(bd) // 2
         self._check(self.L.fx_set_system(self.ctx, len(Z), _ptr(Z, C.c_int32), _ptr(xyz, C.c_double),
-                                         len(ch), _ptr(fr, C.c_int32), _ptr(ch, C.c_int32)))
+                                         len(ch), _ptr(fr, C.c_int32), _ptr(ch, C.c_int32), nb,
+                                         _ptr(bd, C.c_int32) if nb else None))
         self.n_atoms = len(Z)
         self.n_frag = len(ch)
         cnt = self.build_lists_counts()

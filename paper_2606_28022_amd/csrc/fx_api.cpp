@@ -55,6 +55,7 @@ HostParams load_params(const std::string& path) {
   for (int l = 0; l < 3; ++l) P.g.kl[l] = l < (int)g["kl"].size() ? g["kl"][l].d() : 0.0;
   P.g.KAB = g["KAB"].d();
   P.g.kT = g["Tel_K"].d() * g["kB_Eh_per_K"].d();
+  P.g.VHOP = g.has("VHOP") ? g["VHOP"].d() : 1e6;
   double a2b = g["angstrom_to_bohr"].d();
   std::map<std::string, std::pair<std::vector<double>, std::vector<double>>> basis;
   for (auto& kv : root["basis"].obj) {
@@ -160,7 +161,8 @@ double Ctx::now_ms() {
 
 DevSystem Ctx::dev_system() const {
   DevSystem s;
-  s.natoms = N;
+  s.natoms = Ne;
+  s.nreal = N;
   s.nshells = Nsh;
   s.nfrag = F;
   s.xyz = d_xyz.p;
@@ -185,6 +187,11 @@ void Ctx::build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters,
   b.nsys = ns;
   std::vector<SysDesc> desc(ns);
   std::vector<int> atoms, atom_ao0, atom_sh0, sh_global, sh_atom, ao_sh;
+  // covalent-boundary tables (section "Covalent bond fragmentation")
+  std::vector<double> sh_q0, atom_zs, hop_b;
+  std::vector<int> hop_off(1, 0), hop_atom, hop_kind, healed_off(1, 0), healed_sh;
+  std::vector<int> loc(Ne, -1);  // local index of an extended atom in the current system
+  std::vector<int> sh_mono;      // index of each local shell within its fragment's monomer
   long long mat = 0, gam = 0;
   int sh_off = 0, ao_off = 0, atom_off = 0;
   for (int k = 0; k < ns; ++k) {
@@ -196,29 +203,97 @@ void Ctx::build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters,
     d.mat_off = mat;
     d.gam_off = gam;
     int nat = 0, nsh = 0, nao = 0;
-    double nel = 0.0;
+    double charge = 0.0;
     for (int f = 0; f < 3; ++f) d.frag[f] = -1;
+    for (int f = 0; f < 4; ++f) d.comp_sh[f] = 0;
+    auto inside = [&](int fr) {
+      for (int c = 0; c < nfrag_each; ++c)
+        if (clusters[k][c] == fr) return true;
+      return false;
+    };
+    std::vector<int> sys_atoms;
     for (int f = 0; f < nfrag_each; ++f) {
-      int I = clusters[k][f];
+      const int I = clusters[k][f];
       d.frag[f] = I;
-      nel -= frag_charge[I];
+      d.comp_sh[f] = nsh;
+      charge += frag_charge[I];
+      int msh = 0;
       for (int ia = frag_off[I]; ia < frag_off[I + 1]; ++ia) {
-        int A = frag_atoms[ia];
+        const int A = frag_atoms[ia];
         const DevElem& el = P.elems[elem[A]];
+        // a ghost whose detached atom is inside too: the bond is healed
+        if (A >= N && inside(frag[bonds[2 * (A - N)]])) {
+          msh += el.nsh;
+          continue;
+        }
+        for (int s = 0; s < el.nsh; ++s) sh_mono.push_back(msh + s);
+        msh += el.nsh;
+        loc[A] = nat;
+        sys_atoms.push_back(A);
         atoms.push_back(A);
         atom_ao0.push_back(nao);
         atom_sh0.push_back(nsh);
         for (int s = 0; s < el.nsh; ++s) {
           sh_global.push_back(atom_sh0_g[A] + s);
           sh_atom.push_back(nat);
+          sh_q0.push_back(el.q0[s]);
           for (int u = 0; u < el.nao_sh[s]; ++u) ao_sh.push_back(nsh);
-          nel += el.q0[s];
           ++nsh;
         }
+        atom_zs.push_back(1.0);
         nao += el.nao;
         ++nat;
       }
     }
+    d.comp_sh[nfrag_each] = nsh;
+    // boundary atoms of this system: detached atoms whose partner is outside
+    // give up one electron (1/4 s, 3/4 p) and get the projector of their
+    // bond hybrid; ghosts of bonds whose detached atom is outside carry one
+    // electron (1/4 s, 3/4 p); repulsion charges scale by (v-1)/v and 1/v
+    for (int f = 0; f < nfrag_each; ++f) {
+      const int I = clusters[k][f];
+      for (int kb : bda_bonds[I]) {
+        const int a = bonds[2 * kb], bb = bonds[2 * kb + 1];
+        if (inside(frag[bb])) continue;
+        hop_atom.push_back(loc[a]);
+        hop_kind.push_back(1);
+        for (int c = 0; c < 3; ++c) hop_b.push_back(xyz_h[3 * bb + c] - xyz_h[3 * a + c]);
+      }
+      for (int kb : ghost_bonds[I]) {
+        const int a = bonds[2 * kb];
+        if (inside(frag[a])) {
+          const int g = N + kb;
+          for (int s = atom_sh0_g[g]; s < atom_sh0_g[g + 1]; ++s) healed_sh.push_back(s);
+          continue;
+        }
+        const int bb = bonds[2 * kb + 1];
+        hop_atom.push_back(loc[N + kb]);
+        hop_kind.push_back(2);
+        for (int c = 0; c < 3; ++c) hop_b.push_back(xyz_h[3 * bb + c] - xyz_h[3 * a + c]);
+      }
+    }
+    for (int e = hop_off.back(); e < (int)hop_atom.size(); ++e) {
+      double* bv = &hop_b[3 * e];
+      const double r = std::sqrt(bv[0] * bv[0] + bv[1] * bv[1] + bv[2] * bv[2]);
+      for (int c = 0; c < 3; ++c) bv[c] /= r;
+      const int la = hop_atom[e];
+      const int s0 = atom_sh0[atom_off + la];
+      const double v = sh_q0[sh_off + s0] + sh_q0[sh_off + s0 + 1];
+      if (hop_kind[e] == 1) {
+        sh_q0[sh_off + s0] -= 0.25;
+        sh_q0[sh_off + s0 + 1] -= 0.75;
+        atom_zs[atom_off + la] *= (v - 1.0) / v;
+      } else {
+        sh_q0[sh_off + s0] = 0.25;
+        sh_q0[sh_off + s0 + 1] = 0.75;
+        atom_zs[atom_off + la] *= 1.0 / v;
+      }
+    }
+    hop_off.push_back((int)hop_atom.size());
+    healed_off.push_back((int)healed_sh.size());
+    for (int A : sys_atoms) loc[A] = -1;
+    double nel = -charge;
+    for (int s = 0; s < nsh; ++s) nel += sh_q0[sh_off + s];
     if (nao > MAXN) throw FxError(FX_E_UNSUPPORTED, "fragment system larger than 512 AOs");
     d.nat = nat;
     d.nsh = nsh;
@@ -230,6 +305,19 @@ void Ctx::build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters,
     mat += (long long)nao * nao;
     gam += (long long)nsh * nsh;
     b.max_nao = std::max(b.max_nao, nao);
+  }
+  b.sh_mono.upload(sh_mono);
+  b.has_hop = !hop_atom.empty();
+  b.has_healed = !healed_sh.empty();
+  if (b.has_hop || b.has_healed) {
+    b.sh_q0.upload(sh_q0);
+    b.atom_zs.upload(atom_zs);
+    b.hop_off.upload(hop_off);
+    b.hop_atom.upload(hop_atom.empty() ? std::vector<int>{0} : hop_atom);
+    b.hop_kind.upload(hop_kind.empty() ? std::vector<int>{0} : hop_kind);
+    b.hop_b.upload(hop_b.empty() ? std::vector<double>{0.0} : hop_b);
+    b.healed_off.upload(healed_off);
+    b.healed_sh.upload(healed_sh.empty() ? std::vector<int>{0} : healed_sh);
   }
   b.h_desc = desc;
   b.tot_sh = sh_off;
@@ -296,6 +384,17 @@ DevBatch Batch::dev() {
   d.phi = phi.p;
   d.sig = sig.p;
   d.pre = has_pre ? pre.p : nullptr;
+  const bool hb = has_hop || has_healed;
+  d.sh_q0 = hb ? sh_q0.p : nullptr;
+  d.atom_zs = hb ? atom_zs.p : nullptr;
+  d.Vh = has_hop ? Vh.p : nullptr;
+  d.hop_off = hb ? hop_off.p : nullptr;
+  d.hop_atom = hb ? hop_atom.p : nullptr;
+  d.hop_kind = hb ? hop_kind.p : nullptr;
+  d.hop_b = hb ? hop_b.p : nullptr;
+  d.healed_off = has_healed ? healed_off.p : nullptr;
+  d.healed_sh = has_healed ? healed_sh.p : nullptr;
+  d.sh_mono = sh_mono.p;
   d.hx = hx.p;
   d.hr = hr.p;
   d.eps = eps.p;
@@ -421,7 +520,7 @@ void Ctx::build_precond(Batch& b) {
 // kernel with an FP64 working matrix if it fits with a rotation log of at
 // least 4 steps, else with an FP32 working matrix, else the global-memory
 // kernel.  Workgroup size grows with n (one V column per wave).
-JacobiPlan Ctx::jacobi_plan(int n) const {
+JacobiPlan Ctx::jacobi_plan(int n, bool fp64_only) const {
   JacobiPlan jp;
   if (!jacobi_lds || n < 2 || n > MAXN) return jp;
   int t = n <= 32 ? 64 : n <= 96 ? 256 : n <= 160 ? 512 : 1024;
@@ -430,6 +529,7 @@ JacobiPlan Ctx::jacobi_plan(int n) const {
   for (int pass = 0; pass < 2; ++pass)
     for (int elt : {8, 4})
       for (int k : chunks) {
+        if (fp64_only && elt == 4) continue;
         if (pass == 0 && k < 4) continue;
         const unsigned bytes = jacobi_lds_layout(n, elt, k, t / 64).total;
         if ((int)bytes <= lds_max) {
@@ -444,8 +544,10 @@ JacobiPlan Ctx::jacobi_plan(int n) const {
 }
 
 void Ctx::build_matrices(Batch& b) {
+  if (b.has_hop) b.Vh.alloc(std::max(1LL, b.tot_mat));
   DevBatch db = b.dev();
   hipLaunchKernelGGL(k_build_system, dim3(b.nsys), dim3(256), 0, stream, dev_system(), db, nullptr);
+  if (b.has_hop) hipLaunchKernelGGL(k_vhop, dim3(b.nsys), dim3(256), 0, stream, db, P.g.VHOP);
   check(hipGetLastError(), "k_build_system");
 }
 
@@ -481,7 +583,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     }
     check(hipGetLastError(), "initial basis");
   }
-  const JacobiPlan jp = jacobi_plan(b.max_nao);
+  const JacobiPlan jp = jacobi_plan(b.max_nao, b.has_hop);
   std::vector<int> active = list;
   std::vector<int> sweeps(b.nsys), status(b.nsys), niter(b.nsys);
   DevBuf<int> d_act;
@@ -575,9 +677,9 @@ int Ctx::solve_batch(Batch& b, bool cold, long long* iters_out) {
 }
 
 void Ctx::field(const double* d_q, double* d_phi) {
-  const int nchunk = std::max(1, std::min(64, (N + 255) / 256 > 0 ? 2048 / ((N + 255) / 256) : 1));
+  const int nchunk = std::max(1, std::min(64, (Ne + 255) / 256 > 0 ? 2048 / ((Ne + 255) / 256) : 1));
   if ((long long)nchunk * Nsh > field_part.n) field_part.alloc((long long)nchunk * Nsh);
-  dim3 grid((N + 255) / 256, nchunk);
+  dim3 grid((Ne + 255) / 256, nchunk);
   const int ev = timers.begin(stream);
   hipLaunchKernelGGL(k_field_partial, grid, dim3(256), 0, stream, dev_system(), d_q, nchunk, field_part.p);
   timers.end(stream, ev, kt("fx::k_field_partial"), 8e-9 * field_pairs);
@@ -588,6 +690,8 @@ void Ctx::field(const double* d_q, double* d_phi) {
 
 void Ctx::compute_cn() {
   hipLaunchKernelGGL(k_cn, dim3((N + 255) / 256), dim3(256), 0, stream, dev_system(), d_cn.p);
+  if (NB > 0)
+    hipLaunchKernelGGL(k_ghost_cn, dim3((NB + 255) / 256), dim3(256), 0, stream, dev_system(), d_bonds.p, NB, d_cn.p);
   check(hipGetLastError(), "k_cn");
 }
 
@@ -596,7 +700,8 @@ void Ctx::build_lists_impl() {
   DevBuf<int8_t> flag;
   flag.alloc(std::max(1LL, npair));
   if (F > 1) {
-    hipLaunchKernelGGL(k_pair_contacts, dim3(F), dim3(256), 0, stream, dev_system(), d_frag_atoms.p, d_frag_off.p,
+    hipLaunchKernelGGL(k_pair_contacts, dim3(F), dim3(256), 0, stream, dev_system(), d_frag_atoms_real.p,
+                       d_frag_off_real.p,
                        opt.cutoff_bohr * opt.cutoff_bohr, flag.p);
     check(hipGetLastError(), "k_pair_contacts");
   }
@@ -654,8 +759,10 @@ void Ctx::build_lists_impl() {
 }
 
 void Ctx::set_system(int32_t n_atoms, const int32_t* Z, const double* xyz, int32_t n_frag, const int32_t* atom_frag,
-                     const int32_t* fchg) {
+                     const int32_t* fchg, int32_t n_bonds, const int32_t* bonds_in) {
   if (n_atoms <= 0 || n_frag <= 0 || !Z || !xyz || !atom_frag || !fchg) throw FxError(FX_E_INVALID, "bad system");
+  if (n_bonds < 0 || (n_bonds > 0 && !bonds_in)) throw FxError(FX_E_INVALID, "bad bond list");
+  has_system = false;
   N = n_atoms;
   F = n_frag;
   elem.assign(N, 0);
@@ -691,21 +798,56 @@ void Ctx::set_system(int32_t n_atoms, const int32_t* Z, const double* xyz, int32
       grid[key].push_back(A);
     }
   }
-  // fragments: atoms in ascending order
-  frag_off.assign(F + 1, 0);
-  for (int A = 0; A < N; ++A) frag_off[frag[A] + 1]++;
-  for (int I = 0; I < F; ++I) {
-    if (frag_off[I + 1] == 0) throw FxError(FX_E_INVALID, "empty fragment");
-    frag_off[I + 1] += frag_off[I];
+  // covalent boundaries: detached atom (stays in its fragment) and attached
+  // atom; one ghost atom per bond joins the attached atom's fragment
+  NB = n_bonds;
+  bonds.clear();
+  if (NB > 0) bonds.assign(bonds_in, bonds_in + 2 * NB);
+  for (int k = 0; k < NB; ++k) {
+    const int a = bonds[2 * k], b = bonds[2 * k + 1];
+    if (a < 0 || a >= N || b < 0 || b >= N) throw FxError(FX_E_INVALID, "bond atom index out of range");
+    if (frag[a] == frag[b]) throw FxError(FX_E_INVALID, "a cut bond must join two fragments");
+    const DevElem& el = P.elems[elem[a]];
+    if (el.nsh != 2 || el.l[0] != 0 || el.l[1] != 1)
+      throw FxError(FX_E_UNSUPPORTED, "a detached atom needs one s and one p shell");
   }
-  frag_atoms.assign(N, 0);
-  std::vector<int> fill(frag_off.begin(), frag_off.end() - 1);
-  for (int A = 0; A < N; ++A) frag_atoms[fill[frag[A]]++] = A;
+  Ne = N + NB;
+  // fragments, real atoms in ascending order (pair lists)
+  frag_off_real.assign(F + 1, 0);
+  for (int A = 0; A < N; ++A) frag_off_real[frag[A] + 1]++;
+  for (int I = 0; I < F; ++I) {
+    if (frag_off_real[I + 1] == 0) throw FxError(FX_E_INVALID, "empty fragment");
+    frag_off_real[I + 1] += frag_off_real[I];
+  }
+  frag_atoms_real.assign(N, 0);
+  {
+    std::vector<int> fill(frag_off_real.begin(), frag_off_real.end() - 1);
+    for (int A = 0; A < N; ++A) frag_atoms_real[fill[frag[A]]++] = A;
+  }
+  // extended atom tables: ghosts after the real atoms
+  bda_bonds.assign(F, {});
+  ghost_bonds.assign(F, {});
+  for (int k = 0; k < NB; ++k) {
+    const int a = bonds[2 * k], b = bonds[2 * k + 1];
+    bda_bonds[frag[a]].push_back(k);
+    ghost_bonds[frag[b]].push_back(k);
+    elem.push_back(elem[a]);
+    frag.push_back(frag[b]);
+    for (int c = 0; c < 3; ++c) xyz_h.push_back(xyz[3 * a + c]);
+  }
+  // each fragment's monomer atoms: its real atoms, then its ghosts
+  frag_off.assign(F + 1, 0);
+  frag_atoms.clear();
+  for (int I = 0; I < F; ++I) {
+    for (int ia = frag_off_real[I]; ia < frag_off_real[I + 1]; ++ia) frag_atoms.push_back(frag_atoms_real[ia]);
+    for (int k : ghost_bonds[I]) frag_atoms.push_back(N + k);
+    frag_off[I + 1] = (int)frag_atoms.size();
+  }
   // shells
-  atom_sh0_g.assign(N + 1, 0);
+  atom_sh0_g.assign(Ne + 1, 0);
   std::vector<int> sh_atom, sh_frag;
   std::vector<double> sh_eta;
-  for (int A = 0; A < N; ++A) {
+  for (int A = 0; A < Ne; ++A) {
     const DevElem& el = P.elems[elem[A]];
     for (int s = 0; s < el.nsh; ++s) {
       sh_atom.push_back(A);
@@ -717,7 +859,7 @@ void Ctx::set_system(int32_t n_atoms, const int32_t* Z, const double* xyz, int32
   Nsh = (int)sh_atom.size();
   {
     std::vector<double> nsh_f(F, 0.0);
-    for (int A = 0; A < N; ++A) nsh_f[frag[A]] += atom_sh0_g[A + 1] - atom_sh0_g[A];
+    for (int A = 0; A < Ne; ++A) nsh_f[frag[A]] += atom_sh0_g[A + 1] - atom_sh0_g[A];
     field_pairs = (double)Nsh * Nsh;
     for (double v : nsh_f) field_pairs -= v * v;
   }
@@ -733,7 +875,10 @@ void Ctx::set_system(int32_t n_atoms, const int32_t* Z, const double* xyz, int32
   d_sh_ieta.upload(sh_ieta);
   d_frag_atoms.upload(frag_atoms);
   d_frag_off.upload(frag_off);
-  d_cn.alloc(N);
+  d_frag_atoms_real.upload(frag_atoms_real);
+  d_frag_off_real.upload(frag_off_real);
+  d_bonds.upload(bonds.empty() ? std::vector<int>{0, 0} : bonds);
+  d_cn.alloc(Ne);
   d_q.alloc(Nsh);
   d_qnew.alloc(Nsh);
   d_phi.alloc(Nsh);
@@ -750,6 +895,8 @@ void Ctx::set_system(int32_t n_atoms, const int32_t* Z, const double* xyz, int32
 void Ctx::run(fx_result* out) {
   if (!has_system) throw FxError(FX_E_STATE, "no system set");
   if (opt.precision != FX_FP64) throw FxError(FX_E_UNSUPPORTED, "only FX_FP64 is available");
+  if (NB > 0 && opt.want_gradient)
+    throw FxError(FX_E_UNSUPPORTED, "the gradient with cut covalent bonds is not available");
   std::memset(&res, 0, sizeof(res));
   ktimers.clear();
   bool all_conv = true;
@@ -884,7 +1031,7 @@ void Ctx::run(fx_result* out) {
     std::vector<std::array<int, 3>> cl(nscc);
     for (long long k = 0; k < nscc; ++k) cl[k] = {scc_pairs[2 * k], scc_pairs[2 * k + 1], -1};
     build_batch(db_, cl, 2);
-    db_.init_from_mono = true;
+    db_.init_from_mono = !db_.has_healed;
     build_matrices(db_);
     DevBatch ddb = db_.dev();
     hipLaunchKernelGGL(k_cluster_phi, dim3(db_.nsys), dim3(128), 0, stream, dev_system(), ddb, d_phi.p, d_q.p);
@@ -898,6 +1045,9 @@ void Ctx::run(fx_result* out) {
     ddq_scc.alloc(db_.tot_sh);
     hipLaunchKernelGGL(k_cluster_terms, dim3(db_.nsys), dim3(256), 0, stream, ddb, d_q.p, e_mono.p, ddq_scc.p,
                        dEV_scc.p, dE_scc.p);
+    if (db_.has_healed)
+      hipLaunchKernelGGL(k_cluster_healed, dim3(db_.nsys), dim3(128), 0, stream, dev_system(), ddb, d_phi.p, d_q.p,
+                         dEV_scc.p, dE_scc.p);
     check(hipGetLastError(), "k_cluster_terms");
   }
   sync();
@@ -910,7 +1060,7 @@ void Ctx::run(fx_result* out) {
     std::vector<std::array<int, 3>> cl(ntri);
     for (long long k = 0; k < ntri; ++k) cl[k] = {trimers[3 * k], trimers[3 * k + 1], trimers[3 * k + 2]};
     build_batch(tb_, cl, 3);
-    tb_.init_from_mono = true;
+    tb_.init_from_mono = !tb_.has_healed;
     build_matrices(tb_);
     DevBatch dtb = tb_.dev();
     hipLaunchKernelGGL(k_cluster_phi, dim3(tb_.nsys), dim3(128), 0, stream, dev_system(), dtb, d_phi.p, d_q.p);
@@ -927,6 +1077,9 @@ void Ctx::run(fx_result* out) {
     dEX.alloc(ntri);
     hipLaunchKernelGGL(k_cluster_terms, dim3(tb_.nsys), dim3(256), 0, stream, dtb, d_q.p, e_mono.p, ddq.p, dEV.p,
                        dEX.p);
+    if (tb_.has_healed)
+      hipLaunchKernelGGL(k_cluster_healed, dim3(tb_.nsys), dim3(128), 0, stream, dev_system(), dtb, d_phi.p, d_q.p,
+                         dEV.p, dEX.p);
     trimer_dEIJK.resize(ntri);
     dEX.download(trimer_dEIJK, stream);
     sync();
@@ -1116,9 +1269,9 @@ int fx_set_options(fx_ctx* ctx, const fx_options* o) {
 }
 
 int fx_set_system(fx_ctx* ctx, int32_t n_atoms, const int32_t* Z, const double* xyz_bohr, int32_t n_frag,
-                  const int32_t* atom_frag, const int32_t* frag_charge) {
+                  const int32_t* atom_frag, const int32_t* frag_charge, int32_t n_bonds, const int32_t* bonds) {
   if (!ctx) return FX_E_INVALID;
-  FX_GUARD(ctx, ctx->c.set_system(n_atoms, Z, xyz_bohr, n_frag, atom_frag, frag_charge));
+  FX_GUARD(ctx, ctx->c.set_system(n_atoms, Z, xyz_bohr, n_frag, atom_frag, frag_charge, n_bonds, bonds));
 }
 
 int fx_build_lists(fx_ctx* ctx, fx_counts* out) {

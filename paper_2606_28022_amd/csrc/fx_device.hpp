@@ -27,7 +27,7 @@ struct DevElem {
 };
 
 struct DevGlobals {
-  double kg, kf, kEN, k1, k2, kl[3], KAB, kT;
+  double kg, kf, kEN, k1, k2, kl[3], KAB, kT, VHOP;
 };
 
 struct SysDesc {
@@ -36,6 +36,7 @@ struct SysDesc {
   int sh_off;     // into per-system shell vectors
   int ao_off;     // into per-system AO vectors
   int frag[3];
+  int comp_sh[4];     // local shell offset of each fragment's block (comp_sh[nfrag] = nsh)
   long long mat_off;  // into n x n pools
   long long gam_off;  // into the nsh x nsh gamma pool
   double nel;
@@ -50,6 +51,7 @@ struct Slots {
 // Read-only supersystem tables.
 struct DevSystem {
   int natoms, nshells, nfrag;
+  int nreal;              // real atoms (the first nreal); the rest are ghosts
   const double* xyz;      // [3N]
   const int* elem;        // [N] element table index
   const int* frag;        // [N]
@@ -85,6 +87,16 @@ struct DevBatch {
   double* phi;   // external shell potential
   double* sig;   // shell shift of the last Fock build
   const float* pre;  // nsh x nsh mixing preconditioner per system (gam layout) or null
+  const double* sh_q0;     // per local shell reference population (null: element values)
+  const double* atom_zs;   // per local atom repulsion-charge scale (null: 1)
+  double* Vh;              // HOP projector S D S per system (mat layout) or null
+  const int* hop_off;      // [nsys+1] boundary atoms of each system
+  const int* hop_atom;
+  const int* hop_kind;     // 1 detached atom, 2 ghost
+  const double* hop_b;     // [3] unit bond vector per entry
+  const int* healed_off;   // [nsys+1] ghosts healed inside each system (or null)
+  const int* healed_sh;    // their global shells
+  const int* sh_mono;      // per local shell: its index within its fragment's monomer
   double* hx;    // Anderson history of inputs  [sh_off*HIST + k*nsh + s]
   double* hr;    // Anderson history of residuals
   double* eps;

@@ -348,7 +348,7 @@ __global__ void k_cn_grad(DevSystem sys, const double* Ftot, double* g) {
   int C = blockIdx.x * blockDim.x + threadIdx.x;
   __shared__ double sx[256], sy[256], sz[256], sr[256], sF[256];
   double xc = 0, yc = 0, zc = 0, rc = 0, Fc = 0;
-  if (C < sys.natoms) {
+  if (C < sys.nreal) {
     xc = sys.xyz[3 * C];
     yc = sys.xyz[3 * C + 1];
     zc = sys.xyz[3 * C + 2];
@@ -356,10 +356,10 @@ __global__ void k_cn_grad(DevSystem sys, const double* Ftot, double* g) {
     Fc = Ftot[C];
   }
   double f[3] = {0.0, 0.0, 0.0};
-  for (int b0 = 0; b0 < sys.natoms; b0 += 256) {
+  for (int b0 = 0; b0 < sys.nreal; b0 += 256) {
     int b = b0 + threadIdx.x;
     __syncthreads();
-    if (b < sys.natoms) {
+    if (b < sys.nreal) {
       sx[threadIdx.x] = sys.xyz[3 * b];
       sy[threadIdx.x] = sys.xyz[3 * b + 1];
       sz[threadIdx.x] = sys.xyz[3 * b + 2];
@@ -367,8 +367,8 @@ __global__ void k_cn_grad(DevSystem sys, const double* Ftot, double* g) {
       sF[threadIdx.x] = Ftot[b];
     }
     __syncthreads();
-    int nb = min(256, sys.natoms - b0);
-    if (C < sys.natoms) {
+    int nb = min(256, sys.nreal - b0);
+    if (C < sys.nreal) {
       for (int k = 0; k < nb; ++k) {
         if (b0 + k == C) continue;
         double dx = xc - sx[k], dy = yc - sy[k], dz = zc - sz[k];
@@ -384,7 +384,7 @@ __global__ void k_cn_grad(DevSystem sys, const double* Ftot, double* g) {
       }
     }
   }
-  if (C < sys.natoms)
+  if (C < sys.nreal)
     for (int k = 0; k < 3; ++k) g[3 * C + k] = f[k];
 }
 

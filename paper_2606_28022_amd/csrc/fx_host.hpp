@@ -118,6 +118,12 @@ struct Batch {
   // gam layout); used by the mixer when has_pre is set
   DevBuf<float> pre;
   bool has_pre = false;
+  // covalent boundaries: per local shell reference population, per local atom
+  // repulsion-charge scale, boundary atoms (local atom, kind 1 detached /
+  // 2 ghost, bond direction) and the ghosts healed inside each system
+  bool has_hop = false, has_healed = false;
+  DevBuf<double> sh_q0, atom_zs, hop_b, Vh;
+  DevBuf<int> hop_off, hop_atom, hop_kind, healed_off, healed_sh, sh_mono;
   long long tot_gam = 0;
   DevBatch dev();
   // algorithmic work of one n x n product (2 n^3) summed over listed systems
@@ -177,7 +183,13 @@ struct Ctx {
 
   // supersystem
   bool has_system = false, lists_built = false, has_result = false, has_grad = false;
-  int N = 0, F = 0, Nsh = 0;
+  // N real atoms; Ne = N + NB atoms with one ghost per cut covalent bond
+  // (a copy of the detached atom in the attached atom's fragment)
+  int N = 0, F = 0, Nsh = 0, NB = 0, Ne = 0;
+  std::vector<int> bonds;                    // [NB][2] detached, attached
+  std::vector<std::vector<int>> bda_bonds, ghost_bonds;  // per fragment
+  std::vector<int> frag_off_real, frag_atoms_real;
+  DevBuf<int> d_frag_atoms_real, d_frag_off_real, d_bonds;
   double field_pairs = 0.0;  // inter-fragment shell pairs of one field pass
   std::vector<int> elem, frag, frag_charge, frag_off, frag_atoms, atom_sh0_g;
   std::vector<double> xyz_h, guess;
@@ -259,14 +271,14 @@ struct Ctx {
   void sync();
   DevSystem dev_system() const;
   void set_system(int32_t n_atoms, const int32_t* Z, const double* xyz, int32_t n_frag, const int32_t* atom_frag,
-                  const int32_t* fchg);
+                  const int32_t* fchg, int32_t n_bonds, const int32_t* bonds);
   void build_lists_impl();
   void compute_cn();
   void field(const double* d_q, double* d_phi);
   void build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters, int nfrag_each);
   void build_matrices(Batch& b);
   void init_device();
-  JacobiPlan jacobi_plan(int n) const;
+  JacobiPlan jacobi_plan(int n, bool fp64_only = false) const;
   void gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlist, int mode, const double* A,
                   const double* B, double* C, const double* w, double gflop);
   int run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* iters_out, bool single = false);

@@ -29,25 +29,25 @@ __global__ void k_cn(DevSystem sys, double* cn_out) {
   int A = blockIdx.x * blockDim.x + threadIdx.x;
   __shared__ double sx[256], sy[256], sz[256], sr[256];
   double xa = 0, ya = 0, za = 0, ra = 0;
-  if (A < sys.natoms) {
+  if (A < sys.nreal) {
     xa = sys.xyz[3 * A];
     ya = sys.xyz[3 * A + 1];
     za = sys.xyz[3 * A + 2];
     ra = sys.elems[sys.elem[A]].rcov;
   }
   double acc = 0.0;
-  for (int b0 = 0; b0 < sys.natoms; b0 += 256) {
+  for (int b0 = 0; b0 < sys.nreal; b0 += 256) {
     int b = b0 + threadIdx.x;
     __syncthreads();
-    if (b < sys.natoms) {
+    if (b < sys.nreal) {
       sx[threadIdx.x] = sys.xyz[3 * b];
       sy[threadIdx.x] = sys.xyz[3 * b + 1];
       sz[threadIdx.x] = sys.xyz[3 * b + 2];
       sr[threadIdx.x] = sys.elems[sys.elem[b]].rcov;
     }
     __syncthreads();
-    int nb = min(256, sys.natoms - b0);
-    if (A < sys.natoms) {
+    int nb = min(256, sys.nreal - b0);
+    if (A < sys.nreal) {
       for (int k = 0; k < nb; ++k) {
         if (b0 + k == A) continue;
         double dx = xa - sx[k], dy = ya - sy[k], dz = za - sz[k];
@@ -57,7 +57,7 @@ __global__ void k_cn(DevSystem sys, double* cn_out) {
       }
     }
   }
-  if (A < sys.natoms) cn_out[A] = acc;
+  if (A < sys.nreal) cn_out[A] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -211,7 +211,8 @@ __global__ void k_build_system(DevSystem sys, DevBatch bt, const int* list) {
           }
       }
     double al = sqrt(ea.arep * eb.arep);
-    erep += ea.zeff * eb.zeff / R * exp(-al * pow(R, sys.g.kf));
+    const double zs = bt.atom_zs ? bt.atom_zs[d.atom_off + a] * bt.atom_zs[d.atom_off + b] : 1.0;
+    erep += zs * ea.zeff * eb.zeff / R * exp(-al * pow(R, sys.g.kf));
   }
   // gamma of the system's shells
   double* G = bt.gam + d.gam_off;
@@ -240,6 +241,12 @@ __global__ void k_build_system(DevSystem sys, DevBatch bt, const int* list) {
 // One thread per target atom (all its shells); the source atoms are split
 // into `nchunk` slices handled by separate work-groups, whose partial sums
 // are combined in fixed order by k_field_reduce (deterministic).
+// CN of each ghost atom: that of the detached atom it copies
+__global__ void k_ghost_cn(DevSystem sys, const int* bonds, int nbonds, double* cn) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nbonds) cn[sys.nreal + k] = cn[bonds[2 * k]];
+}
+
 __global__ void __launch_bounds__(256) k_field_partial(DevSystem sys, const double* q, int nchunk, double* part) {
   const int A = blockIdx.x * blockDim.x + threadIdx.x;
   const int chunk = blockIdx.y;
@@ -335,7 +342,101 @@ __global__ void k_cluster_phi(DevSystem sys, DevBatch bt, const double* Phi, con
       if (sys.sh_frag[gt] == fs) continue;
       v -= bt.gam[d.gam_off + (long long)s * d.nsh + t] * qmono[gt];
     }
+    if (bt.healed_off) {
+      // ghosts healed inside the cluster belong to its fragments but are not
+      // part of its basis: their monomer charges are not environment either
+      const double xs = sys.xyz[3 * sys.sh_atom[gs]], ys = sys.xyz[3 * sys.sh_atom[gs] + 1],
+                   zs = sys.xyz[3 * sys.sh_atom[gs] + 2];
+      for (int e = bt.healed_off[si]; e < bt.healed_off[si + 1]; ++e) {
+        const int gt = bt.healed_sh[e];
+        if (sys.sh_frag[gt] == fs) continue;
+        const int At = sys.sh_atom[gt];
+        const double dx = xs - sys.xyz[3 * At], dy = ys - sys.xyz[3 * At + 1], dz = zs - sys.xyz[3 * At + 2];
+        v -= gamma_fn(sys.g, dx * dx + dy * dy + dz * dz, sys.sh_eta[gs], sys.sh_eta[gt]) * qmono[gt];
+      }
+    }
     bt.phi[d.sh_off + s] = v;
+  }
+}
+
+// Embedding correction of the ghosts healed inside a cluster: their charge
+// transfer is minus the monomer ghost charge (eq. ctij_ghost), acting on the
+// environment potential at the ghost shells:
+//   dEV += sum_g (-q_g) (Phi_g - sum_{t in cluster, other fragment} gamma_gt q_t)
+// with the cluster's own shells and its other healed ghosts as t.
+__global__ void k_cluster_healed(DevSystem sys, DevBatch bt, const double* Phi, const double* qmono, double* dEV,
+                                 double* dE) {
+  const int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const int e0 = bt.healed_off[si], e1 = bt.healed_off[si + 1];
+  __shared__ double red[128];
+  double loc = 0.0;
+  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int g = bt.healed_sh[e];
+    const int fg = sys.sh_frag[g];
+    const int Ag = sys.sh_atom[g];
+    const double xg = sys.xyz[3 * Ag], yg = sys.xyz[3 * Ag + 1], zg = sys.xyz[3 * Ag + 2];
+    double v = Phi[g];
+    for (int t = 0; t < d.nsh; ++t) {
+      const int gt = bt.sys_sh_global[d.sh_off + t];
+      if (sys.sh_frag[gt] == fg) continue;
+      const int At = sys.sh_atom[gt];
+      const double dx = xg - sys.xyz[3 * At], dy = yg - sys.xyz[3 * At + 1], dz = zg - sys.xyz[3 * At + 2];
+      v -= gamma_fn(sys.g, dx * dx + dy * dy + dz * dz, sys.sh_eta[g], sys.sh_eta[gt]) * qmono[gt];
+    }
+    for (int e2 = e0; e2 < e1; ++e2) {
+      const int gt = bt.healed_sh[e2];
+      if (sys.sh_frag[gt] == fg) continue;
+      const int At = sys.sh_atom[gt];
+      const double dx = xg - sys.xyz[3 * At], dy = yg - sys.xyz[3 * At + 1], dz = zg - sys.xyz[3 * At + 2];
+      v -= gamma_fn(sys.g, dx * dx + dy * dy + dz * dz, sys.sh_eta[g], sys.sh_eta[gt]) * qmono[gt];
+    }
+    loc += -qmono[g] * v;
+  }
+  red[threadIdx.x] = loc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && e1 > e0) {
+    dEV[si] += red[0];
+    dE[si] += red[0];
+  }
+}
+
+// HOP projector of each system, V = S D S (eq. vhop): D = V_HOP h h^T on a
+// detached atom (eq. dd_bda), V_HOP (1_sp - h h^T) on a ghost (eq. dd_ghost),
+// h = 1/2 s + sqrt(3)/2 (b . p) the bond-pointing sp3 hybrid (eq. hybrid).
+__global__ void k_vhop(DevBatch bt, double vhop) {
+  const int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao;
+  double* Vh = bt.Vh + d.mat_off;
+  const double* S = bt.S + d.mat_off;
+  const int e0 = bt.hop_off[si], e1 = bt.hop_off[si + 1];
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int mu = idx / n, nu = idx - mu * n;
+    double v = 0.0;
+    for (int e = e0; e < e1; ++e) {
+      const int o = bt.sys_atom_ao0[d.atom_off + bt.hop_atom[e]];
+      const double* b = bt.hop_b + 3 * e;
+      const double h[4] = {0.5, 0.8660254037844386 * b[0], 0.8660254037844386 * b[1], 0.8660254037844386 * b[2]};
+      double xm[4], xn[4];
+      for (int l = 0; l < 4; ++l) {
+        xm[l] = S[(long long)mu * n + o + l];
+        xn[l] = S[(long long)(o + l) * n + nu];
+      }
+      const double hm = h[0] * xm[0] + h[1] * xm[1] + h[2] * xm[2] + h[3] * xm[3];
+      const double hn = h[0] * xn[0] + h[1] * xn[1] + h[2] * xn[2] + h[3] * xn[3];
+      if (bt.hop_kind[e] == 1) {
+        v += vhop * hm * hn;
+      } else {
+        const double xx = xm[0] * xn[0] + xm[1] * xn[1] + xm[2] * xn[2] + xm[3] * xn[3];
+        v += vhop * (xx - hm * hn);
+      }
+    }
+    Vh[idx] = v;
   }
 }
 

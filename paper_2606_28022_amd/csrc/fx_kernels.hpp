@@ -19,6 +19,10 @@ __global__ void k_esd_pairs(DevSystem sys, const int* pairs, long long npairs, c
                             const int* frag_off, const double* q, double* out);
 
 // SCC (fx_scc.hip)
+__global__ void k_cluster_healed(DevSystem sys, DevBatch bt, const double* Phi, const double* qmono, double* dEV,
+                                 double* dE);
+__global__ void k_vhop(DevBatch bt, double vhop);
+__global__ void k_ghost_cn(DevSystem sys, const int* bonds, int nbonds, double* cn);
 __global__ void k_reset_state(DevBatch bt, const int* list, int nl, int keep_err);
 __global__ void k_precond_step(DevBatch bt, double* out);
 __global__ void k_cholinv(DevBatch bt, const int* list, const double* Apool, double* Lpool, double* Xpool);

@@ -178,10 +178,11 @@ __global__ void k_fock(DevSystem sys, DevBatch bt, const int* list) {
   const double* S = bt.S + d.mat_off;
   const double* H = bt.H0 + d.mat_off;
   double* Fm = bt.F + d.mat_off;
+  const double* Vh = bt.Vh ? bt.Vh + d.mat_off : nullptr;
   const int* aosh = bt.sys_ao_sh + d.ao_off;
   for (long long idx = threadIdx.x; idx < (long long)n * n; idx += blockDim.x) {
     int i = (int)(idx / n), j = (int)(idx - (long long)i * n);
-    Fm[idx] = H[idx] + 0.5 * S[idx] * (sig_s[aosh[i]] + sig_s[aosh[j]]);
+    Fm[idx] = H[idx] + 0.5 * S[idx] * (sig_s[aosh[i]] + sig_s[aosh[j]]) + (Vh ? Vh[idx] : 0.0);
   }
 }
 
@@ -655,7 +656,7 @@ __global__ void k_charges_mix(DevSystem sys, DevBatch bt, const int* list, doubl
     int A = bt.sys_atoms[d.atom_off + a];
     const DevElem& el = sys.elems[sys.elem[A]];
     int ls = s - bt.sys_atom_sh0[d.atom_off + a];
-    qo[s] = v - el.q0[ls];
+    qo[s] = v - (bt.sh_q0 ? bt.sh_q0[d.sh_off + s] : el.q0[ls]);
   }
   __syncthreads();
   for (int a = threadIdx.x; a < d.nat; a += blockDim.x) {
@@ -846,7 +847,10 @@ __global__ void __launch_bounds__(1024)
     const double v = A[e];
     if (i == j) {
       dg[i] = v;
-      loc += v * v;
+      // diagonal entries count at most 10 Eh: a projector shift (section
+      // "Covalent bond fragmentation", 1e6 Eh) must not loosen the threshold
+      // of the physical orbitals
+      loc += fmin(v * v, 100.0);
     } else {
       Ap[pk_index(i, j)] = (T)v;
       loc += 2.0 * v * v;
@@ -864,7 +868,7 @@ __global__ void __launch_bounds__(1024)
   double* col = vt + (long long)wave * (n + 1);
   int sweep = 0;
   for (; sweep < msw; ++sweep) {
-    double maxoff = 0.0;
+    int rot_sweep = 0;
     for (int s0 = 0; s0 < m - 1; s0 += chunk) {
       const int s1 = min(m - 1, s0 + chunk);
       int rot_local = 0;
@@ -884,9 +888,10 @@ __global__ void __launch_bounds__(1024)
           if (q < n) {
             const int ipq = pk_index(p, q);
             const double apq = (double)Ap[ipq];
-            maxoff = fmax(maxoff, fabs(apq));
-            if (fabs(apq) > thr) {
-              const double app = dg[p], aqq = dg[q];
+            const double app = dg[p], aqq = dg[q];
+            // a pair is converged below the absolute threshold or at FP64
+            // resolution of its larger diagonal entry
+            if (fabs(apq) > fmax(thr, rel_tol * fmax(fabs(app), fabs(aqq)))) {
               const double theta = (aqq - app) / (2.0 * apq);
               const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
               c = 1.0 / sqrt(t * t + 1.0);
@@ -943,6 +948,7 @@ __global__ void __launch_bounds__(1024)
       // apply the chunk's rotations to the rows of V, nw columns at a time:
       // coalesced tile loads (next tile prefetched into registers), one
       // column per wave, coalesced stores
+      rot_sweep |= rot_local;
       if (__syncthreads_or(rot_local)) {
         double rg[8];
 #pragma unroll
@@ -995,8 +1001,8 @@ __global__ void __launch_bounds__(1024)
         }
       }
     }
-    const double mo = wblock_max(maxoff, red);
-    if (mo <= thr) break;
+    // converged when no pair rotated in this sweep
+    if (!__syncthreads_or(rot_sweep)) break;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += nt) bt.eps[d.ao_off + i] = dg[i];
@@ -1036,13 +1042,11 @@ __global__ void __launch_bounds__(256)
   const double* G = bt.gam + d.gam_off;
   const double* q = bt.q_in + d.sh_off;
   if (threadIdx.x == 0) {
-    int off = 0;
     for (int c = 0; c < d.nfrag; ++c) {
       comp_frag[c] = d.frag[c];
-      comp_off[c] = off;
-      off += mono.desc[d.frag[c]].nsh;
+      comp_off[c] = d.comp_sh[c];
     }
-    comp_off[d.nfrag] = off;
+    comp_off[d.nfrag] = d.comp_sh[d.nfrag];
   }
   for (int a = threadIdx.x; a < d.nat; a += blockDim.x) {
     const int s0 = bt.sys_atom_sh0[d.atom_off + a];
@@ -1057,9 +1061,10 @@ __global__ void __launch_bounds__(256)
     const int s = idx / ns, t = idx - s * ns;
     int c = 0;
     while (c + 1 < d.nfrag && s >= comp_off[c + 1]) ++c;
-    const int k0 = comp_off[c], k1 = comp_off[c + 1], nsf = k1 - k0;
+    const int k0 = comp_off[c], k1 = comp_off[c + 1];
     const SysDesc md = mono.desc[comp_frag[c]];
-    const double* Mr = Mmono + md.gam_off + (long long)(s - k0) * nsf;
+    const int* smap = bt.sh_mono + d.sh_off;
+    const double* Mr = Mmono + md.gam_off + (long long)smap[s] * md.nsh;
     const int at = bt.sys_sh_atom[d.sh_off + t];
     const int Aat = bt.sys_atoms[d.atom_off + at];
     const double g3 = 2.0 * sys.elems[sys.elem[Aat]].Gamma * qa[at];
@@ -1067,7 +1072,7 @@ __global__ void __launch_bounds__(256)
     for (int k = k0; k < k1; ++k) {
       double g = G[(long long)k * ns + t];
       if (bt.sys_sh_atom[d.sh_off + k] == at) g -= g3;
-      v += Mr[k - k0] * g;
+      v += Mr[smap[k]] * g;
     }
     Kf[idx] = (float)v;
   }

@@ -28,6 +28,10 @@ def case_system(name):
         return w.anthracene_crystal(reps=(2, 2, 1)).subset(list(range(5))), 4 * A2B, 3
     if name == "droplet128":
         return w.water_droplet(128, radius=9.8, seed=22), 4 * A2B, 2
+    if name == "ala4_fmo3":
+        return w.alanine_helix(4), 4 * A2B, 3
+    if name == "ala10":
+        return w.alanine_helix(10), 4 * A2B, 2
     raise KeyError(name)
 
 
@@ -43,7 +47,11 @@ def make(name):
     if order >= 3:
         out["dE_tri"] = list(map(float, r.dE_tri))
         out["trimers"] = r.lists[2].tolist()
-    if order == 2:
+    if order >= 3:
+        out["E_fmo2"] = r.E_fmo2
+    if len(s.bonds):
+        out["bonds"] = s.bonds.tolist()
+    if order == 2 and not len(s.bonds):
         g, _ = F.fmo2_gradient(s, p, r)
         out["grad"] = g.tolist()
     out["oracle_seconds"] = time.time() - t
@@ -53,5 +61,5 @@ def make(name):
 
 
 if __name__ == "__main__":
-    for n in (sys.argv[1:] or ["pentacene6", "anthracene5_fmo3", "droplet128"]):
+    for n in (sys.argv[1:] or ["pentacene6", "anthracene5_fmo3", "droplet128", "ala4_fmo3", "ala10"]):
         make(n)

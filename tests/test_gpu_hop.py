@@ -1,0 +1,107 @@
+"""Covalent fragmentation (hybrid-orbital projectors) on the GPU vs the FP64
+oracle, through the C ABI: alanine helices, one residue per fragment, CA-C
+bonds cut (section "Covalent bond fragmentation").  Energies to 1e-8 Eh per
+fragment term; charges (ghost shells included, after the real ones) to 1e-8.
+"""
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import workloads as w
+from oracle import fmo as F
+
+A2B = w.ANGSTROM_TO_BOHR
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _golden(name):
+    path = os.path.join(HERE, "golden", name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    with open(path) as f:
+        return json.load(f)
+
+
+def _gpu(s, order=2, **opt):
+    from paper_2606_28022_amd import FmoXtb
+    c = FmoXtb()
+    c.set_system(s.Z, s.xyz, s.frag, s.frag_charge, bonds=s.bonds)
+    c.set_options(want_gradient=0, order=order, **opt)
+    r = c.run()
+    return r, c
+
+
+def test_hop_two_fragments(params):
+    _say("HOP ala2 FMO2")
+    s = w.alanine_helix(2)
+    r, c = _gpu(s)
+    ro = F.fmo(s, params, 4 * A2B, order=2)
+    assert abs(r["e_total"] - ro.E) < 1e-8
+    em, ds, de, _ = c.energies()
+    assert np.max(np.abs(em - ro.E_mono)) < 1e-8
+    q = c.charges()
+    assert q.shape == ro.q.shape
+    assert np.max(np.abs(q - ro.q)) < 1e-8
+
+
+def test_hop_ala4_fmo3(params):
+    _say("HOP ala4 FMO3")
+    ref = _golden("ala4_fmo3")
+    s = w.alanine_helix(4)
+    r, c = _gpu(s, order=3)
+    em, ds, de, dt = c.energies()
+    assert np.max(np.abs(em - np.array(ref["E_mono"]))) < 1e-8
+    assert np.max(np.abs(ds - np.array(ref["dE_scc"]))) < 1e-8
+    assert np.max(np.abs(dt - np.array(ref["dE_tri"]))) < 1e-8
+    assert abs(r["e_fmo2"] - ref["E_fmo2"]) < 1e-8 * s.n_frag
+    assert abs(r["e_total"] - ref["E"]) < 1e-8 * s.n_frag
+    assert np.max(np.abs(c.charges() - np.array(ref["q"]))) < 1e-8
+
+
+def test_hop_ala10(params):
+    _say("HOP ala10 FMO2")
+    ref = _golden("ala10")
+    s = w.alanine_helix(10)
+    r, c = _gpu(s)
+    em, ds, de, _ = c.energies()
+    assert np.max(np.abs(em - np.array(ref["E_mono"]))) < 1e-8
+    assert np.max(np.abs(ds - np.array(ref["dE_scc"]))) < 1e-8
+    assert np.max(np.abs(de - np.array(ref["dE_esd"]))) < 1e-9
+    assert abs(r["e_total"] - ref["E"]) < 1e-8 * s.n_frag
+
+
+def test_hop_gradient_unsupported():
+    from paper_2606_28022_amd import FmoXtb
+    from paper_2606_28022_amd.binding import FxError
+    s = w.alanine_helix(2)
+    c = FmoXtb()
+    c.set_system(s.Z, s.xyz, s.frag, s.frag_charge, bonds=s.bonds)
+    c.set_options(want_gradient=1)
+    with pytest.raises(FxError):
+        c.run()
+
+
+def test_hop_invalid_bonds():
+    from paper_2606_28022_amd import FmoXtb
+    from paper_2606_28022_amd.binding import FxError
+    s = w.alanine_helix(2)
+    c = FmoXtb()
+    bad = s.bonds.copy()
+    bad[0, 1] = bad[0, 0] + 1          # both ends in one fragment
+    with pytest.raises(FxError):
+        c.set_system(s.Z, s.xyz, s.frag, s.frag_charge, bonds=bad)
+    bad = s.bonds.copy()
+    bad[0, 0] = s.n_atoms + 5          # out of range
+    with pytest.raises(FxError):
+        c.set_system(s.Z, s.xyz, s.frag, s.frag_charge, bonds=bad)

@@ -17,3 +17,4 @@ from .geometry import (  # noqa: F401
     load_params_json,
     params_path,
 )
+from .peptide import alanine_helix  # noqa: F401

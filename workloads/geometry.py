@@ -38,6 +38,10 @@ class System:
     frag: np.ndarray         # int32 [N] fragment index of each atom
     frag_charge: np.ndarray  # int32 [F] net charge of each fragment
     meta: dict = field(default_factory=dict)
+    # covalent bonds cut by the fragmentation, one row (detached atom, attached
+    # atom) per bond: the first atom stays in its fragment, the second belongs
+    # to the neighbouring fragment
+    bonds: np.ndarray = field(default_factory=lambda: np.zeros((0, 2), dtype=np.int32))
 
     @property
     def n_atoms(self):
@@ -53,11 +57,17 @@ class System:
         frags = list(frags)
         mask = np.isin(self.frag, frags)
         remap = {f: i for i, f in enumerate(frags)}
+        new_index = -np.ones(self.n_atoms, dtype=np.int64)
+        new_index[np.where(mask)[0]] = np.arange(int(mask.sum()))
+        if len(self.bonds) and not all(mask[a] == mask[b] for a, b in self.bonds):
+            raise ValueError("subset would leave a cut bond with one end outside")
+        kept = [(new_index[a], new_index[b]) for a, b in self.bonds if mask[a]]
         return System(
             name=f"{self.name}[{','.join(map(str, frags))}]",
             Z=self.Z[mask].copy(), xyz=self.xyz[mask].copy(),
             frag=np.array([remap[f] for f in self.frag[mask]], dtype=np.int32),
-            frag_charge=self.frag_charge[frags].copy(), meta=dict(self.meta))
+            frag_charge=self.frag_charge[frags].copy(), meta=dict(self.meta),
+            bonds=np.array(kept, dtype=np.int32).reshape(-1, 2))
 
 
 # --------------------------------------------------------------------------
