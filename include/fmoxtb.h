@@ -54,7 +54,7 @@ enum {
 
 enum { FX_FP64 = 0, FX_MIXED = 1 };           /* precision */
 enum { FX_BATCHED = 0, FX_PLAIN_LOOP = 1 };   /* schedule of the fragment solves */
-enum { FX_GUESS_SUPERPOSITION = 0, FX_GUESS_USER = 2 };
+enum { FX_GUESS_SUPERPOSITION = 0, FX_GUESS_LEARNED = 1, FX_GUESS_USER = 2 };
 
 typedef struct fx_params fx_params;
 typedef struct fx_ctx fx_ctx;
@@ -68,8 +68,15 @@ typedef struct fx_options {
   int32_t precision;      /* FX_FP64 (FX_MIXED is reserved; FX_E_UNSUPPORTED) */
   int32_t schedule;       /* FX_BATCHED: all fragments of a kind in one launch
                              sequence; FX_PLAIN_LOOP: one fragment at a time */
-  int32_t guess;          /* initial monomer charges: superposition (zero) or
-                             the charges given with fx_set_guess */
+  int32_t guess;          /* initial monomer charges: superposition (zero),
+                             the learned model (fx_mlp_load) or the charges
+                             given with fx_set_guess */
+  double guess_tau;       /* learned guess: a monomer whose first SCC
+                             residual exceeds guess_tau restarts from
+                             superposition charges (<= 0: never) */
+  int32_t guess_max_iter; /* learned guess: a monomer not converged after this
+                             many iterations of its first solve restarts from
+                             superposition charges (<= 0: never) */
   double scc_tol;         /* SCC convergence: max |dq_out - dq_in| */
   double energy_tol;      /* SCC convergence: |E_k - E_(k-1)| */
   double macro_tol;       /* monomer loop: max change of any monomer charge */
@@ -110,6 +117,9 @@ typedef struct fx_result {
   int64_t solves_mono, solves_dimer, solves_trimer;  /* fragment SCC solves */
   int64_t iters_mono, iters_dimer, iters_trimer;     /* SCC iterations, summed */
   double ms_lists, ms_monomer, ms_dimer, ms_trimer, ms_energy, ms_gradient, ms_response;
+  int64_t guess_fallbacks;      /* monomers restarted from superposition charges */
+  double first_residual_median; /* median over monomers of the first SCC
+                                   residual max|dq_out - dq_in| of the first solve */
   /* device time of the hot kernels, largest first (see fx_kernel_stat) */
   int32_t n_kstat;
   fx_kernel_stat kstat[FX_MAX_KSTAT];
@@ -219,6 +229,49 @@ int fx_embedding_field(fx_ctx* ctx, const double* dq, double* phi);
  * rows of V (same packing as A: row i of matrix k is eigenvector i). */
 int fx_eigh_batched(fx_ctx* ctx, int32_t nmat, const int32_t* n, const double* A, double* w,
                     double* V);
+
+/* ------------------------------------------------------------------------
+ * Learned initial monomer charges (not part of the paper; its SCC starts
+ * from superposition charges).  Per real atom: 20 features (one-hot H, C, N,
+ * O and 16 radial symmetry functions sum_j exp(-eta (R_ij - Rs_k)^2) fc(R_ij)
+ * over atoms within 6 Angstrom, Rs_k = 0.5 .. 6 Angstrom evenly spaced,
+ * eta = 1/(2 * 0.35^2) Angstrom^-2, fc = (cos(pi R / 6 A) + 1) / 2), and a
+ * 20 -> 64 -> 64 -> 2 perceptron (tanh hidden units) giving the atom's two
+ * shell charges.  The forward pass rounds weights and features to bfloat16
+ * (nearest even) and accumulates in FP32.  Each fragment's guess is shifted
+ * uniformly over its real shells to sum to minus its net charge; ghost
+ * shells start at zero.  Weight vector (FX_MLP_NW values): W1[64][20], b1[64],
+ * W2[64][64], b2[64], W3[2][64], b3[2].  Training keeps FP32 master weights
+ * and Adam moments in the context (beta1 0.9, beta2 0.999, eps 1e-8); the
+ * loss is the mean squared error over atoms and both shells, its gradient is
+ * taken with respect to the bfloat16-rounded weights.
+ * ------------------------------------------------------------------------ */
+#define FX_MLP_NW 5634
+#define FX_MLP_NFEAT 20
+
+/* Load bfloat16 weights (host, n = FX_MLP_NW raw bfloat16 bit patterns) as
+ * the master weights; resets the Adam state.  Errors: FX_E_INVALID. */
+int fx_mlp_load(fx_ctx* ctx, const uint16_t* bf16_weights, int64_t n);
+/* The master weights rounded to bfloat16 (host, n = FX_MLP_NW). */
+int fx_mlp_save(fx_ctx* ctx, uint16_t* bf16_out, int64_t n);
+/* FP32 master weights in / out (host, n = FX_MLP_NW); set resets Adam. */
+int fx_mlp_set_master(fx_ctx* ctx, const float* w, int64_t n);
+int fx_mlp_get_master(fx_ctx* ctx, float* w, int64_t n);
+/* Features of the real atoms of the current system into DEVICE memory
+ * d_features[n_atoms][FX_MLP_NFEAT] (FP32, computed in FP64).  Errors:
+ * FX_E_STATE (no system). */
+int fx_mlp_features(fx_ctx* ctx, float* d_features);
+/* Forward pass on n feature rows (DEVICE pointers): d_out[n][2].  Errors:
+ * FX_E_STATE (no weights loaded). */
+int fx_mlp_infer(fx_ctx* ctx, const float* d_features, float* d_out, int64_t n);
+/* Loss and its gradient on n rows (DEVICE features and labels [n][2]);
+ * loss and grad[FX_MLP_NW] returned to host memory (grad may be NULL). */
+int fx_mlp_grad(fx_ctx* ctx, const float* d_features, const float* d_labels, int64_t n, double* loss,
+                float* grad);
+/* One Adam step of learning rate lr on n rows (DEVICE pointers); *loss
+ * (host, may be NULL) is the loss before the step. */
+int fx_mlp_train_step(fx_ctx* ctx, const float* d_features, const float* d_labels, int64_t n, float lr,
+                      double* loss);
 
 #ifdef __cplusplus
 }

@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 FX_OK, FX_E_INVALID, FX_E_NOMEM, FX_E_DEVICE, FX_E_NOCONV, FX_E_STATE, FX_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 FX_FP64, FX_MIXED = 0, 1
 FX_BATCHED, FX_PLAIN_LOOP = 0, 1
-FX_GUESS_SUPERPOSITION, FX_GUESS_USER = 0, 2
+FX_GUESS_SUPERPOSITION, FX_GUESS_LEARNED, FX_GUESS_USER = 0, 1, 2
+FX_MLP_NW, FX_MLP_NFEAT = 5634, 20
 
 
 class FxError(RuntimeError):
@@ -26,7 +27,8 @@ class FxError(RuntimeError):
 
 class fx_options(C.Structure):
     _fields_ = [("order", C.c_int32), ("cutoff_bohr", C.c_double), ("precision", C.c_int32),
-                ("schedule", C.c_int32), ("guess", C.c_int32), ("scc_tol", C.c_double),
+                ("schedule", C.c_int32), ("guess", C.c_int32), ("guess_tau", C.c_double),
+                ("guess_max_iter", C.c_int32), ("scc_tol", C.c_double),
                 ("energy_tol", C.c_double), ("macro_tol", C.c_double), ("max_iter", C.c_int32),
                 ("max_macro", C.c_int32), ("want_gradient", C.c_int32), ("want_response", C.c_int32)]
 
@@ -49,7 +51,8 @@ class fx_result(C.Structure):
                 ("solves_trimer", C.c_int64), ("iters_mono", C.c_int64), ("iters_dimer", C.c_int64),
                 ("iters_trimer", C.c_int64), ("ms_lists", C.c_double), ("ms_monomer", C.c_double),
                 ("ms_dimer", C.c_double), ("ms_trimer", C.c_double), ("ms_energy", C.c_double),
-                ("ms_gradient", C.c_double), ("ms_response", C.c_double), ("n_kstat", C.c_int32),
+                ("ms_gradient", C.c_double), ("ms_response", C.c_double), ("guess_fallbacks", C.c_int64),
+                ("first_residual_median", C.c_double), ("n_kstat", C.c_int32),
                 ("kstat", fx_kernel_stat * FX_MAX_KSTAT)]
 
     def as_dict(self):
@@ -63,7 +66,9 @@ class fx_result(C.Structure):
 EXPORTS = ["fx_params_load", "fx_params_free", "fx_ctx_create", "fx_ctx_destroy", "fx_last_error",
            "fx_default_options", "fx_set_options", "fx_set_system", "fx_build_lists", "fx_get_counts", "fx_get_lists",
            "fx_set_guess", "fx_run", "fx_get_energies", "fx_get_charges", "fx_get_gradient",
-           "fx_compute_cn", "fx_cluster_matrices", "fx_embedding_field", "fx_eigh_batched"]
+           "fx_compute_cn", "fx_cluster_matrices", "fx_embedding_field", "fx_eigh_batched",
+           "fx_mlp_load", "fx_mlp_save", "fx_mlp_set_master", "fx_mlp_get_master", "fx_mlp_features",
+           "fx_mlp_infer", "fx_mlp_grad", "fx_mlp_train_step"]
 
 _lib = None
 
@@ -79,6 +84,12 @@ def load_library():
     path = lib_path()
     if not os.path.exists(path):
         raise FileNotFoundError(f"{path} is missing: build it with python -m paper_2606_28022_amd.build")
+    # torch's HIP runtime first: the library then binds to the same runtime
+    # (same soname), so device pointers and streams are shared with torch
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(path)
     P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     pI32, pD = C.POINTER(C.c_int32), C.POINTER(C.c_double)
@@ -105,10 +116,20 @@ def load_library():
     L.fx_cluster_matrices.argtypes = [P, I32, pI32, pI32, pD, pD]
     L.fx_embedding_field.argtypes = [P, pD, pD]
     L.fx_eigh_batched.argtypes = [P, I32, pI32, pD, pD, pD]
+    pU16, pF = C.POINTER(C.c_uint16), C.POINTER(C.c_float)
+    L.fx_mlp_load.argtypes = [P, pU16, I64]
+    L.fx_mlp_save.argtypes = [P, pU16, I64]
+    L.fx_mlp_set_master.argtypes = [P, pF, I64]
+    L.fx_mlp_get_master.argtypes = [P, pF, I64]
+    L.fx_mlp_features.argtypes = [P, P]
+    L.fx_mlp_infer.argtypes = [P, P, P, I64]
+    L.fx_mlp_grad.argtypes = [P, P, P, I64, pD, pF]
+    L.fx_mlp_train_step.argtypes = [P, P, P, I64, C.c_float, pD]
     for name in ["fx_params_load", "fx_ctx_create", "fx_default_options", "fx_set_options", "fx_set_system",
                  "fx_build_lists", "fx_get_counts", "fx_get_lists", "fx_set_guess", "fx_run", "fx_get_energies",
                  "fx_get_charges", "fx_get_gradient", "fx_compute_cn", "fx_cluster_matrices",
-                 "fx_embedding_field", "fx_eigh_batched"]:
+                 "fx_embedding_field", "fx_eigh_batched", "fx_mlp_load", "fx_mlp_save", "fx_mlp_set_master",
+                 "fx_mlp_get_master", "fx_mlp_features", "fx_mlp_infer", "fx_mlp_grad", "fx_mlp_train_step"]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -137,6 +158,7 @@ class FmoXtb:
 
     def __init__(self, params_path=None, device=0, stream=None):
         self.L = load_library()
+        self.device = device
         pp = C.c_void_p()
         rc = self.L.fx_params_load((params_path or default_params_path()).encode(), C.byref(pp))
         if rc != FX_OK:
@@ -283,3 +305,55 @@ class FmoXtb:
             o += n * n
             ow += n
         return out
+
+    # -- learned initial guess (device buffers are torch tensors on this
+    # context's device; their pointers are passed through unchanged) ----------
+    def mlp_load(self, bf16_bits):
+        w = np.ascontiguousarray(np.asarray(bf16_bits, dtype=np.uint16))
+        self._check(self.L.fx_mlp_load(self.ctx, _ptr(w, C.c_uint16), len(w)))
+
+    def mlp_save(self):
+        w = np.zeros(FX_MLP_NW, dtype=np.uint16)
+        self._check(self.L.fx_mlp_save(self.ctx, _ptr(w, C.c_uint16), len(w)))
+        return w
+
+    def mlp_set_master(self, w):
+        w = np.ascontiguousarray(np.asarray(w, dtype=np.float32))
+        self._check(self.L.fx_mlp_set_master(self.ctx, _ptr(w, C.c_float), len(w)))
+
+    def mlp_get_master(self):
+        w = np.zeros(FX_MLP_NW, dtype=np.float32)
+        self._check(self.L.fx_mlp_get_master(self.ctx, _ptr(w, C.c_float), len(w)))
+        return w
+
+    def mlp_features(self):
+        import torch
+        out = torch.empty((self.n_atoms, FX_MLP_NFEAT), dtype=torch.float32, device=self._torch_device())
+        self._check(self.L.fx_mlp_features(self.ctx, C.c_void_p(out.data_ptr())))
+        return out
+
+    def mlp_infer(self, feats):
+        import torch
+        x = feats.contiguous()
+        y = torch.empty((x.shape[0], 2), dtype=torch.float32, device=x.device)
+        self._check(self.L.fx_mlp_infer(self.ctx, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), x.shape[0]))
+        return y
+
+    def mlp_grad(self, feats, labels):
+        x, t = feats.contiguous(), labels.contiguous()
+        loss = C.c_double()
+        g = np.zeros(FX_MLP_NW, dtype=np.float32)
+        self._check(self.L.fx_mlp_grad(self.ctx, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()), x.shape[0],
+                                       C.byref(loss), _ptr(g, C.c_float)))
+        return loss.value, g
+
+    def mlp_train_step(self, feats, labels, lr):
+        x, t = feats.contiguous(), labels.contiguous()
+        loss = C.c_double()
+        self._check(self.L.fx_mlp_train_step(self.ctx, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                             x.shape[0], float(lr), C.byref(loss)))
+        return loss.value
+
+    def _torch_device(self):
+        import torch
+        return torch.device("cuda", self.device)

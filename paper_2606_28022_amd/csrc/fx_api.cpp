@@ -123,6 +123,7 @@ HostParams load_params(const std::string& path) {
     el.Gamma = e["Gamma"].d();
     el.zeff = e["zeff"].d();
     el.arep = e["alpha_rep"].d();
+    el.Z = Z;
     P.elem_of_Z[Z] = (int)P.elems.size();
     P.elems.push_back(el);
   }
@@ -516,6 +517,77 @@ void Ctx::build_precond(Batch& b) {
   b.has_pre = true;
 }
 
+// ---------------------------------------------------------------------------
+// learned initial guess
+
+void Ctx::mlp_set_master(const float* w) {
+  std::vector<float> h(w, w + FX_MLP_NW);
+  for (float v : h)
+    if (!std::isfinite(v)) throw FxError(FX_E_INVALID, "non-finite weight");
+  mlp_master.upload(h);
+  std::vector<float> z(FX_MLP_NW, 0.0f);
+  mlp_m.upload(z);
+  mlp_v.upload(z);
+  mlp_wr.alloc(FX_MLP_NW);
+  mlp_grad.alloc(FX_MLP_NW);
+  hipLaunchKernelGGL(k_mlp_round, dim3((FX_MLP_NW + 255) / 256), dim3(256), 0, stream, mlp_master.p, mlp_wr.p);
+  check(hipGetLastError(), "k_mlp_round");
+  sync();
+  mlp_t = 0;
+  mlp_loaded = true;
+}
+
+void Ctx::mlp_features(float* d_out) {
+  if (!has_system) throw FxError(FX_E_STATE, "no system set");
+  hipLaunchKernelGGL(k_mlp_features, dim3((N + 255) / 256), dim3(256), 0, stream, dev_system(), d_out);
+  check(hipGetLastError(), "k_mlp_features");
+}
+
+void Ctx::mlp_infer(const float* d_x, float* d_y, long long n) {
+  if (!mlp_loaded) throw FxError(FX_E_STATE, "no guess model loaded");
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, mlp_wr.p, d_x, d_y, n);
+  check(hipGetLastError(), "k_mlp_forward");
+}
+
+// loss and gradient into mlp_grad (device); returns the loss
+double Ctx::mlp_grad_impl(const float* d_x, const float* d_y, long long n) {
+  if (!mlp_loaded) throw FxError(FX_E_STATE, "no guess model loaded");
+  if (n <= 0) throw FxError(FX_E_INVALID, "no training rows");
+  const long long nparts = (n + 31) / 32;
+  if (nparts > 0x7fffffffLL) throw FxError(FX_E_INVALID, "too many training rows");
+  mlp_part.alloc(nparts * FX_MLP_NW);
+  mlp_lpart.alloc(nparts);
+  mlp_loss.alloc(1);
+  hipLaunchKernelGGL(k_mlp_grad_partial, dim3((unsigned)nparts), dim3(256), 0, stream, mlp_wr.p, d_x, d_y, n,
+                     mlp_part.p, mlp_lpart.p);
+  hipLaunchKernelGGL(k_mlp_grad_reduce, dim3((FX_MLP_NW + 255) / 256), dim3(256), 0, stream, mlp_part.p,
+                     (int)nparts, mlp_grad.p);
+  hipLaunchKernelGGL(k_mlp_loss_reduce, dim3(1), dim3(1), 0, stream, mlp_lpart.p, (int)nparts,
+                     1.0 / (2.0 * (double)n), mlp_loss.p);
+  check(hipGetLastError(), "mlp gradient");
+  std::vector<double> h;
+  mlp_loss.download(h, stream, 1);
+  sync();
+  return h[0];
+}
+
+// learned monomer charges into d_q (projected per fragment)
+void Ctx::learned_guess() {
+  if (!mlp_loaded) throw FxError(FX_E_STATE, "learned guess requested but no model loaded");
+  mlp_feat.alloc((long long)N * FX_MLP_NFEAT);
+  mlp_out.alloc(2LL * N);
+  mlp_features(mlp_feat.p);
+  mlp_infer(mlp_feat.p, mlp_out.p, N);
+  DevBuf<int> fc;
+  fc.upload(frag_charge);
+  hipLaunchKernelGGL(k_guess_assemble, dim3((Ne + 255) / 256), dim3(256), 0, stream, dev_system(), mlp_out.p, d_q.p);
+  hipLaunchKernelGGL(k_guess_project, dim3(F), dim3(256), 0, stream, dev_system(), d_frag_atoms.p, d_frag_off.p,
+                     fc.p, d_q.p);
+  check(hipGetLastError(), "learned guess");
+  sync();
+}
+
 // Eigensolver for a batch whose largest system has n AOs: the LDS-resident
 // kernel with an FP64 working matrix if it fits with a rotation log of at
 // least 4 steps, else with an FP32 working matrix, else the global-memory
@@ -621,6 +693,24 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
                        scc_tol_cur > 0 ? scc_tol_cur : opt.scc_tol, etol_cur > 0 ? etol_cur : opt.energy_tol,
                        single ? 1 : opt.max_iter, b.has_pre ? precond_beta : mix_beta);
     check(hipGetLastError(), "scc iteration");
+    if (first_solve && it == 0) {
+      // median first-iteration residual over the batch
+      std::vector<double> e;
+      b.err.download(e, stream);
+      sync();
+      std::vector<double> v;
+      for (int s : active) v.push_back(e[s]);
+      if (!v.empty()) {
+        std::nth_element(v.begin(), v.begin() + v.size() / 2, v.end());
+        res.first_residual_median = v[v.size() / 2];
+      }
+    }
+    if (first_solve && opt.guess == FX_GUESS_LEARNED &&
+        ((it == 0 && opt.guess_tau > 0) || (opt.guess_max_iter > 0 && it + 1 == opt.guess_max_iter))) {
+      hipLaunchKernelGGL(k_guess_fallback, dim3(na), dim3(64), 0, stream, db, d_act.p, na, it == 0 ? 0 : 1,
+                         opt.guess_tau, fallback_flag.p);
+      check(hipGetLastError(), "k_guess_fallback");
+    }
     b.status.download(status, stream);
     b.sweeps.download(sweeps, stream);
     sync();
@@ -914,6 +1004,7 @@ void Ctx::run(fx_result* out) {
   build_matrices(mb);
   DevBatch dmb = mb.dev();
   if (opt.guess == FX_GUESS_USER) d_q.upload_async(guess, stream);
+  else if (opt.guess == FX_GUESS_LEARNED) learned_guess();
   else check(hipMemsetAsync(d_q.p, 0, sizeof(double) * Nsh, stream), "memset");
   hipLaunchKernelGGL(k_gather_shell, dim3(mb.nsys), dim3(64), 0, stream, dmb, d_q.p, mb.q_in.p);
   long long it_mono = 0;
@@ -952,7 +1043,19 @@ void Ctx::run(fx_result* out) {
       // inner solves only as tight as the outer residual requires
       scc_tol_cur = std::max(opt.scc_tol, std::min(1e-4, 1e-3 * delta));
       etol_cur = std::max(opt.energy_tol, std::min(1e-4, 1e-4 * delta));
+      first_solve = cold;
+      if (cold) {
+        fallback_flag.alloc(mb.nsys);
+        check(hipMemsetAsync(fallback_flag.p, 0, sizeof(int) * mb.nsys, stream), "memset");
+      }
       failed = solve_batch(mb, cold, &it_mono);
+      first_solve = false;
+      if (cold) {
+        std::vector<int> fl;
+        fallback_flag.download(fl, stream);
+        sync();
+        for (int v : fl) res.guess_fallbacks += v;
+      }
       scc_tol_cur = etol_cur = -1.0;
       if (cold && precond && monomer_response_setup()) build_precond(mb);
     }
@@ -1244,6 +1347,8 @@ int fx_default_options(fx_options* o) {
   o->precision = FX_FP64;
   o->schedule = FX_BATCHED;
   o->guess = FX_GUESS_SUPERPOSITION;
+  o->guess_tau = 0.0;
+  o->guess_max_iter = 50;
   o->scc_tol = 1e-10;
   o->energy_tol = 1e-11;
   o->macro_tol = 1e-10;
@@ -1449,6 +1554,91 @@ int fx_eigh_batched(fx_ctx* ctx, int32_t nmat, const int32_t* n, const double* A
     dw.download_raw(w, wt, c.stream);
     dV.download_raw(V, tot, c.stream);
     c.sync();
+  });
+}
+
+
+int fx_mlp_load(fx_ctx* ctx, const uint16_t* w, int64_t n) {
+  if (!ctx || !w || n != FX_MLP_NW) return FX_E_INVALID;
+  FX_GUARD(ctx, {
+    std::vector<float> f(FX_MLP_NW);
+    for (int i = 0; i < FX_MLP_NW; ++i) {
+      const uint32_t u = (uint32_t)w[i] << 16;
+      std::memcpy(&f[i], &u, 4);
+    }
+    ctx->c.mlp_set_master(f.data());
+  });
+}
+
+int fx_mlp_save(fx_ctx* ctx, uint16_t* out, int64_t n) {
+  if (!ctx || !out || n != FX_MLP_NW) return FX_E_INVALID;
+  FX_GUARD(ctx, {
+    if (!ctx->c.mlp_loaded) throw fx::FxError(FX_E_STATE, "no guess model loaded");
+    std::vector<float> f;
+    ctx->c.mlp_wr.download(f, ctx->c.stream, FX_MLP_NW);
+    ctx->c.sync();
+    for (int i = 0; i < FX_MLP_NW; ++i) {
+      uint32_t u;
+      std::memcpy(&u, &f[i], 4);
+      out[i] = (uint16_t)(u >> 16);
+    }
+  });
+}
+
+int fx_mlp_set_master(fx_ctx* ctx, const float* w, int64_t n) {
+  if (!ctx || !w || n != FX_MLP_NW) return FX_E_INVALID;
+  FX_GUARD(ctx, ctx->c.mlp_set_master(w));
+}
+
+int fx_mlp_get_master(fx_ctx* ctx, float* w, int64_t n) {
+  if (!ctx || !w || n != FX_MLP_NW) return FX_E_INVALID;
+  FX_GUARD(ctx, {
+    if (!ctx->c.mlp_loaded) throw fx::FxError(FX_E_STATE, "no guess model loaded");
+    ctx->c.mlp_master.download_raw(w, FX_MLP_NW, ctx->c.stream);
+    ctx->c.sync();
+  });
+}
+
+int fx_mlp_features(fx_ctx* ctx, float* d_features) {
+  if (!ctx || !d_features) return FX_E_INVALID;
+  FX_GUARD(ctx, {
+    ctx->c.mlp_features(d_features);
+    ctx->c.sync();
+  });
+}
+
+int fx_mlp_infer(fx_ctx* ctx, const float* d_features, float* d_out, int64_t n) {
+  if (!ctx || !d_features || !d_out || n < 0) return FX_E_INVALID;
+  FX_GUARD(ctx, {
+    ctx->c.mlp_infer(d_features, d_out, n);
+    ctx->c.sync();
+  });
+}
+
+int fx_mlp_grad(fx_ctx* ctx, const float* d_features, const float* d_labels, int64_t n, double* loss, float* grad) {
+  if (!ctx || !d_features || !d_labels || n <= 0) return FX_E_INVALID;
+  FX_GUARD(ctx, {
+    const double L = ctx->c.mlp_grad_impl(d_features, d_labels, n);
+    if (loss) *loss = L;
+    if (grad) {
+      ctx->c.mlp_grad.download_raw(grad, FX_MLP_NW, ctx->c.stream);
+      ctx->c.sync();
+    }
+  });
+}
+
+int fx_mlp_train_step(fx_ctx* ctx, const float* d_features, const float* d_labels, int64_t n, float lr,
+                      double* loss) {
+  if (!ctx || !d_features || !d_labels || n <= 0 || !(lr > 0.0f)) return FX_E_INVALID;
+  FX_GUARD(ctx, {
+    fx::Ctx& c = ctx->c;
+    const double L = c.mlp_grad_impl(d_features, d_labels, n);
+    c.mlp_t += 1;
+    hipLaunchKernelGGL(fx::k_mlp_adam, dim3((FX_MLP_NW + 255) / 256), dim3(256), 0, c.stream, c.mlp_master.p,
+                       c.mlp_m.p, c.mlp_v.p, c.mlp_grad.p, c.mlp_t, lr, c.mlp_wr.p);
+    fx::Ctx::check(hipGetLastError(), "k_mlp_adam");
+    c.sync();
+    if (loss) *loss = L;
   });
 }
 

@@ -17,6 +17,7 @@ constexpr int HIST = 8;       // Anderson mixing memory
 constexpr int MAXN = 512;     // largest system (AOs) handled by the SCC kernels
 
 struct DevElem {
+  int Z;
   int nsh, nao;
   int l[MAXSH_EL], nao_sh[MAXSH_EL], ao0[MAXSH_EL];
   double level[MAXSH_EL], kcn[MAXSH_EL], kpoly[MAXSH_EL], eta[MAXSH_EL], q0[MAXSH_EL];

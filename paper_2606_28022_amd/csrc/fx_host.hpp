@@ -220,6 +220,20 @@ struct Ctx {
   DevBuf<double> mono_tmp;
   bool monomer_response_setup();
   void build_precond(Batch& b);
+  // learned initial guess: FP32 master weights, Adam moments, bfloat16-rounded copy
+  DevBuf<float> mlp_master, mlp_m, mlp_v, mlp_wr, mlp_grad, mlp_part, mlp_feat, mlp_out;
+  DevBuf<double> mlp_lpart, mlp_loss;
+  int mlp_t = 0;
+  bool mlp_loaded = false;
+  void mlp_set_master(const float* w);
+  void mlp_features(float* d_out);
+  void mlp_infer(const float* d_x, float* d_y, long long n);
+  double mlp_grad_impl(const float* d_x, const float* d_y, long long n);
+  void learned_guess();
+  // first monomer solve: record first-iteration residuals and apply the
+  // learned-guess fallback
+  bool first_solve = false;
+  DevBuf<int> fallback_flag;
   std::deque<KernelTimer> ktimers;  // stable addresses
   KernelTimer* kt(const char* name) {
     for (auto& t : ktimers)

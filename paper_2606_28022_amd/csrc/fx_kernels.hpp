@@ -115,4 +115,17 @@ __global__ void k_gather_atoms(int N, const int* rowptr, const int* ent_batch, c
 __global__ void k_final_shift(DevSystem sys, DevBatch bt, double* wvec);
 __global__ void k_make_DS(DevBatch bt, const double* P, const double* W, double* out);
 
+// learned initial guess
+__global__ void k_mlp_features(DevSystem sys, float* out);
+__global__ void k_mlp_forward(const float* wr, const float* X, float* Y, long long n);
+__global__ void k_mlp_grad_partial(const float* wr, const float* X, const float* Yl, long long n, float* part,
+                                   double* loss_part);
+__global__ void k_mlp_grad_reduce(const float* part, int nparts, float* grad);
+__global__ void k_mlp_loss_reduce(const double* loss_part, int nparts, double inv_count, double* out);
+__global__ void k_mlp_adam(float* master, float* m, float* v, const float* g, int t, float lr, float* wr);
+__global__ void k_mlp_round(const float* master, float* wr);
+__global__ void k_guess_assemble(DevSystem sys, const float* Y, double* q);
+__global__ void k_guess_project(DevSystem sys, const int* frag_atoms, const int* frag_off, const int* frag_charge,
+                                double* q);
+__global__ void k_guess_fallback(DevBatch bt, const int* list, int nl, int phase, double tau, int* flag);
 }  // namespace fx
