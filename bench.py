@@ -8,7 +8,7 @@ ES-DIM pairs, the energy and the FMO2 gradient including the embedding
 response.  The system is uploaded before timing (inputs resident in HBM).
 
 Prints one JSON line.  Usage:
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain] [--no-guess]
 """
 
 import argparse
@@ -104,6 +104,52 @@ def plain_vs_batched():
     return tp / tb, abs(rb["e_total"] - rp["e_total"]), tb, tp
 
 
+def learned_guess_stream(n_droplets=8):
+    """Learned initial charges on the streaming workload: the first streaming
+    droplets (32-512 waters) and Ala20/Ala40 helices (cut bonds; nitrogen is
+    absent from the training set), FMO2 energy, superposition vs learned
+    start with the shipped model."""
+    import numpy as np
+    import workloads as w
+    from paper_2606_28022_amd import FmoXtb
+    from paper_2606_28022_amd.binding import trained_guess_model
+    blob, tau = trained_guess_model()
+    systems = [w.stream_droplet(500 + k) for k in range(n_droplets)] + [w.alanine_helix(n) for n in (20, 40)]
+    it0 = it1 = mono = fb = 0
+    t0 = t1 = 0.0
+    dE = 0.0
+    res0 = []
+    res1 = []
+    for s in systems:
+        c = FmoXtb()
+        c.set_system(s.Z, s.xyz, s.frag, s.frag_charge, bonds=s.bonds)
+        c.set_options(want_gradient=0)
+        c.run()
+        t = time.perf_counter()
+        r0 = c.run()
+        t0 += time.perf_counter() - t
+        c.mlp_load(blob)
+        c.set_options(guess=1, guess_tau=tau)
+        t = time.perf_counter()
+        r1 = c.run()
+        t1 += time.perf_counter() - t
+        it0 += r0["iters_mono"]
+        it1 += r1["iters_mono"]
+        mono += s.n_frag
+        fb += r1["guess_fallbacks"]
+        dE = max(dE, abs(r1["e_total"] - r0["e_total"]))
+        res0.append(r0["first_residual_median"])
+        res1.append(r1["first_residual_median"])
+        log(f"  {s.name}: monomer SCC iterations {r0['iters_mono']} -> {r1['iters_mono']}, "
+            f"fallbacks {r1['guess_fallbacks']}, dE {r1['e_total'] - r0['e_total']:.2e}")
+    return {"workload": f"{n_droplets} streaming droplets (seeds 500-{499 + n_droplets}) + Ala20, Ala40 helices, FMO2 energy",
+            "monomer_scc_iterations": {"superposition": it0, "learned": it1},
+            "iterations_saved_frac": 1.0 - it1 / max(1, it0), "max_abs_dE_Eh": dE,
+            "fallback_rate": fb / max(1, mono), "tau": tau,
+            "first_residual_median": {"superposition": float(np.median(res0)), "learned": float(np.median(res1))},
+            "seconds": {"superposition": t0, "learned": t1}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +157,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-guess", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -191,6 +238,8 @@ def main():
         sp, de, tb, tp = plain_vs_batched()
         out["batched_vs_plain"] = {"workload": "water droplet 1024 molecules, FMO2 energy, fp64",
                                    "speedup": sp, "abs_dE": de, "batched_s": tb, "plain_s": tp}
+    if not args.no_guess:
+        out["learned_guess"] = learned_guess_stream()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, r)
     print(json.dumps(out), flush=True)

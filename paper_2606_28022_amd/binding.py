@@ -357,3 +357,16 @@ class FmoXtb:
     def _torch_device(self):
         import torch
         return torch.device("cuda", self.device)
+
+
+def trained_guess_model():
+    """(bfloat16 weights, tau) of the model shipped in data/ (written by
+    train_guess.py)."""
+    import json
+    d = os.path.join(HERE, "data")
+    w = np.fromfile(os.path.join(d, "guess_mlp.bf16"), dtype="<u2")
+    with open(os.path.join(d, "guess_mlp.json")) as f:
+        meta = json.load(f)
+    if len(w) != FX_MLP_NW:
+        raise ValueError("guess_mlp.bf16 has the wrong size")
+    return w, float(meta["tau"])

@@ -117,3 +117,25 @@ def test_mlp_errors():
         c.run()                                    # no model loaded
     with pytest.raises(FxError):
         c.mlp_set_master(np.zeros(10, dtype=np.float32))   # wrong size
+
+
+@pytest.mark.parametrize("which", ["droplet502", "ala10"])
+def test_trained_model_same_energy_fewer_iterations(which):
+    """The shipped model (trained on water and anthracene) as the start of a
+    streaming droplet and of a helix with cut bonds: same converged energy
+    as superposition starts; on the droplet, fewer monomer SCC iterations."""
+    from paper_2606_28022_amd.binding import trained_guess_model
+    _say(f"trained guess model {which}")
+    s = w.stream_droplet(502) if which == "droplet502" else w.alanine_helix(10)
+    blob, tau = trained_guess_model()
+    c = _ctx(s)
+    c.set_options(want_gradient=0)
+    r0 = c.run()
+    c.mlp_load(blob)
+    c.set_options(guess=1, guess_tau=tau)
+    r1 = c.run()
+    assert abs(r1["e_total"] - r0["e_total"]) < 1e-8 * s.n_frag
+    if which == "droplet502":
+        assert r1["guess_fallbacks"] == 0
+        assert r1["iters_mono"] < r0["iters_mono"]
+        assert r1["first_residual_median"] < 0.2 * r0["first_residual_median"]

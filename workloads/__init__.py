@@ -14,6 +14,7 @@ from .geometry import (  # noqa: F401
     anthracene_crystal,
     pentacene_crystal,
     separated_water_pair,
+    stream_droplet,
     load_params_json,
     params_path,
 )

@@ -177,6 +177,15 @@ def water_droplet(n=1024, radius=19.5, seed=2, name="water-droplet"):
                   meta=dict(seed=seed, radius_angstrom=radius))
 
 
+def stream_droplet(seed):
+    """Droplet of the streaming workload: size uniform in [32, 512] waters
+    (drawn from the seed), O placed in a sphere of liquid density
+    0.0334 waters per cubic Angstrom."""
+    n = int(_rng(seed).integers(32, 513))
+    radius = (3.0 * n / (4.0 * math.pi * 0.0334)) ** (1.0 / 3.0)
+    return water_droplet(n=n, radius=radius, seed=seed, name="stream-droplet")
+
+
 def separated_water_pair(closest_angstrom, seed=11):
     """Two waters whose closest interatomic distance is the given value (A)."""
     rng = _rng(seed)
