@@ -53,7 +53,12 @@ enum {
 };
 
 enum { FX_FP64 = 0, FX_MIXED = 1 };           /* precision */
-enum { FX_BATCHED = 0, FX_PLAIN_LOOP = 1 };   /* schedule of the fragment solves */
+/* schedule of the fragment solves: FX_BATCHED launches each SCC iteration
+ * over all still-active systems of a kind; FX_PLAIN_LOOP solves one system
+ * at a time; FX_BATCHED_GRAPH captures the iteration over all systems of a
+ * solve once into a hipGraph and replays it (converged systems skip
+ * themselves on the device), after an eager first iteration */
+enum { FX_BATCHED = 0, FX_PLAIN_LOOP = 1, FX_BATCHED_GRAPH = 2 };
 enum { FX_GUESS_SUPERPOSITION = 0, FX_GUESS_LEARNED = 1, FX_GUESS_USER = 2 };
 
 typedef struct fx_params fx_params;

@@ -436,21 +436,22 @@ void Ctx::init_device() {
 // Batched n x n products of the listed systems (first nl entries of dlist):
 // the matrix-core kernel once a system spans more than one 32 x 32 tile.
 void Ctx::gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlist, int mode, const double* A,
-                     const double* B, double* C, const double* w, double gflop) {
+                     const double* B, double* C, const double* w, double gflop, int skip_done) {
   if (nl <= 0) return;
+  const bool timed = !capturing;
   if (b.max_nao <= 32) {
-    const int ev = timers.begin(stream);
-    hipLaunchKernelGGL(k_gemm, dim3(1, nl), dim3(256), 0, stream, db, dlist, mode, A, B, C, w);
-    timers.end(stream, ev, kt("fx::k_gemm"), gflop);
+    const int ev = timed ? timers.begin(stream) : -1;
+    hipLaunchKernelGGL(k_gemm, dim3(1, nl), dim3(256), 0, stream, db, dlist, mode, A, B, C, w, skip_done);
+    if (timed) timers.end(stream, ev, kt("fx::k_gemm"), gflop);
   } else {
     const int nt = (b.max_nao + 63) / 64;
     const long long tiles = (long long)nl * nt * nt;
     const long long grid = (tiles + 7) / 8 * 8;
     if (grid > 0x7fffffffLL) throw FxError(FX_E_INVALID, "batched product grid too large");
-    const int ev = timers.begin(stream);
+    const int ev = timed ? timers.begin(stream) : -1;
     hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)grid), dim3(256), 0, stream, db, dlist, nl, nt * nt, mode, A, B, C,
-                       w);
-    timers.end(stream, ev, kt("fx::k_gemm_mfma"), gflop);
+                       w, skip_done);
+    if (timed) timers.end(stream, ev, kt("fx::k_gemm_mfma"), gflop);
   }
   check(hipGetLastError(), "batched product");
 }
@@ -588,6 +589,67 @@ void Ctx::learned_guess() {
   sync();
 }
 
+// Launch-shape autotuning of the LDS Jacobi for one size bucket: candidate
+// (threads, chunk) pairs with the same working precision, each timed on fresh
+// copies of the batch's A and C^T with HIP events; the fastest is returned.
+JacobiPlan Ctx::autotune_jacobi(Batch& b, const int* dl, int na, const JacobiPlan& base, double cap) {
+  const long long tm = b.tot_mat;
+  DevBuf<double> A0, V0, A1, V1;
+  A0.alloc(tm);
+  V0.alloc(tm);
+  A1.alloc(tm);
+  V1.alloc(tm);
+  DevBuf<int> sw;
+  sw.alloc(b.nsys);
+  check(hipMemcpyAsync(A0.p, b.Fm.p, sizeof(double) * tm, hipMemcpyDeviceToDevice, stream), "copy");
+  check(hipMemcpyAsync(V0.p, b.Ct.p, sizeof(double) * tm, hipMemcpyDeviceToDevice, stream), "copy");
+  DevBatch db = b.dev();
+  db.F = A1.p;
+  db.Ct = V1.p;
+  std::vector<JacobiPlan> cand;
+  for (int t : {256, 512, 1024})
+    for (int k : {2, 4, 8, 12, 16}) {
+      JacobiPlan p = base;
+      p.threads = t;
+      p.chunk = k;
+      p.lds = jacobi_lds_layout(b.max_nao, base.elt, k, t / 64).total;
+      if ((int)p.lds > lds_max) continue;
+      if (t / 64 > 16) continue;
+      cand.push_back(p);
+    }
+  JacobiPlan best = base;
+  float best_ms = 1e30f;
+  hipEvent_t e0, e1;
+  check(hipEventCreate(&e0), "event");
+  check(hipEventCreate(&e1), "event");
+  for (const JacobiPlan& p : cand) {
+    check(hipMemcpyAsync(A1.p, A0.p, sizeof(double) * tm, hipMemcpyDeviceToDevice, stream), "copy");
+    check(hipMemcpyAsync(V1.p, V0.p, sizeof(double) * tm, hipMemcpyDeviceToDevice, stream), "copy");
+    check(hipEventRecord(e0, stream), "event");
+    if (p.elt == 8)
+      hipLaunchKernelGGL(k_jacobi_lds<double>, dim3(na), dim3(p.threads), p.lds, stream, db, dl, jacobi_max_sweeps,
+                         jacobi_tol, jacobi_thr_scale, cap, sw.p, p.chunk);
+    else
+      hipLaunchKernelGGL(k_jacobi_lds<float>, dim3(na), dim3(p.threads), p.lds, stream, db, dl, jacobi_max_sweeps,
+                         jacobi_tol, jacobi_thr_scale, cap, sw.p, p.chunk);
+    check(hipEventRecord(e1, stream), "event");
+    check(hipGetLastError(), "autotune launch");
+    check(hipEventSynchronize(e1), "event");
+    float ms = 0.0f;
+    check(hipEventElapsedTime(&ms, e0, e1), "event");
+    if (verbose)
+      std::fprintf(stderr, "[fx] autotune n<=%d %s: %d threads, chunk %d: %.3f ms\n", b.max_nao,
+                   p.elt == 8 ? "fp64" : "fp32", p.threads, p.chunk, ms);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = p;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
+}
+
 // Eigensolver for a batch whose largest system has n AOs: the LDS-resident
 // kernel with an FP64 working matrix if it fits with a rotation log of at
 // least 4 steps, else with an FP32 working matrix, else the global-memory
@@ -655,44 +717,91 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     }
     check(hipGetLastError(), "initial basis");
   }
-  const JacobiPlan jp = jacobi_plan(b.max_nao, b.has_hop);
+  JacobiPlan jp = jacobi_plan(b.max_nao, b.has_hop);
+  {
+    auto itp = tuned.find(jp_key(b.max_nao, jp.elt));
+    if (itp != tuned.end()) jp = itp->second;
+  }
   std::vector<int> active = list;
   std::vector<int> sweeps(b.nsys), status(b.nsys), niter(b.nsys);
   DevBuf<int> d_act;
-  const int nt = (b.max_nao + 31) / 32;
-  auto gemm = [&](const std::vector<int>& l, const int* dl, int mode, const double* A, const double* B, double* C,
-                  const double* w) { gemm_batch(b, db, (int)l.size(), dl, mode, A, B, C, w, b.gemm_gflop(l)); };
   KernelTimer* kt_jac = kt(jp.elt == 8 ? "fx::k_jacobi_lds<double>" : jp.elt == 4 ? "fx::k_jacobi_lds<float>"
                                                                                    : "fx::k_jacobi");
   const int max_it = single ? 1 : opt.max_iter + 1;
-  for (int it = 0; it < max_it && !active.empty(); ++it) {
-    d_act.upload(active);
-    const int na = (int)active.size();
-    hipLaunchKernelGGL(k_fock, dim3(na), dim3(256), 0, stream, ds, db, d_act.p);
+  // one SCC iteration over the systems in dl (na of them); converged systems
+  // listed there return at once (device-side status)
+  auto launch_iteration = [&](const std::vector<int>& act, const int* dl, int na, double cap, bool timed) {
+    hipLaunchKernelGGL(k_fock, dim3(na), dim3(256), 0, stream, ds, db, dl);
     // A = C^T F C in the current basis, then Jacobi rotations
-    gemm(active, d_act.p, 0, b.Ct.p, b.Fm.p, b.Tm.p, nullptr);
-    gemm(active, d_act.p, 1, b.Tm.p, b.Ct.p, b.Fm.p, nullptr);
-    {
-      // the first iteration from the Cholesky basis is diagonalised fully
-      const double cap = (cold && it == 0 && !b.init_from_mono) ? 1e300 : jacobi_cap_err;
-      int ev = timers.begin(stream);
-      if (jp.elt == 8)
-        hipLaunchKernelGGL(k_jacobi_lds<double>, dim3(na), dim3(jp.threads), jp.lds, stream, db, d_act.p,
-                           jacobi_max_sweeps, jacobi_tol, jacobi_thr_scale, cap, b.sweeps.p, jp.chunk);
-      else if (jp.elt == 4)
-        hipLaunchKernelGGL(k_jacobi_lds<float>, dim3(na), dim3(jp.threads), jp.lds, stream, db, d_act.p,
-                           jacobi_max_sweeps, jacobi_tol, jacobi_thr_scale, cap, b.sweeps.p, jp.chunk);
-      else
-        hipLaunchKernelGGL(k_jacobi, dim3(na), dim3(jacobi_threads), 0, stream, db, d_act.p, jacobi_max_sweeps,
-                           jacobi_tol, jacobi_thr_scale, cap, b.sweeps.p);
-      timers.end(stream, ev, kt_jac, 0.0);
-    }
-    hipLaunchKernelGGL(k_fermi, dim3(na), dim3(256), 0, stream, ds, db, d_act.p);
-    gemm(active, d_act.p, 2, b.Ct.p, b.Ct.p, b.Pm.p, b.occ.p);
-    hipLaunchKernelGGL(k_charges_mix, dim3(na), dim3(256), 0, stream, ds, db, d_act.p,
+    gemm_batch(b, db, na, dl, 0, b.Ct.p, b.Fm.p, b.Tm.p, nullptr, b.gemm_gflop(act), 1);
+    gemm_batch(b, db, na, dl, 1, b.Tm.p, b.Ct.p, b.Fm.p, nullptr, b.gemm_gflop(act), 1);
+    const int ev = timed ? timers.begin(stream) : -1;
+    if (jp.elt == 8)
+      hipLaunchKernelGGL(k_jacobi_lds<double>, dim3(na), dim3(jp.threads), jp.lds, stream, db, dl, jacobi_max_sweeps,
+                         jacobi_tol, jacobi_thr_scale, cap, b.sweeps.p, jp.chunk);
+    else if (jp.elt == 4)
+      hipLaunchKernelGGL(k_jacobi_lds<float>, dim3(na), dim3(jp.threads), jp.lds, stream, db, dl, jacobi_max_sweeps,
+                         jacobi_tol, jacobi_thr_scale, cap, b.sweeps.p, jp.chunk);
+    else
+      hipLaunchKernelGGL(k_jacobi, dim3(na), dim3(jacobi_threads), 0, stream, db, dl, jacobi_max_sweeps, jacobi_tol,
+                         jacobi_thr_scale, cap, b.sweeps.p);
+    if (timed) timers.end(stream, ev, kt_jac, 0.0);
+    hipLaunchKernelGGL(k_fermi, dim3(na), dim3(256), 0, stream, ds, db, dl);
+    gemm_batch(b, db, na, dl, 2, b.Ct.p, b.Ct.p, b.Pm.p, b.occ.p, b.gemm_gflop(act), 1);
+    hipLaunchKernelGGL(k_charges_mix, dim3(na), dim3(256), 0, stream, ds, db, dl,
                        scc_tol_cur > 0 ? scc_tol_cur : opt.scc_tol, etol_cur > 0 ? etol_cur : opt.energy_tol,
                        single ? 1 : opt.max_iter, b.has_pre ? precond_beta : mix_beta);
     check(hipGetLastError(), "scc iteration");
+  };
+  // FX_BATCHED_GRAPH: after the first (eager) iteration, the iteration over
+  // the whole list is captured once into a hipGraph and replayed; converged
+  // systems skip themselves on the device, the host only reads the status
+  const bool graph_mode = opt.schedule == FX_BATCHED_GRAPH && !single && !first_solve;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  for (int it = 0; it < max_it && !active.empty(); ++it) {
+    const double cap = (cold && it == 0 && !b.init_from_mono) ? 1e300 : jacobi_cap_err;
+    if (graph_mode && it >= 1) {
+      if (!gexec) {
+        if (!gstream) check(hipStreamCreateWithFlags(&gstream, hipStreamNonBlocking), "hipStreamCreate");
+        sync();
+        hipStream_t saved = stream;
+        stream = gstream;
+        capturing = true;
+        check(hipStreamBeginCapture(gstream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        launch_iteration(list, b.d_list.p, nl, jacobi_cap_err, false);
+        const hipError_t ec = hipStreamEndCapture(gstream, &graph);
+        capturing = false;
+        stream = saved;
+        check(ec, "hipStreamEndCapture");
+        check(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+      }
+      const int ev = timers.begin(gstream);
+      check(hipGraphLaunch(gexec, gstream), "hipGraphLaunch");
+      timers.end(gstream, ev, kt("scc iteration (graph)"), 0.0);
+      check(hipStreamSynchronize(gstream), "hipStreamSynchronize");
+      b.status.download(status, stream);
+      sync();
+      timers.resolve();
+      std::vector<int> next;
+      for (int s : active)
+        if (status[s] == 0) next.push_back(s);
+      active.swap(next);
+      continue;
+    }
+    d_act.upload(active);
+    const int na = (int)active.size();
+    if (it == 1 && autotune && jp.elt != 0 && !tuned.count(jp_key(b.max_nao, jp.elt))) {
+      // form this iteration's A once, time the eigensolver's launch shapes
+      // on copies of (A, C^T) and keep the fastest for this size bucket; all
+      // shapes give bitwise identical results
+      hipLaunchKernelGGL(k_fock, dim3(na), dim3(256), 0, stream, ds, db, d_act.p);
+      gemm_batch(b, db, na, d_act.p, 0, b.Ct.p, b.Fm.p, b.Tm.p, nullptr, b.gemm_gflop(active), 1);
+      gemm_batch(b, db, na, d_act.p, 1, b.Tm.p, b.Ct.p, b.Fm.p, nullptr, b.gemm_gflop(active), 1);
+      jp = autotune_jacobi(b, d_act.p, na, jp, cap);
+      tuned[jp_key(b.max_nao, jp.elt)] = jp;
+    }
+    launch_iteration(active, d_act.p, na, cap, true);
     if (first_solve && it == 0) {
       // median first-iteration residual over the batch
       std::vector<double> e;
@@ -727,6 +836,8 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
       if (status[s] == 0) next.push_back(s);
     active.swap(next);
   }
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  if (graph) (void)hipGraphDestroy(graph);
   b.status.download(status, stream);
   b.niter.download(niter, stream);
   sync();
@@ -1367,6 +1478,10 @@ int fx_set_options(fx_ctx* ctx, const fx_options* o) {
         o->max_macro < 1)
       throw fx::FxError(FX_E_INVALID, "bad option value");
     if (o->precision != FX_FP64 && o->precision != FX_MIXED) throw fx::FxError(FX_E_INVALID, "bad precision");
+    if (o->schedule != FX_BATCHED && o->schedule != FX_PLAIN_LOOP && o->schedule != FX_BATCHED_GRAPH)
+      throw fx::FxError(FX_E_INVALID, "bad schedule");
+    if (o->guess != FX_GUESS_SUPERPOSITION && o->guess != FX_GUESS_LEARNED && o->guess != FX_GUESS_USER)
+      throw fx::FxError(FX_E_INVALID, "bad guess");
     bool cutoff_changed = o->cutoff_bohr != ctx->c.opt.cutoff_bohr || o->order != ctx->c.opt.order;
     ctx->c.opt = *o;
     if (cutoff_changed) ctx->c.lists_built = false;

@@ -159,6 +159,9 @@ struct JacobiPlan {
 };
 
 struct Ctx {
+  ~Ctx() {
+    if (gstream) (void)hipStreamDestroy(gstream);
+  }
   HostParams P;
   int device = 0;
   hipStream_t stream = nullptr;
@@ -293,8 +296,16 @@ struct Ctx {
   void build_matrices(Batch& b);
   void init_device();
   JacobiPlan jacobi_plan(int n, bool fp64_only = false) const;
+  // autotuned eigensolver launch shapes per (size bucket, precision)
+  bool autotune = !(std::getenv("FX_AUTOTUNE") && std::atoi(std::getenv("FX_AUTOTUNE")) == 0);
+  std::map<long long, JacobiPlan> tuned;
+  static long long jp_key(int n, int elt) { return (long long)n * 16 + elt; }
+  JacobiPlan autotune_jacobi(Batch& b, const int* dl, int na, const JacobiPlan& base, double cap);
   void gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlist, int mode, const double* A,
-                  const double* B, double* C, const double* w, double gflop);
+                  const double* B, double* C, const double* w, double gflop, int skip_done = 0);
+  // graph-captured SCC iterations (schedule FX_BATCHED_GRAPH)
+  bool capturing = false;
+  hipStream_t gstream = nullptr;
   int run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* iters_out, bool single = false);
   int solve_batch(Batch& b, bool cold, long long* iters_out);
   void run(fx_result* out);

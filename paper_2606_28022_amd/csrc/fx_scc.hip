@@ -148,6 +148,7 @@ __global__ void k_cholinv(DevBatch bt, const int* list, const double* Apool, dou
 // shell shift and Fock matrix
 __global__ void k_fock(DevSystem sys, DevBatch bt, const int* list) {
   int si = list[blockIdx.x];
+  if (bt.status[si] != 0) return;  // converged or failed: nothing to do
   const SysDesc d = bt.desc[si];
   const int n = d.nao, ns = d.nsh;
   __shared__ double qa_s[MAXN];
@@ -191,8 +192,9 @@ __global__ void k_fock(DevSystem sys, DevBatch bt, const int* list) {
 // per work-group (256 threads, 2 x 2 outputs each).  mode:
 //   0  C = A B          1  C = A B^T          2  C = A^T diag(w) B (w = 1 if null)
 __global__ void k_gemm(DevBatch bt, const int* list, int mode, const double* Abase, const double* Bbase,
-                       double* Cbase, const double* wbase) {
+                       double* Cbase, const double* wbase, int skip_done) {
   int si = list[blockIdx.y];
+  if (skip_done && bt.status[si] != 0) return;
   const SysDesc d = bt.desc[si];
   const int n = d.nao;
   const int nt = (n + 31) / 32;
@@ -267,12 +269,14 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256)
     k_gemm_mfma(DevBatch bt, const int* list, int nl, int tiles_per_sys, int mode, const double* __restrict__ Abase,
-                const double* __restrict__ Bbase, double* __restrict__ Cbase, const double* __restrict__ wbase) {
+                const double* __restrict__ Bbase, double* __restrict__ Cbase, const double* __restrict__ wbase,
+                int skip_done) {
   const int L = blockIdx.x, G = gridDim.x;  // G is a multiple of 8
   const int logical = (L & 7) * (G >> 3) + (L >> 3);
   const int sl = logical / tiles_per_sys, tile = logical - sl * tiles_per_sys;
   if (sl >= nl) return;
   const int si = list[sl];
+  if (skip_done && bt.status[si] != 0) return;
   const SysDesc d = bt.desc[si];
   const int n = d.nao;
   const int nt = (n + 63) / 64;
@@ -513,6 +517,7 @@ __device__ void jacobi_solve(double* __restrict__ A, double* __restrict__ V, int
 // the final iterations are diagonalised to rel_tol.
 __global__ void k_jacobi(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale,
                          double cap_err, int* sweeps_out) {
+  if (bt.status[list[blockIdx.x]] != 0) return;
   int si = list[blockIdx.x];
   const SysDesc d = bt.desc[si];
   __shared__ double red[1024];
@@ -550,6 +555,7 @@ __global__ void k_eigh_batched(const int* nvec, const long long* off, double* Ab
 // so that sum n_i = N_el; also -T S_el.
 __global__ void k_fermi(DevSystem sys, DevBatch bt, const int* list) {
   int si = list[blockIdx.x];
+  if (bt.status[si] != 0) return;  // converged or failed: nothing to do
   const SysDesc d = bt.desc[si];
   const int n = d.nao;
   const double kT = sys.g.kT;
@@ -622,6 +628,7 @@ __device__ void solve_small(double* M, double* rhs, int m) {
 __global__ void k_charges_mix(DevSystem sys, DevBatch bt, const int* list, double tol, double etol, int max_iter,
                               double beta) {
   int si = list[blockIdx.x];
+  if (bt.status[si] != 0) return;
   const SysDesc d = bt.desc[si];
   const int n = d.nao, ns = d.nsh;
   __shared__ double red[256];
@@ -789,34 +796,6 @@ namespace fx {
 // eigenpairs carry FP64 accuracy.
 __device__ inline int pk_index(int i, int j) { return i < j ? j * (j - 1) / 2 + i : i * (i - 1) / 2 + j; }
 
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ inline double wave_max(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-// block reductions over per-wave partials, summed in wave order
-__device__ inline double wblock_sum(double v, double* red) {
-  v = wave_sum(v);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double r = 0.0;
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += red[w];
-  return r;
-}
-__device__ inline double wblock_max(double v, double* red) {
-  v = wave_max(v);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double r = 0.0;
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w]);
-  return r;
-}
-
 template <typename T>
 __global__ void __launch_bounds__(1024)
     k_jacobi_lds(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale, double cap_err,
@@ -824,6 +803,7 @@ __global__ void __launch_bounds__(1024)
   extern __shared__ double2 lds_raw[];
   unsigned char* lds = reinterpret_cast<unsigned char*>(lds_raw);
   const int si = list[blockIdx.x];
+  if (bt.status[si] != 0) return;
   const SysDesc d = bt.desc[si];
   const int n = d.nao, nv = d.nao;
   const int m = n + (n & 1), nb = m / 2;
@@ -839,24 +819,37 @@ __global__ void __launch_bounds__(1024)
   const double* __restrict__ A = bt.F + d.mat_off;
   double* __restrict__ V = bt.Ct + d.mat_off;
 
-  // load: diagonal in FP64, strict upper triangle packed in T; |A|_F
-  double loc = 0.0;
+  // load: diagonal in FP64, strict upper triangle packed in T
   for (int e = threadIdx.x; e < n * n; e += nt) {
     const int i = e / n, j = e - i * n;
     if (j < i) continue;
     const double v = A[e];
-    if (i == j) {
+    if (i == j)
       dg[i] = v;
-      // diagonal entries count at most 10 Eh: a projector shift (section
-      // "Covalent bond fragmentation", 1e6 Eh) must not loosen the threshold
-      // of the physical orbitals
-      loc += fmin(v * v, 100.0);
-    } else {
+    else
       Ap[pk_index(i, j)] = (T)v;
-      loc += 2.0 * v * v;
-    }
   }
-  const double fro = sqrt(wblock_sum(loc, red));
+  // |A|_F from per-row sums added in row order, so that the threshold does
+  // not depend on the launch shape; diagonal entries count at most 10 Eh (a
+  // projector shift of section "Covalent bond fragmentation", 1e6 Eh, must
+  // not loosen the threshold of the physical orbitals)
+  for (int i = threadIdx.x; i < n; i += nt) {
+    double r = 0.0;
+    for (int j = i; j < n; ++j) {
+      const double v = A[(long long)i * n + j];
+      r += (j == i) ? fmin(v * v, 100.0) : 2.0 * v * v;
+    }
+    vt[i] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double f = 0.0;
+    for (int i = 0; i < n; ++i) f += vt[i];
+    red[0] = sqrt(f);
+  }
+  __syncthreads();
+  const double fro = red[0];
+  __syncthreads();
   const double err = bt.err[si];
   const double thr = fmax(rel_tol * (fro > 0.0 ? fro : 1.0), thr_scale * err);
   const int msw = err > cap_err ? 1 : max_sweeps;

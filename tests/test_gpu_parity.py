@@ -221,3 +221,28 @@ def test_error_paths(lib, c1):
     with pytest.raises(FxError) as e:
         c.run()
     assert e.value.code == FX_E_NOCONV
+
+
+@pytest.mark.parametrize("which", ["c1", "pentacene4"])
+def test_graph_schedule_matches_batched(lib, which):
+    """FX_BATCHED_GRAPH replays one captured SCC iteration over all systems
+    of a solve; converged systems skip themselves on the device.  Energies
+    and charges equal the eagerly launched schedule bit for bit, also on a
+    second run of the same context (new capture, new replays)."""
+    _say(f"graph schedule {which}")
+    s = w.water_cluster_cube() if which == "c1" else w.pentacene_crystal(reps=(2, 2, 1)).subset([0, 1, 2, 3])
+    c = lib()
+    c.set_system(s.Z, s.xyz, s.frag, s.frag_charge)
+    c.set_options(want_gradient=0, schedule=0)
+    r0 = c.run()
+    e0 = c.energies()
+    q0 = c.charges()
+    c.set_options(schedule=2)
+    for rep in range(2):
+        r1 = c.run()
+        e1 = c.energies()
+        assert r1["e_total"] == r0["e_total"]
+        for a, b in zip(e0, e1):
+            assert np.array_equal(a, b)
+        assert np.array_equal(c.charges(), q0)
+        assert r1["iters_dimer"] == r0["iters_dimer"]
