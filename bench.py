@@ -8,7 +8,7 @@ ES-DIM pairs, the energy and the FMO2 gradient including the embedding
 response.  The system is uploaded before timing (inputs resident in HBM).
 
 Prints one JSON line.  Usage:
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain] [--no-guess]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain] [--no-guess] [--no-mixed]
 """
 
 import argparse
@@ -158,6 +158,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-guess", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -238,6 +239,20 @@ def main():
         sp, de, tb, tp = plain_vs_batched()
         out["batched_vs_plain"] = {"workload": "water droplet 1024 molecules, FMO2 energy, fp64",
                                    "speedup": sp, "abs_dE": de, "batched_s": tb, "plain_s": tp}
+    if not args.no_mixed:
+        # the same step in the mixed-precision form (warm-up run first)
+        c.set_options(precision=1)
+        c.run()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rm = c.run()
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - t
+        gm = c.gradient()
+        c.set_options(precision=0)
+        out["mixed_vs_fp64"] = {"workload": "same step, FX_MIXED", "s_per_step": tm, "speedup": sec / tm,
+                                "abs_dE_Eh": abs(rm["e_total"] - r["e_total"]),
+                                "max_abs_dgrad_Eh_per_bohr": float(np.abs(gm - g).max())}
     if not args.no_guess:
         out["learned_guess"] = learned_guess_stream()
     if not args.no_cpu:

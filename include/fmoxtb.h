@@ -70,7 +70,11 @@ typedef struct fx_options {
                              distance is below this value, otherwise ES-DIM;
                              a trimer is computed when at least two of its
                              three pairs are SCC dimers */
-  int32_t precision;      /* FX_FP64 (FX_MIXED is reserved; FX_E_UNSUPPORTED) */
+  int32_t precision;      /* FX_FP64, or FX_MIXED: FP32 eigensolver working
+                             matrices for every system (the basis stays FP64)
+                             and FP32 embedding-field passes while the monomer
+                             charges still move by more than 1e-6; results
+                             keep the FP64 tolerances (iterative refinement) */
   int32_t schedule;       /* FX_BATCHED: all fragments of a kind in one launch
                              sequence; FX_PLAIN_LOOP: one fragment at a time */
   int32_t guess;          /* initial monomer charges: superposition (zero),

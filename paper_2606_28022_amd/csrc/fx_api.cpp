@@ -654,14 +654,14 @@ JacobiPlan Ctx::autotune_jacobi(Batch& b, const int* dl, int na, const JacobiPla
 // kernel with an FP64 working matrix if it fits with a rotation log of at
 // least 4 steps, else with an FP32 working matrix, else the global-memory
 // kernel.  Workgroup size grows with n (one V column per wave).
-JacobiPlan Ctx::jacobi_plan(int n, bool fp64_only) const {
+JacobiPlan Ctx::jacobi_plan(int n, bool fp64_only, bool prefer_fp32) const {
   JacobiPlan jp;
   if (!jacobi_lds || n < 2 || n > MAXN) return jp;
   int t = n <= 32 ? 64 : n <= 96 ? 256 : n <= 160 ? 512 : 1024;
   if (const char* e = std::getenv("FX_JACOBI_LDS_THREADS")) t = std::atoi(e);
   const int chunks[] = {16, 8, 4, 2};
   for (int pass = 0; pass < 2; ++pass)
-    for (int elt : {8, 4})
+    for (int elt : {prefer_fp32 ? 4 : 8, prefer_fp32 ? 8 : 4})
       for (int k : chunks) {
         if (fp64_only && elt == 4) continue;
         if (pass == 0 && k < 4) continue;
@@ -717,7 +717,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     }
     check(hipGetLastError(), "initial basis");
   }
-  JacobiPlan jp = jacobi_plan(b.max_nao, b.has_hop);
+  JacobiPlan jp = jacobi_plan(b.max_nao, b.has_hop, opt.precision == FX_MIXED && !b.has_hop);
   {
     auto itp = tuned.find(jp_key(b.max_nao, jp.elt));
     if (itp != tuned.end()) jp = itp->second;
@@ -877,13 +877,18 @@ int Ctx::solve_batch(Batch& b, bool cold, long long* iters_out) {
   return failed;
 }
 
-void Ctx::field(const double* d_q, double* d_phi) {
+void Ctx::field(const double* d_q, double* d_phi, bool fp32) {
   const int nchunk = std::max(1, std::min(64, (Ne + 255) / 256 > 0 ? 2048 / ((Ne + 255) / 256) : 1));
   if ((long long)nchunk * Nsh > field_part.n) field_part.alloc((long long)nchunk * Nsh);
   dim3 grid((Ne + 255) / 256, nchunk);
   const int ev = timers.begin(stream);
-  hipLaunchKernelGGL(k_field_partial, grid, dim3(256), 0, stream, dev_system(), d_q, nchunk, field_part.p);
-  timers.end(stream, ev, kt("fx::k_field_partial"), 8e-9 * field_pairs);
+  if (fp32) {
+    hipLaunchKernelGGL(k_field_partial_f32, grid, dim3(256), 0, stream, dev_system(), d_q, nchunk, field_part.p);
+    timers.end(stream, ev, kt("fx::k_field_partial_f32"), 8e-9 * field_pairs);
+  } else {
+    hipLaunchKernelGGL(k_field_partial, grid, dim3(256), 0, stream, dev_system(), d_q, nchunk, field_part.p);
+    timers.end(stream, ev, kt("fx::k_field_partial"), 8e-9 * field_pairs);
+  }
   hipLaunchKernelGGL(k_field_reduce, dim3((Nsh + 255) / 256), dim3(256), 0, stream, Nsh, nchunk, field_part.p,
                      d_phi);
   check(hipGetLastError(), "field");
@@ -1095,7 +1100,7 @@ void Ctx::set_system(int32_t n_atoms, const int32_t* Z, const double* xyz, int32
 
 void Ctx::run(fx_result* out) {
   if (!has_system) throw FxError(FX_E_STATE, "no system set");
-  if (opt.precision != FX_FP64) throw FxError(FX_E_UNSUPPORTED, "only FX_FP64 is available");
+  const bool mixed = opt.precision == FX_MIXED;
   if (NB > 0 && opt.want_gradient)
     throw FxError(FX_E_UNSUPPORTED, "the gradient with cut covalent bonds is not available");
   std::memset(&res, 0, sizeof(res));
@@ -1137,8 +1142,16 @@ void Ctx::run(fx_result* out) {
   std::vector<int> all_mono(mb.nsys);
   for (int k = 0; k < mb.nsys; ++k) all_mono[k] = k;
   bool fused_mode = false;
+  // mixed precision: FP32 field passes until the monomer charges move by
+  // less than 1e-6, FP64 from then on (the fixed point is the FP64 one)
+  bool field32 = mixed;
   for (macro = 1; macro <= opt.max_macro; ++macro) {
-    field(d_q.p, d_phi.p);
+    if (field32 && delta < 1e-6) {
+      field32 = false;
+      slots.clear();
+      next_slot = 0;
+    }
+    field(d_q.p, d_phi.p, field32);
     hipLaunchKernelGGL(k_gather_shell, dim3(mb.nsys), dim3(64), 0, stream, dmb, d_phi.p, mb.phi.p);
     int failed = 0;
     if (fused_mode) {

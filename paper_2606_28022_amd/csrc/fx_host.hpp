@@ -291,11 +291,11 @@ struct Ctx {
                   const int32_t* fchg, int32_t n_bonds, const int32_t* bonds);
   void build_lists_impl();
   void compute_cn();
-  void field(const double* d_q, double* d_phi);
+  void field(const double* d_q, double* d_phi, bool fp32 = false);
   void build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters, int nfrag_each);
   void build_matrices(Batch& b);
   void init_device();
-  JacobiPlan jacobi_plan(int n, bool fp64_only = false) const;
+  JacobiPlan jacobi_plan(int n, bool fp64_only = false, bool prefer_fp32 = false) const;
   // autotuned eigensolver launch shapes per (size bucket, precision)
   bool autotune = !(std::getenv("FX_AUTOTUNE") && std::atoi(std::getenv("FX_AUTOTUNE")) == 0);
   std::map<long long, JacobiPlan> tuned;

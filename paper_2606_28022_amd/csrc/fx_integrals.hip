@@ -318,6 +318,65 @@ __global__ void __launch_bounds__(256) k_field_partial(DevSystem sys, const doub
   }
 }
 
+// Mixed-precision form of the field pass (early monomer steps only): FP32
+// positions relative to the target, FP32 rsqrt and FP32 sums within a source
+// chunk; the chunk partials are added in FP64 by k_field_reduce.
+__global__ void __launch_bounds__(256) k_field_partial_f32(DevSystem sys, const double* q, int nchunk, double* part) {
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  const int chunk = blockIdx.y;
+  const int N = sys.natoms;
+  const int per = (N + nchunk - 1) / nchunk;
+  const int b_begin = chunk * per, b_end = min(N, b_begin + per);
+  __shared__ double sx[256], sy[256], sz[256];
+  __shared__ float si0[256], si1[256], sq0[256], sq1[256];
+  __shared__ int sf[256];
+  double xa = 0, ya = 0, za = 0;
+  float ia0 = 0.5f, ia1 = 0.5f;
+  int fa = -1, na = 0, sh0 = 0;
+  if (A < N) {
+    xa = sys.xyz[3 * A];
+    ya = sys.xyz[3 * A + 1];
+    za = sys.xyz[3 * A + 2];
+    fa = sys.frag[A];
+    sh0 = sys.atom_sh0[A];
+    na = sys.atom_sh0[A + 1] - sh0;
+    ia0 = (float)sys.sh_ieta[sh0];
+    ia1 = na > 1 ? (float)sys.sh_ieta[sh0 + 1] : 0.5f;
+  }
+  float acc0 = 0.0f, acc1 = 0.0f;
+  for (int b0 = b_begin; b0 < b_end; b0 += 256) {
+    const int b = b0 + threadIdx.x;
+    __syncthreads();
+    if (b < b_end) {
+      sx[threadIdx.x] = sys.xyz[3 * b];
+      sy[threadIdx.x] = sys.xyz[3 * b + 1];
+      sz[threadIdx.x] = sys.xyz[3 * b + 2];
+      sf[threadIdx.x] = sys.frag[b];
+      const int s0 = sys.atom_sh0[b];
+      const int nsb = sys.atom_sh0[b + 1] - s0;
+      si0[threadIdx.x] = (float)sys.sh_ieta[s0];
+      sq0[threadIdx.x] = (float)q[s0];
+      si1[threadIdx.x] = nsb > 1 ? (float)sys.sh_ieta[s0 + 1] : 0.5f;
+      sq1[threadIdx.x] = nsb > 1 ? (float)q[s0 + 1] : 0.0f;
+    }
+    __syncthreads();
+    const int nb = min(256, b_end - b0);
+    if (A < N)
+      for (int k = 0; k < nb; ++k) {
+        if (sf[k] == fa) continue;
+        const float dx = (float)(xa - sx[k]), dy = (float)(ya - sy[k]), dz = (float)(za - sz[k]);
+        const float R2 = dx * dx + dy * dy + dz * dz;
+        const float t00 = ia0 + si0[k], t01 = ia0 + si1[k], t10 = ia1 + si0[k], t11 = ia1 + si1[k];
+        acc0 += rsqrtf(R2 + t00 * t00) * sq0[k] + rsqrtf(R2 + t01 * t01) * sq1[k];
+        acc1 += rsqrtf(R2 + t10 * t10) * sq0[k] + rsqrtf(R2 + t11 * t11) * sq1[k];
+      }
+  }
+  if (A < N) {
+    part[(long long)chunk * sys.nshells + sh0] = acc0;
+    if (na > 1) part[(long long)chunk * sys.nshells + sh0 + 1] = acc1;
+  }
+}
+
 __global__ void k_field_reduce(int nshells, int nchunk, const double* part, double* phi) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nshells) return;

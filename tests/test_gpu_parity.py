@@ -246,3 +246,27 @@ def test_graph_schedule_matches_batched(lib, which):
             assert np.array_equal(a, b)
         assert np.array_equal(c.charges(), q0)
         assert r1["iters_dimer"] == r0["iters_dimer"]
+
+
+@pytest.mark.parametrize("which", ["c1", "pentacene6"])
+def test_mixed_precision_matches_fp64(lib, which):
+    """FX_MIXED (FP32 working matrices and early FP32 field passes, FP64
+    basis and final iterations) reaches the FP64 results within the FP64
+    tolerances: fragment energies 1e-8 Eh, gradient 1e-7 Eh/bohr."""
+    _say(f"mixed precision {which}")
+    s = w.water_cluster_cube() if which == "c1" else w.pentacene_crystal(reps=(2, 2, 1)).subset(list(range(6)))
+    c = lib()
+    c.set_system(s.Z, s.xyz, s.frag, s.frag_charge)
+    c.set_options(want_gradient=1, precision=0)
+    r0 = c.run()
+    e0 = c.energies()
+    g0 = c.gradient()
+    c.set_options(precision=1)
+    r1 = c.run()
+    e1 = c.energies()
+    g1 = c.gradient()
+    assert abs(r1["e_total"] - r0["e_total"]) < 1e-8 * s.n_frag
+    for a, b in zip(e0, e1):
+        if len(a):
+            assert np.max(np.abs(a - b)) < 1e-8
+    assert np.max(np.abs(g1 - g0)) < 1e-7
