@@ -429,6 +429,10 @@ void Ctx::init_device() {
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_precond_build),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds_max - 16384);
+  for (const void* k : {reinterpret_cast<const void*>(k_jacobi_rot<double>),
+                        reinterpret_cast<const void*>(k_jacobi_rot<float>),
+                        reinterpret_cast<const void*>(k_apply_rot)})
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
   (void)hipGetLastError();
   if (verbose) std::fprintf(stderr, "[fx] LDS per workgroup %d B, static %u B\n", v, stat);
 }
@@ -730,11 +734,47 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
   const int max_it = single ? 1 : opt.max_iter + 1;
   // one SCC iteration over the systems in dl (na of them); converged systems
   // listed there return at once (device-side status)
+  bool last_split = false;
+  // split eigensolver: rotation log of up to jacobi_max_log sweeps per system
+  const int m_max = b.max_nao + (b.max_nao & 1);
+  const long long log_stride = (long long)jacobi_max_log * (m_max - 1) * (m_max / 2);
+  const bool split_ok = jacobi_split && jp.elt != 0 &&
+                        b.max_nao * 512 + 16 * 16 * (m_max / 2) + 16 * ((16 * (m_max / 2) + 3) / 4) <= lds_max &&
+                        (int)jacobi_lds_layout(b.max_nao, jp.elt, 1, 0).total <= lds_max;
+  if (split_ok) {
+    b.rotlog.alloc((long long)b.nsys * log_stride);
+    b.nlog.alloc(b.nsys);
+  }
+  KernelTimer* kt_rot = kt(jp.elt == 8 ? "fx::k_jacobi_rot<double>" : "fx::k_jacobi_rot<float>");
+  KernelTimer* kt_app = kt("fx::k_apply_rot");
   auto launch_iteration = [&](const std::vector<int>& act, const int* dl, int na, double cap, bool timed) {
     hipLaunchKernelGGL(k_fock, dim3(na), dim3(256), 0, stream, ds, db, dl);
     // A = C^T F C in the current basis, then Jacobi rotations
     gemm_batch(b, db, na, dl, 0, b.Ct.p, b.Fm.p, b.Tm.p, nullptr, b.gemm_gflop(act), 1);
     gemm_batch(b, db, na, dl, 1, b.Tm.p, b.Ct.p, b.Fm.p, nullptr, b.gemm_gflop(act), 1);
+    if (split_ok && cap < 1e299) {
+      const unsigned lds_rot = jacobi_lds_layout(b.max_nao, jp.elt, 1, 0).total;
+      int ev = timed ? timers.begin(stream) : -1;
+      if (jp.elt == 8)
+        hipLaunchKernelGGL(k_jacobi_rot<double>, dim3(na), dim3(jp.threads), lds_rot, stream, db, dl,
+                           jacobi_max_sweeps, jacobi_tol, jacobi_thr_scale, cap, b.sweeps.p, b.rotlog.p, log_stride,
+                           jacobi_max_log, b.nlog.p);
+      else
+        hipLaunchKernelGGL(k_jacobi_rot<float>, dim3(na), dim3(jp.threads), lds_rot, stream, db, dl,
+                           jacobi_max_sweeps, jacobi_tol, jacobi_thr_scale, cap, b.sweeps.p, b.rotlog.p, log_stride,
+                           jacobi_max_log, b.nlog.p);
+      if (timed) timers.end(stream, ev, kt_rot, 0.0);
+      const int tps = (b.max_nao + 63) / 64;
+      const long long grid = ((long long)na * tps + 7) / 8 * 8;
+      ev = timed ? timers.begin(stream) : -1;
+      const unsigned ce = 16u * (unsigned)(m_max / 2);
+      const unsigned lds_app = (unsigned)b.max_nao * 512u + 16u * ce + 16u * ((ce + 3u) / 4u);
+      hipLaunchKernelGGL(k_apply_rot, dim3((unsigned)grid), dim3(1024), lds_app, stream, db, dl,
+                         na, tps, (const double2*)b.rotlog.p, log_stride, (const int*)b.nlog.p);
+      if (timed) timers.end(stream, ev, kt_app, 0.0);
+      last_split = true;
+    } else {
+      last_split = false;
     const int ev = timed ? timers.begin(stream) : -1;
     if (jp.elt == 8)
       hipLaunchKernelGGL(k_jacobi_lds<double>, dim3(na), dim3(jp.threads), jp.lds, stream, db, dl, jacobi_max_sweeps,
@@ -746,6 +786,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
       hipLaunchKernelGGL(k_jacobi, dim3(na), dim3(jacobi_threads), 0, stream, db, dl, jacobi_max_sweeps, jacobi_tol,
                          jacobi_thr_scale, cap, b.sweeps.p);
     if (timed) timers.end(stream, ev, kt_jac, 0.0);
+    }
     hipLaunchKernelGGL(k_fermi, dim3(na), dim3(256), 0, stream, ds, db, dl);
     gemm_batch(b, db, na, dl, 2, b.Ct.p, b.Ct.p, b.Pm.p, b.occ.p, b.gemm_gflop(act), 1);
     hipLaunchKernelGGL(k_charges_mix, dim3(na), dim3(256), 0, stream, ds, db, dl,
@@ -791,7 +832,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     }
     d_act.upload(active);
     const int na = (int)active.size();
-    if (it == 1 && autotune && jp.elt != 0 && !tuned.count(jp_key(b.max_nao, jp.elt))) {
+    if (it == 1 && autotune && !split_ok && jp.elt != 0 && !tuned.count(jp_key(b.max_nao, jp.elt))) {
       // form this iteration's A once, time the eigensolver's launch shapes
       // on copies of (A, C^T) and keep the fastest for this size bucket; all
       // shapes give bitwise identical results
@@ -829,7 +870,14 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     // 6 n^2 flop per step times (n - 1) steps
     for (int s : active) {
       double n = b.h_desc[s].nao;
-      kt_jac->gflop += 1e-9 * 6.0 * n * n * (n - 1.0) * (double)sweeps[s];
+      const double gf = 1e-9 * 6.0 * n * n * (n - 1.0) * (double)sweeps[s];
+      if (last_split) {
+        // the working-matrix update and the basis rotation are half each
+        kt_rot->gflop += 0.5 * gf;
+        kt_app->gflop += 0.5 * gf;
+      } else {
+        kt_jac->gflop += gf;
+      }
     }
     std::vector<int> next;
     for (int s : active)

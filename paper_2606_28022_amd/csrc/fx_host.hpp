@@ -118,6 +118,9 @@ struct Batch {
   // gam layout); used by the mixer when has_pre is set
   DevBuf<float> pre;
   bool has_pre = false;
+  // rotation log of the split eigensolver (k_jacobi_rot / k_apply_rot)
+  DevBuf<double2> rotlog;
+  DevBuf<int> nlog;
   // covalent boundaries: per local shell reference population, per local atom
   // repulsion-charge scale, boundary atoms (local atom, kind 1 detached /
   // 2 ghost, bond direction) and the ghosts healed inside each system
@@ -298,6 +301,10 @@ struct Ctx {
   JacobiPlan jacobi_plan(int n, bool fp64_only = false, bool prefer_fp32 = false) const;
   // autotuned eigensolver launch shapes per (size bucket, precision)
   bool autotune = !(std::getenv("FX_AUTOTUNE") && std::atoi(std::getenv("FX_AUTOTUNE")) == 0);
+  // split eigensolver (rotation kernel + apply kernel) for single-sweep
+  // iterations; FX_JACOBI_SPLIT=0 keeps the fused kernel everywhere
+  bool jacobi_split = !(std::getenv("FX_JACOBI_SPLIT") && std::atoi(std::getenv("FX_JACOBI_SPLIT")) == 0);
+  int jacobi_max_log = 2;
   std::map<long long, JacobiPlan> tuned;
   static long long jp_key(int n, int elt) { return (long long)n * 16 + elt; }
   JacobiPlan autotune_jacobi(Batch& b, const int* dl, int na, const JacobiPlan& base, double cap);

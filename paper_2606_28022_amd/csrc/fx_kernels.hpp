@@ -64,6 +64,12 @@ __host__ __device__ inline JacobiLdsLayout jacobi_lds_layout(int n, int elt, int
   return L;
 }
 template <typename T>
+__global__ void k_jacobi_rot(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale,
+                             double cap_err, int* sweeps_out, double2* logbuf, long long log_stride, int max_log,
+                             int* nlog);
+__global__ void k_apply_rot(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double2* logbuf,
+                            long long log_stride, const int* nlog);
+template <typename T>
 __global__ void k_jacobi_lds(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale,
                              double cap_err, int* sweeps_out, int chunk);
 __global__ void k_eigh_batched(const int* nvec, const long long* off, double* Abuf, double* Vbuf, double* wbuf,

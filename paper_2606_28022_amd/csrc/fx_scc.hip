@@ -1145,3 +1145,258 @@ __global__ void __launch_bounds__(256)
 }
 
 }  // namespace fx
+
+namespace fx {
+
+// ---------------------------------------------------------------------------
+// Split form of the LDS Jacobi for single-sweep SCC iterations.
+//
+// k_jacobi_rot: the same sweeps as k_jacobi_lds on the LDS working matrix,
+// but instead of rotating C^T chunk by chunk it writes the sweep's rotation
+// log (c, s per step and pair, FP64) to HBM: up to `max_log` sweeps.
+// k_apply_rot then applies the logged rotations to C^T in 64-column tiles
+// held in LDS for the whole sweep, several work-groups per system.  C^T is
+// read and written once per launch instead of once per chunk of steps, and
+// every element sees the same rotations in the same order as in
+// k_jacobi_lds, so the results are identical.
+template <typename T>
+__global__ void __launch_bounds__(1024)
+    k_jacobi_rot(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale, double cap_err,
+                 int* sweeps_out, double2* logbuf, long long log_stride, int max_log, int* nlog) {
+  extern __shared__ double2 lds_raw[];
+  unsigned char* lds = reinterpret_cast<unsigned char*>(lds_raw);
+  const int si = list[blockIdx.x];
+  if (bt.status[si] != 0) return;
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao;
+  const int m = n + (n & 1), nb = m / 2;
+  const int nt = blockDim.x;
+  const JacobiLdsLayout L = jacobi_lds_layout(n, (int)sizeof(T), 1, 0);
+  T* Ap = reinterpret_cast<T*>(lds + L.ap);
+  double* dg = reinterpret_cast<double*>(lds + L.dg);
+  double2* cs = reinterpret_cast<double2*>(lds + L.cs);  // [nb] (c, s) of the current step
+  int* pq = reinterpret_cast<int*>(lds + L.pq);          // [nb] p | q << 16
+  double* red = reinterpret_cast<double*>(lds + L.red);
+  double* rows = reinterpret_cast<double*>(cs);  // row sums before the sweeps (nb * 16 >= 8 n bytes)
+  const double* __restrict__ A = bt.F + d.mat_off;
+  double2* lg = logbuf + (long long)si * log_stride;
+  for (int e = threadIdx.x; e < n * n; e += nt) {
+    const int i = e / n, j = e - i * n;
+    if (j < i) continue;
+    const double v = A[e];
+    if (i == j)
+      dg[i] = v;
+    else
+      Ap[pk_index(i, j)] = (T)v;
+  }
+  for (int i = threadIdx.x; i < n; i += nt) {
+    double r = 0.0;
+    for (int j = i; j < n; ++j) {
+      const double v = A[(long long)i * n + j];
+      r += (j == i) ? fmin(v * v, 100.0) : 2.0 * v * v;
+    }
+    rows[i] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double f = 0.0;
+    for (int i = 0; i < n; ++i) f += rows[i];
+    red[0] = sqrt(f);
+  }
+  __syncthreads();
+  const double fro = red[0];
+  const double err = bt.err[si];
+  const double thr = fmax(rel_tol * (fro > 0.0 ? fro : 1.0), thr_scale * err);
+  const int msw = min(max_log, err > cap_err ? 1 : max_sweeps);
+  const int R = nb - 1, hp = R / 2, rect = hp * nb, noff = nb * (nb - 1) / 2;
+  int sweep = 0;
+  bool converged = false;
+  for (; sweep < msw; ++sweep) {
+    int rot_sweep = 0;
+    double2* ls = lg + (long long)sweep * (m - 1) * nb;
+    for (int step = 0; step < m - 1; ++step) {
+      for (int k = threadIdx.x; k < nb; k += nt) {
+        int p = rr_index(k, step, m), q = rr_index(m - 1 - k, step, m);
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          const int ipq = pk_index(p, q);
+          const double apq = (double)Ap[ipq];
+          const double app = dg[p], aqq = dg[q];
+          if (fabs(apq) > fmax(thr, rel_tol * fmax(fabs(app), fabs(aqq)))) {
+            const double theta = (aqq - app) / (2.0 * apq);
+            const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+            dg[p] = app - t * apq;
+            dg[q] = aqq + t * apq;
+            Ap[ipq] = (T)0;
+            rot_sweep = 1;
+          }
+        }
+        cs[k] = make_double2(c, s);
+        pq[k] = p | (q << 16);
+        ls[(long long)step * nb + k] = make_double2(c, s);
+      }
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < noff; idx += nt) {
+        int a, b;
+        if (idx < rect) {
+          const int r = idx / nb, cc = idx - r * nb;
+          if (cc < R - r) {
+            a = r;
+            b = r + 1 + cc;
+          } else {
+            a = R - 1 - r;
+            b = a + 1 + (cc - (R - r));
+          }
+        } else {
+          a = hp;
+          b = hp + 1 + (idx - rect);
+        }
+        const double2 wa = cs[a], wb = cs[b];
+        if (wa.y == 0.0 && wb.y == 0.0) continue;
+        const int va = pq[a], vb = pq[b];
+        const int p = va & 0xffff, q = va >> 16, r = vb & 0xffff, u = vb >> 16;
+        const bool qv = q < n, uv = u < n;
+        const T ca = (T)wa.x, sa = (T)wa.y, cb = (T)wb.x, sb = (T)wb.y;
+        const int ipr = pk_index(p, r);
+        const int ipu = uv ? pk_index(p, u) : 0;
+        const int iqr = qv ? pk_index(q, r) : 0;
+        const int iqu = (qv && uv) ? pk_index(q, u) : 0;
+        const T bpr = Ap[ipr];
+        const T bpu = uv ? Ap[ipu] : (T)0;
+        const T bqr = qv ? Ap[iqr] : (T)0;
+        const T bqu = (qv && uv) ? Ap[iqu] : (T)0;
+        const T tpr = ca * bpr - sa * bqr, tpu = ca * bpu - sa * bqu;
+        const T tqr = sa * bpr + ca * bqr, tqu = sa * bpu + ca * bqu;
+        Ap[ipr] = cb * tpr - sb * tpu;
+        if (uv) Ap[ipu] = sb * tpr + cb * tpu;
+        if (qv) Ap[iqr] = cb * tqr - sb * tqu;
+        if (qv && uv) Ap[iqu] = sb * tqr + cb * tqu;
+      }
+      __syncthreads();
+    }
+    if (!__syncthreads_or(rot_sweep)) {
+      converged = true;  // this sweep rotated nothing: its (identity) log is not applied
+      break;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += nt) bt.eps[d.ao_off + i] = dg[i];
+  if (threadIdx.x == 0) {
+    nlog[si] = sweep;  // sweeps with rotations, all before the empty one
+    if (sweeps_out) sweeps_out[si] = converged ? sweep + 1 : sweep;
+  }
+}
+
+template __global__ void k_jacobi_rot<double>(DevBatch, const int*, int, double, double, double, int*, double2*,
+                                              long long, int, int*);
+template __global__ void k_jacobi_rot<float>(DevBatch, const int*, int, double, double, double, int*, double2*,
+                                             long long, int, int*);
+
+// Apply the logged rotations to the rows of C^T, one 64-column tile per
+// work-group of 16 waves (lane = column): the tile stays in LDS for all
+// logged sweeps; the log is staged into LDS 16 steps at a time (coalesced
+// loads, the next chunk fetched into registers while the current one is
+// applied) together with the pair indices of those steps; within a step the
+// pairs are disjoint, so the waves share them (pair k to wave k % 16, two
+// pairs in flight per wave) with one barrier per step.
+constexpr int APPLY_CHUNK = 16;
+__global__ void __launch_bounds__(1024)
+    k_apply_rot(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double2* logbuf, long long log_stride,
+                const int* nlog) {
+  extern __shared__ double2 lds_raw[];
+  const int Lid = blockIdx.x, G = gridDim.x;  // G is a multiple of 8
+  const int logical = (Lid & 7) * (G >> 3) + (Lid >> 3);
+  const int sl = logical / tiles_per_sys, tcol = logical - sl * tiles_per_sys;
+  if (sl >= nl) return;
+  const int si = list[sl];
+  if (bt.status[si] != 0) return;
+  const int nsw = nlog[si];
+  if (nsw <= 0) return;
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao, nv = d.nao;
+  const int c0 = tcol * 64;
+  if (c0 >= nv) return;
+  const int m = n + (n & 1), nb = m / 2;
+  const int NT = blockDim.x, NW = NT >> 6;
+  double2* lc = lds_raw;                                           // [APPLY_CHUNK][nb] (c, s)
+  int* lpq = reinterpret_cast<int*>(lds_raw + APPLY_CHUNK * nb);   // [APPLY_CHUNK][nb] p | q << 16
+  double* tile = reinterpret_cast<double*>(lds_raw + APPLY_CHUNK * nb + (APPLY_CHUNK * nb + 3) / 4);  // [n][64]
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double* V = bt.Ct + d.mat_off;
+  const bool colok = c0 + lane < nv;
+  for (int i = wave; i < n; i += NW) tile[i * 64 + lane] = colok ? V[(long long)i * nv + c0 + lane] : 0.0;
+  const double2* lg = logbuf + (long long)si * log_stride;
+  const long long total = (long long)nsw * (m - 1);  // steps over all logged sweeps
+  const int CE = APPLY_CHUNK * nb;                   // entries per chunk
+  double2 rg[4];                                     // CE <= 4096 entries, NT = 1024
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int e = threadIdx.x + NT * r;
+    rg[r] = (e < CE && e / nb < total) ? lg[e] : make_double2(1.0, 0.0);
+  }
+  for (long long s0 = 0; s0 < total; s0 += APPLY_CHUNK) {
+    __syncthreads();  // previous chunk applied, tile loaded
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = threadIdx.x + NT * r;
+      if (e < CE) {
+        lc[e] = rg[r];
+        const int c = e / nb, k = e - c * nb;
+        const int step = (int)((s0 + c) % (m - 1));
+        int p = rr_index(k, step, m), q = rr_index(m - 1 - k, step, m);
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        lpq[e] = p | (q << 16);
+      }
+    }
+    __syncthreads();
+    const long long s1 = s0 + APPLY_CHUNK;
+    if (s1 < total) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int e = threadIdx.x + NT * r;
+        rg[r] = (e < CE && s1 + e / nb < total) ? lg[s1 * nb + e] : make_double2(1.0, 0.0);
+      }
+    }
+    const int ns = (int)((total - s0) < APPLY_CHUNK ? (total - s0) : APPLY_CHUNK);
+    for (int c = 0; c < ns; ++c) {
+      const double2* lw = lc + c * nb;
+      const int* lp = lpq + c * nb;
+      for (int k = wave; k < nb; k += 2 * NW) {
+        const int k2 = k + NW;
+        const double2 w1 = lw[k];
+        const double2 w2 = k2 < nb ? lw[k2] : make_double2(1.0, 0.0);
+        const bool r1 = w1.y != 0.0, r2 = w2.y != 0.0;
+        const int v1 = lp[k], v2 = k2 < nb ? lp[k2] : 0;
+        const int p1 = v1 & 0xffff, q1 = v1 >> 16, p2 = v2 & 0xffff, q2 = v2 >> 16;
+        // the two pairs are disjoint: load both, then store both
+        const double a1 = r1 ? tile[p1 * 64 + lane] : 0.0, b1 = r1 ? tile[q1 * 64 + lane] : 0.0;
+        const double a2 = r2 ? tile[p2 * 64 + lane] : 0.0, b2 = r2 ? tile[q2 * 64 + lane] : 0.0;
+        if (r1) {
+          tile[p1 * 64 + lane] = w1.x * a1 - w1.y * b1;
+          tile[q1 * 64 + lane] = w1.y * a1 + w1.x * b1;
+        }
+        if (r2) {
+          tile[p2 * 64 + lane] = w2.x * a2 - w2.y * b2;
+          tile[q2 * 64 + lane] = w2.y * a2 + w2.x * b2;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (colok)
+    for (int i = wave; i < n; i += NW) V[(long long)i * nv + c0 + lane] = tile[i * 64 + lane];
+}
+
+}  // namespace fx
