@@ -440,7 +440,7 @@ void Ctx::init_device() {
 // Batched n x n products of the listed systems (first nl entries of dlist):
 // the matrix-core kernel once a system spans more than one 32 x 32 tile.
 void Ctx::gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlist, int mode, const double* A,
-                     const double* B, double* C, const double* w, double gflop, int skip_done) {
+                     const double* B, double* C, const double* w, double gflop, int skip_done, int sym) {
   if (nl <= 0) return;
   const bool timed = !capturing;
   if (b.max_nao <= 32) {
@@ -454,7 +454,7 @@ void Ctx::gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlis
     if (grid > 0x7fffffffLL) throw FxError(FX_E_INVALID, "batched product grid too large");
     const int ev = timed ? timers.begin(stream) : -1;
     hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)grid), dim3(256), 0, stream, db, dlist, nl, nt * nt, mode, A, B, C,
-                       w, skip_done);
+                       w, skip_done, sym);
     if (timed) timers.end(stream, ev, kt("fx::k_gemm_mfma"), gflop);
   }
   check(hipGetLastError(), "batched product");
@@ -751,7 +751,8 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     hipLaunchKernelGGL(k_fock, dim3(na), dim3(256), 0, stream, ds, db, dl);
     // A = C^T F C in the current basis, then Jacobi rotations
     gemm_batch(b, db, na, dl, 0, b.Ct.p, b.Fm.p, b.Tm.p, nullptr, b.gemm_gflop(act), 1);
-    gemm_batch(b, db, na, dl, 1, b.Tm.p, b.Ct.p, b.Fm.p, nullptr, b.gemm_gflop(act), 1);
+    // A = (C^T F) C is symmetric: upper tiles only, mirrored
+    gemm_batch(b, db, na, dl, 1, b.Tm.p, b.Ct.p, b.Fm.p, nullptr, b.gemm_gflop(act), 1, 1);
     if (split_ok && cap < 1e299) {
       const unsigned lds_rot = jacobi_lds_layout(b.max_nao, jp.elt, 1, 0).total;
       int ev = timed ? timers.begin(stream) : -1;
@@ -788,7 +789,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     if (timed) timers.end(stream, ev, kt_jac, 0.0);
     }
     hipLaunchKernelGGL(k_fermi, dim3(na), dim3(256), 0, stream, ds, db, dl);
-    gemm_batch(b, db, na, dl, 2, b.Ct.p, b.Ct.p, b.Pm.p, b.occ.p, b.gemm_gflop(act), 1);
+    gemm_batch(b, db, na, dl, 2, b.Ct.p, b.Ct.p, b.Pm.p, b.occ.p, b.gemm_gflop(act), 1, 1);
     hipLaunchKernelGGL(k_charges_mix, dim3(na), dim3(256), 0, stream, ds, db, dl,
                        scc_tol_cur > 0 ? scc_tol_cur : opt.scc_tol, etol_cur > 0 ? etol_cur : opt.energy_tol,
                        single ? 1 : opt.max_iter, b.has_pre ? precond_beta : mix_beta);

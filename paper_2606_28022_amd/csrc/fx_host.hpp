@@ -309,7 +309,7 @@ struct Ctx {
   static long long jp_key(int n, int elt) { return (long long)n * 16 + elt; }
   JacobiPlan autotune_jacobi(Batch& b, const int* dl, int na, const JacobiPlan& base, double cap);
   void gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlist, int mode, const double* A,
-                  const double* B, double* C, const double* w, double gflop, int skip_done = 0);
+                  const double* B, double* C, const double* w, double gflop, int skip_done = 0, int sym = 0);
   // graph-captured SCC iterations (schedule FX_BATCHED_GRAPH)
   bool capturing = false;
   hipStream_t gstream = nullptr;

@@ -270,7 +270,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(256)
     k_gemm_mfma(DevBatch bt, const int* list, int nl, int tiles_per_sys, int mode, const double* __restrict__ Abase,
                 const double* __restrict__ Bbase, double* __restrict__ Cbase, const double* __restrict__ wbase,
-                int skip_done) {
+                int skip_done, int sym) {
   const int L = blockIdx.x, G = gridDim.x;  // G is a multiple of 8
   const int logical = (L & 7) * (G >> 3) + (L >> 3);
   const int sl = logical / tiles_per_sys, tile = logical - sl * tiles_per_sys;
@@ -282,6 +282,8 @@ __global__ void __launch_bounds__(256)
   const int nt = (n + 63) / 64;
   if (tile >= nt * nt) return;
   const int ti = tile / nt, tj = tile - ti * nt;
+  // symmetric product: only the upper tiles, mirrored on store
+  if (sym && ti > tj) return;
   const double* A = Abase + d.mat_off;
   const double* B = Bbase + d.mat_off;
   double* C = Cbase + d.mat_off;
@@ -297,31 +299,51 @@ __global__ void __launch_bounds__(256)
   for (int u = 0; u < 2; ++u)
 #pragma unroll
     for (int v = 0; v < 2; ++v) acc[u][v] = (v4d){0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < n; k0 += KS) {
-    // stage A (as [k][i]) and B (as [k][j]); 2048 elements each, 8 per thread
+  // operands of one K slab, 8 A and 8 B elements per thread, held in
+  // registers so that the next slab's loads overlap this slab's products
+  double ra[8], rb[8];
+  auto fetch = [&](int k0) {
 #pragma unroll
     for (int h = 0; h < 8; ++h) {
       const int e = threadIdx.x + 256 * h;
       if (mode == 2) {
-        const int k = e >> 6, i = e & 63;  // A^T diag(w): rows of A are k
+        const int k = e >> 6, i = e & 63;
         const int gk = k0 + k, gi = i0 + i;
-        As[k][i] = (gk < n && gi < n) ? A[(long long)gk * n + gi] * (w ? w[gk] : 1.0) : 0.0;
+        ra[h] = (gk < n && gi < n) ? A[(long long)gk * n + gi] * (w ? w[gk] : 1.0) : 0.0;
       } else {
         const int i = e >> 5, k = e & 31;
         const int gi = i0 + i, gk = k0 + k;
-        As[k][i] = (gi < n && gk < n) ? A[(long long)gi * n + gk] : 0.0;
+        ra[h] = (gi < n && gk < n) ? A[(long long)gi * n + gk] : 0.0;
       }
       if (mode == 1) {
-        const int j = e >> 5, k = e & 31;  // B^T: rows of B are j
+        const int j = e >> 5, k = e & 31;
         const int gj = j0 + j, gk = k0 + k;
-        Bs[k][j] = (gj < n && gk < n) ? B[(long long)gj * n + gk] : 0.0;
+        rb[h] = (gj < n && gk < n) ? B[(long long)gj * n + gk] : 0.0;
       } else {
         const int k = e >> 6, j = e & 63;
         const int gk = k0 + k, gj = j0 + j;
-        Bs[k][j] = (gk < n && gj < n) ? B[(long long)gk * n + gj] : 0.0;
+        rb[h] = (gk < n && gj < n) ? B[(long long)gk * n + gj] : 0.0;
+      }
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < n; k0 += KS) {
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      const int e = threadIdx.x + 256 * h;
+      if (mode == 2) {
+        As[e >> 6][e & 63] = ra[h];
+      } else {
+        As[e & 31][e >> 5] = ra[h];
+      }
+      if (mode == 1) {
+        Bs[e & 31][e >> 5] = rb[h];
+      } else {
+        Bs[e >> 6][e & 63] = rb[h];
       }
     }
     __syncthreads();
+    if (k0 + KS < n) fetch(k0 + KS);
 #pragma unroll
     for (int kk = 0; kk < KS; kk += 4) {
       const int kr = kk + (lane >> 4), c = lane & 15;
@@ -342,7 +364,10 @@ __global__ void __launch_bounds__(256)
       for (int r = 0; r < 4; ++r) {
         const int gi = i0 + wi * 32 + u * 16 + (lane >> 4) + 4 * r;
         const int gj = j0 + wj * 32 + v * 16 + (lane & 15);
-        if (gi < n && gj < n) C[(long long)gi * n + gj] = acc[u][v][r];
+        if (gi < n && gj < n) {
+          C[(long long)gi * n + gj] = acc[u][v][r];
+          if (sym && ti < tj) C[(long long)gj * n + gi] = acc[u][v][r];
+        }
       }
 }
 
