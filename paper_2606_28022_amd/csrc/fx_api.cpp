@@ -427,6 +427,8 @@ void Ctx::init_device() {
   for (const void* k : {reinterpret_cast<const void*>(k_jacobi_lds<double>),
                         reinterpret_cast<const void*>(k_jacobi_lds<float>)})
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_resp_M), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds_max);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_precond_build),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds_max - 16384);
   for (const void* k : {reinterpret_cast<const void*>(k_jacobi_rot<double>),
@@ -460,6 +462,14 @@ void Ctx::gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlis
   check(hipGetLastError(), "batched product");
 }
 
+unsigned Ctx::resp_M_lds(const Batch& b) const {
+  int nsh = 0;
+  for (const auto& d : b.h_desc) nsh = std::max(nsh, d.nsh);
+  const size_t by = resp_M_lds_bytes(nsh);
+  if ((long long)by > (long long)lds_max) throw FxError(FX_E_UNSUPPORTED, "monomer with too many shells");
+  return (unsigned)by;
+}
+
 // Charge susceptibilities of the monomers from their current orbitals
 // (shell-summed transition charges Q and M = sum_ai Q Q^T / (eps_a - eps_i));
 // closed-shell monomers only (returns false otherwise).
@@ -476,6 +486,11 @@ bool Ctx::monomer_response_setup() {
     nocc[k] = ne / 2;
     qoff[k + 1] = qoff[k] + (long long)d.nsh * nocc[k] * (d.nao - nocc[k]);
   }
+  {
+    int nsh = 0;
+    for (const auto& d : b.h_desc) nsh = std::max(nsh, d.nsh);
+    if ((long long)resp_M_lds_bytes(nsh) > (long long)lds_max) return false;
+  }
   DevBatch dmb = b.dev();
   resp_nocc.upload(nocc);
   resp_qoff.upload(qoff);
@@ -490,7 +505,7 @@ bool Ctx::monomer_response_setup() {
   gemm_batch(b, dmb, b.nsys, b.d_list.p, 0, b.Ct.p, b.S.p, b.Tm.p, (const double*)nullptr, b.gemm_gflop_all());
   hipLaunchKernelGGL(k_resp_Q, dim3(b.nsys), dim3(256), 0, stream, dev_system(), dmb, b.Tm.p, resp_order.p,
                      resp_nocc.p, resp_qoff.p, resp_Q.p);
-  hipLaunchKernelGGL(k_resp_M, dim3(b.nsys), dim3(256), 0, stream, dmb, resp_order.p, resp_nocc.p, resp_qoff.p,
+  hipLaunchKernelGGL(k_resp_M, dim3(b.nsys), dim3(256), resp_M_lds(b), stream, dmb, resp_order.p, resp_nocc.p, resp_qoff.p,
                      resp_Q.p, resp_M.p);
   check(hipGetLastError(), "monomer susceptibilities");
   resp_ok = true;
@@ -1154,6 +1169,7 @@ void Ctx::run(fx_result* out) {
     throw FxError(FX_E_UNSUPPORTED, "the gradient with cut covalent bonds is not available");
   std::memset(&res, 0, sizeof(res));
   ktimers.clear();
+  resp_ok = false;
   bool all_conv = true;
   double t0 = now_ms();
   if (!lists_built) build_lists_impl();
@@ -1290,7 +1306,10 @@ void Ctx::run(fx_result* out) {
   }
   res.macro_iter = macro;
   res.iters_mono = it_mono;
-  if (precond) monomer_response_setup();
+  // susceptibilities of the converged monomers: dimer preconditioners and the
+  // response of the gradient
+  resp_ok = false;
+  if (precond || (opt.want_gradient && opt.want_response)) monomer_response_setup();
   // final embedding field of the converged charges
   field(d_q.p, d_phi.p);
   e_mono.alloc(F);

@@ -125,12 +125,14 @@ void Ctx::gradient() {
     d_nocc.upload(nocc);
     DevBuf<long long> d_qoff;
     d_qoff.upload(qoff);
-    order.alloc(b.tot_ao);
     DevBuf<double> Q, M, R, Wk, G1, G2, G3, w, y, yn, ul, gx;
-    Q.alloc(qoff[b.nsys]);
     long long tot_gam = 0;
     for (auto& d : b.h_desc) tot_gam += (long long)d.nsh * d.nsh;
-    M.alloc(tot_gam);
+    if (!resp_ok) {
+      order.alloc(b.tot_ao);
+      Q.alloc(qoff[b.nsys]);
+      M.alloc(tot_gam);
+    }
     R.alloc(tot_gam);
     Wk.alloc(tot_gam);
     G1.alloc(b.tot_mat);
@@ -144,13 +146,25 @@ void Ctx::gradient() {
     for (int k = 0; k < b.nsys; ++k) all[k] = k;
     b.d_list.upload(all);
     const int nt = (b.max_nao + 31) / 32;
-    hipLaunchKernelGGL(k_mo_order, dim3(b.nsys), dim3(256), 0, stream, dmb, d_nocc.p, order.p);
-    // (SC)^T = Ct S into G1
-    gemm_batch(b, dmb, (int)b.nsys, b.d_list.p, 0, b.Ct.p, b.S.p, G1.p, (const double*)nullptr, b.gemm_gflop_all());
-    hipLaunchKernelGGL(k_resp_Q, dim3(b.nsys), dim3(256), 0, stream, ds, dmb, G1.p, order.p, d_nocc.p, d_qoff.p,
-                       Q.p);
-    hipLaunchKernelGGL(k_resp_M, dim3(b.nsys), dim3(256), 0, stream, dmb, order.p, d_nocc.p, d_qoff.p, Q.p, M.p);
-    hipLaunchKernelGGL(k_resp_R, dim3(b.nsys), dim3(256), 0, stream, ds, dmb, M.p, Wk.p, R.p);
+    // the susceptibility blocks of the converged monomer orbitals are kept
+    // from the monomer loop when available
+    const int* p_order = order.p;
+    const double* p_Q = Q.p;
+    const double* p_M = M.p;
+    if (resp_ok) {
+      p_order = resp_order.p;
+      p_Q = resp_Q.p;
+      p_M = resp_M.p;
+    } else {
+      hipLaunchKernelGGL(k_mo_order, dim3(b.nsys), dim3(256), 0, stream, dmb, d_nocc.p, order.p);
+      // (SC)^T = Ct S into G1
+      gemm_batch(b, dmb, (int)b.nsys, b.d_list.p, 0, b.Ct.p, b.S.p, G1.p, (const double*)nullptr,
+                 b.gemm_gflop_all());
+      hipLaunchKernelGGL(k_resp_Q, dim3(b.nsys), dim3(256), 0, stream, ds, dmb, G1.p, order.p, d_nocc.p, d_qoff.p,
+                         Q.p);
+      hipLaunchKernelGGL(k_resp_M, dim3(b.nsys), dim3(256), resp_M_lds(b), stream, dmb, order.p, d_nocc.p, d_qoff.p, Q.p, M.p);
+    }
+    hipLaunchKernelGGL(k_resp_R, dim3(b.nsys), dim3(256), 0, stream, ds, dmb, p_M, Wk.p, R.p);
     check(hipGetLastError(), "response setup");
     // adjoint sweeps y = v + field_excl(u(y)), Anderson-accelerated
     DevBuf<double> yg, yng, hX, hR, hB, hC, fu;
@@ -169,7 +183,7 @@ void Ctx::gradient() {
     int it = 0;
     for (it = 1; it <= 400; ++it) {
       hipLaunchKernelGGL(k_gather_shell, dim3(b.nsys), dim3(64), 0, stream, dmb, yg.p, y.p);
-      hipLaunchKernelGGL(k_resp_apply, dim3(b.nsys), dim3(256), 0, stream, dmb, R.p, M.p, y.p, w.p, ul.p);
+      hipLaunchKernelGGL(k_resp_apply, dim3(b.nsys), dim3(256), 0, stream, dmb, R.p, p_M, y.p, w.p, ul.p);
       hipLaunchKernelGGL(k_scatter_shell, dim3(b.nsys), dim3(64), 0, stream, dmb, ul.p, u.p);
       field(u.p, fu.p);
       hipLaunchKernelGGL(k_axpy, dim3(gN), dim3(256), 0, stream, (long long)Nsh, v.p, 1.0, fu.p, yng.p);
@@ -201,10 +215,10 @@ void Ctx::gradient() {
     response_sweeps = it;
     // final w, u from the converged y
     hipLaunchKernelGGL(k_gather_shell, dim3(b.nsys), dim3(64), 0, stream, dmb, yng.p, y.p);
-    hipLaunchKernelGGL(k_resp_apply, dim3(b.nsys), dim3(256), 0, stream, dmb, R.p, M.p, y.p, w.p, ul.p);
+    hipLaunchKernelGGL(k_resp_apply, dim3(b.nsys), dim3(256), 0, stream, dmb, R.p, p_M, y.p, w.p, ul.p);
     hipLaunchKernelGGL(k_scatter_shell, dim3(b.nsys), dim3(64), 0, stream, dmb, ul.p, u.p);
     // Z and its AO forms
-    hipLaunchKernelGGL(k_resp_Z, dim3(b.nsys), dim3(256), 0, stream, dmb, order.p, d_nocc.p, d_qoff.p, Q.p, w.p,
+    hipLaunchKernelGGL(k_resp_Z, dim3(b.nsys), dim3(256), 0, stream, dmb, p_order, d_nocc.p, d_qoff.p, p_Q, w.p,
                        G2.p, G3.p);
     // Zt = Ct^T (Zm Ct) -> G1 ; WZ = Ct^T (Ze Ct) -> G2
     gemm_batch(b, dmb, (int)b.nsys, b.d_list.p, 0, G2.p, b.Ct.p, b.Tm.p, (const double*)nullptr, b.gemm_gflop_all());

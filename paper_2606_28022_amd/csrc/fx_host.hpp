@@ -225,6 +225,8 @@ struct Ctx {
   double fused_beta = std::getenv("FX_FUSED_BETA") ? std::atof(std::getenv("FX_FUSED_BETA")) : 1.0;
   DevBuf<double> mono_tmp;
   bool monomer_response_setup();
+  // dynamic LDS of k_resp_M for a batch (throws when a system is too large)
+  unsigned resp_M_lds(const Batch& b) const;
   void build_precond(Batch& b);
   // learned initial guess: FP32 master weights, Adam moments, bfloat16-rounded copy
   DevBuf<float> mlp_master, mlp_m, mlp_v, mlp_wr, mlp_grad, mlp_part, mlp_feat, mlp_out;

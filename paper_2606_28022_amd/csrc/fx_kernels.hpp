@@ -97,6 +97,7 @@ __global__ void k_resp_Q(DevSystem sys, DevBatch bt, const double* SCt, const in
                          const long long* qoff, double* Q);
 __global__ void k_resp_M(DevBatch bt, const int* order, const int* nocc, const long long* qoff, const double* Q,
                          double* M);
+size_t resp_M_lds_bytes(int nsh);
 __global__ void k_resp_R(DevSystem sys, DevBatch bt, const double* M, double* Wk, double* R);
 __global__ void k_resp_apply(DevBatch bt, const double* R, const double* M, const double* y, double* w, double* u);
 __global__ void k_resp_Z(DevBatch bt, const int* order, const int* nocc, const long long* qoff, const double* Q,

@@ -65,8 +65,13 @@ __global__ void k_resp_Q(DevSystem sys, DevBatch bt, const double* SCt, const in
 }
 
 // M_st = sum_{a'i'} Q_s,a'i' Q_t,a'i' / (eps_a - eps_i)   (into the nsh^2 pool)
-__global__ void k_resp_M(DevBatch bt, const int* order, const int* nocc, const long long* qoff, const double* Q,
-                         double* M) {
+// M = sum_ai Q_ai Q_ai^T / (eps_a - eps_i), per system: the (a, i) index is
+// staged through LDS 64 columns at a time together with the inverse gaps;
+// each thread accumulates a fixed set of upper-triangle entries (s <= t) in
+// registers over all chunks in order, then mirrors them.
+constexpr int RM_KC = 64, RM_LD = RM_KC + 1, RM_MAXP = 20;
+__global__ void __launch_bounds__(256) k_resp_M(DevBatch bt, const int* order, const int* nocc, const long long* qoff,
+                                                const double* Q, double* M) {
   const int si = blockIdx.x;
   const SysDesc d = bt.desc[si];
   const int n = d.nao, no = nocc[si], nv = n - no, ns = d.nsh;
@@ -74,37 +79,72 @@ __global__ void k_resp_M(DevBatch bt, const int* order, const int* nocc, const l
   const double* e = bt.eps + d.ao_off;
   const long long K = (long long)nv * no;
   const double* Qs = Q + qoff[si];
-  // inverse orbital-energy gaps of a chunk of (a, i) pairs staged in LDS;
-  // M accumulated chunk by chunk in fixed order
-  constexpr int CH = 2048;
-  __shared__ double idn[CH];
+  extern __shared__ double rm_lds[];
+  double* qt = rm_lds;                   // [ns][RM_LD]
+  double* idn = rm_lds + ns * RM_LD;     // [RM_KC]
+  const int npairs = ns * (ns + 1) / 2;
   double* Mo = M + d.gam_off;
-  for (int idx = threadIdx.x; idx < ns * ns; idx += blockDim.x) Mo[idx] = 0.0;
-  for (long long k0 = 0; k0 < K; k0 += CH) {
-    const int kn = (int)((K - k0) < CH ? (K - k0) : CH);
-    __syncthreads();
-    for (int k = threadIdx.x; k < kn; k += blockDim.x) {
-      const long long kk = k0 + k;
-      const int ap = (int)(kk / no), ip = (int)(kk - (long long)ap * no);
-      idn[k] = 1.0 / (e[ord[no + ap]] - e[ord[ip]]);
+  // pairs in groups of RM_MAXP per thread; Q is streamed once per group
+  for (int g0 = 0; g0 < npairs; g0 += RM_MAXP * (int)blockDim.x) {
+    double acc[RM_MAXP];
+    int ps[RM_MAXP], pt[RM_MAXP];
+#pragma unroll
+    for (int r = 0; r < RM_MAXP; ++r) {
+      acc[r] = 0.0;
+      const int idx = g0 + threadIdx.x + r * blockDim.x;
+      int s = 0, t = 0;
+      if (idx < npairs) {
+        // upper-triangle pair number idx -> (s, t), s <= t
+        int rem = idx;
+        while (rem >= ns - s) {
+          rem -= ns - s;
+          ++s;
+        }
+        t = s + rem;
+      }
+      ps[r] = s;
+      pt[r] = t;
     }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < ns * ns; idx += blockDim.x) {
-      const int s = idx / ns, t = idx - s * ns;
-      if (t < s) continue;
-      const double* qs = Qs + (long long)s * K + k0;
-      const double* qt = Qs + (long long)t * K + k0;
-      double v = 0.0;
-      for (int k = 0; k < kn; ++k) v += qs[k] * qt[k] * idn[k];
-      Mo[idx] += v;
+    for (long long k0 = 0; k0 < K; k0 += RM_KC) {
+      const int kn = (int)((K - k0) < RM_KC ? (K - k0) : RM_KC);
+      __syncthreads();
+      for (int x = threadIdx.x; x < ns * RM_KC; x += blockDim.x) {
+        const int sh = x / RM_KC, k = x - sh * RM_KC;
+        qt[sh * RM_LD + k] = k < kn ? Qs[(long long)sh * K + k0 + k] : 0.0;
+      }
+      for (int k = threadIdx.x; k < RM_KC; k += blockDim.x) {
+        double v = 0.0;
+        if (k < kn) {
+          const long long kk = k0 + k;
+          const int ap = (int)(kk / no), ip = (int)(kk - (long long)ap * no);
+          v = 1.0 / (e[ord[no + ap]] - e[ord[ip]]);
+        }
+        idn[k] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < RM_MAXP; ++r) {
+        const int idx = g0 + threadIdx.x + r * blockDim.x;
+        if (idx >= npairs) continue;
+        const double* qa = qt + ps[r] * RM_LD;
+        const double* qb = qt + pt[r] * RM_LD;
+        double v = 0.0;
+        for (int k = 0; k < kn; ++k) v += qa[k] * qb[k] * idn[k];
+        acc[r] += v;
+      }
     }
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < ns * ns; idx += blockDim.x) {
-    const int s = idx / ns, t = idx - s * ns;
-    if (t < s) Mo[idx] = Mo[(long long)t * ns + s];
+#pragma unroll
+    for (int r = 0; r < RM_MAXP; ++r) {
+      const int idx = g0 + threadIdx.x + r * blockDim.x;
+      if (idx >= npairs) continue;
+      Mo[(long long)ps[r] * ns + pt[r]] = acc[r];
+      Mo[(long long)pt[r] * ns + ps[r]] = acc[r];
+    }
   }
 }
+
+// dynamic LDS of k_resp_M for systems of up to nsh shells
+size_t resp_M_lds_bytes(int nsh) { return ((size_t)nsh * RM_LD + RM_KC) * sizeof(double); }
 
 // R = (1 + G M)^-1 with G = gamma - 2 Gamma_A dq_A on same-atom shell blocks
 // (Gauss-Jordan with partial pivoting on a work copy in Wk; one work-group).

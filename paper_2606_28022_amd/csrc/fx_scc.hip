@@ -663,14 +663,15 @@ __global__ void k_charges_mix(DevSystem sys, DevBatch bt, const int* list, doubl
   const double* S = bt.S + d.mat_off;
   const double* P = bt.P + d.mat_off;
   const double* H = bt.H0 + d.mat_off;
-  // AO populations (P S)_mu,mu and Tr(P H0)
+  // AO populations (P S)_mu,mu and Tr(P H0); P, S and H0 are symmetric, so
+  // thread i sums column i (consecutive threads read consecutive addresses)
   double eh = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     double v = 0.0, h = 0.0;
     for (int j = 0; j < n; ++j) {
-      double pij = P[(long long)i * n + j];
-      v += pij * S[(long long)i * n + j];
-      h += pij * H[(long long)i * n + j];
+      const double pji = P[(long long)j * n + i];
+      v += pji * S[(long long)j * n + i];
+      h += pji * H[(long long)j * n + i];
     }
     pop[i] = v;
     eh += h;
