@@ -36,7 +36,7 @@ void explicit_terms(Ctx& c, Batch& b, const double* wsys, DevBuf<double>& g_sys,
   g_sys.alloc(3LL * natot);
   F_sys.alloc(natot);
   hipLaunchKernelGGL(k_grad_contract, dim3(b.nsys), dim3(256), 0, c.stream, ds, db, b.d_list.p, b.Pm.p, b.Fm.p,
-                     b.q_out.p, b.q_out.p, wsys, 1, 0, g_sys.p, F_sys.p);
+                     b.q_out.p, b.q_out.p, wsys, 1, 0, g_sys.p, F_sys.p, b.Tm.p);
   Ctx::check(hipGetLastError(), "explicit gradient terms");
 }
 
@@ -232,7 +232,7 @@ void Ctx::gradient() {
     hipLaunchKernelGGL(k_sym_inplace, dim3(b.nsys), dim3(256), 0, stream, dmb, G1.p);
     hipLaunchKernelGGL(k_resp_DS, dim3(b.nsys), dim3(256), 0, stream, dmb, G1.p, G2.p, G3.p, w.p, b.Fm.p, gx.p);
     hipLaunchKernelGGL(k_grad_contract, dim3(b.nsys), dim3(256), 0, stream, ds, dmb, b.d_list.p, G1.p, b.Fm.p, gx.p,
-                       b.q_out.p, (const double*)nullptr, 0, 1, gm.p, Fm_.p);
+                       b.q_out.p, (const double*)nullptr, 0, 1, gm.p, Fm_.p, b.Tm.p);
     check(hipGetLastError(), "response gradient terms");
     sync();
     res.ms_response = now_ms() - tr;

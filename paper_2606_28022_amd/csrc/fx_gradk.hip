@@ -116,7 +116,7 @@ __device__ void atom_pair_overlap_deriv(const DevElem& ea, const DevElem& eb, co
 // and written (or added) to the per-system atom arrays.
 __global__ void k_grad_contract(DevSystem sys, DevBatch bt, const int* list, const double* DHp, const double* DSp,
                                 const double* gx, const double* gy, const double* wsys, int with_rep, int accumulate,
-                                double* g_out, double* F_out) {
+                                double* g_out, double* F_out, double* scratch) {
   const int si = list[blockIdx.x];
   const SysDesc d = bt.desc[si];
   const int n = d.nao, nat = d.nat;
@@ -126,107 +126,120 @@ __global__ void k_grad_contract(DevSystem sys, DevBatch bt, const int* list, con
   const int* aao = bt.sys_atom_ao0 + d.atom_off;
   const int* ash = bt.sys_atom_sh0 + d.atom_off;
   const double cw = wsys ? wsys[si] : 1.0;
-  __shared__ double part[256][4];
-  const int nslice = nat >= (int)blockDim.x ? 1 : (int)blockDim.x / nat;
-  for (int a0 = 0; a0 < nat; a0 += (nslice == 1 ? (int)blockDim.x : nat)) {
-    int a = a0 + (nslice == 1 ? (int)threadIdx.x : (int)threadIdx.x % nat);
-    int slice = nslice == 1 ? 0 : (int)threadIdx.x / nat;
+  // every pair term is a function of R_a - R_b: each unordered pair (a < b)
+  // is evaluated once, its gradient enters a with + and b with -, plus the
+  // CN sensitivities of both atoms; 5 values per pair in the scratch block
+  // (5 nat (nat - 1) / 2 <= n^2 doubles), then gathered per atom in order
+  double* pb = scratch + d.mat_off;
+  const int np = nat * (nat - 1) / 2;
+  for (int p = threadIdx.x; p < np; p += blockDim.x) {
+    int a = 0, rem = p;
+    while (rem >= nat - 1 - a) {
+      rem -= nat - 1 - a;
+      ++a;
+    }
+    const int b = a + 1 + rem;
+    const int A = atoms[a], B = atoms[b];
+    const DevElem& ea = sys.elems[sys.elem[A]];
+    const DevElem& eb = sys.elems[sys.elem[B]];
+    const double cnA = sys.cn[A], cnB = sys.cn[B];
+    const int oa = aao[a], ob = aao[b];
     double g[3] = {0.0, 0.0, 0.0};
-    double Fa = 0.0;
-    bool active = a < nat && slice < nslice;
-    if (active) {
-      const int A = atoms[a];
-      const DevElem& ea = sys.elems[sys.elem[A]];
-      const double cnA = sys.cn[A];
-      const int oa = aao[a];
-      if (slice == 0) {
-        for (int s = 0; s < ea.nsh; ++s)
-          for (int u = 0; u < ea.nao_sh[s]; ++u) {
-            int mu = oa + ea.ao0[s] + u;
-            Fa += DH[(long long)mu * n + mu] * ea.level[s] * ea.kcn[s];
+    double Fa = 0.0, Fb = 0.0;
+    double Rv[3] = {sys.xyz[3 * A] - sys.xyz[3 * B], sys.xyz[3 * A + 1] - sys.xyz[3 * B + 1],
+                    sys.xyz[3 * A + 2] - sys.xyz[3 * B + 2]};
+    double R = sqrt(Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2]);
+    double uR[3] = {Rv[0] / R, Rv[1] / R, Rv[2] / R};
+    double S[MAXAO_EL][MAXAO_EL], dS[3][MAXAO_EL][MAXAO_EL];
+    atom_pair_overlap_deriv(ea, eb, Rv, S, dS);
+    double den = ea.EN - eb.EN;
+    double enf = 1.0 + sys.g.kEN * den * den;
+    double rcov = ea.rcov + eb.rcov;
+    double x = sqrt(R / rcov);
+    double dx = 0.5 / sqrt(R * rcov);
+    for (int sa = 0; sa < ea.nsh; ++sa)
+      for (int sb = 0; sb < eb.nsh; ++sb) {
+        double kll = 0.5 * (sys.g.kl[ea.l[sa]] + sys.g.kl[eb.l[sb]]);
+        double ha = ea.level[sa] * (1.0 + ea.kcn[sa] * cnA);
+        double hb = eb.level[sb] * (1.0 + eb.kcn[sb] * cnB);
+        double hav = 0.5 * (ha + hb);
+        double pa = 1.0 + ea.kpoly[sa] * x, pbb = 1.0 + eb.kpoly[sb] * x;
+        double Pi = pa * pbb;
+        double dPi = (ea.kpoly[sa] * pbb + pa * eb.kpoly[sb]) * dx;
+        double base = sys.g.KAB * kll * enf;
+        double fac = base * hav * Pi;
+        double sumDHS = 0.0;
+        for (int u = 0; u < ea.nao_sh[sa]; ++u)
+          for (int v = 0; v < eb.nao_sh[sb]; ++v) {
+            int i = ea.ao0[sa] + u, j = eb.ao0[sb] + v;
+            long long mn = (long long)(oa + i) * n + ob + j;
+            double dh = DH[mn], ds = DS[mn];
+            double w = fac * dh + ds;
+            for (int k = 0; k < 3; ++k) g[k] += 2.0 * w * dS[k][i][j];
+            sumDHS += dh * S[i][j];
           }
+        double t = 2.0 * sumDHS * base * hav * dPi;
+        for (int k = 0; k < 3; ++k) g[k] += t * uR[k];
+        Fa += 2.0 * sumDHS * base * Pi * 0.5 * ea.level[sa] * ea.kcn[sa];
+        Fb += 2.0 * sumDHS * base * Pi * 0.5 * eb.level[sb] * eb.kcn[sb];
       }
-      for (int b = slice; b < nat; b += nslice) {
-        if (b == a) continue;
-        const int B = atoms[b];
-        const DevElem& eb = sys.elems[sys.elem[B]];
-        const double cnB = sys.cn[B];
-        const int ob = aao[b];
-        double Rv[3] = {sys.xyz[3 * A] - sys.xyz[3 * B], sys.xyz[3 * A + 1] - sys.xyz[3 * B + 1],
-                        sys.xyz[3 * A + 2] - sys.xyz[3 * B + 2]};
-        double R = sqrt(Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2]);
-        double uR[3] = {Rv[0] / R, Rv[1] / R, Rv[2] / R};
-        double S[MAXAO_EL][MAXAO_EL], dS[3][MAXAO_EL][MAXAO_EL];
-        atom_pair_overlap_deriv(ea, eb, Rv, S, dS);
-        double den = ea.EN - eb.EN;
-        double enf = 1.0 + sys.g.kEN * den * den;
-        double rcov = ea.rcov + eb.rcov;
-        double x = sqrt(R / rcov);
-        double dx = 0.5 / sqrt(R * rcov);
-        for (int sa = 0; sa < ea.nsh; ++sa)
-          for (int sb = 0; sb < eb.nsh; ++sb) {
-            double kll = 0.5 * (sys.g.kl[ea.l[sa]] + sys.g.kl[eb.l[sb]]);
-            double ha = ea.level[sa] * (1.0 + ea.kcn[sa] * cnA);
-            double hb = eb.level[sb] * (1.0 + eb.kcn[sb] * cnB);
-            double hav = 0.5 * (ha + hb);
-            double pa = 1.0 + ea.kpoly[sa] * x, pb = 1.0 + eb.kpoly[sb] * x;
-            double Pi = pa * pb;
-            double dPi = (ea.kpoly[sa] * pb + pa * eb.kpoly[sb]) * dx;
-            double base = sys.g.KAB * kll * enf;
-            double fac = base * hav * Pi;
-            double sumDHS = 0.0;
-            for (int u = 0; u < ea.nao_sh[sa]; ++u)
-              for (int v = 0; v < eb.nao_sh[sb]; ++v) {
-                int i = ea.ao0[sa] + u, j = eb.ao0[sb] + v;
-                long long mn = (long long)(oa + i) * n + ob + j;
-                double dh = DH[mn], ds = DS[mn];
-                double w = fac * dh + ds;
-                for (int k = 0; k < 3; ++k) g[k] += 2.0 * w * dS[k][i][j];
-                sumDHS += dh * S[i][j];
-              }
-            double t = 2.0 * sumDHS * base * hav * dPi;
-            for (int k = 0; k < 3; ++k) g[k] += t * uR[k];
-            Fa += 2.0 * sumDHS * base * Pi * 0.5 * ea.level[sa] * ea.kcn[sa];
-          }
-        if (gx) {
-          int s0 = ash[a], t0 = ash[b];
-          for (int sa = 0; sa < ea.nsh; ++sa)
-            for (int sb = 0; sb < eb.nsh; ++sb) {
-              double dg;
-              gamma_and_deriv(sys.g, R, ea.eta[sa], eb.eta[sb], &dg);
-              double c = 0.5 * (gx[d.sh_off + s0 + sa] * gy[d.sh_off + t0 + sb] +
-                                gy[d.sh_off + s0 + sa] * gx[d.sh_off + t0 + sb]);
-              for (int k = 0; k < 3; ++k) g[k] += c * dg * uR[k];
-            }
+    if (gx) {
+      int s0 = ash[a], t0 = ash[b];
+      for (int sa = 0; sa < ea.nsh; ++sa)
+        for (int sb = 0; sb < eb.nsh; ++sb) {
+          double dg;
+          gamma_and_deriv(sys.g, R, ea.eta[sa], eb.eta[sb], &dg);
+          double c = 0.5 * (gx[d.sh_off + s0 + sa] * gy[d.sh_off + t0 + sb] +
+                            gy[d.sh_off + s0 + sa] * gx[d.sh_off + t0 + sb]);
+          for (int k = 0; k < 3; ++k) g[k] += c * dg * uR[k];
         }
-        if (with_rep) {
-          double al = sqrt(ea.arep * eb.arep);
-          double e = ea.zeff * eb.zeff / R * exp(-al * pow(R, sys.g.kf));
-          double de = e * (-1.0 / R - al * sys.g.kf * pow(R, sys.g.kf - 1.0));
-          for (int k = 0; k < 3; ++k) g[k] += de * uR[k];
-        }
+    }
+    if (with_rep) {
+      double al = sqrt(ea.arep * eb.arep);
+      double e = ea.zeff * eb.zeff / R * exp(-al * pow(R, sys.g.kf));
+      double de = e * (-1.0 / R - al * sys.g.kf * pow(R, sys.g.kf - 1.0));
+      for (int k = 0; k < 3; ++k) g[k] += de * uR[k];
+    }
+    double* o = pb + 5LL * p;
+    o[0] = g[0];
+    o[1] = g[1];
+    o[2] = g[2];
+    o[3] = Fa;
+    o[4] = Fb;
+  }
+  __syncthreads();
+  for (int a = threadIdx.x; a < nat; a += blockDim.x) {
+    const int A = atoms[a];
+    const DevElem& ea = sys.elems[sys.elem[A]];
+    const int oa = aao[a];
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int s = 0; s < ea.nsh; ++s)
+      for (int u = 0; u < ea.nao_sh[s]; ++u) {
+        int mu = oa + ea.ao0[s] + u;
+        t[3] += DH[(long long)mu * n + mu] * ea.level[s] * ea.kcn[s];
+      }
+    for (int b = 0; b < nat; ++b) {
+      if (b == a) continue;
+      if (b > a) {
+        const double* q = pb + 5LL * (a * (2 * nat - a - 1) / 2 + (b - a - 1));
+        t[0] += q[0];
+        t[1] += q[1];
+        t[2] += q[2];
+        t[3] += q[3];
+      } else {
+        const double* q = pb + 5LL * (b * (2 * nat - b - 1) / 2 + (a - b - 1));
+        t[0] -= q[0];
+        t[1] -= q[1];
+        t[2] -= q[2];
+        t[3] += q[4];
       }
     }
-    // fixed-order reduction over slices
-    __syncthreads();
-    part[threadIdx.x][0] = g[0];
-    part[threadIdx.x][1] = g[1];
-    part[threadIdx.x][2] = g[2];
-    part[threadIdx.x][3] = Fa;
-    __syncthreads();
-    if (active && slice == 0) {
-      double t[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int sl = 0; sl < nslice; ++sl) {
-        int tid = nslice == 1 ? (int)threadIdx.x : sl * nat + (int)threadIdx.x % nat;
-        for (int k = 0; k < 4; ++k) t[k] += part[tid][k];
-      }
-      long long o = (long long)d.atom_off + a;
-      for (int k = 0; k < 3; ++k) {
-        double v = cw * t[k];
-        g_out[3 * o + k] = accumulate ? g_out[3 * o + k] + v : v;
-      }
-      F_out[o] = accumulate ? F_out[o] + cw * t[3] : cw * t[3];
+    long long o = (long long)d.atom_off + a;
+    for (int k = 0; k < 3; ++k) {
+      double v = cw * t[k];
+      g_out[3 * o + k] = accumulate ? g_out[3 * o + k] + v : v;
     }
+    F_out[o] = accumulate ? F_out[o] + cw * t[3] : cw * t[3];
   }
 }
 
