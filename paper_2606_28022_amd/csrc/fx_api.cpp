@@ -433,7 +433,9 @@ void Ctx::init_device() {
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds_max - 16384);
   for (const void* k : {reinterpret_cast<const void*>(k_jacobi_rot<double>),
                         reinterpret_cast<const void*>(k_jacobi_rot<float>),
-                        reinterpret_cast<const void*>(k_apply_rot)})
+                        reinterpret_cast<const void*>(k_apply_rot),
+                        reinterpret_cast<const void*>(k_cholinv_lds<double>),
+                        reinterpret_cast<const void*>(k_cholinv_lds<float>)})
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
   (void)hipGetLastError();
   if (verbose) std::fprintf(stderr, "[fx] LDS per workgroup %d B, static %u B\n", v, stat);
@@ -723,16 +725,62 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
   check(hipGetLastError(), "k_reset_state");
   if (cold) {
     const int nt = (b.max_nao + 31) / 32;
+    // inverse Cholesky factor in LDS: FP64 where the packed triangle fits,
+    // else FP32 followed by a third-order correction of the rows' S-norms
+    // (H = Y S Y^T, C^T = (15 I - 10 H + 3 H^2) / 8 Y); the global-memory
+    // kernel beyond that
+    const double gf = b.gemm_gflop(list);
+    const int chol_elt = (long long)cholinv_lds_bytes(b.max_nao, 8) <= lds_max   ? 8
+                         : (long long)cholinv_lds_bytes(b.max_nao, 4) <= lds_max ? 4
+                                                                                  : 0;
+    const unsigned chol_lds = chol_elt ? (unsigned)cholinv_lds_bytes(b.max_nao, chol_elt) : 0;
+    KernelTimer* kt_chol = kt(chol_elt == 8 ? "fx::k_cholinv_lds<double>"
+                              : chol_elt == 4 ? "fx::k_cholinv_lds<float>" : "fx::k_cholinv");
+    auto cholinv = [&](const double* A, double* X) {
+      // factor and inverse: n^3 / 3 multiply-adds each
+      const int ev = capturing ? -1 : timers.begin(stream);
+      if (chol_elt == 8)
+        hipLaunchKernelGGL(k_cholinv_lds<double>, dim3(nl), dim3(CHOL_THREADS_HOST), chol_lds, stream, db,
+                           b.d_list.p, A, X);
+      else if (chol_elt == 4)
+        hipLaunchKernelGGL(k_cholinv_lds<float>, dim3(nl), dim3(CHOL_THREADS_HOST), chol_lds, stream, db,
+                           b.d_list.p, A, X);
+      else
+        hipLaunchKernelGGL(k_cholinv, dim3(nl), dim3(256), 0, stream, db, b.d_list.p, A, b.Pm.p, X);
+      if (!capturing) timers.end(stream, ev, kt_chol, gf / 3.0);
+      check(hipGetLastError(), "k_cholinv");
+    };
+    // rows Y in Tm (approximately S-orthonormal) -> Ct
+    auto refine_rows = [&]() {
+      gemm_batch(b, db, nl, b.d_list.p, 0, b.Tm.p, b.S.p, b.Pm.p, (const double*)nullptr, gf);
+      gemm_batch(b, db, nl, b.d_list.p, 1, b.Pm.p, b.Tm.p, b.Fm.p, (const double*)nullptr, gf, 0, 1);
+      gemm_batch(b, db, nl, b.d_list.p, 1, b.Fm.p, b.Fm.p, b.Pm.p, (const double*)nullptr, gf, 0, 1);
+      hipLaunchKernelGGL(k_ns_poly, dim3(8, nl), dim3(256), 0, stream, db, b.d_list.p, b.Fm.p, b.Pm.p);
+      gemm_batch(b, db, nl, b.d_list.p, 0, b.Fm.p, b.Tm.p, b.Ct.p, (const double*)nullptr, gf);
+    };
     if (b.init_from_mono && mb.nsys > 0) {
       // C0 = blockdiag(monomer C); G = C0^T S C0 = L L^T; C = C0 L^-T
       hipLaunchKernelGGL(k_cluster_init_ct, dim3(nl), dim3(256), 0, stream, db, b.d_list.p, mb.dev());
-      gemm_batch(b, db, (int)nl, b.d_list.p, 0, b.Ct.p, b.S.p, b.Tm.p, (const double*)nullptr, b.gemm_gflop(list));
-      gemm_batch(b, db, (int)nl, b.d_list.p, 1, b.Tm.p, b.Ct.p, b.Fm.p, (const double*)nullptr, b.gemm_gflop(list));
-      hipLaunchKernelGGL(k_cholinv, dim3(nl), dim3(256), 0, stream, db, b.d_list.p, b.Fm.p, b.Tm.p, b.Pm.p);
-      gemm_batch(b, db, (int)nl, b.d_list.p, 0, b.Pm.p, b.Ct.p, b.Tm.p, (const double*)nullptr, b.gemm_gflop(list));
-      check(hipMemcpyAsync(b.Ct.p, b.Tm.p, sizeof(double) * b.tot_mat, hipMemcpyDeviceToDevice, stream), "copy");
+      gemm_batch(b, db, nl, b.d_list.p, 0, b.Ct.p, b.S.p, b.Tm.p, (const double*)nullptr, gf);
+      gemm_batch(b, db, nl, b.d_list.p, 1, b.Tm.p, b.Ct.p, b.Fm.p, (const double*)nullptr, gf, 0, 1);
+      if (chol_elt == 0) {
+        cholinv(b.Fm.p, b.Tm.p);  // (k_cholinv uses Pm as its workspace)
+        gemm_batch(b, db, nl, b.d_list.p, 0, b.Tm.p, b.Ct.p, b.Fm.p, (const double*)nullptr, gf);
+        check(hipMemcpyAsync(b.Ct.p, b.Fm.p, sizeof(double) * b.tot_mat, hipMemcpyDeviceToDevice, stream), "copy");
+      } else {
+        cholinv(b.Fm.p, b.Pm.p);
+        gemm_batch(b, db, nl, b.d_list.p, 0, b.Pm.p, b.Ct.p, b.Tm.p, (const double*)nullptr, gf);
+        if (chol_elt == 4)
+          refine_rows();
+        else
+          check(hipMemcpyAsync(b.Ct.p, b.Tm.p, sizeof(double) * b.tot_mat, hipMemcpyDeviceToDevice, stream),
+                "copy");
+      }
+    } else if (chol_elt == 4) {
+      cholinv(b.S.p, b.Tm.p);
+      refine_rows();
     } else {
-      hipLaunchKernelGGL(k_cholinv, dim3(nl), dim3(256), 0, stream, db, b.d_list.p, b.S.p, b.Tm.p, b.Ct.p);
+      cholinv(b.S.p, b.Ct.p);
     }
     check(hipGetLastError(), "initial basis");
   }

@@ -64,6 +64,11 @@ __host__ __device__ inline JacobiLdsLayout jacobi_lds_layout(int n, int elt, int
   return L;
 }
 template <typename T>
+__global__ void k_cholinv_lds(DevBatch bt, const int* list, const double* Apool, double* Xpool);
+__global__ void k_ns_poly(DevBatch bt, const int* list, double* Hpool, const double* H2pool);
+size_t cholinv_lds_bytes(int n, int elt);
+constexpr int CHOL_THREADS_HOST = 1024;
+template <typename T>
 __global__ void k_jacobi_rot(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale,
                              double cap_err, int* sweeps_out, double2* logbuf, long long log_stride, int max_log,
                              int* nlog);

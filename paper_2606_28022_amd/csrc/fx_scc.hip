@@ -1426,3 +1426,116 @@ __global__ void __launch_bounds__(1024)
 }
 
 }  // namespace fx
+
+namespace fx {
+
+// ---------------------------------------------------------------------------
+// Cholesky factor and its inverse in LDS: A = L L^T (A from Apool), X = L^-1
+// to Xpool (strict upper triangle zero).  The lower triangle is kept packed
+// row by row in LDS in precision T and overwritten in place: first by L
+// (right-looking, one column per step, a wave per trailing row), then by
+// L^-1, one column per step from the last (column j of the inverse needs the
+// already inverted columns to its right and column j of L; four lanes share
+// each row's dot product).  T = double gives the factor to working
+// precision; with T = float the result is an approximate inverse factor that
+// the caller refines.  A non-positive pivot sets status 2.
+constexpr int CHOL_THREADS = 1024;
+
+__device__ inline int tri_index(int i, int j) { return i * (i + 1) / 2 + j; }  // j <= i
+
+template <typename T>
+__global__ void __launch_bounds__(CHOL_THREADS)
+    k_cholinv_lds(DevBatch bt, const int* list, const double* __restrict__ Apool, double* __restrict__ Xpool) {
+  extern __shared__ double2 lds_raw[];
+  const int si = list[blockIdx.x];
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao;
+  const int ntri = n * (n + 1) / 2;
+  T* L = reinterpret_cast<T*>(lds_raw);
+  double* col = reinterpret_cast<double*>(lds_raw) + (ntri * (int)sizeof(T) + 7) / 8;
+  double* dinv = col + n;
+  const double* A = Apool + d.mat_off;
+  double* X = Xpool + d.mat_off;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nwave = nth >> 6;
+  for (int e = tid; e < n * n; e += nth) {
+    const int i = e / n, j = e - i * n;
+    if (j <= i) L[tri_index(i, j)] = (T)A[e];
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double dkk = (double)L[tri_index(k, k)];
+    if (!(dkk > 0.0)) {  // same value in every thread: uniform exit
+      if (tid == 0) bt.status[si] = 2;
+      return;
+    }
+    const double rp = 1.0 / sqrt(dkk);
+    for (int i = k + 1 + tid; i < n; i += nth) {
+      const T v = (T)((double)L[tri_index(i, k)] * rp);
+      L[tri_index(i, k)] = v;
+      col[i] = (double)v;
+    }
+    __syncthreads();
+    if (tid == 0) L[tri_index(k, k)] = (T)sqrt(dkk);
+    for (int i = k + 1 + wave; i < n; i += nwave) {
+      const double ci = col[i];
+      T* row = L + tri_index(i, 0);
+      for (int j = k + 1 + lane; j <= i; j += 64) row[j] = (T)((double)row[j] - ci * col[j]);
+    }
+    __syncthreads();
+  }
+  // in-place inverse: X_jj = 1 / L_jj, X_ij = -X_jj sum_{k=j+1..i} X_ik L_kj
+  const int g = tid & 3, grp = tid >> 2, ngrp = nth >> 2;
+  for (int j = n - 1; j >= 0; --j) {
+    for (int i = j + 1 + tid; i < n; i += nth) col[i] = (double)L[tri_index(i, j)];
+    if (tid == 0) {
+      const double x = 1.0 / (double)L[tri_index(j, j)];
+      dinv[0] = x;
+      L[tri_index(j, j)] = (T)x;
+    }
+    __syncthreads();
+    const double xjj = dinv[0];
+    for (int i0 = j + 1; i0 < n; i0 += ngrp) {
+      const int i = i0 + grp;  // the four lanes of a group share i: uniform within the group
+      double v = 0.0;
+      if (i < n) {
+        const T* row = L + tri_index(i, 0);
+        for (int k = j + 1 + g; k <= i; k += 4) v += (double)row[k] * col[k];
+      }
+      v += __shfl_xor(v, 1);
+      v += __shfl_xor(v, 2);
+      if (i < n && g == 0) L[tri_index(i, j)] = (T)(-xjj * v);
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * n; e += nth) {
+    const int i = e / n, j = e - i * n;
+    X[e] = j <= i ? (double)L[tri_index(i, j)] : 0.0;
+  }
+}
+
+template __global__ void k_cholinv_lds<double>(DevBatch, const int*, const double*, double*);
+template __global__ void k_cholinv_lds<float>(DevBatch, const int*, const double*, double*);
+
+size_t cholinv_lds_bytes(int n, int elt) {
+  const size_t ntri = (size_t)n * (n + 1) / 2;
+  return (ntri * elt + 7) / 8 * 8 + (size_t)n * 8 + 16;
+}
+
+// Third-order correction of nearly orthonormal rows Y (H = Y M Y^T = I + E):
+// H <- (15 I - 10 H + 3 H^2) / 8, the series of H^-1/2 to second order in E,
+// so that f(H) Y has f(H) H f(H) = I + O(E^3).
+__global__ void k_ns_poly(DevBatch bt, const int* list, double* Hpool, const double* H2pool) {
+  const int si = list[blockIdx.y];
+  if (bt.status[si] != 0) return;
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao;
+  double* H = Hpool + d.mat_off;
+  const double* H2 = H2pool + d.mat_off;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * n; e += gridDim.x * blockDim.x) {
+    const int i = e / n, j = e - i * n;
+    H[e] = ((i == j ? 15.0 : 0.0) - 10.0 * H[e] + 3.0 * H2[e]) * 0.125;
+  }
+}
+
+}  // namespace fx
