@@ -60,16 +60,19 @@ enum { FX_FP64 = 0, FX_MIXED = 1 };           /* precision */
  * themselves on the device), after an eager first iteration */
 enum { FX_BATCHED = 0, FX_PLAIN_LOOP = 1, FX_BATCHED_GRAPH = 2 };
 enum { FX_GUESS_SUPERPOSITION = 0, FX_GUESS_LEARNED = 1, FX_GUESS_USER = 2 };
+/* fragment-pair selection (section "Computational Details"): a fixed
+ * closest-contact cutoff, or van der Waals-scaled contacts */
+enum { FX_SELECT_CUTOFF = 0, FX_SELECT_VDW = 1 };
 
 typedef struct fx_params fx_params;
 typedef struct fx_ctx fx_ctx;
 
 typedef struct fx_options {
   int32_t order;          /* 2 (FMO2) or 3 (FMO3) */
-  double cutoff_bohr;     /* a pair is an SCC dimer when its closest interatomic
-                             distance is below this value, otherwise ES-DIM;
-                             a trimer is computed when at least two of its
-                             three pairs are SCC dimers */
+  double cutoff_bohr;     /* FX_SELECT_CUTOFF: a pair is an SCC dimer when its
+                             closest interatomic distance is below this value,
+                             otherwise ES-DIM; a trimer is computed when at
+                             least two of its three pairs are SCC dimers */
   int32_t precision;      /* FX_FP64, or FX_MIXED: FP32 eigensolver working
                              matrices for every system (the basis stays FP64)
                              and FP32 embedding-field passes while the monomer
@@ -93,6 +96,14 @@ typedef struct fx_options {
   int32_t max_macro;      /* monomer self-consistency sweeps */
   int32_t want_gradient;  /* compute the FMO2 gradient (order 2 only) */
   int32_t want_response;  /* include the embedding response term */
+  int32_t selection;      /* FX_SELECT_CUTOFF (default) or FX_SELECT_VDW */
+  double vdw_dimer;       /* FX_SELECT_VDW: a pair is an SCC dimer when some
+                             atom pair a in I, b in J is closer than
+                             vdw_dimer * (r_a + r_b), r the element's van der
+                             Waals radius (parameter file); default 2.0 */
+  double vdw_trimer;      /* FX_SELECT_VDW: a trimer is computed when at least
+                             two of its three pairs meet the same test with
+                             vdw_trimer; default 1.5 */
 } fx_options;
 
 typedef struct fx_counts {
@@ -190,7 +201,11 @@ int fx_get_counts(fx_ctx* ctx, fx_counts* out);
  * esd_pairs[2*n_esd], trimers[3*n_tri] (any pointer may be NULL to skip). */
 int fx_get_lists(fx_ctx* ctx, int32_t* scc_pairs, int32_t* esd_pairs, int32_t* trimers);
 
-/* Initial monomer shell charges dq_shell[n_shells] (used with FX_GUESS_USER). */
+/* Initial monomer shell charges dq_shell[n_shells] (host, n_shells from
+ * fx_counts; copied) used with FX_GUESS_USER, e.g. the previous step's
+ * fx_get_charges in molecular dynamics (the fixed point of the monomer loop
+ * does not depend on the start; section "FMO-xTB").  fx_set_system resets the guess to
+ * zero.  FX_E_STATE without a system, FX_E_INVALID for a non-finite value. */
 int fx_set_guess(fx_ctx* ctx, const double* dq_shell);
 
 /* Run the FMO calculation: lists (if not built), supersystem CN, the monomer

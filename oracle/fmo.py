@@ -1,11 +1,12 @@
 """FMO2 / FMO3 energies and the FMO2 analytic gradient (oracle).
 
 Passages followed:
-* fragment pair lists: a pair is a full SCC dimer when the closest
-  interatomic distance is below the cutoff, otherwise ES-DIM; a trimer is
-  computed when at least two of its three pairs pass the same test
-  (section "Computational Details" uses vdW-scaled radii; this build uses a
-  fixed closest-contact cutoff, 4 Angstrom by default);
+* fragment pair lists (section "Computational Details"): a pair is a full
+  SCC dimer when it passes the contact test, otherwise ES-DIM; a trimer is
+  computed when at least two of its three pairs pass the trimer test.  Two
+  tests: a fixed closest-contact cutoff (4 Angstrom by default, both tests
+  alike), or the paper's van der Waals-scaled contacts: some atom pair closer
+  than lam (r_a + r_b), lam = 2.0 for dimers and 1.5 for trimers;
 * embedding potential, eq. v_esp_matrix: each fragment sees
   phi_s = sum_{K != I} sum_{t in K} gamma_st dq^K_t in its Fock matrix;
 * monomer self-consistency (section "FMO-xTB"): monomers are solved
@@ -81,9 +82,33 @@ def closest_contact_sq(xyz, atoms_i, atoms_j):
     return float(d2.min())
 
 
-def build_lists(system, cutoff_bohr, order=2):
+def vdw_contact(xyz, atoms_i, atoms_j, r, lam):
+    """True when some atom pair a in I, b in J is closer than
+    lam (r_a + r_b) (section "Computational Details"), compared as
+    d2 < (lam (r_a + r_b))^2 with every operation rounded separately."""
+    a = xyz[atoms_i]
+    b = xyz[atoms_j]
+    dx = a[:, None, 0] - b[None, :, 0]
+    dy = a[:, None, 1] - b[None, :, 1]
+    dz = a[:, None, 2] - b[None, :, 2]
+    d2 = (dx * dx + dy * dy) + dz * dz
+    t = lam * (r[atoms_i][:, None] + r[atoms_j][None, :])
+    return bool(np.any(d2 < t * t))
+
+
+def vdw_radii(system, params):
+    """Van der Waals radius (bohr) of every atom, from the parameter file."""
+    r = [params.element(int(z))["rvdw"] for z in system.Z]
+    if any(v is None for v in r):
+        raise KeyError("van der Waals radius missing from the parameters")
+    return np.array(r, dtype=float)
+
+
+def build_lists(system, cutoff_bohr, order=2, vdw=None):
     """SCC dimers, ES-DIM pairs (lexicographic, I < J) and, for order 3, the
-    trimers (I < J < K) with at least two SCC sub-pairs."""
+    trimers (I < J < K) with at least two sub-pairs passing the trimer test.
+    vdw = None: closest contact below cutoff_bohr for both tests;
+    vdw = (radii_bohr, lam_dimer, lam_trimer): van der Waals-scaled contacts."""
     fa = fragment_atoms(system.frag, system.n_frag)
     F = system.n_frag
     c2 = cutoff_bohr * cutoff_bohr
@@ -91,9 +116,16 @@ def build_lists(system, cutoff_bohr, order=2):
     near = np.zeros((F, F), dtype=bool)
     for I in range(F):
         for J in range(I + 1, F):
-            if closest_contact_sq(system.xyz, fa[I], fa[J]) < c2:
+            if vdw is None:
+                is_scc = closest_contact_sq(system.xyz, fa[I], fa[J]) < c2
+                near[I, J] = near[J, I] = is_scc
+            else:
+                r, lam2, lam3 = vdw
+                is_scc = vdw_contact(system.xyz, fa[I], fa[J], r, lam2)
+                if order >= 3:
+                    near[I, J] = near[J, I] = vdw_contact(system.xyz, fa[I], fa[J], r, lam3)
+            if is_scc:
                 scc_pairs.append((I, J))
-                near[I, J] = near[J, I] = True
             else:
                 esd_pairs.append((I, J))
     trimers = []
@@ -326,7 +358,8 @@ def fmo(system, params, cutoff_bohr, order=2, lists=None, scc_tol=1e-10,
             sysX, rX, shl, ddq, dEV = solve_cluster((I, J, K))
             dEIJK = rX.e_int - res[I].e_int - res[J].e_int - res[K].e_int + dEV
             dE_tri[k] = dEIJK - pair_dE[(I, J)] - pair_dE[(I, K)] - pair_dE[(J, K)]
-            out.trimers.append(dict(IJK=(int(I), int(J), int(K)), res=rX, dEIJK=dEIJK))
+            out.trimers.append(dict(IJK=(int(I), int(J), int(K)), sys=sysX, res=rX, shells=shl,
+                                    ddq=ddq, dEIJK=dEIJK))
         out.dE_tri = dE_tri
         out.E_fmo3 = neumaier_sum([out.E_fmo2] + list(dE_tri))
         out.E = out.E_fmo3
@@ -354,29 +387,69 @@ def _inter_gamma_force(sh, pair_weights, natoms):
     return g
 
 
-def fmo2_gradient(system, params, res, with_response=True):
-    """Analytic FMO2 gradient (Eh/bohr, shape (natoms, 3)) for a converged
-    FMO2 result `res` (lists frozen).  Systems with cut covalent bonds are not
-    covered (the HOP gradient is not part of this build)."""
+def _many_body_weights(F, scc_pairs, esd_pairs, trimers):
+    """Coefficients of the embedded-energy identity.
+
+    Writing every Delta E through embedded energies E^emb_X = E'_X + dq^X phi^X
+    (eqs. fmo2-energy-components, dimer_embedding_correction,
+    trimer_interaction_energy, fmo3_energy, with ES-DIM sub-pairs entering the
+    trimer subtraction by their ES-DIM value) gives
+        E = sum_I c_I E^emb_I + sum_SCC s_IJ E^emb_IJ + sum_T E^emb_IJK
+            - sum_ESD (1 - n_T(IJ)) dq^I gamma dq^J,
+    n_T(IJ) = number of trimers containing I and J, s_IJ = 1 - n_T(IJ),
+    c_I = 1 - (SCC pairs containing I)
+          + sum over trimers T containing I of (SCC sub-pairs of T containing I - 1).
+    Without trimers this is the FMO2 identity (s = 1, c_I = 1 - n_I^SCC)."""
+    scc = {(int(I), int(J)) for I, J in scc_pairs}
+    nT = {}
+    c = np.ones(F)
+    for I, J in scc_pairs:
+        c[I] -= 1.0
+        c[J] -= 1.0
+    for T in trimers:
+        I, J, K = (int(x) for x in T)
+        subs = [(I, J), (I, K), (J, K)]
+        for P in subs:
+            nT[P] = nT.get(P, 0) + 1
+        for L in (I, J, K):
+            c[L] += sum(1 for P in subs if L in P and P in scc) - 1.0
+    s_scc = np.array([1.0 - nT.get((int(I), int(J)), 0) for I, J in scc_pairs])
+    w_esd = np.array([1.0 - nT.get((int(I), int(J)), 0) for I, J in esd_pairs])
+    return c, s_scc, w_esd
+
+
+def fmo_gradient(system, params, res, with_response=True):
+    """Analytic FMO2 or FMO3 gradient (Eh/bohr, shape (natoms, 3)) for a
+    converged result `res` (lists frozen).  From the identity of
+    _many_body_weights, with every E^emb_X stationary in its own density:
+        dE/dxi = sum_X w_X g^emb_X (explicit, at fixed monomer charges)
+                 + sum_ESD (1 - n_T) dq^I dgamma dq^J
+                 + sum_SCC s_IJ ddq^IJ . dphi^IJ + sum_T ddq^T . dphi^T
+                 + response of the monomer charges,
+    the response driven by v_K = sum over clusters X not containing K of
+    w_X gamma_{K,X} ddq^X (eq. esp_lagrangian; for trimers the generalized
+    accumulated charge transfer of section "Extension to FMO3").  Systems
+    with cut covalent bonds are not covered (the HOP gradient is not part of
+    this build)."""
     if len(getattr(system, "bonds", ())):
-        raise NotImplementedError("FMO2 gradient with covalent boundaries")
+        raise NotImplementedError("FMO gradient with covalent boundaries")
     sh = res.shells
     F = system.n_frag
     fa, fsh = res.frag_atoms, res.frag_shells
     q = res.q
     N = system.n_atoms
-    scc_pairs, esd_pairs, _ = res.lists
-    nscc = np.zeros(F)
-    for I, J in scc_pairs:
-        nscc[I] += 1
-        nscc[J] += 1
-    c = 1.0 - nscc
+    scc_pairs, esd_pairs, trimers = res.lists
+    tri = getattr(res, "trimers", [])
+    if len(trimers) and len(tri) != len(trimers):
+        raise ValueError("the result holds no trimer solutions (run fmo with order=3)")
+    c, s_scc, w_esd = _many_body_weights(F, scc_pairs, esd_pairs, trimers if len(tri) else [])
+    clusters = [(d, s_scc[k]) for k, d in enumerate(res.dimers)] + [(t, 1.0) for t in tri]
 
     G = np.zeros((N, 3))
     Fcn = np.zeros(N)
     parts = {}
 
-    # explicit fragment terms: sum_X c_X g^emb_X (fixed CN), with sigma containing
+    # explicit fragment terms: sum_X w_X g^emb_X (fixed CN), with sigma containing
     # the embedding potential (eqs. xtb_grad, W_matrix, pair_delta)
     gm = np.zeros((N, 3))
     for I in range(F):
@@ -385,33 +458,37 @@ def fmo2_gradient(system, params, res, with_response=True):
         g, f = system_gradient(sx, r.P, DS, r.q, r.q, True)
         gm[fa[I]] += c[I] * g
         Fcn[fa[I]] += c[I] * f
-    for d in res.dimers:
+    for d, wx in clusters:
         sx, r = d["sys"], d["res"]
-        atoms = np.concatenate([fa[d["I"]], fa[d["J"]]])
+        frags = d["IJK"] if "IJK" in d else (d["I"], d["J"])
+        atoms = np.concatenate([fa[I] for I in frags])
         DS = _ds_matrix(r.sigma[sx.ao_sh], r.P, r.Wt)
         g, f = system_gradient(sx, r.P, DS, r.q, r.q, True)
-        gm[atoms] += g
-        Fcn[atoms] += f
+        gm[atoms] += wx * g
+        Fcn[atoms] += wx * f
     parts["fragments"] = gm
     G += gm
 
-    # ES-DIM (eq. esd_grad) and charge-transfer embedding (eq. ctij) terms
+    # ES-DIM (eq. esd_grad) and charge-transfer embedding (eqs. ctij and the
+    # FMO3 charge transfer) terms
     wl = []
-    for I, J in esd_pairs:
-        wl.append((fsh[I], fsh[J], np.outer(q[fsh[I]], q[fsh[J]])))
+    for k, (I, J) in enumerate(esd_pairs):
+        if w_esd[k] != 0.0:
+            wl.append((fsh[I], fsh[J], w_esd[k] * np.outer(q[fsh[I]], q[fsh[J]])))
     g_esd = _inter_gamma_force(sh, wl, N)
     wl = []
-    for d in res.dimers:
-        I, J = d["I"], d["J"]
-        others = np.where((sh.frag != I) & (sh.frag != J))[0]
-        wl.append((d["shells"], others, np.outer(d["ddq"], q[others])))
+    for d, wx in clusters:
+        frags = d["IJK"] if "IJK" in d else (d["I"], d["J"])
+        others = np.where(~np.isin(sh.frag, frags))[0]
+        if wx != 0.0 and len(others):
+            wl.append((d["shells"], others, wx * np.outer(d["ddq"], q[others])))
     g_ct = _inter_gamma_force(sh, wl, N)
     parts["esd"] = g_esd
     parts["ct"] = g_ct
     G += g_esd + g_ct
 
     if with_response:
-        g_resp, f_resp, info = _response(system, params, res, c)
+        g_resp, f_resp, info = _response(system, params, res, clusters)
         G += g_resp
         Fcn += f_resp
         parts["response"] = g_resp
@@ -423,15 +500,23 @@ def fmo2_gradient(system, params, res, with_response=True):
     return G, parts
 
 
-def lagrangian_potential(res):
-    """v_K on the shells of every monomer K: the potential of the charge
-    transfer of all SCC dimers not containing K (eq. esp_lagrangian)."""
+def fmo2_gradient(system, params, res, with_response=True):
+    """The FMO2 gradient (fmo_gradient of an FMO2 result)."""
+    return fmo_gradient(system, params, res, with_response)
+
+
+def lagrangian_potential(res, clusters=None):
+    """v_K on the shells of every monomer K: the potential of the weighted
+    charge transfer of all clusters not containing K (eq. esp_lagrangian;
+    FMO2: all SCC dimers with weight 1)."""
     sh = res.shells
+    if clusters is None:
+        clusters = [(d, 1.0) for d in res.dimers]
     v = np.zeros(sh.n)
-    for d in res.dimers:
-        I, J = d["I"], d["J"]
-        tg = np.where((sh.frag != I) & (sh.frag != J))[0]
-        v[tg] += sh.gamma_block(tg, d["shells"]) @ d["ddq"]
+    for d, wx in clusters:
+        frags = d["IJK"] if "IJK" in d else (d["I"], d["J"])
+        tg = np.where(~np.isin(sh.frag, frags))[0]
+        v[tg] += wx * (sh.gamma_block(tg, d["shells"]) @ d["ddq"])
     return v
 
 
@@ -460,13 +545,13 @@ def _monomer_response_blocks(sx, r):
     return dict(Q=Q, D=D, M=M, G=Gm, Co=Co, Cv=Cv, eo=eo, ev=ev)
 
 
-def _response(system, params, res, c):
+def _response(system, params, res, clusters):
     sh = res.shells
     F = system.n_frag
     fa, fsh = res.frag_atoms, res.frag_shells
     N = system.n_atoms
     q = res.q
-    v = lagrangian_potential(res)
+    v = lagrangian_potential(res, clusters)
     blocks = [_monomer_response_blocks(res.mono_sys[I], res.mono[I]) for I in range(F)]
     # susceptibility chi_K = -(1 + M G)^-1 M, block diagonal over fragments
     ns = sh.n

@@ -38,7 +38,8 @@ class Params:
                              kappa=float(s["kappa"])) for s in e["shells"]],
                 EN=float(e["EN"]), rcov=float(e["rcov_angstrom"]) * a2b,
                 eta=float(e["eta"]), Gamma=float(e["Gamma"]),
-                zeff=float(e["zeff"]), arep=float(e["alpha_rep"]))
+                zeff=float(e["zeff"]), arep=float(e["alpha_rep"]),
+                rvdw=float(e["rvdw_angstrom"]) * a2b if "rvdw_angstrom" in e else None)
 
     def element(self, Z):
         if Z not in self.elem:

@@ -30,7 +30,8 @@ class fx_options(C.Structure):
                 ("schedule", C.c_int32), ("guess", C.c_int32), ("guess_tau", C.c_double),
                 ("guess_max_iter", C.c_int32), ("scc_tol", C.c_double),
                 ("energy_tol", C.c_double), ("macro_tol", C.c_double), ("max_iter", C.c_int32),
-                ("max_macro", C.c_int32), ("want_gradient", C.c_int32), ("want_response", C.c_int32)]
+                ("max_macro", C.c_int32), ("want_gradient", C.c_int32), ("want_response", C.c_int32),
+                ("selection", C.c_int32), ("vdw_dimer", C.c_double), ("vdw_trimer", C.c_double)]
 
 
 class fx_counts(C.Structure):
@@ -239,7 +240,9 @@ class FmoXtb:
         return scc, esd, tri
 
     def set_guess(self, dq_shell):
-        dq = _f64(dq_shell)
+        dq = _f64(dq_shell).reshape(-1)
+        if dq.size != self.n_shells:
+            raise ValueError(f"guess has {dq.size} shell charges, the system has {self.n_shells}")
         self._check(self.L.fx_set_guess(self.ctx, _ptr(dq, C.c_double)))
 
     # -- run and results -----------------------------------------------------

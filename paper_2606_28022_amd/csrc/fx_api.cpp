@@ -123,6 +123,7 @@ HostParams load_params(const std::string& path) {
     el.Gamma = e["Gamma"].d();
     el.zeff = e["zeff"].d();
     el.arep = e["alpha_rep"].d();
+    el.rvdw = e.has("rvdw_angstrom") ? e["rvdw_angstrom"].d() * a2b : 0.0;
     el.Z = Z;
     P.elem_of_Z[Z] = (int)P.elems.size();
     P.elems.push_back(el);
@@ -799,11 +800,9 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
   // listed there return at once (device-side status)
   bool last_split = false;
   // split eigensolver: rotation log of up to jacobi_max_log sweeps per system
-  const int m_max = b.max_nao + (b.max_nao & 1);
-  const long long log_stride = (long long)jacobi_max_log * (m_max - 1) * (m_max / 2);
-  const bool split_ok = jacobi_split && jp.elt != 0 &&
-                        b.max_nao * 512 + 16 * 16 * (m_max / 2) + 16 * ((16 * (m_max / 2) + 3) / 4) <= lds_max &&
-                        (int)jacobi_lds_layout(b.max_nao, jp.elt, 1, 0).total <= lds_max;
+  const long long log_stride = (long long)jacobi_max_log * jacobi_rot_log_entries(b.max_nao);
+  const bool split_ok = jacobi_split && jp.elt != 0 && (long long)apply_rot_lds_bytes(b.max_nao) <= lds_max &&
+                        (int)jacobi_rot_layout(b.max_nao, jp.elt).total <= lds_max;
   if (split_ok) {
     b.rotlog.alloc((long long)b.nsys * log_stride);
     b.nlog.alloc(b.nsys);
@@ -817,7 +816,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     // A = (C^T F) C is symmetric: upper tiles only, mirrored
     gemm_batch(b, db, na, dl, 1, b.Tm.p, b.Ct.p, b.Fm.p, nullptr, b.gemm_gflop(act), 1, 1);
     if (split_ok && cap < 1e299) {
-      const unsigned lds_rot = jacobi_lds_layout(b.max_nao, jp.elt, 1, 0).total;
+      const unsigned lds_rot = jacobi_rot_layout(b.max_nao, jp.elt).total;
       int ev = timed ? timers.begin(stream) : -1;
       if (jp.elt == 8)
         hipLaunchKernelGGL(k_jacobi_rot<double>, dim3(na), dim3(jp.threads), lds_rot, stream, db, dl,
@@ -831,9 +830,9 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
       const int tps = (b.max_nao + 63) / 64;
       const long long grid = ((long long)na * tps + 7) / 8 * 8;
       ev = timed ? timers.begin(stream) : -1;
-      const unsigned ce = 16u * (unsigned)(m_max / 2);
-      const unsigned lds_app = (unsigned)b.max_nao * 512u + 16u * ce + 16u * ((ce + 3u) / 4u);
-      hipLaunchKernelGGL(k_apply_rot, dim3((unsigned)grid), dim3(1024), lds_app, stream, db, dl,
+      const unsigned lds_app = (unsigned)apply_rot_lds_bytes(b.max_nao);
+      hipLaunchKernelGGL(k_apply_rot, dim3((unsigned)grid), dim3(64 * apply_rot_waves(b.max_nao)), lds_app, stream,
+                         db, dl,
                          na, tps, (const double2*)b.rotlog.p, log_stride, (const int*)b.nlog.p);
       if (timed) timers.end(stream, ev, kt_app, 0.0);
       last_split = true;
@@ -1017,10 +1016,15 @@ void Ctx::build_lists_impl() {
   const long long npair = (long long)F * (F - 1) / 2;
   DevBuf<int8_t> flag;
   flag.alloc(std::max(1LL, npair));
+  const bool vdw = opt.selection == FX_SELECT_VDW;
+  if (vdw)
+    for (int a = 0; a < N; ++a)
+      if (!(P.elems[elem[a]].rvdw > 0.0))
+        throw FxError(FX_E_UNSUPPORTED, "van der Waals radius missing from the parameters");
   if (F > 1) {
     hipLaunchKernelGGL(k_pair_contacts, dim3(F), dim3(256), 0, stream, dev_system(), d_frag_atoms_real.p,
-                       d_frag_off_real.p,
-                       opt.cutoff_bohr * opt.cutoff_bohr, flag.p);
+                       d_frag_off_real.p, vdw ? 1 : 0, opt.cutoff_bohr * opt.cutoff_bohr, opt.vdw_dimer,
+                       opt.vdw_trimer, flag.p);
     check(hipGetLastError(), "k_pair_contacts");
   }
   std::vector<int8_t> h(npair);
@@ -1029,23 +1033,27 @@ void Ctx::build_lists_impl() {
   scc_pairs.clear();
   esd_pairs.clear();
   trimers.clear();
+  // flag bit 0: SCC dimer; bit 1: the pair counts for the trimer rule
   std::vector<std::vector<int>> nb(F);
   long long k = 0;
   for (int I = 0; I < F; ++I)
     for (int J = I + 1; J < F; ++J, ++k) {
-      if (h[k]) {
-        scc_pairs.push_back(I);
-        scc_pairs.push_back(J);
+      if (h[k] & 2) {
         nb[I].push_back(J);
         nb[J].push_back(I);
+      }
+      if (h[k] & 1) {
+        scc_pairs.push_back(I);
+        scc_pairs.push_back(J);
       } else {
         esd_pairs.push_back(I);
         esd_pairs.push_back(J);
       }
     }
   if (opt.order >= 3) {
-    // trimers I<J<K with at least two SCC sub-pairs: every such trimer has a
-    // fragment adjacent to both others; enumerate candidates from neighbour lists
+    // trimers I<J<K with at least two sub-pairs meeting the trimer rule: every
+    // such trimer has a fragment adjacent to both others; enumerate candidates
+    // from neighbour lists
     std::vector<std::vector<char>> adj;
     auto near = [&](int a, int b) {
       const std::vector<int>& v = nb[a];
@@ -1596,6 +1604,9 @@ int fx_default_options(fx_options* o) {
   o->max_macro = 200;
   o->want_gradient = 1;
   o->want_response = 1;
+  o->selection = FX_SELECT_CUTOFF;
+  o->vdw_dimer = 2.0;
+  o->vdw_trimer = 1.5;
   return FX_OK;
 }
 
@@ -1611,7 +1622,14 @@ int fx_set_options(fx_ctx* ctx, const fx_options* o) {
       throw fx::FxError(FX_E_INVALID, "bad schedule");
     if (o->guess != FX_GUESS_SUPERPOSITION && o->guess != FX_GUESS_LEARNED && o->guess != FX_GUESS_USER)
       throw fx::FxError(FX_E_INVALID, "bad guess");
-    bool cutoff_changed = o->cutoff_bohr != ctx->c.opt.cutoff_bohr || o->order != ctx->c.opt.order;
+    if (o->selection != FX_SELECT_CUTOFF && o->selection != FX_SELECT_VDW)
+      throw fx::FxError(FX_E_INVALID, "bad selection rule");
+    if (!(o->vdw_dimer > 0.0) || !(o->vdw_trimer > 0.0) || !std::isfinite(o->vdw_dimer) ||
+        !std::isfinite(o->vdw_trimer))
+      throw fx::FxError(FX_E_INVALID, "van der Waals scaling factors must be positive");
+    const fx_options& c = ctx->c.opt;
+    bool cutoff_changed = o->cutoff_bohr != c.cutoff_bohr || o->order != c.order || o->selection != c.selection ||
+                          o->vdw_dimer != c.vdw_dimer || o->vdw_trimer != c.vdw_trimer;
     ctx->c.opt = *o;
     if (cutoff_changed) ctx->c.lists_built = false;
   });
@@ -1664,6 +1682,8 @@ int fx_set_guess(fx_ctx* ctx, const double* dq) {
   if (!ctx || !dq) return FX_E_INVALID;
   FX_GUARD(ctx, {
     if (!ctx->c.has_system) throw fx::FxError(FX_E_STATE, "no system set");
+    for (int k = 0; k < ctx->c.Nsh; ++k)
+      if (!std::isfinite(dq[k])) throw fx::FxError(FX_E_INVALID, "non-finite guess charge");
     ctx->c.guess.assign(dq, dq + ctx->c.Nsh);
   });
 }

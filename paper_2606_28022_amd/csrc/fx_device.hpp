@@ -25,6 +25,7 @@ struct DevElem {
   int orth;                 // second s shell orthogonalised against the first
   double orthN, orthS12;    // |s2'> = N (|s2> - S12 |s1>)
   double EN, rcov, Gamma, zeff, arep;
+  double rvdw;              // van der Waals radius (bohr) of the pair selection rule; 0 if not given
 };
 
 struct DevGlobals {

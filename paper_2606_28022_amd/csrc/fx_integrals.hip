@@ -61,10 +61,16 @@ __global__ void k_cn(DevSystem sys, double* cn_out) {
 }
 
 // ---------------------------------------------------------------------------
-// closest contact of every fragment pair (I < J), flag = d2 < cutoff^2.
-// d2 = (dx*dx + dy*dy) + dz*dz with every operation rounded separately.
-__global__ void k_pair_contacts(DevSystem sys, const int* frag_atoms, const int* frag_off,
-                                double cut2, int8_t* flag) {
+// Fragment-pair selection (section "Computational Details"), one flag per
+// pair I < J: bit 0 = SCC dimer, bit 1 = the pair counts towards the trimer
+// rule (at least two of a trimer's three pairs).
+//   rule 0: closest contact d2 < cut2 (both bits);
+//   rule 1: some atom pair a, b with d2 < (lam (r_a + r_b))^2, van der Waals
+//           radii r; bit 0 with lam = lam2, bit 1 with lam = lam3.
+// d2 = (dx*dx + dy*dy) + dz*dz and the threshold lam * (r_a + r_b), squared,
+// with every operation rounded separately (no contraction).
+__global__ void k_pair_contacts(DevSystem sys, const int* frag_atoms, const int* frag_off, int rule, double cut2,
+                                double lam2, double lam3, int8_t* flag) {
 #pragma clang fp contract(off)
   int I = blockIdx.x;
   int F = sys.nfrag;
@@ -73,9 +79,11 @@ __global__ void k_pair_contacts(DevSystem sys, const int* frag_atoms, const int*
   for (int J = I + 1 + threadIdx.x; J < F; J += blockDim.x) {
     int b0 = frag_off[J], b1 = frag_off[J + 1];
     double best = 1e300;
+    int bits = 0;
     for (int ia = a0; ia < a1; ++ia) {
       int a = frag_atoms[ia];
       double xa = sys.xyz[3 * a], ya = sys.xyz[3 * a + 1], za = sys.xyz[3 * a + 2];
+      const double ra = sys.elems[sys.elem[a]].rvdw;
       for (int ib = b0; ib < b1; ++ib) {
         int b = frag_atoms[ib];
         double dx = xa - sys.xyz[3 * b];
@@ -85,10 +93,18 @@ __global__ void k_pair_contacts(DevSystem sys, const int* frag_atoms, const int*
         double yy = __dmul_rn(dy, dy);
         double zz = __dmul_rn(dz, dz);
         double d2 = __dadd_rn(__dadd_rn(xx, yy), zz);
-        best = d2 < best ? d2 : best;
+        if (rule == 0) {
+          best = d2 < best ? d2 : best;
+        } else {
+          const double rs = __dadd_rn(ra, sys.elems[sys.elem[b]].rvdw);
+          const double t2 = __dmul_rn(lam2, rs), t3 = __dmul_rn(lam3, rs);
+          if (d2 < __dmul_rn(t2, t2)) bits |= 1;
+          if (d2 < __dmul_rn(t3, t3)) bits |= 2;
+        }
       }
     }
-    flag[base + (J - I - 1)] = best < cut2 ? 1 : 0;
+    if (rule == 0) bits = best < cut2 ? 3 : 0;
+    flag[base + (J - I - 1)] = (int8_t)bits;
   }
 }
 

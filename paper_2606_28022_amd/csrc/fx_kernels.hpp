@@ -9,8 +9,8 @@ namespace fx {
 
 // integrals / lists / fields (fx_integrals.hip)
 __global__ void k_cn(DevSystem sys, double* cn_out);
-__global__ void k_pair_contacts(DevSystem sys, const int* frag_atoms, const int* frag_off, double cut2,
-                                int8_t* flag);
+__global__ void k_pair_contacts(DevSystem sys, const int* frag_atoms, const int* frag_off, int rule, double cut2,
+                                double lam2, double lam3, int8_t* flag);
 __global__ void k_build_system(DevSystem sys, DevBatch bt, const int* list);
 __global__ void k_field_partial(DevSystem sys, const double* q, int nchunk, double* part);
 __global__ void k_field_partial_f32(DevSystem sys, const double* q, int nchunk, double* part);
@@ -63,6 +63,30 @@ __host__ __device__ inline JacobiLdsLayout jacobi_lds_layout(int n, int elt, int
   L.total = o;
   return L;
 }
+// LDS of k_jacobi_rot: packed strict upper triangle (elt bytes per element),
+// FP64 diagonal, (c, s) of one step or round (m entries, m = n rounded up to a
+// multiple of four), a reduction slot
+struct JacobiRotLayout {
+  unsigned ap, dg, cs, red, total;
+};
+__host__ __device__ inline JacobiRotLayout jacobi_rot_layout(int n, int elt) {
+  const unsigned m = (unsigned)(n + 3) & ~3u;
+  JacobiRotLayout L;
+  unsigned o = 0;
+  L.ap = o;
+  o = jl_align(o + (unsigned)n * (unsigned)(n - 1) / 2u * (unsigned)elt);
+  L.dg = o;
+  o = jl_align(o + 8u * (unsigned)n);
+  L.cs = o;
+  o = jl_align(o + 16u * m);
+  L.red = o;
+  o = jl_align(o + 8u * 64u);
+  L.total = o;
+  return L;
+}
+size_t apply_rot_lds_bytes(int n);
+int apply_rot_waves(int n);
+long long jacobi_rot_log_entries(int n);  // rotation log entries per sweep
 template <typename T>
 __global__ void k_cholinv_lds(DevBatch bt, const int* list, const double* Apool, double* Xpool);
 __global__ void k_ns_poly(DevBatch bt, const int* list, double* Hpool, const double* H2pool);

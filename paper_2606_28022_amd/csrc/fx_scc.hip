@@ -15,6 +15,8 @@
 #include "fx_device.hpp"
 #include "fx_kernels.hpp"
 
+#include <algorithm>
+
 namespace fx {
 
 __device__ inline double block_sum(double v, double* red) {
@@ -1175,16 +1177,105 @@ __global__ void __launch_bounds__(256)
 namespace fx {
 
 // ---------------------------------------------------------------------------
-// Split form of the LDS Jacobi for single-sweep SCC iterations.
+// Split form of the LDS Jacobi for single-sweep SCC iterations, with a
+// blocked cyclic ordering.
 //
-// k_jacobi_rot: the same sweeps as k_jacobi_lds on the LDS working matrix,
-// but instead of rotating C^T chunk by chunk it writes the sweep's rotation
-// log (c, s per step and pair, FP64) to HBM: up to `max_log` sweeps.
-// k_apply_rot then applies the logged rotations to C^T in 64-column tiles
-// held in LDS for the whole sweep, several work-groups per system.  C^T is
-// read and written once per launch instead of once per chunk of steps, and
-// every element sees the same rotations in the same order as in
-// k_jacobi_lds, so the results are identical.
+// The indices (padded to m, a multiple of four) form fixed blocks
+// {2k, 2k+1}.  A sweep is one step that rotates every block's own pair,
+// then m/2 - 1 round-robin rounds over the blocks; in each round the blocks
+// meet as quartets (X, Y) with rows x1 = 2X, x2 = 2X+1, y1 = 2Y, y2 = 2Y+1,
+// and each quartet takes two steps: (x1, y1) with (x2, y2), then (x1, y2)
+// with (x2, y1).  Every pair is rotated once per sweep in m - 1 steps, as in
+// the plain round-robin, but two steps share one pass over the data.
+//
+// k_jacobi_rot: sweeps on the LDS working matrix (packed strict upper
+// triangle in T, FP64 diagonal).  Per round, one thread per quartet solves
+// its 4 x 4 diagonal block (the two steps in order, rotation angles in FP64),
+// then every off-diagonal 4 x 4 block between two quartets is rotated on both
+// sides in one pass.  The rotations (c, s) go to the log in HBM: per sweep
+// the m/2 block rotations, then per round four per quartet (x1 y1, x2 y2,
+// x1 y2, x2 y1); up to `max_log` sweeps.
+// k_apply_rot applies the logged rotations to C^T in 64-column tiles held in
+// LDS: one wave per quartet reads its four (c, s) with uniform loads and
+// takes the quartet's four rows through both steps in registers.
+__device__ inline long long jq_sweep_entries(int m) { return (long long)m / 2 + (long long)(m / 2 - 1) * m; }
+
+// (a, b), a < b, of the idx-th unordered pair of N items (rows folded so that
+// every row of the enumeration has N entries)
+__device__ inline void tri_pair(int idx, int N, int& a, int& b) {
+  const int R = N - 1, hp = R / 2, rect = hp * N;
+  if (idx < rect) {
+    const int r = idx / N, cc = idx - r * N;
+    if (cc < R - r) {
+      a = r;
+      b = r + 1 + cc;
+    } else {
+      a = R - 1 - r;
+      b = a + 1 + (cc - (R - r));
+    }
+  } else {
+    a = hp;
+    b = hp + 1 + (idx - rect);
+  }
+}
+
+// Jacobi rotation zeroing a_pq of a symmetric matrix: (c, s, t), identity if
+// |a_pq| is below the threshold
+__device__ inline void jq_angle(double app, double aqq, double apq, double thr, double rel_tol, double& c, double& s,
+                                double& t) {
+  c = 1.0;
+  s = 0.0;
+  t = 0.0;
+  if (fabs(apq) > fmax(thr, rel_tol * fmax(fabs(app), fabs(aqq)))) {
+    const double theta = (aqq - app) / (2.0 * apq);
+    t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+    c = 1.0 / sqrt(t * t + 1.0);
+    s = t * c;
+  }
+}
+
+// two-sided rotation of rows/columns p, q of a symmetric 4 x 4 block
+template <int P, int Q>
+__device__ inline void jq_rot4(double (&M)[4][4], double c, double s, double t) {
+  if (s == 0.0) return;
+  const double app = M[P][P], aqq = M[Q][Q], apq = M[P][Q];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double a = M[P][k], b = M[Q][k];
+    M[P][k] = c * a - s * b;
+    M[Q][k] = s * a + c * b;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double a = M[k][P], b = M[k][Q];
+    M[k][P] = c * a - s * b;
+    M[k][Q] = s * a + c * b;
+  }
+  M[P][P] = app - t * apq;
+  M[Q][Q] = aqq + t * apq;
+  M[P][Q] = M[Q][P] = 0.0;
+}
+
+// rows P, Q of a 4 x 4 block rotated (left side only)
+template <int P, int Q, typename T>
+__device__ inline void jq_rows(T (&B)[4][4], T c, T s) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const T a = B[P][k], b = B[Q][k];
+    B[P][k] = c * a - s * b;
+    B[Q][k] = s * a + c * b;
+  }
+}
+template <int P, int Q, typename T>
+__device__ inline void jq_cols(T (&B)[4][4], T c, T s) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const T a = B[k][P], b = B[k][Q];
+    B[k][P] = c * a - s * b;
+    B[k][Q] = s * a + c * b;
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(1024)
     k_jacobi_rot(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale, double cap_err,
@@ -1195,15 +1286,14 @@ __global__ void __launch_bounds__(1024)
   if (bt.status[si] != 0) return;
   const SysDesc d = bt.desc[si];
   const int n = d.nao;
-  const int m = n + (n & 1), nb = m / 2;
+  const int m = (n + 3) & ~3, nb2 = m / 2, nq = m / 4;
   const int nt = blockDim.x;
-  const JacobiLdsLayout L = jacobi_lds_layout(n, (int)sizeof(T), 1, 0);
+  const JacobiRotLayout L = jacobi_rot_layout(n, (int)sizeof(T));
   T* Ap = reinterpret_cast<T*>(lds + L.ap);
   double* dg = reinterpret_cast<double*>(lds + L.dg);
-  double2* cs = reinterpret_cast<double2*>(lds + L.cs);  // [nb] (c, s) of the current step
-  int* pq = reinterpret_cast<int*>(lds + L.pq);          // [nb] p | q << 16
+  double2* cs = reinterpret_cast<double2*>(lds + L.cs);  // [m]: block step [nb2], then 4 per quartet
   double* red = reinterpret_cast<double*>(lds + L.red);
-  double* rows = reinterpret_cast<double*>(cs);  // row sums before the sweeps (nb * 16 >= 8 n bytes)
+  double* rows = reinterpret_cast<double*>(cs);  // row sums before the sweeps (16 m >= 8 n bytes)
   const double* __restrict__ A = bt.F + d.mat_off;
   double2* lg = logbuf + (long long)si * log_stride;
   for (int e = threadIdx.x; e < n * n; e += nt) {
@@ -1234,76 +1324,153 @@ __global__ void __launch_bounds__(1024)
   const double err = bt.err[si];
   const double thr = fmax(rel_tol * (fro > 0.0 ? fro : 1.0), thr_scale * err);
   const int msw = min(max_log, err > cap_err ? 1 : max_sweeps);
-  const int R = nb - 1, hp = R / 2, rect = hp * nb, noff = nb * (nb - 1) / 2;
+  const long long swe = jq_sweep_entries(m);
+  const int nblk = nb2 * (nb2 - 1) / 2, nqp = nq * (nq - 1) / 2;
   int sweep = 0;
   bool converged = false;
   for (; sweep < msw; ++sweep) {
     int rot_sweep = 0;
-    double2* ls = lg + (long long)sweep * (m - 1) * nb;
-    for (int step = 0; step < m - 1; ++step) {
-      for (int k = threadIdx.x; k < nb; k += nt) {
-        int p = rr_index(k, step, m), q = rr_index(m - 1 - k, step, m);
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
+    double2* ls = lg + (long long)sweep * swe;
+    // block step: pairs (2k, 2k+1)
+    for (int k = threadIdx.x; k < nb2; k += nt) {
+      const int p = 2 * k, q = p + 1;
+      double c = 1.0, s = 0.0, t = 0.0;
+      if (q < n) {
+        const int ipq = pk_index(p, q);
+        const double apq = (double)Ap[ipq], app = dg[p], aqq = dg[q];
+        jq_angle(app, aqq, apq, thr, rel_tol, c, s, t);
+        if (s != 0.0) {
+          dg[p] = app - t * apq;
+          dg[q] = aqq + t * apq;
+          Ap[ipq] = (T)0;
+          rot_sweep = 1;
         }
-        double c = 1.0, s = 0.0;
-        if (q < n) {
-          const int ipq = pk_index(p, q);
-          const double apq = (double)Ap[ipq];
-          const double app = dg[p], aqq = dg[q];
-          if (fabs(apq) > fmax(thr, rel_tol * fmax(fabs(app), fabs(aqq)))) {
-            const double theta = (aqq - app) / (2.0 * apq);
-            const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            s = t * c;
-            dg[p] = app - t * apq;
-            dg[q] = aqq + t * apq;
-            Ap[ipq] = (T)0;
-            rot_sweep = 1;
+      }
+      cs[k] = make_double2(c, s);
+      ls[k] = make_double2(c, s);
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nblk; idx += nt) {
+      int a, b;
+      tri_pair(idx, nb2, a, b);
+      const double2 wa = cs[a], wb = cs[b];
+      if (wa.y == 0.0 && wb.y == 0.0) continue;
+      const int p = 2 * a, q = p + 1, r = 2 * b, u = r + 1;  // p < q < r < u
+      if (r >= n) continue;  // block b wholly padded: nothing stored in its columns
+      const bool qv = q < n, uv = u < n;
+      const T ca = (T)wa.x, sa = (T)wa.y, cb = (T)wb.x, sb = (T)wb.y;
+      const int ipr = pk_index(p, r);
+      const int ipu = uv ? pk_index(p, u) : 0;
+      const int iqr = qv ? pk_index(q, r) : 0;
+      const int iqu = (qv && uv) ? pk_index(q, u) : 0;
+      const T bpr = Ap[ipr];
+      const T bpu = uv ? Ap[ipu] : (T)0;
+      const T bqr = qv ? Ap[iqr] : (T)0;
+      const T bqu = (qv && uv) ? Ap[iqu] : (T)0;
+      const T tpr = ca * bpr - sa * bqr, tpu = ca * bpu - sa * bqu;
+      const T tqr = sa * bpr + ca * bqr, tqu = sa * bpu + ca * bqu;
+      Ap[ipr] = cb * tpr - sb * tpu;
+      if (uv) Ap[ipu] = sb * tpr + cb * tpu;
+      if (qv) Ap[iqr] = cb * tqr - sb * tqu;
+      if (qv && uv) Ap[iqu] = sb * tqr + cb * tqu;
+    }
+    __syncthreads();
+    for (int rd = 0; rd < nb2 - 1; ++rd) {
+      double2* lr = ls + nb2 + (long long)rd * m;
+      // quartet solves: the two steps on the quartet's own 4 x 4 block
+      for (int qd = threadIdx.x; qd < nq; qd += nt) {
+        const int X = rr_index(qd, rd, nb2), Y = rr_index(nb2 - 1 - qd, rd, nb2);
+        const int ix[4] = {2 * X, 2 * X + 1, 2 * Y, 2 * Y + 1};
+        double M[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            double v = 0.0;
+            if (ix[i] < n && ix[j] < n) v = i == j ? dg[ix[i]] : (double)Ap[pk_index(ix[i], ix[j])];
+            M[i][j] = v;
           }
         }
-        cs[k] = make_double2(c, s);
-        pq[k] = p | (q << 16);
-        ls[(long long)step * nb + k] = make_double2(c, s);
+        double c0, s0, t0, c1, s1, t1, c2, s2, t2, c3, s3, t3;
+        // step 1: (x1, y1) and (x2, y2), both from the block before the step
+        jq_angle(M[0][0], M[2][2], M[0][2], thr, rel_tol, c0, s0, t0);
+        jq_angle(M[1][1], M[3][3], M[1][3], thr, rel_tol, c1, s1, t1);
+        // (padded rows and columns are zero, so their rotations are the
+        // identity already; the tests make that explicit)
+        if (ix[0] >= n || ix[2] >= n) c0 = 1.0, s0 = 0.0, t0 = 0.0;
+        if (ix[1] >= n || ix[3] >= n) c1 = 1.0, s1 = 0.0, t1 = 0.0;
+        jq_rot4<0, 2>(M, c0, s0, t0);
+        jq_rot4<1, 3>(M, c1, s1, t1);
+        // step 2: (x1, y2) and (x2, y1)
+        jq_angle(M[0][0], M[3][3], M[0][3], thr, rel_tol, c2, s2, t2);
+        jq_angle(M[1][1], M[2][2], M[1][2], thr, rel_tol, c3, s3, t3);
+        if (ix[0] >= n || ix[3] >= n) c2 = 1.0, s2 = 0.0, t2 = 0.0;
+        if (ix[1] >= n || ix[2] >= n) c3 = 1.0, s3 = 0.0, t3 = 0.0;
+        jq_rot4<0, 3>(M, c2, s2, t2);
+        jq_rot4<1, 2>(M, c3, s3, t3);
+        if (s0 != 0.0 || s1 != 0.0 || s2 != 0.0 || s3 != 0.0) {
+          rot_sweep = 1;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (ix[i] < n) dg[ix[i]] = M[i][i];
+#pragma unroll
+            for (int j = i + 1; j < 4; ++j)
+              if (ix[i] < n && ix[j] < n) Ap[pk_index(ix[i], ix[j])] = (T)M[i][j];
+          }
+        }
+        const double2 w0 = make_double2(c0, s0), w1 = make_double2(c1, s1), w2 = make_double2(c2, s2),
+                      w3 = make_double2(c3, s3);
+        cs[4 * qd] = w0;
+        cs[4 * qd + 1] = w1;
+        cs[4 * qd + 2] = w2;
+        cs[4 * qd + 3] = w3;
+        lr[4 * qd] = w0;
+        lr[4 * qd + 1] = w1;
+        lr[4 * qd + 2] = w2;
+        lr[4 * qd + 3] = w3;
       }
       __syncthreads();
-      for (int idx = threadIdx.x; idx < noff; idx += nt) {
+      // off-diagonal blocks: rows of quartet a, columns of quartet b
+      for (int idx = threadIdx.x; idx < nqp; idx += nt) {
         int a, b;
-        if (idx < rect) {
-          const int r = idx / nb, cc = idx - r * nb;
-          if (cc < R - r) {
-            a = r;
-            b = r + 1 + cc;
-          } else {
-            a = R - 1 - r;
-            b = a + 1 + (cc - (R - r));
+        tri_pair(idx, nq, a, b);
+        const double2 va0 = cs[4 * a], va1 = cs[4 * a + 1], va2 = cs[4 * a + 2], va3 = cs[4 * a + 3];
+        const double2 vb0 = cs[4 * b], vb1 = cs[4 * b + 1], vb2 = cs[4 * b + 2], vb3 = cs[4 * b + 3];
+        const bool ra = va0.y != 0.0 || va1.y != 0.0 || va2.y != 0.0 || va3.y != 0.0;
+        const bool rb = vb0.y != 0.0 || vb1.y != 0.0 || vb2.y != 0.0 || vb3.y != 0.0;
+        if (!ra && !rb) continue;
+        const int Xa = rr_index(a, rd, nb2), Ya = rr_index(nb2 - 1 - a, rd, nb2);
+        const int Xb = rr_index(b, rd, nb2), Yb = rr_index(nb2 - 1 - b, rd, nb2);
+        const int ia[4] = {2 * Xa, 2 * Xa + 1, 2 * Ya, 2 * Ya + 1};
+        const int ib[4] = {2 * Xb, 2 * Xb + 1, 2 * Yb, 2 * Yb + 1};
+        int h[4][4];
+        T B[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const bool ok = ia[i] < n && ib[j] < n;
+            h[i][j] = ok ? pk_index(ia[i], ib[j]) : -1;
+            B[i][j] = ok ? Ap[h[i][j]] : (T)0;
           }
-        } else {
-          a = hp;
-          b = hp + 1 + (idx - rect);
         }
-        const double2 wa = cs[a], wb = cs[b];
-        if (wa.y == 0.0 && wb.y == 0.0) continue;
-        const int va = pq[a], vb = pq[b];
-        const int p = va & 0xffff, q = va >> 16, r = vb & 0xffff, u = vb >> 16;
-        const bool qv = q < n, uv = u < n;
-        const T ca = (T)wa.x, sa = (T)wa.y, cb = (T)wb.x, sb = (T)wb.y;
-        const int ipr = pk_index(p, r);
-        const int ipu = uv ? pk_index(p, u) : 0;
-        const int iqr = qv ? pk_index(q, r) : 0;
-        const int iqu = (qv && uv) ? pk_index(q, u) : 0;
-        const T bpr = Ap[ipr];
-        const T bpu = uv ? Ap[ipu] : (T)0;
-        const T bqr = qv ? Ap[iqr] : (T)0;
-        const T bqu = (qv && uv) ? Ap[iqu] : (T)0;
-        const T tpr = ca * bpr - sa * bqr, tpu = ca * bpu - sa * bqu;
-        const T tqr = sa * bpr + ca * bqr, tqu = sa * bpu + ca * bqu;
-        Ap[ipr] = cb * tpr - sb * tpu;
-        if (uv) Ap[ipu] = sb * tpr + cb * tpu;
-        if (qv) Ap[iqr] = cb * tqr - sb * tqu;
-        if (qv && uv) Ap[iqu] = sb * tqr + cb * tqu;
+        if (ra) {
+          jq_rows<0, 2>(B, (T)va0.x, (T)va0.y);
+          jq_rows<1, 3>(B, (T)va1.x, (T)va1.y);
+          jq_rows<0, 3>(B, (T)va2.x, (T)va2.y);
+          jq_rows<1, 2>(B, (T)va3.x, (T)va3.y);
+        }
+        if (rb) {
+          jq_cols<0, 2>(B, (T)vb0.x, (T)vb0.y);
+          jq_cols<1, 3>(B, (T)vb1.x, (T)vb1.y);
+          jq_cols<0, 3>(B, (T)vb2.x, (T)vb2.y);
+          jq_cols<1, 2>(B, (T)vb3.x, (T)vb3.y);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (h[i][j] >= 0) Ap[h[i][j]] = B[i][j];
       }
       __syncthreads();
     }
@@ -1326,16 +1493,21 @@ template __global__ void k_jacobi_rot<float>(DevBatch, const int*, int, double, 
                                              long long, int, int*);
 
 // Apply the logged rotations to the rows of C^T, one 64-column tile per
-// work-group of 16 waves (lane = column): the tile stays in LDS for all
-// logged sweeps; the log is staged into LDS 16 steps at a time (coalesced
-// loads, the next chunk fetched into registers while the current one is
-// applied) together with the pair indices of those steps; within a step the
-// pairs are disjoint, so the waves share them (pair k to wave k % 16, two
-// pairs in flight per wave) with one barrier per step.
-constexpr int APPLY_CHUNK = 16;
+// work-group (lane = column); the tile stays in LDS for all logged sweeps.
+// Pairs of one step are disjoint and quartets of one round are disjoint, so
+// the waves share them (block k or quartet k to wave k mod waves) with one
+// barrier per step of the block step and one per round.  The rotation
+// parameters and indices are uniform in a wave (scalar loads and integer
+// arithmetic).
+__device__ inline void jq_apply2(double& a, double& b, double2 w) {
+  const double x = a, y = b;
+  a = w.x * x - w.y * y;
+  b = w.y * x + w.x * y;
+}
+
 __global__ void __launch_bounds__(1024)
-    k_apply_rot(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double2* logbuf, long long log_stride,
-                const int* nlog) {
+    k_apply_rot(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double2* __restrict__ logbuf,
+                long long log_stride, const int* nlog) {
   extern __shared__ double2 lds_raw[];
   const int Lid = blockIdx.x, G = gridDim.x;  // G is a multiple of 8
   const int logical = (Lid & 7) * (G >> 3) + (Lid >> 3);
@@ -1349,80 +1521,65 @@ __global__ void __launch_bounds__(1024)
   const int n = d.nao, nv = d.nao;
   const int c0 = tcol * 64;
   if (c0 >= nv) return;
-  const int m = n + (n & 1), nb = m / 2;
-  const int NT = blockDim.x, NW = NT >> 6;
-  double2* lc = lds_raw;                                           // [APPLY_CHUNK][nb] (c, s)
-  int* lpq = reinterpret_cast<int*>(lds_raw + APPLY_CHUNK * nb);   // [APPLY_CHUNK][nb] p | q << 16
-  double* tile = reinterpret_cast<double*>(lds_raw + APPLY_CHUNK * nb + (APPLY_CHUNK * nb + 3) / 4);  // [n][64]
+  const int m = (n + 3) & ~3, nb2 = m / 2, nq = m / 4;
+  const int NW = blockDim.x >> 6;
+  double* tile = reinterpret_cast<double*>(lds_raw);  // [m][64], padded rows zero
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double* V = bt.Ct + d.mat_off;
   const bool colok = c0 + lane < nv;
-  for (int i = wave; i < n; i += NW) tile[i * 64 + lane] = colok ? V[(long long)i * nv + c0 + lane] : 0.0;
+  for (int i = wave; i < m; i += NW) tile[i * 64 + lane] = (colok && i < n) ? V[(long long)i * nv + c0 + lane] : 0.0;
   const double2* lg = logbuf + (long long)si * log_stride;
-  const long long total = (long long)nsw * (m - 1);  // steps over all logged sweeps
-  const int CE = APPLY_CHUNK * nb;                   // entries per chunk
-  double2 rg[4];                                     // CE <= 4096 entries, NT = 1024
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int e = threadIdx.x + NT * r;
-    rg[r] = (e < CE && e / nb < total) ? lg[e] : make_double2(1.0, 0.0);
-  }
-  for (long long s0 = 0; s0 < total; s0 += APPLY_CHUNK) {
-    __syncthreads();  // previous chunk applied, tile loaded
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int e = threadIdx.x + NT * r;
-      if (e < CE) {
-        lc[e] = rg[r];
-        const int c = e / nb, k = e - c * nb;
-        const int step = (int)((s0 + c) % (m - 1));
-        int p = rr_index(k, step, m), q = rr_index(m - 1 - k, step, m);
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
-        }
-        lpq[e] = p | (q << 16);
-      }
+  const long long swe = jq_sweep_entries(m);
+  for (int sw = 0; sw < nsw; ++sw) {
+    const double2* ls = lg + (long long)sw * swe;
+    __syncthreads();  // tile loaded / previous round applied
+    for (int k = wave; k < nb2; k += NW) {
+      const double2 w = ls[k];
+      if (w.y == 0.0) continue;  // identity (also every pair with a padded index)
+      double* r0 = tile + (2 * k) * 64 + lane;
+      double a = r0[0], b = r0[64];
+      jq_apply2(a, b, w);
+      r0[0] = a;
+      r0[64] = b;
     }
-    __syncthreads();
-    const long long s1 = s0 + APPLY_CHUNK;
-    if (s1 < total) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int e = threadIdx.x + NT * r;
-        rg[r] = (e < CE && s1 + e / nb < total) ? lg[s1 * nb + e] : make_double2(1.0, 0.0);
-      }
-    }
-    const int ns = (int)((total - s0) < APPLY_CHUNK ? (total - s0) : APPLY_CHUNK);
-    for (int c = 0; c < ns; ++c) {
-      const double2* lw = lc + c * nb;
-      const int* lp = lpq + c * nb;
-      for (int k = wave; k < nb; k += 2 * NW) {
-        const int k2 = k + NW;
-        const double2 w1 = lw[k];
-        const double2 w2 = k2 < nb ? lw[k2] : make_double2(1.0, 0.0);
-        const bool r1 = w1.y != 0.0, r2 = w2.y != 0.0;
-        const int v1 = lp[k], v2 = k2 < nb ? lp[k2] : 0;
-        const int p1 = v1 & 0xffff, q1 = v1 >> 16, p2 = v2 & 0xffff, q2 = v2 >> 16;
-        // the two pairs are disjoint: load both, then store both
-        const double a1 = r1 ? tile[p1 * 64 + lane] : 0.0, b1 = r1 ? tile[q1 * 64 + lane] : 0.0;
-        const double a2 = r2 ? tile[p2 * 64 + lane] : 0.0, b2 = r2 ? tile[q2 * 64 + lane] : 0.0;
-        if (r1) {
-          tile[p1 * 64 + lane] = w1.x * a1 - w1.y * b1;
-          tile[q1 * 64 + lane] = w1.y * a1 + w1.x * b1;
-        }
-        if (r2) {
-          tile[p2 * 64 + lane] = w2.x * a2 - w2.y * b2;
-          tile[q2 * 64 + lane] = w2.y * a2 + w2.x * b2;
-        }
-      }
+    for (int rd = 0; rd < nb2 - 1; ++rd) {
       __syncthreads();
+      const double2* lr = ls + nb2 + (long long)rd * m;
+      for (int qd = wave; qd < nq; qd += NW) {
+        const double2 w0 = lr[4 * qd], w1 = lr[4 * qd + 1], w2 = lr[4 * qd + 2], w3 = lr[4 * qd + 3];
+        if (w0.y == 0.0 && w1.y == 0.0 && w2.y == 0.0 && w3.y == 0.0) continue;
+        const int X = rr_index(qd, rd, nb2), Y = rr_index(nb2 - 1 - qd, rd, nb2);
+        // rows x1 x2 (block X) and y1 y2 (block Y); padded rows stay zero
+        // (their rotations are the identity)
+        double* px = tile + (2 * X) * 64 + lane;
+        double* py = tile + (2 * Y) * 64 + lane;
+        double x1 = px[0], x2 = px[64], y1 = py[0], y2 = py[64];
+        jq_apply2(x1, y1, w0);
+        jq_apply2(x2, y2, w1);
+        jq_apply2(x1, y2, w2);
+        jq_apply2(x2, y1, w3);
+        px[0] = x1;
+        px[64] = x2;
+        py[0] = y1;
+        py[64] = y2;
+      }
     }
   }
+  __syncthreads();
   if (colok)
     for (int i = wave; i < n; i += NW) V[(long long)i * nv + c0 + lane] = tile[i * 64 + lane];
+}
+
+size_t apply_rot_lds_bytes(int n) { return (size_t)((n + 3) & ~3) * 64 * 8; }
+int apply_rot_waves(int n) {
+  const int nq = ((n + 3) & ~3) / 4;
+  const int per = (nq + 15) / 16;  // quartets per wave at 16 waves
+  return std::max(1, std::min(16, (nq + per - 1) / per));
+}
+long long jacobi_rot_log_entries(int n) {
+  const long long m = (n + 3) & ~3;
+  return m / 2 + (m / 2 - 1) * m;
 }
 
 }  // namespace fx

@@ -270,3 +270,93 @@ def test_mixed_precision_matches_fp64(lib, which):
         if len(a):
             assert np.max(np.abs(a - b)) < 1e-8
     assert np.max(np.abs(g1 - g0)) < 1e-7
+
+
+def test_user_guess_warm_start(lib, params, c1):
+    """FX_GUESS_USER starts the monomer loop from given shell charges (an MD
+    step from the previous geometry).  The fixed point does not depend on the
+    start: from the converged charges the energy and charges are reproduced
+    with fewer monomer iterations; after a 0.001 A displacement of every atom
+    the warm-started step equals a cold solve and the oracle there."""
+    _say("user guess warm start")
+    c = _ctx(lib, c1, want_gradient=1)
+    r0 = c.run()
+    q0 = c.charges()
+    g0 = c.gradient()
+    c.set_options(guess=2)
+    c.set_guess(q0)
+    r1 = c.run()
+    assert abs(r1["e_total"] - r0["e_total"]) < 1e-9
+    assert np.max(np.abs(c.charges() - q0)) < 1e-9
+    assert np.max(np.abs(c.gradient() - g0)) < 1e-8
+    assert r1["iters_mono"] < r0["iters_mono"]
+    rng = np.random.default_rng(11)
+    d = rng.normal(size=c1.xyz.shape)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    xyz2 = c1.xyz + 0.001 * A2B * d
+    s2 = w.System(name="displaced", Z=c1.Z, xyz=xyz2, frag=c1.frag, frag_charge=c1.frag_charge)
+    c.set_system(s2.Z, s2.xyz, s2.frag, s2.frag_charge)
+    c.set_guess(q0)
+    rw = c.run()
+    qw = c.charges()
+    c.set_options(guess=0)
+    rc = c.run()
+    assert abs(rw["e_total"] - rc["e_total"]) < 1e-9
+    assert np.max(np.abs(qw - c.charges())) < 1e-9
+    assert rw["iters_mono"] < rc["iters_mono"]
+    ro = F.fmo(s2, params, 4 * A2B)
+    assert abs(rw["e_total"] - ro.E) < 1e-8
+    from paper_2606_28022_amd.binding import FxError
+    with pytest.raises((FxError, ValueError)):
+        c.set_guess(q0[:-1])
+
+
+@pytest.mark.parametrize("which", ["c1", "anthracene8", "pentacene"])
+def test_lists_vdw_bit_exact(lib, params, c1, c4, which):
+    """Van der Waals-scaled selection (section "Computational Details"):
+    SCC dimers at 2.0 (r_a + r_b), trimers with two of three pairs at 1.5,
+    integer lists equal to the oracle's."""
+    _say(f"vdW lists {which}")
+    s, order = {"c1": (c1, 3), "anthracene8": (None, 3), "pentacene": (c4, 2)}[which]
+    if s is None:
+        s = w.anthracene_crystal(reps=(2, 2, 2))
+    c = _ctx(lib, s, order=order, selection=1, vdw_dimer=2.0, vdw_trimer=1.5)
+    scc, esd, tri = c.build_lists()
+    o_scc, o_esd, o_tri = F.build_lists(s, 0.0, order=order, vdw=(F.vdw_radii(s, params), 2.0, 1.5))
+    assert np.array_equal(scc, o_scc) and np.array_equal(esd, o_esd) and np.array_equal(tri, o_tri)
+    assert len(scc) > 0 and len(esd) > 0 and (order < 3 or len(tri) > 0)
+    # the rule differs from the fixed cutoff on these systems
+    c.set_options(selection=0)
+    assert not np.array_equal(c.build_lists()[0], scc) or which == "c1"
+
+
+def test_fmo3_energy_vdw_selection(lib, params, c1):
+    _say("FMO3 vdW selection")
+    s = c1.subset([0, 1, 2, 3, 4])
+    lists = F.build_lists(s, 0.0, order=3, vdw=(F.vdw_radii(s, params), 2.0, 1.5))
+    assert len(lists[2]) > 0
+    c = _ctx(lib, s, order=3, selection=1, want_gradient=0)
+    r = c.run()
+    ro = F.fmo(s, params, 0.0, order=3, lists=lists)
+    assert r["solves_trimer"] == len(lists[2])
+    _compare_fmo(c, ro, len(lists[0]))
+    assert abs(r["e_total"] - ro.E) < 1e-8
+
+
+def test_multimolecule_fragments(lib, params, c1):
+    """Two waters per fragment (fragments need not be contiguous in the atom
+    order): FMO2 energy and gradient, FMO3 energy, against the oracle."""
+    _say("two waters per fragment")
+    s = c1.grouped(2)
+    assert s.n_frag == 4
+    c = _ctx(lib, s, want_gradient=1)
+    r = c.run()
+    ro = F.fmo(s, params, 4 * A2B)
+    _compare_fmo(c, ro, len(ro.lists[0]))
+    assert abs(r["e_total"] - ro.E) < 1e-8
+    go, _ = F.fmo2_gradient(s, params, ro)
+    assert np.max(np.abs(c.gradient() - go)) < 1e-7
+    c.set_options(order=3, want_gradient=0)
+    r3 = c.run()
+    ro3 = F.fmo(s, params, 4 * A2B, order=3)
+    assert abs(r3["e_total"] - ro3.E) < 1e-8

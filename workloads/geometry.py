@@ -69,6 +69,37 @@ class System:
             frag_charge=self.frag_charge[frags].copy(), meta=dict(self.meta),
             bonds=np.array(kept, dtype=np.int32).reshape(-1, 2))
 
+    def grouped(self, k):
+        """The same atoms with k molecules (fragments of this system) per
+        fragment: the lowest-numbered free molecule takes its k - 1 nearest
+        free molecules by centroid distance (ties by number); the last
+        fragment may hold fewer.  Fragment charges add up.  Systems with cut
+        covalent bonds are not regrouped."""
+        if k < 1:
+            raise ValueError("k must be positive")
+        if len(self.bonds):
+            raise ValueError("regrouping a system with cut bonds")
+        F = self.n_frag
+        cen = np.array([self.xyz[self.frag == I].mean(axis=0) for I in range(F)])
+        free = np.ones(F, dtype=bool)
+        new_of = np.empty(F, dtype=np.int64)
+        charges = []
+        g = 0
+        for I in range(F):
+            if not free[I]:
+                continue
+            cand = np.where(free)[0]
+            d2 = ((cen[cand] - cen[I]) ** 2).sum(axis=1)
+            order = np.lexsort((cand, d2))[:k]
+            members = cand[order]
+            free[members] = False
+            new_of[members] = g
+            charges.append(int(self.frag_charge[members].sum()))
+            g += 1
+        return System(name=f"{self.name}/{k}", Z=self.Z.copy(), xyz=self.xyz.copy(),
+                      frag=new_of[self.frag].astype(np.int32),
+                      frag_charge=np.array(charges, dtype=np.int32), meta=dict(self.meta))
+
 
 # --------------------------------------------------------------------------
 # small geometric helpers

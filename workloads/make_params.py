@@ -82,16 +82,17 @@ def fit_sto(n, l, nprim=NPRIM):
     return a.tolist(), dn.tolist(), overlap
 
 
-# anchors: level (eV), Slater exponent, reference occupation per shell
+# anchors: level (eV), Slater exponent, reference occupation per shell;
+# rvdw: Bondi van der Waals radius (Angstrom)
 ELEMENTS = {
     "H": dict(Z=1, shells=[(1, 0, 1.20, -13.6, 1.0), (2, 0, 0.75, -3.0, 0.0)],
-              EN=2.20, rcov=0.32, eta=0.47, Gamma=0.08, zeff=1.0, arep=2.2),
+              EN=2.20, rcov=0.32, eta=0.47, Gamma=0.08, zeff=1.0, arep=2.2, rvdw=1.20),
     "C": dict(Z=6, shells=[(2, 0, 1.625, -21.4, 2.0), (2, 1, 1.625, -11.4, 2.0)],
-              EN=2.55, rcov=0.75, eta=0.48, Gamma=0.05, zeff=4.0, arep=1.25),
+              EN=2.55, rcov=0.75, eta=0.48, Gamma=0.05, zeff=4.0, arep=1.25, rvdw=1.70),
     "N": dict(Z=7, shells=[(2, 0, 1.95, -26.0, 2.0), (2, 1, 1.95, -13.4, 3.0)],
-              EN=3.04, rcov=0.71, eta=0.46, Gamma=0.06, zeff=5.0, arep=1.35),
+              EN=3.04, rcov=0.71, eta=0.46, Gamma=0.06, zeff=5.0, arep=1.35, rvdw=1.55),
     "O": dict(Z=8, shells=[(2, 0, 2.275, -32.3, 2.0), (2, 1, 2.275, -14.8, 4.0)],
-              EN=3.44, rcov=0.63, eta=0.45, Gamma=0.07, zeff=6.0, arep=1.6),
+              EN=3.44, rcov=0.63, eta=0.45, Gamma=0.07, zeff=6.0, arep=1.6, rvdw=1.52),
 }
 
 
@@ -120,6 +121,9 @@ def make(seed=0):
             Z=e["Z"], shells=shells, EN=jit(e["EN"]), rcov_angstrom=jit(e["rcov"]),
             eta=jit(e["eta"]), Gamma=jit(e["Gamma"]), zeff=jit(e["zeff"]),
             alpha_rep=jit(e["arep"]),
+            # van der Waals radius of the fragment-pair selection rule: Bondi's
+            # values as data, not drawn (no random number is consumed)
+            rvdw_angstrom=e["rvdw"],
         )
 
     return dict(
