@@ -12,8 +12,9 @@
  *     trimer_embedding): the many-body energy;
  *   - section "FMO-xTB" (eq. v_esp_matrix and the monomer self-consistency
  *     it describes): the electrostatic embedding;
- *   - section "Analytic energy gradients" (eqs. grad_decomp .. response_grad_full):
- *     the FMO2 gradient including the response of the embedding.
+ *   - section "Analytic energy gradients" (eqs. grad_decomp .. response_grad_full)
+ *     and its subsection "Extension to FMO3": the FMO2 and FMO3 gradients
+ *     including the response of the embedding.
  *
  * Conventions shared by every call
  *   - Units: bohr for lengths, Hartree for energies, Eh/bohr for gradients.
@@ -94,7 +95,8 @@ typedef struct fx_options {
   double macro_tol;       /* monomer loop: max change of any monomer charge */
   int32_t max_iter;       /* SCC iterations per fragment solve */
   int32_t max_macro;      /* monomer self-consistency sweeps */
-  int32_t want_gradient;  /* compute the FMO2 gradient (order 2 only) */
+  int32_t want_gradient;  /* compute the FMO2 or FMO3 analytic gradient
+                             (molecular fragments; not with cut bonds) */
   int32_t want_response;  /* include the embedding response term */
   int32_t selection;      /* FX_SELECT_CUTOFF (default) or FX_SELECT_VDW */
   double vdw_dimer;       /* FX_SELECT_VDW: a pair is an SCC dimer when some
@@ -210,7 +212,8 @@ int fx_set_guess(fx_ctx* ctx, const double* dq_shell);
 
 /* Run the FMO calculation: lists (if not built), supersystem CN, the monomer
  * self-consistency loop, dimer (and trimer) SCC solves in the converged
- * embedding, ES-DIM pairs, the energy and, if requested, the FMO2 gradient.
+ * embedding, ES-DIM pairs, the energy and, if requested, the FMO2 or FMO3
+ * gradient.
  * Blocks until done.  Returns FX_E_NOCONV (results still readable) when a
  * solve hit max_iter or the monomer loop hit max_macro. */
 int fx_run(fx_ctx* ctx, fx_result* out);
@@ -225,7 +228,7 @@ int fx_run(fx_ctx* ctx, fx_result* out);
 int fx_get_energies(fx_ctx* ctx, double* E_mono, double* dE_scc, double* dE_esd, double* dE_tri);
 /* Converged monomer shell charges dq_shell[n_shells]. */
 int fx_get_charges(fx_ctx* ctx, double* dq_shell);
-/* FMO2 gradient grad[3*n_atoms] (Eh/bohr) of the last run.
+/* FMO2 / FMO3 gradient grad[3*n_atoms] (Eh/bohr) of the last run.
  * Errors: FX_E_STATE if the last run did not compute it. */
 int fx_get_gradient(fx_ctx* ctx, double* grad);
 

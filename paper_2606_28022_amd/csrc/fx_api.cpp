@@ -1422,11 +1422,11 @@ void Ctx::run(fx_result* out) {
     if (failed) all_conv = false;
     res.solves_trimer = ntri;
     res.iters_trimer = itt;
-    DevBuf<double> ddq, dEV, dEX;
-    ddq.alloc(tb_.tot_sh);
+    DevBuf<double> dEV, dEX;
+    ddq_tri.alloc(tb_.tot_sh);
     dEV.alloc(ntri);
     dEX.alloc(ntri);
-    hipLaunchKernelGGL(k_cluster_terms, dim3(tb_.nsys), dim3(256), 0, stream, dtb, d_q.p, e_mono.p, ddq.p, dEV.p,
+    hipLaunchKernelGGL(k_cluster_terms, dim3(tb_.nsys), dim3(256), 0, stream, dtb, d_q.p, e_mono.p, ddq_tri.p, dEV.p,
                        dEX.p);
     if (tb_.has_healed)
       hipLaunchKernelGGL(k_cluster_healed, dim3(tb_.nsys), dim3(128), 0, stream, dev_system(), dtb, d_phi.p, d_q.p,
@@ -1498,7 +1498,7 @@ void Ctx::run(fx_result* out) {
   res.converged = all_conv ? 1 : 0;
   has_result = true;
   has_grad = false;
-  if (opt.want_gradient && opt.order == 2) {
+  if (opt.want_gradient) {
     gradient();
     has_grad = true;
   }

@@ -1,4 +1,4 @@
-// Host driver of the FMO2 analytic gradient: explicit fragment terms, the
+// Host driver of the FMO2 and FMO3 analytic gradients: explicit fragment terms, the
 // inter-fragment kernel derivatives, the response of the self-consistent
 // embedding and the CN chain (section "Analytic energy gradients").  The
 // host only builds index tables and launches kernels; per-atom sums are
@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <unordered_map>
 #include <vector>
 
 #include "fx_host.hpp"
@@ -40,34 +41,88 @@ void explicit_terms(Ctx& c, Batch& b, const double* wsys, DevBuf<double>& g_sys,
   Ctx::check(hipGetLastError(), "explicit gradient terms");
 }
 
+// CSR map global shell -> local shell slots of a cluster batch, in batch order
+void cluster_csr(Ctx& c, Batch& b, DevBuf<int>& ptr, DevBuf<int>& ent) {
+  std::vector<int> cnt(c.Nsh + 1, 0), e;
+  std::vector<std::vector<int>> rows(c.Nsh);
+  std::vector<int> shg;
+  b.d_sh_global.download(shg, c.stream);
+  c.sync();
+  for (int k = 0; k < (int)shg.size(); ++k) rows[shg[k]].push_back(k);
+  for (int s = 0; s < c.Nsh; ++s) {
+    cnt[s + 1] = cnt[s] + (int)rows[s].size();
+    for (int x : rows[s]) e.push_back(x);
+  }
+  ptr.upload(cnt);
+  ent.upload(e.empty() ? std::vector<int>{0} : e);
+}
+
 }  // namespace
 
 void Ctx::gradient() {
   const double t0 = now_ms();
   DevSystem ds = dev_system();
   const long long nscc = (long long)scc_pairs.size() / 2;
-  // ---- monomer weights c_I = 1 - (number of SCC dimers containing I)
-  std::vector<double> cw(F, 1.0);
-  for (long long k = 0; k < nscc; ++k) {
-    cw[scc_pairs[2 * k]] -= 1.0;
-    cw[scc_pairs[2 * k + 1]] -= 1.0;
+  const long long ntri = opt.order >= 3 ? (long long)trimers.size() / 3 : 0;
+  // ---- weights of the energy identity: monomers c_I, SCC dimers
+  //      s_IJ = 1 - n_T(IJ), trimers 1; an ES-DIM sub-pair of a trimer
+  //      (bit of tmask) takes one unit of its dq gamma dq term away
+  std::vector<double> cw(F, 1.0), sw(std::max(1LL, nscc), 1.0);
+  std::vector<int> tmask(std::max(1LL, ntri), 0);
+  {
+    std::unordered_map<long long, long long> sidx;
+    for (long long k = 0; k < nscc; ++k) {
+      const int I = scc_pairs[2 * k], J = scc_pairs[2 * k + 1];
+      sidx[(long long)I * F + J] = k;
+      cw[I] -= 1.0;
+      cw[J] -= 1.0;
+    }
+    for (long long t = 0; t < ntri; ++t) {
+      const int f[3] = {trimers[3 * t], trimers[3 * t + 1], trimers[3 * t + 2]};
+      const int sub[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+      int nscc_of[3] = {0, 0, 0};
+      for (int b = 0; b < 3; ++b) {
+        const int a = sub[b][0], c = sub[b][1];
+        auto it = sidx.find((long long)f[a] * F + f[c]);
+        if (it != sidx.end()) {
+          sw[it->second] -= 1.0;
+          ++nscc_of[a];
+          ++nscc_of[c];
+        } else {
+          tmask[t] |= 1 << b;
+        }
+      }
+      for (int a = 0; a < 3; ++a) cw[f[a]] += nscc_of[a] - 1.0;
+    }
   }
-  DevBuf<double> d_cw;
+  DevBuf<double> d_cw, d_sw;
+  DevBuf<int> d_tmask;
   d_cw.upload(cw);
+  d_sw.upload(sw);
+  d_tmask.upload(tmask);
 
-  // ---- explicit fragment terms
-  DevBuf<double> gm, Fm_, gd, Fd;
+  // ---- explicit fragment terms and the per-cluster corrections of the
+  //      all-pairs force pass
+  DevBuf<double> gm, Fm_, gd, Fd, gt, Ft;
   explicit_terms(*this, mb, d_cw.p, gm, Fm_);
   if (nscc > 0) {
-    explicit_terms(*this, db_, nullptr, gd, Fd);
+    explicit_terms(*this, db_, d_sw.p, gd, Fd);
     DevBatch ddb = db_.dev();
-    hipLaunchKernelGGL(k_grad_pair_corr, dim3(db_.nsys), dim3(128), 0, stream, ds, ddb, d_q.p, ddq_scc.p, gd.p);
+    hipLaunchKernelGGL(k_grad_pair_corr, dim3(db_.nsys), dim3(128), 0, stream, ds, ddb, d_q.p, ddq_scc.p, d_sw.p,
+                       (const int*)nullptr, gd.p);
     check(hipGetLastError(), "k_grad_pair_corr");
   }
+  if (ntri > 0) {
+    explicit_terms(*this, tb_, nullptr, gt, Ft);
+    DevBatch dtb = tb_.dev();
+    hipLaunchKernelGGL(k_grad_pair_corr, dim3(tb_.nsys), dim3(128), 0, stream, ds, dtb, d_q.p, ddq_tri.p,
+                       (const double*)nullptr, d_tmask.p, gt.p);
+    check(hipGetLastError(), "k_grad_pair_corr (trimers)");
+  }
 
-  // ---- accumulated dimer charge transfer qbar and the Lagrangian potential v
-  //      v = field_excl(qbar) - sum over SCC dimers containing K of their
-  //      cross-fragment potential of ddq
+  // ---- accumulated charge transfer qbar = sum_SCC s_IJ ddq^IJ + sum_T ddq^T
+  //      and the Lagrangian potential v = field_excl(qbar) - sum over the
+  //      clusters containing K of their weighted cross-fragment potential
   DevBuf<double> qbar, v, u, a;
   qbar.alloc(Nsh);
   v.alloc(Nsh);
@@ -75,39 +130,43 @@ void Ctx::gradient() {
   a.alloc(Nsh);
   check(hipMemsetAsync(qbar.p, 0, sizeof(double) * Nsh, stream), "memset");
   check(hipMemsetAsync(u.p, 0, sizeof(double) * Nsh, stream), "memset");
-  DevBuf<int> csr_ptr, csr_ent;
+  check(hipMemsetAsync(v.p, 0, sizeof(double) * Nsh, stream), "memset");
+  const unsigned gS = (unsigned)((Nsh + 255) / 256);
+  DevBuf<int> dptr, dent, tptr, tent;
+  DevBuf<double> ddq_w, vc_d, vc_t, fq;
   if (nscc > 0) {
-    // CSR: global shell -> local shell slots of the dimer batch, dimer order
-    std::vector<int> cnt(Nsh + 1, 0), ent;
-    std::vector<std::vector<int>> rows(Nsh);
-    std::vector<int> shg;
-    db_.d_sh_global.download(shg, stream);
-    sync();
-    for (int k = 0; k < (int)shg.size(); ++k) rows[shg[k]].push_back(k);
-    for (int s = 0; s < Nsh; ++s) {
-      cnt[s + 1] = cnt[s] + (int)rows[s].size();
-      for (int e : rows[s]) ent.push_back(e);
-    }
-    csr_ptr.upload(cnt);
-    csr_ent.upload(ent.empty() ? std::vector<int>{0} : ent);
-    const unsigned g = (unsigned)((Nsh + 255) / 256);
-    hipLaunchKernelGGL(k_gather_csr, dim3(g), dim3(256), 0, stream, Nsh, csr_ptr.p, csr_ent.p, ddq_scc.p,
-                       (const double*)nullptr, 1.0, qbar.p);
-    DevBuf<double> vc, fq;
-    vc.alloc(db_.tot_sh);
-    fq.alloc(Nsh);
+    cluster_csr(*this, db_, dptr, dent);
     DevBatch ddb = db_.dev();
-    hipLaunchKernelGGL(k_cluster_cross, dim3(db_.nsys), dim3(128), 0, stream, ds, ddb, ddq_scc.p, vc.p);
+    ddq_w.alloc(db_.tot_sh);
+    vc_d.alloc(db_.tot_sh);
+    hipLaunchKernelGGL(k_scale_cluster, dim3(db_.nsys), dim3(64), 0, stream, ddb, d_sw.p, ddq_scc.p, ddq_w.p);
+    hipLaunchKernelGGL(k_gather_csr, dim3(gS), dim3(256), 0, stream, Nsh, dptr.p, dent.p, ddq_w.p,
+                       (const double*)nullptr, 1.0, qbar.p);
+    hipLaunchKernelGGL(k_cluster_cross, dim3(db_.nsys), dim3(128), 0, stream, ds, ddb, ddq_w.p, vc_d.p);
+  }
+  if (ntri > 0) {
+    cluster_csr(*this, tb_, tptr, tent);
+    DevBatch dtb = tb_.dev();
+    vc_t.alloc(tb_.tot_sh);
+    hipLaunchKernelGGL(k_gather_csr, dim3(gS), dim3(256), 0, stream, Nsh, tptr.p, tent.p, ddq_tri.p,
+                       (const double*)qbar.p, 1.0, qbar.p);
+    hipLaunchKernelGGL(k_cluster_cross, dim3(tb_.nsys), dim3(128), 0, stream, ds, dtb, ddq_tri.p, vc_t.p);
+  }
+  if (nscc > 0 || ntri > 0) {
+    fq.alloc(Nsh);
     field(qbar.p, fq.p);
-    hipLaunchKernelGGL(k_gather_csr, dim3(g), dim3(256), 0, stream, Nsh, csr_ptr.p, csr_ent.p, vc.p, fq.p, -1.0,
-                       v.p);
+    check(hipMemcpyAsync(v.p, fq.p, sizeof(double) * Nsh, hipMemcpyDeviceToDevice, stream), "copy");
+    if (nscc > 0)
+      hipLaunchKernelGGL(k_gather_csr, dim3(gS), dim3(256), 0, stream, Nsh, dptr.p, dent.p, vc_d.p,
+                         (const double*)v.p, -1.0, v.p);
+    if (ntri > 0)
+      hipLaunchKernelGGL(k_gather_csr, dim3(gS), dim3(256), 0, stream, Nsh, tptr.p, tent.p, vc_t.p,
+                         (const double*)v.p, -1.0, v.p);
     check(hipGetLastError(), "lagrangian potential");
-  } else {
-    check(hipMemsetAsync(v.p, 0, sizeof(double) * Nsh, stream), "memset");
   }
 
   // ---- response of the monomer charges (adjoint of the self-consistency)
-  if (opt.want_response && nscc > 0) {
+  if (opt.want_response && (nscc > 0 || ntri > 0)) {
     const double tr = now_ms();
     Batch& b = mb;
     DevBatch dmb = b.dev();
@@ -247,15 +306,17 @@ void Ctx::gradient() {
       const SysDesc& d = mb.h_desc[k];
       for (int a = 0; a < d.nat; ++a) rows[frag_atoms[frag_off[d.frag[0]] + a]].push_back({0, d.atom_off + a});
     }
-    if (nscc > 0) {
+    auto add_batch = [&](Batch& b, int id) {
       std::vector<int> at;
-      db_.d_atoms.download(at, stream);
+      b.d_atoms.download(at, stream);
       sync();
-      for (int k = 0; k < db_.nsys; ++k) {
-        const SysDesc& d = db_.h_desc[k];
-        for (int a = 0; a < d.nat; ++a) rows[at[d.atom_off + a]].push_back({1, d.atom_off + a});
+      for (int k = 0; k < b.nsys; ++k) {
+        const SysDesc& d = b.h_desc[k];
+        for (int a = 0; a < d.nat; ++a) rows[at[d.atom_off + a]].push_back({id, d.atom_off + a});
       }
-    }
+    };
+    if (nscc > 0) add_batch(db_, 1);
+    if (ntri > 0) add_batch(tb_, 2);
     for (int A = 0; A < N; ++A) {
       rowptr[A + 1] = rowptr[A] + (int)rows[A].size();
       for (auto& e : rows[A]) {
@@ -269,8 +330,8 @@ void Ctx::gradient() {
   d_rp.upload(rowptr);
   d_eb.upload(ent_b);
   d_eo.upload(ent_o);
-  std::vector<const double*> gb = {gm.p, nscc > 0 ? gd.p : gm.p};
-  std::vector<const double*> fb = {Fm_.p, nscc > 0 ? Fd.p : Fm_.p};
+  std::vector<const double*> gb = {gm.p, nscc > 0 ? gd.p : gm.p, ntri > 0 ? gt.p : gm.p};
+  std::vector<const double*> fb = {Fm_.p, nscc > 0 ? Fd.p : Fm_.p, ntri > 0 ? Ft.p : Fm_.p};
   DevBuf<const double*> d_gb, d_fb;
   d_gb.upload(gb);
   d_fb.upload(fb);

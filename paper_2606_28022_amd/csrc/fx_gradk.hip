@@ -1,9 +1,14 @@
-// Kernels of the FMO2 analytic gradient (section "Analytic energy gradients").
+// Kernels of the FMO2 and FMO3 analytic gradients (section "Analytic energy
+// gradients" and its FMO3 extension).
 //
 // The gradient is assembled from the energy identity
-//   E = sum_I c_I E^emb_I + sum_SCC E^emb_IJ - sum_ESD dq^I gamma dq^J,
-//   c_I = 1 - (number of SCC dimers containing I),
-// whose fragment terms are stationary in their own densities:
+//   E = sum_I c_I E^emb_I + sum_SCC s_IJ E^emb_IJ + sum_T E^emb_IJK
+//       - sum_ESD (1 - n_T(IJ)) dq^I gamma dq^J,
+//   n_T(IJ) = trimers containing I and J, s_IJ = 1 - n_T(IJ),
+//   c_I = 1 - (SCC pairs containing I) + sum over trimers T containing I of
+//         (SCC sub-pairs of T containing I - 1)
+// (FMO2: no trimers, s = 1), whose fragment terms are stationary in their
+// own densities:
 //  * per fragment system: the single-system gradient of eq. xtb_grad with the
 //    W matrix of eq. W_matrix (sigma containing the embedding potential), the
 //    H0 derivative split of eq. H0_deriv and the CN sensitivity of
@@ -11,7 +16,7 @@
 //  * inter-fragment kernel derivatives: ES-DIM (eq. esd_grad), charge-transfer
 //    embedding (eq. ctij) and the response charges (eq. ZxG_inter) in one
 //    N-body force pass over all cross-fragment shell pairs (k_force_inter)
-//    with a per-SCC-dimer correction (k_grad_pair_corr);
+//    with a per-cluster correction (k_grad_pair_corr);
 //  * the CN chain of eq. cn_grad over all atoms (k_cn_grad);
 //  * the response: the Lagrangian potential of eq. esp_lagrangian, the
 //    fragment charge response built from the transition charges of
@@ -246,20 +251,36 @@ __global__ void k_grad_contract(DevSystem sys, DevBatch bt, const int* list, con
 // For an SCC dimer (I, K): remove the cross-fragment pairs of the all-pairs
 // inter-fragment force, c_st = q_s q_t + ddq_s q_t + q_s ddq_t (added to the
 // dimer's atom arrays).
-__global__ void k_grad_pair_corr(DevSystem sys, DevBatch bt, const double* qmono, const double* ddq, double* g_out) {
+// Correction of the all-pairs force pass inside each cluster X (an SCC dimer
+// or a trimer): for every atom pair of different fragments of X it removes
+//   w_X (ddq^X_s q_t + q_s ddq^X_t)   (the charge transfer acts only on
+//                                      fragments outside X)
+// and, for the sub-pairs selected by qqmask (bit 0: fragments 0,1; bit 1:
+// 0,2; bit 2: 1,2; null = every sub-pair), q_s q_t (an SCC pair has no
+// ES-DIM term; an ES-DIM sub-pair inside a trimer carries 1 - n_T of it).
+// w null: w_X = 1.
+__global__ void k_grad_pair_corr(DevSystem sys, DevBatch bt, const double* qmono, const double* ddq,
+                                 const double* wct, const int* qqmask, double* g_out) {
   const int si = blockIdx.x;
   const SysDesc d = bt.desc[si];
   const int nat = d.nat;
   const int* atoms = bt.sys_atoms + d.atom_off;
   const int* ash = bt.sys_atom_sh0 + d.atom_off;
+  const double wx = wct ? wct[si] : 1.0;
+  const int mask = qqmask ? qqmask[si] : 7;
   for (int a = threadIdx.x; a < nat; a += blockDim.x) {
     const int A = atoms[a];
     const DevElem& ea = sys.elems[sys.elem[A]];
     const int fa = sys.frag[A];
+    const int pa = fa == d.frag[0] ? 0 : (fa == d.frag[1] ? 1 : 2);
     double g[3] = {0.0, 0.0, 0.0};
     for (int b = 0; b < nat; ++b) {
       const int B = atoms[b];
-      if (sys.frag[B] == fa) continue;
+      const int fb = sys.frag[B];
+      if (fb == fa) continue;
+      const int pb = fb == d.frag[0] ? 0 : (fb == d.frag[1] ? 1 : 2);
+      const int sub = pa + pb - 1;  // (0,1) -> 0, (0,2) -> 1, (1,2) -> 2
+      const double wqq = (mask >> sub) & 1 ? 1.0 : 0.0;
       const DevElem& eb = sys.elems[sys.elem[B]];
       double Rv[3] = {sys.xyz[3 * A] - sys.xyz[3 * B], sys.xyz[3 * A + 1] - sys.xyz[3 * B + 1],
                       sys.xyz[3 * A + 2] - sys.xyz[3 * B + 2]};
@@ -268,7 +289,7 @@ __global__ void k_grad_pair_corr(DevSystem sys, DevBatch bt, const double* qmono
         for (int sb = 0; sb < eb.nsh; ++sb) {
           int ls = ash[a] + sa, lt = ash[b] + sb;
           double qs = qmono[sys.atom_sh0[A] + sa], qt = qmono[sys.atom_sh0[B] + sb];
-          double c = qs * qt + ddq[d.sh_off + ls] * qt + qs * ddq[d.sh_off + lt];
+          double c = wqq * qs * qt + wx * (ddq[d.sh_off + ls] * qt + qs * ddq[d.sh_off + lt]);
           double dg;
           gamma_and_deriv(sys.g, R, ea.eta[sa], eb.eta[sb], &dg);
           for (int k = 0; k < 3; ++k) g[k] -= c * dg * Rv[k] / R;
@@ -277,6 +298,14 @@ __global__ void k_grad_pair_corr(DevSystem sys, DevBatch bt, const double* qmono
     long long o = (long long)d.atom_off + a;
     for (int k = 0; k < 3; ++k) g_out[3 * o + k] += g[k];
   }
+}
+
+// dst = w_X src on the shells of every system X of a batch
+__global__ void k_scale_cluster(DevBatch bt, const double* w, const double* src, double* dst) {
+  const int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const double wx = w[si];
+  for (int s = threadIdx.x; s < d.nsh; s += blockDim.x) dst[d.sh_off + s] = wx * src[d.sh_off + s];
 }
 
 // All cross-fragment shell pairs: force on atom A from

@@ -208,7 +208,7 @@ struct Ctx {
 
   // batches and results
   Batch mb, db_, tb_;
-  DevBuf<double> e_mono, dE_scc, dEV_scc, dE_esd, dE_tri, ddq_scc;
+  DevBuf<double> e_mono, dE_scc, dEV_scc, dE_esd, dE_tri, ddq_scc, ddq_tri;
   std::vector<double> trimer_dEIJK;
   fx_result res{};
   // monomer susceptibility blocks (shell-summed transition charges Q and

@@ -142,7 +142,9 @@ __global__ void k_axpy(long long n, const double* x, double a, const double* y, 
 __global__ void k_grad_contract(DevSystem sys, DevBatch bt, const int* list, const double* DHp, const double* DSp,
                                 const double* gx, const double* gy, const double* wsys, int with_rep, int accumulate,
                                 double* g_out, double* F_out, double* scratch);
-__global__ void k_grad_pair_corr(DevSystem sys, DevBatch bt, const double* qmono, const double* ddq, double* g_out);
+__global__ void k_grad_pair_corr(DevSystem sys, DevBatch bt, const double* qmono, const double* ddq,
+                                 const double* wct, const int* qqmask, double* g_out);
+__global__ void k_scale_cluster(DevBatch bt, const double* w, const double* src, double* dst);
 __global__ void k_force_inter(DevSystem sys, const double* q, const double* av, int nchunk, double* part);
 __global__ void k_force_reduce(int N, int nchunk, const double* part, double* out);
 __global__ void k_cn_grad(DevSystem sys, const double* Ftot, double* g);

@@ -1546,15 +1546,35 @@ __global__ void __launch_bounds__(1024)
     for (int rd = 0; rd < nb2 - 1; ++rd) {
       __syncthreads();
       const double2* lr = ls + nb2 + (long long)rd * m;
-      for (int qd = wave; qd < nq; qd += NW) {
-        const double2 w0 = lr[4 * qd], w1 = lr[4 * qd + 1], w2 = lr[4 * qd + 2], w3 = lr[4 * qd + 3];
-        if (w0.y == 0.0 && w1.y == 0.0 && w2.y == 0.0 && w3.y == 0.0) continue;
-        const int X = rr_index(qd, rd, nb2), Y = rr_index(nb2 - 1 - qd, rd, nb2);
-        // rows x1 x2 (block X) and y1 y2 (block Y); padded rows stay zero
-        // (their rotations are the identity)
-        double* px = tile + (2 * X) * 64 + lane;
-        double* py = tile + (2 * Y) * 64 + lane;
-        double x1 = px[0], x2 = px[64], y1 = py[0], y2 = py[64];
+      int qd = wave;
+      if (qd >= nq) continue;
+      // rows x1 x2 (block X) and y1 y2 (block Y) of the wave's quartets;
+      // padded rows stay zero (their rotations are the identity, applied
+      // exactly).  The next quartet's parameters and rows are loaded before
+      // the current one is rotated and stored (quartets of a round are
+      // disjoint), so the load latency overlaps the arithmetic.
+      double2 w0 = lr[4 * qd], w1 = lr[4 * qd + 1], w2 = lr[4 * qd + 2], w3 = lr[4 * qd + 3];
+      double* px = tile + (2 * rr_index(qd, rd, nb2)) * 64 + lane;
+      double* py = tile + (2 * rr_index(nb2 - 1 - qd, rd, nb2)) * 64 + lane;
+      double x1 = px[0], x2 = px[64], y1 = py[0], y2 = py[64];
+      for (;;) {
+        const int qn = qd + NW;
+        const bool more = qn < nq;
+        double2 v0, v1, v2, v3;
+        double *nx = px, *ny = py;
+        double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;
+        if (more) {
+          v0 = lr[4 * qn];
+          v1 = lr[4 * qn + 1];
+          v2 = lr[4 * qn + 2];
+          v3 = lr[4 * qn + 3];
+          nx = tile + (2 * rr_index(qn, rd, nb2)) * 64 + lane;
+          ny = tile + (2 * rr_index(nb2 - 1 - qn, rd, nb2)) * 64 + lane;
+          a1 = nx[0];
+          a2 = nx[64];
+          b1 = ny[0];
+          b2 = ny[64];
+        }
         jq_apply2(x1, y1, w0);
         jq_apply2(x2, y2, w1);
         jq_apply2(x1, y2, w2);
@@ -1563,6 +1583,18 @@ __global__ void __launch_bounds__(1024)
         px[64] = x2;
         py[0] = y1;
         py[64] = y2;
+        if (!more) break;
+        w0 = v0;
+        w1 = v1;
+        w2 = v2;
+        w3 = v3;
+        px = nx;
+        py = ny;
+        x1 = a1;
+        x2 = a2;
+        y1 = b1;
+        y2 = b2;
+        qd = qn;
       }
     }
   }
