@@ -51,8 +51,8 @@ def make(name):
         out["E_fmo2"] = r.E_fmo2
     if len(s.bonds):
         out["bonds"] = s.bonds.tolist()
-    if order == 2 and not len(s.bonds):
-        g, _ = F.fmo2_gradient(s, p, r)
+    if not len(s.bonds):
+        g, _ = F.fmo_gradient(s, p, r)
         out["grad"] = g.tolist()
     out["oracle_seconds"] = time.time() - t
     with open(os.path.join(HERE, f"{name}.json"), "w") as f:

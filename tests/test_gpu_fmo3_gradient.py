@@ -84,3 +84,26 @@ def test_fmo3_gradient_invariances_anthracene(lib):
     assert np.max(np.abs(np.cross(s.xyz, g).sum(0))) < 1e-7
     c.run()
     assert np.array_equal(c.gradient(), g)
+
+
+def test_fmo3_anthracene_golden(lib):
+    """Five anthracene molecules (n = 76 / 152 / 228 AOs: FP32 working
+    matrices, matrix-core products, the corrected FP32 start basis of the
+    trimers) against stored oracle values (tests/golden/anthracene5_fmo3.json,
+    written by tests/golden/make_golden.py): energies 1e-8 Eh, gradient
+    1e-7 Eh/bohr."""
+    import json
+    import os
+    _say("FMO3 anthracene 5 molecules vs stored oracle values")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "anthracene5_fmo3.json")
+    with open(path) as f:
+        ref = json.load(f)
+    s = w.anthracene_crystal(reps=(2, 2, 1)).subset(list(range(5)))
+    r, g, c = _run(lib, s, cutoff_bohr=ref["cutoff_bohr"])
+    em, ds, de, dt = c.energies()
+    assert np.max(np.abs(em - np.array(ref["E_mono"]))) < 1e-8
+    assert np.max(np.abs(ds - np.array(ref["dE_scc"]))) < 1e-8
+    assert np.max(np.abs(de - np.array(ref["dE_esd"]))) < 1e-8
+    assert np.max(np.abs(dt - np.array(ref["dE_tri"]))) < 1e-8
+    assert abs(r["e_total"] - ref["E"]) < 1e-8 * s.n_frag
+    assert np.max(np.abs(g - np.array(ref["grad"]))) < 1e-7, np.max(np.abs(g - np.array(ref["grad"])))
