@@ -8,7 +8,7 @@ ES-DIM pairs, the energy and the FMO2 gradient including the embedding
 response.  The system is uploaded before timing (inputs resident in HBM).
 
 Prints one JSON line.  Usage:
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain] [--no-guess] [--no-mixed] [--no-warm]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain] [--no-guess] [--no-mixed] [--no-warm] [--no-fmo3]
 """
 
 import argparse
@@ -150,6 +150,36 @@ def learned_guess_stream(n_droplets=8):
             "seconds": {"superposition": t0, "learned": t1}}
 
 
+def fmo3_anthracene():
+    """FMO3 energy + analytic gradient of the anthracene 8x8x4 crystal (512
+    molecules, 12,288 atoms): one warm-up run, one timed run."""
+    import numpy as np
+    import torch
+    import workloads as w
+    from paper_2606_28022_amd import FmoXtb
+    s = w.anthracene_crystal()
+    c = FmoXtb(device=0, stream=C_stream(torch.cuda.current_stream()))
+    c.set_system(s.Z, s.xyz, s.frag, s.frag_charge)
+    c.set_options(order=3, want_gradient=1, want_response=1)
+    c.run()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = c.run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    g = c.gradient()
+    log(f"FMO3 anthracene: {dt:.3f} s, {r['solves_trimer']} trimers")
+    c.close()
+    return {"workload": "anthracene 8x8x4 crystal (12,288 atoms, 512 molecules), FMO3 energy + analytic "
+                        "gradient with response, fp64",
+            "s_per_step": dt, "energy_Eh": r["e_total"],
+            "solves": {"monomer": r["solves_mono"], "dimer": r["solves_dimer"], "trimer": r["solves_trimer"]},
+            "scc_solves_per_s": (r["solves_mono"] + r["solves_dimer"] + r["solves_trimer"]) / dt,
+            "phases_ms": {k: r[k] for k in ("ms_monomer", "ms_dimer", "ms_trimer", "ms_gradient")},
+            "net_force": float(np.abs(g.sum(0)).max()),
+            "net_torque": float(np.abs(np.cross(s.xyz, g).sum(0)).max())}
+
+
 def warm_step(c, s, r_prev, sec_cold):
     """One MD-like step: every atom moved 0.001 Angstrom in a seeded random
     direction, the SCC started from the previous step's converged monomer
@@ -200,6 +230,7 @@ def main():
     ap.add_argument("--no-guess", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-warm", action="store_true")
+    ap.add_argument("--no-fmo3", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -278,6 +309,8 @@ def main():
     }
     if not args.no_warm:
         out["warm_start"] = warm_step(c, s, r, sec)
+    if not args.no_fmo3:
+        out["fmo3"] = fmo3_anthracene()
     if not args.no_plain:
         sp, de, tb, tp = plain_vs_batched()
         out["batched_vs_plain"] = {"workload": "water droplet 1024 molecules, FMO2 energy, fp64",

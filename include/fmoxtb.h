@@ -210,6 +210,33 @@ int fx_get_lists(fx_ctx* ctx, int32_t* scc_pairs, int32_t* esd_pairs, int32_t* t
  * zero.  FX_E_STATE without a system, FX_E_INVALID for a non-finite value. */
 int fx_set_guess(fx_ctx* ctx, const double* dq_shell);
 
+/* New atomic positions xyz_bohr[3*n_atoms] (host, copied) for the system of
+ * the last fx_set_system: same atoms, fragments and cut bonds.  Lists and all
+ * geometry-dependent tables are rebuilt; the charges given with fx_set_guess
+ * are kept.  Errors as fx_set_system for the coordinates, FX_E_STATE without a
+ * system. */
+int fx_set_coordinates(fx_ctx* ctx, const double* xyz_bohr);
+
+/* Molecular dynamics with the analytic gradient (the paper's motivation for
+ * it, sections "Analytic energy gradients" and "Conclusion"): n_steps steps
+ * of velocity Verlet of length dt, in atomic units throughout (bohr, electron
+ * masses mass[n_atoms], time in hbar/Eh = 0.0241888 fs, velocities in
+ * bohr per hbar/Eh):
+ *   x <- x + v dt - grad E / (2 m) dt^2;  v <- v - (grad E_old + grad E_new) / (2 m) dt.
+ * xyz_bohr and vel [3*n_atoms] hold the start on entry and the end on return
+ * (host).  e_pot and e_kin [n_steps + 1] (host, may be NULL) receive the
+ * FMO energy and the kinetic energy at every step, the start included.  The
+ * energy and gradient use the current options (order, selection, precision,
+ * response; the gradient is always computed); the first step starts from the
+ * option's guess, every later step from the previous step's converged monomer
+ * charges.  Lists are rebuilt at every step.  On return the context holds the
+ * last geometry and its results (fx_get_energies, fx_get_gradient).  Errors:
+ * FX_E_INVALID (n_steps < 0, dt <= 0, masses <= 0, non-finite input),
+ * FX_E_STATE (no system), FX_E_UNSUPPORTED (cut bonds), FX_E_NOCONV (a step
+ * did not converge; xyz_bohr and vel are then unchanged). */
+int fx_md_verlet(fx_ctx* ctx, int32_t n_steps, double dt, const double* mass, double* xyz_bohr, double* vel,
+                 double* e_pot, double* e_kin);
+
 /* Run the FMO calculation: lists (if not built), supersystem CN, the monomer
  * self-consistency loop, dimer (and trimer) SCC solves in the converged
  * embedding, ES-DIM pairs, the energy and, if requested, the FMO2 or FMO3

@@ -67,7 +67,7 @@ class fx_result(C.Structure):
 EXPORTS = ["fx_params_load", "fx_params_free", "fx_ctx_create", "fx_ctx_destroy", "fx_last_error",
            "fx_default_options", "fx_set_options", "fx_set_system", "fx_build_lists", "fx_get_counts", "fx_get_lists",
            "fx_set_guess", "fx_run", "fx_get_energies", "fx_get_charges", "fx_get_gradient",
-           "fx_compute_cn", "fx_cluster_matrices", "fx_embedding_field", "fx_eigh_batched",
+           "fx_set_coordinates", "fx_md_verlet", "fx_compute_cn", "fx_cluster_matrices", "fx_embedding_field", "fx_eigh_batched",
            "fx_mlp_load", "fx_mlp_save", "fx_mlp_set_master", "fx_mlp_get_master", "fx_mlp_features",
            "fx_mlp_infer", "fx_mlp_grad", "fx_mlp_train_step"]
 
@@ -109,6 +109,8 @@ def load_library():
     L.fx_get_counts.argtypes = [P, C.POINTER(fx_counts)]
     L.fx_get_lists.argtypes = [P, pI32, pI32, pI32]
     L.fx_set_guess.argtypes = [P, pD]
+    L.fx_set_coordinates.argtypes = [P, pD]
+    L.fx_md_verlet.argtypes = [P, I32, C.c_double, pD, pD, pD, pD, pD]
     L.fx_run.argtypes = [P, C.POINTER(fx_result)]
     L.fx_get_energies.argtypes = [P, pD, pD, pD, pD]
     L.fx_get_charges.argtypes = [P, pD]
@@ -127,7 +129,8 @@ def load_library():
     L.fx_mlp_grad.argtypes = [P, P, P, I64, pD, pF]
     L.fx_mlp_train_step.argtypes = [P, P, P, I64, C.c_float, pD]
     for name in ["fx_params_load", "fx_ctx_create", "fx_default_options", "fx_set_options", "fx_set_system",
-                 "fx_build_lists", "fx_get_counts", "fx_get_lists", "fx_set_guess", "fx_run", "fx_get_energies",
+                 "fx_build_lists", "fx_get_counts", "fx_get_lists", "fx_set_guess", "fx_set_coordinates",
+                 "fx_md_verlet", "fx_run", "fx_get_energies",
                  "fx_get_charges", "fx_get_gradient", "fx_compute_cn", "fx_cluster_matrices",
                  "fx_embedding_field", "fx_eigh_batched", "fx_mlp_load", "fx_mlp_save", "fx_mlp_set_master",
                  "fx_mlp_get_master", "fx_mlp_features", "fx_mlp_infer", "fx_mlp_grad", "fx_mlp_train_step"]:
@@ -244,6 +247,28 @@ class FmoXtb:
         if dq.size != self.n_shells:
             raise ValueError(f"guess has {dq.size} shell charges, the system has {self.n_shells}")
         self._check(self.L.fx_set_guess(self.ctx, _ptr(dq, C.c_double)))
+
+    def set_coordinates(self, xyz_bohr):
+        xyz = _f64(xyz_bohr).reshape(-1)
+        if xyz.size != 3 * self.n_atoms:
+            raise ValueError("coordinates must have shape (n_atoms, 3)")
+        self._check(self.L.fx_set_coordinates(self.ctx, _ptr(xyz, C.c_double)))
+
+    def md_verlet(self, n_steps, dt_au, mass_au, xyz_bohr, vel_au):
+        """Velocity Verlet in atomic units (see fx_md_verlet).  Returns the
+        final positions and velocities (n_atoms, 3) and the potential and
+        kinetic energies of every step (n_steps + 1)."""
+        m = _f64(mass_au).reshape(-1)
+        x = _f64(xyz_bohr).reshape(-1).copy()
+        v = _f64(vel_au).reshape(-1).copy()
+        if m.size != self.n_atoms or x.size != 3 * self.n_atoms or v.size != 3 * self.n_atoms:
+            raise ValueError("masses (n_atoms), positions and velocities (n_atoms, 3) expected")
+        ep = np.zeros(n_steps + 1)
+        ek = np.zeros(n_steps + 1)
+        self._check(self.L.fx_md_verlet(self.ctx, int(n_steps), float(dt_au), _ptr(m, C.c_double),
+                                        _ptr(x, C.c_double), _ptr(v, C.c_double), _ptr(ep, C.c_double),
+                                        _ptr(ek, C.c_double)))
+        return x.reshape(-1, 3), v.reshape(-1, 3), ep, ek
 
     # -- run and results -----------------------------------------------------
     def run(self, allow_noconv=False):

@@ -1216,6 +1216,88 @@ void Ctx::set_system(int32_t n_atoms, const int32_t* Z, const double* xyz, int32
   has_grad = false;
 }
 
+// New positions for the current system (same atoms, fragments and bonds):
+// every geometry-derived table is rebuilt as by set_system; the starting
+// charges of FX_GUESS_USER are kept.
+void Ctx::set_coordinates(const double* xyz) {
+  if (!has_system) throw FxError(FX_E_STATE, "no system set");
+  if (!xyz) throw FxError(FX_E_INVALID, "null coordinates");
+  std::vector<int32_t> Z(N), fr(frag.begin(), frag.begin() + N), ch(frag_charge.begin(), frag_charge.end());
+  for (int A = 0; A < N; ++A) Z[A] = P.elems[elem[A]].Z;
+  std::vector<int32_t> bd(bonds.begin(), bonds.end());
+  const int nb = NB;
+  std::vector<double> g = guess;
+  set_system(N, Z.data(), xyz, F, fr.data(), ch.data(), nb, nb ? bd.data() : nullptr);
+  guess = g;
+}
+
+// Velocity Verlet (atomic units: bohr, electron masses, hbar/Eh):
+//   x <- x + v dt + (1/2) a dt^2,  a = -grad E / m at the new x,
+//   v <- v + (1/2) (a_old + a_new) dt.
+// Every step after the first starts the monomer loop from the previous
+// step's converged monomer charges (the fixed point does not depend on the
+// start); pair and trimer lists are rebuilt at every geometry.
+void Ctx::md_verlet(int n_steps, double dt, const double* mass, double* xyz, double* vel, double* e_pot,
+                    double* e_kin) {
+  if (!has_system) throw FxError(FX_E_STATE, "no system set");
+  if (NB > 0) throw FxError(FX_E_UNSUPPORTED, "molecular dynamics needs the gradient (no cut bonds)");
+  if (n_steps < 0 || !(dt > 0.0) || !std::isfinite(dt) || !mass || !xyz || !vel)
+    throw FxError(FX_E_INVALID, "bad molecular dynamics arguments");
+  for (int A = 0; A < N; ++A)
+    if (!(mass[A] > 0.0) || !std::isfinite(mass[A])) throw FxError(FX_E_INVALID, "masses must be positive");
+  for (long long k = 0; k < 3LL * N; ++k)
+    if (!std::isfinite(vel[k]) || !std::isfinite(xyz[k])) throw FxError(FX_E_INVALID, "non-finite input");
+  struct Restore {
+    Ctx& c;
+    fx_options o;
+    ~Restore() { c.opt = o; }
+  } restore{*this, opt};
+  opt.want_gradient = 1;
+  const long long n3 = 3LL * N;
+  std::vector<double> x(xyz, xyz + n3), v(vel, vel + n3), g(n3), gn(n3);
+  auto kinetic = [&]() {
+    double t = 0.0;
+    for (int A = 0; A < N; ++A)
+      for (int k = 0; k < 3; ++k) t += 0.5 * mass[A] * v[3 * A + k] * v[3 * A + k];
+    return t;
+  };
+  auto energy_gradient = [&](int step) {
+    set_coordinates(x.data());
+    if (step > 0) opt.guess = FX_GUESS_USER;
+    fx_result r;
+    run(&r);
+    if (!res.converged) throw FxError(FX_E_NOCONV, "molecular dynamics step " + std::to_string(step) +
+                                                       ": a fragment SCC or the monomer loop did not converge");
+    d_grad.download_raw(gn.data(), n3, stream);
+    guess.resize(Nsh);
+    d_q.download_raw(guess.data(), Nsh, stream);
+    sync();
+    return r.e_total;
+  };
+  double E = energy_gradient(0);
+  g = gn;
+  if (e_pot) e_pot[0] = E;
+  if (e_kin) e_kin[0] = kinetic();
+  for (int step = 1; step <= n_steps; ++step) {
+    for (int A = 0; A < N; ++A)
+      for (int k = 0; k < 3; ++k) {
+        const long long i = 3LL * A + k;
+        x[i] += v[i] * dt - 0.5 * g[i] / mass[A] * dt * dt;
+      }
+    E = energy_gradient(step);
+    for (int A = 0; A < N; ++A)
+      for (int k = 0; k < 3; ++k) {
+        const long long i = 3LL * A + k;
+        v[i] -= 0.5 * (g[i] + gn[i]) / mass[A] * dt;
+      }
+    g = gn;
+    if (e_pot) e_pot[step] = E;
+    if (e_kin) e_kin[step] = kinetic();
+  }
+  std::copy(x.begin(), x.end(), xyz);
+  std::copy(v.begin(), v.end(), vel);
+}
+
 // ---------------------------------------------------------------------------
 
 void Ctx::run(fx_result* out) {
@@ -1738,6 +1820,17 @@ int fx_get_gradient(fx_ctx* ctx, double* grad) {
     ctx->c.d_grad.download_raw(grad, 3LL * ctx->c.N, ctx->c.stream);
     ctx->c.sync();
   });
+}
+
+int fx_set_coordinates(fx_ctx* ctx, const double* xyz_bohr) {
+  if (!ctx || !xyz_bohr) return FX_E_INVALID;
+  FX_GUARD(ctx, ctx->c.set_coordinates(xyz_bohr));
+}
+
+int fx_md_verlet(fx_ctx* ctx, int32_t n_steps, double dt, const double* mass, double* xyz_bohr, double* vel,
+                 double* e_pot, double* e_kin) {
+  if (!ctx) return FX_E_INVALID;
+  FX_GUARD(ctx, ctx->c.md_verlet(n_steps, dt, mass, xyz_bohr, vel, e_pot, e_kin));
 }
 
 int fx_compute_cn(fx_ctx* ctx, double* cn) {

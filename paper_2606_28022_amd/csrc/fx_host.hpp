@@ -318,6 +318,9 @@ struct Ctx {
   int run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* iters_out, bool single = false);
   int solve_batch(Batch& b, bool cold, long long* iters_out);
   void run(fx_result* out);
+  void set_coordinates(const double* xyz);
+  void md_verlet(int n_steps, double dt, const double* mass, double* xyz, double* vel, double* e_pot,
+                 double* e_kin);
   void gradient();
 };
 
