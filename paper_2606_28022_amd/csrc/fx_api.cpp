@@ -458,8 +458,15 @@ void Ctx::gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlis
     const long long grid = (tiles + 7) / 8 * 8;
     if (grid > 0x7fffffffLL) throw FxError(FX_E_INVALID, "batched product grid too large");
     const int ev = timed ? timers.begin(stream) : -1;
-    hipLaunchKernelGGL(k_gemm_mfma, dim3((unsigned)grid), dim3(256), 0, stream, db, dlist, nl, nt * nt, mode, A, B, C,
-                       w, skip_done, sym);
+    if (mode == 0)
+      hipLaunchKernelGGL(k_gemm_mfma<0>, dim3((unsigned)grid), dim3(256), 0, stream, db, dlist, nl, nt * nt, A, B, C,
+                         w, skip_done, sym);
+    else if (mode == 1)
+      hipLaunchKernelGGL(k_gemm_mfma<1>, dim3((unsigned)grid), dim3(256), 0, stream, db, dlist, nl, nt * nt, A, B, C,
+                         w, skip_done, sym);
+    else
+      hipLaunchKernelGGL(k_gemm_mfma<2>, dim3((unsigned)grid), dim3(256), 0, stream, db, dlist, nl, nt * nt, A, B, C,
+                         w, skip_done, sym);
     if (timed) timers.end(stream, ev, kt("fx::k_gemm_mfma"), gflop);
   }
   check(hipGetLastError(), "batched product");

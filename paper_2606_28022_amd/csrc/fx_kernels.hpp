@@ -31,8 +31,9 @@ __global__ void k_cluster_init_ct(DevBatch bt, const int* list, DevBatch mono);
 __global__ void k_fock(DevSystem sys, DevBatch bt, const int* list);
 __global__ void k_precond_build(DevSystem sys, DevBatch bt, const int* list, DevBatch mono, const double* Mmono,
                                 float* pre, int* ok);
-__global__ void k_gemm_mfma(DevBatch bt, const int* list, int nl, int tiles_per_sys, int mode, const double* A,
-                            const double* B, double* C, const double* w, int skip_done, int sym);
+template <int MODE>
+__global__ void k_gemm_mfma(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double* Abase,
+                            const double* Bbase, double* Cbase, const double* wbase, int skip_done, int sym);
 __global__ void k_gemm(DevBatch bt, const int* list, int mode, const double* A, const double* B, double* C,
                        const double* w, int skip_done);
 __global__ void k_jacobi(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale,

@@ -269,8 +269,13 @@ __global__ void k_gemm(DevBatch bt, const int* list, int mode, const double* Aba
 // keeps each system's operand panels in one L2.
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(256)
-    k_gemm_mfma(DevBatch bt, const int* list, int nl, int tiles_per_sys, int mode, const double* __restrict__ Abase,
+// MODE is a template argument: each product form gets its own kernel with
+// only its own addressing, and every thread keeps 32-bit element offsets that
+// advance by one K slab per step (few registers, so several work-groups share
+// a CU and hide each other's load latency).
+template <int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+    k_gemm_mfma(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double* __restrict__ Abase,
                 const double* __restrict__ Bbase, double* __restrict__ Cbase, const double* __restrict__ wbase,
                 int skip_done, int sym) {
   const int L = blockIdx.x, G = gridDim.x;  // G is a multiple of 8
@@ -293,7 +298,8 @@ __global__ void __launch_bounds__(256)
   constexpr int KS = 32, LD = 66;
   __shared__ double As[KS][LD];  // [k][i]
   __shared__ double Bs[KS][LD];  // [k][j]
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int wi = wave >> 1, wj = wave & 1;
   const int i0 = ti * 64, j0 = tj * 64;
   v4d acc[2][2];
@@ -301,56 +307,78 @@ __global__ void __launch_bounds__(256)
   for (int u = 0; u < 2; ++u)
 #pragma unroll
     for (int v = 0; v < 2; ++v) acc[u][v] = (v4d){0.0, 0.0, 0.0, 0.0};
-  // operands of one K slab, 8 A and 8 B elements per thread, held in
-  // registers so that the next slab's loads overlap this slab's products
+  // element h (0..7) of this thread in a slab: tile row/column and k index
+  //   "row-major" operand (A in modes 0/1, B in mode 1): r = tid / 32 + 8 h, k = tid % 32
+  //   "k-major" operand (A in mode 2, B in modes 0/2):   k = tid / 64 + 4 h, r = tid % 64
+  const int rr = tid >> 5, rk = tid & 31;  // row-major
+  const int kk_ = tid >> 6, kr = tid & 63; // k-major
+  // A: slab element offsets at k0 = 0 and validity of the fixed index
+  int a_off, b_off, a_step, b_step, a_hstep, b_hstep;
+  bool a_fix, b_fix;
+  if (MODE == 2) {
+    a_off = kk_ * n + i0 + kr;
+    a_hstep = 4 * n;
+    a_step = KS * n;
+    a_fix = i0 + kr < n;
+  } else {
+    a_off = (i0 + rr) * n + rk;
+    a_hstep = 8 * n;
+    a_step = KS;
+    a_fix = true;
+  }
+  if (MODE == 1) {
+    b_off = (j0 + rr) * n + rk;
+    b_hstep = 8 * n;
+    b_step = KS;
+    b_fix = true;
+  } else {
+    b_off = kk_ * n + j0 + kr;
+    b_hstep = 4 * n;
+    b_step = KS * n;
+    b_fix = j0 + kr < n;
+  }
   double ra[8], rb[8];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int h = 0; h < 8; ++h) {
-      const int e = threadIdx.x + 256 * h;
-      if (mode == 2) {
-        const int k = e >> 6, i = e & 63;
-        const int gk = k0 + k, gi = i0 + i;
-        ra[h] = (gk < n && gi < n) ? A[(long long)gk * n + gi] * (w ? w[gk] : 1.0) : 0.0;
+      if (MODE == 2) {
+        const int gk = k0 + kk_ + 4 * h;
+        ra[h] = (a_fix && gk < n) ? A[a_off + h * a_hstep] * (w ? w[gk] : 1.0) : 0.0;
       } else {
-        const int i = e >> 5, k = e & 31;
-        const int gi = i0 + i, gk = k0 + k;
-        ra[h] = (gi < n && gk < n) ? A[(long long)gi * n + gk] : 0.0;
+        const int gi = i0 + rr + 8 * h, gk = k0 + rk;
+        ra[h] = (gi < n && gk < n) ? A[a_off + h * a_hstep] : 0.0;
       }
-      if (mode == 1) {
-        const int j = e >> 5, k = e & 31;
-        const int gj = j0 + j, gk = k0 + k;
-        rb[h] = (gj < n && gk < n) ? B[(long long)gj * n + gk] : 0.0;
+      if (MODE == 1) {
+        const int gj = j0 + rr + 8 * h, gk = k0 + rk;
+        rb[h] = (gj < n && gk < n) ? B[b_off + h * b_hstep] : 0.0;
       } else {
-        const int k = e >> 6, j = e & 63;
-        const int gk = k0 + k, gj = j0 + j;
-        rb[h] = (gk < n && gj < n) ? B[(long long)gk * n + gj] : 0.0;
+        const int gk = k0 + kk_ + 4 * h;
+        rb[h] = (b_fix && gk < n) ? B[b_off + h * b_hstep] : 0.0;
       }
     }
+    a_off += a_step;
+    b_off += b_step;
   };
   fetch(0);
   for (int k0 = 0; k0 < n; k0 += KS) {
 #pragma unroll
     for (int h = 0; h < 8; ++h) {
-      const int e = threadIdx.x + 256 * h;
-      if (mode == 2) {
-        As[e >> 6][e & 63] = ra[h];
-      } else {
-        As[e & 31][e >> 5] = ra[h];
-      }
-      if (mode == 1) {
-        Bs[e & 31][e >> 5] = rb[h];
-      } else {
-        Bs[e >> 6][e & 63] = rb[h];
-      }
+      if (MODE == 2)
+        As[kk_ + 4 * h][kr] = ra[h];
+      else
+        As[rk][rr + 8 * h] = ra[h];
+      if (MODE == 1)
+        Bs[rk][rr + 8 * h] = rb[h];
+      else
+        Bs[kk_ + 4 * h][kr] = rb[h];
     }
     __syncthreads();
     if (k0 + KS < n) fetch(k0 + KS);
 #pragma unroll
     for (int kk = 0; kk < KS; kk += 4) {
-      const int kr = kk + (lane >> 4), c = lane & 15;
-      const double a0 = As[kr][wi * 32 + c], a1 = As[kr][wi * 32 + 16 + c];
-      const double b0 = Bs[kr][wj * 32 + c], b1 = Bs[kr][wj * 32 + 16 + c];
+      const int krow = kk + (lane >> 4), c = lane & 15;
+      const double a0 = As[krow][wi * 32 + c], a1 = As[krow][wi * 32 + 16 + c];
+      const double b0 = Bs[krow][wj * 32 + c], b1 = Bs[krow][wj * 32 + 16 + c];
       acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
@@ -372,6 +400,13 @@ __global__ void __launch_bounds__(256)
         }
       }
 }
+
+template __global__ void k_gemm_mfma<0>(DevBatch, const int*, int, int, const double*, const double*, double*,
+                                        const double*, int, int);
+template __global__ void k_gemm_mfma<1>(DevBatch, const int*, int, int, const double*, const double*, double*,
+                                        const double*, int, int);
+template __global__ void k_gemm_mfma<2>(DevBatch, const int*, int, int, const double*, const double*, double*,
+                                        const double*, int, int);
 
 // ---------------------------------------------------------------------------
 // Parallel cyclic Jacobi on the symmetric matrix A (in place), rotating the
