@@ -808,8 +808,11 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
   bool last_split = false;
   // split eigensolver: rotation log of up to jacobi_max_log sweeps per system
   const long long log_stride = (long long)jacobi_max_log * jacobi_rot_log_entries(b.max_nao);
+  // (the apply kernel stages 8 rounds of (c, s), at most two entries per thread)
+  const int m4 = (b.max_nao + 3) & ~3;
   const bool split_ok = jacobi_split && jp.elt != 0 && (long long)apply_rot_lds_bytes(b.max_nao) <= lds_max &&
-                        (int)jacobi_rot_layout(b.max_nao, jp.elt).total <= lds_max;
+                        (int)jacobi_rot_layout(b.max_nao, jp.elt).total <= lds_max &&
+                        8 * m4 <= 2 * 64 * apply_rot_waves(b.max_nao);
   if (split_ok) {
     b.rotlog.alloc((long long)b.nsys * log_stride);
     b.nlog.alloc(b.nsys);

@@ -66,9 +66,9 @@ __host__ __device__ inline JacobiLdsLayout jacobi_lds_layout(int n, int elt, int
 }
 // LDS of k_jacobi_rot: packed strict upper triangle (elt bytes per element),
 // FP64 diagonal, (c, s) of one step or round (m entries, m = n rounded up to a
-// multiple of four), a reduction slot
+// multiple of four), the quartets' blocks of the round, a reduction slot
 struct JacobiRotLayout {
-  unsigned ap, dg, cs, red, total;
+  unsigned ap, dg, cs, qr, red, total;
 };
 __host__ __device__ inline JacobiRotLayout jacobi_rot_layout(int n, int elt) {
   const unsigned m = (unsigned)(n + 3) & ~3u;
@@ -80,6 +80,8 @@ __host__ __device__ inline JacobiRotLayout jacobi_rot_layout(int n, int elt) {
   o = jl_align(o + 8u * (unsigned)n);
   L.cs = o;
   o = jl_align(o + 16u * m);
+  L.qr = o;  // per quartet of the current round: its blocks X | Y << 16
+  o = jl_align(o + 4u * (m / 4u));
   L.red = o;
   o = jl_align(o + 8u * 64u);
   L.total = o;

@@ -1327,6 +1327,7 @@ __global__ void __launch_bounds__(1024)
   T* Ap = reinterpret_cast<T*>(lds + L.ap);
   double* dg = reinterpret_cast<double*>(lds + L.dg);
   double2* cs = reinterpret_cast<double2*>(lds + L.cs);  // [m]: block step [nb2], then 4 per quartet
+  int* qr = reinterpret_cast<int*>(lds + L.qr);          // [nq] blocks X | Y << 16 of the round
   double* red = reinterpret_cast<double*>(lds + L.red);
   double* rows = reinterpret_cast<double*>(cs);  // row sums before the sweeps (16 m >= 8 n bytes)
   const double* __restrict__ A = bt.F + d.mat_off;
@@ -1415,6 +1416,7 @@ __global__ void __launch_bounds__(1024)
       // quartet solves: the two steps on the quartet's own 4 x 4 block
       for (int qd = threadIdx.x; qd < nq; qd += nt) {
         const int X = rr_index(qd, rd, nb2), Y = rr_index(nb2 - 1 - qd, rd, nb2);
+        qr[qd] = X | (Y << 16);
         const int ix[4] = {2 * X, 2 * X + 1, 2 * Y, 2 * Y + 1};
         double M[4][4];
 #pragma unroll
@@ -1474,19 +1476,24 @@ __global__ void __launch_bounds__(1024)
         const bool ra = va0.y != 0.0 || va1.y != 0.0 || va2.y != 0.0 || va3.y != 0.0;
         const bool rb = vb0.y != 0.0 || vb1.y != 0.0 || vb2.y != 0.0 || vb3.y != 0.0;
         if (!ra && !rb) continue;
-        const int Xa = rr_index(a, rd, nb2), Ya = rr_index(nb2 - 1 - a, rd, nb2);
-        const int Xb = rr_index(b, rd, nb2), Yb = rr_index(nb2 - 1 - b, rd, nb2);
+        const int qa = qr[a], qb = qr[b];
+        const int Xa = qa & 0xffff, Ya = qa >> 16, Xb = qb & 0xffff, Yb = qb >> 16;
         const int ia[4] = {2 * Xa, 2 * Xa + 1, 2 * Ya, 2 * Ya + 1};
         const int ib[4] = {2 * Xb, 2 * Xb + 1, 2 * Yb, 2 * Yb + 1};
-        int h[4][4];
+        // packed index of (i, j), i != j: max(i,j) (max(i,j) - 1) / 2 + min(i,j)
+        int ha[4], hb[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          ha[k] = ia[k] * (ia[k] - 1) / 2;
+          hb[k] = ib[k] * (ib[k] - 1) / 2;
+        }
         T B[4][4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const bool ok = ia[i] < n && ib[j] < n;
-            h[i][j] = ok ? pk_index(ia[i], ib[j]) : -1;
-            B[i][j] = ok ? Ap[h[i][j]] : (T)0;
+            B[i][j] = ok ? Ap[ia[i] < ib[j] ? hb[j] + ia[i] : ha[i] + ib[j]] : (T)0;
           }
         }
         if (ra) {
@@ -1505,7 +1512,7 @@ __global__ void __launch_bounds__(1024)
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int j = 0; j < 4; ++j)
-            if (h[i][j] >= 0) Ap[h[i][j]] = B[i][j];
+            if (ia[i] < n && ib[j] < n) Ap[ia[i] < ib[j] ? hb[j] + ia[i] : ha[i] + ib[j]] = B[i][j];
       }
       __syncthreads();
     }
@@ -1540,6 +1547,8 @@ __device__ inline void jq_apply2(double& a, double& b, double2 w) {
   b = w.y * x + w.x * y;
 }
 
+constexpr int APPLY_RCH = 8;  // rounds of rotation parameters staged in LDS at a time
+
 __global__ void __launch_bounds__(1024)
     k_apply_rot(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double2* __restrict__ logbuf,
                 long long log_stride, const int* nlog) {
@@ -1557,8 +1566,9 @@ __global__ void __launch_bounds__(1024)
   const int c0 = tcol * 64;
   if (c0 >= nv) return;
   const int m = (n + 3) & ~3, nb2 = m / 2, nq = m / 4;
-  const int NW = blockDim.x >> 6;
-  double* tile = reinterpret_cast<double*>(lds_raw);  // [m][64], padded rows zero
+  const int NT = blockDim.x, NW = NT >> 6;
+  double* tile = reinterpret_cast<double*>(lds_raw);       // [m][64], padded rows zero
+  double2* lgs = lds_raw + (long long)m * 32;             // [APPLY_RCH][m] staged (c, s)
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double* V = bt.Ct + d.mat_off;
@@ -1566,9 +1576,25 @@ __global__ void __launch_bounds__(1024)
   for (int i = wave; i < m; i += NW) tile[i * 64 + lane] = (colok && i < n) ? V[(long long)i * nv + c0 + lane] : 0.0;
   const double2* lg = logbuf + (long long)si * log_stride;
   const long long swe = jq_sweep_entries(m);
+  const int nrd = nb2 - 1;                   // rounds per sweep
+  const int CE = APPLY_RCH * m;              // staged entries per chunk
+  const int per = (CE + NT - 1) / NT;        // <= 2 for m <= 256 and NT >= 960
+  double2 rg[2];
+  // staged entries of rounds [r0, r0 + APPLY_RCH) of sweep sw into registers
+  auto fetch = [&](int sw, int r0) {
+    const double2* src = lg + (long long)sw * swe + nb2 + (long long)r0 * m;
+    const int lim = min(APPLY_RCH, nrd - r0) * m;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int e = threadIdx.x + NT * r;
+      rg[r] = (r < per && e < lim) ? src[e] : make_double2(1.0, 0.0);
+    }
+  };
   for (int sw = 0; sw < nsw; ++sw) {
     const double2* ls = lg + (long long)sw * swe;
-    __syncthreads();  // tile loaded / previous round applied
+    fetch(sw, 0);
+    __syncthreads();  // tile loaded / previous sweep applied
+    // block step: pairs (2k, 2k+1)
     for (int k = wave; k < nb2; k += NW) {
       const double2 w = ls[k];
       if (w.y == 0.0) continue;  // identity (also every pair with a padded index)
@@ -1578,58 +1604,68 @@ __global__ void __launch_bounds__(1024)
       r0[0] = a;
       r0[64] = b;
     }
-    for (int rd = 0; rd < nb2 - 1; ++rd) {
-      __syncthreads();
-      const double2* lr = ls + nb2 + (long long)rd * m;
-      int qd = wave;
-      if (qd >= nq) continue;
-      // rows x1 x2 (block X) and y1 y2 (block Y) of the wave's quartets;
-      // padded rows stay zero (their rotations are the identity, applied
-      // exactly).  The next quartet's parameters and rows are loaded before
-      // the current one is rotated and stored (quartets of a round are
-      // disjoint), so the load latency overlaps the arithmetic.
-      double2 w0 = lr[4 * qd], w1 = lr[4 * qd + 1], w2 = lr[4 * qd + 2], w3 = lr[4 * qd + 3];
-      double* px = tile + (2 * rr_index(qd, rd, nb2)) * 64 + lane;
-      double* py = tile + (2 * rr_index(nb2 - 1 - qd, rd, nb2)) * 64 + lane;
-      double x1 = px[0], x2 = px[64], y1 = py[0], y2 = py[64];
-      for (;;) {
-        const int qn = qd + NW;
-        const bool more = qn < nq;
-        double2 v0, v1, v2, v3;
-        double *nx = px, *ny = py;
-        double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;
-        if (more) {
-          v0 = lr[4 * qn];
-          v1 = lr[4 * qn + 1];
-          v2 = lr[4 * qn + 2];
-          v3 = lr[4 * qn + 3];
-          nx = tile + (2 * rr_index(qn, rd, nb2)) * 64 + lane;
-          ny = tile + (2 * rr_index(nb2 - 1 - qn, rd, nb2)) * 64 + lane;
-          a1 = nx[0];
-          a2 = nx[64];
-          b1 = ny[0];
-          b2 = ny[64];
+    for (int r0 = 0; r0 < nrd; r0 += APPLY_RCH) {
+      __syncthreads();  // the previous chunk's parameters are no longer read
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int e = threadIdx.x + NT * r;
+        if (r < per && e < CE) lgs[e] = rg[r];
+      }
+      if (r0 + APPLY_RCH < nrd) fetch(sw, r0 + APPLY_RCH);
+      const int r1 = min(nrd, r0 + APPLY_RCH);
+      for (int rd = r0; rd < r1; ++rd) {
+        __syncthreads();  // previous round applied; staged parameters visible
+        const double2* lr = lgs + (rd - r0) * m;
+        int qd = wave;
+        if (qd >= nq) continue;
+        // rows x1 x2 (block X) and y1 y2 (block Y) of the wave's quartets;
+        // padded rows stay zero (their rotations are the identity, applied
+        // exactly).  The next quartet's parameters and rows are loaded before
+        // the current one is rotated and stored (quartets of a round are
+        // disjoint), so the load latency overlaps the arithmetic.
+        double2 w0 = lr[4 * qd], w1 = lr[4 * qd + 1], w2 = lr[4 * qd + 2], w3 = lr[4 * qd + 3];
+        double* px = tile + (2 * rr_index(qd, rd, nb2)) * 64 + lane;
+        double* py = tile + (2 * rr_index(nb2 - 1 - qd, rd, nb2)) * 64 + lane;
+        double x1 = px[0], x2 = px[64], y1 = py[0], y2 = py[64];
+        for (;;) {
+          const int qn = qd + NW;
+          const bool more = qn < nq;
+          double2 v0, v1, v2, v3;
+          double *nx = px, *ny = py;
+          double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;
+          if (more) {
+            v0 = lr[4 * qn];
+            v1 = lr[4 * qn + 1];
+            v2 = lr[4 * qn + 2];
+            v3 = lr[4 * qn + 3];
+            nx = tile + (2 * rr_index(qn, rd, nb2)) * 64 + lane;
+            ny = tile + (2 * rr_index(nb2 - 1 - qn, rd, nb2)) * 64 + lane;
+            a1 = nx[0];
+            a2 = nx[64];
+            b1 = ny[0];
+            b2 = ny[64];
+          }
+          jq_apply2(x1, y1, w0);
+          jq_apply2(x2, y2, w1);
+          jq_apply2(x1, y2, w2);
+          jq_apply2(x2, y1, w3);
+          px[0] = x1;
+          px[64] = x2;
+          py[0] = y1;
+          py[64] = y2;
+          if (!more) break;
+          w0 = v0;
+          w1 = v1;
+          w2 = v2;
+          w3 = v3;
+          px = nx;
+          py = ny;
+          x1 = a1;
+          x2 = a2;
+          y1 = b1;
+          y2 = b2;
+          qd = qn;
         }
-        jq_apply2(x1, y1, w0);
-        jq_apply2(x2, y2, w1);
-        jq_apply2(x1, y2, w2);
-        jq_apply2(x2, y1, w3);
-        px[0] = x1;
-        px[64] = x2;
-        py[0] = y1;
-        py[64] = y2;
-        if (!more) break;
-        w0 = v0;
-        w1 = v1;
-        w2 = v2;
-        w3 = v3;
-        px = nx;
-        py = ny;
-        x1 = a1;
-        x2 = a2;
-        y1 = b1;
-        y2 = b2;
-        qd = qn;
       }
     }
   }
@@ -1638,7 +1674,10 @@ __global__ void __launch_bounds__(1024)
     for (int i = wave; i < n; i += NW) V[(long long)i * nv + c0 + lane] = tile[i * 64 + lane];
 }
 
-size_t apply_rot_lds_bytes(int n) { return (size_t)((n + 3) & ~3) * 64 * 8; }
+size_t apply_rot_lds_bytes(int n) {
+  const size_t m = (size_t)((n + 3) & ~3);
+  return m * 64 * 8 + (size_t)APPLY_RCH * m * 16;
+}
 int apply_rot_waves(int n) {
   const int nq = ((n + 3) & ~3) / 4;
   const int per = (nq + 15) / 16;  // quartets per wave at 16 waves
