@@ -1233,6 +1233,15 @@ namespace fx {
 // k_apply_rot applies the logged rotations to C^T in 64-column tiles held in
 // LDS: one wave per quartet reads its four (c, s) with uniform loads and
 // takes the quartet's four rows through both steps in registers.
+// rr_index(pos, step, M) for pos <= M - 1 and step <= M - 2 (within one
+// sweep, pos - 1 + step < 2 (M - 1)): one conditional subtraction instead of
+// the modulo
+__device__ inline int rr_fast(int pos, int step, int M) {
+  int t = pos - 1 + step;
+  t = t >= M - 1 ? t - (M - 1) : t;
+  return pos == 0 ? 0 : 1 + t;
+}
+
 __device__ inline long long jq_sweep_entries(int m) { return (long long)m / 2 + (long long)(m / 2 - 1) * m; }
 
 // (a, b), a < b, of the idx-th unordered pair of N items (rows folded so that
@@ -1309,6 +1318,52 @@ __device__ inline void jq_cols(T (&B)[4][4], T c, T s) {
     B[k][P] = c * a - s * b;
     B[k][Q] = s * a + c * b;
   }
+}
+
+// One off-diagonal 4 x 4 block of a round: rows of the quartet with blocks
+// qa (X | Y << 16), columns of the quartet qb; rows take that quartet's two
+// steps (x1 y1, x2 y2, then x1 y2, x2 y1), columns the other's.  PAD: some
+// indices may be padding (>= n; nothing stored there).
+template <typename T, bool PAD>
+__device__ inline void jq_offdiag(T* __restrict__ Ap, int n, int qa, int qb, bool ra, bool rb, double2 va0,
+                                  double2 va1, double2 va2, double2 va3, double2 vb0, double2 vb1, double2 vb2,
+                                  double2 vb3) {
+  const int Xa = qa & 0xffff, Ya = qa >> 16, Xb = qb & 0xffff, Yb = qb >> 16;
+  const int ia[4] = {2 * Xa, 2 * Xa + 1, 2 * Ya, 2 * Ya + 1};
+  const int ib[4] = {2 * Xb, 2 * Xb + 1, 2 * Yb, 2 * Yb + 1};
+  // packed index of (i, j), i != j: max (max - 1) / 2 + min
+  int h[4][4];
+  T B[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int hi = ia[i] * (ia[i] - 1) / 2;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int hj = ib[j] * (ib[j] - 1) / 2;
+      h[i][j] = ia[i] < ib[j] ? hj + ia[i] : hi + ib[j];
+      if (PAD)
+        B[i][j] = (ia[i] < n && ib[j] < n) ? Ap[h[i][j]] : (T)0;
+      else
+        B[i][j] = Ap[h[i][j]];
+    }
+  }
+  if (ra) {
+    jq_rows<0, 2>(B, (T)va0.x, (T)va0.y);
+    jq_rows<1, 3>(B, (T)va1.x, (T)va1.y);
+    jq_rows<0, 3>(B, (T)va2.x, (T)va2.y);
+    jq_rows<1, 2>(B, (T)va3.x, (T)va3.y);
+  }
+  if (rb) {
+    jq_cols<0, 2>(B, (T)vb0.x, (T)vb0.y);
+    jq_cols<1, 3>(B, (T)vb1.x, (T)vb1.y);
+    jq_cols<0, 3>(B, (T)vb2.x, (T)vb2.y);
+    jq_cols<1, 2>(B, (T)vb3.x, (T)vb3.y);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (!PAD || (ia[i] < n && ib[j] < n)) Ap[h[i][j]] = B[i][j];
 }
 
 template <typename T>
@@ -1415,7 +1470,7 @@ __global__ void __launch_bounds__(1024)
       double2* lr = ls + nb2 + (long long)rd * m;
       // quartet solves: the two steps on the quartet's own 4 x 4 block
       for (int qd = threadIdx.x; qd < nq; qd += nt) {
-        const int X = rr_index(qd, rd, nb2), Y = rr_index(nb2 - 1 - qd, rd, nb2);
+        const int X = rr_fast(qd, rd, nb2), Y = rr_fast(nb2 - 1 - qd, rd, nb2);
         qr[qd] = X | (Y << 16);
         const int ix[4] = {2 * X, 2 * X + 1, 2 * Y, 2 * Y + 1};
         double M[4][4];
@@ -1477,42 +1532,10 @@ __global__ void __launch_bounds__(1024)
         const bool rb = vb0.y != 0.0 || vb1.y != 0.0 || vb2.y != 0.0 || vb3.y != 0.0;
         if (!ra && !rb) continue;
         const int qa = qr[a], qb = qr[b];
-        const int Xa = qa & 0xffff, Ya = qa >> 16, Xb = qb & 0xffff, Yb = qb >> 16;
-        const int ia[4] = {2 * Xa, 2 * Xa + 1, 2 * Ya, 2 * Ya + 1};
-        const int ib[4] = {2 * Xb, 2 * Xb + 1, 2 * Yb, 2 * Yb + 1};
-        // packed index of (i, j), i != j: max(i,j) (max(i,j) - 1) / 2 + min(i,j)
-        int ha[4], hb[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          ha[k] = ia[k] * (ia[k] - 1) / 2;
-          hb[k] = ib[k] * (ib[k] - 1) / 2;
-        }
-        T B[4][4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const bool ok = ia[i] < n && ib[j] < n;
-            B[i][j] = ok ? Ap[ia[i] < ib[j] ? hb[j] + ia[i] : ha[i] + ib[j]] : (T)0;
-          }
-        }
-        if (ra) {
-          jq_rows<0, 2>(B, (T)va0.x, (T)va0.y);
-          jq_rows<1, 3>(B, (T)va1.x, (T)va1.y);
-          jq_rows<0, 3>(B, (T)va2.x, (T)va2.y);
-          jq_rows<1, 2>(B, (T)va3.x, (T)va3.y);
-        }
-        if (rb) {
-          jq_cols<0, 2>(B, (T)vb0.x, (T)vb0.y);
-          jq_cols<1, 3>(B, (T)vb1.x, (T)vb1.y);
-          jq_cols<0, 3>(B, (T)vb2.x, (T)vb2.y);
-          jq_cols<1, 2>(B, (T)vb3.x, (T)vb3.y);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (ia[i] < n && ib[j] < n) Ap[ia[i] < ib[j] ? hb[j] + ia[i] : ha[i] + ib[j]] = B[i][j];
+        if (m == n)
+          jq_offdiag<T, false>(Ap, n, qa, qb, ra, rb, va0, va1, va2, va3, vb0, vb1, vb2, vb3);
+        else
+          jq_offdiag<T, true>(Ap, n, qa, qb, ra, rb, va0, va1, va2, va3, vb0, vb1, vb2, vb3);
       }
       __syncthreads();
     }
@@ -1624,8 +1647,8 @@ __global__ void __launch_bounds__(1024)
         // the current one is rotated and stored (quartets of a round are
         // disjoint), so the load latency overlaps the arithmetic.
         double2 w0 = lr[4 * qd], w1 = lr[4 * qd + 1], w2 = lr[4 * qd + 2], w3 = lr[4 * qd + 3];
-        double* px = tile + (2 * rr_index(qd, rd, nb2)) * 64 + lane;
-        double* py = tile + (2 * rr_index(nb2 - 1 - qd, rd, nb2)) * 64 + lane;
+        double* px = tile + (2 * rr_fast(qd, rd, nb2)) * 64 + lane;
+        double* py = tile + (2 * rr_fast(nb2 - 1 - qd, rd, nb2)) * 64 + lane;
         double x1 = px[0], x2 = px[64], y1 = py[0], y2 = py[64];
         for (;;) {
           const int qn = qd + NW;
@@ -1638,8 +1661,8 @@ __global__ void __launch_bounds__(1024)
             v1 = lr[4 * qn + 1];
             v2 = lr[4 * qn + 2];
             v3 = lr[4 * qn + 3];
-            nx = tile + (2 * rr_index(qn, rd, nb2)) * 64 + lane;
-            ny = tile + (2 * rr_index(nb2 - 1 - qn, rd, nb2)) * 64 + lane;
+            nx = tile + (2 * rr_fast(qn, rd, nb2)) * 64 + lane;
+            ny = tile + (2 * rr_fast(nb2 - 1 - qn, rd, nb2)) * 64 + lane;
             a1 = nx[0];
             a2 = nx[64];
             b1 = ny[0];
