@@ -535,7 +535,7 @@ void Ctx::build_precond(Batch& b) {
   DevBuf<int> ok;
   ok.alloc(b.nsys);
   DevBatch db = b.dev();
-  hipLaunchKernelGGL(k_precond_build, dim3(b.nsys), dim3(256), bytes, stream, dev_system(), db, b.d_all.p, mb.dev(),
+  hipLaunchKernelGGL(k_precond_build, dim3(b.nsys), dim3(1024), bytes, stream, dev_system(), db, b.d_all.p, mb.dev(),
                      (const double*)resp_M.p, b.pre.p, ok.p);
   check(hipGetLastError(), "k_precond_build");
   std::vector<int> h;

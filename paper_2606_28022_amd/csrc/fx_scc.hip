@@ -1081,22 +1081,22 @@ namespace fx {
 // Gauss-Jordan inversion in place, in FP32 in LDS (the preconditioner only
 // steers the mixer; the fixed point does not depend on it).  ok[si] = 0 and
 // the identity are written when a pivot vanishes.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
     k_precond_build(DevSystem sys, DevBatch bt, const int* list, DevBatch mono, const double* Mmono, float* pre,
                     int* ok) {
   extern __shared__ float Kf[];  // ns x ns
   __shared__ double qa[MAXN];
-  __shared__ float fcol[MAXN];
+  __shared__ float colk[MAXN], rowk[MAXN];
   __shared__ int perm[MAXN];
   __shared__ int comp_off[4], comp_frag[3];
   __shared__ int pivrow;
-  __shared__ float redv[256];
-  __shared__ int redi[256];
+  __shared__ float pivval;
   const int si = list[blockIdx.x];
   const SysDesc d = bt.desc[si];
   const int ns = d.nsh;
   const double* G = bt.gam + d.gam_off;
   const double* q = bt.q_in + d.sh_off;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   if (threadIdx.x == 0) {
     for (int c = 0; c < d.nfrag; ++c) {
       comp_frag[c] = d.frag[c];
@@ -1112,79 +1112,84 @@ __global__ void __launch_bounds__(256)
     qa[a] = v;
   }
   __syncthreads();
-  // K = 1 + M G'
-  for (int idx = threadIdx.x; idx < ns * ns; idx += blockDim.x) {
-    const int s = idx / ns, t = idx - s * ns;
+  // K = 1 + M G' (a wave per row, lanes over columns)
+  const int* smap = bt.sh_mono + d.sh_off;
+  for (int s = wave; s < ns; s += nw) {
     int c = 0;
     while (c + 1 < d.nfrag && s >= comp_off[c + 1]) ++c;
     const int k0 = comp_off[c], k1 = comp_off[c + 1];
     const SysDesc md = mono.desc[comp_frag[c]];
-    const int* smap = bt.sh_mono + d.sh_off;
     const double* Mr = Mmono + md.gam_off + (long long)smap[s] * md.nsh;
-    const int at = bt.sys_sh_atom[d.sh_off + t];
-    const int Aat = bt.sys_atoms[d.atom_off + at];
-    const double g3 = 2.0 * sys.elems[sys.elem[Aat]].Gamma * qa[at];
-    double v = (s == t) ? 1.0 : 0.0;
-    for (int k = k0; k < k1; ++k) {
-      double g = G[(long long)k * ns + t];
-      if (bt.sys_sh_atom[d.sh_off + k] == at) g -= g3;
-      v += Mr[smap[k]] * g;
+    for (int t = lane; t < ns; t += 64) {
+      const int at = bt.sys_sh_atom[d.sh_off + t];
+      const int Aat = bt.sys_atoms[d.atom_off + at];
+      const double g3 = 2.0 * sys.elems[sys.elem[Aat]].Gamma * qa[at];
+      double v = (s == t) ? 1.0 : 0.0;
+      for (int k = k0; k < k1; ++k) {
+        double g = G[(long long)k * ns + t];
+        if (bt.sys_sh_atom[d.sh_off + k] == at) g -= g3;
+        v += Mr[smap[k]] * g;
+      }
+      Kf[s * ns + t] = (float)v;
     }
-    Kf[idx] = (float)v;
   }
   __syncthreads();
+  // Gauss-Jordan with partial pivoting (largest |K[i][k]|, i >= k, lowest
+  // index on ties), in place
   bool good = true;
   for (int k = 0; k < ns; ++k) {
-    // pivot: largest |K[i][k]|, i >= k (lowest index on ties)
-    float best = -1.0f;
-    int bi = k;
-    for (int i = k + threadIdx.x; i < ns; i += blockDim.x) {
-      const float v = fabsf(Kf[i * ns + k]);
-      if (v > best) {
-        best = v;
-        bi = i;
-      }
-    }
-    redv[threadIdx.x] = best;
-    redi[threadIdx.x] = bi;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-      if (threadIdx.x < w) {
-        const float o = redv[threadIdx.x + w];
-        const int oi = redi[threadIdx.x + w];
-        if (o > redv[threadIdx.x] || (o == redv[threadIdx.x] && oi < redi[threadIdx.x])) {
-          redv[threadIdx.x] = o;
-          redi[threadIdx.x] = oi;
+    if (wave == 0) {
+      float best = -1.0f;
+      int bi = k;
+      for (int i = k + lane; i < ns; i += 64) {
+        const float v = fabsf(Kf[i * ns + k]);
+        if (v > best) {
+          best = v;
+          bi = i;
         }
       }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      pivrow = redi[0];
-      perm[k] = redi[0];
+      for (int off = 32; off >= 1; off >>= 1) {
+        const float ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        pivrow = bi;
+        perm[k] = bi;
+        pivval = best;
+      }
     }
     __syncthreads();
     const int p = pivrow;
-    if (redv[0] < 1e-20f) {
+    if (pivval < 1e-20f) {  // same value in every thread: uniform exit
       good = false;
       break;
     }
-    if (p != k)
+    if (p != k) {
       for (int j = threadIdx.x; j < ns; j += blockDim.x) {
         const float t = Kf[k * ns + j];
         Kf[k * ns + j] = Kf[p * ns + j];
         Kf[p * ns + j] = t;
       }
-    __syncthreads();
+      __syncthreads();
+    }
     const float piv = Kf[k * ns + k];
-    for (int i = threadIdx.x; i < ns; i += blockDim.x) fcol[i] = (i == k) ? 0.0f : Kf[i * ns + k];
+    for (int x = threadIdx.x; x < ns; x += blockDim.x) {
+      rowk[x] = (x == k ? 1.0f : Kf[k * ns + x]) / piv;
+      colk[x] = (x == k) ? 0.0f : Kf[x * ns + k];
+    }
     __syncthreads();
-    for (int j = threadIdx.x; j < ns; j += blockDim.x) Kf[k * ns + j] = (j == k ? 1.0f : Kf[k * ns + j]) / piv;
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < ns * ns; idx += blockDim.x) {
-      const int i = idx / ns, j = idx - i * ns;
-      if (i == k) continue;
-      Kf[idx] = (j == k ? 0.0f : Kf[idx]) - fcol[i] * Kf[k * ns + j];
+    for (int i = wave; i < ns; i += nw) {
+      float* row = Kf + i * ns;
+      if (i == k) {
+        for (int j = lane; j < ns; j += 64) row[j] = rowk[j];
+      } else {
+        const float ci = colk[i];
+        for (int j = lane; j < ns; j += 64) row[j] = (j == k ? 0.0f : row[j]) - ci * rowk[j];
+      }
     }
     __syncthreads();
   }
@@ -1202,8 +1207,8 @@ __global__ void __launch_bounds__(256)
     }
   }
   float* out = pre + d.gam_off;
-  for (int idx = threadIdx.x; idx < ns * ns; idx += blockDim.x)
-    out[idx] = good ? Kf[idx] : ((idx / ns == idx % ns) ? 1.0f : 0.0f);
+  for (int s = wave; s < ns; s += nw)
+    for (int t = lane; t < ns; t += 64) out[s * ns + t] = good ? Kf[s * ns + t] : (s == t ? 1.0f : 0.0f);
   if (threadIdx.x == 0) ok[si] = good ? 1 : 0;
 }
 
