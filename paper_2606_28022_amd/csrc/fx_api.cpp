@@ -108,6 +108,11 @@ HostParams load_params(const std::string& path) {
       for (int i = 0; i < NPRIM; ++i) el.coef[s][i] /= std::sqrt(norm2);
     }
     el.nao = ao;
+    // the derivative kernels address AO blocks by shell position: shell 0 an
+    // s shell (AO 0), shell 1 (if any) from AO 1
+    if (el.nsh < 1 || el.nsh > MAXSH_EL || el.l[0] != 0)
+      throw FxError(FX_E_UNSUPPORTED, "element " + kv.first + ": the first shell must be an s shell (at most " +
+                                          std::to_string(MAXSH_EL) + " shells)");
     el.orth = 0;
     if (el.nsh == 2 && el.l[0] == 0 && el.l[1] == 0) {
       double s12 = 0.0;

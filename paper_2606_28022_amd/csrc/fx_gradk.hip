@@ -55,10 +55,16 @@ __device__ void atom_pair_overlap_deriv(const DevElem& ea, const DevElem& eb, co
       S[i][j] = 0.0;
       for (int k = 0; k < 3; ++k) dS[k][i][j] = 0.0;
     }
-  for (int sa = 0; sa < ea.nsh; ++sa)
-    for (int sb = 0; sb < eb.nsh; ++sb) {
-      int la = ea.l[sa], lb = eb.l[sb];
-      int oa = ea.ao0[sa], ob = eb.ao0[sb];
+  // shell 0 is an s shell at AO 0 and shell 1 (if any) starts at AO 1 (the
+  // parameter loader checks this), so every array index below is a
+  // compile-time constant and the blocks stay in registers
+#pragma unroll
+  for (int sa = 0; sa < MAXSH_EL; ++sa)
+#pragma unroll
+    for (int sb = 0; sb < MAXSH_EL; ++sb) {
+      if (sa >= ea.nsh || sb >= eb.nsh) continue;
+      const int la = ea.l[sa], lb = eb.l[sb];
+      const int oa = sa, ob = sb;
       for (int i = 0; i < NPRIM; ++i) {
         double a = ea.alpha[sa][i];
         for (int j = 0; j < NPRIM; ++j) {
@@ -97,18 +103,21 @@ __device__ void atom_pair_overlap_deriv(const DevElem& ea, const DevElem& eb, co
         }
       }
     }
+  // second s shell orthogonalised against the first (AOs 0 and 1)
   if (ea.orth) {
-    int r1 = ea.ao0[0], r2 = ea.ao0[1];
-    for (int j = 0; j < eb.nao; ++j) {
-      S[r2][j] = ea.orthN * (S[r2][j] - ea.orthS12 * S[r1][j]);
-      for (int k = 0; k < 3; ++k) dS[k][r2][j] = ea.orthN * (dS[k][r2][j] - ea.orthS12 * dS[k][r1][j]);
+#pragma unroll
+    for (int j = 0; j < MAXAO_EL; ++j) {
+      S[1][j] = ea.orthN * (S[1][j] - ea.orthS12 * S[0][j]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) dS[k][1][j] = ea.orthN * (dS[k][1][j] - ea.orthS12 * dS[k][0][j]);
     }
   }
   if (eb.orth) {
-    int c1 = eb.ao0[0], c2 = eb.ao0[1];
-    for (int i = 0; i < ea.nao; ++i) {
-      S[i][c2] = eb.orthN * (S[i][c2] - eb.orthS12 * S[i][c1]);
-      for (int k = 0; k < 3; ++k) dS[k][i][c2] = eb.orthN * (dS[k][i][c2] - eb.orthS12 * dS[k][i][c1]);
+#pragma unroll
+    for (int i = 0; i < MAXAO_EL; ++i) {
+      S[i][1] = eb.orthN * (S[i][1] - eb.orthS12 * S[i][0]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) dS[k][i][1] = eb.orthN * (dS[k][i][1] - eb.orthS12 * dS[k][i][0]);
     }
   }
 }
@@ -119,7 +128,8 @@ __device__ void atom_pair_overlap_deriv(const DevElem& ea, const DevElem& eb, co
 // at fixed CN, for every atom a of the system, and the CN sensitivity
 // F_a = d/dCN_a of the D_H term.  Results are multiplied by the system weight
 // and written (or added) to the per-system atom arrays.
-__global__ void k_grad_contract(DevSystem sys, DevBatch bt, const int* list, const double* DHp, const double* DSp,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+    k_grad_contract(DevSystem sys, DevBatch bt, const int* list, const double* DHp, const double* DSp,
                                 const double* gx, const double* gy, const double* wsys, int with_rep, int accumulate,
                                 double* g_out, double* F_out, double* scratch) {
   const int si = list[blockIdx.x];
@@ -162,31 +172,50 @@ __global__ void k_grad_contract(DevSystem sys, DevBatch bt, const int* list, con
     double rcov = ea.rcov + eb.rcov;
     double x = sqrt(R / rcov);
     double dx = 0.5 / sqrt(R * rcov);
-    for (int sa = 0; sa < ea.nsh; ++sa)
-      for (int sb = 0; sb < eb.nsh; ++sb) {
-        double kll = 0.5 * (sys.g.kl[ea.l[sa]] + sys.g.kl[eb.l[sb]]);
-        double ha = ea.level[sa] * (1.0 + ea.kcn[sa] * cnA);
-        double hb = eb.level[sb] * (1.0 + eb.kcn[sb] * cnB);
-        double hav = 0.5 * (ha + hb);
-        double pa = 1.0 + ea.kpoly[sa] * x, pbb = 1.0 + eb.kpoly[sb] * x;
-        double Pi = pa * pbb;
-        double dPi = (ea.kpoly[sa] * pbb + pa * eb.kpoly[sb]) * dx;
-        double base = sys.g.KAB * kll * enf;
-        double fac = base * hav * Pi;
-        double sumDHS = 0.0;
-        for (int u = 0; u < ea.nao_sh[sa]; ++u)
-          for (int v = 0; v < eb.nao_sh[sb]; ++v) {
-            int i = ea.ao0[sa] + u, j = eb.ao0[sb] + v;
-            long long mn = (long long)(oa + i) * n + ob + j;
-            double dh = DH[mn], ds = DS[mn];
-            double w = fac * dh + ds;
-            for (int k = 0; k < 3; ++k) g[k] += 2.0 * w * dS[k][i][j];
-            sumDHS += dh * S[i][j];
-          }
-        double t = 2.0 * sumDHS * base * hav * dPi;
+    // shell-pair factors (shell 0: AO 0; shell 1: AOs 1..)
+    double fac[MAXSH_EL][MAXSH_EL], sumDHS[MAXSH_EL][MAXSH_EL];
+#pragma unroll
+    for (int sa = 0; sa < MAXSH_EL; ++sa)
+#pragma unroll
+      for (int sb = 0; sb < MAXSH_EL; ++sb) {
+        sumDHS[sa][sb] = 0.0;
+        fac[sa][sb] = 0.0;
+        if (sa >= ea.nsh || sb >= eb.nsh) continue;
+        const double kll = 0.5 * (sys.g.kl[ea.l[sa]] + sys.g.kl[eb.l[sb]]);
+        const double ha = ea.level[sa] * (1.0 + ea.kcn[sa] * cnA);
+        const double hb = eb.level[sb] * (1.0 + eb.kcn[sb] * cnB);
+        const double pa = 1.0 + ea.kpoly[sa] * x, pbb = 1.0 + eb.kpoly[sb] * x;
+        fac[sa][sb] = sys.g.KAB * kll * enf * 0.5 * (ha + hb) * pa * pbb;
+      }
+#pragma unroll
+    for (int i = 0; i < MAXAO_EL; ++i)
+#pragma unroll
+      for (int j = 0; j < MAXAO_EL; ++j) {
+        if (i >= ea.nao || j >= eb.nao) continue;
+        const int sa = i == 0 ? 0 : 1, sb = j == 0 ? 0 : 1;
+        const long long mn = (long long)(oa + i) * n + ob + j;
+        const double dh = DH[mn], ds = DS[mn];
+        const double w = fac[sa][sb] * dh + ds;
+        for (int k = 0; k < 3; ++k) g[k] += 2.0 * w * dS[k][i][j];
+        sumDHS[sa][sb] += dh * S[i][j];
+      }
+#pragma unroll
+    for (int sa = 0; sa < MAXSH_EL; ++sa)
+#pragma unroll
+      for (int sb = 0; sb < MAXSH_EL; ++sb) {
+        if (sa >= ea.nsh || sb >= eb.nsh) continue;
+        const double kll = 0.5 * (sys.g.kl[ea.l[sa]] + sys.g.kl[eb.l[sb]]);
+        const double ha = ea.level[sa] * (1.0 + ea.kcn[sa] * cnA);
+        const double hb = eb.level[sb] * (1.0 + eb.kcn[sb] * cnB);
+        const double hav = 0.5 * (ha + hb);
+        const double pa = 1.0 + ea.kpoly[sa] * x, pbb = 1.0 + eb.kpoly[sb] * x;
+        const double Pi = pa * pbb;
+        const double dPi = (ea.kpoly[sa] * pbb + pa * eb.kpoly[sb]) * dx;
+        const double base = sys.g.KAB * kll * enf;
+        const double t = 2.0 * sumDHS[sa][sb] * base * hav * dPi;
         for (int k = 0; k < 3; ++k) g[k] += t * uR[k];
-        Fa += 2.0 * sumDHS * base * Pi * 0.5 * ea.level[sa] * ea.kcn[sa];
-        Fb += 2.0 * sumDHS * base * Pi * 0.5 * eb.level[sb] * eb.kcn[sb];
+        Fa += 2.0 * sumDHS[sa][sb] * base * Pi * 0.5 * ea.level[sa] * ea.kcn[sa];
+        Fb += 2.0 * sumDHS[sa][sb] * base * Pi * 0.5 * eb.level[sb] * eb.kcn[sb];
       }
     if (gx) {
       int s0 = ash[a], t0 = ash[b];
