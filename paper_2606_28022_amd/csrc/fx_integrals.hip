@@ -118,10 +118,16 @@ __device__ void atom_pair_overlap(const DevElem& ea, const DevElem& eb, double R
   double Rv[3] = {Rx, Ry, Rz};
   for (int i = 0; i < MAXAO_EL; ++i)
     for (int j = 0; j < MAXAO_EL; ++j) out[i][j] = 0.0;
-  for (int sa = 0; sa < ea.nsh; ++sa) {
-    for (int sb = 0; sb < eb.nsh; ++sb) {
-      int la = ea.l[sa], lb = eb.l[sb];
-      int oa = ea.ao0[sa], ob = eb.ao0[sb];
+  // shell 0 is an s shell at AO 0, shell 1 (if any) starts at AO 1 (checked
+  // when the parameters are loaded): compile-time block indices, so the
+  // block stays in registers
+#pragma unroll
+  for (int sa = 0; sa < MAXSH_EL; ++sa) {
+#pragma unroll
+    for (int sb = 0; sb < MAXSH_EL; ++sb) {
+      if (sa >= ea.nsh || sb >= eb.nsh) continue;
+      const int la = ea.l[sa], lb = eb.l[sb];
+      const int oa = sa, ob = sb;
       for (int i = 0; i < NPRIM; ++i) {
         double a = ea.alpha[sa][i];
         for (int j = 0; j < NPRIM; ++j) {
@@ -148,13 +154,13 @@ __device__ void atom_pair_overlap(const DevElem& ea, const DevElem& eb, double R
       }
     }
   }
-  if (ea.orth) {  // rows: second s shell of A
-    int r1 = ea.ao0[0], r2 = ea.ao0[1];
-    for (int j = 0; j < eb.nao; ++j) out[r2][j] = ea.orthN * (out[r2][j] - ea.orthS12 * out[r1][j]);
+  if (ea.orth) {  // rows: second s shell of A (AO 1) against the first (AO 0)
+#pragma unroll
+    for (int j = 0; j < MAXAO_EL; ++j) out[1][j] = ea.orthN * (out[1][j] - ea.orthS12 * out[0][j]);
   }
   if (eb.orth) {
-    int c1 = eb.ao0[0], c2 = eb.ao0[1];
-    for (int i = 0; i < ea.nao; ++i) out[i][c2] = eb.orthN * (out[i][c2] - eb.orthS12 * out[i][c1]);
+#pragma unroll
+    for (int i = 0; i < MAXAO_EL; ++i) out[i][1] = eb.orthN * (out[i][1] - eb.orthS12 * out[i][0]);
   }
 }
 
@@ -172,7 +178,8 @@ __device__ inline double h0_prefactor(const DevGlobals& g, const DevElem& ea, in
 
 // ---------------------------------------------------------------------------
 // per-system S, H0, gamma and repulsion; one work-group per system.
-__global__ void k_build_system(DevSystem sys, DevBatch bt, const int* list) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+    k_build_system(DevSystem sys, DevBatch bt, const int* list) {
   int si = list ? list[blockIdx.x] : blockIdx.x;
   const SysDesc d = bt.desc[si];
   const int n = d.nao;
@@ -212,19 +219,24 @@ __global__ void k_build_system(DevSystem sys, DevBatch bt, const int* list) {
     double blk[MAXAO_EL][MAXAO_EL];
     atom_pair_overlap(ea, eb, Rx, Ry, Rz, blk);
     int oa = aao[a], ob = aao[b];
-    for (int sa = 0; sa < ea.nsh; ++sa)
-      for (int sb = 0; sb < eb.nsh; ++sb) {
-        double f = h0_prefactor(sys.g, ea, sa, sys.cn[A], eb, sb, sys.cn[B], R);
-        for (int u = 0; u < ea.nao_sh[sa]; ++u)
-          for (int v = 0; v < eb.nao_sh[sb]; ++v) {
-            int i = ea.ao0[sa] + u, j = eb.ao0[sb] + v;
-            double sv = blk[i][j];
-            double hv = f * sv;
-            S[(long long)(oa + i) * n + ob + j] = sv;
-            S[(long long)(ob + j) * n + oa + i] = sv;
-            H[(long long)(oa + i) * n + ob + j] = hv;
-            H[(long long)(ob + j) * n + oa + i] = hv;
-          }
+    double f[MAXSH_EL][MAXSH_EL];
+#pragma unroll
+    for (int sa = 0; sa < MAXSH_EL; ++sa)
+#pragma unroll
+      for (int sb = 0; sb < MAXSH_EL; ++sb)
+        f[sa][sb] = (sa < ea.nsh && sb < eb.nsh) ? h0_prefactor(sys.g, ea, sa, sys.cn[A], eb, sb, sys.cn[B], R)
+                                                  : 0.0;
+#pragma unroll
+    for (int i = 0; i < MAXAO_EL; ++i)
+#pragma unroll
+      for (int j = 0; j < MAXAO_EL; ++j) {
+        if (i >= ea.nao || j >= eb.nao) continue;
+        const double sv = blk[i][j];
+        const double hv = f[i == 0 ? 0 : 1][j == 0 ? 0 : 1] * sv;
+        S[(long long)(oa + i) * n + ob + j] = sv;
+        S[(long long)(ob + j) * n + oa + i] = sv;
+        H[(long long)(oa + i) * n + ob + j] = hv;
+        H[(long long)(ob + j) * n + oa + i] = hv;
       }
     double al = sqrt(ea.arep * eb.arep);
     const double zs = bt.atom_zs ? bt.atom_zs[d.atom_off + a] * bt.atom_zs[d.atom_off + b] : 1.0;
