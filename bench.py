@@ -169,10 +169,21 @@ def fmo3_anthracene():
     dt = time.perf_counter() - t
     g = c.gradient()
     log(f"FMO3 anthracene: {dt:.3f} s, {r['solves_trimer']} trimers")
+    # the same step in the mixed-precision form
+    c.set_options(precision=1)
+    c.run()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rm = c.run()
+    torch.cuda.synchronize()
+    dtm = time.perf_counter() - t
+    gm = c.gradient()
     c.close()
     return {"workload": "anthracene 8x8x4 crystal (12,288 atoms, 512 molecules), FMO3 energy + analytic "
                         "gradient with response, fp64",
             "s_per_step": dt, "energy_Eh": r["e_total"],
+            "mixed_vs_fp64": {"s_per_step": dtm, "abs_dE_Eh": abs(rm["e_total"] - r["e_total"]),
+                              "max_abs_dgrad_Eh_per_bohr": float(np.abs(gm - g).max())},
             "solves": {"monomer": r["solves_mono"], "dimer": r["solves_dimer"], "trimer": r["solves_trimer"]},
             "scc_solves_per_s": (r["solves_mono"] + r["solves_dimer"] + r["solves_trimer"]) / dt,
             "phases_ms": {k: r[k] for k in ("ms_monomer", "ms_dimer", "ms_trimer", "ms_gradient")},
@@ -300,6 +311,8 @@ def main():
                    "es_dim_pairs": int(cnt.n_esd_pairs), "cutoff_angstrom": 4.0, "precision": "fp64",
                    "schedule": "batched"},
         "scc_solves_per_s": solves / sec,
+        "solves_per_s_by_phase": {"monomer": r["solves_mono"] / (1e-3 * r["ms_monomer"]),
+                                  "dimer": r["solves_dimer"] / (1e-3 * r["ms_dimer"])},
         "energy_Eh": r["e_total"], "grad_max_Eh_per_bohr": float(np.abs(g).max()),
         "net_force": float(np.abs(g.sum(0)).max()),
         "phases_ms": {k: r[k] for k in ("ms_lists", "ms_monomer", "ms_dimer", "ms_energy", "ms_gradient",
