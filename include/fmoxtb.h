@@ -106,6 +106,14 @@ typedef struct fx_options {
   double vdw_trimer;      /* FX_SELECT_VDW: a trimer is computed when at least
                              two of its three pairs meet the same test with
                              vdw_trimer; default 1.5 */
+  int32_t warm_clusters;  /* 1: an SCC dimer that was also solved in the last
+                             fx_run on this system (same fragments, other
+                             coordinates, e.g. the previous molecular-dynamics
+                             step) starts from that run's converged charges
+                             and orbitals (the orbitals re-orthonormalised in
+                             the new overlap) instead of the monomers'; the
+                             fixed point is the same.  Default 0; fx_md_verlet
+                             sets it for its steps. */
 } fx_options;
 
 typedef struct fx_counts {
@@ -145,6 +153,7 @@ typedef struct fx_result {
   /* device time of the hot kernels, largest first (see fx_kernel_stat) */
   int32_t n_kstat;
   fx_kernel_stat kstat[FX_MAX_KSTAT];
+  int64_t warm_dimers;    /* SCC dimers started from the last run (warm_clusters) */
 } fx_result;
 
 /* Load element constants and STO-nG basis expansions from a JSON file.

@@ -31,7 +31,8 @@ class fx_options(C.Structure):
                 ("guess_max_iter", C.c_int32), ("scc_tol", C.c_double),
                 ("energy_tol", C.c_double), ("macro_tol", C.c_double), ("max_iter", C.c_int32),
                 ("max_macro", C.c_int32), ("want_gradient", C.c_int32), ("want_response", C.c_int32),
-                ("selection", C.c_int32), ("vdw_dimer", C.c_double), ("vdw_trimer", C.c_double)]
+                ("selection", C.c_int32), ("vdw_dimer", C.c_double), ("vdw_trimer", C.c_double),
+                ("warm_clusters", C.c_int32)]
 
 
 class fx_counts(C.Structure):
@@ -54,7 +55,7 @@ class fx_result(C.Structure):
                 ("ms_dimer", C.c_double), ("ms_trimer", C.c_double), ("ms_energy", C.c_double),
                 ("ms_gradient", C.c_double), ("ms_response", C.c_double), ("guess_fallbacks", C.c_int64),
                 ("first_residual_median", C.c_double), ("n_kstat", C.c_int32),
-                ("kstat", fx_kernel_stat * FX_MAX_KSTAT)]
+                ("kstat", fx_kernel_stat * FX_MAX_KSTAT), ("warm_dimers", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("kstat", "n_kstat")}

@@ -18,6 +18,7 @@
 #include <sstream>
 #include <stdexcept>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/fmoxtb.h"
@@ -773,7 +774,8 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     };
     if (b.init_from_mono && mb.nsys > 0) {
       // C0 = blockdiag(monomer C); G = C0^T S C0 = L L^T; C = C0 L^-T
-      hipLaunchKernelGGL(k_cluster_init_ct, dim3(nl), dim3(256), 0, stream, db, b.d_list.p, mb.dev());
+      hipLaunchKernelGGL(k_cluster_init_ct, dim3(nl), dim3(256), 0, stream, db, b.d_list.p, mb.dev(),
+                         b.has_warm ? (const long long*)b.warm_off.p : nullptr);
       gemm_batch(b, db, nl, b.d_list.p, 0, b.Ct.p, b.S.p, b.Tm.p, (const double*)nullptr, gf);
       gemm_batch(b, db, nl, b.d_list.p, 1, b.Tm.p, b.Ct.p, b.Fm.p, (const double*)nullptr, gf, 0, 1);
       if (chol_elt == 0) {
@@ -1225,6 +1227,7 @@ void Ctx::set_system(int32_t n_atoms, const int32_t* Z, const double* xyz, int32
   d_phi.alloc(Nsh);
   d_scalar.alloc(8);
   guess.assign(Nsh, 0.0);
+  warm_valid = false;
   has_system = true;
   lists_built = false;
   has_result = false;
@@ -1242,8 +1245,10 @@ void Ctx::set_coordinates(const double* xyz) {
   std::vector<int32_t> bd(bonds.begin(), bonds.end());
   const int nb = NB;
   std::vector<double> g = guess;
+  const bool wv = warm_valid;
   set_system(N, Z.data(), xyz, F, fr.data(), ch.data(), nb, nb ? bd.data() : nullptr);
   guess = g;
+  warm_valid = wv;  // same fragments: the last run's clusters remain valid starts
 }
 
 // Velocity Verlet (atomic units: bohr, electron masses, hbar/Eh):
@@ -1268,6 +1273,7 @@ void Ctx::md_verlet(int n_steps, double dt, const double* mass, double* xyz, dou
     ~Restore() { c.opt = o; }
   } restore{*this, opt};
   opt.want_gradient = 1;
+  opt.warm_clusters = 1;
   const long long n3 = 3LL * N;
   std::vector<double> x(xyz, xyz + n3), v(vel, vel + n3), g(n3), gn(n3);
   auto kinetic = [&]() {
@@ -1484,6 +1490,30 @@ void Ctx::run(fx_result* out) {
     DevBatch ddb = db_.dev();
     hipLaunchKernelGGL(k_cluster_phi, dim3(db_.nsys), dim3(128), 0, stream, dev_system(), ddb, d_phi.p, d_q.p);
     hipLaunchKernelGGL(k_gather_shell, dim3(db_.nsys), dim3(64), 0, stream, ddb, d_q.p, db_.q_in.p);
+    // dimers also solved in the last run start from that solution
+    db_.has_warm = false;
+    if (opt.warm_clusters && warm_valid && db_.init_from_mono) {
+      std::unordered_map<long long, int> old;
+      for (size_t k = 0; 2 * k < warm_pairs.size(); ++k) old[(long long)warm_pairs[2 * k] * F + warm_pairs[2 * k + 1]] = (int)k;
+      std::vector<long long> mo(nscc, -1), so(nscc, -1);
+      long long nwarm = 0;
+      for (long long k = 0; k < nscc; ++k) {
+        auto it = old.find((long long)scc_pairs[2 * k] * F + scc_pairs[2 * k + 1]);
+        if (it == old.end()) continue;
+        mo[k] = warm_matoff[it->second];
+        so[k] = warm_shoff[it->second];
+        ++nwarm;
+      }
+      if (nwarm > 0) {
+        db_.warm_off.upload(mo);
+        warm_so.upload(so);
+        hipLaunchKernelGGL(k_warm_start, dim3(db_.nsys), dim3(256), 0, stream, ddb, db_.warm_off.p, warm_so.p,
+                           warm_C.p, warm_q.p);
+        check(hipGetLastError(), "k_warm_start");
+        db_.has_warm = true;
+      }
+      res.warm_dimers = nwarm;
+    }
     build_precond(db_);
     long long itd = 0;
     int failed = solve_batch(db_, true, &itd);
@@ -1497,7 +1527,25 @@ void Ctx::run(fx_result* out) {
       hipLaunchKernelGGL(k_cluster_healed, dim3(db_.nsys), dim3(128), 0, stream, dev_system(), ddb, d_phi.p, d_q.p,
                          dEV_scc.p, dE_scc.p);
     check(hipGetLastError(), "k_cluster_terms");
+    db_.has_warm = false;
+    if (opt.warm_clusters) {
+      warm_pairs = scc_pairs;
+      warm_matoff.resize(db_.nsys);
+      warm_shoff.resize(db_.nsys);
+      for (int k = 0; k < db_.nsys; ++k) {
+        warm_matoff[k] = db_.h_desc[k].mat_off;
+        warm_shoff[k] = db_.h_desc[k].sh_off;
+      }
+      warm_C.alloc(db_.tot_mat);
+      warm_q.alloc(db_.tot_sh);
+      check(hipMemcpyAsync(warm_C.p, db_.Ct.p, sizeof(double) * db_.tot_mat, hipMemcpyDeviceToDevice, stream),
+            "copy");
+      check(hipMemcpyAsync(warm_q.p, db_.q_out.p, sizeof(double) * db_.tot_sh, hipMemcpyDeviceToDevice, stream),
+            "copy");
+      warm_valid = true;
+    }
   }
+  if (nscc == 0) warm_valid = false;
   sync();
   double t3 = now_ms();
   res.ms_dimer = t3 - t2;
@@ -1704,6 +1752,7 @@ int fx_default_options(fx_options* o) {
   o->selection = FX_SELECT_CUTOFF;
   o->vdw_dimer = 2.0;
   o->vdw_trimer = 1.5;
+  o->warm_clusters = 0;
   return FX_OK;
 }
 
@@ -1724,6 +1773,7 @@ int fx_set_options(fx_ctx* ctx, const fx_options* o) {
     if (!(o->vdw_dimer > 0.0) || !(o->vdw_trimer > 0.0) || !std::isfinite(o->vdw_dimer) ||
         !std::isfinite(o->vdw_trimer))
       throw fx::FxError(FX_E_INVALID, "van der Waals scaling factors must be positive");
+    if (o->warm_clusters != 0 && o->warm_clusters != 1) throw fx::FxError(FX_E_INVALID, "warm_clusters must be 0 or 1");
     const fx_options& c = ctx->c.opt;
     bool cutoff_changed = o->cutoff_bohr != c.cutoff_bohr || o->order != c.order || o->selection != c.selection ||
                           o->vdw_dimer != c.vdw_dimer || o->vdw_trimer != c.vdw_trimer;

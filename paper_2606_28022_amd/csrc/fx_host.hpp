@@ -106,6 +106,8 @@ struct Batch {
   int nsys = 0;
   int max_nao = 0;
   bool init_from_mono = false;  // first basis from the monomers' eigenvectors
+  bool has_warm = false;        // some systems start from the previous run (warm_off >= 0)
+  DevBuf<long long> warm_off;   // per system: C^T offset in the previous run's layout, or -1
   int tot_sh = 0, tot_ao = 0;
   long long tot_mat = 0;
   std::vector<SysDesc> h_desc;
@@ -209,6 +211,13 @@ struct Ctx {
   // batches and results
   Batch mb, db_, tb_;
   DevBuf<double> e_mono, dE_scc, dEV_scc, dE_esd, dE_tri, ddq_scc, ddq_tri;
+  // converged SCC dimers of the last run (warm_clusters): pair list, C^T and
+  // charges in that run's batch layout
+  bool warm_valid = false;
+  std::vector<int> warm_pairs;
+  std::vector<long long> warm_matoff, warm_shoff;
+  DevBuf<double> warm_C, warm_q;  // last run's SCC dimer orbitals (C^T) and shell charges
+  DevBuf<long long> warm_so;       // per dimer of this run: shell offset in warm_q, or -1
   std::vector<double> trimer_dEIJK;
   fx_result res{};
   // monomer susceptibility blocks (shell-summed transition charges Q and

@@ -27,7 +27,9 @@ __global__ void k_ghost_cn(DevSystem sys, const int* bonds, int nbonds, double* 
 __global__ void k_reset_state(DevBatch bt, const int* list, int nl, int keep_err);
 __global__ void k_precond_step(DevBatch bt, double* out);
 __global__ void k_cholinv(DevBatch bt, const int* list, const double* Apool, double* Lpool, double* Xpool);
-__global__ void k_cluster_init_ct(DevBatch bt, const int* list, DevBatch mono);
+__global__ void k_cluster_init_ct(DevBatch bt, const int* list, DevBatch mono, const long long* warm_off);
+__global__ void k_warm_start(DevBatch bt, const long long* mat_off_old, const long long* sh_off_old,
+                             const double* Cold, const double* qold);
 __global__ void k_fock(DevSystem sys, DevBatch bt, const int* list);
 __global__ void k_precond_build(DevSystem sys, DevBatch bt, const int* list, DevBatch mono, const double* Mmono,
                                 float* pre, int* ok);

@@ -81,8 +81,9 @@ __global__ void k_precond_step(DevBatch bt, double* out) {
 
 // initial basis of a cluster from its monomers' eigenvectors: block-diagonal
 // rows of the monomer C^T (fragment order), later S-orthonormalised.
-__global__ void k_cluster_init_ct(DevBatch bt, const int* list, DevBatch mono) {
+__global__ void k_cluster_init_ct(DevBatch bt, const int* list, DevBatch mono, const long long* warm_off) {
   int si = list[blockIdx.x];
+  if (warm_off && warm_off[si] >= 0) return;  // started from the previous run's orbitals
   const SysDesc d = bt.desc[si];
   const int n = d.nao;
   double* C = bt.Ct + d.mat_off;
@@ -99,6 +100,22 @@ __global__ void k_cluster_init_ct(DevBatch bt, const int* list, DevBatch mono) {
     }
     off += nm;
   }
+}
+
+// Start of a cluster from its converged solution of the previous run (same
+// fragments, hence the same matrix order): C^T and the input charges are
+// copied from that run's batch layout (offsets < 0: no previous solution).
+__global__ void k_warm_start(DevBatch bt, const long long* mat_off_old, const long long* sh_off_old,
+                             const double* Cold, const double* qold) {
+  const int si = blockIdx.x;
+  const long long mo = mat_off_old[si];
+  if (mo < 0) return;
+  const SysDesc d = bt.desc[si];
+  const long long nn = (long long)d.nao * d.nao;
+  double* C = bt.Ct + d.mat_off;
+  for (long long i = threadIdx.x; i < nn; i += blockDim.x) C[i] = Cold[mo + i];
+  const long long so = sh_off_old[si];
+  for (int s = threadIdx.x; s < d.nsh; s += blockDim.x) bt.q_in[d.sh_off + s] = qold[so + s];
 }
 
 // ---------------------------------------------------------------------------

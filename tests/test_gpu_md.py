@@ -94,3 +94,31 @@ def test_set_coordinates_equals_set_system(lib, params):
         c.md_verlet(2, -1.0, M.masses_au(s.Z), s.xyz, np.zeros_like(s.xyz))
     with pytest.raises(FxError):
         c.md_verlet(2, 1.0, -M.masses_au(s.Z), s.xyz, np.zeros_like(s.xyz))
+
+
+def test_warm_clusters_same_fixed_point(lib):
+    """Dimers started from the previous geometry's converged solution reach
+    the same energy and gradient as a cold start, in fewer SCC iterations;
+    fx_set_system forgets the saved solution."""
+    _say("warm clusters 8 waters")
+    s = w.water_cluster_cube()
+    rng = np.random.default_rng(11)
+    xyz2 = s.xyz + 0.02 * rng.normal(size=s.xyz.shape)
+    c = lib()
+    c.set_system(s.Z, s.xyz, s.frag, s.frag_charge)
+    c.set_options(warm_clusters=1)
+    r0 = c.run()
+    assert r0["warm_dimers"] == 0
+    c.set_coordinates(xyz2)
+    rw = c.run()
+    gw = c.gradient()
+    d = lib()
+    d.set_system(s.Z, xyz2, s.frag, s.frag_charge)
+    rc = d.run()
+    n_scc = d.get_counts().n_scc_pairs
+    assert n_scc > 0 and rw["warm_dimers"] == n_scc
+    assert abs(rw["e_total"] - rc["e_total"]) < 1e-9
+    assert np.max(np.abs(gw - d.gradient())) < 1e-7
+    assert rw["iters_dimer"] < rc["iters_dimer"], (rw["iters_dimer"], rc["iters_dimer"])
+    c.set_system(s.Z, xyz2, s.frag, s.frag_charge)
+    assert c.run()["warm_dimers"] == 0
