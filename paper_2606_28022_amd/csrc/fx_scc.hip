@@ -1253,8 +1253,8 @@ namespace fx {
 // the m/2 block rotations, then per round four per quartet (x1 y1, x2 y2,
 // x1 y2, x2 y1); up to `max_log` sweeps.
 // k_apply_rot applies the logged rotations to C^T in 64-column tiles held in
-// LDS: one wave per quartet reads its four (c, s) with uniform loads and
-// takes the quartet's four rows through both steps in registers.
+// LDS: a 16-lane group per quartet reads its four (c, s) and takes the
+// quartet's four rows through both steps in registers.
 // rr_index(pos, step, M) for pos <= M - 1 and step <= M - 2 (within one
 // sweep, pos - 1 + step < 2 (M - 1)): one conditional subtraction instead of
 // the modulo
@@ -1580,16 +1580,27 @@ template __global__ void k_jacobi_rot<float>(DevBatch, const int*, int, double, 
                                              long long, int, int*);
 
 // Apply the logged rotations to the rows of C^T, one 64-column tile per
-// work-group (lane = column); the tile stays in LDS for all logged sweeps.
-// Pairs of one step are disjoint and quartets of one round are disjoint, so
-// the waves share them (block k or quartet k to wave k mod waves) with one
-// barrier per step of the block step and one per round.  The rotation
-// parameters and indices are uniform in a wave (scalar loads and integer
-// arithmetic).
+// work-group; the tile stays in LDS for all logged sweeps.  Pairs of one step
+// are disjoint and quartets of one round are disjoint, so the waves share
+// them with one barrier per step of the block step and one per round.  Block
+// step: lane = column, block k to wave k mod waves.  Rounds: quartet q to
+// 16-lane group q mod 4 of wave q / 4, each lane taking four columns of the
+// quartet's rows with 16-byte LDS accesses (on gfx950 an LDS instruction
+// costs about the same for 8 or 16 bytes per lane, so this halves the
+// instructions per rotated element, and the rotation parameters are read
+// once per four columns).
 __device__ inline void jq_apply2(double& a, double& b, double2 w) {
   const double x = a, y = b;
   a = w.x * x - w.y * y;
   b = w.y * x + w.x * y;
+}
+
+// rotation w of four columns held as two double2 (row a: al, ah; row b: bl, bh)
+__device__ inline void jq_apply4(double2& al, double2& ah, double2& bl, double2& bh, double2 w) {
+  jq_apply2(al.x, bl.x, w);
+  jq_apply2(al.y, bl.y, w);
+  jq_apply2(ah.x, bh.x, w);
+  jq_apply2(ah.y, bh.y, w);
 }
 
 constexpr int APPLY_RCH = 8;  // rounds of rotation parameters staged in LDS at a time
@@ -1614,7 +1625,7 @@ __global__ void __launch_bounds__(1024)
   const int NT = blockDim.x, NW = NT >> 6;
   double* tile = reinterpret_cast<double*>(lds_raw);       // [m][64], padded rows zero
   double2* lgs = lds_raw + (long long)m * 32;             // [APPLY_RCH][m] staged (c, s)
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, grp = lane >> 4, sub = lane & 15;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double* V = bt.Ct + d.mat_off;
   const bool colok = c0 + lane < nv;
@@ -1660,57 +1671,32 @@ __global__ void __launch_bounds__(1024)
       const int r1 = min(nrd, r0 + APPLY_RCH);
       for (int rd = r0; rd < r1; ++rd) {
         __syncthreads();  // previous round applied; staged parameters visible
-        const double2* lr = lgs + (rd - r0) * m;
-        int qd = wave;
+        // one quartet per 16-lane group (quartet 4 wave + group); a lane
+        // holds columns 2 sub, 2 sub + 1, 32 + 2 sub, 33 + 2 sub of the
+        // quartet's four rows (16-byte LDS accesses, each group's row segment
+        // contiguous).  Padded rows stay zero: their rotations are the
+        // identity, applied exactly.
+        const int qd = wave * 4 + grp;
         if (qd >= nq) continue;
-        // rows x1 x2 (block X) and y1 y2 (block Y) of the wave's quartets;
-        // padded rows stay zero (their rotations are the identity, applied
-        // exactly).  The next quartet's parameters and rows are loaded before
-        // the current one is rotated and stored (quartets of a round are
-        // disjoint), so the load latency overlaps the arithmetic.
-        double2 w0 = lr[4 * qd], w1 = lr[4 * qd + 1], w2 = lr[4 * qd + 2], w3 = lr[4 * qd + 3];
-        double* px = tile + (2 * rr_fast(qd, rd, nb2)) * 64 + lane;
-        double* py = tile + (2 * rr_fast(nb2 - 1 - qd, rd, nb2)) * 64 + lane;
-        double x1 = px[0], x2 = px[64], y1 = py[0], y2 = py[64];
-        for (;;) {
-          const int qn = qd + NW;
-          const bool more = qn < nq;
-          double2 v0, v1, v2, v3;
-          double *nx = px, *ny = py;
-          double a1 = 0.0, a2 = 0.0, b1 = 0.0, b2 = 0.0;
-          if (more) {
-            v0 = lr[4 * qn];
-            v1 = lr[4 * qn + 1];
-            v2 = lr[4 * qn + 2];
-            v3 = lr[4 * qn + 3];
-            nx = tile + (2 * rr_fast(qn, rd, nb2)) * 64 + lane;
-            ny = tile + (2 * rr_fast(nb2 - 1 - qn, rd, nb2)) * 64 + lane;
-            a1 = nx[0];
-            a2 = nx[64];
-            b1 = ny[0];
-            b2 = ny[64];
-          }
-          jq_apply2(x1, y1, w0);
-          jq_apply2(x2, y2, w1);
-          jq_apply2(x1, y2, w2);
-          jq_apply2(x2, y1, w3);
-          px[0] = x1;
-          px[64] = x2;
-          py[0] = y1;
-          py[64] = y2;
-          if (!more) break;
-          w0 = v0;
-          w1 = v1;
-          w2 = v2;
-          w3 = v3;
-          px = nx;
-          py = ny;
-          x1 = a1;
-          x2 = a2;
-          y1 = b1;
-          y2 = b2;
-          qd = qn;
-        }
+        const double2* lq = lgs + (rd - r0) * m + 4 * qd;
+        const double2 w0 = lq[0], w1 = lq[1], w2 = lq[2], w3 = lq[3];
+        double2* px = reinterpret_cast<double2*>(tile + (2 * rr_fast(qd, rd, nb2)) * 64 + 2 * sub);
+        double2* py = reinterpret_cast<double2*>(tile + (2 * rr_fast(nb2 - 1 - qd, rd, nb2)) * 64 + 2 * sub);
+        // [0] row 1 low columns, [16] row 1 high, [32] row 2 low, [48] row 2 high
+        double2 x1l = px[0], x1h = px[16], x2l = px[32], x2h = px[48];
+        double2 y1l = py[0], y1h = py[16], y2l = py[32], y2h = py[48];
+        jq_apply4(x1l, x1h, y1l, y1h, w0);
+        jq_apply4(x2l, x2h, y2l, y2h, w1);
+        jq_apply4(x1l, x1h, y2l, y2h, w2);
+        jq_apply4(x2l, x2h, y1l, y1h, w3);
+        px[0] = x1l;
+        px[16] = x1h;
+        px[32] = x2l;
+        px[48] = x2h;
+        py[0] = y1l;
+        py[16] = y1h;
+        py[32] = y2l;
+        py[48] = y2h;
       }
     }
   }
@@ -1725,8 +1711,7 @@ size_t apply_rot_lds_bytes(int n) {
 }
 int apply_rot_waves(int n) {
   const int nq = ((n + 3) & ~3) / 4;
-  const int per = (nq + 15) / 16;  // quartets per wave at 16 waves
-  return std::max(1, std::min(16, (nq + per - 1) / per));
+  return std::max(1, (nq + 3) / 4);  // four quartets per wave; 16 waves for m = 256
 }
 long long jacobi_rot_log_entries(int n) {
   const long long m = (n + 3) & ~3;
