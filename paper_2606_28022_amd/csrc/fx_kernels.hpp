@@ -66,22 +66,26 @@ __host__ __device__ inline JacobiLdsLayout jacobi_lds_layout(int n, int elt, int
   L.total = o;
   return L;
 }
-// LDS of k_jacobi_rot: packed strict upper triangle (elt bytes per element),
-// FP64 diagonal, (c, s) of one step or round (m entries, m = n rounded up to a
-// multiple of four), the quartets' blocks of the round, a reduction slot
+// LDS of k_jacobi_rot: 2 x 2 tiles of the upper block triangle (m/2 (m/2 + 1)
+// / 2 tiles of four elt-byte elements, m = n rounded up to a multiple of
+// four), FP64 diagonal (m), (c, s) of one step or round (m double2), their
+// FP32 copy for the FP32 form (two float4 per quartet), the quartets' blocks
+// of the round, a reduction slot
 struct JacobiRotLayout {
-  unsigned ap, dg, cs, qr, red, total;
+  unsigned ap, dg, cs, csf, qr, red, total;
 };
 __host__ __device__ inline JacobiRotLayout jacobi_rot_layout(int n, int elt) {
-  const unsigned m = (unsigned)(n + 3) & ~3u;
+  const unsigned m = (unsigned)(n + 3) & ~3u, nb2 = m / 2u;
   JacobiRotLayout L;
   unsigned o = 0;
   L.ap = o;
-  o = jl_align(o + (unsigned)n * (unsigned)(n - 1) / 2u * (unsigned)elt);
+  o = jl_align(o + nb2 * (nb2 + 1u) / 2u * 4u * (unsigned)elt);
   L.dg = o;
-  o = jl_align(o + 8u * (unsigned)n);
+  o = jl_align(o + 8u * m);
   L.cs = o;
   o = jl_align(o + 16u * m);
+  L.csf = o;
+  o = jl_align(o + (elt == 4 ? 8u * m : 0u));
   L.qr = o;  // per quartet of the current round: its blocks X | Y << 16
   o = jl_align(o + 4u * (m / 4u));
   L.red = o;

@@ -1342,56 +1342,102 @@ __device__ inline void jq_cols(T (&B)[4][4], T c, T s) {
   }
 }
 
+// The working matrix is held as 2 x 2 tiles of the upper block triangle
+// (blocks {2k, 2k+1}): tile (a, b), a <= b, at jt_index(a, b) holds
+// A(2a + i, 2b + j) in component 2 i + j (x, y, z, w); a diagonal tile keeps
+// only its y component, A(2a, 2a + 1) (the diagonal itself is held in FP64
+// apart).  Padded rows and columns are stored as zeros and stay zero, since
+// every rotation that involves a padded index is the identity, so no access
+// needs a padding test.  A 4 x 4 block between two quartets is four tiles:
+// four 16-byte (FP32) or 32-byte (FP64) LDS accesses each way.
+__device__ inline int jt_index(int a, int b) { return b * (b + 1) / 2 + a; }
+
+template <typename T>
+struct JtVec;
+template <>
+struct JtVec<float> {
+  typedef float4 type;
+};
+template <>
+struct JtVec<double> {
+  typedef double4 type;
+};
+
+// 2 x 2 block of rows of block rb and columns of block cb, rb != cb
+template <typename T>
+__device__ inline void jt_get(const typename JtVec<T>::type* At, int rb, int cb, T& e00, T& e01, T& e10, T& e11) {
+  const bool tr = rb > cb;
+  const typename JtVec<T>::type v = At[jt_index(min(rb, cb), max(rb, cb))];
+  e00 = v.x;
+  e11 = v.w;
+  e01 = tr ? v.z : v.y;
+  e10 = tr ? v.y : v.z;
+}
+template <typename T>
+__device__ inline void jt_put(typename JtVec<T>::type* At, int rb, int cb, T e00, T e01, T e10, T e11) {
+  const bool tr = rb > cb;
+  typename JtVec<T>::type v;
+  v.x = e00;
+  v.w = e11;
+  v.y = tr ? e10 : e01;
+  v.z = tr ? e01 : e10;
+  At[jt_index(min(rb, cb), max(rb, cb))] = v;
+}
+
+// the four (c, s) of quartet q in the working precision: FP32 from the packed
+// float copy (two 16-byte reads), FP64 from the double2 entries
+template <typename T>
+__device__ inline void jq_params(const double2* cs, const float4* csf, int q, T (&w)[8]);
+template <>
+__device__ inline void jq_params<float>(const double2*, const float4* csf, int q, float (&w)[8]) {
+  const float4 u = csf[2 * q], v = csf[2 * q + 1];
+  w[0] = u.x, w[1] = u.y, w[2] = u.z, w[3] = u.w, w[4] = v.x, w[5] = v.y, w[6] = v.z, w[7] = v.w;
+}
+template <>
+__device__ inline void jq_params<double>(const double2* cs, const float4*, int q, double (&w)[8]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double2 u = cs[4 * q + k];
+    w[2 * k] = u.x;
+    w[2 * k + 1] = u.y;
+  }
+}
+
 // One off-diagonal 4 x 4 block of a round: rows of the quartet with blocks
 // qa (X | Y << 16), columns of the quartet qb; rows take that quartet's two
-// steps (x1 y1, x2 y2, then x1 y2, x2 y1), columns the other's.  PAD: some
-// indices may be padding (>= n; nothing stored there).
-template <typename T, bool PAD>
-__device__ inline void jq_offdiag(T* __restrict__ Ap, int n, int qa, int qb, bool ra, bool rb, double2 va0,
-                                  double2 va1, double2 va2, double2 va3, double2 vb0, double2 vb1, double2 vb2,
-                                  double2 vb3) {
-  const int Xa = qa & 0xffff, Ya = qa >> 16, Xb = qb & 0xffff, Yb = qb >> 16;
-  const int ia[4] = {2 * Xa, 2 * Xa + 1, 2 * Ya, 2 * Ya + 1};
-  const int ib[4] = {2 * Xb, 2 * Xb + 1, 2 * Yb, 2 * Yb + 1};
-  // packed index of (i, j), i != j: max (max - 1) / 2 + min
-  int h[4][4];
+// steps (x1 y1, x2 y2, then x1 y2, x2 y1), columns the other's.
+template <typename T>
+__device__ inline void jt_offdiag(typename JtVec<T>::type* At, int qa, int qb, bool ra, bool rb, const T (&wa)[8],
+                                  const T (&wb)[8]) {
+  const int Xa = qa & 0xffff, Ya = (qa >> 16) & 0x7fff, Xb = qb & 0xffff, Yb = (qb >> 16) & 0x7fff;
   T B[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int hi = ia[i] * (ia[i] - 1) / 2;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int hj = ib[j] * (ib[j] - 1) / 2;
-      h[i][j] = ia[i] < ib[j] ? hj + ia[i] : hi + ib[j];
-      if (PAD)
-        B[i][j] = (ia[i] < n && ib[j] < n) ? Ap[h[i][j]] : (T)0;
-      else
-        B[i][j] = Ap[h[i][j]];
-    }
-  }
+  jt_get<T>(At, Xa, Xb, B[0][0], B[0][1], B[1][0], B[1][1]);
+  jt_get<T>(At, Xa, Yb, B[0][2], B[0][3], B[1][2], B[1][3]);
+  jt_get<T>(At, Ya, Xb, B[2][0], B[2][1], B[3][0], B[3][1]);
+  jt_get<T>(At, Ya, Yb, B[2][2], B[2][3], B[3][2], B[3][3]);
   if (ra) {
-    jq_rows<0, 2>(B, (T)va0.x, (T)va0.y);
-    jq_rows<1, 3>(B, (T)va1.x, (T)va1.y);
-    jq_rows<0, 3>(B, (T)va2.x, (T)va2.y);
-    jq_rows<1, 2>(B, (T)va3.x, (T)va3.y);
+    jq_rows<0, 2>(B, wa[0], wa[1]);
+    jq_rows<1, 3>(B, wa[2], wa[3]);
+    jq_rows<0, 3>(B, wa[4], wa[5]);
+    jq_rows<1, 2>(B, wa[6], wa[7]);
   }
   if (rb) {
-    jq_cols<0, 2>(B, (T)vb0.x, (T)vb0.y);
-    jq_cols<1, 3>(B, (T)vb1.x, (T)vb1.y);
-    jq_cols<0, 3>(B, (T)vb2.x, (T)vb2.y);
-    jq_cols<1, 2>(B, (T)vb3.x, (T)vb3.y);
+    jq_cols<0, 2>(B, wb[0], wb[1]);
+    jq_cols<1, 3>(B, wb[2], wb[3]);
+    jq_cols<0, 3>(B, wb[4], wb[5]);
+    jq_cols<1, 2>(B, wb[6], wb[7]);
   }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (!PAD || (ia[i] < n && ib[j] < n)) Ap[h[i][j]] = B[i][j];
+  jt_put<T>(At, Xa, Xb, B[0][0], B[0][1], B[1][0], B[1][1]);
+  jt_put<T>(At, Xa, Yb, B[0][2], B[0][3], B[1][2], B[1][3]);
+  jt_put<T>(At, Ya, Xb, B[2][0], B[2][1], B[3][0], B[3][1]);
+  jt_put<T>(At, Ya, Yb, B[2][2], B[2][3], B[3][2], B[3][3]);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(1024)
     k_jacobi_rot(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale, double cap_err,
                  int* sweeps_out, double2* logbuf, long long log_stride, int max_log, int* nlog) {
+  typedef typename JtVec<T>::type V4;
   extern __shared__ double2 lds_raw[];
   unsigned char* lds = reinterpret_cast<unsigned char*>(lds_raw);
   const int si = list[blockIdx.x];
@@ -1401,14 +1447,20 @@ __global__ void __launch_bounds__(1024)
   const int m = (n + 3) & ~3, nb2 = m / 2, nq = m / 4;
   const int nt = blockDim.x;
   const JacobiRotLayout L = jacobi_rot_layout(n, (int)sizeof(T));
-  T* Ap = reinterpret_cast<T*>(lds + L.ap);
+  V4* At = reinterpret_cast<V4*>(lds + L.ap);
+  T* Ae = reinterpret_cast<T*>(lds + L.ap);
   double* dg = reinterpret_cast<double*>(lds + L.dg);
   double2* cs = reinterpret_cast<double2*>(lds + L.cs);  // [m]: block step [nb2], then 4 per quartet
-  int* qr = reinterpret_cast<int*>(lds + L.qr);          // [nq] blocks X | Y << 16 of the round
+  float4* csf = reinterpret_cast<float4*>(lds + L.csf);  // FP32: the quartets' (c, s), 2 per quartet
+  int* qr = reinterpret_cast<int*>(lds + L.qr);          // [nq] X | Y << 16, sign bit: rotates
   double* red = reinterpret_cast<double*>(lds + L.red);
   double* rows = reinterpret_cast<double*>(cs);  // row sums before the sweeps (16 m >= 8 n bytes)
   const double* __restrict__ A = bt.F + d.mat_off;
   double2* lg = logbuf + (long long)si * log_stride;
+  const int ntile = nb2 * (nb2 + 1) / 2;
+  for (int e = threadIdx.x; e < 4 * ntile; e += nt) Ae[e] = (T)0;
+  for (int i = threadIdx.x; i < m; i += nt) dg[i] = 0.0;
+  __syncthreads();
   for (int e = threadIdx.x; e < n * n; e += nt) {
     const int i = e / n, j = e - i * n;
     if (j < i) continue;
@@ -1416,7 +1468,7 @@ __global__ void __launch_bounds__(1024)
     if (i == j)
       dg[i] = v;
     else
-      Ap[pk_index(i, j)] = (T)v;
+      Ae[4 * jt_index(i >> 1, j >> 1) + 2 * (i & 1) + (j & 1)] = (T)v;
   }
   for (int i = threadIdx.x; i < n; i += nt) {
     double r = 0.0;
@@ -1449,13 +1501,13 @@ __global__ void __launch_bounds__(1024)
       const int p = 2 * k, q = p + 1;
       double c = 1.0, s = 0.0, t = 0.0;
       if (q < n) {
-        const int ipq = pk_index(p, q);
-        const double apq = (double)Ap[ipq], app = dg[p], aqq = dg[q];
+        T* e01 = Ae + 4 * jt_index(k, k) + 1;
+        const double apq = (double)*e01, app = dg[p], aqq = dg[q];
         jq_angle(app, aqq, apq, thr, rel_tol, c, s, t);
         if (s != 0.0) {
           dg[p] = app - t * apq;
           dg[q] = aqq + t * apq;
-          Ap[ipq] = (T)0;
+          *e01 = (T)0;
           rot_sweep = 1;
         }
       }
@@ -1463,29 +1515,22 @@ __global__ void __launch_bounds__(1024)
       ls[k] = make_double2(c, s);
     }
     __syncthreads();
+    // the block step on the off-diagonal tiles: rows by block a's rotation,
+    // then columns by block b's
     for (int idx = threadIdx.x; idx < nblk; idx += nt) {
       int a, b;
       tri_pair(idx, nb2, a, b);
       const double2 wa = cs[a], wb = cs[b];
       if (wa.y == 0.0 && wb.y == 0.0) continue;
-      const int p = 2 * a, q = p + 1, r = 2 * b, u = r + 1;  // p < q < r < u
-      if (r >= n) continue;  // block b wholly padded: nothing stored in its columns
-      const bool qv = q < n, uv = u < n;
       const T ca = (T)wa.x, sa = (T)wa.y, cb = (T)wb.x, sb = (T)wb.y;
-      const int ipr = pk_index(p, r);
-      const int ipu = uv ? pk_index(p, u) : 0;
-      const int iqr = qv ? pk_index(q, r) : 0;
-      const int iqu = (qv && uv) ? pk_index(q, u) : 0;
-      const T bpr = Ap[ipr];
-      const T bpu = uv ? Ap[ipu] : (T)0;
-      const T bqr = qv ? Ap[iqr] : (T)0;
-      const T bqu = (qv && uv) ? Ap[iqu] : (T)0;
-      const T tpr = ca * bpr - sa * bqr, tpu = ca * bpu - sa * bqu;
-      const T tqr = sa * bpr + ca * bqr, tqu = sa * bpu + ca * bqu;
-      Ap[ipr] = cb * tpr - sb * tpu;
-      if (uv) Ap[ipu] = sb * tpr + cb * tpu;
-      if (qv) Ap[iqr] = cb * tqr - sb * tqu;
-      if (qv && uv) Ap[iqu] = sb * tqr + cb * tqu;
+      V4 v = At[jt_index(a, b)];
+      const T tpr = ca * v.x - sa * v.z, tpu = ca * v.y - sa * v.w;
+      const T tqr = sa * v.x + ca * v.z, tqu = sa * v.y + ca * v.w;
+      v.x = cb * tpr - sb * tpu;
+      v.y = sb * tpr + cb * tpu;
+      v.z = cb * tqr - sb * tqu;
+      v.w = sb * tqr + cb * tqu;
+      At[jt_index(a, b)] = v;
     }
     __syncthreads();
     for (int rd = 0; rd < nb2 - 1; ++rd) {
@@ -1493,18 +1538,20 @@ __global__ void __launch_bounds__(1024)
       // quartet solves: the two steps on the quartet's own 4 x 4 block
       for (int qd = threadIdx.x; qd < nq; qd += nt) {
         const int X = rr_fast(qd, rd, nb2), Y = rr_fast(nb2 - 1 - qd, rd, nb2);
-        qr[qd] = X | (Y << 16);
         const int ix[4] = {2 * X, 2 * X + 1, 2 * Y, 2 * Y + 1};
+        T* ex = Ae + 4 * jt_index(X, X) + 1;
+        T* ey = Ae + 4 * jt_index(Y, Y) + 1;
+        T e00, e01, e10, e11;
+        jt_get<T>(At, X, Y, e00, e01, e10, e11);
         double M[4][4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            double v = 0.0;
-            if (ix[i] < n && ix[j] < n) v = i == j ? dg[ix[i]] : (double)Ap[pk_index(ix[i], ix[j])];
-            M[i][j] = v;
-          }
-        }
+        for (int i = 0; i < 4; ++i) M[i][i] = dg[ix[i]];
+        M[0][1] = M[1][0] = (double)*ex;
+        M[2][3] = M[3][2] = (double)*ey;
+        M[0][2] = M[2][0] = (double)e00;
+        M[0][3] = M[3][0] = (double)e01;
+        M[1][2] = M[2][1] = (double)e10;
+        M[1][3] = M[3][1] = (double)e11;
         double c0, s0, t0, c1, s1, t1, c2, s2, t2, c3, s3, t3;
         // step 1: (x1, y1) and (x2, y2), both from the block before the step
         jq_angle(M[0][0], M[2][2], M[0][2], thr, rel_tol, c0, s0, t0);
@@ -1522,22 +1569,27 @@ __global__ void __launch_bounds__(1024)
         if (ix[1] >= n || ix[2] >= n) c3 = 1.0, s3 = 0.0, t3 = 0.0;
         jq_rot4<0, 3>(M, c2, s2, t2);
         jq_rot4<1, 2>(M, c3, s3, t3);
-        if (s0 != 0.0 || s1 != 0.0 || s2 != 0.0 || s3 != 0.0) {
+        const bool rot = s0 != 0.0 || s1 != 0.0 || s2 != 0.0 || s3 != 0.0;
+        if (rot) {
           rot_sweep = 1;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            if (ix[i] < n) dg[ix[i]] = M[i][i];
-#pragma unroll
-            for (int j = i + 1; j < 4; ++j)
-              if (ix[i] < n && ix[j] < n) Ap[pk_index(ix[i], ix[j])] = (T)M[i][j];
-          }
+          for (int i = 0; i < 4; ++i) dg[ix[i]] = M[i][i];
+          *ex = (T)M[0][1];
+          *ey = (T)M[2][3];
+          jt_put<T>(At, X, Y, (T)M[0][2], (T)M[0][3], (T)M[1][2], (T)M[1][3]);
         }
+        qr[qd] = X | (Y << 16) | (rot ? (int)0x80000000u : 0);
         const double2 w0 = make_double2(c0, s0), w1 = make_double2(c1, s1), w2 = make_double2(c2, s2),
                       w3 = make_double2(c3, s3);
-        cs[4 * qd] = w0;
-        cs[4 * qd + 1] = w1;
-        cs[4 * qd + 2] = w2;
-        cs[4 * qd + 3] = w3;
+        if (sizeof(T) == 4) {
+          csf[2 * qd] = make_float4((float)c0, (float)s0, (float)c1, (float)s1);
+          csf[2 * qd + 1] = make_float4((float)c2, (float)s2, (float)c3, (float)s3);
+        } else {
+          cs[4 * qd] = w0;
+          cs[4 * qd + 1] = w1;
+          cs[4 * qd + 2] = w2;
+          cs[4 * qd + 3] = w3;
+        }
         lr[4 * qd] = w0;
         lr[4 * qd + 1] = w1;
         lr[4 * qd + 2] = w2;
@@ -1548,16 +1600,13 @@ __global__ void __launch_bounds__(1024)
       for (int idx = threadIdx.x; idx < nqp; idx += nt) {
         int a, b;
         tri_pair(idx, nq, a, b);
-        const double2 va0 = cs[4 * a], va1 = cs[4 * a + 1], va2 = cs[4 * a + 2], va3 = cs[4 * a + 3];
-        const double2 vb0 = cs[4 * b], vb1 = cs[4 * b + 1], vb2 = cs[4 * b + 2], vb3 = cs[4 * b + 3];
-        const bool ra = va0.y != 0.0 || va1.y != 0.0 || va2.y != 0.0 || va3.y != 0.0;
-        const bool rb = vb0.y != 0.0 || vb1.y != 0.0 || vb2.y != 0.0 || vb3.y != 0.0;
-        if (!ra && !rb) continue;
         const int qa = qr[a], qb = qr[b];
-        if (m == n)
-          jq_offdiag<T, false>(Ap, n, qa, qb, ra, rb, va0, va1, va2, va3, vb0, vb1, vb2, vb3);
-        else
-          jq_offdiag<T, true>(Ap, n, qa, qb, ra, rb, va0, va1, va2, va3, vb0, vb1, vb2, vb3);
+        const bool ra = qa < 0, rb = qb < 0;
+        if (!ra && !rb) continue;
+        T wa[8], wb[8];
+        jq_params<T>(cs, csf, a, wa);
+        jq_params<T>(cs, csf, b, wb);
+        jt_offdiag<T>(At, qa, qb, ra, rb, wa, wb);
       }
       __syncthreads();
     }
