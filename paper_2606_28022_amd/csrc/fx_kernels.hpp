@@ -68,9 +68,9 @@ __host__ __device__ inline JacobiLdsLayout jacobi_lds_layout(int n, int elt, int
 }
 // LDS of k_jacobi_rot: 2 x 2 tiles of the upper block triangle (m/2 (m/2 + 1)
 // / 2 tiles of four elt-byte elements, m = n rounded up to a multiple of
-// four), FP64 diagonal (m), (c, s) of one step or round (m double2), their
-// FP32 copy for the FP32 form (two float4 per quartet), the quartets' blocks
-// of the round, a reduction slot
+// four), FP64 diagonal (m), (c, s) of the block step and of two consecutive
+// rounds (double2; the FP32 form keeps the rounds' as two float4 per
+// quartet), the quartets' blocks of two rounds, a reduction slot
 struct JacobiRotLayout {
   unsigned ap, dg, cs, csf, qr, red, total;
 };
@@ -82,12 +82,12 @@ __host__ __device__ inline JacobiRotLayout jacobi_rot_layout(int n, int elt) {
   o = jl_align(o + nb2 * (nb2 + 1u) / 2u * 4u * (unsigned)elt);
   L.dg = o;
   o = jl_align(o + 8u * m);
-  L.cs = o;
-  o = jl_align(o + 16u * m);
-  L.csf = o;
-  o = jl_align(o + (elt == 4 ? 8u * m : 0u));
-  L.qr = o;  // per quartet of the current round: its blocks X | Y << 16
-  o = jl_align(o + 4u * (m / 4u));
+  L.cs = o;  // block step, and (FP64 form) the quartets of two rounds
+  o = jl_align(o + (elt == 4 ? 16u * m : 32u * m));
+  L.csf = o;  // FP32 form: the quartets of two rounds
+  o = jl_align(o + (elt == 4 ? 16u * m : 0u));
+  L.qr = o;  // per quartet of two rounds: its blocks X | Y << 16, sign bit: rotates
+  o = jl_align(o + 8u * (m / 4u));
   L.red = o;
   o = jl_align(o + 8u * 64u);
   L.total = o;

@@ -1433,6 +1433,87 @@ __device__ inline void jt_offdiag(typename JtVec<T>::type* At, int qa, int qb, b
   jt_put<T>(At, Ya, Yb, B[2][2], B[2][3], B[3][2], B[3][3]);
 }
 
+// The two steps of round rd on quartet qd's own 4 x 4 block (rotation angles
+// in FP64): the rotated block back to LDS, the four (c, s) to the round's
+// parameter slots (buffer b) and to the log.  Returns whether it rotated.
+template <typename T>
+__device__ inline bool jq_quartet(int qd, int rd, int n, int nb2, int nq, int b, double thr, double rel_tol,
+                                  typename JtVec<T>::type* At, T* Ae, double* dg, double2* cs, float4* csf, int* qr,
+                                  double2* lr) {
+  const int X = rr_fast(qd, rd, nb2), Y = rr_fast(nb2 - 1 - qd, rd, nb2);
+  const int ix[4] = {2 * X, 2 * X + 1, 2 * Y, 2 * Y + 1};
+  T* ex = Ae + 4 * jt_index(X, X) + 1;
+  T* ey = Ae + 4 * jt_index(Y, Y) + 1;
+  T e00, e01, e10, e11;
+  jt_get<T>(At, X, Y, e00, e01, e10, e11);
+  double M[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) M[i][i] = dg[ix[i]];
+  M[0][1] = M[1][0] = (double)*ex;
+  M[2][3] = M[3][2] = (double)*ey;
+  M[0][2] = M[2][0] = (double)e00;
+  M[0][3] = M[3][0] = (double)e01;
+  M[1][2] = M[2][1] = (double)e10;
+  M[1][3] = M[3][1] = (double)e11;
+  double c0, s0, t0, c1, s1, t1, c2, s2, t2, c3, s3, t3;
+  // step 1: (x1, y1) and (x2, y2), both from the block before the step
+  jq_angle(M[0][0], M[2][2], M[0][2], thr, rel_tol, c0, s0, t0);
+  jq_angle(M[1][1], M[3][3], M[1][3], thr, rel_tol, c1, s1, t1);
+  // (padded rows and columns are zero, so their rotations are the identity
+  // already; the tests make that explicit)
+  if (ix[0] >= n || ix[2] >= n) c0 = 1.0, s0 = 0.0, t0 = 0.0;
+  if (ix[1] >= n || ix[3] >= n) c1 = 1.0, s1 = 0.0, t1 = 0.0;
+  jq_rot4<0, 2>(M, c0, s0, t0);
+  jq_rot4<1, 3>(M, c1, s1, t1);
+  // step 2: (x1, y2) and (x2, y1)
+  jq_angle(M[0][0], M[3][3], M[0][3], thr, rel_tol, c2, s2, t2);
+  jq_angle(M[1][1], M[2][2], M[1][2], thr, rel_tol, c3, s3, t3);
+  if (ix[0] >= n || ix[3] >= n) c2 = 1.0, s2 = 0.0, t2 = 0.0;
+  if (ix[1] >= n || ix[2] >= n) c3 = 1.0, s3 = 0.0, t3 = 0.0;
+  jq_rot4<0, 3>(M, c2, s2, t2);
+  jq_rot4<1, 2>(M, c3, s3, t3);
+  const bool rot = s0 != 0.0 || s1 != 0.0 || s2 != 0.0 || s3 != 0.0;
+  if (rot) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) dg[ix[i]] = M[i][i];
+    *ex = (T)M[0][1];
+    *ey = (T)M[2][3];
+    jt_put<T>(At, X, Y, (T)M[0][2], (T)M[0][3], (T)M[1][2], (T)M[1][3]);
+  }
+  qr[b * nq + qd] = X | (Y << 16) | (rot ? (int)0x80000000u : 0);
+  const double2 w0 = make_double2(c0, s0), w1 = make_double2(c1, s1), w2 = make_double2(c2, s2),
+                w3 = make_double2(c3, s3);
+  if (sizeof(T) == 4) {
+    csf[2 * (b * nq + qd)] = make_float4((float)c0, (float)s0, (float)c1, (float)s1);
+    csf[2 * (b * nq + qd) + 1] = make_float4((float)c2, (float)s2, (float)c3, (float)s3);
+  } else {
+    double2* cb = cs + 4 * (b * nq + qd);
+    cb[0] = w0;
+    cb[1] = w1;
+    cb[2] = w2;
+    cb[3] = w3;
+  }
+  lr[4 * qd] = w0;
+  lr[4 * qd + 1] = w1;
+  lr[4 * qd + 2] = w2;
+  lr[4 * qd + 3] = w3;
+  return rot;
+}
+
+// One off-diagonal block (a, b), a < b, of a round with the parameters of
+// buffer bf: returns without work when neither quartet rotated.
+template <typename T>
+__device__ inline void jq_block(int a, int b, int nq, int bf, typename JtVec<T>::type* At, const double2* cs,
+                                const float4* csf, const int* qr) {
+  const int qa = qr[bf * nq + a], qb = qr[bf * nq + b];
+  const bool ra = qa < 0, rb = qb < 0;
+  if (!ra && !rb) return;
+  T wa[8], wb[8];
+  jq_params<T>(cs + 4 * bf * nq, csf + 2 * bf * nq, a, wa);
+  jq_params<T>(cs + 4 * bf * nq, csf + 2 * bf * nq, b, wb);
+  jt_offdiag<T>(At, qa, qb, ra, rb, wa, wb);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(1024)
     k_jacobi_rot(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale, double cap_err,
@@ -1533,81 +1614,46 @@ __global__ void __launch_bounds__(1024)
       At[jt_index(a, b)] = v;
     }
     __syncthreads();
-    for (int rd = 0; rd < nb2 - 1; ++rd) {
-      double2* lr = ls + nb2 + (long long)rd * m;
-      // quartet solves: the two steps on the quartet's own 4 x 4 block
-      for (int qd = threadIdx.x; qd < nq; qd += nt) {
-        const int X = rr_fast(qd, rd, nb2), Y = rr_fast(nb2 - 1 - qd, rd, nb2);
-        const int ix[4] = {2 * X, 2 * X + 1, 2 * Y, 2 * Y + 1};
-        T* ex = Ae + 4 * jt_index(X, X) + 1;
-        T* ey = Ae + 4 * jt_index(Y, Y) + 1;
-        T e00, e01, e10, e11;
-        jt_get<T>(At, X, Y, e00, e01, e10, e11);
-        double M[4][4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) M[i][i] = dg[ix[i]];
-        M[0][1] = M[1][0] = (double)*ex;
-        M[2][3] = M[3][2] = (double)*ey;
-        M[0][2] = M[2][0] = (double)e00;
-        M[0][3] = M[3][0] = (double)e01;
-        M[1][2] = M[2][1] = (double)e10;
-        M[1][3] = M[3][1] = (double)e11;
-        double c0, s0, t0, c1, s1, t1, c2, s2, t2, c3, s3, t3;
-        // step 1: (x1, y1) and (x2, y2), both from the block before the step
-        jq_angle(M[0][0], M[2][2], M[0][2], thr, rel_tol, c0, s0, t0);
-        jq_angle(M[1][1], M[3][3], M[1][3], thr, rel_tol, c1, s1, t1);
-        // (padded rows and columns are zero, so their rotations are the
-        // identity already; the tests make that explicit)
-        if (ix[0] >= n || ix[2] >= n) c0 = 1.0, s0 = 0.0, t0 = 0.0;
-        if (ix[1] >= n || ix[3] >= n) c1 = 1.0, s1 = 0.0, t1 = 0.0;
-        jq_rot4<0, 2>(M, c0, s0, t0);
-        jq_rot4<1, 3>(M, c1, s1, t1);
-        // step 2: (x1, y2) and (x2, y1)
-        jq_angle(M[0][0], M[3][3], M[0][3], thr, rel_tol, c2, s2, t2);
-        jq_angle(M[1][1], M[2][2], M[1][2], thr, rel_tol, c3, s3, t3);
-        if (ix[0] >= n || ix[3] >= n) c2 = 1.0, s2 = 0.0, t2 = 0.0;
-        if (ix[1] >= n || ix[2] >= n) c3 = 1.0, s3 = 0.0, t3 = 0.0;
-        jq_rot4<0, 3>(M, c2, s2, t2);
-        jq_rot4<1, 2>(M, c3, s3, t3);
-        const bool rot = s0 != 0.0 || s1 != 0.0 || s2 != 0.0 || s3 != 0.0;
-        if (rot) {
-          rot_sweep = 1;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) dg[ix[i]] = M[i][i];
-          *ex = (T)M[0][1];
-          *ey = (T)M[2][3];
-          jt_put<T>(At, X, Y, (T)M[0][2], (T)M[0][3], (T)M[1][2], (T)M[1][3]);
+    // Rounds.  Round rd's quartet solves use parameter buffer rd & 1.  In
+    // the round-robin order the blocks of round rd + 1's quartets meet in
+    // the off-diagonal blocks (q - 1, q + 1), (0, 1) and (nq - 2, nq - 1) of
+    // round rd, and nothing else that round rd + 1's solves read changes in
+    // round rd's off-diagonal pass.  So wave 0 rotates those blocks first and
+    // then solves round rd + 1's quartets while the other waves rotate the
+    // remaining blocks: one barrier per round, and the FP64 quartet solves
+    // overlap the bulk of the off-diagonal work.  (Wave 0's own stores are
+    // visible to its later loads: LDS operations of a wave complete in order.)
+    const int nrd = nb2 - 1;
+    const int ncrit = nq >= 3 ? nq : (nq == 2 ? 1 : 0);
+    for (int qd = threadIdx.x; qd < nq; qd += nt)
+      if (jq_quartet<T>(qd, 0, n, nb2, nq, 0, thr, rel_tol, At, Ae, dg, cs, csf, qr, ls + nb2)) rot_sweep = 1;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int rd = 0; rd < nrd; ++rd) {
+      const int bf = rd & 1;
+      if (wave == 0) {
+        if (lane < ncrit) {
+          const int a = lane == 0 ? 0 : (lane == nq - 1 ? nq - 2 : lane - 1);
+          const int b = lane == 0 ? 1 : (lane == nq - 1 ? nq - 1 : lane + 1);
+          jq_block<T>(a, b, nq, bf, At, cs, csf, qr);
         }
-        qr[qd] = X | (Y << 16) | (rot ? (int)0x80000000u : 0);
-        const double2 w0 = make_double2(c0, s0), w1 = make_double2(c1, s1), w2 = make_double2(c2, s2),
-                      w3 = make_double2(c3, s3);
-        if (sizeof(T) == 4) {
-          csf[2 * qd] = make_float4((float)c0, (float)s0, (float)c1, (float)s1);
-          csf[2 * qd + 1] = make_float4((float)c2, (float)s2, (float)c3, (float)s3);
-        } else {
-          cs[4 * qd] = w0;
-          cs[4 * qd + 1] = w1;
-          cs[4 * qd + 2] = w2;
-          cs[4 * qd + 3] = w3;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (rd + 1 < nrd && lane < nq)
+          if (jq_quartet<T>(lane, rd + 1, n, nb2, nq, bf ^ 1, thr, rel_tol, At, Ae, dg, cs, csf, qr,
+                            ls + nb2 + (long long)(rd + 1) * m))
+            rot_sweep = 1;
+      }
+      // the remaining blocks: the other waves (wave 0 itself in a one-wave
+      // work-group)
+      const int t0 = nt > 64 ? 64 : 0;
+      if ((int)threadIdx.x >= t0)
+        for (int idx = threadIdx.x - t0; idx < nqp; idx += nt - t0) {
+          int a, b;
+          tri_pair(idx, nq, a, b);
+          if (b == a + 2 || (a == 0 && b == 1) || (a == nq - 2 && b == nq - 1)) continue;  // wave 0's
+          jq_block<T>(a, b, nq, bf, At, cs, csf, qr);
         }
-        lr[4 * qd] = w0;
-        lr[4 * qd + 1] = w1;
-        lr[4 * qd + 2] = w2;
-        lr[4 * qd + 3] = w3;
-      }
-      __syncthreads();
-      // off-diagonal blocks: rows of quartet a, columns of quartet b
-      for (int idx = threadIdx.x; idx < nqp; idx += nt) {
-        int a, b;
-        tri_pair(idx, nq, a, b);
-        const int qa = qr[a], qb = qr[b];
-        const bool ra = qa < 0, rb = qb < 0;
-        if (!ra && !rb) continue;
-        T wa[8], wb[8];
-        jq_params<T>(cs, csf, a, wa);
-        jq_params<T>(cs, csf, b, wb);
-        jt_offdiag<T>(At, qa, qb, ra, rb, wa, wb);
-      }
       __syncthreads();
     }
     if (!__syncthreads_or(rot_sweep)) {
