@@ -1252,9 +1252,8 @@ namespace fx {
 // sides in one pass.  The rotations (c, s) go to the log in HBM: per sweep
 // the m/2 block rotations, then per round four per quartet (x1 y1, x2 y2,
 // x1 y2, x2 y1); up to `max_log` sweeps.
-// k_apply_rot applies the logged rotations to C^T in 64-column tiles held in
-// LDS: a 16-lane group per quartet reads its four (c, s) and takes the
-// quartet's four rows through both steps in registers.
+// k_apply_rot applies the logged rotations to C^T, the rows in registers
+// (lane = quartet) and moved between lanes from round to round.
 // rr_index(pos, step, M) for pos <= M - 1 and step <= M - 2 (within one
 // sweep, pos - 1 + step < 2 (M - 1)): one conditional subtraction instead of
 // the modulo
@@ -1675,30 +1674,42 @@ template __global__ void k_jacobi_rot<float>(DevBatch, const int*, int, double, 
                                              long long, int, int*);
 
 // Apply the logged rotations to the rows of C^T, one 64-column tile per
-// work-group; the tile stays in LDS for all logged sweeps.  Pairs of one step
-// are disjoint and quartets of one round are disjoint, so the waves share
-// them with one barrier per step of the block step and one per round.  Block
-// step: lane = column, block k to wave k mod waves.  Rounds: quartet q to
-// 16-lane group q mod 4 of wave q / 4, each lane taking four columns of the
-// quartet's rows with 16-byte LDS accesses (on gfx950 an LDS instruction
-// costs about the same for 8 or 16 bytes per lane, so this halves the
-// instructions per rotated element, and the rotation parameters are read
-// once per four columns).
+// work-group and four columns per wave.  Lane q holds, for the wave's four
+// columns, the rows of the two blocks that quartet q pairs in the current
+// round, in registers for the whole launch: a round rotates them in place,
+// and the round-robin step to the next round moves whole blocks between
+// neighbouring lanes.  With quartet q pairing positions q and nb2 - 1 - q and
+// positions 1 .. nb2 - 1 advancing one place per round, the block in X moves
+// to lane q - 1 and the block in Y to lane q + 1, except that lane 0 keeps
+// block 0 and takes lane 1's X block as its Y, and the last quartet's Y block
+// becomes its own X.  The moves are DPP lane shifts; the rows never pass
+// through LDS and the waves need no barrier between rounds.  Only the
+// rotation parameters are staged in LDS (APPLY_RCH rounds at a time,
+// rotation-major so that each lane's 16-byte read is conflict-free).  After
+// the last round of a sweep the ring has advanced nb2 - 1 places, back to
+// the starting arrangement, in which the block step rotates each lane's two
+// blocks and the tile is stored.
 __device__ inline void jq_apply2(double& a, double& b, double2 w) {
   const double x = a, y = b;
   a = w.x * x - w.y * y;
   b = w.y * x + w.x * y;
 }
 
-// rotation w of four columns held as two double2 (row a: al, ah; row b: bl, bh)
-__device__ inline void jq_apply4(double2& al, double2& ah, double2& bl, double2& bh, double2 w) {
-  jq_apply2(al.x, bl.x, w);
-  jq_apply2(al.y, bl.y, w);
-  jq_apply2(ah.x, bh.x, w);
-  jq_apply2(ah.y, bh.y, w);
+// lane i takes lane i + 1's value (DPP wave_shl:1) or lane i - 1's
+// (wave_shr:1); the lane without a source reads zero (never used)
+__device__ inline double lane_from_next(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x130, 0xf, 0xf, true),
+                          __builtin_amdgcn_mov_dpp(lo, 0x130, 0xf, 0xf, true));
+}
+__device__ inline double lane_from_prev(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x138, 0xf, 0xf, true),
+                          __builtin_amdgcn_mov_dpp(lo, 0x138, 0xf, 0xf, true));
 }
 
 constexpr int APPLY_RCH = 8;  // rounds of rotation parameters staged in LDS at a time
+constexpr int APPLY_COLS = 4;  // columns per wave
 
 __global__ void __launch_bounds__(1024)
     k_apply_rot(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double2* __restrict__ logbuf,
@@ -1716,20 +1727,35 @@ __global__ void __launch_bounds__(1024)
   const int n = d.nao, nv = d.nao;
   const int c0 = tcol * 64;
   if (c0 >= nv) return;
-  const int m = (n + 3) & ~3, nb2 = m / 2, nq = m / 4;
-  const int NT = blockDim.x, NW = NT >> 6;
-  double* tile = reinterpret_cast<double*>(lds_raw);       // [m][64], padded rows zero
-  double2* lgs = lds_raw + (long long)m * 32;             // [APPLY_RCH][m] staged (c, s)
-  const int lane = threadIdx.x & 63, grp = lane >> 4, sub = lane & 15;
+  const int m = (n + 3) & ~3, nb2 = m / 2, nq = m / 4, nrd = nb2 - 1;
+  const int NT = blockDim.x;
+  double2* lgs = lds_raw;  // [APPLY_RCH][4][nq] staged (c, s)
+  const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int cw = c0 + APPLY_COLS * wave;  // the wave's first column
+  const bool wact = cw < nv;              // uniform in the wave
+  const int q = lane, qc = min(q, nq - 1);
+  const bool act = q < nq;
+  const bool first = q == 0, last = q == nq - 1;
   double* V = bt.Ct + d.mat_off;
-  const bool colok = c0 + lane < nv;
-  for (int i = wave; i < m; i += NW) tile[i * 64 + lane] = (colok && i < n) ? V[(long long)i * nv + c0 + lane] : 0.0;
+  // rows of quartet q's blocks in the starting arrangement: blocks q and
+  // nb2 - 1 - q (lanes past the last quartet hold zeros and never feed an
+  // active lane)
+  const int rx = 2 * q, ry = 2 * (nb2 - 1 - qc);
+  double x1[APPLY_COLS], x2[APPLY_COLS], y1[APPLY_COLS], y2[APPLY_COLS];
+#pragma unroll
+  for (int c = 0; c < APPLY_COLS; ++c) {
+    const int col = cw + c;
+    const bool ok = act && col < nv;
+    x1[c] = (ok && rx < n) ? V[(long long)rx * nv + col] : 0.0;
+    x2[c] = (ok && rx + 1 < n) ? V[(long long)(rx + 1) * nv + col] : 0.0;
+    y1[c] = (ok && ry < n) ? V[(long long)ry * nv + col] : 0.0;
+    y2[c] = (ok && ry + 1 < n) ? V[(long long)(ry + 1) * nv + col] : 0.0;
+  }
   const double2* lg = logbuf + (long long)si * log_stride;
   const long long swe = jq_sweep_entries(m);
-  const int nrd = nb2 - 1;                   // rounds per sweep
-  const int CE = APPLY_RCH * m;              // staged entries per chunk
-  const int per = (CE + NT - 1) / NT;        // <= 2 for m <= 256 and NT >= 960
+  const int CE = APPLY_RCH * m;        // staged entries per chunk
+  const int per = (CE + NT - 1) / NT;  // <= 2 for m <= 256 and NT = 1024
   double2 rg[2];
   // staged entries of rounds [r0, r0 + APPLY_RCH) of sweep sw into registers
   auto fetch = [&](int sw, int r0) {
@@ -1744,70 +1770,72 @@ __global__ void __launch_bounds__(1024)
   for (int sw = 0; sw < nsw; ++sw) {
     const double2* ls = lg + (long long)sw * swe;
     fetch(sw, 0);
-    __syncthreads();  // tile loaded / previous sweep applied
-    // block step: pairs (2k, 2k+1)
-    for (int k = wave; k < nb2; k += NW) {
-      const double2 w = ls[k];
-      if (w.y == 0.0) continue;  // identity (also every pair with a padded index)
-      double* r0 = tile + (2 * k) * 64 + lane;
-      double a = r0[0], b = r0[64];
-      jq_apply2(a, b, w);
-      r0[0] = a;
-      r0[64] = b;
+    // block step: pairs (2k, 2k+1) of the lane's two blocks
+    if (wact) {
+      const double2 wx = ls[q < nb2 ? q : 0], wy = ls[nb2 - 1 - qc];
+#pragma unroll
+      for (int c = 0; c < APPLY_COLS; ++c) {
+        jq_apply2(x1[c], x2[c], wx);
+        jq_apply2(y1[c], y2[c], wy);
+      }
     }
     for (int r0 = 0; r0 < nrd; r0 += APPLY_RCH) {
       __syncthreads();  // the previous chunk's parameters are no longer read
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         const int e = threadIdx.x + NT * r;
-        if (r < per && e < CE) lgs[e] = rg[r];
+        if (r < per && e < CE) {
+          const int j = e / m, i = e - j * m;  // round j of the chunk, entry 4 quartet + k
+          lgs[j * m + (i & 3) * nq + (i >> 2)] = rg[r];
+        }
       }
       if (r0 + APPLY_RCH < nrd) fetch(sw, r0 + APPLY_RCH);
+      __syncthreads();  // staged parameters visible
       const int r1 = min(nrd, r0 + APPLY_RCH);
+      if (!wact) continue;
       for (int rd = r0; rd < r1; ++rd) {
-        __syncthreads();  // previous round applied; staged parameters visible
-        // one quartet per 16-lane group (quartet 4 wave + group); a lane
-        // holds columns 2 sub, 2 sub + 1, 32 + 2 sub, 33 + 2 sub of the
-        // quartet's four rows (16-byte LDS accesses, each group's row segment
-        // contiguous).  Padded rows stay zero: their rotations are the
-        // identity, applied exactly.
-        const int qd = wave * 4 + grp;
-        if (qd >= nq) continue;
-        const double2* lq = lgs + (rd - r0) * m + 4 * qd;
-        const double2 w0 = lq[0], w1 = lq[1], w2 = lq[2], w3 = lq[3];
-        double2* px = reinterpret_cast<double2*>(tile + (2 * rr_fast(qd, rd, nb2)) * 64 + 2 * sub);
-        double2* py = reinterpret_cast<double2*>(tile + (2 * rr_fast(nb2 - 1 - qd, rd, nb2)) * 64 + 2 * sub);
-        // [0] row 1 low columns, [16] row 1 high, [32] row 2 low, [48] row 2 high
-        double2 x1l = px[0], x1h = px[16], x2l = px[32], x2h = px[48];
-        double2 y1l = py[0], y1h = py[16], y2l = py[32], y2h = py[48];
-        jq_apply4(x1l, x1h, y1l, y1h, w0);
-        jq_apply4(x2l, x2h, y2l, y2h, w1);
-        jq_apply4(x1l, x1h, y2l, y2h, w2);
-        jq_apply4(x2l, x2h, y1l, y1h, w3);
-        px[0] = x1l;
-        px[16] = x1h;
-        px[32] = x2l;
-        px[48] = x2h;
-        py[0] = y1l;
-        py[16] = y1h;
-        py[32] = y2l;
-        py[48] = y2h;
+        const double2* lr = lgs + (rd - r0) * m + qc;
+        const double2 w0 = lr[0], w1 = lr[nq], w2 = lr[2 * nq], w3 = lr[3 * nq];
+#pragma unroll
+        for (int c = 0; c < APPLY_COLS; ++c) {
+          jq_apply2(x1[c], y1[c], w0);
+          jq_apply2(x2[c], y2[c], w1);
+          jq_apply2(x1[c], y2[c], w2);
+          jq_apply2(x2[c], y1[c], w3);
+        }
+        if (nq > 1) {
+#pragma unroll
+          for (int c = 0; c < APPLY_COLS; ++c) {
+            const double n1 = lane_from_next(x1[c]), n2 = lane_from_next(x2[c]);
+            const double p1 = lane_from_prev(y1[c]), p2 = lane_from_prev(y2[c]);
+            const double t1 = last ? y1[c] : n1, t2 = last ? y2[c] : n2;
+            y1[c] = first ? n1 : p1;
+            y2[c] = first ? n2 : p2;
+            x1[c] = first ? x1[c] : t1;
+            x2[c] = first ? x2[c] : t2;
+          }
+        }
       }
     }
   }
-  __syncthreads();
-  if (colok)
-    for (int i = wave; i < n; i += NW) V[(long long)i * nv + c0 + lane] = tile[i * 64 + lane];
+  if (wact && act) {
+#pragma unroll
+    for (int c = 0; c < APPLY_COLS; ++c) {
+      const int col = cw + c;
+      if (col >= nv) continue;
+      if (rx < n) V[(long long)rx * nv + col] = x1[c];
+      if (rx + 1 < n) V[(long long)(rx + 1) * nv + col] = x2[c];
+      if (ry < n) V[(long long)ry * nv + col] = y1[c];
+      if (ry + 1 < n) V[(long long)(ry + 1) * nv + col] = y2[c];
+    }
+  }
 }
 
 size_t apply_rot_lds_bytes(int n) {
   const size_t m = (size_t)((n + 3) & ~3);
-  return m * 64 * 8 + (size_t)APPLY_RCH * m * 16;
+  return (size_t)APPLY_RCH * m * 16;
 }
-int apply_rot_waves(int n) {
-  const int nq = ((n + 3) & ~3) / 4;
-  return std::max(1, (nq + 3) / 4);  // four quartets per wave; 16 waves for m = 256
-}
+int apply_rot_waves(int) { return 64 / APPLY_COLS; }  // a 64-column tile
 long long jacobi_rot_log_entries(int n) {
   const long long m = (n + 3) & ~3;
   return m / 2 + (m / 2 - 1) * m;
