@@ -355,6 +355,8 @@ void Ctx::build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters,
   b.hr.alloc((long long)sh_off * HIST);
   b.eps.alloc(ao_off);
   b.occ.alloc(ao_off);
+  b.occ_idx.alloc(ao_off);
+  b.occ_cnt.alloc(ns);
   b.erep.alloc(ns);
   b.e_int.alloc(ns);
   b.e_prev.alloc(ns);
@@ -407,6 +409,8 @@ DevBatch Batch::dev() {
   d.hr = hr.p;
   d.eps = eps.p;
   d.occ = occ.p;
+  d.occ_idx = occ_idx.p;
+  d.occ_cnt = occ_cnt.p;
   d.erep = erep.p;
   d.e_int = e_int.p;
   d.e_prev = e_prev.p;
@@ -451,7 +455,8 @@ void Ctx::init_device() {
 // Batched n x n products of the listed systems (first nl entries of dlist):
 // the matrix-core kernel once a system spans more than one 32 x 32 tile.
 void Ctx::gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlist, int mode, const double* A,
-                     const double* B, double* C, const double* w, double gflop, int skip_done, int sym) {
+                     const double* B, double* C, const double* w, double gflop, int skip_done, int sym,
+                     bool occ_list) {
   if (nl <= 0) return;
   const bool timed = !capturing;
   if (b.max_nao <= 32) {
@@ -466,13 +471,13 @@ void Ctx::gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlis
     const int ev = timed ? timers.begin(stream) : -1;
     if (mode == 0)
       hipLaunchKernelGGL(k_gemm_mfma<0>, dim3((unsigned)grid), dim3(256), 0, stream, db, dlist, nl, nt * nt, A, B, C,
-                         w, skip_done, sym);
+                         w, skip_done, sym, occ_list ? 1 : 0);
     else if (mode == 1)
       hipLaunchKernelGGL(k_gemm_mfma<1>, dim3((unsigned)grid), dim3(256), 0, stream, db, dlist, nl, nt * nt, A, B, C,
-                         w, skip_done, sym);
+                         w, skip_done, sym, occ_list ? 1 : 0);
     else
       hipLaunchKernelGGL(k_gemm_mfma<2>, dim3((unsigned)grid), dim3(256), 0, stream, db, dlist, nl, nt * nt, A, B, C,
-                         w, skip_done, sym);
+                         w, skip_done, sym, occ_list ? 1 : 0);
     if (timed) timers.end(stream, ev, kt("fx::k_gemm_mfma"), gflop);
   }
   check(hipGetLastError(), "batched product");
@@ -868,7 +873,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     if (timed) timers.end(stream, ev, kt_jac, 0.0);
     }
     hipLaunchKernelGGL(k_fermi, dim3(na), dim3(256), 0, stream, ds, db, dl);
-    gemm_batch(b, db, na, dl, 2, b.Ct.p, b.Ct.p, b.Pm.p, b.occ.p, b.gemm_gflop(act), 1, 1);
+    gemm_batch(b, db, na, dl, 2, b.Ct.p, b.Ct.p, b.Pm.p, b.occ.p, b.gemm_gflop_occ(act), 1, 1, true);
     hipLaunchKernelGGL(k_charges_mix, dim3(na), dim3(256), 0, stream, ds, db, dl,
                        scc_tol_cur > 0 ? scc_tol_cur : opt.scc_tol, etol_cur > 0 ? etol_cur : opt.energy_tol,
                        single ? 1 : opt.max_iter, b.has_pre ? precond_beta : mix_beta);

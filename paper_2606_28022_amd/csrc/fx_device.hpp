@@ -111,6 +111,12 @@ struct DevBatch {
   int* status;   // 0 active, 1 converged, 2 failed
   int* niter;
   int* nhist;
+  int* occ_idx;  // [ao_off + k]: the orbitals whose occupation exceeds OCC_MIN, ascending
+  int* occ_cnt;  // per system: their number
 };
+// occupations below this bound are left out of the density product: each
+// such term changes an element of P by less than 1e-30, far below the FP64
+// rounding of any element that matters
+constexpr double OCC_MIN = 1e-30;
 
 }  // namespace fx

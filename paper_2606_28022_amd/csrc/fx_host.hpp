@@ -114,6 +114,7 @@ struct Batch {
   DevBuf<SysDesc> d_desc;
   DevBuf<int> d_atoms, d_atom_ao0, d_atom_sh0, d_sh_global, d_sh_atom, d_ao_sh, d_all, d_list;
   DevBuf<double> S, H0, Fm, Ct, Pm, Tm, gam, q_in, q_out, phi, sig, hx, hr, eps, occ;
+  DevBuf<int> occ_idx, occ_cnt;  // significant orbitals of the last occupation (k_fermi)
   DevBuf<double> erep, e_int, e_prev, mts, err;
   DevBuf<int> status, niter, nhist, sweeps;
   // Newton preconditioner (1 + M G)^-1 of the Anderson residuals (FP32,
@@ -135,6 +136,15 @@ struct Batch {
   double gemm_gflop(const std::vector<int>& l) const {
     double g = 0.0;
     for (int s : l) g += 2e-9 * std::pow((double)h_desc[s].nao, 3);
+    return g;
+  }
+  // the density product over the occupied orbitals only: 2 n^2 ceil(N_el / 2)
+  double gemm_gflop_occ(const std::vector<int>& l) const {
+    double g = 0.0;
+    for (int s : l) {
+      const double n = h_desc[s].nao, k = std::min(n, std::ceil(0.5 * h_desc[s].nel));
+      g += 2e-9 * n * n * k;
+    }
     return g;
   }
   double gemm_gflop_all() const {
@@ -320,7 +330,8 @@ struct Ctx {
   static long long jp_key(int n, int elt) { return (long long)n * 16 + elt; }
   JacobiPlan autotune_jacobi(Batch& b, const int* dl, int na, const JacobiPlan& base, double cap);
   void gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlist, int mode, const double* A,
-                  const double* B, double* C, const double* w, double gflop, int skip_done = 0, int sym = 0);
+                  const double* B, double* C, const double* w, double gflop, int skip_done = 0, int sym = 0,
+                  bool occ_list = false);
   // graph-captured SCC iterations (schedule FX_BATCHED_GRAPH)
   bool capturing = false;
   hipStream_t gstream = nullptr;

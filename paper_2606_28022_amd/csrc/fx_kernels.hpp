@@ -35,7 +35,8 @@ __global__ void k_precond_build(DevSystem sys, DevBatch bt, const int* list, Dev
                                 float* pre, int* ok);
 template <int MODE>
 __global__ void k_gemm_mfma(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double* Abase,
-                            const double* Bbase, double* Cbase, const double* wbase, int skip_done, int sym);
+                            const double* Bbase, double* Cbase, const double* wbase, int skip_done, int sym,
+                            int occ_list);
 __global__ void k_gemm(DevBatch bt, const int* list, int mode, const double* A, const double* B, double* C,
                        const double* w, int skip_done);
 __global__ void k_jacobi(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale,

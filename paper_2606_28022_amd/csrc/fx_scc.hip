@@ -294,7 +294,7 @@ template <int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
     k_gemm_mfma(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double* __restrict__ Abase,
                 const double* __restrict__ Bbase, double* __restrict__ Cbase, const double* __restrict__ wbase,
-                int skip_done, int sym) {
+                int skip_done, int sym, int occ_list) {
   const int L = blockIdx.x, G = gridDim.x;  // G is a multiple of 8
   const int logical = (L & 7) * (G >> 3) + (L >> 3);
   const int sl = logical / tiles_per_sys, tile = logical - sl * tiles_per_sys;
@@ -312,10 +312,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
   const double* B = Bbase + d.mat_off;
   double* C = Cbase + d.mat_off;
   const double* w = wbase ? wbase + d.ao_off : nullptr;
+  // mode 2 with occ_list: the sum runs over the orbitals listed by k_fermi
+  // (occupation above OCC_MIN) instead of all n
+  const bool use_list = MODE == 2 && occ_list;
+  const int nk = use_list ? bt.occ_cnt[si] : n;
   constexpr int KS = 32, LD = 66;
   __shared__ double As[KS][LD];  // [k][i]
   __shared__ double Bs[KS][LD];  // [k][j]
+  __shared__ int kxs[MODE == 2 ? MAXN : 1];  // the listed orbitals, staged once
   const int tid = threadIdx.x;
+  if (use_list) {
+    const int* kg = bt.occ_idx + d.ao_off;
+    for (int k = tid; k < nk; k += 256) kxs[k] = kg[k];
+    __syncthreads();
+  }
   const int lane = tid & 63, wave = tid >> 6;
   const int wi = wave >> 1, wj = wave & 1;
   const int i0 = ti * 64, j0 = tj * 64;
@@ -356,6 +366,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
   }
   double ra[8], rb[8];
   auto fetch = [&](int k0) {
+    if (MODE == 2 && use_list) {
+      int gk[8];
+#pragma unroll
+      for (int h = 0; h < 8; ++h) {
+        const int pk = k0 + kk_ + 4 * h;
+        gk[h] = pk < nk ? kxs[pk] : -1;
+      }
+#pragma unroll
+      for (int h = 0; h < 8; ++h) {
+        ra[h] = (a_fix && gk[h] >= 0) ? A[gk[h] * n + i0 + kr] * w[gk[h]] : 0.0;
+        rb[h] = (b_fix && gk[h] >= 0) ? B[gk[h] * n + j0 + kr] : 0.0;
+      }
+      return;
+    }
 #pragma unroll
     for (int h = 0; h < 8; ++h) {
       if (MODE == 2) {
@@ -377,7 +401,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
     b_off += b_step;
   };
   fetch(0);
-  for (int k0 = 0; k0 < n; k0 += KS) {
+  for (int k0 = 0; k0 < nk; k0 += KS) {
 #pragma unroll
     for (int h = 0; h < 8; ++h) {
       if (MODE == 2)
@@ -390,7 +414,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
         Bs[kk_ + 4 * h][kr] = rb[h];
     }
     __syncthreads();
-    if (k0 + KS < n) fetch(k0 + KS);
+    if (k0 + KS < nk) fetch(k0 + KS);
 #pragma unroll
     for (int kk = 0; kk < KS; kk += 4) {
       const int krow = kk + (lane >> 4), c = lane & 15;
@@ -419,11 +443,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 }
 
 template __global__ void k_gemm_mfma<0>(DevBatch, const int*, int, int, const double*, const double*, double*,
-                                        const double*, int, int);
+                                        const double*, int, int, int);
 template __global__ void k_gemm_mfma<1>(DevBatch, const int*, int, int, const double*, const double*, double*,
-                                        const double*, int, int);
+                                        const double*, int, int, int);
 template __global__ void k_gemm_mfma<2>(DevBatch, const int*, int, int, const double*, const double*, double*,
-                                        const double*, int, int);
+                                        const double*, int, int, int);
 
 // ---------------------------------------------------------------------------
 // Parallel cyclic Jacobi on the symmetric matrix A (in place), rotating the
@@ -667,7 +691,16 @@ __global__ void k_fermi(DevSystem sys, DevBatch bt, const int* list) {
     ts += t;
   }
   ts = block_sum(ts, red);
-  if (threadIdx.x == 0) bt.mts[si] = 2.0 * kT * ts;
+  if (threadIdx.x == 0) {
+    bt.mts[si] = 2.0 * kT * ts;
+    // orbitals that enter the density product, in ascending order
+    int c = 0;
+    const double* oc = bt.occ + d.ao_off;
+    int* ix = bt.occ_idx + d.ao_off;
+    for (int i = 0; i < n; ++i)
+      if (oc[i] > OCC_MIN) ix[c++] = i;
+    bt.occ_cnt[si] = c;
+  }
 }
 
 // ---------------------------------------------------------------------------
