@@ -29,8 +29,12 @@ void explicit_terms(Ctx& c, Batch& b, const double* wsys, DevBuf<double>& g_sys,
   std::vector<int> all(b.nsys);
   for (int k = 0; k < b.nsys; ++k) all[k] = k;
   b.d_list.upload(all);
-  // W = C diag(n eps) C^T into T, D_S into F
-  c.gemm_batch(b, db, (int)b.nsys, b.d_list.p, 2, b.Ct.p, b.Ct.p, b.Tm.p, (const double*)wvec.p, b.gemm_gflop_all());
+  // W = C diag(n eps) C^T into T (symmetric; over the orbitals of the last
+  // occupation list, whose weights n eps vanish with n), D_S into F
+  std::vector<int> all_sys(b.nsys);
+  for (int k = 0; k < b.nsys; ++k) all_sys[k] = k;
+  c.gemm_batch(b, db, (int)b.nsys, b.d_list.p, 2, b.Ct.p, b.Ct.p, b.Tm.p, (const double*)wvec.p,
+               b.gemm_gflop_occ(all_sys), 0, 1, true);
   hipLaunchKernelGGL(k_make_DS, dim3(b.nsys), dim3(256), 0, c.stream, db, b.Pm.p, b.Tm.p, b.Fm.p);
   int natot = 0;
   for (auto& d : b.h_desc) natot += d.nat;
