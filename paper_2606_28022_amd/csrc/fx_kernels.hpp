@@ -71,9 +71,10 @@ __host__ __device__ inline JacobiLdsLayout jacobi_lds_layout(int n, int elt, int
 // / 2 tiles of four elt-byte elements, m = n rounded up to a multiple of
 // four), FP64 diagonal (m), (c, s) of the block step and of two consecutive
 // rounds (double2; the FP32 form keeps the rounds' as two float4 per
-// quartet), the quartets' blocks of two rounds, a reduction slot
+// quartet), the quartets' blocks of two rounds, the table of quartet pairs,
+// a reduction slot
 struct JacobiRotLayout {
-  unsigned ap, dg, cs, csf, qr, red, total;
+  unsigned ap, dg, cs, csf, qr, pt, red, total;
 };
 __host__ __device__ inline JacobiRotLayout jacobi_rot_layout(int n, int elt) {
   const unsigned m = (unsigned)(n + 3) & ~3u, nb2 = m / 2u;
@@ -89,6 +90,8 @@ __host__ __device__ inline JacobiRotLayout jacobi_rot_layout(int n, int elt) {
   o = jl_align(o + (elt == 4 ? 16u * m : 0u));
   L.qr = o;  // per quartet of two rounds: its blocks X | Y << 16, sign bit: rotates
   o = jl_align(o + 8u * (m / 4u));
+  L.pt = o;  // quartet pairs a | b << 8 (| 1 << 16: wave 0's) of the off-diagonal pass
+  o = jl_align(o + 4u * (m / 4u) * (m / 4u - 1u) / 2u);
   L.red = o;
   o = jl_align(o + 8u * 64u);
   L.total = o;

@@ -1565,7 +1565,8 @@ __global__ void __launch_bounds__(1024)
   double* dg = reinterpret_cast<double*>(lds + L.dg);
   double2* cs = reinterpret_cast<double2*>(lds + L.cs);  // [m]: block step [nb2], then 4 per quartet
   float4* csf = reinterpret_cast<float4*>(lds + L.csf);  // FP32: the quartets' (c, s), 2 per quartet
-  int* qr = reinterpret_cast<int*>(lds + L.qr);          // [nq] X | Y << 16, sign bit: rotates
+  int* qr = reinterpret_cast<int*>(lds + L.qr);          // [2][nq] X | Y << 16, sign bit: rotates
+  int* pt = reinterpret_cast<int*>(lds + L.pt);          // [nq (nq - 1) / 2] quartet pairs
   double* red = reinterpret_cast<double*>(lds + L.red);
   double* rows = reinterpret_cast<double*>(cs);  // row sums before the sweeps (16 m >= 8 n bytes)
   const double* __restrict__ A = bt.F + d.mat_off;
@@ -1573,6 +1574,14 @@ __global__ void __launch_bounds__(1024)
   const int ntile = nb2 * (nb2 + 1) / 2;
   for (int e = threadIdx.x; e < 4 * ntile; e += nt) Ae[e] = (T)0;
   for (int i = threadIdx.x; i < m; i += nt) dg[i] = 0.0;
+  // off-diagonal pass: pairs (a, b), a < b, of quartets; flagged: the blocks
+  // that hold the next round's quartets (wave 0 rotates them first, see below)
+  for (int idx = threadIdx.x; idx < nq * (nq - 1) / 2; idx += nt) {
+    int a, b;
+    tri_pair(idx, nq, a, b);
+    const bool crit = b == a + 2 || (a == 0 && b == 1) || (a == nq - 2 && b == nq - 1);
+    pt[idx] = a | (b << 8) | (crit ? 1 << 16 : 0);
+  }
   __syncthreads();
   for (int e = threadIdx.x; e < n * n; e += nt) {
     const int i = e / n, j = e - i * n;
@@ -1681,10 +1690,9 @@ __global__ void __launch_bounds__(1024)
       const int t0 = nt > 64 ? 64 : 0;
       if ((int)threadIdx.x >= t0)
         for (int idx = threadIdx.x - t0; idx < nqp; idx += nt - t0) {
-          int a, b;
-          tri_pair(idx, nq, a, b);
-          if (b == a + 2 || (a == 0 && b == 1) || (a == nq - 2 && b == nq - 1)) continue;  // wave 0's
-          jq_block<T>(a, b, nq, bf, At, cs, csf, qr);
+          const int e = pt[idx];
+          if (e >> 16) continue;  // wave 0's
+          jq_block<T>(e & 255, (e >> 8) & 255, nq, bf, At, cs, csf, qr);
         }
       __syncthreads();
     }
