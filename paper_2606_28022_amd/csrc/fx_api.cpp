@@ -849,13 +849,13 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
                            jacobi_max_sweeps, jacobi_tol, jacobi_thr_scale, cap, b.sweeps.p, b.rotlog.p, log_stride,
                            jacobi_max_log, b.nlog.p);
       if (timed) timers.end(stream, ev, kt_rot, 0.0);
-      const int tps = (b.max_nao + 63) / 64;
+      const int tw = apply_rot_tile(b.max_nao);
+      const int tps = (b.max_nao + tw - 1) / tw;
       const long long grid = ((long long)na * tps + 7) / 8 * 8;
       ev = timed ? timers.begin(stream) : -1;
       const unsigned lds_app = (unsigned)apply_rot_lds_bytes(b.max_nao);
       hipLaunchKernelGGL(k_apply_rot, dim3((unsigned)grid), dim3(64 * apply_rot_waves(b.max_nao)), lds_app, stream,
-                         db, dl,
-                         na, tps, (const double2*)b.rotlog.p, log_stride, (const int*)b.nlog.p);
+                         db, dl, na, tps, tw, (const double2*)b.rotlog.p, log_stride, (const int*)b.nlog.p);
       if (timed) timers.end(stream, ev, kt_app, 0.0);
       last_split = true;
     } else {

@@ -98,6 +98,7 @@ __host__ __device__ inline JacobiRotLayout jacobi_rot_layout(int n, int elt) {
   return L;
 }
 size_t apply_rot_lds_bytes(int n);
+int apply_rot_tile(int n);  // columns per work-group of k_apply_rot (64 or 128)
 int apply_rot_waves(int n);
 long long jacobi_rot_log_entries(int n);  // rotation log entries per sweep
 template <typename T>
@@ -109,8 +110,8 @@ template <typename T>
 __global__ void k_jacobi_rot(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale,
                              double cap_err, int* sweeps_out, double2* logbuf, long long log_stride, int max_log,
                              int* nlog);
-__global__ void k_apply_rot(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double2* logbuf,
-                            long long log_stride, const int* nlog);
+__global__ void k_apply_rot(DevBatch bt, const int* list, int nl, int tiles_per_sys, int tile_w,
+                            const double2* logbuf, long long log_stride, const int* nlog);
 template <typename T>
 __global__ void k_jacobi_lds(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale,
                              double cap_err, int* sweeps_out, int chunk);

@@ -1753,8 +1753,8 @@ constexpr int APPLY_RCH = 8;  // rounds of rotation parameters staged in LDS at 
 constexpr int APPLY_COLS = 4;  // columns per wave
 
 __global__ void __launch_bounds__(1024)
-    k_apply_rot(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double2* __restrict__ logbuf,
-                long long log_stride, const int* nlog) {
+    k_apply_rot(DevBatch bt, const int* list, int nl, int tiles_per_sys, int tile_w,
+                const double2* __restrict__ logbuf, long long log_stride, const int* nlog) {
   extern __shared__ double2 lds_raw[];
   const int Lid = blockIdx.x, G = gridDim.x;  // G is a multiple of 8
   const int logical = (Lid & 7) * (G >> 3) + (Lid >> 3);
@@ -1766,16 +1766,22 @@ __global__ void __launch_bounds__(1024)
   if (nsw <= 0) return;
   const SysDesc d = bt.desc[si];
   const int n = d.nao, nv = d.nao;
-  const int c0 = tcol * 64;
+  // tile_w 128 (every system of the batch has at most 32 quartets): each
+  // half-wave takes its own four columns with the same quartets (no active
+  // lane reads across the half boundary: lane 31 moves only as the last
+  // quartet, which takes its own Y, and lane 32 only as quartet 0)
+  const bool packed = tile_w == 128;
+  const int c0 = tcol * tile_w;
   if (c0 >= nv) return;
   const int m = (n + 3) & ~3, nb2 = m / 2, nq = m / 4, nrd = nb2 - 1;
   const int NT = blockDim.x;
   double2* lgs = lds_raw;  // [APPLY_RCH][4][nq] staged (c, s)
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int cw = c0 + APPLY_COLS * wave;  // the wave's first column
-  const bool wact = cw < nv;              // uniform in the wave
-  const int q = lane, qc = min(q, nq - 1);
+  const int wcols = packed ? 2 * APPLY_COLS : APPLY_COLS;
+  const bool wact = c0 + wcols * wave < nv;  // uniform in the wave
+  const int cw = c0 + wcols * wave + (packed ? APPLY_COLS * (lane >> 5) : 0);  // the lane's first column
+  const int q = packed ? (lane & 31) : lane, qc = min(q, nq - 1);
   const bool act = q < nq;
   const bool first = q == 0, last = q == nq - 1;
   double* V = bt.Ct + d.mat_off;
@@ -1872,6 +1878,7 @@ __global__ void __launch_bounds__(1024)
   }
 }
 
+int apply_rot_tile(int n) { return ((n + 3) & ~3) <= 128 ? 128 : 64; }
 size_t apply_rot_lds_bytes(int n) {
   const size_t m = (size_t)((n + 3) & ~3);
   return (size_t)APPLY_RCH * m * 16;

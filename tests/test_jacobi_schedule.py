@@ -97,3 +97,43 @@ def test_apply_lane_moves_follow_the_rounds(m):
                     nxt.append((from_next, from_prev))
             lanes = nxt
     assert lanes == [(q, nb2 - 1 - q) for q in range(nq)]
+
+
+def wave_step(X, Y, nq, half):
+    """One round-to-round move of the apply kernel over a 64-lane wave: DPP
+    wave_shl:1 (lane i reads i + 1) and wave_shr:1 (lane i reads i - 1), then
+    the per-lane choices; half = 32 when two column sets share the wave."""
+    L = len(X)
+    shl = [X[i + 1] if i + 1 < L else 0 for i in range(L)]
+    shr = [Y[i - 1] if i >= 1 else 0 for i in range(L)]
+    nX, nY = list(X), list(Y)
+    for lane in range(L):
+        q = lane % half
+        first, last = q == 0, q == nq - 1
+        t = Y[lane] if last else shl[lane]
+        nY[lane] = shl[lane] if first else shr[lane]
+        nX[lane] = X[lane] if first else t
+    return nX, nY
+
+
+@pytest.mark.parametrize("m", SIZES)
+def test_apply_wave_moves_with_two_column_sets(m):
+    """The DPP moves over the whole wave keep each half's quartets right,
+    also when two column sets share a wave (m <= 128): no active lane reads a
+    value from the other half."""
+    nb2, nq = m // 2, m // 4
+    half = 32 if m <= 128 else 64
+    sets = 64 // half
+    # lanes past the last quartet carry a marker that must never reach an active lane
+    X = [(lane // half, lane % half) if lane % half < nq else ("idle", lane) for lane in range(64)]
+    Y = [(lane // half, nb2 - 1 - lane % half) if lane % half < nq else ("idle", lane) for lane in range(64)]
+    for rd in range(nb2 - 1):
+        for s in range(sets):
+            got = [(X[s * half + q], Y[s * half + q]) for q in range(nq)]
+            want = [((s, a), (s, b)) for a, b in quartets(m, rd)]
+            assert got == want, (m, rd, s)
+        if nq > 1:
+            X, Y = wave_step(X, Y, nq, half)
+    for s in range(sets):
+        assert [(X[s * half + q], Y[s * half + q]) for q in range(nq)] == \
+            [((s, q), (s, nb2 - 1 - q)) for q in range(nq)]
