@@ -1594,7 +1594,8 @@ void Ctx::run(fx_result* out) {
   if (nesd > 0) {
     DevBuf<int> dp;
     dp.upload(esd_pairs);
-    hipLaunchKernelGGL(k_esd_pairs, dim3((unsigned)((nesd + 127) / 128)), dim3(128), 0, stream, dev_system(), dp.p,
+    if (nesd > 0x7fffffffLL) throw FxError(FX_E_INVALID, "too many ES-DIM pairs");
+    hipLaunchKernelGGL(k_esd_pairs, dim3((unsigned)nesd), dim3(64), 0, stream, dev_system(), dp.p,
                        nesd, d_frag_atoms.p, d_frag_off.p, d_q.p, dE_esd.p);
     check(hipGetLastError(), "k_esd_pairs");
     sync();

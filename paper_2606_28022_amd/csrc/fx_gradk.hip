@@ -347,6 +347,7 @@ __global__ void k_force_inter(DevSystem sys, const double* q, const double* av, 
   int per = (N + nchunk - 1) / nchunk;
   int b_begin = chunk * per, b_end = min(N, b_begin + per);
   __shared__ double sx[256], sy[256], sz[256], seta[256][MAXSH_EL], sq[256][MAXSH_EL], sa_[256][MAXSH_EL];
+  __shared__ double sio[256][MAXSH_EL];  // 1/(2 eta) per source shell (kg = 2)
   __shared__ int sf[256], sn[256];
   double xa = 0, ya = 0, za = 0, ea[MAXSH_EL] = {1.0, 1.0}, qa[MAXSH_EL] = {0, 0}, aa[MAXSH_EL] = {0, 0};
   int fa = -1, na = 0;
@@ -364,6 +365,13 @@ __global__ void k_force_inter(DevSystem sys, const double* q, const double* av, 
     }
   }
   double f[3] = {0.0, 0.0, 0.0};
+  // kg = 2: gamma = (R^2 + c^2)^(-1/2), c = iota_s + iota_t, and
+  // dgamma/dR / R = -gamma^3 (no square root or division; an absent second
+  // shell has q = a = 0 and adds exactly zero)
+  const bool kg2 = sys.g.kg == 2.0;
+  double ia[MAXSH_EL] = {0.5, 0.5};
+  if (A < N)
+    for (int k = 0; k < na; ++k) ia[k] = sys.sh_ieta[sys.atom_sh0[A] + k];
   for (int b0 = b_begin; b0 < b_end; b0 += 256) {
     int b = b0 + threadIdx.x;
     __syncthreads();
@@ -377,13 +385,32 @@ __global__ void k_force_inter(DevSystem sys, const double* q, const double* av, 
       sn[threadIdx.x] = nsb;
       for (int k = 0; k < MAXSH_EL; ++k) {
         seta[threadIdx.x][k] = k < nsb ? sys.sh_eta[s0 + k] : 1.0;
+        sio[threadIdx.x][k] = k < nsb ? sys.sh_ieta[s0 + k] : 0.5;
         sq[threadIdx.x][k] = k < nsb ? q[s0 + k] : 0.0;
         sa_[threadIdx.x][k] = k < nsb ? av[s0 + k] : 0.0;
       }
     }
     __syncthreads();
     int nb = min(256, b_end - b0);
-    if (A < N) {
+    if (A < N && kg2) {
+      for (int k = 0; k < nb; ++k) {
+        if (sf[k] == fa) continue;
+        const double dx = xa - sx[k], dy = ya - sy[k], dz = za - sz[k];
+        const double R2 = dx * dx + dy * dy + dz * dz;
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < MAXSH_EL; ++u)
+#pragma unroll
+          for (int v = 0; v < MAXSH_EL; ++v) {
+            const double c = ia[u] + sio[k][v];
+            const double x = rsqrt(R2 + c * c);
+            acc -= (qa[u] * (sq[k][v] + sa_[k][v]) + aa[u] * sq[k][v]) * (x * x * x);
+          }
+        f[0] += acc * dx;
+        f[1] += acc * dy;
+        f[2] += acc * dz;
+      }
+    } else if (A < N) {
       for (int k = 0; k < nb; ++k) {
         if (sf[k] == fa) continue;
         double dx = xa - sx[k], dy = ya - sy[k], dz = za - sz[k];

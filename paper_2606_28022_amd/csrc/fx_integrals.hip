@@ -528,26 +528,47 @@ __global__ void k_vhop(DevBatch bt, double vhop) {
 }
 
 // ES-DIM pair energies dq^I gamma_IJ dq^J for a list of pairs.
-__global__ void k_esd_pairs(DevSystem sys, const int* pairs, long long npairs, const int* frag_atoms,
-                            const int* frag_off, const double* q, double* out) {
-  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per ES-DIM pair (I, J): lane = atom of I, J's atoms taken in
+// turn by the whole wave (uniform loads); with kg = 2 the kernel
+// (R^2 + (iota_s + iota_t)^2)^(-1/2) with iota = 1/(2 eta), as in the field
+// pass; lane sums combined by a fixed butterfly (deterministic).
+__global__ void __launch_bounds__(64) k_esd_pairs(DevSystem sys, const int* pairs, long long npairs,
+                                                  const int* frag_atoms, const int* frag_off, const double* q,
+                                                  double* out) {
+  const long long k = blockIdx.x;
   if (k >= npairs) return;
-  int I = pairs[2 * k], J = pairs[2 * k + 1];
+  const int lane = threadIdx.x;
+  const int I = pairs[2 * k], J = pairs[2 * k + 1];
+  const int j0 = frag_off[J], j1 = frag_off[J + 1];
+  const bool kg2 = sys.g.kg == 2.0;
   double acc = 0.0;
-  for (int ia = frag_off[I]; ia < frag_off[I + 1]; ++ia) {
-    int a = frag_atoms[ia];
-    double xa = sys.xyz[3 * a], ya = sys.xyz[3 * a + 1], za = sys.xyz[3 * a + 2];
-    int sa0 = sys.atom_sh0[a], sa1 = sys.atom_sh0[a + 1];
-    for (int ib = frag_off[J]; ib < frag_off[J + 1]; ++ib) {
-      int b = frag_atoms[ib];
-      double dx = xa - sys.xyz[3 * b], dy = ya - sys.xyz[3 * b + 1], dz = za - sys.xyz[3 * b + 2];
-      double R2 = dx * dx + dy * dy + dz * dz;
-      int sb0 = sys.atom_sh0[b], sb1 = sys.atom_sh0[b + 1];
-      for (int s = sa0; s < sa1; ++s)
-        for (int t = sb0; t < sb1; ++t) acc += q[s] * gamma_fn(sys.g, R2, sys.sh_eta[s], sys.sh_eta[t]) * q[t];
+  for (int ia = frag_off[I] + lane; ia < frag_off[I + 1]; ia += 64) {
+    const int a = frag_atoms[ia];
+    const double xa = sys.xyz[3 * a], ya = sys.xyz[3 * a + 1], za = sys.xyz[3 * a + 2];
+    const int sa0 = sys.atom_sh0[a], nsa = sys.atom_sh0[a + 1] - sa0;
+    const double qa0 = q[sa0], qa1 = nsa > 1 ? q[sa0 + 1] : 0.0;
+    const double ia0 = sys.sh_ieta[sa0], ia1 = nsa > 1 ? sys.sh_ieta[sa0 + 1] : 0.5;
+    for (int ib = j0; ib < j1; ++ib) {
+      const int b = frag_atoms[ib];
+      const double dx = xa - sys.xyz[3 * b], dy = ya - sys.xyz[3 * b + 1], dz = za - sys.xyz[3 * b + 2];
+      const double R2 = dx * dx + dy * dy + dz * dz;
+      const int sb0 = sys.atom_sh0[b], nsb = sys.atom_sh0[b + 1] - sb0;
+      if (kg2) {
+        // an absent second shell carries q = 0 and adds exactly zero
+        const double qb0 = q[sb0], qb1 = nsb > 1 ? q[sb0 + 1] : 0.0;
+        const double ib0 = sys.sh_ieta[sb0], ib1 = nsb > 1 ? sys.sh_ieta[sb0 + 1] : 0.5;
+        const double t00 = ia0 + ib0, t01 = ia0 + ib1, t10 = ia1 + ib0, t11 = ia1 + ib1;
+        acc += qa0 * (rsqrt(R2 + t00 * t00) * qb0 + rsqrt(R2 + t01 * t01) * qb1) +
+               qa1 * (rsqrt(R2 + t10 * t10) * qb0 + rsqrt(R2 + t11 * t11) * qb1);
+      } else {
+        for (int s = sa0; s < sa0 + nsa; ++s)
+          for (int t = sb0; t < sb0 + nsb; ++t) acc += q[s] * gamma_fn(sys.g, R2, sys.sh_eta[s], sys.sh_eta[t]) * q[t];
+      }
     }
   }
-  out[k] = acc;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) out[k] = acc;
 }
 
 }  // namespace fx
