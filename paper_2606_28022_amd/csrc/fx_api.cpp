@@ -1028,7 +1028,11 @@ void Ctx::field(const double* d_q, double* d_phi, bool fp32) {
 }
 
 void Ctx::compute_cn() {
-  hipLaunchKernelGGL(k_cn, dim3((N + 255) / 256), dim3(256), 0, stream, dev_system(), d_cn.p);
+  const int gA = (N + 255) / 256;
+  const int nchunk = std::max(1, std::min(64, 2048 / std::max(1, gA)));
+  if ((long long)nchunk * N > field_part.n) field_part.alloc((long long)nchunk * N);
+  hipLaunchKernelGGL(k_cn, dim3(gA, nchunk), dim3(256), 0, stream, dev_system(), nchunk, field_part.p);
+  hipLaunchKernelGGL(k_field_reduce, dim3(gA), dim3(256), 0, stream, N, nchunk, field_part.p, d_cn.p);
   if (NB > 0)
     hipLaunchKernelGGL(k_ghost_cn, dim3((NB + 255) / 256), dim3(256), 0, stream, dev_system(), d_bonds.p, NB, d_cn.p);
   check(hipGetLastError(), "k_cn");

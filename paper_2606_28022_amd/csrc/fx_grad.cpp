@@ -345,7 +345,14 @@ void Ctx::gradient() {
   const unsigned gA = (unsigned)((N + 255) / 256);
   hipLaunchKernelGGL(k_gather_atoms, dim3(gA), dim3(256), 0, stream, N, d_rp.p, d_eb.p, d_eo.p, d_gb.p, d_fb.p,
                      d_grad.p, Ftot.p, 0);
-  hipLaunchKernelGGL(k_cn_grad, dim3(gA), dim3(256), 0, stream, ds, Ftot.p, d_grad.p);
+  {
+    const int nchunk = std::max(1, std::min(64, 2048 / (int)gA));
+    DevBuf<double> part;
+    part.alloc((long long)nchunk * 3 * N);
+    hipLaunchKernelGGL(k_cn_grad, dim3(gA, nchunk), dim3(256), 0, stream, ds, Ftot.p, nchunk, part.p);
+    hipLaunchKernelGGL(k_force_reduce, dim3((unsigned)((3 * N + 255) / 256)), dim3(256), 0, stream, N, nchunk, part.p,
+                       d_grad.p);
+  }
   // inter-fragment kernel derivatives with a = qbar + u
   hipLaunchKernelGGL(k_axpy, dim3((unsigned)((Nsh + 255) / 256)), dim3(256), 0, stream, (long long)Nsh, qbar.p, 1.0,
                      u.p, a.p);

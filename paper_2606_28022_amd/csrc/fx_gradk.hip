@@ -442,11 +442,16 @@ __global__ void k_force_reduce(int N, int nchunk, const double* part, double* ou
 }
 
 // CN chain: g_C = sum_{A != C} (F_A + F_C) f'(R_AC) (R_C - R_A) / R_AC
-__global__ void k_cn_grad(DevSystem sys, const double* Ftot, double* g) {
-  int C = blockIdx.x * blockDim.x + threadIdx.x;
+// (partners split into nchunk slices as in k_cn; part[(chunk N + C) 3 + k]
+// over the N real atoms, summed by k_force_reduce)
+__global__ void k_cn_grad(DevSystem sys, const double* Ftot, int nchunk, double* part) {
+  const int C = blockIdx.x * blockDim.x + threadIdx.x;
+  const int NR = sys.nreal, N = sys.nreal, chunk = blockIdx.y;
+  const int per = (NR + nchunk - 1) / nchunk;
+  const int b_begin = chunk * per, b_end = min(NR, b_begin + per);
   __shared__ double sx[256], sy[256], sz[256], sr[256], sF[256];
   double xc = 0, yc = 0, zc = 0, rc = 0, Fc = 0;
-  if (C < sys.nreal) {
+  if (C < NR) {
     xc = sys.xyz[3 * C];
     yc = sys.xyz[3 * C + 1];
     zc = sys.xyz[3 * C + 2];
@@ -454,10 +459,10 @@ __global__ void k_cn_grad(DevSystem sys, const double* Ftot, double* g) {
     Fc = Ftot[C];
   }
   double f[3] = {0.0, 0.0, 0.0};
-  for (int b0 = 0; b0 < sys.nreal; b0 += 256) {
+  for (int b0 = b_begin; b0 < b_end; b0 += 256) {
     int b = b0 + threadIdx.x;
     __syncthreads();
-    if (b < sys.nreal) {
+    if (b < b_end) {
       sx[threadIdx.x] = sys.xyz[3 * b];
       sy[threadIdx.x] = sys.xyz[3 * b + 1];
       sz[threadIdx.x] = sys.xyz[3 * b + 2];
@@ -465,25 +470,25 @@ __global__ void k_cn_grad(DevSystem sys, const double* Ftot, double* g) {
       sF[threadIdx.x] = Ftot[b];
     }
     __syncthreads();
-    int nb = min(256, sys.nreal - b0);
-    if (C < sys.nreal) {
+    int nb = min(256, b_end - b0);
+    if (C < NR) {
       for (int k = 0; k < nb; ++k) {
         if (b0 + k == C) continue;
         double dx = xc - sx[k], dy = yc - sy[k], dz = zc - sz[k];
-        double R = sqrt(dx * dx + dy * dy + dz * dz);
+        const double ri = rsqrt(dx * dx + dy * dy + dz * dz);  // 1 / R
         double rcs = rc + sr[k];
-        double x = -sys.g.k1 * (sys.g.k2 * rcs / R - 1.0);
+        double x = -sys.g.k1 * (sys.g.k2 * rcs * ri - 1.0);
         double fv = 1.0 / (1.0 + exp(x));
-        double dfdR = -fv * (1.0 - fv) * sys.g.k1 * sys.g.k2 * rcs / (R * R);
-        double w = (sF[k] + Fc) * dfdR / R;
+        // df/dR / R = -f (1 - f) k1 k2 rcs / R^3
+        double w = (sF[k] + Fc) * (-fv * (1.0 - fv) * sys.g.k1 * sys.g.k2 * rcs * (ri * ri * ri));
         f[0] += w * dx;
         f[1] += w * dy;
         f[2] += w * dz;
       }
     }
   }
-  if (C < sys.nreal)
-    for (int k = 0; k < 3; ++k) g[3 * C + k] = f[k];
+  if (C < N)
+    for (int k = 0; k < 3; ++k) part[((long long)chunk * N + C) * 3 + k] = f[k];
 }
 
 // Per-atom gather of the per-system contributions in a fixed order.

@@ -24,40 +24,45 @@ __device__ inline double gamma_fn(const DevGlobals& g, double R2, double eta_s, 
 }
 
 // ---------------------------------------------------------------------------
-// coordination numbers: one thread per atom, all partners (no cutoff)
-__global__ void k_cn(DevSystem sys, double* cn_out) {
-  int A = blockIdx.x * blockDim.x + threadIdx.x;
+// coordination numbers: one thread per atom, all partners (no cutoff); the
+// partners are split into nchunk slices over the second grid dimension
+// (enough work-groups to fill the chip), whose partial sums k_field_reduce
+// adds in fixed order
+__global__ void k_cn(DevSystem sys, int nchunk, double* part) {
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = sys.nreal, chunk = blockIdx.y;
+  const int per = (N + nchunk - 1) / nchunk;
+  const int b_begin = chunk * per, b_end = min(N, b_begin + per);
   __shared__ double sx[256], sy[256], sz[256], sr[256];
   double xa = 0, ya = 0, za = 0, ra = 0;
-  if (A < sys.nreal) {
+  if (A < N) {
     xa = sys.xyz[3 * A];
     ya = sys.xyz[3 * A + 1];
     za = sys.xyz[3 * A + 2];
     ra = sys.elems[sys.elem[A]].rcov;
   }
   double acc = 0.0;
-  for (int b0 = 0; b0 < sys.nreal; b0 += 256) {
+  for (int b0 = b_begin; b0 < b_end; b0 += 256) {
     int b = b0 + threadIdx.x;
     __syncthreads();
-    if (b < sys.nreal) {
+    if (b < b_end) {
       sx[threadIdx.x] = sys.xyz[3 * b];
       sy[threadIdx.x] = sys.xyz[3 * b + 1];
       sz[threadIdx.x] = sys.xyz[3 * b + 2];
       sr[threadIdx.x] = sys.elems[sys.elem[b]].rcov;
     }
     __syncthreads();
-    int nb = min(256, sys.nreal - b0);
-    if (A < sys.nreal) {
+    int nb = min(256, b_end - b0);
+    if (A < N) {
       for (int k = 0; k < nb; ++k) {
         if (b0 + k == A) continue;
         double dx = xa - sx[k], dy = ya - sy[k], dz = za - sz[k];
-        double R = sqrt(dx * dx + dy * dy + dz * dz);
-        double x = -sys.g.k1 * (sys.g.k2 * (ra + sr[k]) / R - 1.0);
+        double x = -sys.g.k1 * (sys.g.k2 * (ra + sr[k]) * rsqrt(dx * dx + dy * dy + dz * dz) - 1.0);
         acc += 1.0 / (1.0 + exp(x));
       }
     }
   }
-  if (A < sys.nreal) cn_out[A] = acc;
+  if (A < N) part[(long long)chunk * N + A] = acc;
 }
 
 // ---------------------------------------------------------------------------

@@ -8,7 +8,7 @@
 namespace fx {
 
 // integrals / lists / fields (fx_integrals.hip)
-__global__ void k_cn(DevSystem sys, double* cn_out);
+__global__ void k_cn(DevSystem sys, int nchunk, double* part);
 __global__ void k_pair_contacts(DevSystem sys, const int* frag_atoms, const int* frag_off, int rule, double cut2,
                                 double lam2, double lam3, int8_t* flag);
 __global__ void k_build_system(DevSystem sys, DevBatch bt, const int* list);
@@ -161,7 +161,7 @@ __global__ void k_grad_pair_corr(DevSystem sys, DevBatch bt, const double* qmono
 __global__ void k_scale_cluster(DevBatch bt, const double* w, const double* src, double* dst);
 __global__ void k_force_inter(DevSystem sys, const double* q, const double* av, int nchunk, double* part);
 __global__ void k_force_reduce(int N, int nchunk, const double* part, double* out);
-__global__ void k_cn_grad(DevSystem sys, const double* Ftot, double* g);
+__global__ void k_cn_grad(DevSystem sys, const double* Ftot, int nchunk, double* part);
 __global__ void k_gather_atoms(int N, const int* rowptr, const int* ent_batch, const long long* ent_off,
                                const double* const* g_batches, const double* const* F_batches, double* g_tot,
                                double* F_tot, int mode);
