@@ -540,14 +540,17 @@ void Ctx::build_precond(Batch& b) {
   if (!precond || !resp_ok || b.nsys == 0) return;
   int nsmax = 0;
   for (const auto& d : b.h_desc) nsmax = std::max(nsmax, d.nsh);
-  const unsigned bytes = (unsigned)nsmax * (unsigned)nsmax * 4u;
-  if ((int)bytes > lds_max - 16384 || nsmax > MAXN) return;
+  int ncmax = 1;  // largest component (monomer) of any system, in shells
+  for (const auto& d : mb.h_desc) ncmax = std::max(ncmax, d.nsh);
+  const unsigned kb = (unsigned)nsmax * (unsigned)nsmax * 4u, mrow = 16u * 8u * (unsigned)ncmax + 8u;
+  if ((int)(kb + mrow) > lds_max - 16384 || nsmax > MAXN) return;
+  const unsigned bytes = kb + mrow;
   b.pre.alloc(std::max(1LL, b.tot_gam));
   DevBuf<int> ok;
   ok.alloc(b.nsys);
   DevBatch db = b.dev();
   hipLaunchKernelGGL(k_precond_build, dim3(b.nsys), dim3(1024), bytes, stream, dev_system(), db, b.d_all.p, mb.dev(),
-                     (const double*)resp_M.p, b.pre.p, ok.p);
+                     (const double*)resp_M.p, b.pre.p, ok.p, ncmax);
   check(hipGetLastError(), "k_precond_build");
   std::vector<int> h;
   ok.download(h, stream);

@@ -32,7 +32,7 @@ __global__ void k_warm_start(DevBatch bt, const long long* mat_off_old, const lo
                              const double* Cold, const double* qold);
 __global__ void k_fock(DevSystem sys, DevBatch bt, const int* list);
 __global__ void k_precond_build(DevSystem sys, DevBatch bt, const int* list, DevBatch mono, const double* Mmono,
-                                float* pre, int* ok);
+                                float* pre, int* ok, int ncmax);
 template <int MODE>
 __global__ void k_gemm_mfma(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double* Abase,
                             const double* Bbase, double* Cbase, const double* wbase, int skip_done, int sym,

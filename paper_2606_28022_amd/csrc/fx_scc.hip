@@ -1133,8 +1133,10 @@ namespace fx {
 // the identity are written when a pivot vanishes.
 __global__ void __launch_bounds__(1024)
     k_precond_build(DevSystem sys, DevBatch bt, const int* list, DevBatch mono, const double* Mmono, float* pre,
-                    int* ok) {
-  extern __shared__ float Kf[];  // ns x ns
+                    int* ok, int ncmax) {
+  // LDS: K (ns x ns, FP32), then one row of the monomer susceptibility per
+  // wave (ncmax doubles each)
+  extern __shared__ float Kf[];
   __shared__ double qa[MAXN];
   __shared__ float colk[MAXN], rowk[MAXN];
   __shared__ int perm[MAXN];
@@ -1162,26 +1164,33 @@ __global__ void __launch_bounds__(1024)
     qa[a] = v;
   }
   __syncthreads();
-  // K = 1 + M G' (a wave per row, lanes over columns)
+  // K = 1 + M G' (a wave per row, lanes over columns): the row of M is
+  // gathered once per row into the wave's LDS slot (instead of two dependent
+  // loads per term)
   const int* smap = bt.sh_mono + d.sh_off;
+  double* mrow = reinterpret_cast<double*>(Kf + ((ns * ns + 1) & ~1)) + wave * ncmax;
   for (int s = wave; s < ns; s += nw) {
     int c = 0;
     while (c + 1 < d.nfrag && s >= comp_off[c + 1]) ++c;
-    const int k0 = comp_off[c], k1 = comp_off[c + 1];
+    const int k0 = comp_off[c], nc = comp_off[c + 1] - k0;
     const SysDesc md = mono.desc[comp_frag[c]];
     const double* Mr = Mmono + md.gam_off + (long long)smap[s] * md.nsh;
+    for (int k = lane; k < nc; k += 64) mrow[k] = Mr[smap[k0 + k]];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
     for (int t = lane; t < ns; t += 64) {
       const int at = bt.sys_sh_atom[d.sh_off + t];
-      const int Aat = bt.sys_atoms[d.atom_off + at];
-      const double g3 = 2.0 * sys.elems[sys.elem[Aat]].Gamma * qa[at];
+      const double g3 = 2.0 * sys.elems[sys.elem[bt.sys_atoms[d.atom_off + at]]].Gamma * qa[at];
       double v = (s == t) ? 1.0 : 0.0;
-      for (int k = k0; k < k1; ++k) {
-        double g = G[(long long)k * ns + t];
-        if (bt.sys_sh_atom[d.sh_off + k] == at) g -= g3;
-        v += Mr[smap[k]] * g;
+      for (int k = 0; k < nc; ++k) {
+        double g = G[(long long)(k0 + k) * ns + t];
+        if (bt.sys_sh_atom[d.sh_off + k0 + k] == at) g -= g3;
+        v += mrow[k] * g;
       }
       Kf[s * ns + t] = (float)v;
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();  // the slot is rewritten for the next row
   }
   __syncthreads();
   // Gauss-Jordan with partial pivoting (largest |K[i][k]|, i >= k, lowest
