@@ -1879,7 +1879,7 @@ __global__ void __launch_bounds__(1024)
   // in one coalesced write instead of tile_w / 4 partial-line pieces from
   // different waves (which cost 2.5 times the algorithmic HBM writes).
   double* st = reinterpret_cast<double*>(lds_raw);
-  const int band = m;
+  const int band = m, ld = tile_w + 1;  // padded row: a wave's lanes (one row each) spread over the banks
   const int ccol = cw - c0;                      // the lane's first column within the tile
   for (int r0 = 0; r0 < n; r0 += band) {
     __syncthreads();  // the area is free (parameters read / previous band written)
@@ -1891,14 +1891,14 @@ __global__ void __launch_bounds__(1024)
         if (r < 0 || r >= band) continue;
 #pragma unroll
         for (int c = 0; c < APPLY_COLS; ++c)
-          st[r * tile_w + ccol + c] = h == 0 ? x1[c] : h == 1 ? x2[c] : h == 2 ? y1[c] : y2[c];
+          st[r * ld + ccol + c] = h == 0 ? x1[c] : h == 1 ? x2[c] : h == 2 ? y1[c] : y2[c];
       }
     }
     __syncthreads();
     const int nr = min(band, n - r0);
     for (int e = threadIdx.x; e < nr * tile_w; e += NT) {
-      const int r = e / tile_w, col = c0 + (e - r * tile_w);
-      if (col < nv) V[(long long)(r0 + r) * nv + col] = st[e];
+      const int r = e / tile_w, cc = e - r * tile_w, col = c0 + cc;
+      if (col < nv) V[(long long)(r0 + r) * nv + col] = st[r * ld + cc];
     }
   }
 }
@@ -1906,7 +1906,7 @@ __global__ void __launch_bounds__(1024)
 int apply_rot_tile(int n) { return ((n + 3) & ~3) <= 128 ? 128 : 64; }
 size_t apply_rot_lds_bytes(int n) {
   const size_t m = (size_t)((n + 3) & ~3);
-  return std::max((size_t)APPLY_RCH * m * 16, m * (size_t)apply_rot_tile(n) * 8);  // parameters, then the tile
+  return std::max((size_t)APPLY_RCH * m * 16, m * (size_t)(apply_rot_tile(n) + 1) * 8);  // parameters, then the tile
 }
 int apply_rot_waves(int) { return 64 / APPLY_COLS; }  // a 64-column tile
 long long jacobi_rot_log_entries(int n) {
