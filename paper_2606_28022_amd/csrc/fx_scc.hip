@@ -1798,16 +1798,29 @@ __global__ void __launch_bounds__(1024)
   // nb2 - 1 - q (lanes past the last quartet hold zeros and never feed an
   // active lane)
   const int rx = 2 * q, ry = 2 * (nb2 - 1 - qc);
+  // the tile comes in through LDS (whole-row reads; padded rows and columns
+  // past the matrix are zero), the same area and padded row length as the
+  // store at the end
+  double* st = reinterpret_cast<double*>(lds_raw);
+  const int ld = tile_w + 1;  // padded row: a wave's lanes (one row each) spread over the banks
+  const int ccol = cw - c0;   // the lane's first column within the tile
+  for (int e = threadIdx.x; e < m * tile_w; e += NT) {
+    const int r = e / tile_w, cc = e - r * tile_w, col = c0 + cc;
+    st[r * ld + cc] = (r < n && col < nv) ? V[(long long)r * nv + col] : 0.0;
+  }
+  __syncthreads();
   double x1[APPLY_COLS], x2[APPLY_COLS], y1[APPLY_COLS], y2[APPLY_COLS];
+  const int rxc = 2 * qc;  // (addresses inside the tile for every lane)
 #pragma unroll
   for (int c = 0; c < APPLY_COLS; ++c) {
-    const int col = cw + c;
-    const bool ok = act && col < nv;
-    x1[c] = (ok && rx < n) ? V[(long long)rx * nv + col] : 0.0;
-    x2[c] = (ok && rx + 1 < n) ? V[(long long)(rx + 1) * nv + col] : 0.0;
-    y1[c] = (ok && ry < n) ? V[(long long)ry * nv + col] : 0.0;
-    y2[c] = (ok && ry + 1 < n) ? V[(long long)(ry + 1) * nv + col] : 0.0;
+    const double a = st[rxc * ld + ccol + c], b = st[(rxc + 1) * ld + ccol + c];
+    const double u = st[ry * ld + ccol + c], v = st[(ry + 1) * ld + ccol + c];
+    x1[c] = act ? a : 0.0;
+    x2[c] = act ? b : 0.0;
+    y1[c] = act ? u : 0.0;
+    y2[c] = act ? v : 0.0;
   }
+  __syncthreads();  // the area is reused for the rotation parameters
   const double2* lg = logbuf + (long long)si * log_stride;
   const long long swe = jq_sweep_entries(m);
   const int CE = APPLY_RCH * m;        // staged entries per chunk
@@ -1875,12 +1888,10 @@ __global__ void __launch_bounds__(1024)
     }
   }
   // Store the tile through LDS (the parameter area, sized by the host for
-  // the whole m x tile_w tile), so that each row segment of the tile leaves
-  // in one coalesced write instead of tile_w / 4 partial-line pieces from
-  // different waves (which cost 2.5 times the algorithmic HBM writes).
-  double* st = reinterpret_cast<double*>(lds_raw);
-  const int band = m, ld = tile_w + 1;  // padded row: a wave's lanes (one row each) spread over the banks
-  const int ccol = cw - c0;                      // the lane's first column within the tile
+  // the whole padded m x tile_w tile), so that each row segment of the tile
+  // leaves in one coalesced write instead of tile_w / 4 partial-line pieces
+  // from different waves (which cost 2.5 times the algorithmic HBM writes).
+  const int band = m;
   for (int r0 = 0; r0 < n; r0 += band) {
     __syncthreads();  // the area is free (parameters read / previous band written)
     if (wact && act) {
