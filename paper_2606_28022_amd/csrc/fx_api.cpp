@@ -1013,6 +1013,20 @@ int Ctx::solve_batch(Batch& b, bool cold, long long* iters_out) {
   return failed;
 }
 
+void Ctx::max_absdiff(const double* a, const double* b, int n, double* out) {
+  const int np = std::max(1, std::min(64, (n + 2047) / 2048));
+  if (red_part.n < 64LL * 36) red_part.alloc(64LL * 36);
+  hipLaunchKernelGGL(k_absdiff_part, dim3(np), dim3(256), 0, stream, a, b, n, red_part.p);
+  hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, stream, red_part.p, np, out);
+}
+
+void Ctx::hist_coef(const double* R, long long n, const Slots& sl, double* coef) {
+  const int np = (int)std::max(1LL, std::min(64LL, (n + 2047) / 2048));
+  if (red_part.n < 64LL * 36) red_part.alloc(64LL * 36);  // 64 partials of HIST (HIST + 1) / 2 = 36
+  hipLaunchKernelGGL(k_hist_gram_part, dim3(np), dim3(256), 0, stream, R, n, sl, red_part.p);
+  hipLaunchKernelGGL(k_hist_solve, dim3(1), dim3(64), 0, stream, red_part.p, np, sl, coef);
+}
+
 void Ctx::field(const double* d_q, double* d_phi, bool fp32) {
   const int nchunk = std::max(1, std::min(64, (Ne + 255) / 256 > 0 ? 2048 / ((Ne + 255) / 256) : 1));
   if ((long long)nchunk * Nsh > field_part.n) field_part.alloc((long long)nchunk * Nsh);
@@ -1364,10 +1378,9 @@ void Ctx::run(fx_result* out) {
   double delta = 1e300;
   bool cold = true;
   // Anderson mixing of the monomer charge vector across sweeps
-  DevBuf<double> hX, hR, hB, hC;
+  DevBuf<double> hX, hR, hC;
   hX.alloc((long long)HIST * Nsh);
   hR.alloc((long long)HIST * Nsh);
-  hB.alloc(HIST * HIST);
   hC.alloc(HIST);
   std::vector<int> slots;
   int next_slot = 0;
@@ -1423,7 +1436,7 @@ void Ctx::run(fx_result* out) {
     cold = false;
     res.solves_mono += mb.nsys;
     hipLaunchKernelGGL(k_scatter_shell, dim3(mb.nsys), dim3(64), 0, stream, dmb, mb.q_out.p, d_qnew.p);
-    hipLaunchKernelGGL(k_max_absdiff, dim3(1), dim3(256), 0, stream, d_qnew.p, d_q.p, Nsh, d_scalar.p);
+    max_absdiff(d_qnew.p, d_q.p, Nsh, d_scalar.p);
     std::vector<double> hs(1);
     d_scalar.download(hs, stream, 1);
     sync();
@@ -1465,8 +1478,7 @@ void Ctx::run(fx_result* out) {
     Slots sl;
     sl.m = (int)slots.size();
     for (int k = 0; k < sl.m; ++k) sl.id[k] = slots[k];
-    hipLaunchKernelGGL(k_hist_gram, dim3(sl.m * sl.m), dim3(256), 0, stream, hR.p, (long long)Nsh, sl, hB.p);
-    hipLaunchKernelGGL(k_hist_coef, dim3(1), dim3(1), 0, stream, hB.p, sl, hC.p);
+    hist_coef(hR.p, (long long)Nsh, sl, hC.p);
     hipLaunchKernelGGL(k_hist_mix, dim3(gN), dim3(256), 0, stream, hX.p, hR.p, (long long)Nsh, sl, hC.p,
                        fused_mode ? fused_beta : macro_beta, d_q.p);
     check(hipGetLastError(), "monomer mixing");

@@ -29,10 +29,25 @@ __global__ void k_scatter_shell(DevBatch bt, const double* src_local, double* ds
     dst_global[bt.sys_sh_global[d.sh_off + s]] = src_local[d.sh_off + s];
 }
 
-__global__ void k_max_absdiff(const double* a, const double* b, int n, double* out) {
+// max |a - b| in two stages: one partial per work-group (grid-stride), then
+// one work-group over the partials (the maximum does not depend on the order)
+__global__ void k_absdiff_part(const double* a, const double* b, int n, double* part) {
   __shared__ double red[256];
   double m = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, fabs(a[i] - b[i]));
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) m = fmax(m, fabs(a[i] - b[i]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_max_reduce(const double* part, int np, double* out) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) m = fmax(m, part[i]);
   red[threadIdx.x] = m;
   __syncthreads();
   for (int w = blockDim.x / 2; w > 0; w >>= 1) {
@@ -110,35 +125,66 @@ __global__ void k_sum_neumaier(const double* const* arrays, const long long* len
 // Anderson (Pulay) mixing of a long vector (the monomer charges of the
 // self-consistent embedding).  History slots are passed oldest first.
 // B_ij = r_i . r_j, one work-group per (i, j), fixed-order tree reduction
-__global__ void k_hist_gram(const double* R, long long n, Slots sl, double* B) {
-  int i = blockIdx.x / sl.m, j = blockIdx.x % sl.m;
-  const double* a = R + (long long)sl.id[i] * n;
-  const double* b = R + (long long)sl.id[j] * n;
-  __shared__ double red[256];
-  double v = 0.0;
-  for (long long k = threadIdx.x; k < n; k += blockDim.x) v += a[k] * b[k];
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
+// Gram matrix of the history residuals in one pass over them: each
+// work-group accumulates all m (m + 1) / 2 products of its slice (grid-stride)
+// and writes them to part[block][HIST_TRI]; k_hist_solve adds the partials in
+// block order (deterministic).
+constexpr int HIST_TRI = HIST * (HIST + 1) / 2;
+__global__ void __launch_bounds__(256) k_hist_gram_part(const double* R, long long n, Slots sl, double* part) {
+  const int m = sl.m;
+  double acc[HIST_TRI];
+#pragma unroll
+  for (int t = 0; t < HIST_TRI; ++t) acc[t] = 0.0;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x) {
+    double r[HIST];
+#pragma unroll
+    for (int i = 0; i < HIST; ++i) r[i] = i < m ? R[(long long)sl.id[i] * n + k] : 0.0;
+    int t = 0;
+#pragma unroll
+    for (int i = 0; i < HIST; ++i)
+#pragma unroll
+      for (int j = i; j < HIST; ++j) acc[t++] += r[i] * r[j];
   }
-  if (threadIdx.x == 0) B[i * sl.m + j] = red[0];
+  __shared__ double red[4][HIST_TRI];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < HIST_TRI; ++t) {
+    double v = acc[t];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) red[wave][t] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < HIST_TRI)
+    part[(long long)blockIdx.x * HIST_TRI + threadIdx.x] =
+        red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
 }
 
+// B_ij from the partials (block order), then the mixing coefficients:
 // minimise |sum c_k r_k| subject to sum c_k = 1 (bordered normal equations,
-// Gaussian elimination with partial pivoting); one thread
-__global__ void k_hist_coef(const double* B, Slots sl, double* coef) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Gaussian elimination with partial pivoting, in LDS by one thread)
+__global__ void k_hist_solve(const double* part, int np, Slots sl, double* coef) {
   const int m = sl.m, M = m + 1;
-  double A[(HIST + 1) * (HIST + 1)], rhs[HIST + 1];
+  __shared__ double tri[HIST_TRI];
+  __shared__ double A[(HIST + 1) * (HIST + 1)], rhs[HIST + 1];
+  for (int t = threadIdx.x; t < HIST_TRI; t += blockDim.x) {
+    double v = 0.0;
+    for (int p = 0; p < np; ++p) v += part[(long long)p * HIST_TRI + t];
+    tri[t] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  auto Bij = [&](int i, int j) {
+    const int a = i < j ? i : j, b = i < j ? j : i;
+    return tri[a * HIST - a * (a - 1) / 2 + (b - a)];  // row a of the packed upper triangle
+  };
   double tr = 0.0;
-  for (int i = 0; i < m; ++i) tr += B[i * m + i];
+  for (int i = 0; i < m; ++i) tr += Bij(i, i);
   for (int i = 0; i < M; ++i) {
     rhs[i] = (i == m) ? 1.0 : 0.0;
     for (int j = 0; j < M; ++j) {
       double v;
-      if (i < m && j < m) v = B[i * m + j] + (i == j ? 1e-14 * tr : 0.0);
+      if (i < m && j < m) v = Bij(i, j) + (i == j ? 1e-14 * tr : 0.0);
       else if (i == m && j == m) v = 0.0;
       else v = 1.0;
       A[i * M + j] = v;

@@ -230,13 +230,12 @@ void Ctx::gradient() {
     hipLaunchKernelGGL(k_resp_R, dim3(b.nsys), dim3(256), 0, stream, ds, dmb, p_M, Wk.p, R.p);
     check(hipGetLastError(), "response setup");
     // adjoint sweeps y = v + field_excl(u(y)), Anderson-accelerated
-    DevBuf<double> yg, yng, hX, hR, hB, hC, fu;
+    DevBuf<double> yg, yng, hX, hR, hC, fu;
     yg.alloc(Nsh);
     yng.alloc(Nsh);
     fu.alloc(Nsh);
     hX.alloc((long long)HIST * Nsh);
     hR.alloc((long long)HIST * Nsh);
-    hB.alloc(HIST * HIST);
     hC.alloc(HIST);
     check(hipMemcpyAsync(yg.p, v.p, sizeof(double) * Nsh, hipMemcpyDeviceToDevice, stream), "copy");
     std::vector<int> slots;
@@ -250,7 +249,7 @@ void Ctx::gradient() {
       hipLaunchKernelGGL(k_scatter_shell, dim3(b.nsys), dim3(64), 0, stream, dmb, ul.p, u.p);
       field(u.p, fu.p);
       hipLaunchKernelGGL(k_axpy, dim3(gN), dim3(256), 0, stream, (long long)Nsh, v.p, 1.0, fu.p, yng.p);
-      hipLaunchKernelGGL(k_max_absdiff, dim3(1), dim3(256), 0, stream, yng.p, yg.p, Nsh, d_scalar.p);
+      max_absdiff(yng.p, yg.p, Nsh, d_scalar.p);
       std::vector<double> hs(1);
       d_scalar.download(hs, stream, 1);
       sync();
@@ -269,8 +268,7 @@ void Ctx::gradient() {
       Slots sl;
       sl.m = (int)slots.size();
       for (int k = 0; k < sl.m; ++k) sl.id[k] = slots[k];
-      hipLaunchKernelGGL(k_hist_gram, dim3(sl.m * sl.m), dim3(256), 0, stream, hR.p, (long long)Nsh, sl, hB.p);
-      hipLaunchKernelGGL(k_hist_coef, dim3(1), dim3(1), 0, stream, hB.p, sl, hC.p);
+      hist_coef(hR.p, (long long)Nsh, sl, hC.p);
       hipLaunchKernelGGL(k_hist_mix, dim3(gN), dim3(256), 0, stream, hX.p, hR.p, (long long)Nsh, sl, hC.p, 1.0,
                          yg.p);
       check(hipGetLastError(), "response mixing");

@@ -315,6 +315,11 @@ struct Ctx {
                   const int32_t* fchg, int32_t n_bonds, const int32_t* bonds);
   void build_lists_impl();
   void compute_cn();
+  // max |a - b| over n entries into *out (device), and the Anderson mixing
+  // coefficients of the history residuals R (slots sl, n entries each)
+  DevBuf<double> red_part;
+  void max_absdiff(const double* a, const double* b, int n, double* out);
+  void hist_coef(const double* R, long long n, const Slots& sl, double* coef);
   void field(const double* d_q, double* d_phi, bool fp32 = false);
   void build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters, int nfrag_each);
   void build_matrices(Batch& b);

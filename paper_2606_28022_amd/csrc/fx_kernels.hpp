@@ -124,12 +124,13 @@ __global__ void k_charges_mix(DevSystem sys, DevBatch bt, const int* list, doubl
 // FMO assembly (fx_fmo.hip)
 __global__ void k_gather_shell(DevBatch bt, const double* src_global, double* dst_local);
 __global__ void k_scatter_shell(DevBatch bt, const double* src_local, double* dst_global);
-__global__ void k_max_absdiff(const double* a, const double* b, int n, double* out);
+__global__ void k_absdiff_part(const double* a, const double* b, int n, double* part);
+__global__ void k_max_reduce(const double* part, int np, double* out);
 __global__ void k_cluster_terms(DevBatch bt, const double* qmono, const double* e_mono, double* ddq, double* dEV,
                                 double* dE);
 __global__ void k_sum_neumaier(const double* const* arrays, const long long* lens, int narrays, double* out);
-__global__ void k_hist_gram(const double* R, long long n, Slots sl, double* B);
-__global__ void k_hist_coef(const double* B, Slots sl, double* coef);
+__global__ void k_hist_gram_part(const double* R, long long n, Slots sl, double* part);
+__global__ void k_hist_solve(const double* part, int np, Slots sl, double* coef);
 __global__ void k_hist_mix(const double* X, const double* R, long long n, Slots sl, const double* coef, double beta,
                            double* q);
 __global__ void k_hist_store(const double* x, const double* y, long long n, int slot, double* X, double* R);
