@@ -1732,10 +1732,11 @@ template __global__ void k_jacobi_rot<float>(DevBatch, const int*, int, double, 
 // positions 1 .. nb2 - 1 advancing one place per round, the block in X moves
 // to lane q - 1 and the block in Y to lane q + 1, except that lane 0 keeps
 // block 0 and takes lane 1's X block as its Y, and the last quartet's Y block
-// becomes its own X.  The moves are DPP lane shifts; the rows never pass
-// through LDS and the waves need no barrier between rounds.  Only the
-// rotation parameters are staged in LDS (APPLY_RCH rounds at a time,
-// rotation-major so that each lane's 16-byte read is conflict-free).  After
+// becomes its own X.  The moves are DPP lane shifts; during the rounds the
+// rows stay in registers and the waves need no barrier between rounds.  Only
+// the rotation parameters are staged in LDS then (APPLY_RCH rounds at a time,
+// rotation-major so that each lane's 16-byte read is conflict-free); the tile
+// enters and leaves through the same LDS area in whole-row accesses.  After
 // the last round of a sweep the ring has advanced nb2 - 1 places, back to
 // the starting arrangement, in which the block step rotates each lane's two
 // blocks and the tile is stored.
