@@ -446,7 +446,8 @@ void Ctx::init_device() {
                         reinterpret_cast<const void*>(k_jacobi_rot<float>),
                         reinterpret_cast<const void*>(k_apply_rot),
                         reinterpret_cast<const void*>(k_cholinv_lds<double>),
-                        reinterpret_cast<const void*>(k_cholinv_lds<float>)})
+                        reinterpret_cast<const void*>(k_cholinv_lds<float>),
+                        reinterpret_cast<const void*>(k_cholinv_block2)})
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
   (void)hipGetLastError();
   if (verbose) std::fprintf(stderr, "[fx] LDS per workgroup %d B, static %u B\n", v, stat);
@@ -791,7 +792,33 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
         gemm_batch(b, db, nl, b.d_list.p, 0, b.Tm.p, b.Ct.p, b.Fm.p, (const double*)nullptr, gf);
         check(hipMemcpyAsync(b.Ct.p, b.Fm.p, sizeof(double) * b.tot_mat, hipMemcpyDeviceToDevice, stream), "copy");
       } else {
-        cholinv(b.Fm.p, b.Pm.p);
+        // two-fragment clusters all started from their monomers: the factor
+        // of I - X^T X (half the order) gives the same inverse factor
+        bool block2 = chol_elt == 4 && !b.has_warm;
+        int n1max = 0, n2max = 0;
+        for (int k = 0; block2 && k < nl; ++k) {
+          const SysDesc& sd = b.h_desc[list[k]];
+          if (sd.nfrag != 2) {
+            block2 = false;
+            break;
+          }
+          const int n1 = mb.h_desc[sd.frag[0]].nao;
+          n1max = std::max(n1max, n1);
+          n2max = std::max(n2max, sd.nao - n1);
+        }
+        if (block2 && (long long)cholinv_block2_lds_bytes(n1max, n2max) <= lds_max) {
+          const int ev = capturing ? -1 : timers.begin(stream);
+          hipLaunchKernelGGL(k_cholinv_block2, dim3(nl), dim3(CHOL_THREADS_HOST),
+                             (unsigned)cholinv_block2_lds_bytes(n1max, n2max), stream, db, b.d_list.p, mb.dev(),
+                             (const double*)b.Fm.p, b.Pm.p);
+          // the factor and inverse of the n/2 block plus the two n/2 products: about n^3 / 6
+          double g2 = 0.0;
+          for (int k = 0; k < nl; ++k) g2 += 1e-9 * std::pow((double)b.h_desc[list[k]].nao, 3) / 6.0;
+          if (!capturing) timers.end(stream, ev, kt("fx::k_cholinv_block2"), g2);
+          check(hipGetLastError(), "k_cholinv_block2");
+        } else {
+          cholinv(b.Fm.p, b.Pm.p);
+        }
         gemm_batch(b, db, nl, b.d_list.p, 0, b.Pm.p, b.Ct.p, b.Tm.p, (const double*)nullptr, gf);
         if (chol_elt == 4)
           refine_rows();

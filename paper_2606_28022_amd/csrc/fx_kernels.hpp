@@ -105,6 +105,8 @@ template <typename T>
 __global__ void k_cholinv_lds(DevBatch bt, const int* list, const double* Apool, double* Xpool);
 __global__ void k_ns_poly(DevBatch bt, const int* list, double* Hpool, const double* H2pool);
 size_t cholinv_lds_bytes(int n, int elt);
+__global__ void k_cholinv_block2(DevBatch bt, const int* list, DevBatch mono, const double* Apool, double* Xpool);
+size_t cholinv_block2_lds_bytes(int n1, int n2);
 constexpr int CHOL_THREADS_HOST = 1024;
 template <typename T>
 __global__ void k_jacobi_rot(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale,

@@ -1944,32 +1944,16 @@ constexpr int CHOL_THREADS = 1024;
 
 __device__ inline int tri_index(int i, int j) { return i * (i + 1) / 2 + j; }  // j <= i
 
+// Factor and invert in place the packed lower triangle L (n x n, loaded):
+// afterwards L holds L^-1.  col and dinv: n + 1 doubles of LDS scratch.
+// Returns false (uniformly) on a non-positive pivot.
 template <typename T>
-__global__ void __launch_bounds__(CHOL_THREADS)
-    k_cholinv_lds(DevBatch bt, const int* list, const double* __restrict__ Apool, double* __restrict__ Xpool) {
-  extern __shared__ double2 lds_raw[];
-  const int si = list[blockIdx.x];
-  const SysDesc d = bt.desc[si];
-  const int n = d.nao;
-  const int ntri = n * (n + 1) / 2;
-  T* L = reinterpret_cast<T*>(lds_raw);
-  double* col = reinterpret_cast<double*>(lds_raw) + (ntri * (int)sizeof(T) + 7) / 8;
-  double* dinv = col + n;
-  const double* A = Apool + d.mat_off;
-  double* X = Xpool + d.mat_off;
+__device__ bool chol_inv_packed(T* L, int n, double* col, double* dinv) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, nwave = nth >> 6;
-  for (int e = tid; e < n * n; e += nth) {
-    const int i = e / n, j = e - i * n;
-    if (j <= i) L[tri_index(i, j)] = (T)A[e];
-  }
-  __syncthreads();
   for (int k = 0; k < n; ++k) {
     const double dkk = (double)L[tri_index(k, k)];
-    if (!(dkk > 0.0)) {  // same value in every thread: uniform exit
-      if (tid == 0) bt.status[si] = 2;
-      return;
-    }
+    if (!(dkk > 0.0)) return false;  // same value in every thread: uniform exit
     const double rp = 1.0 / sqrt(dkk);
     for (int i = k + 1 + tid; i < n; i += nth) {
       const T v = (T)((double)L[tri_index(i, k)] * rp);
@@ -2009,10 +1993,106 @@ __global__ void __launch_bounds__(CHOL_THREADS)
     }
     __syncthreads();
   }
+  return true;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(CHOL_THREADS)
+    k_cholinv_lds(DevBatch bt, const int* list, const double* __restrict__ Apool, double* __restrict__ Xpool) {
+  extern __shared__ double2 lds_raw[];
+  const int si = list[blockIdx.x];
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao;
+  const int ntri = n * (n + 1) / 2;
+  T* L = reinterpret_cast<T*>(lds_raw);
+  double* col = reinterpret_cast<double*>(lds_raw) + (ntri * (int)sizeof(T) + 7) / 8;
+  double* dinv = col + n;
+  const double* A = Apool + d.mat_off;
+  double* X = Xpool + d.mat_off;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  for (int e = tid; e < n * n; e += nth) {
+    const int i = e / n, j = e - i * n;
+    if (j <= i) L[tri_index(i, j)] = (T)A[e];
+  }
+  __syncthreads();
+  if (!chol_inv_packed<T>(L, n, col, dinv)) {
+    if (tid == 0) bt.status[si] = 2;
+    return;
+  }
   for (int e = tid; e < n * n; e += nth) {
     const int i = e / n, j = e - i * n;
     X[e] = j <= i ? (double)L[tri_index(i, j)] : 0.0;
   }
+}
+
+// The same inverse factor for a two-fragment cluster started from its
+// monomers' orbitals: G = C0^T S C0 = [[I, X], [X^T, I]] (the monomer blocks
+// are the identity to FP64 rounding), so L = [[I, 0], [X^T, L22]] with
+// L22 L22^T = I - X^T X, and L^-1 = [[I, 0], [-L22^-1 X^T, L22^-1]]: one
+// factor of half the order instead of the whole.  FP32 in LDS (the caller
+// refines the rows as after k_cholinv_lds<float>).  A non-positive pivot
+// sets status 2.
+__global__ void __launch_bounds__(CHOL_THREADS)
+    k_cholinv_block2(DevBatch bt, const int* list, DevBatch mono, const double* __restrict__ Apool,
+                     double* __restrict__ Xpool) {
+  extern __shared__ double2 lds_raw[];
+  const int si = list[blockIdx.x];
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao, n1 = mono.desc[d.frag[0]].nao, n2 = n - n1;
+  const int t2 = n2 * (n2 + 1) / 2;
+  float* L = reinterpret_cast<float*>(lds_raw);  // packed lower triangle, n2
+  float* XT = L + ((t2 + 3) & ~3);                // X^T, n2 x n1
+  double* col = reinterpret_cast<double*>(XT + (((long long)n2 * n1 + 3) & ~3));
+  double* dinv = col + n2;
+  const double* A = Apool + d.mat_off;
+  double* X = Xpool + d.mat_off;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  for (int e = tid; e < n2 * n1; e += nth) {
+    const int i = e / n1, j = e - i * n1;
+    XT[e] = (float)A[(long long)(n1 + i) * n + j];
+  }
+  __syncthreads();
+  // I - X^T X, lower triangle
+  for (int e = tid; e < t2; e += nth) {
+    int i = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
+    while (i * (i + 1) / 2 > e) --i;
+    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+    const int k = e - i * (i + 1) / 2;
+    const float* a = XT + (long long)i * n1;
+    const float* b = XT + (long long)k * n1;
+    double v = i == k ? 1.0 : 0.0;
+    for (int j = 0; j < n1; ++j) v -= (double)a[j] * (double)b[j];
+    L[e] = (float)v;
+  }
+  __syncthreads();
+  if (!chol_inv_packed<float>(L, n2, col, dinv)) {
+    if (tid == 0) bt.status[si] = 2;
+    return;
+  }
+  // rows of L^-1: [I 0] for the first fragment, [-L22^-1 X^T, L22^-1] below
+  for (long long e = tid; e < (long long)n * n; e += nth) {
+    const int i = (int)(e / n), j = (int)(e - (long long)i * n);
+    double v;
+    if (i < n1) {
+      v = i == j ? 1.0 : 0.0;
+    } else if (j >= n1) {
+      const int a = i - n1, b = j - n1;
+      v = b <= a ? (double)L[tri_index(a, b)] : 0.0;
+    } else {
+      const int a = i - n1;
+      const float* lr = L + tri_index(a, 0);
+      double s = 0.0;
+      for (int k = 0; k <= a; ++k) s += (double)lr[k] * (double)XT[(long long)k * n1 + j];
+      v = -s;
+    }
+    X[e] = v;
+  }
+}
+
+size_t cholinv_block2_lds_bytes(int n1, int n2) {
+  const size_t t2 = ((size_t)n2 * (n2 + 1) / 2 + 3) & ~(size_t)3;
+  const size_t xt = ((size_t)n2 * n1 + 3) & ~(size_t)3;
+  return (t2 + xt) * 4 + (size_t)n2 * 8 + 16;
 }
 
 template __global__ void k_cholinv_lds<double>(DevBatch, const int*, const double*, double*);
