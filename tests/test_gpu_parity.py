@@ -250,9 +250,10 @@ def test_graph_schedule_matches_batched(lib, which):
 
 @pytest.mark.parametrize("which", ["c1", "pentacene6"])
 def test_mixed_precision_matches_fp64(lib, which):
-    """FX_MIXED (FP32 working matrices and early FP32 field passes, FP64
-    basis and final iterations) reaches the FP64 results within the FP64
-    tolerances: fragment energies 1e-8 Eh, gradient 1e-7 Eh/bohr."""
+    """FX_MIXED (FP32 working matrices, early FP32 field passes in the monomer
+    loop and the response sweeps, FP64 basis and final iterations) reaches
+    the FP64 results within the FP64 tolerances: fragment energies 1e-8 Eh,
+    gradient 1e-7 Eh/bohr."""
     _say(f"mixed precision {which}")
     s = w.water_cluster_cube() if which == "c1" else w.pentacene_crystal(reps=(2, 2, 1)).subset(list(range(6)))
     c = lib()
