@@ -119,4 +119,15 @@ struct DevBatch {
 // rounding of any element that matters
 constexpr double OCC_MIN = 1e-30;
 
+// 1/sqrt(x) for positive finite x (the damped Coulomb kernels, where
+// x = R^2 + c^2 with c > 0): the hardware estimate y followed by one step of
+// the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ..., e = 1 - x y^2, which
+// triples the number of correct bits; no handling of zero, infinite or NaN
+// arguments, which these callers never pass.
+__device__ inline double rsqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y, y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
 }  // namespace fx

@@ -394,7 +394,6 @@ __global__ void k_force_inter(DevSystem sys, const double* q, const double* av, 
     int nb = min(256, b_end - b0);
     if (A < N && kg2) {
       for (int k = 0; k < nb; ++k) {
-        if (sf[k] == fa) continue;
         const double dx = xa - sx[k], dy = ya - sy[k], dz = za - sz[k];
         const double R2 = dx * dx + dy * dy + dz * dz;
         double acc = 0.0;
@@ -403,9 +402,10 @@ __global__ void k_force_inter(DevSystem sys, const double* q, const double* av, 
 #pragma unroll
           for (int v = 0; v < MAXSH_EL; ++v) {
             const double c = ia[u] + sio[k][v];
-            const double x = rsqrt(R2 + c * c);
+            const double x = rsqrt_pos(R2 + c * c);
             acc -= (qa[u] * (sq[k][v] + sa_[k][v]) + aa[u] * sq[k][v]) * (x * x * x);
           }
+        acc = sf[k] == fa ? 0.0 : acc;  // own fragment: adds exactly +0 (a select, no branch)
         f[0] += acc * dx;
         f[1] += acc * dy;
         f[2] += acc * dz;

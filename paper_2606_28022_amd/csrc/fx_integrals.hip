@@ -323,16 +323,19 @@ __global__ void __launch_bounds__(256) k_field_partial(DevSystem sys, const doub
     __syncthreads();
     const int nb = min(256, b_end - b0);
     if (A < N && kg2) {
-      // gamma = (R^2 + (1/eta_st)^2)^(-1/2)
+      // gamma = (R^2 + (1/eta_st)^2)^(-1/2); a source in the target's own
+      // fragment adds exactly +0 (a select, no branch per source)
+#pragma unroll 2
       for (int k = 0; k < nb; ++k) {
-        if (sf[k] == fa) continue;
         const double dx = xa - sx[k], dy = ya - sy[k], dz = za - sz[k];
         const double R2 = dx * dx + dy * dy + dz * dz;
         const double t00 = ia0 + si0[k], t01 = ia0 + si1[k], t10 = ia1 + si0[k], t11 = ia1 + si1[k];
-        acc0 += rsqrt(R2 + t00 * t00) * sq0[k];
-        acc0 += rsqrt(R2 + t01 * t01) * sq1[k];
-        acc1 += rsqrt(R2 + t10 * t10) * sq0[k];
-        acc1 += rsqrt(R2 + t11 * t11) * sq1[k];
+        const double q0 = sq0[k], q1 = sq1[k];
+        const double g0 = rsqrt_pos(R2 + t00 * t00) * q0 + rsqrt_pos(R2 + t01 * t01) * q1;
+        const double g1 = rsqrt_pos(R2 + t10 * t10) * q0 + rsqrt_pos(R2 + t11 * t11) * q1;
+        const bool own = sf[k] == fa;
+        acc0 += own ? 0.0 : g0;
+        acc1 += own ? 0.0 : g1;
       }
     } else if (A < N) {
       for (int k = 0; k < nb; ++k) {
@@ -395,13 +398,16 @@ __global__ void __launch_bounds__(256) k_field_partial_f32(DevSystem sys, const 
     __syncthreads();
     const int nb = min(256, b_end - b0);
     if (A < N)
+#pragma unroll 2
       for (int k = 0; k < nb; ++k) {
-        if (sf[k] == fa) continue;
         const float dx = (float)(xa - sx[k]), dy = (float)(ya - sy[k]), dz = (float)(za - sz[k]);
         const float R2 = dx * dx + dy * dy + dz * dz;
         const float t00 = ia0 + si0[k], t01 = ia0 + si1[k], t10 = ia1 + si0[k], t11 = ia1 + si1[k];
-        acc0 += rsqrtf(R2 + t00 * t00) * sq0[k] + rsqrtf(R2 + t01 * t01) * sq1[k];
-        acc1 += rsqrtf(R2 + t10 * t10) * sq0[k] + rsqrtf(R2 + t11 * t11) * sq1[k];
+        const float g0 = rsqrtf(R2 + t00 * t00) * sq0[k] + rsqrtf(R2 + t01 * t01) * sq1[k];
+        const float g1 = rsqrtf(R2 + t10 * t10) * sq0[k] + rsqrtf(R2 + t11 * t11) * sq1[k];
+        const bool own = sf[k] == fa;  // own fragment: adds exactly +0
+        acc0 += own ? 0.0f : g0;
+        acc1 += own ? 0.0f : g1;
       }
   }
   if (A < N) {
@@ -563,8 +569,8 @@ __global__ void __launch_bounds__(64) k_esd_pairs(DevSystem sys, const int* pair
         const double qb0 = q[sb0], qb1 = nsb > 1 ? q[sb0 + 1] : 0.0;
         const double ib0 = sys.sh_ieta[sb0], ib1 = nsb > 1 ? sys.sh_ieta[sb0 + 1] : 0.5;
         const double t00 = ia0 + ib0, t01 = ia0 + ib1, t10 = ia1 + ib0, t11 = ia1 + ib1;
-        acc += qa0 * (rsqrt(R2 + t00 * t00) * qb0 + rsqrt(R2 + t01 * t01) * qb1) +
-               qa1 * (rsqrt(R2 + t10 * t10) * qb0 + rsqrt(R2 + t11 * t11) * qb1);
+        acc += qa0 * (rsqrt_pos(R2 + t00 * t00) * qb0 + rsqrt_pos(R2 + t01 * t01) * qb1) +
+               qa1 * (rsqrt_pos(R2 + t10 * t10) * qb0 + rsqrt_pos(R2 + t11 * t11) * qb1);
       } else {
         for (int s = sa0; s < sa0 + nsa; ++s)
           for (int t = sb0; t < sb0 + nsb; ++t) acc += q[s] * gamma_fn(sys.g, R2, sys.sh_eta[s], sys.sh_eta[t]) * q[t];
