@@ -195,14 +195,29 @@ __global__ void k_fock(DevSystem sys, DevBatch bt, const int* list) {
     bt.sig[d.sh_off + s] = v;
   }
   __syncthreads();
+  // the shift of each AO (that of its shell)
+  __shared__ double sig_ao[MAXN];
+  const int* aosh = bt.sys_ao_sh + d.ao_off;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sig_ao[i] = sig_s[aosh[i]];
+  __syncthreads();
   const double* S = bt.S + d.mat_off;
   const double* H = bt.H0 + d.mat_off;
   double* Fm = bt.F + d.mat_off;
   const double* Vh = bt.Vh ? bt.Vh + d.mat_off : nullptr;
-  const int* aosh = bt.sys_ao_sh + d.ao_off;
-  for (long long idx = threadIdx.x; idx < (long long)n * n; idx += blockDim.x) {
-    int i = (int)(idx / n), j = (int)(idx - (long long)i * n);
-    Fm[idx] = H[idx] + 0.5 * S[idx] * (sig_s[aosh[i]] + sig_s[aosh[j]]) + (Vh ? Vh[idx] : 0.0);
+  // element idx = i n + j, (i, j) advanced incrementally (no division per
+  // element); unrolled so that several loads per thread are in flight
+  const int nn = n * n, step = blockDim.x;
+  const int di = step / n, dj = step - di * n;
+  int i = threadIdx.x / n, j = threadIdx.x - i * n;
+#pragma unroll 4
+  for (int idx = threadIdx.x; idx < nn; idx += step) {
+    Fm[idx] = H[idx] + 0.5 * S[idx] * (sig_ao[i] + sig_ao[j]) + (Vh ? Vh[idx] : 0.0);
+    i += di;
+    j += dj;
+    if (j >= n) {
+      j -= n;
+      ++i;
+    }
   }
 }
 
@@ -755,6 +770,7 @@ __global__ void k_charges_mix(DevSystem sys, DevBatch bt, const int* list, doubl
   double eh = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     double v = 0.0, h = 0.0;
+#pragma unroll 8
     for (int j = 0; j < n; ++j) {
       const double pji = P[(long long)j * n + i];
       v += pji * S[(long long)j * n + i];
@@ -770,6 +786,7 @@ __global__ void k_charges_mix(DevSystem sys, DevBatch bt, const int* list, doubl
   const int* aosh = bt.sys_ao_sh + d.ao_off;
   for (int s = threadIdx.x; s < ns; s += blockDim.x) {
     double v = 0.0;
+#pragma unroll 8
     for (int i = 0; i < n; ++i)
       if (aosh[i] == s) v += pop[i];
     int a = bt.sys_sh_atom[d.sh_off + s];
