@@ -88,7 +88,7 @@ struct DevBatch {
   double* q_out;
   double* phi;   // external shell potential
   double* sig;   // shell shift of the last Fock build
-  const float* pre;  // nsh x nsh mixing preconditioner per system (gam layout) or null
+  const float* pre;  // nsh x nsh mixing preconditioner per system (gam offsets, stored transposed) or null
   const double* sh_q0;     // per local shell reference population (null: element values)
   const double* atom_zs;   // per local atom repulsion-charge scale (null: 1)
   double* Vh;              // HOP projector S D S per system (mat layout) or null

@@ -118,7 +118,7 @@ struct Batch {
   DevBuf<double> erep, e_int, e_prev, mts, err;
   DevBuf<int> status, niter, nhist, sweeps;
   // Newton preconditioner (1 + M G)^-1 of the Anderson residuals (FP32,
-  // gam layout); used by the mixer when has_pre is set
+  // gam offsets, each block stored transposed); used by the mixer when has_pre is set
   DevBuf<float> pre;
   bool has_pre = false;
   // rotation log of the split eigensolver (k_jacobi_rot / k_apply_rot)

@@ -74,7 +74,8 @@ __global__ void k_precond_step(DevBatch bt, double* out) {
   const float* Pr = bt.pre + d.gam_off;
   for (int s = threadIdx.x; s < ns; s += blockDim.x) {
     double v = 0.0;
-    for (int t = 0; t < ns; ++t) v += (double)Pr[(long long)s * ns + t] * r[t];
+#pragma unroll 8
+    for (int t = 0; t < ns; ++t) v += (double)Pr[(long long)t * ns + s] * r[t];  // stored transposed
     out[d.sh_off + s] = qi[s] + v;
   }
 }
@@ -186,7 +187,10 @@ __global__ void k_fock(DevSystem sys, DevBatch bt, const int* list) {
   const double* G = bt.gam + d.gam_off;
   for (int s = threadIdx.x; s < ns; s += blockDim.x) {
     double v = 0.0;
-    for (int t = 0; t < ns; ++t) v += G[(long long)s * ns + t] * q[t];
+    // G is stored exactly symmetric: column s is read (consecutive threads,
+    // consecutive addresses), several loads in flight
+#pragma unroll 8
+    for (int t = 0; t < ns; ++t) v += G[(long long)t * ns + s] * q[t];
     int a = bt.sys_sh_atom[d.sh_off + s];
     int A = bt.sys_atoms[d.atom_off + a];
     double Gam = sys.elems[sys.elem[A]].Gamma;
@@ -204,6 +208,38 @@ __global__ void k_fock(DevSystem sys, DevBatch bt, const int* list) {
   const double* H = bt.H0 + d.mat_off;
   double* Fm = bt.F + d.mat_off;
   const double* Vh = bt.Vh ? bt.Vh + d.mat_off : nullptr;
+  if (!Vh && blockDim.x == 256) {
+    // H0 and S are stored exactly symmetric, so F is: only the upper 32 x 32
+    // tiles are read, and each is written as itself and, through LDS, as its
+    // mirror tile (2 n^2 instead of 3 n^2 elements of HBM traffic)
+    __shared__ double tr[32][33];
+    const int nt = (n + 31) / 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 8 rows of a tile per pass
+    for (int I = 0; I < nt; ++I)
+      for (int J = I; J < nt; ++J) {
+        const int j = 32 * J + tx;
+#pragma unroll
+        for (int r = 0; r < 32; r += 8) {
+          const int i = 32 * I + r + ty;
+          if (i < n && j < n) {
+            const long long e = (long long)i * n + j;
+            const double f = H[e] + 0.5 * S[e] * (sig_ao[i] + sig_ao[j]);
+            Fm[e] = f;
+            tr[r + ty][tx] = f;
+          }
+        }
+        if (I == J) continue;
+        __syncthreads();
+        const int ic = 32 * I + tx;
+#pragma unroll
+        for (int r = 0; r < 32; r += 8) {
+          const int jr = 32 * J + r + ty;
+          if (jr < n) Fm[(long long)jr * n + ic] = tr[tx][r + ty];
+        }
+        __syncthreads();  // before the next tile overwrites tr
+      }
+    return;
+  }
   // element idx = i n + j, (i, j) advanced incrementally (no division per
   // element); unrolled so that several loads per thread are in flight
   const int nn = n * n, step = blockDim.x;
@@ -765,19 +801,60 @@ __global__ void k_charges_mix(DevSystem sys, DevBatch bt, const int* list, doubl
   const double* S = bt.S + d.mat_off;
   const double* P = bt.P + d.mat_off;
   const double* H = bt.H0 + d.mat_off;
-  // AO populations (P S)_mu,mu and Tr(P H0); P, S and H0 are symmetric, so
-  // thread i sums column i (consecutive threads read consecutive addresses)
+  // AO populations (P S)_mu,mu = sum_nu P_mu,nu S_mu,nu and Tr(P H0).  P, S
+  // and H0 are symmetric: only the upper 32 x 32 tiles are read.  A diagonal
+  // tile adds its row sums to the populations of its rows; an off-diagonal
+  // tile (I, J) adds its row sums to those of the rows in I and its column
+  // sums to those of the columns in J, and counts twice in Tr(P H0).  Every
+  // sum is taken in a fixed order (deterministic).
   double eh = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    double v = 0.0, h = 0.0;
-#pragma unroll 8
-    for (int j = 0; j < n; ++j) {
-      const double pji = P[(long long)j * n + i];
-      v += pji * S[(long long)j * n + i];
-      h += pji * H[(long long)j * n + i];
-    }
-    pop[i] = v;
-    eh += h;
+  {
+    __shared__ double colp[8][33];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) pop[i] = 0.0;
+    __syncthreads();
+    const int nt = (n + 31) / 32;
+    // (256 threads: a half-wave per tile row, 8 rows per pass)
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int I = 0; I < nt; ++I)
+      for (int J = I; J < nt; ++J) {
+        const int j = 32 * J + tx;
+        const double wh = I == J ? 1.0 : 2.0;
+        double rs[4], cs = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int i = 32 * I + 8 * k + ty;
+          double x = 0.0;
+          if (i < n && j < n) {
+            const long long e = (long long)i * n + j;
+            const double pv = P[e];
+            x = pv * S[e];
+            eh += wh * (pv * H[e]);
+          }
+          rs[k] = x;
+          cs += x;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int off = 16; off > 0; off >>= 1) rs[k] += __shfl_xor(rs[k], off, 32);
+        if (tx == 0)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int i = 32 * I + 8 * k + ty;
+            if (i < n) pop[i] += rs[k];
+          }
+        if (I != J) {
+          colp[ty][tx] = cs;
+          __syncthreads();
+          if (ty == 0 && j < n) {
+            double c = 0.0;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) c += colp[t][tx];
+            pop[j] += c;
+          }
+        }
+        __syncthreads();
+      }
   }
   eh = block_sum(eh, red);
   // shell charges
@@ -809,7 +886,10 @@ __global__ void k_charges_mix(DevSystem sys, DevBatch bt, const int* list, doubl
   double e2 = 0.0, e3 = 0.0, err = 0.0;
   for (int s = threadIdx.x; s < ns; s += blockDim.x) {
     double v = 0.0;
-    for (int t = 0; t < ns; ++t) v += G[(long long)s * ns + t] * qo[t];
+    // G is stored exactly symmetric: column s is read (consecutive threads,
+    // consecutive addresses), several loads in flight
+#pragma unroll 8
+    for (int t = 0; t < ns; ++t) v += G[(long long)t * ns + s] * qo[t];
     e2 += 0.5 * qo[s] * v;
     err = fmax(err, fabs(qo[s] - qi[s]));
   }
@@ -849,7 +929,8 @@ __global__ void k_charges_mix(DevSystem sys, DevBatch bt, const int* list, doubl
     __syncthreads();
     for (int s = threadIdx.x; s < ns; s += blockDim.x) {
       double v = 0.0;
-      for (int t = 0; t < ns; ++t) v += (double)Pr[(long long)s * ns + t] * pop[t];
+#pragma unroll 8
+      for (int t = 0; t < ns; ++t) v += (double)Pr[(long long)t * ns + s] * pop[t];  // stored transposed
       hx[(long long)slot * ns + s] = qi[s];
       hr[(long long)slot * ns + s] = v;
     }
@@ -1282,9 +1363,11 @@ __global__ void __launch_bounds__(1024)
       __syncthreads();
     }
   }
+  // stored transposed (element (s, t) at t ns + s), so that the products
+  // with it read consecutive addresses across threads
   float* out = pre + d.gam_off;
-  for (int s = wave; s < ns; s += nw)
-    for (int t = lane; t < ns; t += 64) out[s * ns + t] = good ? Kf[s * ns + t] : (s == t ? 1.0f : 0.0f);
+  for (int t = wave; t < ns; t += nw)
+    for (int s = lane; s < ns; s += 64) out[t * ns + s] = good ? Kf[s * ns + t] : (s == t ? 1.0f : 0.0f);
   if (threadIdx.x == 0) ok[si] = good ? 1 : 0;
 }
 
