@@ -1055,6 +1055,24 @@ void Ctx::hist_coef(const double* R, long long n, const Slots& sl, double* coef)
 }
 
 void Ctx::field(const double* d_q, double* d_phi, bool fp32) {
+  const DevSystem ds = dev_system();
+  const int nbk = (Ne + 63) / 64;
+  const long long ncol = (long long)nbk * (nbk - 1) / 2 * 128;
+  if (!fp32 && ds.g.kg == 2.0 && ncol <= (1LL << 29)) {
+    // symmetric pass: each inter-fragment atom pair once (4 source blocks per wave)
+    const int group = 4, ngmax = (nbk + group - 1) / group;
+    const long long nrow = (long long)nbk * ngmax * 128;
+    if (nrow > field_part.n) field_part.alloc(nrow);
+    if (ncol > field_col.n) field_col.alloc(std::max(1LL, ncol));
+    const int ev = timers.begin(stream);
+    hipLaunchKernelGGL(k_field_sym, dim3(nbk, ngmax), dim3(64), 0, stream, ds, d_q, group, ngmax, field_part.p,
+                       field_col.p);
+    timers.end(stream, ev, kt("fx::k_field_sym"), 8e-9 * field_pairs);
+    hipLaunchKernelGGL(k_field_sym_reduce, dim3((Ne + 255) / 256), dim3(256), 0, stream, ds, group, ngmax,
+                       (const double*)field_part.p, (const double*)field_col.p, d_phi);
+    check(hipGetLastError(), "field");
+    return;
+  }
   const int nchunk = std::max(1, std::min(64, (Ne + 255) / 256 > 0 ? 2048 / ((Ne + 255) / 256) : 1));
   if ((long long)nchunk * Nsh > field_part.n) field_part.alloc((long long)nchunk * Nsh);
   dim3 grid((Ne + 255) / 256, nchunk);

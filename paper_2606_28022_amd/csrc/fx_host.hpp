@@ -213,6 +213,7 @@ struct Ctx {
   std::vector<double> xyz_h, guess;
   DevBuf<DevElem> d_elems;
   DevBuf<double> d_xyz, d_cn, d_sh_eta, d_sh_ieta, d_q, d_qnew, d_phi, d_scalar, field_part, d_grad;
+  DevBuf<double> field_col;  // column partial sums of the symmetric field pass
   DevBuf<int> d_elem, d_frag, d_atom_sh0, d_sh_atom, d_sh_frag, d_frag_atoms, d_frag_off;
 
   // lists

@@ -416,6 +416,145 @@ __global__ void __launch_bounds__(256) k_field_partial_f32(DevSystem sys, const 
   }
 }
 
+// Symmetric form of the FP64 field pass for kg = 2 (gamma_st = gamma_ts):
+// every inter-fragment atom pair is evaluated once and used in both
+// directions.  Atoms form blocks of 64; one wave (the whole work-group) takes
+// a target block I and source blocks J = I + g G .. I + g G + G - 1 (J >= I).
+// Lane i holds target atom 64 I + i; in step r it meets source atom
+// k = (i + r) mod 64 of block J, adds gamma q_k to its own row sums and
+// gamma q_i to the column sums of atom k, which move one lane down after each
+// step (DPP rotation), so that after 64 steps lane k holds the column sums of
+// its own source atom.  The diagonal block (J = I) is taken in one direction
+// only (r = 1 .. 63, row sums).  Row sums go to rowpart[(I, g)], column sums
+// to colpart[(I, J)] (I < J); k_field_sym_reduce adds them in fixed order.
+__device__ inline double wave_rol1(double v) {
+  // lane i reads lane i + 1 (lane 63 reads lane 0)
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x134, 0xf, 0xf, true),
+                          __builtin_amdgcn_mov_dpp(lo, 0x134, 0xf, 0xf, true));
+}
+
+__global__ void __launch_bounds__(64) k_field_sym(DevSystem sys, const double* q, int group, int ngmax,
+                                                  double* rowpart, double* colpart) {
+  const int N = sys.natoms;
+  const int nb = (N + 63) / 64;
+  const int I = blockIdx.x, g = blockIdx.y;
+  const int J0 = I + g * group;
+  if (J0 >= nb) return;
+  const int J1 = min(nb, J0 + group);
+  const int lane = threadIdx.x;
+  // source block: position and ieta0 | ieta1, q0, q1, fragment
+  __shared__ double4 sa[64], sb[64];
+  // target atom of this lane (an absent atom or second shell carries q = 0)
+  double xa = 0.0, ya = 0.0, za = 0.0, ia0 = 0.5, ia1 = 0.5, qa0 = 0.0, qa1 = 0.0, fa = -1.0;
+  {
+    const int A = 64 * I + lane;
+    if (A < N) {
+      xa = sys.xyz[3 * A];
+      ya = sys.xyz[3 * A + 1];
+      za = sys.xyz[3 * A + 2];
+      fa = (double)sys.frag[A];
+      const int s0 = sys.atom_sh0[A], ns = sys.atom_sh0[A + 1] - s0;
+      ia0 = sys.sh_ieta[s0];
+      qa0 = q[s0];
+      if (ns > 1) {
+        ia1 = sys.sh_ieta[s0 + 1];
+        qa1 = q[s0 + 1];
+      }
+    }
+  }
+  double r0 = 0.0, r1 = 0.0;
+  for (int J = J0; J < J1; ++J) {
+    __syncthreads();
+    {
+      const int B = 64 * J + lane;
+      double4 a = make_double4(0.0, 0.0, 0.0, 0.5), b = make_double4(0.5, 0.0, 0.0, -2.0);
+      if (B < N) {
+        a.x = sys.xyz[3 * B];
+        a.y = sys.xyz[3 * B + 1];
+        a.z = sys.xyz[3 * B + 2];
+        const int s0 = sys.atom_sh0[B], ns = sys.atom_sh0[B + 1] - s0;
+        a.w = sys.sh_ieta[s0];
+        b.y = q[s0];
+        if (ns > 1) {
+          b.x = sys.sh_ieta[s0 + 1];
+          b.z = q[s0 + 1];
+        }
+        b.w = (double)sys.frag[B];
+      }
+      sa[lane] = a;
+      sb[lane] = b;
+    }
+    __syncthreads();
+    if (J == I) {
+      for (int r = 1; r < 64; ++r) {
+        const int k = (lane + r) & 63;
+        const double4 a = sa[k], b = sb[k];
+        const double dx = xa - a.x, dy = ya - a.y, dz = za - a.z;
+        const double R2 = dx * dx + dy * dy + dz * dz;
+        const double t00 = ia0 + a.w, t01 = ia0 + b.x, t10 = ia1 + a.w, t11 = ia1 + b.x;
+        const double g0 = rsqrt_pos(R2 + t00 * t00) * b.y + rsqrt_pos(R2 + t01 * t01) * b.z;
+        const double g1 = rsqrt_pos(R2 + t10 * t10) * b.y + rsqrt_pos(R2 + t11 * t11) * b.z;
+        const bool own = b.w == fa;  // own fragment: adds exactly +0
+        r0 += own ? 0.0 : g0;
+        r1 += own ? 0.0 : g1;
+      }
+    } else {
+      double c0 = 0.0, c1 = 0.0;  // column sums of source atom (lane + r) mod 64
+      for (int r = 0; r < 64; ++r) {
+        const int k = (lane + r) & 63;
+        const double4 a = sa[k], b = sb[k];
+        const double dx = xa - a.x, dy = ya - a.y, dz = za - a.z;
+        const double R2 = dx * dx + dy * dy + dz * dz;
+        const double t00 = ia0 + a.w, t01 = ia0 + b.x, t10 = ia1 + a.w, t11 = ia1 + b.x;
+        const double x00 = rsqrt_pos(R2 + t00 * t00), x01 = rsqrt_pos(R2 + t01 * t01);
+        const double x10 = rsqrt_pos(R2 + t10 * t10), x11 = rsqrt_pos(R2 + t11 * t11);
+        const bool own = b.w == fa;
+        const double g0 = x00 * b.y + x01 * b.z, g1 = x10 * b.y + x11 * b.z;
+        const double h0 = x00 * qa0 + x10 * qa1, h1 = x01 * qa0 + x11 * qa1;
+        r0 += own ? 0.0 : g0;
+        r1 += own ? 0.0 : g1;
+        c0 = wave_rol1(c0 + (own ? 0.0 : h0));
+        c1 = wave_rol1(c1 + (own ? 0.0 : h1));
+      }
+      // lane holds the column sums of its own source atom 64 J + lane
+      double* cp = colpart + ((long long)J * (J - 1) / 2 + I) * 128;
+      cp[2 * lane] = c0;
+      cp[2 * lane + 1] = c1;
+    }
+  }
+  double* rp = rowpart + ((long long)I * ngmax + g) * 128;
+  rp[2 * lane] = r0;
+  rp[2 * lane + 1] = r1;
+}
+
+// phi of each atom's shells: its row sums (groups g in order), then its
+// column sums (target blocks I < its block, in order)
+__global__ void k_field_sym_reduce(DevSystem sys, int group, int ngmax, const double* rowpart,
+                                   const double* colpart, double* phi) {
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = sys.natoms;
+  if (A >= N) return;
+  const int nb = (N + 63) / 64;
+  const int B = A >> 6, l = A & 63;
+  const int ng = (nb - B + group - 1) / group;
+  double v0 = 0.0, v1 = 0.0;
+  const double* rp = rowpart + (long long)B * ngmax * 128 + 2 * l;
+  for (int g = 0; g < ng; ++g) {
+    v0 += rp[(long long)g * 128];
+    v1 += rp[(long long)g * 128 + 1];
+  }
+  const double* cp = colpart + (long long)B * (B - 1) / 2 * 128 + 2 * l;
+#pragma unroll 4
+  for (int I = 0; I < B; ++I) {
+    v0 += cp[(long long)I * 128];
+    v1 += cp[(long long)I * 128 + 1];
+  }
+  const int s0 = sys.atom_sh0[A], ns = sys.atom_sh0[A + 1] - s0;
+  phi[s0] = v0;
+  if (ns > 1) phi[s0 + 1] = v1;
+}
+
 __global__ void k_field_reduce(int nshells, int nchunk, const double* part, double* phi) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nshells) return;

@@ -15,6 +15,9 @@ __global__ void k_build_system(DevSystem sys, DevBatch bt, const int* list);
 __global__ void k_field_partial(DevSystem sys, const double* q, int nchunk, double* part);
 __global__ void k_field_partial_f32(DevSystem sys, const double* q, int nchunk, double* part);
 __global__ void k_field_reduce(int nshells, int nchunk, const double* part, double* phi);
+__global__ void k_field_sym(DevSystem sys, const double* q, int group, int ngmax, double* rowpart, double* colpart);
+__global__ void k_field_sym_reduce(DevSystem sys, int group, int ngmax, const double* rowpart,
+                                   const double* colpart, double* phi);
 __global__ void k_cluster_phi(DevSystem sys, DevBatch bt, const double* Phi, const double* qmono);
 __global__ void k_esd_pairs(DevSystem sys, const int* pairs, long long npairs, const int* frag_atoms,
                             const int* frag_off, const double* q, double* out);
