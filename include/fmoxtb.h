@@ -129,8 +129,10 @@ typedef struct fx_counts {
  * launch), launch count and algorithmic work in GFLOP:
  *   fx::k_jacobi_lds<float|double>, fx::k_jacobi   6 n^2 (n - 1) per sweep
  *   fx::k_gemm_mfma, fx::k_gemm                      2 n^3 per product
- *   fx::k_field_partial      8 per inter-fragment shell pair (one rsqrt,
- *                            the distance shared by an atom pair's shells) */
+ *   fx::k_field_sym,         8 per ordered inter-fragment shell pair (one
+ *   fx::k_field_partial      rsqrt, the distance shared by an atom pair's
+ *                            shells); the symmetric form evaluates each
+ *                            unordered pair once and uses it both ways */
 #define FX_MAX_KSTAT 8
 typedef struct fx_kernel_stat {
   char name[48];          /* kernel name as rocprofv3 prints it, without arguments */

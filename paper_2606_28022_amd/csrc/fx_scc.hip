@@ -19,6 +19,20 @@
 
 namespace fx {
 
+// sum over the work-group (blockDim a multiple of 64, at most 1024): a
+// butterfly within each wave, then the wave totals in order; every thread
+// gets the same value
+__device__ inline double block_sum_waves(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();  // red may still be read by a previous reduction
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+  return t;
+}
+
 __device__ inline double block_sum(double v, double* red) {
   __syncthreads();
   red[threadIdx.x] = v;
@@ -714,43 +728,63 @@ __global__ void k_fermi(DevSystem sys, DevBatch bt, const int* list) {
   const int n = d.nao;
   const double kT = sys.g.kT;
   __shared__ double red[256];
+  // (256 threads, n <= 512: each thread keeps its two eigenvalues in registers)
   const double* e = bt.eps + d.ao_off;
+  constexpr int PER = MAXN / 256;
+  double ev[PER];
   double lo = 1e300, hi = -1e300;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    lo = fmin(lo, e[i]);
-    hi = fmax(hi, e[i]);
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    ev[k] = i < n ? e[i] : 0.0;
+    if (i < n) {
+      lo = fmin(lo, ev[k]);
+      hi = fmax(hi, ev[k]);
+    }
   }
   lo = -block_max(-lo, red) - 1.0;
   hi = block_max(hi, red) + 1.0;
   for (int it = 0; it < 300; ++it) {
     double mid = 0.5 * (lo + hi);
     double loc = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) loc += 2.0 / (1.0 + exp((e[i] - mid) / kT));
-    double tot = block_sum(loc, red);
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+      if (threadIdx.x + 256 * k < n) loc += 2.0 / (1.0 + exp((ev[k] - mid) / kT));
+    double tot = block_sum_waves(loc, red);
     if (tot > d.nel) hi = mid;
     else lo = mid;
     if (hi - lo < 1e-15) break;
   }
   double ef = 0.5 * (lo + hi);
   double ts = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    double f = 1.0 / (1.0 + exp((e[i] - ef) / kT));
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    if (i >= n) continue;
+    double f = 1.0 / (1.0 + exp((ev[k] - ef) / kT));
     bt.occ[d.ao_off + i] = 2.0 * f;
     double t = 0.0;
     if (f > 0.0) t += f * log(f);
     if (f < 1.0) t += (1.0 - f) * log(1.0 - f);
     ts += t;
   }
-  ts = block_sum(ts, red);
-  if (threadIdx.x == 0) {
-    bt.mts[si] = 2.0 * kT * ts;
-    // orbitals that enter the density product, in ascending order
-    int c = 0;
+  ts = block_sum_waves(ts, red);  // (its barriers also publish the occupations)
+  if (threadIdx.x == 0) bt.mts[si] = 2.0 * kT * ts;
+  if (threadIdx.x < 64) {
+    // orbitals that enter the density product, in ascending order: one wave,
+    // 64 orbitals per step, positions from a ballot
+    const int lane = threadIdx.x;
     const double* oc = bt.occ + d.ao_off;
     int* ix = bt.occ_idx + d.ao_off;
-    for (int i = 0; i < n; ++i)
-      if (oc[i] > OCC_MIN) ix[c++] = i;
-    bt.occ_cnt[si] = c;
+    int c = 0;
+    for (int base = 0; base < n; base += 64) {
+      const int i = base + lane;
+      const bool take = i < n && oc[i] > OCC_MIN;
+      const unsigned long long m = __ballot(take);
+      if (take) ix[c + __popcll(m & ((1ULL << lane) - 1ULL))] = i;
+      c += __popcll(m);
+    }
+    if (lane == 0) bt.occ_cnt[si] = c;
   }
 }
 

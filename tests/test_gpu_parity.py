@@ -102,9 +102,12 @@ def test_cluster_matrices_pentacene_dimer(lib, params, c4):
     assert np.max(np.abs(H - sx.H0)) < 1e-13
 
 
-def test_embedding_field(lib, params):
-    _say("embedding field droplet")
-    s = w.water_droplet(256, radius=12.5, seed=21)
+@pytest.mark.parametrize("nmol", [256, 250, 5])
+def test_embedding_field(lib, params, nmol):
+    """Whole 64-atom blocks (768 atoms), a ragged last block (750 atoms) and
+    a single partial block (15 atoms, the diagonal block only)."""
+    _say(f"embedding field droplet {nmol}")
+    s = w.water_droplet(nmol, radius=12.5 * (nmol / 256) ** (1 / 3), seed=21)
     c = _ctx(lib, s)
     rng = np.random.Generator(np.random.PCG64(5))
     q = rng.normal(scale=0.3, size=c.n_shells)
