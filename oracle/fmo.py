@@ -38,6 +38,7 @@ Passages followed:
 """
 
 import math
+import multiprocessing
 
 import numpy as np
 
@@ -234,6 +235,120 @@ class Shells:
         return out
 
 
+# --------------------------------------------------------------------------
+# optional process pool over fragments (the oracle's arithmetic is unchanged:
+# every task is one monomer SCC, one cluster solve or one chunk of targets of
+# an embedding-potential sum; results are gathered in input order)
+
+_POOL_STATE = {}
+
+
+def _pool_init():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
+
+
+class _Runner:
+    """map() over tasks, serially or with `workers` forked processes that see
+    the module state set before the pool starts."""
+
+    def __init__(self, workers):
+        self.workers = int(workers or 1)
+        self.pool = None
+
+    def start(self, **state):
+        _POOL_STATE.clear()
+        _POOL_STATE.update(state)
+        if self.workers > 1:
+            self.close()
+            ctx = multiprocessing.get_context("fork")
+            self.pool = ctx.Pool(self.workers, initializer=_pool_init)
+
+    def map(self, fn, tasks):
+        if self.pool is None:
+            return [fn(t) for t in tasks]
+        return self.pool.map(fn, tasks, chunksize=1)
+
+    def close(self):
+        if self.pool is not None:
+            self.pool.close()
+            self.pool.join()
+            self.pool = None
+
+
+def _task_potential(args):
+    i0, i1, q_all, mask = args
+    sh = _POOL_STATE["sh"]
+    if mask == "same_frag":
+        fn = lambda s, t: sh.frag[s] == sh.frag[t]
+    else:
+        fn = lambda s, t: np.zeros_like(s, dtype=bool)
+    return sh.potential(np.arange(i0, i1), q_all, fn, chunk=512)
+
+
+def _field_all(runner, sh, q):
+    """phi over every shell from the charges of the other fragments."""
+    if runner.pool is None:
+        same_frag = lambda s, t: sh.frag[s] == sh.frag[t]
+        return sh.potential(np.arange(sh.n), q, same_frag)
+    step = 2048
+    tasks = [(i0, min(sh.n, i0 + step), q, "same_frag") for i0 in range(0, sh.n, step)]
+    return np.concatenate(runner.map(_task_potential, tasks))
+
+
+def _task_monomer(args):
+    I, phi_I, guess = args
+    st = _POOL_STATE
+    r = scc(st["mono"][I], phi_I, q_guess=guess, tol=st["scc_tol"], etol=st["scc_etol"])
+    return r if st["keep"] else SCCResultLight(r)
+
+
+def _task_cluster(frags):
+    st = _POOL_STATE
+    out = _solve_cluster(st["params"], st["ext"], st["sh"], st["q"], st["frag_charge"],
+                         st["scc_tol"], st["scc_etol"], frags)
+    if not st["keep"]:
+        sysX, rX, shl, ddq, dEV = out
+        light = SCCResultLight(rX)
+        return None, light, shl, ddq, dEV
+    return out
+
+
+class SCCResultLight:
+    """The scalars and charges of a cluster solve (what the energy needs),
+    without its matrices, for large runs."""
+
+    def __init__(self, r):
+        self.e_int = r.e_int
+        self.q = r.q
+        self.niter = r.niter
+        self.converged = r.converged
+
+
+def _solve_cluster(params, ext, sh, q, frag_charge, scc_tol, scc_etol, frags):
+    """SCC of the cluster made of `frags` in the field of all other monomers
+    (eqs. dimer_embedding_correction, ddq_calc; trimers alike)."""
+    atoms, hop, healed = ext.layout(frags)
+    shl = sh.of_atoms(atoms)
+    inside = np.isin(sh.frag, np.asarray(frags))
+    no_mask = lambda s, t: np.zeros_like(s, dtype=bool)
+    q_out = np.where(inside, 0.0, q)
+    phiX = sh.potential(shl, q_out, no_mask)
+    sysX = _system_for(params, ext, atoms, int(sum(frag_charge[I] for I in frags)), hop)
+    rX = scc(sysX, phiX, q_guess=q[shl], tol=scc_tol, etol=scc_etol)
+    ddq = rX.q - q[shl]
+    dEV = float(ddq @ phiX)
+    if len(healed):
+        # ghosts of bonds healed inside the cluster: their monomer charge is
+        # the charge transfer, with the opposite sign (eq. ctij_ghost)
+        hs = sh.of_atoms(healed)
+        dEV += float(-q[hs] @ sh.potential(hs, q_out, no_mask))
+    return sysX, rX, shl, ddq, dEV
+
+
 def _system_for(params, ext, atoms, charge, hop=None):
     return XtbSystem(params, ext.Z[atoms], ext.xyz[atoms], ext.cn[atoms], charge=charge, hop=hop)
 
@@ -243,9 +358,29 @@ class FMOResult:
 
 
 def fmo(system, params, cutoff_bohr, order=2, lists=None, scc_tol=1e-10,
-        macro_tol=1e-10, max_macro=200, verbose=False):
+        macro_tol=1e-10, max_macro=200, verbose=False, workers=1, keep_clusters=True,
+        scc_etol=1e-11):
     """FMO2 (order=2) or FMO3 (order=3) energy.  Returns an FMOResult with the
-    converged monomer, dimer and trimer results and the energy terms."""
+    converged monomer, dimer and trimer results and the energy terms.
+
+    workers > 1 spreads the monomer solves, the cluster solves and the chunks
+    of the embedding-potential sums over that many forked processes (same
+    arithmetic, same order of every sum).  keep_clusters = False keeps only
+    the energies and charges of the monomer and cluster solves (no matrices),
+    for large systems whose gradient is not wanted.  The result records whether every
+    solve converged (all_scc_converged) and the final monomer-loop change
+    (macro_delta).  scc_tol and scc_etol are the charge and energy
+    tolerances of every fragment SCC."""
+    runner = _Runner(workers)
+    try:
+        return _fmo(system, params, cutoff_bohr, order, lists, scc_tol, scc_etol, macro_tol, max_macro,
+                    verbose, runner, keep_clusters)
+    finally:
+        runner.close()
+
+
+def _fmo(system, params, cutoff_bohr, order, lists, scc_tol, scc_etol, macro_tol, max_macro, verbose,
+         runner, keep_clusters):
     F = system.n_frag
     cn = coordination_numbers(params, system.Z, system.xyz)
     ext = ExtendedAtoms(system, cn)
@@ -260,19 +395,19 @@ def fmo(system, params, cutoff_bohr, order=2, lists=None, scc_tol=1e-10,
     mono = [_system_for(params, ext, fa[I], int(system.frag_charge[I]), lay[I][1]) for I in range(F)]
     q = np.zeros(sh.n)   # superposition guess: zero shell charges
     res = [None] * F
-    same_frag = lambda s, t: sh.frag[s] == sh.frag[t]
     # Monomer self-consistency: every sweep solves all monomers in the field of
     # the current charges; the sweep map q -> q_out is driven to its fixed
     # point with Anderson (Pulay) mixing of the whole charge vector, which
     # also converges where plain repeated sweeps oscillate.
     X_h, R_h = [], []
     beta = 0.5
+    runner.start(mono=mono, sh=sh, scc_tol=scc_tol, scc_etol=scc_etol, keep=keep_clusters)
     for it in range(1, max_macro + 1):
-        phi = sh.potential(np.arange(sh.n), q, same_frag)
+        phi = _field_all(runner, sh, q)
         qn = q.copy()
+        tasks = [(I, phi[fsh[I]], res[I].q if res[I] is not None else q[fsh[I]]) for I in range(F)]
+        res = runner.map(_task_monomer, tasks)
         for I in range(F):
-            g = res[I].q if res[I] is not None else q[fsh[I]]
-            res[I] = scc(mono[I], phi[fsh[I]], q_guess=g, tol=scc_tol)
             qn[fsh[I]] = res[I].q
         r = qn - q
         delta = float(np.max(np.abs(r)))
@@ -300,8 +435,9 @@ def fmo(system, params, cutoff_bohr, order=2, lists=None, scc_tol=1e-10,
     out = FMOResult()
     out.macro_iter = it
     out.macro_converged = delta < macro_tol
+    out.macro_delta = delta
     # final embedding potential of every monomer (consistent with q)
-    phi = sh.potential(np.arange(sh.n), q, same_frag)
+    phi = _field_all(runner, sh, q)
     out.q = q
     out.phi_mono = phi
     out.cn = cn
@@ -314,28 +450,16 @@ def fmo(system, params, cutoff_bohr, order=2, lists=None, scc_tol=1e-10,
     out.lists = lists
     out.E_mono = np.array([r.e_int for r in res])
 
-    def solve_cluster(frags):
-        atoms, hop, healed = ext.layout(frags)
-        shl = sh.of_atoms(atoms)
-        inside = np.isin(sh.frag, np.asarray(frags))
-        no_mask = lambda s, t: np.zeros_like(s, dtype=bool)
-        q_out = np.where(inside, 0.0, q)
-        phiX = sh.potential(shl, q_out, no_mask)
-        sysX = _system_for(params, ext, atoms, int(sum(system.frag_charge[I] for I in frags)), hop)
-        rX = scc(sysX, phiX, q_guess=q[shl], tol=scc_tol)
-        ddq = rX.q - q[shl]
-        dEV = float(ddq @ phiX)
-        if len(healed):
-            # ghosts of bonds healed inside the cluster: their monomer charge is
-            # the charge transfer, with the opposite sign (eq. ctij_ghost)
-            hs = sh.of_atoms(healed)
-            dEV += float(-q[hs] @ sh.potential(hs, q_out, no_mask))
-        return sysX, rX, shl, ddq, dEV
+    runner.start(params=params, ext=ext, sh=sh, q=q, frag_charge=system.frag_charge,
+                 scc_tol=scc_tol, scc_etol=scc_etol, keep=keep_clusters)
+    conv = [bool(r.converged) for r in res]
 
     out.dimers = []
     dE_scc = np.zeros(len(scc_pairs))
+    solved = runner.map(_task_cluster, [(int(I), int(J)) for I, J in scc_pairs])
     for k, (I, J) in enumerate(scc_pairs):
-        sysX, rX, shl, ddq, dEV = solve_cluster((I, J))
+        sysX, rX, shl, ddq, dEV = solved[k]
+        conv.append(bool(rX.converged))
         dE_scc[k] = rX.e_int - res[I].e_int - res[J].e_int + dEV
         out.dimers.append(dict(I=int(I), J=int(J), sys=sysX, res=rX, shells=shl,
                                ddq=ddq, dEV=dEV))
@@ -354,8 +478,10 @@ def fmo(system, params, cutoff_bohr, order=2, lists=None, scc_tol=1e-10,
             pair_dE[(int(I), int(J))] = dE_esd[k]
         out.trimers = []
         dE_tri = np.zeros(len(trimers))
+        solved = runner.map(_task_cluster, [(int(I), int(J), int(K)) for I, J, K in trimers])
         for k, (I, J, K) in enumerate(trimers):
-            sysX, rX, shl, ddq, dEV = solve_cluster((I, J, K))
+            sysX, rX, shl, ddq, dEV = solved[k]
+            conv.append(bool(rX.converged))
             dEIJK = rX.e_int - res[I].e_int - res[J].e_int - res[K].e_int + dEV
             dE_tri[k] = dEIJK - pair_dE[(I, J)] - pair_dE[(I, K)] - pair_dE[(J, K)]
             out.trimers.append(dict(IJK=(int(I), int(J), int(K)), sys=sysX, res=rX, shells=shl,
@@ -363,6 +489,7 @@ def fmo(system, params, cutoff_bohr, order=2, lists=None, scc_tol=1e-10,
         out.dE_tri = dE_tri
         out.E_fmo3 = neumaier_sum([out.E_fmo2] + list(dE_tri))
         out.E = out.E_fmo3
+    out.all_scc_converged = all(conv)
     return out
 
 

@@ -391,6 +391,8 @@ def scc(sysx, phi=None, q_guess=None, tol=1e-10, etol=1e-11, maxiter=500,
             c = np.linalg.lstsq(M, rhs, rcond=None)[0][:m]
             q_in = sum(c[k] * (X[k] + beta * Rr[k]) for k in range(m))
     res.niter = it
+    res.err = err       # final max |q_out - q_in|
+    res.de = de         # final |E_k - E_(k-1)|
     res.q = q_out
     res.P = P
     res.C = C

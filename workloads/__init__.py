@@ -11,6 +11,7 @@ from .geometry import (  # noqa: F401
     System,
     water_cluster_cube,
     water_droplet,
+    ion_pair_cluster,
     anthracene_crystal,
     pentacene_crystal,
     separated_water_pair,

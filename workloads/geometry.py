@@ -195,6 +195,46 @@ def water_cluster_cube(n=8, box=9.0, seed=1, name="water-cube"):
                   meta=dict(seed=seed, box_angstrom=box))
 
 
+def ion_pair_cluster(seed=1):
+    """Charged fragments: the 8-water cube with water 6 turned into OH- (its
+    second H removed, fragment charge -1) and water 7 into H3O+ (a third H at
+    0.98 Angstrom from O, fragment charge +1).  The new H points away from the
+    two existing ones and out of their plane, on the side where it keeps at
+    least 1.5 Angstrom from every other atom."""
+    base = water_cluster_cube(seed=seed)
+    Z = list(base.Z)
+    X = [x / ANGSTROM_TO_BOHR for x in base.xyz]
+    frag = list(base.frag)
+    drop = [a for a in range(len(Z)) if frag[a] == 6][2]
+    o7 = [a for a in range(len(Z)) if frag[a] == 7]
+    O, H1, H2 = (np.asarray(X[a]) for a in o7)
+    b1 = (H1 - O) / np.linalg.norm(H1 - O)
+    b2 = (H2 - O) / np.linalg.norm(H2 - O)
+    back = -(b1 + b2) / np.linalg.norm(b1 + b2)
+    nrm = np.cross(b1, b2)
+    nrm /= np.linalg.norm(nrm)
+    others = np.array([X[a] for a in range(len(Z)) if a != drop and a not in o7])
+    newH = None
+    for sgn in (1.0, -1.0):
+        d = math.cos(math.radians(50.0)) * back + sgn * math.sin(math.radians(50.0)) * nrm
+        cand = O + 0.98 * d / np.linalg.norm(d)
+        if np.min(np.linalg.norm(others - cand, axis=1)) >= 1.5:
+            newH = cand
+            break
+    if newH is None:
+        raise RuntimeError("no clash-free position for the third H of H3O+")
+    keep = [a for a in range(len(Z)) if a != drop]
+    Z = [Z[a] for a in keep] + [1]
+    X = [X[a] for a in keep] + [newH]
+    frag = [frag[a] for a in keep] + [7]
+    order = np.argsort(np.array(frag), kind="stable")
+    charge = np.zeros(8, np.int32)
+    charge[6], charge[7] = -1, 1
+    return System(name="ion-pair-cube", Z=np.array(Z, np.int32)[order],
+                  xyz=np.array(X)[order] * ANGSTROM_TO_BOHR, frag=np.array(frag, np.int32)[order],
+                  frag_charge=charge, meta=dict(seed=seed))
+
+
 def water_droplet(n=1024, radius=19.5, seed=2, name="water-droplet"):
     """n rigid waters with O uniform inside a sphere of the given radius (A)."""
     def sample(r):
