@@ -114,6 +114,10 @@ typedef struct fx_options {
                              the new overlap) instead of the monomers'; the
                              fixed point is the same.  Default 0; fx_md_verlet
                              sets it for its steps. */
+  int32_t max_response;   /* sweeps of the adjoint response equation of the
+                             gradient (default 400); a run whose response
+                             has not reached its tolerance by then returns
+                             FX_E_NOCONV (gradient still readable) */
 } fx_options;
 
 typedef struct fx_counts {
@@ -156,7 +160,34 @@ typedef struct fx_result {
   int32_t n_kstat;
   fx_kernel_stat kstat[FX_MAX_KSTAT];
   int64_t warm_dimers;    /* SCC dimers started from the last run (warm_clusters) */
+  int64_t device_allocs;  /* hipMalloc calls made by this fx_run (0 with a
+                             workspace, and 0 without one once the buffers of
+                             the same system and options already exist) */
 } fx_result;
+
+/* Caller-owned device memory (the PyTorch wrapper passes a uint8 tensor).
+ *
+ * fx_workspace_size: *bytes = the workspace size that the calls made on this
+ * context since its creation (or since its last fx_set_workspace) need: the
+ * peak of the library's first-fit layout of its device buffers, tracked also
+ * while the library allocates with hipMalloc, plus a margin of 1/32 of it and
+ * 4 MiB (launch shapes chosen by timing can change a few buffer sizes between
+ * otherwise identical calls).  Typical use: fx_set_system and fx_run once
+ * without a workspace, query the size, allocate it, call fx_set_workspace,
+ * then fx_set_system again and run; repeating the same calls fits.
+ *
+ * fx_set_workspace: dev_ptr is DEVICE memory on the context's device, at
+ * least 256-byte aligned, `bytes` long; the caller keeps ownership and must
+ * keep it alive until the context is destroyed or given another workspace.
+ * The context is first reset to its state after fx_ctx_create (its system,
+ * lists, results and learned-guess weights are dropped; options are kept),
+ * then every device buffer it creates is carved from the workspace and the
+ * library calls no hipMalloc or hipFree.  dev_ptr = NULL with bytes = 0
+ * returns to library allocation (also a reset).  A call that needs more than
+ * the workspace fails with FX_E_NOMEM and names the size reached.
+ * Errors: FX_E_INVALID (misaligned or empty workspace), FX_E_DEVICE. */
+int fx_workspace_size(fx_ctx* ctx, size_t* bytes);
+int fx_set_workspace(fx_ctx* ctx, void* dev_ptr, size_t bytes);
 
 /* Load element constants and STO-nG basis expansions from a JSON file.
  * *out is owned by the caller; release with fx_params_free.
@@ -285,7 +316,10 @@ int fx_cluster_matrices(fx_ctx* ctx, int32_t nfrag, const int32_t* frags, int32_
 
 /* Electrostatic embedding field of eq. v_esp_matrix on every shell:
  * phi[s] = sum over shells t of other fragments of gamma_st * dq[t], for the
- * given shell charges dq[n_shells]. */
+ * given shell charges dq[n_shells].  With precision FX_MIXED in the options
+ * the pass of the mixed-precision form runs (FP32 distances, reciprocal
+ * square roots and sums within a source chunk, chunk sums added in FP64);
+ * otherwise the FP64 pass. */
 int fx_embedding_field(fx_ctx* ctx, const double* dq, double* phi);
 
 /* Batched symmetric eigensolver used by the SCC: nmat matrices of sizes n[k]

@@ -32,7 +32,7 @@ class fx_options(C.Structure):
                 ("energy_tol", C.c_double), ("macro_tol", C.c_double), ("max_iter", C.c_int32),
                 ("max_macro", C.c_int32), ("want_gradient", C.c_int32), ("want_response", C.c_int32),
                 ("selection", C.c_int32), ("vdw_dimer", C.c_double), ("vdw_trimer", C.c_double),
-                ("warm_clusters", C.c_int32)]
+                ("warm_clusters", C.c_int32), ("max_response", C.c_int32)]
 
 
 class fx_counts(C.Structure):
@@ -55,7 +55,8 @@ class fx_result(C.Structure):
                 ("ms_dimer", C.c_double), ("ms_trimer", C.c_double), ("ms_energy", C.c_double),
                 ("ms_gradient", C.c_double), ("ms_response", C.c_double), ("guess_fallbacks", C.c_int64),
                 ("first_residual_median", C.c_double), ("n_kstat", C.c_int32),
-                ("kstat", fx_kernel_stat * FX_MAX_KSTAT), ("warm_dimers", C.c_int64)]
+                ("kstat", fx_kernel_stat * FX_MAX_KSTAT), ("warm_dimers", C.c_int64),
+                ("device_allocs", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("kstat", "n_kstat")}
@@ -66,9 +67,11 @@ class fx_result(C.Structure):
 
 
 EXPORTS = ["fx_params_load", "fx_params_free", "fx_ctx_create", "fx_ctx_destroy", "fx_last_error",
+           "fx_workspace_size", "fx_set_workspace",
            "fx_default_options", "fx_set_options", "fx_set_system", "fx_build_lists", "fx_get_counts", "fx_get_lists",
            "fx_set_guess", "fx_run", "fx_get_energies", "fx_get_charges", "fx_get_gradient",
-           "fx_set_coordinates", "fx_md_verlet", "fx_compute_cn", "fx_cluster_matrices", "fx_embedding_field", "fx_eigh_batched",
+           "fx_set_coordinates", "fx_md_verlet", "fx_compute_cn", "fx_cluster_matrices", "fx_embedding_field",
+           "fx_eigh_batched",
            "fx_mlp_load", "fx_mlp_save", "fx_mlp_set_master", "fx_mlp_get_master", "fx_mlp_features",
            "fx_mlp_infer", "fx_mlp_grad", "fx_mlp_train_step"]
 
@@ -103,6 +106,8 @@ def load_library():
     L.fx_ctx_destroy.restype = None
     L.fx_last_error.argtypes = [P]
     L.fx_last_error.restype = C.c_char_p
+    L.fx_workspace_size.argtypes = [P, C.POINTER(C.c_size_t)]
+    L.fx_set_workspace.argtypes = [P, P, C.c_size_t]
     L.fx_default_options.argtypes = [C.POINTER(fx_options)]
     L.fx_set_options.argtypes = [P, C.POINTER(fx_options)]
     L.fx_set_system.argtypes = [P, I32, pI32, pD, I32, pI32, pI32, I32, pI32]
@@ -129,7 +134,8 @@ def load_library():
     L.fx_mlp_infer.argtypes = [P, P, P, I64]
     L.fx_mlp_grad.argtypes = [P, P, P, I64, pD, pF]
     L.fx_mlp_train_step.argtypes = [P, P, P, I64, C.c_float, pD]
-    for name in ["fx_params_load", "fx_ctx_create", "fx_default_options", "fx_set_options", "fx_set_system",
+    for name in ["fx_params_load", "fx_ctx_create", "fx_workspace_size", "fx_set_workspace",
+                 "fx_default_options", "fx_set_options", "fx_set_system",
                  "fx_build_lists", "fx_get_counts", "fx_get_lists", "fx_set_guess", "fx_set_coordinates",
                  "fx_md_verlet", "fx_run", "fx_get_energies",
                  "fx_get_charges", "fx_get_gradient", "fx_compute_cn", "fx_cluster_matrices",
@@ -158,12 +164,27 @@ def default_params_path():
     return os.path.join(ROOT, "workloads", "gfn1_like.json")
 
 
+def _torch_stream_handle(device):
+    """hipStream_t of torch's current stream on `device` (None without a GPU)."""
+    try:
+        import torch
+        if not torch.cuda.is_available():
+            return None
+        return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    except ImportError:
+        return None
+
+
 class FmoXtb:
-    """One library context on a HIP device; methods map 1:1 to the C ABI."""
+    """One library context on a HIP device; methods map 1:1 to the C ABI.
+    stream: a hipStream_t handle; by default torch's current stream on that
+    device (the library's work is then ordered with torch's)."""
 
     def __init__(self, params_path=None, device=0, stream=None):
         self.L = load_library()
         self.device = device
+        if stream is None:
+            stream = _torch_stream_handle(device)
         pp = C.c_void_p()
         rc = self.L.fx_params_load((params_path or default_params_path()).encode(), C.byref(pp))
         if rc != FX_OK:
@@ -209,7 +230,37 @@ class FmoXtb:
             setattr(self.opt, k, v)
         self._check(self.L.fx_set_options(self.ctx, C.byref(self.opt)))
 
+    def workspace_size(self):
+        n = C.c_size_t()
+        self._check(self.L.fx_workspace_size(self.ctx, C.byref(n)))
+        return int(n.value)
+
+    def set_workspace(self, tensor):
+        """Hand the context a caller-owned device workspace (a torch uint8
+        tensor on this device, kept referenced here), or None to return to
+        library allocation.  The context is reset (fx_set_workspace): the
+        system given last is set again."""
+        if tensor is None:
+            self._check(self.L.fx_set_workspace(self.ctx, None, 0))
+        else:
+            if not tensor.is_contiguous() or tensor.element_size() != 1:
+                raise ValueError("workspace must be a contiguous uint8 tensor")
+            self._check(self.L.fx_set_workspace(self.ctx, C.c_void_p(tensor.data_ptr()), tensor.numel()))
+        self._workspace = tensor
+        if getattr(self, "_system_args", None) is not None:
+            self.set_system(*self._system_args)
+
+    def use_workspace(self):
+        """Allocate the workspace that the calls made so far needed as a torch
+        tensor and switch the context to it."""
+        import torch
+        n = self.workspace_size()
+        ws = torch.empty(n, dtype=torch.uint8, device=self._torch_device())
+        self.set_workspace(ws)
+        return ws
+
     def set_system(self, Z, xyz_bohr, atom_frag, frag_charge, bonds=None):
+        self._system_args = (Z, xyz_bohr, atom_frag, frag_charge, bonds)
         Z, xyz, fr, ch = _i32(Z), _f64(xyz_bohr).reshape(-1), _i32(atom_frag), _i32(frag_charge)
         bd = _i32(np.zeros((0, 2)) if bonds is None else np.asarray(bonds).reshape(-1, 2)).reshape(-1)
         nb = len(bd) // 2

@@ -148,16 +148,10 @@ struct fx_params {
 
 namespace fx {
 
+thread_local DevMem* g_devmem = nullptr;
+
 void Ctx::check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw FxError(FX_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-void* Ctx::dmalloc(size_t bytes) {
-  if (bytes == 0) bytes = 8;
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) throw FxError(FX_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-  return p;
 }
 
 void Ctx::sync() { check(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
@@ -1740,13 +1734,11 @@ void Ctx::run(fx_result* out) {
 // ---------------------------------------------------------------------------
 // C ABI
 
-struct fx_ctx {
-  fx::Ctx c;
-};
 
 static thread_local std::string g_param_error;
 
 #define FX_GUARD(ctx, ...)                                   \
+  fx::DevMemScope fx_mem_scope_(&(ctx)->mem);                \
   try {                                                      \
     __VA_ARGS__;                                             \
     (ctx)->c.last_error.clear();                             \
@@ -1782,6 +1774,7 @@ void fx_params_free(fx_params* p) { delete p; }
 int fx_ctx_create(const fx_params* p, int device, void* hip_stream, fx_ctx** out) {
   if (!p || !out) return FX_E_INVALID;
   auto* c = new fx_ctx();
+  fx::DevMemScope scope(&c->mem);
   try {
     c->c.P = p->P;
     c->c.device = device;
@@ -1800,6 +1793,59 @@ int fx_ctx_create(const fx_params* p, int device, void* hip_stream, fx_ctx** out
 }
 
 void fx_ctx_destroy(fx_ctx* ctx) { delete ctx; }
+
+int fx_workspace_size(fx_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return FX_E_INVALID;
+  // the peak plus a margin: launch shapes chosen by timing (the eigensolver
+  // autotuner) can change a few buffer sizes between otherwise identical runs
+  const size_t p = ctx->mem.peak;
+  *bytes = (p + p / 32 + (size_t(4) << 20) + fx::DevMem::kAlign - 1) / fx::DevMem::kAlign * fx::DevMem::kAlign;
+  return FX_OK;
+}
+
+int fx_set_workspace(fx_ctx* ctx, void* dev_ptr, size_t bytes) {
+  if (!ctx) return FX_E_INVALID;
+  if (dev_ptr && (bytes == 0 || reinterpret_cast<uintptr_t>(dev_ptr) % fx::DevMem::kAlign != 0)) {
+    ctx->c.last_error = "workspace must be non-empty and 256-byte aligned";
+    return FX_E_INVALID;
+  }
+  if (!dev_ptr && bytes != 0) {
+    ctx->c.last_error = "a NULL workspace must have size 0";
+    return FX_E_INVALID;
+  }
+  fx::DevMemScope scope(&ctx->mem);
+  try {
+    // back to the state after fx_ctx_create: every buffer is released to the
+    // memory it came from before the new memory takes over
+    fx::HostParams P = ctx->c.P;
+    const int device = ctx->c.device;
+    hipStream_t stream = ctx->c.stream;
+    const fx_options opt = ctx->c.opt;
+    ctx->c.~Ctx();
+    new (&ctx->c) fx::Ctx();
+    if (!ctx->mem.live.empty()) throw fx::FxError(FX_E_STATE, "device buffers outlived the context reset");
+    ctx->mem.base = static_cast<char*>(dev_ptr);
+    ctx->mem.size = bytes;
+    ctx->mem.top = 0;
+    ctx->mem.peak = 0;
+    ctx->mem.free_.clear();
+    ctx->c.P = P;
+    ctx->c.device = device;
+    fx::Ctx::check(hipSetDevice(device), "hipSetDevice");
+    ctx->c.stream = stream;
+    ctx->c.init_device();
+    ctx->c.d_elems.upload(ctx->c.P.elems);
+    ctx->c.opt = opt;
+    ctx->c.last_error.clear();
+    return FX_OK;
+  } catch (const fx::FxError& e) {
+    ctx->c.last_error = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    ctx->c.last_error = e.what();
+    return FX_E_INVALID;
+  }
+}
 
 const char* fx_last_error(const fx_ctx* ctx) { return ctx ? ctx->c.last_error.c_str() : g_param_error.c_str(); }
 
@@ -1823,6 +1869,7 @@ int fx_default_options(fx_options* o) {
   o->vdw_dimer = 2.0;
   o->vdw_trimer = 1.5;
   o->warm_clusters = 0;
+  o->max_response = 400;
   return FX_OK;
 }
 
@@ -1844,6 +1891,7 @@ int fx_set_options(fx_ctx* ctx, const fx_options* o) {
         !std::isfinite(o->vdw_trimer))
       throw fx::FxError(FX_E_INVALID, "van der Waals scaling factors must be positive");
     if (o->warm_clusters != 0 && o->warm_clusters != 1) throw fx::FxError(FX_E_INVALID, "warm_clusters must be 0 or 1");
+    if (o->max_response < 1) throw fx::FxError(FX_E_INVALID, "max_response must be positive");
     const fx_options& c = ctx->c.opt;
     bool cutoff_changed = o->cutoff_bohr != c.cutoff_bohr || o->order != c.order || o->selection != c.selection ||
                           o->vdw_dimer != c.vdw_dimer || o->vdw_trimer != c.vdw_trimer;
@@ -1907,8 +1955,12 @@ int fx_set_guess(fx_ctx* ctx, const double* dq) {
 
 int fx_run(fx_ctx* ctx, fx_result* out) {
   if (!ctx) return FX_E_INVALID;
+  fx::DevMemScope scope(&ctx->mem);
   try {
+    const long long allocs0 = ctx->mem.hip_allocs;
     ctx->c.run(out);
+    ctx->c.res.device_allocs = ctx->mem.hip_allocs - allocs0;
+    if (out) out->device_allocs = ctx->c.res.device_allocs;
     ctx->c.last_error.clear();
     if (!ctx->c.res.converged) {
       ctx->c.last_error = "a fragment SCC or the monomer loop did not converge";
@@ -2010,7 +2062,7 @@ int fx_embedding_field(fx_ctx* ctx, const double* dq, double* phi) {
     fx::DevBuf<double> q, p;
     q.upload(std::vector<double>(dq, dq + c.Nsh));
     p.alloc(c.Nsh);
-    c.field(q.p, p.p);
+    c.field(q.p, p.p, c.opt.precision == FX_MIXED);
     p.download_raw(phi, c.Nsh, c.stream);
     c.sync();
   });

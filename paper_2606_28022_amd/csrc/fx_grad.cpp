@@ -247,7 +247,11 @@ void Ctx::gradient() {
     // more than 1e-6, FP64 from then on (the fixed point is the FP64 one; the
     // tolerance is only tested on FP64 sweeps)
     bool field32 = opt.precision == FX_MIXED;
-    for (it = 1; it <= 400; ++it) {
+    bool resp_converged = false;
+    const int max_sweeps = opt.max_response;
+    // the FP32 sweeps end after a quarter of the allowed sweeps at the latest
+    const int max_fp32_sweeps = std::max(1, max_sweeps / 4);
+    for (it = 1; it <= max_sweeps; ++it) {
       hipLaunchKernelGGL(k_gather_shell, dim3(b.nsys), dim3(64), 0, stream, dmb, yg.p, y.p);
       hipLaunchKernelGGL(k_resp_apply, dim3(b.nsys), dim3(256), 0, stream, dmb, R.p, p_M, y.p, w.p, ul.p);
       hipLaunchKernelGGL(k_scatter_shell, dim3(b.nsys), dim3(64), 0, stream, dmb, ul.p, u.p);
@@ -259,11 +263,12 @@ void Ctx::gradient() {
       sync();
       delta = hs[0];
       if (verbose) std::fprintf(stderr, "[fx] response sweep %d: max |dy| = %.3e\n", it, delta);
-      if (field32 && delta < 1e-6) {
+      if (field32 && (delta < 1e-6 || it >= max_fp32_sweeps)) {
         field32 = false;
         slots.clear();
         next_slot = 0;
       } else if (!field32 && delta < response_tol) {
+        resp_converged = true;
         break;
       }
       int slot;
@@ -283,7 +288,12 @@ void Ctx::gradient() {
                          yg.p);
       check(hipGetLastError(), "response mixing");
     }
-    response_sweeps = it;
+    response_sweeps = std::min(it, max_sweeps);
+    if (!resp_converged) {
+      res.converged = 0;
+      if (verbose) std::fprintf(stderr, "[fx] response not converged after %d sweeps (max |dy| = %.3e)\n",
+                                max_sweeps, delta);
+    }
     // final w, u from the converged y
     hipLaunchKernelGGL(k_gather_shell, dim3(b.nsys), dim3(64), 0, stream, dmb, yng.p, y.p);
     hipLaunchKernelGGL(k_resp_apply, dim3(b.nsys), dim3(256), 0, stream, dmb, R.p, p_M, y.p, w.p, ul.p);

@@ -4,13 +4,17 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
+#include <iterator>
 #include <cmath>
 #include <cstdlib>
 #include <deque>
 #include <map>
 #include <stdexcept>
 #include <string>
+#include <unordered_map>
+#include <utility>
 #include <vector>
 
 #include "../../include/fmoxtb.h"
@@ -23,18 +27,111 @@ struct FxError : std::runtime_error {
   FxError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
 };
 
-// Owning device buffer (hipMalloc / hipFree).
+// Device memory of one context.  Without a workspace every block comes from
+// hipMalloc; with a caller-owned workspace every block is carved from it (first
+// fit over 256-byte granules, freed neighbours merged) and hipMalloc is never
+// called.  The first-fit layout is kept in both modes (in the first only as
+// offsets), so the workspace size a sequence of calls needs is known from a
+// run without one: replaying the same calls into a workspace of `peak` bytes
+// reproduces the same layout.
+struct DevMem {
+  static constexpr size_t kAlign = 256;
+  char* base = nullptr;  // workspace, or nullptr
+  size_t size = 0;
+  size_t top = 0;        // end of the highest block in use
+  size_t peak = 0;       // largest `top` since the last reset
+  long long hip_allocs = 0;
+  std::map<size_t, size_t> free_;                                 // offset -> bytes below top
+  std::unordered_map<void*, std::pair<size_t, size_t>> live;      // block -> (offset, bytes)
+
+  void* alloc(size_t bytes) {
+    bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+    size_t off = top;
+    bool from_free = false;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        off = it->first;
+        const size_t rest = it->second - bytes;
+        free_.erase(it);
+        if (rest) free_[off + bytes] = rest;
+        from_free = true;
+        break;
+      }
+    }
+    if (!from_free && base && top + bytes > size)
+      throw FxError(FX_E_NOMEM, "workspace of " + std::to_string(size) + " bytes is too small (" +
+                                    std::to_string(top + bytes) + " needed so far; fx_workspace_size reports the "
+                                    "need after a run without a workspace)");
+    void* p = nullptr;
+    if (base) {
+      p = base + off;
+    } else {
+      if (hipMalloc(&p, bytes) != hipSuccess) {
+        if (from_free) give_back(off, bytes);
+        throw FxError(FX_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+      }
+      ++hip_allocs;
+    }
+    if (!from_free) top += bytes;
+    peak = std::max(peak, top);
+    live[p] = {off, bytes};
+    return p;
+  }
+  void free(void* p) {
+    auto it = live.find(p);
+    if (it == live.end()) return;
+    const size_t off = it->second.first, bytes = it->second.second;
+    live.erase(it);
+    if (!base) (void)hipFree(p);
+    give_back(off, bytes);
+  }
+  void give_back(size_t off, size_t bytes) {
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && nx->first == off + bytes) {
+      bytes += nx->second;
+      nx = free_.erase(nx);
+    }
+    if (nx != free_.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) {
+        off = pv->first;
+        bytes += pv->second;
+        free_.erase(pv);
+      }
+    }
+    if (off + bytes == top) {
+      top = off;
+    } else {
+      free_[off] = bytes;
+    }
+  }
+};
+
+// the memory of the context whose call is running on this thread
+extern thread_local DevMem* g_devmem;
+
+// Sets g_devmem for the duration of a library call.
+struct DevMemScope {
+  DevMem* prev;
+  explicit DevMemScope(DevMem* m) : prev(g_devmem) { g_devmem = m; }
+  ~DevMemScope() { g_devmem = prev; }
+};
+
+// Owning device buffer; its memory comes from the context's DevMem (hipMalloc
+// or the caller's workspace).
 template <class T>
 struct DevBuf {
   T* p = nullptr;
   long long n = 0;
+  DevMem* mem = nullptr;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), cap(o.cap) {
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), mem(o.mem), cap(o.cap) {
     o.p = nullptr;
     o.n = 0;
     o.cap = 0;
+    o.mem = nullptr;
   }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
@@ -42,22 +139,30 @@ struct DevBuf {
       p = o.p;
       n = o.n;
       cap = o.cap;
+      mem = o.mem;
       o.p = nullptr;
       o.n = 0;
       o.cap = 0;
+      o.mem = nullptr;
     }
     return *this;
   }
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (mem)
+        mem->free(p);
+      else
+        (void)hipFree(p);
+    }
     p = nullptr;
     n = 0;
     cap = 0;
+    mem = nullptr;
   }
   long long cap = 0;
-  // keeps the allocation when it is already large enough (no hipMalloc/hipFree
-  // on repeated runs of the same system)
+  // keeps the allocation when it is already large enough (no new device
+  // memory on repeated runs of the same system)
   void alloc(long long count) {
     if (p && count <= cap) {
       n = count;
@@ -65,7 +170,10 @@ struct DevBuf {
     }
     release();
     size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
-    if (hipMalloc(&p, bytes) != hipSuccess) {
+    if (g_devmem) {
+      p = static_cast<T*>(g_devmem->alloc(bytes));
+      mem = g_devmem;
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
       p = nullptr;
       throw FxError(FX_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
     }
@@ -308,7 +416,6 @@ struct Ctx {
 
 
   static void check(hipError_t e, const char* what);
-  static void* dmalloc(size_t bytes);
   static double now_ms();
   void sync();
   DevSystem dev_system() const;
@@ -351,3 +458,9 @@ struct Ctx {
 };
 
 }  // namespace fx
+
+// the opaque context of the C ABI
+struct fx_ctx {
+  fx::DevMem mem;  // declared first: outlives every buffer of c
+  fx::Ctx c;
+};
