@@ -322,6 +322,21 @@ int fx_cluster_matrices(fx_ctx* ctx, int32_t nfrag, const int32_t* frags, int32_
  * otherwise the FP64 pass. */
 int fx_embedding_field(fx_ctx* ctx, const double* dq, double* phi);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the field
+ * of fx_embedding_field (FP64) with DEVICE pointers d_dq[n_shells] (input
+ * shell charges) and d_phi[n_shells] (output), both owned by the caller.  It
+ * calls no hipMalloc, hipFree or allocating routine: its partial sums live in
+ * a static device array of FX_NOALLOC_SCRATCH_DOUBLES doubles (8 MiB) that
+ * every GPU the library runs on holds until the process ends.  The work is
+ * enqueued on the context's stream and the call returns without waiting;
+ * d_phi is complete when that stream reaches this point.  Calls that overlap
+ * on one GPU (other threads or streams, any context) share the array and
+ * race.  Errors: FX_E_STATE (no system), FX_E_INVALID (NULL pointer, or a
+ * system with more than FX_NOALLOC_SCRATCH_DOUBLES shells), FX_E_DEVICE. */
+#define FX_NOALLOC_SCRATCH_DOUBLES (1 << 20)
+int fx_embedding_field_noalloc(fx_ctx* ctx, const double* d_dq, double* d_phi);
+
 /* Batched symmetric eigensolver used by the SCC: nmat matrices of sizes n[k]
  * (each <= 512), packed one after another row-major in A (sum n[k]^2
  * doubles).  Writes eigenvalues w (sum n[k], unsorted) and eigenvectors as

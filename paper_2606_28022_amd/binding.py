@@ -71,7 +71,7 @@ EXPORTS = ["fx_params_load", "fx_params_free", "fx_ctx_create", "fx_ctx_destroy"
            "fx_default_options", "fx_set_options", "fx_set_system", "fx_build_lists", "fx_get_counts", "fx_get_lists",
            "fx_set_guess", "fx_run", "fx_get_energies", "fx_get_charges", "fx_get_gradient",
            "fx_set_coordinates", "fx_md_verlet", "fx_compute_cn", "fx_cluster_matrices", "fx_embedding_field",
-           "fx_eigh_batched",
+           "fx_embedding_field_noalloc", "fx_eigh_batched",
            "fx_mlp_load", "fx_mlp_save", "fx_mlp_set_master", "fx_mlp_get_master", "fx_mlp_features",
            "fx_mlp_infer", "fx_mlp_grad", "fx_mlp_train_step"]
 
@@ -124,6 +124,7 @@ def load_library():
     L.fx_compute_cn.argtypes = [P, pD]
     L.fx_cluster_matrices.argtypes = [P, I32, pI32, pI32, pD, pD]
     L.fx_embedding_field.argtypes = [P, pD, pD]
+    L.fx_embedding_field_noalloc.argtypes = [P, P, P]
     L.fx_eigh_batched.argtypes = [P, I32, pI32, pD, pD, pD]
     pU16, pF = C.POINTER(C.c_uint16), C.POINTER(C.c_float)
     L.fx_mlp_load.argtypes = [P, pU16, I64]
@@ -139,7 +140,7 @@ def load_library():
                  "fx_build_lists", "fx_get_counts", "fx_get_lists", "fx_set_guess", "fx_set_coordinates",
                  "fx_md_verlet", "fx_run", "fx_get_energies",
                  "fx_get_charges", "fx_get_gradient", "fx_compute_cn", "fx_cluster_matrices",
-                 "fx_embedding_field", "fx_eigh_batched", "fx_mlp_load", "fx_mlp_save", "fx_mlp_set_master",
+                 "fx_embedding_field", "fx_embedding_field_noalloc", "fx_eigh_batched", "fx_mlp_load", "fx_mlp_save", "fx_mlp_set_master",
                  "fx_mlp_get_master", "fx_mlp_features", "fx_mlp_infer", "fx_mlp_grad", "fx_mlp_train_step"]:
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -370,6 +371,15 @@ class FmoXtb:
         phi = np.zeros_like(dq)
         self._check(self.L.fx_embedding_field(self.ctx, _ptr(dq, C.c_double), _ptr(phi, C.c_double)))
         return phi
+
+    def embedding_field_noalloc(self, dq, phi):
+        """fx_embedding_field_noalloc on torch tensors (float64, on this
+        context's device, n_shells each); enqueued on the context's stream."""
+        for t in (dq, phi):
+            if t.dtype.itemsize != 8 or not t.is_contiguous() or (self.n_shells and t.numel() != self.n_shells):
+                raise ValueError("float64 contiguous tensors of n_shells entries expected")
+        self._check(self.L.fx_embedding_field_noalloc(self.ctx, C.c_void_p(dq.data_ptr()),
+                                                      C.c_void_p(phi.data_ptr())))
 
     def eigh_batched(self, mats):
         ns = _i32([m.shape[0] for m in mats])

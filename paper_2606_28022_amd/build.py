@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfmoxtb.so")
 SOURCES = ["fx_api.cpp", "fx_grad.cpp", "fx_integrals.hip", "fx_scc.hip", "fx_fmo.hip", "fx_gradk.hip",
-           "fx_resp.hip", "fx_mlp.hip"]
+           "fx_resp.hip", "fx_mlp.hip", "fx_noalloc.hip"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

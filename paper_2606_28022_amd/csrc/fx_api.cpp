@@ -444,6 +444,7 @@ void Ctx::init_device() {
                         reinterpret_cast<const void*>(k_cholinv_block2)})
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
   (void)hipGetLastError();
+  noalloc_init(device);
   if (verbose) std::fprintf(stderr, "[fx] LDS per workgroup %d B, static %u B\n", v, stat);
 }
 

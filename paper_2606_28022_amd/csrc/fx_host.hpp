@@ -432,6 +432,9 @@ struct Ctx {
   void build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters, int nfrag_each);
   void build_matrices(Batch& b);
   void init_device();
+  // embedding field through the chunked pass into caller-given device
+  // buffers, partial sums in the library's static scratch (no allocation)
+  void field_noalloc(const double* d_q, double* d_phi);
   JacobiPlan jacobi_plan(int n, bool fp64_only = false, bool prefer_fp32 = false) const;
   // autotuned eigensolver launch shapes per (size bucket, precision)
   bool autotune = !(std::getenv("FX_AUTOTUNE") && std::atoi(std::getenv("FX_AUTOTUNE")) == 0);
@@ -456,6 +459,11 @@ struct Ctx {
                  double* e_kin);
   void gradient();
 };
+
+// static device scratch of fx_embedding_field_noalloc: address lookup once per
+// device (called from init_device with that device current) and the address
+void noalloc_init(int device);
+double* noalloc_scratch(int device);
 
 }  // namespace fx
 
