@@ -8,7 +8,7 @@ ES-DIM pairs, the energy and the FMO2 gradient including the embedding
 response.  The system is uploaded before timing (inputs resident in HBM).
 
 Prints one JSON line.  Usage:
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain] [--no-guess] [--no-mixed] [--no-warm] [--no-fmo3]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain] [--no-guess] [--no-forms] [--no-warm] [--no-fmo3]
 """
 
 import argparse
@@ -22,14 +22,89 @@ sys.path.insert(0, ROOT)
 
 MI355X_FP64_PEAK_TFLOPS = 78.6
 
+# HBM traffic of the dominant kernel on this workload, from two rocprofv3 PMC
+# passes (FETCH_SIZE scaled by 2 and WRITE_SIZE by 1, the factors a 1 GiB
+# device copy gives), bytes per launch; valid while the kernel is unchanged
+# (profiles/k_apply_rot_pentacene_fmo2.md gives the commands)
+PMC_TRAFFIC_BYTES = {"fx::k_apply_rot": 734e6 + 365e6}
+
+
+def scc_iteration_work(n, n_occ):
+    """Algorithmic flops of one SCC iteration of an n-AO system with n_occ
+    occupied orbitals: 3.3 n^3 for a dense symmetric eigensolve (reduction and
+    back-transformation of the eigenvectors) plus 5 n^2 n_occ for the
+    transformations and the density over the occupied orbitals."""
+    return 3.3 * n ** 3 + 5.0 * n * n * n_occ
+
+
+def fragment_sizes(s):
+    """(AOs, occupied orbitals) of a neutral fragment of the system (the
+    crystal's fragments are identical molecules)."""
+    import numpy as np
+    from oracle.params import default_params
+    p = default_params()
+    atoms = np.where(s.frag == 0)[0]
+    nao = sum(sum(1 if sh["l"] == 0 else 3 for sh in p.element(int(s.Z[a]))["shells"]) for a in atoms)
+    nel = sum(sum(sh["q0"] for sh in p.element(int(s.Z[a]))["shells"]) for a in atoms)
+    return nao, int(round(nel / 2))
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(system, timed_result):
-    """Time the FP64 oracle on a bounded sample of the same workload and scale
-    it to seconds per step with the GPU run's solve counts."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_ORACLE = {}
+
+
+def _oracle_task(args):
+    """One unit of oracle work in a pool worker: a monomer SCC, an SCC dimer
+    (with its explicit gradient terms) or a chunk of an embedding-field pass
+    (all in the zero embedding field where a field is needed)."""
+    import numpy as np
+    from oracle import fmo as F
+    from oracle import xtb as X
+    kind, idx = args
+    st = _ORACLE
+    p, s, fa, cn = st["p"], st["s"], st["fa"], st["cn"]
+    t = time.perf_counter()
+    if kind == "mono":
+        sm = X.XtbSystem(p, s.Z[fa[idx]], s.xyz[fa[idx]], cn[fa[idx]])
+        X.scc(sm)
+    elif kind == "dimer":
+        I, J = idx
+        at = np.concatenate([fa[I], fa[J]])
+        sd = X.XtbSystem(p, s.Z[at], s.xyz[at], cn[at])
+        rd = X.scc(sd)
+        DS = 0.5 * (rd.sigma[sd.ao_sh][:, None] + rd.sigma[sd.ao_sh][None, :]) * rd.P - rd.Wt
+        X.system_gradient(sd, rd.P, DS, rd.q, rd.q, True)
+    else:
+        sh = st["sh"]
+        same = lambda a, b: sh.frag[a] == sh.frag[b]
+        sh.potential(np.arange(idx, min(sh.n, idx + 512)), st["q"], same, chunk=512)
+    return time.perf_counter() - t
+
+
+def cpu_baseline(system, timed_result, workers):
+    """Time the FP64 oracle on a bounded sample of the same workload, with a
+    process pool over fragments as the oracle runs large systems, and scale it
+    to seconds per step: the supersystem CN (timed on 4096 atoms, scaled by
+    the square of the atom ratio); one pool round of monomer SCCs, one of SCC
+    dimers with their explicit gradient terms and one of field-pass chunks,
+    each scaled to the step's counts (monomer solves per sweep times the
+    sweeps, SCC dimers, field chunks per pass times the passes).  The oracle's
+    response (dense inter-fragment kernel) is not part of the sample."""
+    import multiprocessing
     import numpy as np
     from oracle import fmo as F
     from oracle import xtb as X
@@ -37,51 +112,115 @@ def cpu_baseline(system, timed_result):
 
     p = default_params()
     A2B = 1.0 / 0.529177210903
-    # the oracle CN is an all-pairs O(N^2) sum: time it on the first 4096
-    # atoms and scale by (N / 4096)^2
     nsub = min(4096, system.n_atoms)
-    t0 = time.time()
+    t0 = time.perf_counter()
     X.coordination_numbers(p, system.Z[:nsub], system.xyz[:nsub])
-    t_cn = (time.time() - t0) * (system.n_atoms / nsub) ** 2
+    t_cn = (time.perf_counter() - t0) * (system.n_atoms / nsub) ** 2
     cn = np.zeros(system.n_atoms)
     fa = F.fragment_atoms(system.frag, system.n_frag)
-    # CN of the sampled fragments' atoms from their 12-molecule neighbourhood
-    near = np.concatenate([fa[k] for k in range(12)])
-    sub = system.subset(list(range(12)))
+    sub = system.subset(list(range(24)))
+    near = np.concatenate([fa[k] for k in range(24)])
     cn[near] = X.coordination_numbers(p, sub.Z, sub.xyz)
-    # one monomer SCC and one SCC dimer (with its gradient terms) of the crystal
-    t0 = time.time()
-    sm = X.XtbSystem(p, system.Z[fa[0]], system.xyz[fa[0]], cn[fa[0]])
-    rm = X.scc(sm)
-    t_mono = time.time() - t0
-    scc, _, _ = F.build_lists(system.subset(list(range(12))), 4.0 * A2B)
-    I, J = scc[0]
-    at = np.concatenate([fa[I], fa[J]])
-    t0 = time.time()
-    sd = X.XtbSystem(p, system.Z[at], system.xyz[at], cn[at])
-    rd = X.scc(sd, q_guess=None)
-    t_dimer = time.time() - t0
-    t0 = time.time()
-    DS = 0.5 * (rd.sigma[sd.ao_sh][:, None] + rd.sigma[sd.ao_sh][None, :]) * rd.P - rd.Wt
-    X.system_gradient(sd, rd.P, DS, rd.q, rd.q, True)
-    t_dgrad = time.time() - t0
-    n_mono_solves = timed_result["solves_mono"]
+    scc_pairs, _, _ = F.build_lists(sub, 4.0 * A2B)
+    sh = F.Shells(p, F.ExtendedAtoms(system, cn))
+    rng = np.random.Generator(np.random.PCG64(5))
+    _ORACLE.update(p=p, s=system, fa=fa, cn=cn, sh=sh, q=rng.normal(0.0, 0.1, sh.n))
+    ctx = multiprocessing.get_context("fork")
+
+    def init():
+        try:
+            from threadpoolctl import threadpool_limits
+            threadpool_limits(1)
+        except ImportError:
+            pass
+
+    def pool_round(tasks):
+        with ctx.Pool(workers, initializer=init) as pool:
+            t = time.perf_counter()
+            pool.map(_oracle_task, tasks, chunksize=1)
+            return time.perf_counter() - t
+
+    nw = workers
+    t_mono = pool_round([("mono", k % 24) for k in range(nw)])
+    dimers = [tuple(map(int, scc_pairs[k % len(scc_pairs)])) for k in range(nw)]
+    t_dimer = pool_round([("dimer", d) for d in dimers])
+    t_field = pool_round([("field", 512 * k) for k in range(nw)])
+    sweeps = timed_result["macro_iter"]
+    n_mono = sweeps * system.n_frag
     n_dimers = timed_result["solves_dimer"]
-    est = (t_cn + n_mono_solves * t_mono + n_dimers * (t_dimer + t_dgrad)
-           + system.n_frag * t_dgrad / 4.0)
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count()
+    chunks_per_pass = (sh.n + 511) // 512
+    est = (t_cn + t_mono * n_mono / nw + t_dimer * n_dimers / nw
+           + t_field * (sweeps + 1) * chunks_per_pass / nw)
     return {
-        "value": est, "unit": "s/step", "cores": int(cores), "kind": "oracle",
-        "sample": (f"oracle timed on one monomer SCC ({t_mono:.2f} s), one SCC dimer "
-                   f"({t_dimer:.2f} s) plus its gradient terms ({t_dgrad:.2f} s) and the "
-                   f"supersystem CN ({t_cn:.2f} s, timed on {nsub} atoms and scaled by the square "
-                   f"of the atom ratio) of this crystal, scaled by the GPU run's "
-                   f"{n_mono_solves} monomer solves and {n_dimers} dimers"),
+        "value": est, "unit": "s/step", "cores": int(nw), "kind": "oracle",
+        "cpu_model": _cpu_model(),
+        "sample": (f"FP64 oracle, pool of {nw} worker processes (one BLAS thread each): one round of {nw} "
+                   f"monomer SCCs ({t_mono:.2f} s), of {nw} SCC dimers with their explicit gradient terms "
+                   f"({t_dimer:.2f} s) and of {nw} field-pass chunks of 512 target shells ({t_field:.2f} s), "
+                   f"plus the supersystem CN ({t_cn:.2f} s, timed on {nsub} atoms and scaled by the square of "
+                   f"the atom ratio); scaled to {sweeps} sweeps of {system.n_frag} monomer solves, "
+                   f"{n_dimers} SCC dimers and {sweeps + 1} field passes of {chunks_per_pass} chunks; the "
+                   f"oracle's response is not included"),
     }
+
+
+def _golden_c4():
+    path = os.path.join(ROOT, "tests", "golden", "pentacene_c4.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def forms_c4(c, s, sec_fp64, r64, g64):
+    """The forms of the step on the same crystal, each timed after a warm-up
+    run (the one-system-at-a-time loop once, without warm-up): the plain
+    per-fragment GPU loop (FX_PLAIN_LOOP, FP64), the batched FP64 form (the
+    headline), the mixed-precision form, the learned initial guess, the
+    captured-graph schedule, and the combined batched + mixed + learned form.
+    Each reports |E - E_oracle| against the oracle golden of this crystal and
+    max |g - g_FP64| against the batched FP64 gradient (pinned by central
+    differences in the tests)."""
+    import numpy as np
+    import torch
+    from paper_2606_28022_amd.binding import trained_guess_model
+    ref = _golden_c4()
+    blob, tau = trained_guess_model()
+    c.mlp_load(blob)
+    defaults = dict(schedule=0, precision=0, guess=0, guess_tau=0.0)
+    variants = [("plain_loop_fp64", dict(schedule=1), False),
+                ("batched_mixed", dict(precision=1), True),
+                ("batched_learned_guess", dict(guess=1, guess_tau=tau), True),
+                ("graph_fp64", dict(schedule=2), True),
+                ("combined_batched_mixed_learned", dict(precision=1, guess=1, guess_tau=tau), True)]
+    out = {"workload": "same crystal, FMO2 energy + analytic gradient with response",
+           "batched_fp64": {"s_per_step": sec_fp64,
+                            "abs_dE_vs_oracle_Eh": abs(r64["e_total"] - ref["E"]) if ref else None}}
+    for name, opts, warm in variants:
+        c.set_options(**defaults)
+        c.set_options(**opts)
+        if warm:
+            c.run()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rv = c.run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        gv = c.gradient()
+        out[name] = {"s_per_step": dt,
+                     "abs_dE_vs_oracle_Eh": abs(rv["e_total"] - ref["E"]) if ref else None,
+                     "abs_dE_vs_fp64_Eh": abs(rv["e_total"] - r64["e_total"]),
+                     "max_abs_dgrad_vs_fp64_Eh_per_bohr": float(np.abs(gv - g64).max()),
+                     "iterations": {"monomer": rv["iters_mono"], "dimer": rv["iters_dimer"],
+                                    "macro": rv["macro_iter"], "fp32": rv["iters_fp32"]},
+                     "phases_ms": {k: round(rv[k], 2) for k in ("ms_monomer", "ms_dimer", "ms_gradient",
+                                                                "ms_response")}}
+        log(f"form {name}: {dt:.3f} s, E = {rv['e_total']:.8f}")
+    c.set_options(**defaults)
+    t_plain = out["plain_loop_fp64"]["s_per_step"]
+    out["speedup_vs_plain_loop"] = {k: t_plain / v["s_per_step"] for k, v in out.items()
+                                    if isinstance(v, dict) and "s_per_step" in v and k != "plain_loop_fp64"}
+    return out
 
 
 def plain_vs_batched():
@@ -255,7 +394,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-guess", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-warm", action="store_true")
     ap.add_argument("--no-fmo3", action="store_true")
     args = ap.parse_args()
@@ -299,9 +438,14 @@ def main():
     solves = r["solves_mono"] + r["solves_dimer"]
 
     # roofline of the dominant kernel: the library times its hot kernels with
-    # HIP events on the context stream (fx_result.kstat, largest first); all
-    # of them compute in FP64 (the FP32-stored Jacobi working matrix aside),
-    # so the FP64 peak (78.6 TFLOP/s, vector and matrix alike) is the ceiling
+    # HIP events on the context stream (fx_result.kstat, largest first) and
+    # credits each with algorithmic work: the eigensolver kernels 3.3 n^3 per
+    # SCC iteration (the split form: 1.3 n^3 to the rotation kernel, 2 n^3,
+    # the back-transformation of the eigenvectors, to the apply kernel),
+    # products 2 n^3 (symmetric ones by the tiles computed, the density over
+    # the occupied orbitals 2 n^2 n_occ), field passes 8 flop per shell pair.
+    # All compute in FP64 (the FP32-stored Jacobi working matrix aside), so the
+    # FP64 peak (78.6 TFLOP/s, vector and matrix alike) is the ceiling.
     kern = {}
     for k in r["kernels"]:
         nl = max(1, k["launches"])
@@ -310,12 +454,26 @@ def main():
                            "avg_launch_ms": avg, "launches": k["launches"], "total_ms": k["ms"],
                            "share_of_step": k["ms"] / (1000.0 * sec)}
     dom = r["kernels"][0]["name"]
-    bound = "mfma" if "gemm_mfma" in dom else "alu"
+    bound = "mfma" if "gemm" in dom else "alu"
+    # whole step: the SCC iterations at 3.3 n^3 + 5 n^2 n_occ each plus the
+    # field passes, over the measured step time
+    nm, om = fragment_sizes(s)
+    field_gflop = sum(k["gflop"] for k in r["kernels"] if k["name"].startswith("fx::k_field"))
+    work = (r["iters_mono"] * scc_iteration_work(nm, om) + r["iters_dimer"] * scc_iteration_work(2 * nm, 2 * om)
+            + 1e9 * field_gflop)
+    step_rate = work / sec / 1e12
+    traffic = PMC_TRAFFIC_BYTES.get(dom)
     roofline = {"bound": bound, "kernel": dom,
                 "achieved": kern[dom]["achieved"], "peak": MI355X_FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": kern[dom]["achieved"] / MI355X_FP64_PEAK_TFLOPS, "traffic": None,
+                "frac": kern[dom]["achieved"] / MI355X_FP64_PEAK_TFLOPS, "traffic": traffic,
+                "traffic_unit": "bytes per launch (HBM, PMC)" if traffic else None,
                 "avg_launch_ms": kern[dom]["avg_launch_ms"], "launches": kern[dom]["launches"],
-                "share_of_step": kern[dom]["share_of_step"], "kernels": kern}
+                "share_of_step": kern[dom]["share_of_step"],
+                "whole_step": {"achieved": step_rate, "frac": step_rate / MI355X_FP64_PEAK_TFLOPS,
+                               "algorithmic_tflop": work / 1e12,
+                               "accounting": f"SCC iterations x (3.3 n^3 + 5 n^2 n_occ), n = {nm} / {2 * nm}, "
+                                             f"n_occ = {om} / {2 * om}, plus field passes"},
+                "kernels": kern}
 
     out = {
         "metric": "FMO2 energy+grad s/step; fragment SCC solves/s; batched vs plain @1e-6 Eh",
@@ -324,7 +482,10 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "pentacene 11x5x6 crystal, FMO2 energy + analytic gradient with response",
                    "atoms": s.n_atoms, "fragments": s.n_frag, "scc_dimers": int(cnt.n_scc_pairs),
-                   "es_dim_pairs": int(cnt.n_esd_pairs), "cutoff_angstrom": 4.0, "precision": "fp64",
+                   "es_dim_pairs": int(cnt.n_esd_pairs), "cutoff_angstrom": 4.0,
+                   "precision": ("fp64: basis, products, rotation angles, energies and gradient; the Jacobi "
+                                 "working matrix of the 232-AO dimers is stored in FP32 between FP64 rebuilds "
+                                 "of C^T F C"),
                    "schedule": "batched"},
         "scc_solves_per_s": solves / sec,
         "solves_per_s_by_phase": {"monomer": r["solves_mono"] / (1e-3 * r["ms_monomer"]),
@@ -344,24 +505,12 @@ def main():
         sp, de, tb, tp = plain_vs_batched()
         out["batched_vs_plain"] = {"workload": "water droplet 1024 molecules, FMO2 energy, fp64",
                                    "speedup": sp, "abs_dE": de, "batched_s": tb, "plain_s": tp}
-    if not args.no_mixed:
-        # the same step in the mixed-precision form (warm-up run first)
-        c.set_options(precision=1)
-        c.run()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        rm = c.run()
-        torch.cuda.synchronize()
-        tm = time.perf_counter() - t
-        gm = c.gradient()
-        c.set_options(precision=0)
-        out["mixed_vs_fp64"] = {"workload": "same step, FX_MIXED", "s_per_step": tm, "speedup": sec / tm,
-                                "abs_dE_Eh": abs(rm["e_total"] - r["e_total"]),
-                                "max_abs_dgrad_Eh_per_bohr": float(np.abs(gm - g).max())}
+    if not args.no_forms:
+        out["forms"] = forms_c4(c, s, sec, r, g)
     if not args.no_guess:
         out["learned_guess"] = learned_guess_stream()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(s, r)
+        out["cpu_baseline"] = cpu_baseline(s, r, workers=min(16, os.cpu_count() or 1))
     print(json.dumps(out), flush=True)
 
 

@@ -74,11 +74,21 @@ typedef struct fx_options {
                              closest interatomic distance is below this value,
                              otherwise ES-DIM; a trimer is computed when at
                              least two of its three pairs are SCC dimers */
-  int32_t precision;      /* FX_FP64, or FX_MIXED: FP32 eigensolver working
-                             matrices for every system (the basis stays FP64)
-                             and FP32 embedding-field passes while the monomer
-                             charges still move by more than 1e-6; results
-                             keep the FP64 tolerances (iterative refinement) */
+  int32_t precision;      /* FX_FP64, or FX_MIXED: while an SCC residual is
+                             above 1e-5, the Fock matrix is assembled in FP32
+                             from FP32 copies of H0 and S and the congruence
+                             product C^T F C and the density product
+                             C diag(n) C^T run on the FP32 matrix cores with
+                             FP32 accumulation (systems of more than 32 AOs
+                             without cut bonds); the embedding-field passes
+                             are FP32 while the monomer charges move by more
+                             than 1e-6.  The basis, the eigensolver, the last
+                             SCC iterations, the energies and the pair
+                             differences stay FP64, so results keep the FP64
+                             tolerances.  In both forms the Jacobi working
+                             matrix of systems too large for an FP64 copy in
+                             LDS (more than about 180 AOs) is stored in FP32
+                             between FP64 rebuilds of C^T F C. */
   int32_t schedule;       /* FX_BATCHED: all fragments of a kind in one launch
                              sequence; FX_PLAIN_LOOP: one fragment at a time */
   int32_t guess;          /* initial monomer charges: superposition (zero),
@@ -163,6 +173,8 @@ typedef struct fx_result {
   int64_t device_allocs;  /* hipMalloc calls made by this fx_run (0 with a
                              workspace, and 0 without one once the buffers of
                              the same system and options already exist) */
+  int64_t iters_fp32;     /* FX_MIXED: SCC iterations (summed over systems)
+                             that ran the FP32 Fock build and products */
 } fx_result;
 
 /* Caller-owned device memory (the PyTorch wrapper passes a uint8 tensor).

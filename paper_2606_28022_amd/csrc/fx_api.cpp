@@ -479,6 +479,30 @@ void Ctx::gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlis
   check(hipGetLastError(), "batched product");
 }
 
+void Ctx::gemm_batch_f32(const Batch& b, const DevBatch& db, int nl, const int* dlist, int mode, const void* A,
+                         const void* B, void* C, const double* w, double gflop, int skip_done, int sym,
+                         bool occ_list) {
+  if (nl <= 0) return;
+  const int nt = (b.max_nao + 63) / 64;
+  const long long tiles = (long long)nl * nt * nt;
+  const long long grid = (tiles + 7) / 8 * 8;
+  if (grid > 0x7fffffffLL) throw FxError(FX_E_INVALID, "batched product grid too large");
+  const int ev = capturing ? -1 : timers.begin(stream);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_gemm_f32<0, double, float, float>), dim3((unsigned)grid), dim3(256), 0, stream, db, dlist,
+                       nl, nt * nt, (const double*)A, (const float*)B, (float*)C, w, skip_done, sym, occ_list ? 1 : 0);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_gemm_f32<1, float, double, double>), dim3((unsigned)grid), dim3(256), 0, stream, db,
+                       dlist, nl, nt * nt, (const float*)A, (const double*)B, (double*)C, w, skip_done, sym,
+                       occ_list ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_gemm_f32<2, double, double, double>), dim3((unsigned)grid), dim3(256), 0, stream, db,
+                       dlist, nl, nt * nt, (const double*)A, (const double*)B, (double*)C, w, skip_done, sym,
+                       occ_list ? 1 : 0);
+  if (!capturing) timers.end(stream, ev, kt("fx::k_gemm_f32"), gflop);
+  check(hipGetLastError(), "batched FP32 product");
+}
+
 unsigned Ctx::resp_M_lds(const Batch& b) const {
   int nsh = 0;
   for (const auto& d : b.h_desc) nsh = std::max(nsh, d.nsh);
@@ -722,6 +746,19 @@ void Ctx::build_matrices(Batch& b) {
   hipLaunchKernelGGL(k_build_system, dim3(b.nsys), dim3(256), 0, stream, dev_system(), db, nullptr);
   if (b.has_hop) hipLaunchKernelGGL(k_vhop, dim3(b.nsys), dim3(256), 0, stream, db, P.g.VHOP);
   check(hipGetLastError(), "k_build_system");
+  // mixed precision: FP32 copies of H0 and S for the FP32 Fock builds
+  b.has_f32 = opt.precision == FX_MIXED && !b.has_hop && b.max_nao > 32;
+  if (b.has_f32) {
+    const long long m = std::max(1LL, b.tot_mat);
+    b.H0f.alloc(m);
+    b.Sf.alloc(m);
+    b.Ff.alloc(m);
+    b.Tf.alloc(m);
+    const unsigned g = (unsigned)std::min<long long>(65536, (m + 255) / 256);
+    hipLaunchKernelGGL(k_to_f32, dim3(g), dim3(256), 0, stream, (const double*)b.H0.p, b.H0f.p, b.tot_mat);
+    hipLaunchKernelGGL(k_to_f32, dim3(g), dim3(256), 0, stream, (const double*)b.S.p, b.Sf.p, b.tot_mat);
+    check(hipGetLastError(), "k_to_f32");
+  }
 }
 
 // SCC for the systems in `list` (indices into the batch).  q_in must hold the
@@ -829,13 +866,13 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     }
     check(hipGetLastError(), "initial basis");
   }
-  JacobiPlan jp = jacobi_plan(b.max_nao, b.has_hop, opt.precision == FX_MIXED && !b.has_hop);
+  JacobiPlan jp = jacobi_plan(b.max_nao, b.has_hop, false);
   {
     auto itp = tuned.find(jp_key(b.max_nao, jp.elt));
     if (itp != tuned.end()) jp = itp->second;
   }
   std::vector<int> active = list;
-  std::vector<int> sweeps(b.nsys), status(b.nsys), niter(b.nsys);
+  std::vector<int> status(b.nsys), niter(b.nsys);
   DevBuf<int> d_act;
   KernelTimer* kt_jac = kt(jp.elt == 8 ? "fx::k_jacobi_lds<double>" : jp.elt == 4 ? "fx::k_jacobi_lds<float>"
                                                                                    : "fx::k_jacobi");
@@ -856,12 +893,38 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
   }
   KernelTimer* kt_rot = kt(jp.elt == 8 ? "fx::k_jacobi_rot<double>" : "fx::k_jacobi_rot<float>");
   KernelTimer* kt_app = kt("fx::k_apply_rot");
-  auto launch_iteration = [&](const std::vector<int>& act, const int* dl, int na, double cap, bool timed) {
-    hipLaunchKernelGGL(k_fock, dim3(na), dim3(256), 0, stream, ds, db, dl);
-    // A = C^T F C in the current basis, then Jacobi rotations
-    gemm_batch(b, db, na, dl, 0, b.Ct.p, b.Fm.p, b.Tm.p, nullptr, b.gemm_gflop(act), 1);
-    // A = (C^T F) C is symmetric: upper tiles only, mirrored
-    gemm_batch(b, db, na, dl, 1, b.Tm.p, b.Ct.p, b.Fm.p, nullptr, b.gemm_gflop(act), 1, 1);
+  // mixed precision: FP32 Fock build and FP32 matrix-core products for this
+  // iteration (the basis, the rotation angles and the convergence test stay
+  // FP64; a system converges only in an FP64 iteration).  Not with the
+  // captured graph, whose launches are fixed.
+  const bool graph_mode = opt.schedule == FX_BATCHED_GRAPH && !single && !first_solve;
+  const bool f32_ok = b.has_f32 && !graph_mode && prod_mode != 0;
+  // per system: still in the FP32 phase (until its own SCC residual drops to
+  // mixed_thr; its Anderson history is then cleared, so that the FP64
+  // iterations mix FP64 residuals only)
+  std::vector<char> is32(b.nsys, f32_ok ? 1 : 0);
+  std::vector<int> switched;
+  DevBuf<int> d_switched;
+  // one SCC iteration over the na systems listed in dl, of which the first
+  // n32 run the FP32 Fock build and products (mixed precision)
+  auto launch_iteration = [&](const std::vector<int>& act, const int* dl, int na, int n32, double cap,
+                              bool timed) {
+    const int n64 = na - n32;
+    const int* dl64 = dl + n32;
+    const std::vector<int> a32(act.begin(), act.begin() + n32), a64(act.begin() + n32, act.end());
+    if (n32 > 0) {
+      hipLaunchKernelGGL(k_fock_f32, dim3(n32), dim3(256), 0, stream, ds, db, dl, (const float*)b.H0f.p,
+                         (const float*)b.Sf.p, b.Ff.p);
+      gemm_batch_f32(b, db, n32, dl, 0, b.Ct.p, b.Ff.p, b.Tf.p, nullptr, b.gemm_gflop(a32), 1, 0, false);
+      gemm_batch_f32(b, db, n32, dl, 1, b.Tf.p, b.Ct.p, b.Fm.p, nullptr, b.gemm_gflop_sym(a32), 1, 1, false);
+    }
+    if (n64 > 0) {
+      hipLaunchKernelGGL(k_fock, dim3(n64), dim3(256), 0, stream, ds, db, dl64);
+      // A = C^T F C in the current basis, then Jacobi rotations
+      gemm_batch(b, db, n64, dl64, 0, b.Ct.p, b.Fm.p, b.Tm.p, nullptr, b.gemm_gflop(a64), 1);
+      // A = (C^T F) C is symmetric: upper tiles only, mirrored
+      gemm_batch(b, db, n64, dl64, 1, b.Tm.p, b.Ct.p, b.Fm.p, nullptr, b.gemm_gflop_sym(a64), 1, 1);
+    }
     if (split_ok && cap < 1e299) {
       const unsigned lds_rot = jacobi_rot_layout(b.max_nao, jp.elt).total;
       int ev = timed ? timers.begin(stream) : -1;
@@ -898,16 +961,24 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     if (timed) timers.end(stream, ev, kt_jac, 0.0);
     }
     hipLaunchKernelGGL(k_fermi, dim3(na), dim3(256), 0, stream, ds, db, dl);
-    gemm_batch(b, db, na, dl, 2, b.Ct.p, b.Ct.p, b.Pm.p, b.occ.p, b.gemm_gflop_occ(act), 1, 1, true);
-    hipLaunchKernelGGL(k_charges_mix, dim3(na), dim3(256), 0, stream, ds, db, dl,
-                       scc_tol_cur > 0 ? scc_tol_cur : opt.scc_tol, etol_cur > 0 ? etol_cur : opt.energy_tol,
-                       single ? 1 : opt.max_iter, b.has_pre ? precond_beta : mix_beta);
+    if (n32 > 0)
+      gemm_batch_f32(b, db, n32, dl, 2, b.Ct.p, b.Ct.p, b.Pm.p, b.occ.p, b.gemm_gflop_occ(a32), 1, 1, true);
+    if (n64 > 0)
+      gemm_batch(b, db, n64, dl64, 2, b.Ct.p, b.Ct.p, b.Pm.p, b.occ.p, b.gemm_gflop_occ(a64), 1, 1, true);
+    // a system converges only in an FP64 iteration
+    const double beta = b.has_pre ? precond_beta : mix_beta;
+    if (n32 > 0)
+      hipLaunchKernelGGL(k_charges_mix, dim3(n32), dim3(256), 0, stream, ds, db, dl, -1.0, -1.0,
+                         single ? 1 : opt.max_iter, beta);
+    if (n64 > 0)
+      hipLaunchKernelGGL(k_charges_mix, dim3(n64), dim3(256), 0, stream, ds, db, dl64,
+                         scc_tol_cur > 0 ? scc_tol_cur : opt.scc_tol, etol_cur > 0 ? etol_cur : opt.energy_tol,
+                         single ? 1 : opt.max_iter, beta);
     check(hipGetLastError(), "scc iteration");
   };
   // FX_BATCHED_GRAPH: after the first (eager) iteration, the iteration over
   // the whole list is captured once into a hipGraph and replayed; converged
   // systems skip themselves on the device, the host only reads the status
-  const bool graph_mode = opt.schedule == FX_BATCHED_GRAPH && !single && !first_solve;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   for (int it = 0; it < max_it && !active.empty(); ++it) {
@@ -920,7 +991,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
         stream = gstream;
         capturing = true;
         check(hipStreamBeginCapture(gstream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-        launch_iteration(list, b.d_list.p, nl, jacobi_cap_err, false);
+        launch_iteration(list, b.d_list.p, nl, 0, jacobi_cap_err, false);
         const hipError_t ec = hipStreamEndCapture(gstream, &graph);
         capturing = false;
         stream = saved;
@@ -940,8 +1011,24 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
       active.swap(next);
       continue;
     }
+    int n32 = 0;
+    if (f32_ok) {
+      std::vector<int> ordered;
+      for (int s : active)
+        if (is32[s]) ordered.push_back(s);
+      n32 = (int)ordered.size();
+      for (int s : active)
+        if (!is32[s]) ordered.push_back(s);
+      active.swap(ordered);
+    }
     d_act.upload(active);
     const int na = (int)active.size();
+    if (!switched.empty()) {
+      d_switched.upload(switched);
+      hipLaunchKernelGGL(k_hist_reset, dim3(((int)switched.size() + 255) / 256), dim3(256), 0, stream, db,
+                         (const int*)d_switched.p, (int)switched.size());
+      switched.clear();
+    }
     if (it == 1 && autotune && !split_ok && jp.elt != 0 && !tuned.count(jp_key(b.max_nao, jp.elt))) {
       // form this iteration's A once, time the eigensolver's launch shapes
       // on copies of (A, C^T) and keep the fastest for this size bucket; all
@@ -952,7 +1039,8 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
       jp = autotune_jacobi(b, d_act.p, na, jp, cap);
       tuned[jp_key(b.max_nao, jp.elt)] = jp;
     }
-    launch_iteration(active, d_act.p, na, cap, true);
+    launch_iteration(active, d_act.p, na, n32, cap, true);
+    res.iters_fp32 += n32;
     if (first_solve && it == 0) {
       // median first-iteration residual over the batch
       std::vector<double> e;
@@ -972,27 +1060,52 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
       check(hipGetLastError(), "k_guess_fallback");
     }
     b.status.download(status, stream);
-    b.sweeps.download(sweeps, stream);
+    std::vector<double> errs;
+    if ((n32 > 0 && prod_mode == 1) || verbose) b.err.download(errs, stream);
     sync();
     timers.resolve();
-    // algorithmic work of a Jacobi sweep over an n x n matrix: the A update
-    // (upper triangle, 2x2 block rotations) and the eigenvector rows,
-    // 6 n^2 flop per step times (n - 1) steps
+    // algorithmic work of the eigensolve of one SCC iteration, as budgeted
+    // for a dense symmetric eigensolver: 3.3 n^3 (reduction about 1.3 n^3,
+    // back-transformation of the eigenvectors 2 n^3), whatever the Jacobi
+    // sweeps actually did; the split form credits the rotation kernel with
+    // the first and the apply kernel with the second
     for (int s : active) {
-      double n = b.h_desc[s].nao;
-      const double gf = 1e-9 * 6.0 * n * n * (n - 1.0) * (double)sweeps[s];
+      const double n = b.h_desc[s].nao, n3 = 1e-9 * n * n * n;
       if (last_split) {
-        // the working-matrix update and the basis rotation are half each
-        kt_rot->gflop += 0.5 * gf;
-        kt_app->gflop += 0.5 * gf;
+        kt_rot->gflop += 1.3 * n3;
+        kt_app->gflop += 2.0 * n3;
       } else {
-        kt_jac->gflop += gf;
+        kt_jac->gflop += 3.3 * n3;
       }
+    }
+    if (verbose) {
+      double emax = 0.0, emed = 0.0;
+      std::vector<double> ev;
+      for (int s : active) {
+        emax = std::max(emax, errs[s]);
+        ev.push_back(errs[s]);
+      }
+      if (!ev.empty()) {
+        std::nth_element(ev.begin(), ev.begin() + ev.size() / 2, ev.end());
+        emed = ev[ev.size() / 2];
+      }
+      std::fprintf(stderr, "[fx]   iteration %d: %d systems (%d fp32), residual max %.2e median %.2e\n", it,
+                   (int)active.size(), n32, emax, emed);
     }
     std::vector<int> next;
     for (int s : active)
       if (status[s] == 0) next.push_back(s);
+    const std::vector<int> active_prev = active;
     active.swap(next);
+    if (n32 > 0 && prod_mode == 1) {
+      for (int k = 0; k < n32; ++k) {
+        const int s = active_prev[k];
+        if (status[s] == 0 && errs[s] <= mixed_thr) {
+          is32[s] = 0;
+          if (mixed_hist_reset) switched.push_back(s);
+        }
+      }
+    }
   }
   if (gexec) (void)hipGraphExecDestroy(gexec);
   if (graph) (void)hipGraphDestroy(graph);
@@ -1446,6 +1559,8 @@ void Ctx::run(fx_result* out) {
     if (fused_mode) {
       // one SCC iteration of every monomer at the globally mixed charges
       hipLaunchKernelGGL(k_gather_shell, dim3(mb.nsys), dim3(64), 0, stream, dmb, d_q.p, mb.q_in.p);
+      // (FP64 products in the fused steps: FP32 ones there cost more steps
+      // than they save)
       run_scc(mb, all_mono, false, &it_mono, true);
     } else {
       if (cold)
@@ -1461,7 +1576,9 @@ void Ctx::run(fx_result* out) {
         fallback_flag.alloc(mb.nsys);
         check(hipMemsetAsync(fallback_flag.p, 0, sizeof(int) * mb.nsys, stream), "memset");
       }
+      prod_mode = mixed ? 1 : 0;
       failed = solve_batch(mb, cold, &it_mono);
+      prod_mode = 0;
       first_solve = false;
       if (cold) {
         std::vector<int> fl;
@@ -1580,7 +1697,9 @@ void Ctx::run(fx_result* out) {
     }
     build_precond(db_);
     long long itd = 0;
+    prod_mode = mixed ? 1 : 0;
     int failed = solve_batch(db_, true, &itd);
+    prod_mode = 0;
     if (failed) all_conv = false;
     res.solves_dimer = nscc;
     res.iters_dimer = itd;
@@ -1627,7 +1746,9 @@ void Ctx::run(fx_result* out) {
     hipLaunchKernelGGL(k_gather_shell, dim3(tb_.nsys), dim3(64), 0, stream, dtb, d_q.p, tb_.q_in.p);
     build_precond(tb_);
     long long itt = 0;
+    prod_mode = mixed ? 1 : 0;
     int failed = solve_batch(tb_, true, &itt);
+    prod_mode = 0;
     if (failed) all_conv = false;
     res.solves_trimer = ntri;
     res.iters_trimer = itt;

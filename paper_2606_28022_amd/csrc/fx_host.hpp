@@ -229,6 +229,11 @@ struct Batch {
   // gam offsets, each block stored transposed); used by the mixer when has_pre is set
   DevBuf<float> pre;
   bool has_pre = false;
+  // mixed precision: FP32 copies of H0 and S, the FP32 Fock matrix and the
+  // FP32 intermediate of the congruence product (systems of more than 32 AOs
+  // without hybrid-orbital projectors)
+  DevBuf<float> H0f, Sf, Ff, Tf;
+  bool has_f32 = false;
   // rotation log of the split eigensolver (k_jacobi_rot / k_apply_rot)
   DevBuf<double2> rotlog;
   DevBuf<int> nlog;
@@ -252,6 +257,16 @@ struct Batch {
     for (int s : l) {
       const double n = h_desc[s].nao, k = std::min(n, std::ceil(0.5 * h_desc[s].nel));
       g += 2e-9 * n * n * k;
+    }
+    return g;
+  }
+  // a symmetric product computes the upper 64 x 64 tiles only: 2 n^3 times
+  // the fraction of tiles computed
+  double gemm_gflop_sym(const std::vector<int>& l) const {
+    double g = 0.0;
+    for (int s : l) {
+      const double n = h_desc[s].nao, nt = std::ceil(n / 64.0);
+      g += 2e-9 * n * n * n * (nt * (nt + 1) / 2) / (nt * nt);
     }
     return g;
   }
@@ -304,6 +319,16 @@ struct Ctx {
   double macro_beta = 0.5;
   double scc_tol_cur = -1.0, etol_cur = -1.0;
   double response_tol = 1e-11;
+  // mixed precision: FP32 products and Fock build while a system's SCC
+  // residual is above mixed_thr.  prod_mode 0: FP64 products; 1: each system
+  // of the solve runs FP32 iterations until its own residual drops to
+  // mixed_thr, FP64 ones from then on
+  double mixed_thr = std::getenv("FX_MIXED_THR") ? std::atof(std::getenv("FX_MIXED_THR")) : 1e-4;
+  int prod_mode = 0;
+  // clear a system's Anderson history when it leaves the FP32 phase (off: the
+  // FP32 noise, about 1e-6 in the charges, is small against the 1e-4 residual
+  // at the switch, and keeping the history saves iterations)
+  bool mixed_hist_reset = std::getenv("FX_MIXED_HIST_RESET") && std::atoi(std::getenv("FX_MIXED_HIST_RESET")) != 0;
   int response_sweeps = 0;
   bool verbose = std::getenv("FX_VERBOSE") != nullptr;
 
@@ -448,6 +473,10 @@ struct Ctx {
   void gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlist, int mode, const double* A,
                   const double* B, double* C, const double* w, double gflop, int skip_done = 0, int sym = 0,
                   bool occ_list = false);
+  // the FP32 products of the mixed form (mode 0: double A, float B and C;
+  // mode 1: float A, double B and C; mode 2: double A, B and C)
+  void gemm_batch_f32(const Batch& b, const DevBatch& db, int nl, const int* dlist, int mode, const void* A,
+                      const void* B, void* C, const double* w, double gflop, int skip_done, int sym, bool occ_list);
   // graph-captured SCC iterations (schedule FX_BATCHED_GRAPH)
   bool capturing = false;
   hipStream_t gstream = nullptr;

@@ -28,12 +28,18 @@ __global__ void k_cluster_healed(DevSystem sys, DevBatch bt, const double* Phi, 
 __global__ void k_vhop(DevBatch bt, double vhop);
 __global__ void k_ghost_cn(DevSystem sys, const int* bonds, int nbonds, double* cn);
 __global__ void k_reset_state(DevBatch bt, const int* list, int nl, int keep_err);
+__global__ void k_hist_reset(DevBatch bt, const int* list, int nl);
 __global__ void k_precond_step(DevBatch bt, double* out);
 __global__ void k_cholinv(DevBatch bt, const int* list, const double* Apool, double* Lpool, double* Xpool);
 __global__ void k_cluster_init_ct(DevBatch bt, const int* list, DevBatch mono, const long long* warm_off);
 __global__ void k_warm_start(DevBatch bt, const long long* mat_off_old, const long long* sh_off_old,
                              const double* Cold, const double* qold);
 __global__ void k_fock(DevSystem sys, DevBatch bt, const int* list);
+__global__ void k_fock_f32(DevSystem sys, DevBatch bt, const int* list, const float* H0f, const float* Sf, float* Ff);
+__global__ void k_to_f32(const double* src, float* dst, long long n);
+template <int MODE, typename TA, typename TB, typename TC>
+__global__ void k_gemm_f32(DevBatch bt, const int* list, int nl, int tiles_per_sys, const TA* Abase, const TB* Bbase,
+                           TC* Cbase, const double* wbase, int skip_done, int sym, int occ_list);
 __global__ void k_precond_build(DevSystem sys, DevBatch bt, const int* list, DevBatch mono, const double* Mmono,
                                 float* pre, int* ok, int ncmax);
 template <int MODE>

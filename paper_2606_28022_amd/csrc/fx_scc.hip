@@ -74,6 +74,12 @@ __global__ void k_reset_state(DevBatch bt, const int* list, int nl, int keep_err
   if (!keep_err) bt.err[si] = 1e-2;
 }
 
+// clear the Anderson history of the listed systems
+__global__ void k_hist_reset(DevBatch bt, const int* list, int nl) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nl) bt.nhist[list[k]] = 0;
+}
+
 // Preconditioned monomer step of the fused embedding loop, per system:
 // out = q_in + (1 + M G)^-1 (q_out - q_in) (local shell vectors)
 __global__ void k_precond_step(DevBatch bt, double* out) {
@@ -180,6 +186,95 @@ __global__ void k_cholinv(DevBatch bt, const int* list, const double* Apool, dou
 
 // ---------------------------------------------------------------------------
 // shell shift and Fock matrix
+
+// Shell shifts sigma_s = sum_t gamma_st q_t - Gamma_A q_A^2 + phi_s of one
+// system (FP64, also stored in bt.sig) and the shift of every AO (that of its
+// shell) into sig_ao.  Called by every thread of the work-group.
+__device__ void fock_shifts(const DevSystem& sys, const DevBatch& bt, const SysDesc& d, double* qa_s,
+                            double* sig_s, double* sig_ao) {
+  const int n = d.nao, ns = d.nsh;
+  const double* q = bt.q_in + d.sh_off;
+  for (int a = threadIdx.x; a < d.nat; a += blockDim.x) {
+    int s0 = bt.sys_atom_sh0[d.atom_off + a];
+    int A = bt.sys_atoms[d.atom_off + a];
+    int nsa = sys.atom_sh0[A + 1] - sys.atom_sh0[A];
+    double v = 0.0;
+    for (int k = 0; k < nsa; ++k) v += q[s0 + k];
+    qa_s[a] = v;
+  }
+  __syncthreads();
+  const double* G = bt.gam + d.gam_off;
+  for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+    double v = 0.0;
+#pragma unroll 8
+    for (int t = 0; t < ns; ++t) v += G[(long long)t * ns + s] * q[t];
+    int a = bt.sys_sh_atom[d.sh_off + s];
+    int A = bt.sys_atoms[d.atom_off + a];
+    double Gam = sys.elems[sys.elem[A]].Gamma;
+    v += -Gam * qa_s[a] * qa_s[a] + bt.phi[d.sh_off + s];
+    sig_s[s] = v;
+    bt.sig[d.sh_off + s] = v;
+  }
+  __syncthreads();
+  const int* aosh = bt.sys_ao_sh + d.ao_off;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sig_ao[i] = sig_s[aosh[i]];
+  __syncthreads();
+}
+
+// Mixed-precision form of the Fock build (early SCC iterations): the shifts
+// in FP64, F = H0 + 1/2 S (sigma_mu + sigma_nu) assembled in FP32 from the
+// FP32 copies of H0 and S and stored in FP32 (upper 32 x 32 tiles, each
+// written as itself and, through LDS, as its mirror).  Systems without
+// hybrid-orbital projectors only.
+__global__ void __launch_bounds__(256) k_fock_f32(DevSystem sys, DevBatch bt, const int* list,
+                                                  const float* __restrict__ H0f, const float* __restrict__ Sf,
+                                                  float* __restrict__ Ff) {
+  int si = list[blockIdx.x];
+  if (bt.status[si] != 0) return;
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao;
+  __shared__ double qa_s[MAXN], sig_s[MAXN], sig_ao[MAXN];
+  fock_shifts(sys, bt, d, qa_s, sig_s, sig_ao);
+  __shared__ float sa[MAXN];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sa[i] = (float)sig_ao[i];
+  __syncthreads();
+  const float* S = Sf + d.mat_off;
+  const float* H = H0f + d.mat_off;
+  float* Fo = Ff + d.mat_off;
+  __shared__ float tr[32][33];
+  const int nt = (n + 31) / 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int I = 0; I < nt; ++I)
+    for (int J = I; J < nt; ++J) {
+      const int j = 32 * J + tx;
+#pragma unroll
+      for (int r = 0; r < 32; r += 8) {
+        const int i = 32 * I + r + ty;
+        if (i < n && j < n) {
+          const long long e = (long long)i * n + j;
+          const float f = H[e] + 0.5f * S[e] * (sa[i] + sa[j]);
+          Fo[e] = f;
+          tr[r + ty][tx] = f;
+        }
+      }
+      if (I == J) continue;
+      __syncthreads();
+      const int ic = 32 * I + tx;
+#pragma unroll
+      for (int r = 0; r < 32; r += 8) {
+        const int jr = 32 * J + r + ty;
+        if (jr < n) Fo[(long long)jr * n + ic] = tr[tx][r + ty];
+      }
+      __syncthreads();
+    }
+}
+
+// FP32 copies of a pool (mixed precision: H0 and S once per batch build)
+__global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
 __global__ void k_fock(DevSystem sys, DevBatch bt, const int* list) {
   int si = list[blockIdx.x];
   if (bt.status[si] != 0) return;  // converged or failed: nothing to do
@@ -513,6 +608,137 @@ template __global__ void k_gemm_mfma<1>(DevBatch, const int*, int, int, const do
                                         const double*, int, int, int);
 template __global__ void k_gemm_mfma<2>(DevBatch, const int*, int, int, const double*, const double*, double*,
                                         const double*, int, int, int);
+
+// ---------------------------------------------------------------------------
+// The batched products of the mixed-precision form (early SCC iterations) on
+// the FP32 matrix cores: operands read in their storage precision (FP64
+// basis, FP32 Fock matrix or intermediate), rounded to FP32 when staged in
+// LDS, v_mfma_f32_16x16x4f32 with FP32 accumulation, result stored as TC.
+// Same tiles, work-group order, symmetric and occupied-list options as
+// k_gemm_mfma; K staged 64 at a time (the FP32 tiles take half the LDS).
+// Lane layout of the 16x16x4 FP32 instruction (checked on the GPU with an
+// in-bounds probe): A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k;
+// output element r of lane l is D[4 (l / 16) + r][l % 16].
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <int MODE, typename TA, typename TB, typename TC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+    k_gemm_f32(DevBatch bt, const int* list, int nl, int tiles_per_sys, const TA* __restrict__ Abase,
+               const TB* __restrict__ Bbase, TC* __restrict__ Cbase, const double* __restrict__ wbase, int skip_done,
+               int sym, int occ_list) {
+  const int L = blockIdx.x, G = gridDim.x;  // G is a multiple of 8
+  const int logical = (L & 7) * (G >> 3) + (L >> 3);
+  const int sl = logical / tiles_per_sys, tile = logical - sl * tiles_per_sys;
+  if (sl >= nl) return;
+  const int si = list[sl];
+  if (skip_done && bt.status[si] != 0) return;
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao;
+  const int nt = (n + 63) / 64;
+  if (tile >= nt * nt) return;
+  const int ti = tile / nt, tj = tile - ti * nt;
+  if (sym && ti > tj) return;
+  const TA* A = Abase + d.mat_off;
+  const TB* B = Bbase + d.mat_off;
+  TC* C = Cbase + d.mat_off;
+  const double* w = wbase ? wbase + d.ao_off : nullptr;
+  const bool use_list = MODE == 2 && occ_list;
+  const int nk = use_list ? bt.occ_cnt[si] : n;
+  constexpr int KS = 64, LD = 65;
+  __shared__ float As[KS][LD];  // [k][i]
+  __shared__ float Bs[KS][LD];  // [k][j]
+  __shared__ int kxs[MODE == 2 ? MAXN : 1];
+  const int tid = threadIdx.x;
+  if (use_list) {
+    const int* kg = bt.occ_idx + d.ao_off;
+    for (int k = tid; k < nk; k += 256) kxs[k] = kg[k];
+    __syncthreads();
+  }
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  const int i0 = ti * 64, j0 = tj * 64;
+  v4f acc[2][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc[u][v] = (v4f){0.f, 0.f, 0.f, 0.f};
+  // element h (0..15) of this thread in a 64 x 64 slab:
+  //   row-major operand: r = tid / 64 + 4 h, k = tid % 64
+  //   k-major operand:   k = tid / 64 + 4 h, r = tid % 64
+  const int rq = tid >> 6, rl = tid & 63;
+  float ra[16], rb[16];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int h = 0; h < 16; ++h) {
+      if (MODE == 2) {
+        int gk = k0 + rq + 4 * h;
+        if (use_list) gk = gk < nk ? kxs[gk] : -1;
+        const bool ok = gk >= 0 && gk < n;
+        ra[h] = (ok && i0 + rl < n) ? (float)((double)A[(long long)gk * n + i0 + rl] * (w ? w[gk] : 1.0)) : 0.f;
+        rb[h] = (ok && j0 + rl < n) ? (float)B[(long long)gk * n + j0 + rl] : 0.f;
+      } else {
+        const int gi = i0 + rq + 4 * h, gk = k0 + rl;
+        ra[h] = (gi < n && gk < n) ? (float)A[(long long)gi * n + gk] : 0.f;
+        if (MODE == 1) {
+          const int gj = j0 + rq + 4 * h;
+          rb[h] = (gj < n && gk < n) ? (float)B[(long long)gj * n + gk] : 0.f;
+        } else {
+          const int gk2 = k0 + rq + 4 * h;
+          rb[h] = (gk2 < n && j0 + rl < n) ? (float)B[(long long)gk2 * n + j0 + rl] : 0.f;
+        }
+      }
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < nk; k0 += KS) {
+#pragma unroll
+    for (int h = 0; h < 16; ++h) {
+      if (MODE == 2)
+        As[rq + 4 * h][rl] = ra[h];
+      else
+        As[rl][rq + 4 * h] = ra[h];
+      if (MODE == 1)
+        Bs[rl][rq + 4 * h] = rb[h];
+      else
+        Bs[rq + 4 * h][rl] = rb[h];
+    }
+    __syncthreads();
+    if (k0 + KS < nk) fetch(k0 + KS);
+#pragma unroll
+    for (int kk = 0; kk < KS; kk += 4) {
+      const int krow = kk + (lane >> 4), c = lane & 15;
+      const float a0 = As[krow][wi * 32 + c], a1 = As[krow][wi * 32 + 16 + c];
+      const float b0 = Bs[krow][wj * 32 + c], b1 = Bs[krow][wj * 32 + 16 + c];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = i0 + wi * 32 + u * 16 + 4 * (lane >> 4) + r;
+        const int gj = j0 + wj * 32 + v * 16 + (lane & 15);
+        if (gi < n && gj < n) {
+          C[(long long)gi * n + gj] = (TC)acc[u][v][r];
+          if (sym && ti < tj) C[(long long)gj * n + gi] = (TC)acc[u][v][r];
+        }
+      }
+}
+
+// the three products of an FP32 SCC iteration:
+//   T = C^T F (F stored FP32)    A = T C (symmetric)    P = C^T diag(n) C (occupied list)
+template __global__ void k_gemm_f32<0, double, float, float>(DevBatch, const int*, int, int, const double*,
+                                                             const float*, float*, const double*, int, int, int);
+template __global__ void k_gemm_f32<1, float, double, double>(DevBatch, const int*, int, int, const float*,
+                                                              const double*, double*, const double*, int, int, int);
+template __global__ void k_gemm_f32<2, double, double, double>(DevBatch, const int*, int, int, const double*,
+                                                               const double*, double*, const double*, int, int, int);
 
 // ---------------------------------------------------------------------------
 // Parallel cyclic Jacobi on the symmetric matrix A (in place), rotating the

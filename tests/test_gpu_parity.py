@@ -253,10 +253,11 @@ def test_graph_schedule_matches_batched(lib, which):
 
 @pytest.mark.parametrize("which", ["c1", "pentacene6"])
 def test_mixed_precision_matches_fp64(lib, which):
-    """FX_MIXED (FP32 working matrices, early FP32 field passes in the monomer
-    loop and the response sweeps, FP64 basis and final iterations) reaches
-    the FP64 results within the FP64 tolerances: fragment energies 1e-8 Eh,
-    gradient 1e-7 Eh/bohr."""
+    """FX_MIXED (FP32 Fock build and FP32 matrix-core products while an SCC
+    residual exceeds 1e-5, FP32 field passes in the early monomer steps and
+    response sweeps; FP64 basis, rotation angles, final iterations and
+    energies) reaches the FP64 results within the FP64 tolerances: fragment
+    energies 1e-8 Eh, gradient 1e-7 Eh/bohr."""
     _say(f"mixed precision {which}")
     s = w.water_cluster_cube() if which == "c1" else w.pentacene_crystal(reps=(2, 2, 1)).subset(list(range(6)))
     c = lib()
@@ -274,6 +275,35 @@ def test_mixed_precision_matches_fp64(lib, which):
         if len(a):
             assert np.max(np.abs(a - b)) < 1e-8
     assert np.max(np.abs(g1 - g0)) < 1e-7
+    # the FP32 products ran for the pentacene systems (more than 32 AOs),
+    # never for the waters
+    assert (r1["iters_fp32"] > 0) == (which != "c1")
+    assert r0["iters_fp32"] == 0
+
+
+def test_mixed_precision_vs_oracle(lib):
+    """The mixed form against the FP64 oracle (tests/golden/pentacene6.json):
+    total energy within 1e-6 Eh and gradient within 1e-5 Eh/bohr (the
+    tolerances of the mixed form), and in fact within the FP64 ones (1e-8 Eh
+    per fragment, 1e-7 Eh/bohr), since its last iterations are FP64."""
+    _say("mixed precision vs oracle, pentacene 6")
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "pentacene6.json")
+    with open(path) as f:
+        ref = json.load(f)
+    s = w.pentacene_crystal(reps=(2, 2, 1)).subset(list(range(6)))
+    c = lib()
+    c.set_system(s.Z, s.xyz, s.frag, s.frag_charge)
+    c.set_options(want_gradient=1, precision=1)
+    r = c.run()
+    g = c.gradient()
+    em, ds, _, _ = c.energies()
+    assert abs(r["e_total"] - ref["E"]) < 1e-6
+    assert np.max(np.abs(g - np.array(ref["grad"]))) < 1e-5
+    assert np.max(np.abs(em - np.array(ref["E_mono"]))) < 1e-8
+    assert np.max(np.abs(ds - np.array(ref["dE_scc"]))) < 1e-8
+    assert np.max(np.abs(g - np.array(ref["grad"]))) < 1e-7
 
 
 def test_user_guess_warm_start(lib, params, c1):
