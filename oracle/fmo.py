@@ -311,9 +311,8 @@ def _task_cluster(frags):
     out = _solve_cluster(st["params"], st["ext"], st["sh"], st["q"], st["frag_charge"],
                          st["scc_tol"], st["scc_etol"], frags)
     if not st["keep"]:
-        sysX, rX, shl, ddq, dEV = out
-        light = SCCResultLight(rX)
-        return None, light, shl, ddq, dEV
+        sysX, rX, shl, ddq, dEV, atoms, hs = out
+        return None, SCCResultLight(rX), shl, ddq, dEV, atoms, hs
     return out
 
 
@@ -341,12 +340,13 @@ def _solve_cluster(params, ext, sh, q, frag_charge, scc_tol, scc_etol, frags):
     rX = scc(sysX, phiX, q_guess=q[shl], tol=scc_tol, etol=scc_etol)
     ddq = rX.q - q[shl]
     dEV = float(ddq @ phiX)
+    hs = np.zeros(0, dtype=np.int64)
     if len(healed):
         # ghosts of bonds healed inside the cluster: their monomer charge is
         # the charge transfer, with the opposite sign (eq. ctij_ghost)
         hs = sh.of_atoms(healed)
         dEV += float(-q[hs] @ sh.potential(hs, q_out, no_mask))
-    return sysX, rX, shl, ddq, dEV
+    return sysX, rX, shl, ddq, dEV, atoms, hs
 
 
 def _system_for(params, ext, atoms, charge, hop=None):
@@ -458,11 +458,15 @@ def _fmo(system, params, cutoff_bohr, order, lists, scc_tol, scc_etol, macro_tol
     dE_scc = np.zeros(len(scc_pairs))
     solved = runner.map(_task_cluster, [(int(I), int(J)) for I, J in scc_pairs])
     for k, (I, J) in enumerate(scc_pairs):
-        sysX, rX, shl, ddq, dEV = solved[k]
+        sysX, rX, shl, ddq, dEV, atoms, hs = solved[k]
         conv.append(bool(rX.converged))
         dE_scc[k] = rX.e_int - res[I].e_int - res[J].e_int + dEV
+        # charge transfer on the cluster's shells and, with the opposite
+        # monomer charge, on the ghosts of bonds healed inside it
         out.dimers.append(dict(I=int(I), J=int(J), sys=sysX, res=rX, shells=shl,
-                               ddq=ddq, dEV=dEV))
+                               ddq=ddq, dEV=dEV, atoms=atoms,
+                               ct_shells=np.concatenate([shl, hs]),
+                               ct_ddq=np.concatenate([ddq, -q[hs]])))
     dE_esd = np.zeros(len(esd_pairs))
     for k, (I, J) in enumerate(esd_pairs):
         dE_esd[k] = float(q[fsh[I]] @ sh.gamma_block(fsh[I], fsh[J]) @ q[fsh[J]])
@@ -480,12 +484,14 @@ def _fmo(system, params, cutoff_bohr, order, lists, scc_tol, scc_etol, macro_tol
         dE_tri = np.zeros(len(trimers))
         solved = runner.map(_task_cluster, [(int(I), int(J), int(K)) for I, J, K in trimers])
         for k, (I, J, K) in enumerate(trimers):
-            sysX, rX, shl, ddq, dEV = solved[k]
+            sysX, rX, shl, ddq, dEV, atoms, hs = solved[k]
             conv.append(bool(rX.converged))
             dEIJK = rX.e_int - res[I].e_int - res[J].e_int - res[K].e_int + dEV
             dE_tri[k] = dEIJK - pair_dE[(I, J)] - pair_dE[(I, K)] - pair_dE[(J, K)]
             out.trimers.append(dict(IJK=(int(I), int(J), int(K)), sys=sysX, res=rX, shells=shl,
-                                    ddq=ddq, dEIJK=dEIJK))
+                                    ddq=ddq, dEIJK=dEIJK, atoms=atoms,
+                                    ct_shells=np.concatenate([shl, hs]),
+                                    ct_ddq=np.concatenate([ddq, -q[hs]])))
         out.dE_tri = dE_tri
         out.E_fmo3 = neumaier_sum([out.E_fmo2] + list(dE_tri))
         out.E = out.E_fmo3
@@ -502,13 +508,16 @@ def _ds_matrix(sig_ao, P, Wt):
 
 def _inter_gamma_force(sh, pair_weights, natoms):
     """sum over listed shell pairs (s, t) of w_st d gamma_st / d R, as atom
-    forces; pair_weights: list of (si, tj, W) with W of shape (len si, len tj)."""
+    forces; pair_weights: list of (si, tj, W) with W of shape (len si, len tj).
+    A pair at zero distance (a ghost shell and its detached atom, in different
+    fragments) contributes nothing: gamma is smooth and even in R there."""
     g = np.zeros((natoms, 3))
     for si, tj, W in pair_weights:
         d = sh.xyz[si][:, None, :] - sh.xyz[tj][None, :, :]
         R = np.sqrt(np.sum(d * d, axis=2))
-        dg = gamma_deriv(sh.p, R, sh.eta[si][:, None], sh.eta[tj][None, :])
-        f = (W * dg / R)[:, :, None] * d          # d/dR_s of gamma_st (per pair)
+        Rs = np.where(R > 0.0, R, 1.0)
+        dg = gamma_deriv(sh.p, Rs, sh.eta[si][:, None], sh.eta[tj][None, :])
+        f = (np.where(R > 0.0, W * dg / Rs, 0.0))[:, :, None] * d   # d/dR_s of gamma_st
         np.add.at(g, sh.atom[si], f.sum(axis=1))
         np.add.at(g, sh.atom[tj], -f.sum(axis=0))
     return g
@@ -545,6 +554,88 @@ def _many_body_weights(F, scc_pairs, esd_pairs, trimers):
     return c, s_scc, w_esd
 
 
+def _hop_bond_of(ext, atoms, sx, entry):
+    """Cut bond (index into the system's bond list) of a boundary entry
+    (local atom, kind, b) of system sx whose atoms are `atoms` (extended
+    indices)."""
+    A, kind, b = entry
+    a = int(atoms[A])
+    if kind == "ghost":
+        return a - ext.N
+    for k, (u, v) in enumerate(ext.bonds):
+        if int(u) == a and np.allclose(ext.bond_vector(k), b, atol=0.0, rtol=0.0):
+            return k
+    raise ValueError("boundary atom without its cut bond")
+
+
+def _hop_derivative_terms(ext, sx, atoms, Dm):
+    """Explicit derivative of Tr(Dm V^HOP) at fixed Dm, V^HOP = S D S
+    (eq. vhop), for a symmetric density-like matrix Dm of system sx:
+    * overlap part (eq. hopsder): sum_mu,nu dS_mu,nu (Dm S D + D S Dm)_mu,nu,
+      returned as that matrix, to be contracted with dS like the other
+      overlap terms;
+    * hybrid-coefficient part (eq. hopcoder): D = +-V h h^T (+ const), h =
+      1/2 s + sqrt(3)/2 b.p on the boundary atom, b = (R_attached -
+      R_detached) / |...|; d Tr(S Dm S D) = +-2 V (dh)^T (S Dm S) h with
+      dh_p = sqrt(3)/2 db, db/dR_attached = (1 - b b^T) / |R|, on the
+      attached atom and the opposite on the detached one (global real atoms),
+      with + for a detached atom and - for a ghost.
+    Returns (DS_add, forces (n_real, 3))."""
+    N = ext.N
+    g = np.zeros((N, 3))
+    if not sx.hop:
+        return np.zeros_like(sx.S), g
+    D = sx.D_hop
+    DS_add = Dm @ sx.S @ D + D @ sx.S @ Dm
+    SDS = sx.S @ Dm @ sx.S
+    V = sx.p.VHOP
+    for entry in sx.hop:
+        A, kind, b = entry
+        k = _hop_bond_of(ext, atoms, sx, entry)
+        a_det, a_att = int(ext.bonds[k][0]), int(ext.bonds[k][1])
+        u = ext.xyz[a_att] - ext.xyz[a_det]
+        L = float(np.linalg.norm(u))
+        h = sx.hybrid(A, b)
+        w = SDS @ h
+        s_sh, p_sh = sx._hop_atom_layout(A)
+        p0 = sx.sh_ao0[p_sh]
+        wp = w[p0:p0 + 3]
+        sign = 1.0 if kind == "bda" else -1.0
+        bb = np.asarray(b, float)
+        f = sign * 2.0 * V * (0.5 * math.sqrt(3.0)) / L * (wp - bb * (bb @ wp))
+        g[a_att] += f
+        g[a_det] -= f
+    return DS_add, g
+
+
+def _scatter_ghosts(ext, v):
+    """Values on the extended atoms (real atoms, then one ghost per cut bond)
+    summed onto the real atoms: a ghost sits on its detached atom."""
+    out = np.array(v[:ext.N], copy=True)
+    for k in range(len(ext.bonds)):
+        out[int(ext.bonds[k][0])] += v[ext.N + k]
+    return out
+
+
+def hop_projector_energy(res):
+    """sum_X w_X Tr(P_X V^HOP_X) over the monomers (w = c_I) and SCC dimers
+    (w = 1) of an FMO2 result: the constraint term that the reported energy
+    leaves out (section "FMO-xTB HOP energy") and that the SCC of every
+    fragment makes stationary together with the energy."""
+    F = len(res.mono)
+    c, _, _ = _many_body_weights(F, res.lists[0], res.lists[1], [])
+    e = 0.0
+    for I in range(F):
+        sx, r = res.mono_sys[I], res.mono[I]
+        if sx.hop:
+            e += c[I] * float(np.sum(r.P * sx.V_hop))
+    for d in res.dimers:
+        sx, r = d["sys"], d["res"]
+        if sx.hop:
+            e += float(np.sum(r.P * sx.V_hop))
+    return e
+
+
 def fmo_gradient(system, params, res, with_response=True):
     """Analytic FMO2 or FMO3 gradient (Eh/bohr, shape (natoms, 3)) for a
     converged result `res` (lists frozen).  From the identity of
@@ -555,16 +646,26 @@ def fmo_gradient(system, params, res, with_response=True):
                  + response of the monomer charges,
     the response driven by v_K = sum over clusters X not containing K of
     w_X gamma_{K,X} ddq^X (eq. esp_lagrangian; for trimers the generalized
-    accumulated charge transfer of section "Extension to FMO3").  Systems
-    with cut covalent bonds are not covered (the HOP gradient is not part of
-    this build)."""
-    if len(getattr(system, "bonds", ())):
-        raise NotImplementedError("FMO gradient with covalent boundaries")
+    accumulated charge transfer of section "Extension to FMO3").
+
+    Cut covalent bonds (FMO2; section "FMO-xTB HOP gradient"): the systems
+    are stationary for E^emb_X + Tr(P_X V^HOP_X), so this is the gradient of
+    the reported energy plus hop_projector_energy (the two differ by terms
+    of order 1/V_HOP).  Ghost shells are part of their monomer's charges;
+    the ghost of a bond healed in a dimer carries the charge transfer
+    -dq^ghost (eq. ctij_ghost); the projector derivative (eqs. hop_grad,
+    hopsder, hopcoder) enters every system with the density and the
+    response with the Z-vector density (eq. hop_resp); every ghost force
+    acts on its detached atom."""
+    if len(getattr(system, "bonds", ())) and len(res.lists[2]):
+        raise NotImplementedError("FMO3 gradient with covalent boundaries")
     sh = res.shells
+    ext = res.ext
     F = system.n_frag
     fa, fsh = res.frag_atoms, res.frag_shells
     q = res.q
     N = system.n_atoms
+    Ne = ext.n_atoms
     scc_pairs, esd_pairs, trimers = res.lists
     tri = getattr(res, "trimers", [])
     if len(trimers) and len(tri) != len(trimers):
@@ -573,43 +674,42 @@ def fmo_gradient(system, params, res, with_response=True):
     clusters = [(d, s_scc[k]) for k, d in enumerate(res.dimers)] + [(t, 1.0) for t in tri]
 
     G = np.zeros((N, 3))
-    Fcn = np.zeros(N)
+    Fcn = np.zeros(Ne)
     parts = {}
 
     # explicit fragment terms: sum_X w_X g^emb_X (fixed CN), with sigma containing
-    # the embedding potential (eqs. xtb_grad, W_matrix, pair_delta)
-    gm = np.zeros((N, 3))
-    for I in range(F):
-        sx, r = res.mono_sys[I], res.mono[I]
+    # the embedding potential (eqs. xtb_grad, W_matrix, pair_delta), plus the
+    # projector derivative of systems with boundary atoms
+    gm = np.zeros((Ne, 3))
+    g_hop = np.zeros((N, 3))
+    systems = [(res.mono_sys[I], res.mono[I], fa[I], c[I]) for I in range(F)]
+    systems += [(d["sys"], d["res"], d["atoms"], wx) for d, wx in clusters]
+    for sx, r, atoms, wx in systems:
+        if wx == 0.0:
+            continue
         DS = _ds_matrix(r.sigma[sx.ao_sh], r.P, r.Wt)
-        g, f = system_gradient(sx, r.P, DS, r.q, r.q, True)
-        gm[fa[I]] += c[I] * g
-        Fcn[fa[I]] += c[I] * f
-    for d, wx in clusters:
-        sx, r = d["sys"], d["res"]
-        frags = d["IJK"] if "IJK" in d else (d["I"], d["J"])
-        atoms = np.concatenate([fa[I] for I in frags])
-        DS = _ds_matrix(r.sigma[sx.ao_sh], r.P, r.Wt)
-        g, f = system_gradient(sx, r.P, DS, r.q, r.q, True)
+        dsh, gh = _hop_derivative_terms(ext, sx, atoms, r.P)
+        g, f = system_gradient(sx, r.P, DS + dsh, r.q, r.q, True)
         gm[atoms] += wx * g
         Fcn[atoms] += wx * f
-    parts["fragments"] = gm
-    G += gm
+        g_hop += wx * gh
+    parts["fragments"] = _scatter_ghosts(ext, gm) + g_hop
+    G += parts["fragments"]
 
-    # ES-DIM (eq. esd_grad) and charge-transfer embedding (eqs. ctij and the
-    # FMO3 charge transfer) terms
+    # ES-DIM (eq. esd_grad) and charge-transfer embedding (eqs. ctij,
+    # ctij_ghost and the FMO3 charge transfer) terms
     wl = []
     for k, (I, J) in enumerate(esd_pairs):
         if w_esd[k] != 0.0:
             wl.append((fsh[I], fsh[J], w_esd[k] * np.outer(q[fsh[I]], q[fsh[J]])))
-    g_esd = _inter_gamma_force(sh, wl, N)
+    g_esd = _scatter_ghosts(ext, _inter_gamma_force(sh, wl, Ne))
     wl = []
     for d, wx in clusters:
         frags = d["IJK"] if "IJK" in d else (d["I"], d["J"])
         others = np.where(~np.isin(sh.frag, frags))[0]
         if wx != 0.0 and len(others):
-            wl.append((d["shells"], others, wx * np.outer(d["ddq"], q[others])))
-    g_ct = _inter_gamma_force(sh, wl, N)
+            wl.append((d["ct_shells"], others, wx * np.outer(d["ct_ddq"], q[others])))
+    g_ct = _scatter_ghosts(ext, _inter_gamma_force(sh, wl, Ne))
     parts["esd"] = g_esd
     parts["ct"] = g_ct
     G += g_esd + g_ct
@@ -621,7 +721,8 @@ def fmo_gradient(system, params, res, with_response=True):
         parts["response"] = g_resp
         parts.update(info)
 
-    g_cn = cn_gradient(params, system.Z, system.xyz, Fcn)
+    # a ghost's CN is its detached atom's
+    g_cn = cn_gradient(params, system.Z, system.xyz, _scatter_ghosts(ext, Fcn))
     parts["cn"] = g_cn
     G += g_cn
     return G, parts
@@ -643,7 +744,7 @@ def lagrangian_potential(res, clusters=None):
     for d, wx in clusters:
         frags = d["IJK"] if "IJK" in d else (d["I"], d["J"])
         tg = np.where(~np.isin(sh.frag, frags))[0]
-        v[tg] += wx * (sh.gamma_block(tg, d["shells"]) @ d["ddq"])
+        v[tg] += wx * (sh.gamma_block(tg, d["ct_shells"]) @ d["ct_ddq"])
     return v
 
 
@@ -693,8 +794,11 @@ def _response(system, params, res, clusters):
     # adjoint of the monomer self-consistency: y = v + Goff chi y
     y = np.linalg.solve(np.eye(ns) - Goff @ chi, v)
     u = chi @ y
-    g = np.zeros((N, 3))
-    Fcn = np.zeros(N)
+    ext = res.ext
+    Ne = ext.n_atoms
+    g = np.zeros((Ne, 3))
+    g_hop = np.zeros((N, 3))
+    Fcn = np.zeros(Ne)
     zinfo = []
     for I in range(F):
         sx, r, b = res.mono_sys[I], res.mono[I], blocks[I]
@@ -712,9 +816,12 @@ def _response(system, params, res, clusters):
         PSDP = P @ sx.S @ (wa[:, None] * P)
         DS = (0.5 * (sig[:, None] + sig[None, :]) * Zb - WZs
               + 0.5 * (wa[:, None] + wa[None, :]) * P - 0.25 * (PSDP + PSDP.T))
-        gI, fI = system_gradient(sx, Zb, DS, 2.0 * QZ, r.q, with_rep=False)
+        # the projector derivative with the Z-vector density (eq. hop_resp)
+        dsh, gh = _hop_derivative_terms(ext, sx, fa[I], Zb)
+        gI, fI = system_gradient(sx, Zb, DS + dsh, 2.0 * QZ, r.q, with_rep=False)
         g[fa[I]] += gI
         Fcn[fa[I]] += fI
+        g_hop += gh
         zinfo.append(dict(Z=Z, w=w))
     # inter-fragment kernel derivative with the response charges u
     wl = []
@@ -722,8 +829,8 @@ def _response(system, params, res, clusters):
         for K in range(I + 1, F):
             W = np.outer(u[fsh[I]], q[fsh[K]]) + np.outer(q[fsh[I]], u[fsh[K]])
             wl.append((fsh[I], fsh[K], W))
-    g += _inter_gamma_force(sh, wl, N)
-    return g, Fcn, dict(v=v, y=y, u=u, zinfo=zinfo)
+    g += _inter_gamma_force(sh, wl, Ne)
+    return _scatter_ghosts(ext, g) + g_hop, Fcn, dict(v=v, y=y, u=u, zinfo=zinfo)
 
 
 # --------------------------------------------------------------------------

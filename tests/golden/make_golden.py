@@ -49,6 +49,8 @@ def case_system(name):
         return w.alanine_helix(4), 4 * A2B, 3
     if name == "ala10":
         return w.alanine_helix(10), 4 * A2B, 2
+    if name in ("ala20", "ala40", "ala60", "ala100"):
+        return w.alanine_helix(int(name[3:])), 4 * A2B, 2
     if name == "pentacene_3x2x2":
         return w.pentacene_crystal(reps=(3, 2, 2)), 4 * A2B, 2
     if name == "pentacene_c4":
@@ -58,6 +60,8 @@ def case_system(name):
 
 # cases too large for a stored gradient and for full per-pair output
 LARGE = {"pentacene_c4"}
+# helices of the streaming workload: energies and charges, no gradient
+HELICES = {"ala20", "ala40", "ala60", "ala100"}
 
 
 def cpu_model():
@@ -114,9 +118,12 @@ def make(name, workers=1):
         out["E_fmo2"] = r.E_fmo2
     if len(s.bonds):
         out["bonds"] = s.bonds.tolist()
-    if not len(s.bonds) and not large:
+    if not large and name not in HELICES and (order == 2 or not len(s.bonds)):
         g, _ = F.fmo_gradient(s, p, r)
         out["grad"] = g.tolist()
+        if len(s.bonds):
+            # the gradient is that of the energy plus the projector term
+            out["E_hop_projector"] = F.hop_projector_energy(r)
     out["oracle_seconds"] = time.time() - t
     out["oracle_seconds_energy"] = t_energy
     out["oracle_workers"] = workers

@@ -108,3 +108,43 @@ def test_vhop_limit(params):
     d2 = E[1] - E[2]
     assert np.all(np.abs(d1) < 1e-6)
     assert np.allclose(d1 / d2, 10.0, rtol=1e-2)
+
+
+def _augmented_energy(s, p, cut, lists, **kw):
+    r = F.fmo(s, p, cut, lists=lists, **kw)
+    return r.E + F.hop_projector_energy(r)
+
+
+@pytest.mark.parametrize("n_res", [2, 4])
+def test_hop_gradient_finite_differences(params, n_res):
+    """The FMO2 gradient with cut bonds (section "FMO-xTB HOP gradient") is
+    the derivative of the energy plus the projector term sum_X w_X
+    Tr(P_X V^HOP_X), the functional every fragment SCC makes stationary.
+    Central differences (h = 2e-4 bohr, lists frozen) of that functional at
+    V_HOP = 1e4 Eh, where the SCC converges to 1e-11 in the charges: the two
+    ends of a cut bond and two other atoms, within 1e-7 Eh/bohr.  Ala2 heals
+    its bond in the dimer; Ala4 also has dimers with a detached atom and a
+    ghost (partial bonds).  Net force and torque vanish."""
+    from threadpoolctl import threadpool_limits
+    p = copy.copy(params)
+    p.VHOP = 1e4
+    s = w.alanine_helix(n_res)
+    cut = 4 * A2B
+    kw = dict(scc_tol=1e-11, macro_tol=1e-11, scc_etol=1e-12)
+    with threadpool_limits(1):
+        r = F.fmo(s, p, cut, **kw)
+        assert r.macro_converged and r.all_scc_converged
+        G, _ = F.fmo_gradient(s, p, r)
+        assert np.max(np.abs(G.sum(0))) < 1e-9
+        assert np.max(np.abs(np.cross(s.xyz, G).sum(0))) < 1e-8
+        a0, a1 = (int(x) for x in s.bonds[0])
+        coords = [(a0, 0), (a1, 1), (n_res * 5, 2), (s.n_atoms - 1, 1)]
+        h = 2e-4
+        for a, k in coords:
+            e = []
+            for sg in (1.0, -1.0):
+                s2 = copy.deepcopy(s)
+                s2.xyz[a, k] += sg * h
+                e.append(_augmented_energy(s2, p, cut, r.lists, **kw))
+            fd = (e[0] - e[1]) / (2 * h)
+            assert abs(fd - G[a, k]) < 1e-7, (a, k, fd, G[a, k])
