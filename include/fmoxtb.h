@@ -106,7 +106,10 @@ typedef struct fx_options {
   int32_t max_iter;       /* SCC iterations per fragment solve */
   int32_t max_macro;      /* monomer self-consistency sweeps */
   int32_t want_gradient;  /* compute the FMO2 or FMO3 analytic gradient
-                             (molecular fragments; not with cut bonds) */
+                             (FMO2 also with cut bonds: the derivative of
+                             the energy plus the projector term sum_X w_X
+                             Tr(P_X V^HOP_X), section "FMO-xTB HOP gradient";
+                             FMO3 with cut bonds: FX_E_UNSUPPORTED) */
   int32_t want_response;  /* include the embedding response term */
   int32_t selection;      /* FX_SELECT_CUTOFF (default) or FX_SELECT_VDW */
   double vdw_dimer;       /* FX_SELECT_VDW: a pair is an SCC dimer when some
@@ -234,8 +237,9 @@ int fx_set_options(fx_ctx* ctx, const fx_options* o);
  * must have one s and one p shell.  Inputs are copied.
  * With cut bonds the shell vectors of fx_get_charges / fx_set_guess hold the
  * ghost shells after those of the real atoms (one ghost per bond, in bond
- * order); the gradient is not available (FX_E_UNSUPPORTED from fx_run when
- * want_gradient is set).
+ * order); the FMO2 gradient acts on real atoms only (a ghost's forces go to
+ * its detached atom); the FMO3 gradient and molecular dynamics with cut bonds
+ * return FX_E_UNSUPPORTED.
  * Errors: FX_E_INVALID (bad sizes, NaN, atoms closer than 0.3 bohr, empty
  * fragment, bond index out of range or inside one fragment),
  * FX_E_UNSUPPORTED (element without parameters, detached atom without s and

@@ -191,7 +191,7 @@ void Ctx::build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters,
   std::vector<int> atoms, atom_ao0, atom_sh0, sh_global, sh_atom, ao_sh;
   // covalent-boundary tables (section "Covalent bond fragmentation")
   std::vector<double> sh_q0, atom_zs, hop_b;
-  std::vector<int> hop_off(1, 0), hop_atom, hop_kind, healed_off(1, 0), healed_sh;
+  std::vector<int> hop_off(1, 0), hop_atom, hop_kind, hop_bond, healed_off(1, 0), healed_sh;
   std::vector<int> loc(Ne, -1);  // local index of an extended atom in the current system
   std::vector<int> sh_mono;      // index of each local shell within its fragment's monomer
   long long mat = 0, gam = 0;
@@ -259,6 +259,7 @@ void Ctx::build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters,
         if (inside(frag[bb])) continue;
         hop_atom.push_back(loc[a]);
         hop_kind.push_back(1);
+        hop_bond.push_back(kb);
         for (int c = 0; c < 3; ++c) hop_b.push_back(xyz_h[3 * bb + c] - xyz_h[3 * a + c]);
       }
       for (int kb : ghost_bonds[I]) {
@@ -271,6 +272,7 @@ void Ctx::build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters,
         const int bb = bonds[2 * kb + 1];
         hop_atom.push_back(loc[N + kb]);
         hop_kind.push_back(2);
+        hop_bond.push_back(kb);
         for (int c = 0; c < 3; ++c) hop_b.push_back(xyz_h[3 * bb + c] - xyz_h[3 * a + c]);
       }
     }
@@ -309,7 +311,12 @@ void Ctx::build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters,
     b.max_nao = std::max(b.max_nao, nao);
   }
   b.sh_mono.upload(sh_mono);
+  b.h_hop_off = hop_off;
+  b.h_hop_bond = hop_bond;
+  b.h_healed_off = healed_off;
+  b.h_healed_sh = healed_sh;
   b.has_hop = !hop_atom.empty();
+  b.n_hop = (int)hop_atom.size();
   b.has_healed = !healed_sh.empty();
   if (b.has_hop || b.has_healed) {
     b.sh_q0.upload(sh_q0);
@@ -317,6 +324,7 @@ void Ctx::build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters,
     b.hop_off.upload(hop_off);
     b.hop_atom.upload(hop_atom.empty() ? std::vector<int>{0} : hop_atom);
     b.hop_kind.upload(hop_kind.empty() ? std::vector<int>{0} : hop_kind);
+    b.hop_bond.upload(hop_bond.empty() ? std::vector<int>{0} : hop_bond);
     b.hop_b.upload(hop_b.empty() ? std::vector<double>{0.0} : hop_b);
     b.healed_off.upload(healed_off);
     b.healed_sh.upload(healed_sh.empty() ? std::vector<int>{0} : healed_sh);
@@ -396,6 +404,7 @@ DevBatch Batch::dev() {
   d.hop_atom = hb ? hop_atom.p : nullptr;
   d.hop_kind = hb ? hop_kind.p : nullptr;
   d.hop_b = hb ? hop_b.p : nullptr;
+  d.hop_bond = hb ? hop_bond.p : nullptr;
   d.healed_off = has_healed ? healed_off.p : nullptr;
   d.healed_sh = has_healed ? healed_sh.p : nullptr;
   d.sh_mono = sh_mono.p;
@@ -1503,8 +1512,8 @@ void Ctx::md_verlet(int n_steps, double dt, const double* mass, double* xyz, dou
 void Ctx::run(fx_result* out) {
   if (!has_system) throw FxError(FX_E_STATE, "no system set");
   const bool mixed = opt.precision == FX_MIXED;
-  if (NB > 0 && opt.want_gradient)
-    throw FxError(FX_E_UNSUPPORTED, "the gradient with cut covalent bonds is not available");
+  if (NB > 0 && opt.want_gradient && opt.order >= 3)
+    throw FxError(FX_E_UNSUPPORTED, "the FMO3 gradient with cut covalent bonds is not available");
   std::memset(&res, 0, sizeof(res));
   ktimers.clear();
   resp_ok = false;

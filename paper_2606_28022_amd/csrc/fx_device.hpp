@@ -92,6 +92,7 @@ struct DevBatch {
   const double* sh_q0;     // per local shell reference population (null: element values)
   const double* atom_zs;   // per local atom repulsion-charge scale (null: 1)
   double* Vh;              // HOP projector S D S per system (mat layout) or null
+  const int* hop_bond;     // cut bond (index into the system's bond list) of each boundary entry
   const int* hop_off;      // [nsys+1] boundary atoms of each system
   const int* hop_atom;
   const int* hop_kind;     // 1 detached atom, 2 ghost
@@ -124,6 +125,13 @@ constexpr double OCC_MIN = 1e-30;
 // the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ..., e = 1 - x y^2, which
 // triples the number of correct bits; no handling of zero, infinite or NaN
 // arguments, which these callers never pass.
+// gamma_st at distance R (Klopman-Ohno form, eta_st the harmonic mean)
+__device__ inline double gamma_pair(const DevGlobals& g, double R, double eta_s, double eta_t) {
+  const double ie = 0.5 * (1.0 / eta_s + 1.0 / eta_t);
+  if (g.kg == 2.0) return 1.0 / sqrt(R * R + ie * ie);
+  return pow(pow(R, g.kg) + pow(ie, g.kg), -1.0 / g.kg);
+}
+
 __device__ inline double rsqrt_pos(double x) {
   const double y = __builtin_amdgcn_rsq(x);
   const double e = fma(-x * y, y, 1.0);

@@ -18,8 +18,11 @@ namespace fx {
 
 namespace {
 
-// explicit per-system terms of one batch into (g_sys, F_sys)
-void explicit_terms(Ctx& c, Batch& b, const double* wsys, DevBuf<double>& g_sys, DevBuf<double>& F_sys) {
+// explicit per-system terms of one batch into (g_sys, F_sys); with boundary
+// atoms also the projector derivative (its hybrid-coefficient forces into
+// hop_f from slot slot_base on)
+void explicit_terms(Ctx& c, Batch& b, const double* wsys, DevBuf<double>& g_sys, DevBuf<double>& F_sys,
+                    double* hop_f, long long slot_base) {
   DevBatch db = b.dev();
   DevSystem ds = c.dev_system();
   DevBuf<double> wvec;
@@ -36,6 +39,9 @@ void explicit_terms(Ctx& c, Batch& b, const double* wsys, DevBuf<double>& g_sys,
   c.gemm_batch(b, db, (int)b.nsys, b.d_list.p, 2, b.Ct.p, b.Ct.p, b.Tm.p, (const double*)wvec.p,
                b.gemm_gflop_occ(all_sys), 0, 1, true);
   hipLaunchKernelGGL(k_make_DS, dim3(b.nsys), dim3(256), 0, c.stream, db, b.Pm.p, b.Tm.p, b.Fm.p);
+  if (b.has_hop)
+    hipLaunchKernelGGL(k_hop_grad, dim3(b.nsys), dim3(256), 0, c.stream, ds, db, (const double*)b.Pm.p, b.Fm.p, wsys,
+                       (const int*)c.d_bonds.p, c.P.g.VHOP, slot_base, hop_f);
   int natot = 0;
   for (auto& d : b.h_desc) natot += d.nat;
   g_sys.alloc(3LL * natot);
@@ -106,21 +112,29 @@ void Ctx::gradient() {
   d_tmask.upload(tmask);
 
   // ---- explicit fragment terms and the per-cluster corrections of the
-  //      all-pairs force pass
+  //      all-pairs force pass; projector forces of boundary entries in
+  //      slots: monomers, SCC dimers, then the monomers' response terms
+  const long long n_hop_m = mb.n_hop, n_hop_d = nscc > 0 ? db_.n_hop : 0;
+  const long long n_slots = 2 * n_hop_m + n_hop_d;
+  DevBuf<double> hop_f, ghost_f, zero_f;
+  hop_f.alloc(std::max(1LL, 6 * n_slots));
+  check(hipMemsetAsync(hop_f.p, 0, sizeof(double) * std::max(1LL, 6 * n_slots), stream), "memset");
+  const long long n_healed = nscc > 0 && !db_.h_healed_sh.empty() ? (long long)db_.h_healed_sh.size() : 0;
+  ghost_f.alloc(std::max(1LL, 3 * n_healed));
   DevBuf<double> gm, Fm_, gd, Fd, gt, Ft;
-  explicit_terms(*this, mb, d_cw.p, gm, Fm_);
+  explicit_terms(*this, mb, d_cw.p, gm, Fm_, hop_f.p, 0);
   if (nscc > 0) {
-    explicit_terms(*this, db_, d_sw.p, gd, Fd);
+    explicit_terms(*this, db_, d_sw.p, gd, Fd, hop_f.p, n_hop_m);
     DevBatch ddb = db_.dev();
     hipLaunchKernelGGL(k_grad_pair_corr, dim3(db_.nsys), dim3(128), 0, stream, ds, ddb, d_q.p, ddq_scc.p, d_sw.p,
-                       (const int*)nullptr, gd.p);
+                       (const int*)nullptr, gd.p, ghost_f.p);
     check(hipGetLastError(), "k_grad_pair_corr");
   }
   if (ntri > 0) {
-    explicit_terms(*this, tb_, nullptr, gt, Ft);
+    explicit_terms(*this, tb_, nullptr, gt, Ft, nullptr, 0);
     DevBatch dtb = tb_.dev();
     hipLaunchKernelGGL(k_grad_pair_corr, dim3(tb_.nsys), dim3(128), 0, stream, ds, dtb, d_q.p, ddq_tri.p,
-                       (const double*)nullptr, d_tmask.p, gt.p);
+                       (const double*)nullptr, d_tmask.p, gt.p, ghost_f.p);
     check(hipGetLastError(), "k_grad_pair_corr (trimers)");
   }
 
@@ -137,7 +151,7 @@ void Ctx::gradient() {
   check(hipMemsetAsync(v.p, 0, sizeof(double) * Nsh, stream), "memset");
   const unsigned gS = (unsigned)((Nsh + 255) / 256);
   DevBuf<int> dptr, dent, tptr, tent;
-  DevBuf<double> ddq_w, vc_d, vc_t, fq;
+  DevBuf<double> ddq_w, vc_d, vc_t, fq, vc_gh;
   if (nscc > 0) {
     cluster_csr(*this, db_, dptr, dent);
     DevBatch ddb = db_.dev();
@@ -146,7 +160,13 @@ void Ctx::gradient() {
     hipLaunchKernelGGL(k_scale_cluster, dim3(db_.nsys), dim3(64), 0, stream, ddb, d_sw.p, ddq_scc.p, ddq_w.p);
     hipLaunchKernelGGL(k_gather_csr, dim3(gS), dim3(256), 0, stream, Nsh, dptr.p, dent.p, ddq_w.p,
                        (const double*)nullptr, 1.0, qbar.p);
-    hipLaunchKernelGGL(k_cluster_cross, dim3(db_.nsys), dim3(128), 0, stream, ds, ddb, ddq_w.p, vc_d.p);
+    // the ghosts of bonds healed in a dimer carry -q (eq. ctij_ghost)
+    if (db_.has_healed)
+      hipLaunchKernelGGL(k_healed_ct, dim3(db_.nsys), dim3(64), 0, stream, ddb, (const double*)d_sw.p,
+                         (const double*)d_q.p, qbar.p);
+    vc_gh.alloc(std::max(1LL, n_healed));
+    hipLaunchKernelGGL(k_cluster_cross, dim3(db_.nsys), dim3(128), 0, stream, ds, ddb, ddq_w.p, (const double*)d_q.p,
+                       (const double*)d_sw.p, vc_d.p, db_.has_healed ? vc_gh.p : (double*)nullptr);
   }
   if (ntri > 0) {
     cluster_csr(*this, tb_, tptr, tent);
@@ -154,15 +174,19 @@ void Ctx::gradient() {
     vc_t.alloc(tb_.tot_sh);
     hipLaunchKernelGGL(k_gather_csr, dim3(gS), dim3(256), 0, stream, Nsh, tptr.p, tent.p, ddq_tri.p,
                        (const double*)qbar.p, 1.0, qbar.p);
-    hipLaunchKernelGGL(k_cluster_cross, dim3(tb_.nsys), dim3(128), 0, stream, ds, dtb, ddq_tri.p, vc_t.p);
+    hipLaunchKernelGGL(k_cluster_cross, dim3(tb_.nsys), dim3(128), 0, stream, ds, dtb, ddq_tri.p, (const double*)d_q.p,
+                       (const double*)nullptr, vc_t.p, (double*)nullptr);
   }
   if (nscc > 0 || ntri > 0) {
     fq.alloc(Nsh);
     field(qbar.p, fq.p);
     check(hipMemcpyAsync(v.p, fq.p, sizeof(double) * Nsh, hipMemcpyDeviceToDevice, stream), "copy");
-    if (nscc > 0)
+    if (nscc > 0) {
       hipLaunchKernelGGL(k_gather_csr, dim3(gS), dim3(256), 0, stream, Nsh, dptr.p, dent.p, vc_d.p,
                          (const double*)v.p, -1.0, v.p);
+      if (db_.has_healed)
+        hipLaunchKernelGGL(k_sub_healed, dim3(db_.nsys), dim3(64), 0, stream, db_.dev(), (const double*)vc_gh.p, v.p);
+    }
     if (ntri > 0)
       hipLaunchKernelGGL(k_gather_csr, dim3(gS), dim3(256), 0, stream, Nsh, tptr.p, tent.p, vc_t.p,
                          (const double*)v.p, -1.0, v.p);
@@ -312,6 +336,10 @@ void Ctx::gradient() {
     gemm_batch(b, dmb, (int)b.nsys, b.d_list.p, 0, b.Pm.p, b.Tm.p, G3.p, (const double*)nullptr, b.gemm_gflop_all());
     hipLaunchKernelGGL(k_sym_inplace, dim3(b.nsys), dim3(256), 0, stream, dmb, G1.p);
     hipLaunchKernelGGL(k_resp_DS, dim3(b.nsys), dim3(256), 0, stream, dmb, G1.p, G2.p, G3.p, w.p, b.Fm.p, gx.p);
+    // the projector derivative with the Z-vector density (eq. hop_resp)
+    if (b.has_hop)
+      hipLaunchKernelGGL(k_hop_grad, dim3(b.nsys), dim3(256), 0, stream, ds, dmb, (const double*)G1.p, b.Fm.p,
+                         (const double*)nullptr, (const int*)d_bonds.p, P.g.VHOP, n_hop_m + n_hop_d, hop_f.p);
     hipLaunchKernelGGL(k_grad_contract, dim3(b.nsys), dim3(256), 0, stream, ds, dmb, b.d_list.p, G1.p, b.Fm.p, gx.p,
                        b.q_out.p, (const double*)nullptr, 0, 1, gm.p, Fm_.p, b.Tm.p);
     check(hipGetLastError(), "response gradient terms");
@@ -323,22 +351,39 @@ void Ctx::gradient() {
   std::vector<int> rowptr(N + 1, 0), ent_b;
   std::vector<long long> ent_o;
   {
+    // a ghost (extended atom N + k) sits on the detached atom of bond k: its
+    // forces and CN sensitivity go to that atom's row
+    auto row_of = [&](int A) { return A < N ? A : bonds[2 * (A - N)]; };
     std::vector<std::vector<std::pair<int, long long>>> rows(N);
-    for (int k = 0; k < mb.nsys; ++k) {
-      const SysDesc& d = mb.h_desc[k];
-      for (int a = 0; a < d.nat; ++a) rows[frag_atoms[frag_off[d.frag[0]] + a]].push_back({0, d.atom_off + a});
-    }
     auto add_batch = [&](Batch& b, int id) {
       std::vector<int> at;
       b.d_atoms.download(at, stream);
       sync();
       for (int k = 0; k < b.nsys; ++k) {
         const SysDesc& d = b.h_desc[k];
-        for (int a = 0; a < d.nat; ++a) rows[at[d.atom_off + a]].push_back({id, d.atom_off + a});
+        for (int a = 0; a < d.nat; ++a) rows[row_of(at[d.atom_off + a])].push_back({id, d.atom_off + a});
       }
     };
+    add_batch(mb, 0);
     if (nscc > 0) add_batch(db_, 1);
     if (ntri > 0) add_batch(tb_, 2);
+    // opposite forces on the ghosts healed in the SCC dimers (batch 3)
+    for (long long e = 0; e < n_healed; ++e) {
+      const int t = db_.h_healed_sh[e];
+      const int G = (int)(std::upper_bound(atom_sh0_g.begin(), atom_sh0_g.end(), t) - atom_sh0_g.begin()) - 1;
+      rows[row_of(G)].push_back({3, e});
+    }
+    // projector hybrid-coefficient forces (batch 4): attached atom, detached atom
+    auto add_hop = [&](const Batch& b, long long base) {
+      for (int e = 0; e < b.n_hop; ++e) {
+        const int kb = b.h_hop_bond[e];
+        rows[bonds[2 * kb + 1]].push_back({4, 2 * (base + e)});
+        rows[bonds[2 * kb]].push_back({4, 2 * (base + e) + 1});
+      }
+    };
+    add_hop(mb, 0);
+    if (nscc > 0) add_hop(db_, n_hop_m);
+    if (opt.want_response && (nscc > 0 || ntri > 0)) add_hop(mb, n_hop_m + n_hop_d);
     for (int A = 0; A < N; ++A) {
       rowptr[A + 1] = rowptr[A] + (int)rows[A].size();
       for (auto& e : rows[A]) {
@@ -352,8 +397,12 @@ void Ctx::gradient() {
   d_rp.upload(rowptr);
   d_eb.upload(ent_b);
   d_eo.upload(ent_o);
-  std::vector<const double*> gb = {gm.p, nscc > 0 ? gd.p : gm.p, ntri > 0 ? gt.p : gm.p};
-  std::vector<const double*> fb = {Fm_.p, nscc > 0 ? Fd.p : Fm_.p, ntri > 0 ? Ft.p : Fm_.p};
+  // batches 3 and 4 carry forces only: their CN sensitivities read zeros
+  zero_f.alloc(std::max(1LL, std::max(n_healed, 2 * n_slots)));
+  check(hipMemsetAsync(zero_f.p, 0, sizeof(double) * std::max(1LL, std::max(n_healed, 2 * n_slots)), stream),
+        "memset");
+  std::vector<const double*> gb = {gm.p, nscc > 0 ? gd.p : gm.p, ntri > 0 ? gt.p : gm.p, ghost_f.p, hop_f.p};
+  std::vector<const double*> fb = {Fm_.p, nscc > 0 ? Fd.p : Fm_.p, ntri > 0 ? Ft.p : Fm_.p, zero_f.p, zero_f.p};
   DevBuf<const double*> d_gb, d_fb;
   d_gb.upload(gb);
   d_fb.upload(fb);
@@ -375,15 +424,18 @@ void Ctx::gradient() {
   hipLaunchKernelGGL(k_axpy, dim3((unsigned)((Nsh + 255) / 256)), dim3(256), 0, stream, (long long)Nsh, qbar.p, 1.0,
                      u.p, a.p);
   {
-    const int nchunk = std::max(1, std::min(64, 2048 / (int)gA));
+    // over the extended atoms (ghosts included), then every ghost's force
+    // onto its detached atom
+    const unsigned gE = (unsigned)((Ne + 255) / 256);
+    const int nchunk = std::max(1, std::min(64, 2048 / (int)gE));
     DevBuf<double> part, fi;
-    part.alloc((long long)nchunk * 3 * N);
-    fi.alloc(3LL * N);
-    hipLaunchKernelGGL(k_force_inter, dim3(gA, nchunk), dim3(256), 0, stream, ds, d_q.p, a.p, nchunk, part.p);
-    hipLaunchKernelGGL(k_force_reduce, dim3((unsigned)((3 * N + 255) / 256)), dim3(256), 0, stream, N, nchunk, part.p,
-                       fi.p);
-    hipLaunchKernelGGL(k_axpy, dim3((unsigned)((3 * N + 255) / 256)), dim3(256), 0, stream, 3LL * N, d_grad.p, 1.0,
-                       fi.p, d_grad.p);
+    part.alloc((long long)nchunk * 3 * Ne);
+    fi.alloc(3LL * Ne);
+    hipLaunchKernelGGL(k_force_inter, dim3(gE, nchunk), dim3(256), 0, stream, ds, d_q.p, a.p, nchunk, part.p);
+    hipLaunchKernelGGL(k_force_reduce, dim3((unsigned)((3 * Ne + 255) / 256)), dim3(256), 0, stream, Ne, nchunk,
+                       part.p, fi.p);
+    hipLaunchKernelGGL(k_add_ext_forces, dim3(gA), dim3(256), 0, stream, N, NB, (const int*)d_bonds.p,
+                       (const double*)fi.p, d_grad.p);
   }
   hipLaunchKernelGGL(k_gather_atoms, dim3(gA), dim3(256), 0, stream, N, d_rp.p, d_eb.p, d_eo.p, d_gb.p, d_fb.p,
                      d_grad.p, Ftot.p, 1);

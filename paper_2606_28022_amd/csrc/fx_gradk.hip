@@ -230,7 +230,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
     }
     if (with_rep) {
       double al = sqrt(ea.arep * eb.arep);
-      double e = ea.zeff * eb.zeff / R * exp(-al * pow(R, sys.g.kf));
+      // repulsion charges of boundary atoms are scaled (detached atom, ghost)
+      const double zs = bt.atom_zs ? bt.atom_zs[d.atom_off + a] * bt.atom_zs[d.atom_off + b] : 1.0;
+      double e = zs * ea.zeff * eb.zeff / R * exp(-al * pow(R, sys.g.kf));
       double de = e * (-1.0 / R - al * sys.g.kf * pow(R, sys.g.kf - 1.0));
       for (int k = 0; k < 3; ++k) g[k] += de * uR[k];
     }
@@ -289,7 +291,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
 // ES-DIM term; an ES-DIM sub-pair inside a trimer carries 1 - n_T of it).
 // w null: w_X = 1.
 __global__ void k_grad_pair_corr(DevSystem sys, DevBatch bt, const double* qmono, const double* ddq,
-                                 const double* wct, const int* qqmask, double* g_out) {
+                                 const double* wct, const int* qqmask, double* g_out, double* ghost_out) {
   const int si = blockIdx.x;
   const SysDesc d = bt.desc[si];
   const int nat = d.nat;
@@ -297,6 +299,10 @@ __global__ void k_grad_pair_corr(DevSystem sys, DevBatch bt, const double* qmono
   const int* ash = bt.sys_atom_sh0 + d.atom_off;
   const double wx = wct ? wct[si] : 1.0;
   const int mask = qqmask ? qqmask[si] : 7;
+  // ghosts of bonds healed inside the cluster: not atoms of the cluster, but
+  // their monomer charges are cross-fragment charges of the all-pairs pass
+  // and their charge transfer is -q (eq. ctij_ghost)
+  const int h0 = bt.healed_off ? bt.healed_off[si] : 0, h1 = bt.healed_off ? bt.healed_off[si + 1] : 0;
   for (int a = threadIdx.x; a < nat; a += blockDim.x) {
     const int A = atoms[a];
     const DevElem& ea = sys.elems[sys.elem[A]];
@@ -324,9 +330,161 @@ __global__ void k_grad_pair_corr(DevSystem sys, DevBatch bt, const double* qmono
           for (int k = 0; k < 3; ++k) g[k] -= c * dg * Rv[k] / R;
         }
     }
+    for (int e = h0; e < h1; ++e) {
+      const int t = bt.healed_sh[e], G = sys.sh_atom[t];
+      if (sys.frag[G] == fa) continue;
+      double Rv[3] = {sys.xyz[3 * A] - sys.xyz[3 * G], sys.xyz[3 * A + 1] - sys.xyz[3 * G + 1],
+                      sys.xyz[3 * A + 2] - sys.xyz[3 * G + 2]};
+      double R = sqrt(Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2]);
+      if (R == 0.0) continue;  // a ghost on its own detached atom: gamma is flat there
+      const double qt = qmono[t];
+      for (int sa = 0; sa < ea.nsh; ++sa) {
+        const double qs = qmono[sys.atom_sh0[A] + sa];
+        const double c = qs * qt + wx * (ddq[d.sh_off + ash[a] + sa] * qt - qs * qt);
+        double dg;
+        gamma_and_deriv(sys.g, R, ea.eta[sa], sys.sh_eta[t], &dg);
+        for (int k = 0; k < 3; ++k) g[k] -= c * dg * Rv[k] / R;
+      }
+    }
     long long o = (long long)d.atom_off + a;
     for (int k = 0; k < 3; ++k) g_out[3 * o + k] += g[k];
   }
+  // the opposite forces on the healed ghosts (one entry per healed shell)
+  for (int e = h0 + threadIdx.x; e < h1; e += blockDim.x) {
+    const int t = bt.healed_sh[e], G = sys.sh_atom[t];
+    const double qt = qmono[t];
+    double g[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < nat; ++a) {
+      const int A = atoms[a];
+      if (sys.frag[A] == sys.frag[G]) continue;
+      const DevElem& ea = sys.elems[sys.elem[A]];
+      double Rv[3] = {sys.xyz[3 * A] - sys.xyz[3 * G], sys.xyz[3 * A + 1] - sys.xyz[3 * G + 1],
+                      sys.xyz[3 * A + 2] - sys.xyz[3 * G + 2]};
+      double R = sqrt(Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2]);
+      if (R == 0.0) continue;
+      for (int sa = 0; sa < ea.nsh; ++sa) {
+        const double qs = qmono[sys.atom_sh0[A] + sa];
+        const double c = qs * qt + wx * (ddq[d.sh_off + ash[a] + sa] * qt - qs * qt);
+        double dg;
+        gamma_and_deriv(sys.g, R, ea.eta[sa], sys.sh_eta[t], &dg);
+        for (int k = 0; k < 3; ++k) g[k] += c * dg * Rv[k] / R;
+      }
+    }
+    for (int k = 0; k < 3; ++k) ghost_out[3LL * e + k] = g[k];
+  }
+}
+
+// Explicit derivative of Tr(Dm V^HOP) at fixed Dm for the boundary entries of
+// every system of a batch, V^HOP = S D S (eq. vhop), D = V h h^T on a
+// detached atom and V (1_sp - h h^T) on a ghost, h = 1/2 s + sqrt(3)/2 b.p:
+//  * overlap part (eq. hopsder): Dm S D + D S Dm is added to the system's
+//    D_S matrix, which k_grad_contract contracts with the overlap derivative;
+//  * hybrid-coefficient part (eq. hopcoder): with db/dR_attached =
+//    (1 - b b^T) / |R_attached - R_detached|, the force on the attached atom
+//    is +-2 V sqrt(3)/2 (1 - b b^T) w_p / |R| with w = (S Dm S) h on the
+//    boundary atom (+ detached atom, - ghost) and the detached atom takes
+//    the opposite; both, times the system weight, go to hop_f at slot
+//    2 (slot_base + entry) (attached) and the next (detached).
+// Dm: the density (explicit terms) or the symmetric Z-vector density (the
+// response, eq. hop_resp).  One work-group per system, entries in order.
+__global__ void __launch_bounds__(256) k_hop_grad(DevSystem sys, DevBatch bt, const double* Dmp, double* DSp,
+                                                  const double* wsys, const int* bonds, double V, long long slot_base,
+                                                  double* hop_f) {
+  const int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao;
+  const double* Dm = Dmp + d.mat_off;
+  const double* S = bt.S + d.mat_off;
+  double* DS = DSp + d.mat_off;
+  const double cw = wsys ? wsys[si] : 1.0;
+  __shared__ double X[MAXN][4];
+  __shared__ double Y[MAXN][4];
+  __shared__ double red[256][4];
+  const double cp = 0.5 * sqrt(3.0);
+  for (int e = bt.hop_off[si]; e < bt.hop_off[si + 1]; ++e) {
+    const int la = bt.hop_atom[e];
+    const int o = bt.sys_atom_ao0[d.atom_off + la];
+    const double* bv = bt.hop_b + 3 * e;
+    const double h[4] = {0.5, cp * bv[0], cp * bv[1], cp * bv[2]};
+    const bool bda = bt.hop_kind[e] == 1;
+    double D[4][4];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) D[i][j] = bda ? V * h[i] * h[j] : V * ((i == j ? 1.0 : 0.0) - h[i] * h[j]);
+    // X = Dm S[:, boundary AOs], Y = X D
+    for (int mu = threadIdx.x; mu < n; mu += blockDim.x) {
+      double x[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int nu = 0; nu < n; ++nu) {
+        const double p = Dm[(long long)mu * n + nu];
+        for (int j = 0; j < 4; ++j) x[j] += p * S[(long long)nu * n + o + j];
+      }
+      for (int j = 0; j < 4; ++j) {
+        X[mu][j] = x[j];
+        double y = 0.0;
+        for (int k = 0; k < 4; ++k) y += x[k] * D[k][j];
+        Y[mu][j] = y;
+      }
+    }
+    __syncthreads();
+    for (int mu = threadIdx.x; mu < n; mu += blockDim.x)
+      for (int j = 0; j < 4; ++j) DS[(long long)mu * n + o + j] += Y[mu][j];
+    __syncthreads();
+    for (int mu = threadIdx.x; mu < n; mu += blockDim.x)
+      for (int j = 0; j < 4; ++j) DS[(long long)(o + j) * n + mu] += Y[mu][j];
+    // w_i = sum_mu S[o + i][mu] (X h)[mu]: partial sums per thread, fixed order
+    double wpart[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int mu = threadIdx.x; mu < n; mu += blockDim.x) {
+      const double xh = X[mu][0] * h[0] + X[mu][1] * h[1] + X[mu][2] * h[2] + X[mu][3] * h[3];
+      for (int i = 0; i < 4; ++i) wpart[i] += S[(long long)(o + i) * n + mu] * xh;
+    }
+    for (int i = 0; i < 4; ++i) red[threadIdx.x][i] = wpart[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double w[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int t = 0; t < (int)blockDim.x; ++t)
+        for (int i = 0; i < 4; ++i) w[i] += red[t][i];
+      const int kb = bt.hop_bond[e];
+      const int det = bonds[2 * kb], att = bonds[2 * kb + 1];
+      double u[3], L2 = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        u[k] = sys.xyz[3 * att + k] - sys.xyz[3 * det + k];
+        L2 += u[k] * u[k];
+      }
+      const double L = sqrt(L2);
+      const double bw = bv[0] * w[1] + bv[1] * w[2] + bv[2] * w[3];
+      const double pre = cw * (bda ? 1.0 : -1.0) * 2.0 * V * cp / L;
+      double* f = hop_f + 6 * (slot_base + e);
+      for (int k = 0; k < 3; ++k) {
+        const double fk = pre * (w[1 + k] - bv[k] * bw);
+        f[k] = fk;
+        f[3 + k] = -fk;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// accumulated charge transfer of the ghosts of bonds healed inside each
+// cluster: qbar += -w_X q (eq. ctij_ghost); every ghost shell is healed in
+// at most one cluster of a batch
+__global__ void k_healed_ct(DevBatch bt, const double* w, const double* qmono, double* qbar) {
+  const int si = blockIdx.x;
+  const double wx = w ? w[si] : 1.0;
+  for (int e = bt.healed_off[si] + threadIdx.x; e < bt.healed_off[si + 1]; e += blockDim.x) {
+    const int t = bt.healed_sh[e];
+    qbar[t] += -wx * qmono[t];
+  }
+}
+
+// forces of the extended atoms (real atoms, then one ghost per cut bond) added
+// to the real atoms: a ghost sits on its detached atom (fixed order)
+__global__ void k_add_ext_forces(int N, int NB, const int* bonds, const double* f_ext, double* grad) {
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= N) return;
+  double g[3] = {f_ext[3 * A], f_ext[3 * A + 1], f_ext[3 * A + 2]};
+  for (int k = 0; k < NB; ++k)
+    if (bonds[2 * k] == A)
+      for (int c = 0; c < 3; ++c) g[c] += f_ext[3LL * (N + k) + c];
+  for (int c = 0; c < 3; ++c) grad[3 * A + c] += g[c];
 }
 
 // dst = w_X src on the shells of every system X of a batch
@@ -415,6 +573,7 @@ __global__ void k_force_inter(DevSystem sys, const double* q, const double* av, 
         if (sf[k] == fa) continue;
         double dx = xa - sx[k], dy = ya - sy[k], dz = za - sz[k];
         double R = sqrt(dx * dx + dy * dy + dz * dz);
+        if (R == 0.0) continue;  // a ghost on its own detached atom: gamma is flat there
         double acc = 0.0;
         for (int u = 0; u < na; ++u)
           for (int v = 0; v < sn[k]; ++v) {

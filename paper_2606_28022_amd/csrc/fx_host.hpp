@@ -242,7 +242,9 @@ struct Batch {
   // 2 ghost, bond direction) and the ghosts healed inside each system
   bool has_hop = false, has_healed = false;
   DevBuf<double> sh_q0, atom_zs, hop_b, Vh;
-  DevBuf<int> hop_off, hop_atom, hop_kind, healed_off, healed_sh, sh_mono;
+  DevBuf<int> hop_off, hop_atom, hop_kind, hop_bond, healed_off, healed_sh, sh_mono;
+  int n_hop = 0;  // boundary entries of the batch
+  std::vector<int> h_hop_off, h_hop_bond, h_healed_off, h_healed_sh;  // host copies
   long long tot_gam = 0;
   DevBatch dev();
   // algorithmic work of one n x n product (2 n^3) summed over listed systems

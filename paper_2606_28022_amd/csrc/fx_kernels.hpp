@@ -161,7 +161,9 @@ __global__ void k_rowscale(DevBatch bt, const double* wsh, const double* P, doub
 __global__ void k_sym_inplace(DevBatch bt, double* A);
 __global__ void k_resp_DS(DevBatch bt, const double* Zb, const double* WZ, const double* X2, const double* wsh,
                           double* DS, double* gx);
-__global__ void k_cluster_cross(DevSystem sys, DevBatch bt, const double* x, double* out);
+__global__ void k_cluster_cross(DevSystem sys, DevBatch bt, const double* x, const double* qmono, const double* w,
+                                double* out, double* out_gh);
+__global__ void k_sub_healed(DevBatch bt, const double* vgh, double* v);
 __global__ void k_gather_csr(int n, const int* rowptr, const int* ent, const double* src, const double* base,
                              double sign, double* dst);
 __global__ void k_axpy(long long n, const double* x, double a, const double* y, double* out);
@@ -169,7 +171,11 @@ __global__ void k_grad_contract(DevSystem sys, DevBatch bt, const int* list, con
                                 const double* gx, const double* gy, const double* wsys, int with_rep, int accumulate,
                                 double* g_out, double* F_out, double* scratch);
 __global__ void k_grad_pair_corr(DevSystem sys, DevBatch bt, const double* qmono, const double* ddq,
-                                 const double* wct, const int* qqmask, double* g_out);
+                                 const double* wct, const int* qqmask, double* g_out, double* ghost_out);
+__global__ void k_hop_grad(DevSystem sys, DevBatch bt, const double* Dmp, double* DSp, const double* wsys,
+                           const int* bonds, double V, long long slot_base, double* hop_f);
+__global__ void k_healed_ct(DevBatch bt, const double* w, const double* qmono, double* qbar);
+__global__ void k_add_ext_forces(int N, int NB, const int* bonds, const double* f_ext, double* grad);
 __global__ void k_scale_cluster(DevBatch bt, const double* w, const double* src, double* dst);
 __global__ void k_force_inter(DevSystem sys, const double* q, const double* av, int nchunk, double* part);
 __global__ void k_force_reduce(int N, int nchunk, const double* part, double* out);

@@ -345,10 +345,13 @@ __global__ void k_resp_DS(DevBatch bt, const double* Zb, const double* WZ, const
 
 // per cluster system: cross-fragment potential of a local shell vector x,
 // out_s = sum_{t in X, frag(t) != frag(s)} gamma_st x_t
-__global__ void k_cluster_cross(DevSystem sys, DevBatch bt, const double* x, double* out) {
+__global__ void k_cluster_cross(DevSystem sys, DevBatch bt, const double* x, const double* qmono, const double* w,
+                                double* out, double* out_gh) {
   const int si = blockIdx.x;
   const SysDesc d = bt.desc[si];
   const int* shg = bt.sys_sh_global + d.sh_off;
+  const int h0 = bt.healed_off ? bt.healed_off[si] : 0, h1 = bt.healed_off ? bt.healed_off[si + 1] : 0;
+  const double wx = w ? w[si] : 1.0;
   for (int s = threadIdx.x; s < d.nsh; s += blockDim.x) {
     int fs = sys.sh_frag[shg[s]];
     double v = 0.0;
@@ -356,8 +359,51 @@ __global__ void k_cluster_cross(DevSystem sys, DevBatch bt, const double* x, dou
       if (sys.sh_frag[shg[t]] == fs) continue;
       v += bt.gam[d.gam_off + (long long)s * d.nsh + t] * x[d.sh_off + t];
     }
+    // the charge transfer -w q of the ghosts healed inside the cluster (eq.
+    // ctij_ghost) on the shells of the other fragment
+    const int gs = shg[s], As = sys.sh_atom[gs];
+    for (int e = h0; e < h1; ++e) {
+      const int t = bt.healed_sh[e], G = sys.sh_atom[t];
+      if (sys.sh_frag[t] == fs) continue;
+      double R2 = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        const double dx = sys.xyz[3 * As + k] - sys.xyz[3 * G + k];
+        R2 += dx * dx;
+      }
+      v += gamma_pair(sys.g, sqrt(R2), sys.sh_eta[gs], sys.sh_eta[t]) * (-wx * qmono[t]);
+    }
     out[d.sh_off + s] = v;
   }
+  // the same cross-fragment potential at the healed ghosts' own shells (they
+  // are monomer shells of one of the cluster's fragments, outside its basis)
+  if (!out_gh) return;
+  for (int e = h0 + threadIdx.x; e < h1; e += blockDim.x) {
+    const int gs = bt.healed_sh[e], fs = sys.sh_frag[gs], As = sys.sh_atom[gs];
+    auto gam = [&](int t) {
+      const int At = sys.sh_atom[t];
+      double R2 = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        const double dx = sys.xyz[3 * As + k] - sys.xyz[3 * At + k];
+        R2 += dx * dx;
+      }
+      return gamma_pair(sys.g, sqrt(R2), sys.sh_eta[gs], sys.sh_eta[t]);
+    };
+    double v = 0.0;
+    for (int t = 0; t < d.nsh; ++t)
+      if (sys.sh_frag[shg[t]] != fs) v += gam(shg[t]) * x[d.sh_off + t];
+    for (int e2 = h0; e2 < h1; ++e2) {
+      const int t = bt.healed_sh[e2];
+      if (sys.sh_frag[t] != fs) v += gam(t) * (-wx * qmono[t]);
+    }
+    out_gh[e] = v;
+  }
+}
+
+// v[s] -= cross-fragment potential of the cluster that heals ghost shell s
+__global__ void k_sub_healed(DevBatch bt, const double* vgh, double* v) {
+  const int si = blockIdx.x;
+  for (int e = bt.healed_off[si] + threadIdx.x; e < bt.healed_off[si + 1]; e += blockDim.x)
+    v[bt.healed_sh[e]] -= vgh[e];
 }
 
 // dst[s] = base[s] + sign * sum over CSR entries of src[entry] (fixed order)
