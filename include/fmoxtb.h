@@ -353,10 +353,17 @@ int fx_embedding_field(fx_ctx* ctx, const double* dq, double* phi);
 #define FX_NOALLOC_SCRATCH_DOUBLES (1 << 20)
 int fx_embedding_field_noalloc(fx_ctx* ctx, const double* d_dq, double* d_phi);
 
-/* Batched symmetric eigensolver used by the SCC: nmat matrices of sizes n[k]
- * (each <= 512), packed one after another row-major in A (sum n[k]^2
- * doubles).  Writes eigenvalues w (sum n[k], unsorted) and eigenvectors as
- * rows of V (same packing as A: row i of matrix k is eigenvector i). */
+/* Batched symmetric eigensolver used by the SCC, as the SCC runs it: the
+ * LDS-resident Jacobi of a cold solve (working matrix in FP64 where it fits
+ * in LDS, else FP32 with FP64 angles and eigenvectors), run to convergence,
+ * then one warm iteration (A' = V A V^T rebuilt in FP64 on the matrix cores,
+ * the rotation kernel on the LDS working matrix, the apply kernel on V);
+ * matrices smaller than 8 (no SCC system is) and sizes without an LDS plan
+ * use a global-memory Jacobi.  nmat matrices of
+ * sizes n[k] (each <= 512), packed one after another row-major in A (sum
+ * n[k]^2 doubles).  Writes eigenvalues w (sum n[k], unsorted) and
+ * eigenvectors as rows of V (same packing as A: row i of matrix k is
+ * eigenvector i). */
 int fx_eigh_batched(fx_ctx* ctx, int32_t nmat, const int32_t* n, const double* A, double* w,
                     double* V);
 

@@ -749,6 +749,109 @@ JacobiPlan Ctx::jacobi_plan(int n, bool fp64_only, bool prefer_fp32) const {
   return jp;
 }
 
+// Eigenpairs of symmetric matrices with the eigensolver of the SCC: the
+// LDS-resident Jacobi of a cold solve, run to convergence, then one
+// iteration of the form every later SCC iteration runs (A' = V A V^T rebuilt
+// in FP64 on the matrix cores, the rotation kernel on the LDS working matrix,
+// the apply kernel on V); sizes without an LDS plan use the global-memory
+// kernel.  Eigenvalues unsorted, eigenvectors as rows of V.
+void Ctx::eigh_hot(const std::vector<int>& nv, const double* A, double* w, double* V, bool global_kernel) {
+  const int nmat = (int)nv.size();
+  Batch b;
+  b.nsys = nmat;
+  b.h_desc.resize(nmat);
+  long long mat = 0, ao = 0;
+  std::vector<long long> off(nmat), woff(nmat);
+  for (int k = 0; k < nmat; ++k) {
+    SysDesc& d = b.h_desc[k];
+    d = SysDesc{};
+    d.nao = nv[k];
+    d.mat_off = mat;
+    d.ao_off = (int)ao;
+    for (int f = 0; f < 3; ++f) d.frag[f] = -1;
+    off[k] = mat;
+    woff[k] = ao;
+    mat += (long long)nv[k] * nv[k];
+    ao += nv[k];
+    b.max_nao = std::max(b.max_nao, nv[k]);
+  }
+  b.tot_mat = mat;
+  b.tot_ao = (int)ao;
+  b.d_desc.upload(b.h_desc);
+  std::vector<double> hA(A, A + mat), hI(mat, 0.0);
+  for (int k = 0; k < nmat; ++k)
+    for (int i = 0; i < nv[k]; ++i) hI[off[k] + (long long)i * nv[k] + i] = 1.0;
+  b.Pm.upload(hA);  // the input, kept for the rebuild
+  b.Fm.upload(hA);
+  b.Ct.upload(hI);
+  b.Tm.alloc(mat);
+  b.eps.alloc(ao);
+  b.status.upload(std::vector<int>(nmat, 0));
+  b.err.upload(std::vector<double>(nmat, 0.0));
+  b.sweeps.alloc(nmat);
+  std::vector<int> all(nmat);
+  for (int k = 0; k < nmat; ++k) all[k] = k;
+  b.d_list.upload(all);
+  DevBatch db = b.dev();
+  const JacobiPlan jp = global_kernel ? JacobiPlan{} : jacobi_plan(b.max_nao, false, false);
+  if (jp.elt == 0) {
+    DevBuf<int> dn;
+    dn.upload(nv);
+    DevBuf<long long> doff, dwoff;
+    doff.upload(off);
+    dwoff.upload(woff);
+    hipLaunchKernelGGL(k_eigh_batched, dim3(nmat), dim3(256), 0, stream, dn.p, doff.p, b.Fm.p, b.Ct.p, b.eps.p,
+                       dwoff.p, 60, 1e-15);
+    check(hipGetLastError(), "k_eigh_batched");
+  } else {
+    if (jp.elt == 8)
+      hipLaunchKernelGGL(k_jacobi_lds<double>, dim3(nmat), dim3(jp.threads), jp.lds, stream, db, b.d_list.p,
+                         jacobi_max_sweeps, jacobi_tol, jacobi_thr_scale, 1e300, b.sweeps.p, jp.chunk);
+    else
+      hipLaunchKernelGGL(k_jacobi_lds<float>, dim3(nmat), dim3(jp.threads), jp.lds, stream, db, b.d_list.p,
+                         jacobi_max_sweeps, jacobi_tol, jacobi_thr_scale, 1e300, b.sweeps.p, jp.chunk);
+    check(hipGetLastError(), "cold eigensolver");
+    // the warm iteration: A' = V A V^T (FP64), then rotations and their
+    // application to V
+    gemm_batch(b, db, nmat, b.d_list.p, 0, b.Ct.p, b.Pm.p, b.Tm.p, nullptr, b.gemm_gflop(all), 0);
+    gemm_batch(b, db, nmat, b.d_list.p, 1, b.Tm.p, b.Ct.p, b.Fm.p, nullptr, b.gemm_gflop_sym(all), 0, 1);
+    const int m4 = (b.max_nao + 3) & ~3;
+    const bool split_ok = (long long)apply_rot_lds_bytes(b.max_nao) <= lds_max &&
+                          (int)jacobi_rot_layout(b.max_nao, jp.elt).total <= lds_max &&
+                          8 * m4 <= 2 * 64 * apply_rot_waves(b.max_nao);
+    if (split_ok) {
+      const long long log_stride = (long long)jacobi_max_log * jacobi_rot_log_entries(b.max_nao);
+      b.rotlog.alloc((long long)nmat * log_stride);
+      b.nlog.alloc(nmat);
+      const unsigned lds_rot = jacobi_rot_layout(b.max_nao, jp.elt).total;
+      if (jp.elt == 8)
+        hipLaunchKernelGGL(k_jacobi_rot<double>, dim3(nmat), dim3(jp.threads), lds_rot, stream, db, b.d_list.p,
+                           jacobi_max_sweeps, jacobi_tol, jacobi_thr_scale, jacobi_cap_err, b.sweeps.p, b.rotlog.p,
+                           log_stride, jacobi_max_log, b.nlog.p);
+      else
+        hipLaunchKernelGGL(k_jacobi_rot<float>, dim3(nmat), dim3(jp.threads), lds_rot, stream, db, b.d_list.p,
+                           jacobi_max_sweeps, jacobi_tol, jacobi_thr_scale, jacobi_cap_err, b.sweeps.p, b.rotlog.p,
+                           log_stride, jacobi_max_log, b.nlog.p);
+      const int tw = apply_rot_tile(b.max_nao);
+      const int tps = (b.max_nao + tw - 1) / tw;
+      const long long grid = ((long long)nmat * tps + 7) / 8 * 8;
+      hipLaunchKernelGGL(k_apply_rot, dim3((unsigned)grid), dim3(64 * apply_rot_waves(b.max_nao)),
+                         (unsigned)apply_rot_lds_bytes(b.max_nao), stream, db, b.d_list.p, nmat, tps, tw,
+                         (const double2*)b.rotlog.p, log_stride, (const int*)b.nlog.p);
+    } else if (jp.elt == 8) {
+      hipLaunchKernelGGL(k_jacobi_lds<double>, dim3(nmat), dim3(jp.threads), jp.lds, stream, db, b.d_list.p,
+                         jacobi_max_sweeps, jacobi_tol, jacobi_thr_scale, jacobi_cap_err, b.sweeps.p, jp.chunk);
+    } else {
+      hipLaunchKernelGGL(k_jacobi_lds<float>, dim3(nmat), dim3(jp.threads), jp.lds, stream, db, b.d_list.p,
+                         jacobi_max_sweeps, jacobi_tol, jacobi_thr_scale, jacobi_cap_err, b.sweeps.p, jp.chunk);
+    }
+    check(hipGetLastError(), "warm eigensolver iteration");
+  }
+  b.eps.download_raw(w, ao, stream);
+  b.Ct.download_raw(V, mat, stream);
+  sync();
+}
+
 void Ctx::build_matrices(Batch& b) {
   if (b.has_hop) b.Vh.alloc(std::max(1LL, b.tot_mat));
   DevBatch db = b.dev();
@@ -2202,33 +2305,43 @@ int fx_embedding_field(fx_ctx* ctx, const double* dq, double* phi) {
 int fx_eigh_batched(fx_ctx* ctx, int32_t nmat, const int32_t* n, const double* A, double* w, double* V) {
   if (!ctx || nmat < 0 || !n || !A || !w || !V) return FX_E_INVALID;
   FX_GUARD(ctx, {
-    fx::Ctx& c = ctx->c;
     std::vector<int> nv(n, n + nmat);
-    std::vector<long long> off(nmat), woff(nmat);
-    long long tot = 0, wt = 0;
-    for (int k = 0; k < nmat; ++k) {
+    for (int k = 0; k < nmat; ++k)
       if (nv[k] < 1 || nv[k] > fx::MAXN) throw fx::FxError(FX_E_INVALID, "matrix size out of range");
-      off[k] = tot;
-      woff[k] = wt;
-      tot += (long long)nv[k] * nv[k];
-      wt += nv[k];
-    }
     if (nmat == 0) return FX_OK;
-    fx::DevBuf<int> dn;
-    dn.upload(nv);
-    fx::DevBuf<long long> doff, dwoff;
-    doff.upload(off);
-    dwoff.upload(woff);
-    fx::DevBuf<double> dA, dV, dw;
-    dA.upload(std::vector<double>(A, A + tot));
-    dV.alloc(tot);
-    dw.alloc(wt);
-    hipLaunchKernelGGL(fx::k_eigh_batched, dim3(nmat), dim3(256), 0, c.stream, dn.p, doff.p, dA.p, dV.p, dw.p, dwoff.p,
-                       60, 1e-15);
-    fx::Ctx::check(hipGetLastError(), "k_eigh_batched");
-    dw.download_raw(w, wt, c.stream);
-    dV.download_raw(V, tot, c.stream);
-    c.sync();
+    // matrices smaller than any SCC system (8 AOs) go to the global-memory
+    // kernel, the others through the SCC's eigensolver
+    std::vector<long long> off(nmat + 1, 0), woff(nmat + 1, 0);
+    for (int k = 0; k < nmat; ++k) {
+      off[k + 1] = off[k] + (long long)nv[k] * nv[k];
+      woff[k + 1] = woff[k] + nv[k];
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<int> sel, ns;
+      std::vector<double> a;
+      for (int k = 0; k < nmat; ++k)
+        if ((nv[k] >= 8) == (pass == 0)) {
+          sel.push_back(k);
+          ns.push_back(nv[k]);
+          a.insert(a.end(), A + off[k], A + off[k + 1]);
+        }
+      if (sel.empty()) continue;
+      long long tot = 0, wt = 0;
+      for (int x : ns) {
+        tot += (long long)x * x;
+        wt += x;
+      }
+      std::vector<double> ws(wt), vs(tot);
+      ctx->c.eigh_hot(ns, a.data(), ws.data(), vs.data(), pass == 1);
+      long long o = 0, ow = 0;
+      for (size_t i = 0; i < sel.size(); ++i) {
+        const int k = sel[i];
+        std::copy(vs.begin() + o, vs.begin() + o + (long long)nv[k] * nv[k], V + off[k]);
+        std::copy(ws.begin() + ow, ws.begin() + ow + nv[k], w + woff[k]);
+        o += (long long)nv[k] * nv[k];
+        ow += nv[k];
+      }
+    }
   });
 }
 

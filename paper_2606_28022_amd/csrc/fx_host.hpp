@@ -458,6 +458,7 @@ struct Ctx {
   void field(const double* d_q, double* d_phi, bool fp32 = false);
   void build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters, int nfrag_each);
   void build_matrices(Batch& b);
+  void eigh_hot(const std::vector<int>& nv, const double* A, double* w, double* V, bool global_kernel = false);
   void init_device();
   // embedding field through the chunked pass into caller-given device
   // buffers, partial sums in the library's static scratch (no allocation)
