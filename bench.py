@@ -2,10 +2,11 @@
 crystal (11 x 5 x 6 triclinic herringbone cells, 660 molecules, seeded
 +-0.05 A jitter) on one MI355X.
 
-A step is one full pass of the hot path for one geometry: pair lists,
-supersystem CN, the self-consistent monomer embedding, all SCC dimers, the
-ES-DIM pairs, the energy and the FMO2 gradient including the embedding
-response.  The system is uploaded before timing (inputs resident in HBM).
+A step is one full pass of the hot path for one geometry: the pair lists
+(classification of every fragment pair on the GPU), supersystem CN, the
+self-consistent monomer embedding, all SCC dimers, the ES-DIM pairs, the
+energy and the FMO2 gradient including the embedding response.  The system
+is uploaded before timing (inputs resident in HBM).
 
 Prints one JSON line.  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain] [--no-guess] [--no-forms] [--no-warm] [--no-fmo3]
@@ -419,6 +420,7 @@ def main():
     cnt = c.get_counts()
 
     for k in range(args.warmup):
+        c.build_lists_counts()
         r = c.run()
         log(f"warmup {k}: {r['ms_monomer'] + r['ms_dimer'] + r['ms_gradient']:.0f} ms")
 
@@ -427,6 +429,7 @@ def main():
     for k in range(args.steps):
         torch.cuda.synchronize()
         t = time.perf_counter()
+        c.build_lists_counts()   # the pair lists are part of the step
         r = c.run()
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t)

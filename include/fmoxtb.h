@@ -75,7 +75,7 @@ typedef struct fx_options {
                              otherwise ES-DIM; a trimer is computed when at
                              least two of its three pairs are SCC dimers */
   int32_t precision;      /* FX_FP64, or FX_MIXED: while an SCC residual is
-                             above 1e-5, the Fock matrix is assembled in FP32
+                             above 1e-4, the Fock matrix is assembled in FP32
                              from FP32 copies of H0 and S and the congruence
                              product C^T F C and the density product
                              C diag(n) C^T run on the FP32 matrix cores with

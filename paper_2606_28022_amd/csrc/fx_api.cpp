@@ -1006,14 +1006,14 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
   KernelTimer* kt_rot = kt(jp.elt == 8 ? "fx::k_jacobi_rot<double>" : "fx::k_jacobi_rot<float>");
   KernelTimer* kt_app = kt("fx::k_apply_rot");
   // mixed precision: FP32 Fock build and FP32 matrix-core products for this
-  // iteration (the basis, the rotation angles and the convergence test stay
-  // FP64; a system converges only in an FP64 iteration).  Not with the
-  // captured graph, whose launches are fixed.
+  // iteration (the basis, the rotation angles, the charges and the
+  // convergence test stay FP64; a final solve's tolerance lies far below the
+  // switch threshold, so its converged state comes from FP64 iterations).
+  // Not with the captured graph, whose launches are fixed.
   const bool graph_mode = opt.schedule == FX_BATCHED_GRAPH && !single && !first_solve;
   const bool f32_ok = b.has_f32 && !graph_mode && prod_mode != 0;
   // per system: still in the FP32 phase (until its own SCC residual drops to
-  // mixed_thr; its Anderson history is then cleared, so that the FP64
-  // iterations mix FP64 residuals only)
+  // mixed_thr; its Anderson history is kept unless mixed_hist_reset is set)
   std::vector<char> is32(b.nsys, f32_ok ? 1 : 0);
   std::vector<int> switched;
   DevBuf<int> d_switched;
@@ -1873,9 +1873,8 @@ void Ctx::run(fx_result* out) {
     if (tb_.has_healed)
       hipLaunchKernelGGL(k_cluster_healed, dim3(tb_.nsys), dim3(128), 0, stream, dev_system(), dtb, d_phi.p, d_q.p,
                          dEV.p, dEX.p);
-    trimer_dEIJK.resize(ntri);
-    dEX.download(trimer_dEIJK, stream);
-    sync();
+    d_dEIJK.alloc(ntri);
+    check(hipMemcpyAsync(d_dEIJK.p, dEX.p, sizeof(double) * ntri, hipMemcpyDeviceToDevice, stream), "copy");
   }
   double t4 = now_ms();
   res.ms_trimer = t4 - t3;
@@ -1907,21 +1906,26 @@ void Ctx::run(fx_result* out) {
     res.e_total = hs[0];
   }
   if (opt.order >= 3 && ntri > 0) {
-    // trimer corrections Delta E_IJK - Delta E_IJ - Delta E_IK - Delta E_JK
-    std::vector<double> h_scc(nscc), h_esd(nesd);
-    if (nscc) dE_scc.download(h_scc, stream);
-    if (nesd) dE_esd.download(h_esd, stream);
-    sync();
-    std::vector<double> corr(ntri);
-    auto pair_index = [&](int I, int J) -> long long { return (long long)I * F - (long long)I * (I + 1) / 2 + (J - I - 1); };
-    std::vector<double> pair_dE((size_t)F * (F - 1) / 2, 0.0);
-    for (long long k = 0; k < nscc; ++k) pair_dE[pair_index(scc_pairs[2 * k], scc_pairs[2 * k + 1])] = h_scc[k];
-    for (long long k = 0; k < nesd; ++k) pair_dE[pair_index(esd_pairs[2 * k], esd_pairs[2 * k + 1])] = h_esd[k];
+    // trimer corrections Delta E_IJK - Delta E_IJ - Delta E_IK - Delta E_JK on
+    // the device; the host only locates each sub-pair in the pair lists
+    // (index into dE_scc, or nscc + index into dE_esd)
+    std::unordered_map<long long, long long> where;
+    where.reserve((size_t)(nscc + nesd) * 2);
+    for (long long k = 0; k < nscc; ++k) where[(long long)scc_pairs[2 * k] * F + scc_pairs[2 * k + 1]] = k;
+    for (long long k = 0; k < nesd; ++k) where[(long long)esd_pairs[2 * k] * F + esd_pairs[2 * k + 1]] = nscc + k;
+    std::vector<long long> sub_idx(3 * ntri);
     for (long long k = 0; k < ntri; ++k) {
-      int I = trimers[3 * k], J = trimers[3 * k + 1], K = trimers[3 * k + 2];
-      corr[k] = trimer_dEIJK[k] - pair_dE[pair_index(I, J)] - pair_dE[pair_index(I, K)] - pair_dE[pair_index(J, K)];
+      const int I = trimers[3 * k], J = trimers[3 * k + 1], K = trimers[3 * k + 2];
+      sub_idx[3 * k] = where.at((long long)I * F + J);
+      sub_idx[3 * k + 1] = where.at((long long)I * F + K);
+      sub_idx[3 * k + 2] = where.at((long long)J * F + K);
     }
-    dE_tri.upload(corr);
+    DevBuf<long long> d_sub;
+    d_sub.upload(sub_idx);
+    hipLaunchKernelGGL(k_trimer_corr, dim3((unsigned)((ntri + 255) / 256)), dim3(256), 0, stream, ntri,
+                       (const double*)d_dEIJK.p, (const double*)dE_scc.p, nscc, (const double*)dE_esd.p,
+                       (const long long*)d_sub.p, dE_tri.p);
+    check(hipGetLastError(), "k_trimer_corr");
     std::vector<const double*> arr = {d_scalar.p, dE_tri.p};
     std::vector<long long> len = {1, ntri};
     DevBuf<const double*> da;

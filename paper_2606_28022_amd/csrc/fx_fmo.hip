@@ -242,4 +242,20 @@ __global__ void k_hist_store(const double* x, const double* y, long long n, int 
   R[(long long)slot * n + k] = y[k] - x[k];
 }
 
+// Trimer corrections Delta E_IJK - Delta E_IJ - Delta E_IK - Delta E_JK
+// (eq. fmo3_energy; an ES-DIM sub-pair enters with its ES-DIM value): sub
+// holds, per trimer, the three sub-pairs as an index into dE_scc or nscc +
+// an index into dE_esd.
+__global__ void k_trimer_corr(long long ntri, const double* dEIJK, const double* dE_scc, long long nscc,
+                              const double* dE_esd, const long long* sub, double* out) {
+  const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (k >= ntri) return;
+  double v = dEIJK[k];
+  for (int p = 0; p < 3; ++p) {
+    const long long e = sub[3 * k + p];
+    v -= e < nscc ? dE_scc[e] : dE_esd[e - nscc];
+  }
+  out[k] = v;
+}
+
 }  // namespace fx

@@ -364,7 +364,7 @@ struct Ctx {
   std::vector<long long> warm_matoff, warm_shoff;
   DevBuf<double> warm_C, warm_q;  // last run's SCC dimer orbitals (C^T) and shell charges
   DevBuf<long long> warm_so;       // per dimer of this run: shell offset in warm_q, or -1
-  std::vector<double> trimer_dEIJK;
+  DevBuf<double> d_dEIJK;  // Delta E_IJK of the trimers of the last run
   fx_result res{};
   // monomer susceptibility blocks (shell-summed transition charges Q and
   // M = sum_ai Q Q^T / (eps_a - eps_i)) of the current monomer orbitals

@@ -161,6 +161,8 @@ __global__ void k_rowscale(DevBatch bt, const double* wsh, const double* P, doub
 __global__ void k_sym_inplace(DevBatch bt, double* A);
 __global__ void k_resp_DS(DevBatch bt, const double* Zb, const double* WZ, const double* X2, const double* wsh,
                           double* DS, double* gx);
+__global__ void k_trimer_corr(long long ntri, const double* dEIJK, const double* dE_scc, long long nscc,
+                              const double* dE_esd, const long long* sub, double* out);
 __global__ void k_cluster_cross(DevSystem sys, DevBatch bt, const double* x, const double* qmono, const double* w,
                                 double* out, double* out_gh);
 __global__ void k_sub_healed(DevBatch bt, const double* vgh, double* v);
