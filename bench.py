@@ -177,8 +177,10 @@ def forms_c4(c, s, sec_fp64, r64, g64):
     """The forms of the step on the same crystal, each timed after a warm-up
     run (the one-system-at-a-time loop once, without warm-up): the plain
     per-fragment GPU loop (FX_PLAIN_LOOP, FP64), the batched FP64 form (the
-    headline), the mixed-precision form, the learned initial guess, the
-    captured-graph schedule, and the combined batched + mixed + learned form.
+    headline, device-compacted active lists), the mixed-precision form, the
+    learned initial guess, the batched form with one host synchronisation
+    per SCC iteration, the captured-graph schedule, and the combined batched
+    + mixed + learned form.
     Each reports |E - E_oracle| against the oracle golden of this crystal and
     max |g - g_FP64| against the batched FP64 gradient (pinned by central
     differences in the tests)."""
@@ -192,6 +194,7 @@ def forms_c4(c, s, sec_fp64, r64, g64):
     variants = [("plain_loop_fp64", dict(schedule=1), False),
                 ("batched_mixed", dict(precision=1), True),
                 ("batched_learned_guess", dict(guess=1, guess_tau=tau), True),
+                ("host_synced_fp64", dict(schedule=3), True),
                 ("graph_fp64", dict(schedule=2), True),
                 ("combined_batched_mixed_learned", dict(precision=1, guess=1, guess_tau=tau), True)]
     out = {"workload": "same crystal, FMO2 energy + analytic gradient with response",

@@ -54,12 +54,22 @@ enum {
 };
 
 enum { FX_FP64 = 0, FX_MIXED = 1 };           /* precision */
-/* schedule of the fragment solves: FX_BATCHED launches each SCC iteration
- * over all still-active systems of a kind; FX_PLAIN_LOOP solves one system
- * at a time; FX_BATCHED_GRAPH captures the iteration over all systems of a
- * solve once into a hipGraph and replays it (converged systems skip
- * themselves on the device), after an eager first iteration */
-enum { FX_BATCHED = 0, FX_PLAIN_LOOP = 1, FX_BATCHED_GRAPH = 2 };
+/* schedule of the fragment solves:
+ * FX_BATCHED launches each SCC iteration over all still-active systems of a
+ *   kind.  The active list is compacted on the device after every iteration
+ *   (systems still iterating first); the next iteration is launched at once,
+ *   over as many slots as the latest count that has come back to the host,
+ *   and the host waits for a count only when two iterations are already in
+ *   flight behind it (FP64 solves with the split eigensolver; the others
+ *   run as FX_BATCHED_HOST_SYNC).
+ * FX_BATCHED_HOST_SYNC compacts the active list on the host and
+ *   synchronises once per iteration.
+ * FX_PLAIN_LOOP solves one system at a time.
+ * FX_BATCHED_GRAPH captures the iteration over all systems of a solve once
+ *   into a hipGraph and replays it (converged systems skip themselves on the
+ *   device), after an eager first iteration.
+ * All four give bitwise identical results. */
+enum { FX_BATCHED = 0, FX_PLAIN_LOOP = 1, FX_BATCHED_GRAPH = 2, FX_BATCHED_HOST_SYNC = 3 };
 enum { FX_GUESS_SUPERPOSITION = 0, FX_GUESS_LEARNED = 1, FX_GUESS_USER = 2 };
 /* fragment-pair selection (section "Computational Details"): a fixed
  * closest-contact cutoff, or van der Waals-scaled contacts */
@@ -89,8 +99,9 @@ typedef struct fx_options {
                              matrix of systems too large for an FP64 copy in
                              LDS (more than about 180 AOs) is stored in FP32
                              between FP64 rebuilds of C^T F C. */
-  int32_t schedule;       /* FX_BATCHED: all fragments of a kind in one launch
-                             sequence; FX_PLAIN_LOOP: one fragment at a time */
+  int32_t schedule;       /* FX_BATCHED (device-compacted active lists),
+                             FX_BATCHED_HOST_SYNC, FX_BATCHED_GRAPH or
+                             FX_PLAIN_LOOP (one fragment at a time) */
   int32_t guess;          /* initial monomer charges: superposition (zero),
                              the learned model (fx_mlp_load) or the charges
                              given with fx_set_guess */

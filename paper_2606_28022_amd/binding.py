@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 
 FX_OK, FX_E_INVALID, FX_E_NOMEM, FX_E_DEVICE, FX_E_NOCONV, FX_E_STATE, FX_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 FX_FP64, FX_MIXED = 0, 1
-FX_BATCHED, FX_PLAIN_LOOP, FX_BATCHED_GRAPH = 0, 1, 2
+FX_BATCHED, FX_PLAIN_LOOP, FX_BATCHED_GRAPH, FX_BATCHED_HOST_SYNC = 0, 1, 2, 3
 FX_GUESS_SUPERPOSITION, FX_GUESS_LEARNED, FX_GUESS_USER = 0, 1, 2
 FX_MLP_NW, FX_MLP_NFEAT = 5634, 20
 

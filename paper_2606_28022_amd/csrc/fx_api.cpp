@@ -470,8 +470,7 @@ void Ctx::gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlis
     if (timed) timers.end(stream, ev, kt("fx::k_gemm"), gflop);
   } else {
     const int nt = (b.max_nao + 63) / 64;
-    const long long tiles = (long long)nl * nt * nt;
-    const long long grid = (tiles + 7) / 8 * 8;
+    const long long grid = xcd_grid(nl, nt * nt);
     if (grid > 0x7fffffffLL) throw FxError(FX_E_INVALID, "batched product grid too large");
     const int ev = timed ? timers.begin(stream) : -1;
     if (mode == 0)
@@ -493,8 +492,7 @@ void Ctx::gemm_batch_f32(const Batch& b, const DevBatch& db, int nl, const int* 
                          bool occ_list) {
   if (nl <= 0) return;
   const int nt = (b.max_nao + 63) / 64;
-  const long long tiles = (long long)nl * nt * nt;
-  const long long grid = (tiles + 7) / 8 * 8;
+  const long long grid = xcd_grid(nl, nt * nt);
   if (grid > 0x7fffffffLL) throw FxError(FX_E_INVALID, "batched product grid too large");
   const int ev = capturing ? -1 : timers.begin(stream);
   if (mode == 0)
@@ -834,7 +832,7 @@ void Ctx::eigh_hot(const std::vector<int>& nv, const double* A, double* w, doubl
                            log_stride, jacobi_max_log, b.nlog.p);
       const int tw = apply_rot_tile(b.max_nao);
       const int tps = (b.max_nao + tw - 1) / tw;
-      const long long grid = ((long long)nmat * tps + 7) / 8 * 8;
+      const long long grid = xcd_grid(nmat, tps);
       hipLaunchKernelGGL(k_apply_rot, dim3((unsigned)grid), dim3(64 * apply_rot_waves(b.max_nao)),
                          (unsigned)apply_rot_lds_bytes(b.max_nao), stream, db, b.d_list.p, nmat, tps, tw,
                          (const double2*)b.rotlog.p, log_stride, (const int*)b.nlog.p);
@@ -1051,7 +1049,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
       if (timed) timers.end(stream, ev, kt_rot, 0.0);
       const int tw = apply_rot_tile(b.max_nao);
       const int tps = (b.max_nao + tw - 1) / tw;
-      const long long grid = ((long long)na * tps + 7) / 8 * 8;
+      const long long grid = xcd_grid(na, tps);
       ev = timed ? timers.begin(stream) : -1;
       const unsigned lds_app = (unsigned)apply_rot_lds_bytes(b.max_nao);
       hipLaunchKernelGGL(k_apply_rot, dim3((unsigned)grid), dim3(64 * apply_rot_waves(b.max_nao)), lds_app, stream,
@@ -1093,6 +1091,21 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
   // systems skip themselves on the device, the host only reads the status
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  // device-driven form (the FP64 batched solves with the split eigensolver):
+  // after each iteration k_compact_active rewrites d_act with the systems
+  // still iterating first and copies their count to a pinned slot; the next
+  // iteration is launched at once over ub slots, ub being the latest count
+  // that has arrived (counts only fall, so ub bounds the true one, and the
+  // converged systems in the slots beyond it return at once)
+  const bool async = opt.schedule == FX_BATCHED && !single && !f32_ok && !verbose && split_ok;
+  int ub = nl;
+  std::deque<int> pending;
+  const std::vector<int> no_list;
+  if (async) {
+    count_ring_init();
+    d_act.alloc(nl);
+    check(hipMemcpyAsync(d_act.p, b.d_list.p, sizeof(int) * nl, hipMemcpyDeviceToDevice, stream), "copy");
+  }
   for (int it = 0; it < max_it && !active.empty(); ++it) {
     const double cap = (cold && it == 0 && !b.init_from_mono) ? 1e300 : jacobi_cap_err;
     if (graph_mode && it >= 1) {
@@ -1121,6 +1134,53 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
       for (int s : active)
         if (status[s] == 0) next.push_back(s);
       active.swap(next);
+      continue;
+    }
+    if (async) {
+      launch_iteration(no_list, d_act.p, ub, 0, cap, true);
+      if (first_solve && it == 0) {
+        // median first-iteration residual over the batch (all listed systems
+        // took part in iteration 0)
+        std::vector<double> e;
+        b.err.download(e, stream);
+        sync();
+        std::vector<double> v;
+        for (int s : list) v.push_back(e[s]);
+        std::nth_element(v.begin(), v.begin() + v.size() / 2, v.end());
+        res.first_residual_median = v[v.size() / 2];
+      }
+      if (first_solve && opt.guess == FX_GUESS_LEARNED &&
+          ((it == 0 && opt.guess_tau > 0) || (opt.guess_max_iter > 0 && it + 1 == opt.guess_max_iter))) {
+        hipLaunchKernelGGL(k_guess_fallback, dim3(ub), dim3(64), 0, stream, db, d_act.p, ub, it == 0 ? 0 : 1,
+                           opt.guess_tau, fallback_flag.p);
+        check(hipGetLastError(), "k_guess_fallback");
+      }
+      const int slot = it % CNT_RING;
+      hipLaunchKernelGGL(k_compact_active, dim3(1), dim3(1024), 0, stream, (const int*)b.status.p,
+                         (const int*)b.d_list.p, nl, d_act.p, cnt_dev.p + slot);
+      check(hipGetLastError(), "k_compact_active");
+      check(hipMemcpyAsync(cnt_host + slot, cnt_dev.p + slot, sizeof(int), hipMemcpyDeviceToHost, stream),
+            "count copy");
+      check(hipEventRecord(cnt_ev[slot], stream), "hipEventRecord");
+      pending.push_back(slot);
+      // take the counts that have arrived; block only when async_lag
+      // iterations are already in flight behind the oldest one
+      while (!pending.empty()) {
+        const int k = pending.front();
+        if ((int)pending.size() <= async_lag) {
+          const hipError_t q = hipEventQuery(cnt_ev[k]);
+          if (q == hipErrorNotReady) {
+            (void)hipGetLastError();  // not an error: the copy is still queued
+            break;
+          }
+          check(q, "hipEventQuery");
+        } else {
+          check(hipEventSynchronize(cnt_ev[k]), "hipEventSynchronize");
+        }
+        ub = std::min(ub, cnt_host[k]);
+        pending.pop_front();
+      }
+      if (ub == 0) break;
       continue;
     }
     int n32 = 0;
@@ -1224,6 +1284,25 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
   b.status.download(status, stream);
   b.niter.download(niter, stream);
   sync();
+  if (async) {
+    timers.resolve();
+    // algorithmic work from the per-system iteration counts (the launches
+    // were timed without it): the eigensolver as in the host-driven form,
+    // the products by the forms each iteration runs
+    KernelTimer* kt_g = kt(b.max_nao <= 32 ? "fx::k_gemm" : "fx::k_gemm_mfma");
+    const bool cold_full = cold && !b.init_from_mono;
+    for (int s : list) {
+      const int its = niter[s];
+      if (its <= 0) continue;
+      const int n_full = cold_full ? 1 : 0, n_split = its - n_full;
+      const double n = b.h_desc[s].nao, n3 = 1e-9 * n * n * n;
+      kt_jac->gflop += 3.3 * n3 * n_full;
+      kt_rot->gflop += 1.3 * n3 * n_split;
+      kt_app->gflop += 2.0 * n3 * n_split;
+      const std::vector<int> one{s};
+      kt_g->gflop += its * (b.gemm_gflop(one) + b.gemm_gflop_sym(one) + b.gemm_gflop_occ(one));
+    }
+  }
   if (verbose) {
     long long tot = 0;
     int mx = 0;
@@ -1245,6 +1324,14 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
   }
   if (iters_out) *iters_out += iters;
   return single ? 0 : failed;
+}
+
+void Ctx::count_ring_init() {
+  if (cnt_host) return;
+  if (cnt_dev.n < CNT_RING) cnt_dev.alloc(CNT_RING);
+  cnt_ev.assign(CNT_RING, nullptr);
+  for (auto& e : cnt_ev) check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+  check(hipHostMalloc((void**)&cnt_host, sizeof(int) * CNT_RING, hipHostMallocDefault), "hipHostMalloc");
 }
 
 // solve a batch either all at once or one system at a time
@@ -2119,7 +2206,8 @@ int fx_set_options(fx_ctx* ctx, const fx_options* o) {
         o->max_macro < 1)
       throw fx::FxError(FX_E_INVALID, "bad option value");
     if (o->precision != FX_FP64 && o->precision != FX_MIXED) throw fx::FxError(FX_E_INVALID, "bad precision");
-    if (o->schedule != FX_BATCHED && o->schedule != FX_PLAIN_LOOP && o->schedule != FX_BATCHED_GRAPH)
+    if (o->schedule != FX_BATCHED && o->schedule != FX_PLAIN_LOOP && o->schedule != FX_BATCHED_GRAPH &&
+        o->schedule != FX_BATCHED_HOST_SYNC)
       throw fx::FxError(FX_E_INVALID, "bad schedule");
     if (o->guess != FX_GUESS_SUPERPOSITION && o->guess != FX_GUESS_LEARNED && o->guess != FX_GUESS_USER)
       throw fx::FxError(FX_E_INVALID, "bad guess");

@@ -138,4 +138,17 @@ __device__ inline double rsqrt_pos(double x) {
   return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
+
+// List slot and tile of work-group L in a launch of xcd_grid(nl, tps)
+// work-groups over nl systems of tps tiles each.  The dispatcher deals
+// consecutive work-group ids to the 8 XCDs in turn; slot s runs on XCD s % 8
+// with all of its tiles, so that each system's operands stay in one L2, and
+// the leading slots (the systems still iterating, in a list compacted on the
+// device) spread evenly over the XCDs whatever the launch's slot bound.
+__device__ inline void xcd_slot_tile(int L, int tps, int& sl, int& tile) {
+  const int x = L & 7, j = L >> 3;
+  const int q = j / tps;
+  tile = j - q * tps;
+  sl = 8 * q + x;
+}
 }  // namespace fx

@@ -301,6 +301,9 @@ struct JacobiPlan {
 struct Ctx {
   ~Ctx() {
     if (gstream) (void)hipStreamDestroy(gstream);
+    for (hipEvent_t e : cnt_ev)
+      if (e) (void)hipEventDestroy(e);
+    if (cnt_host) (void)hipHostFree(cnt_host);
   }
   HostParams P;
   int device = 0;
@@ -483,6 +486,16 @@ struct Ctx {
   // graph-captured SCC iterations (schedule FX_BATCHED_GRAPH)
   bool capturing = false;
   hipStream_t gstream = nullptr;
+  // device-driven SCC iterations (schedule FX_BATCHED): the active list is
+  // compacted on the device after every iteration; its count comes back
+  // through a ring of pinned slots, each with an event, which the host polls
+  // at most async_lag iterations behind the launches
+  static constexpr int CNT_RING = 8;
+  int async_lag = 2;
+  int* cnt_host = nullptr;  // [CNT_RING], pinned
+  std::vector<hipEvent_t> cnt_ev;
+  DevBuf<int> cnt_dev;
+  void count_ring_init();
   int run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* iters_out, bool single = false);
   int solve_batch(Batch& b, bool cold, long long* iters_out);
   void run(fx_result* out);

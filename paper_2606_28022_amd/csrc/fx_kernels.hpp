@@ -29,6 +29,10 @@ __global__ void k_vhop(DevBatch bt, double vhop);
 __global__ void k_ghost_cn(DevSystem sys, const int* bonds, int nbonds, double* cn);
 __global__ void k_reset_state(DevBatch bt, const int* list, int nl, int keep_err);
 __global__ void k_hist_reset(DevBatch bt, const int* list, int nl);
+// work-groups of a launch over nl systems of tps tiles each, numbered by
+// xcd_slot_tile: 8 ceil(nl / 8) tps
+inline long long xcd_grid(int nl, int tps) { return 8LL * ((nl + 7) / 8) * tps; }
+__global__ void k_compact_active(const int* status, const int* list, int nl, int* act, int* count);
 __global__ void k_precond_step(DevBatch bt, double* out);
 __global__ void k_cholinv(DevBatch bt, const int* list, const double* Apool, double* Lpool, double* Xpool);
 __global__ void k_cluster_init_ct(DevBatch bt, const int* list, DevBatch mono, const long long* warm_off);

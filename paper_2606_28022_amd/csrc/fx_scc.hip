@@ -80,6 +80,41 @@ __global__ void k_hist_reset(DevBatch bt, const int* list, int nl) {
   if (k < nl) bt.nhist[list[k]] = 0;
 }
 
+// Stable partition of the list by status, on the device: the systems still
+// iterating (status 0) first, in list order, then the others, in list order;
+// *count = the number of the former.  One work-group of 1024 threads: each
+// thread takes a contiguous chunk of the list, and a scan over the chunk
+// counts places it.  Every list entry is written, so a kernel launched over
+// more slots than *count finds converged systems there and returns.
+__global__ void __launch_bounds__(1024) k_compact_active(const int* status, const int* list, int nl, int* act,
+                                                         int* count) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int per = (nl + nt - 1) / nt;
+  const int lo = min(nl, t * per), hi = min(nl, lo + per);
+  int na = 0;
+  for (int i = lo; i < hi; ++i) na += status[list[i]] == 0 ? 1 : 0;
+  part[t] = na;
+  __syncthreads();
+  for (int off = 1; off < nt; off <<= 1) {
+    const int v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  const int total = part[nt - 1];
+  int pa = part[t] - na;        // active entries before this chunk
+  int pi = total + (lo - pa);   // inactive ones go after all active ones
+  for (int i = lo; i < hi; ++i) {
+    const int si = list[i];
+    if (status[si] == 0)
+      act[pa++] = si;
+    else
+      act[pi++] = si;
+  }
+  if (t == 0) *count = total;
+}
+
 // Preconditioned monomer step of the fused embedding loop, per system:
 // out = q_in + (1 + M G)^-1 (q_out - q_in) (local shell vectors)
 __global__ void k_precond_step(DevBatch bt, double* out) {
@@ -441,9 +476,8 @@ __global__ void k_gemm(DevBatch bt, const int* list, int mode, const double* Aba
 // v_mfma_f64_16x16x4 blocks; K staged through LDS 32 at a time.  Lane layout
 // of the 16x16x4 FP64 instruction: A[i][k] and B[k][j] from lane i + 16 k
 // (resp. j + 16 k); output element r of lane l is D[l / 16 + 4 r][l % 16].
-// Work-groups are numbered so that all tiles of one system share an XCD (the
-// dispatcher deals consecutive work-group ids to the 8 XCDs in turn), which
-// keeps each system's operand panels in one L2.
+// Work-groups are numbered so that all tiles of one system share an XCD, which
+// keeps each system's operand panels in one L2 (xcd_slot_tile).
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // MODE is a template argument: each product form gets its own kernel with
@@ -455,9 +489,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
     k_gemm_mfma(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double* __restrict__ Abase,
                 const double* __restrict__ Bbase, double* __restrict__ Cbase, const double* __restrict__ wbase,
                 int skip_done, int sym, int occ_list) {
-  const int L = blockIdx.x, G = gridDim.x;  // G is a multiple of 8
-  const int logical = (L & 7) * (G >> 3) + (L >> 3);
-  const int sl = logical / tiles_per_sys, tile = logical - sl * tiles_per_sys;
+  int sl, tile;
+  xcd_slot_tile(blockIdx.x, tiles_per_sys, sl, tile);
   if (sl >= nl) return;
   const int si = list[sl];
   if (skip_done && bt.status[si] != 0) return;
@@ -626,9 +659,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
     k_gemm_f32(DevBatch bt, const int* list, int nl, int tiles_per_sys, const TA* __restrict__ Abase,
                const TB* __restrict__ Bbase, TC* __restrict__ Cbase, const double* __restrict__ wbase, int skip_done,
                int sym, int occ_list) {
-  const int L = blockIdx.x, G = gridDim.x;  // G is a multiple of 8
-  const int logical = (L & 7) * (G >> 3) + (L >> 3);
-  const int sl = logical / tiles_per_sys, tile = logical - sl * tiles_per_sys;
+  int sl, tile;
+  xcd_slot_tile(blockIdx.x, tiles_per_sys, sl, tile);
   if (sl >= nl) return;
   const int si = list[sl];
   if (skip_done && bt.status[si] != 0) return;
@@ -2126,9 +2158,8 @@ __global__ void __launch_bounds__(1024)
     k_apply_rot(DevBatch bt, const int* list, int nl, int tiles_per_sys, int tile_w,
                 const double2* __restrict__ logbuf, long long log_stride, const int* nlog) {
   extern __shared__ double2 lds_raw[];
-  const int Lid = blockIdx.x, G = gridDim.x;  // G is a multiple of 8
-  const int logical = (Lid & 7) * (G >> 3) + (Lid >> 3);
-  const int sl = logical / tiles_per_sys, tcol = logical - sl * tiles_per_sys;
+  int sl, tcol;
+  xcd_slot_tile(blockIdx.x, tiles_per_sys, sl, tcol);
   if (sl >= nl) return;
   const int si = list[sl];
   if (bt.status[si] != 0) return;

@@ -251,6 +251,37 @@ def test_graph_schedule_matches_batched(lib, which):
         assert r1["iters_dimer"] == r0["iters_dimer"]
 
 
+@pytest.mark.parametrize("which", ["c1", "pentacene6", "anthracene5"])
+def test_device_driven_matches_host_sync(lib, which):
+    """FX_BATCHED compacts the active list on the device and launches each
+    SCC iteration without waiting for the last one; FX_BATCHED_HOST_SYNC
+    compacts on the host after a synchronisation.  Energies, charges,
+    iteration counts and the gradient are bitwise identical, also on a
+    second run of the same context."""
+    _say(f"device-driven vs host-synced {which}")
+    if which == "c1":
+        s, order = w.water_cluster_cube(), 2
+    elif which == "pentacene6":
+        s, order = w.pentacene_crystal(reps=(2, 2, 1)).subset([0, 1, 2, 3, 4, 5]), 2
+    else:
+        s, order = w.anthracene_crystal(reps=(2, 2, 1), seed=3).subset([0, 1, 2, 3, 4]), 3
+    c = lib()
+    c.set_system(s.Z, s.xyz, s.frag, s.frag_charge)
+    c.set_options(want_gradient=1, order=order, schedule=3)
+    r0 = c.run()
+    e0, q0, g0 = c.energies(), c.charges(), c.gradient()
+    c.set_options(schedule=0)
+    for rep in range(2):
+        r1 = c.run()
+        assert r1["e_total"] == r0["e_total"]
+        for a, b in zip(e0, c.energies()):
+            assert np.array_equal(a, b)
+        assert np.array_equal(c.charges(), q0)
+        assert np.array_equal(c.gradient(), g0)
+        for k in ("iters_mono", "iters_dimer", "iters_trimer", "macro_iter"):
+            assert r1[k] == r0[k], k
+
+
 @pytest.mark.parametrize("which", ["c1", "pentacene6"])
 def test_mixed_precision_matches_fp64(lib, which):
     """FX_MIXED (FP32 Fock build and FP32 matrix-core products while an SCC
