@@ -313,8 +313,12 @@ struct Ctx {
   // numerical settings of the kernels
   int jacobi_max_sweeps = 40;
   double jacobi_tol = 1e-14;
-  double jacobi_thr_scale = 1e-3;
-  double jacobi_cap_err = 1e-9;
+  // rotations below thr_scale times the last SCC residual are skipped: at
+  // 1e-3 the orbitals of an iteration were off by a few per cent of the
+  // residual, which stalled the mixing of the slow dimers (C4: 43,497 dimer
+  // iterations, at most 26 per dimer; at 1e-5: 38,555, at most 16)
+  double jacobi_thr_scale = std::getenv("FX_JACOBI_THR_SCALE") ? std::atof(std::getenv("FX_JACOBI_THR_SCALE")) : 1e-5;
+  double jacobi_cap_err = std::getenv("FX_JACOBI_CAP_ERR") ? std::atof(std::getenv("FX_JACOBI_CAP_ERR")) : 1e-9;
   int jacobi_threads = std::getenv("FX_JACOBI_THREADS") ? std::atoi(std::getenv("FX_JACOBI_THREADS")) : 1024;
   // LDS-resident eigensolver (k_jacobi_lds) where the system fits; FX_JACOBI_LDS=0
   // selects the global-memory kernel everywhere
@@ -472,7 +476,7 @@ struct Ctx {
   // split eigensolver (rotation kernel + apply kernel) for single-sweep
   // iterations; FX_JACOBI_SPLIT=0 keeps the fused kernel everywhere
   bool jacobi_split = !(std::getenv("FX_JACOBI_SPLIT") && std::atoi(std::getenv("FX_JACOBI_SPLIT")) == 0);
-  int jacobi_max_log = 2;
+  int jacobi_max_log = std::getenv("FX_JACOBI_MAX_LOG") ? std::atoi(std::getenv("FX_JACOBI_MAX_LOG")) : 2;
   std::map<long long, JacobiPlan> tuned;
   static long long jp_key(int n, int elt) { return (long long)n * 16 + elt; }
   JacobiPlan autotune_jacobi(Batch& b, const int* dl, int na, const JacobiPlan& base, double cap);
