@@ -27,7 +27,7 @@ MI355X_FP64_PEAK_TFLOPS = 78.6
 # passes (FETCH_SIZE scaled by 2 and WRITE_SIZE by 1, the factors a 1 GiB
 # device copy gives), bytes per launch; valid while the kernel is unchanged
 # (profiles/k_apply_rot_pentacene_fmo2.md gives the commands)
-PMC_TRAFFIC_BYTES = {"fx::k_apply_rot": 734e6 + 365e6}
+PMC_TRAFFIC_BYTES = {"fx::k_apply_rot": 704e6 + 358e6}
 
 
 def scc_iteration_work(n, n_occ):
