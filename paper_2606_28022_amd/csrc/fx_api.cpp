@@ -433,7 +433,9 @@ void Ctx::init_device() {
   // rejects an oversized launch, which check() then reports)
   unsigned stat = 0;
   for (const void* k : {reinterpret_cast<const void*>(k_jacobi_lds<double>),
-                        reinterpret_cast<const void*>(k_jacobi_lds<float>)}) {
+                        reinterpret_cast<const void*>(k_jacobi_lds<float>),
+                        reinterpret_cast<const void*>(k_jacobi_rot<double>),
+                        reinterpret_cast<const void*>(k_jacobi_rot<float>)}) {
     hipFuncAttributes fa{};
     if (hipFuncGetAttributes(&fa, k) == hipSuccess) stat = std::max(stat, (unsigned)fa.sharedSizeBytes);
   }
@@ -453,6 +455,7 @@ void Ctx::init_device() {
                         reinterpret_cast<const void*>(k_cholinv_block2)})
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
   (void)hipGetLastError();
+  check(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device), "CU count query");
   noalloc_init(device);
   if (verbose) std::fprintf(stderr, "[fx] LDS per workgroup %d B, static %u B\n", v, stat);
 }
@@ -822,14 +825,8 @@ void Ctx::eigh_hot(const std::vector<int>& nv, const double* A, double* w, doubl
       b.rotlog.alloc((long long)nmat * log_stride);
       b.nlog.alloc(nmat);
       const unsigned lds_rot = jacobi_rot_layout(b.max_nao, jp.elt).total;
-      if (jp.elt == 8)
-        hipLaunchKernelGGL(k_jacobi_rot<double>, dim3(nmat), dim3(jp.threads), lds_rot, stream, db, b.d_list.p,
-                           jacobi_max_sweeps, jacobi_tol, jacobi_thr_scale, jacobi_cap_err, b.sweeps.p, b.rotlog.p,
-                           log_stride, jacobi_max_log, b.nlog.p);
-      else
-        hipLaunchKernelGGL(k_jacobi_rot<float>, dim3(nmat), dim3(jp.threads), lds_rot, stream, db, b.d_list.p,
-                           jacobi_max_sweeps, jacobi_tol, jacobi_thr_scale, jacobi_cap_err, b.sweeps.p, b.rotlog.p,
-                           log_stride, jacobi_max_log, b.nlog.p);
+      (void)lds_rot;
+      launch_rot(b, db, b.d_list.p, nmat, jp.elt, jacobi_cap_err, RotShape{jp.threads, false}, log_stride);
       const int tw = apply_rot_tile(b.max_nao);
       const int tps = (b.max_nao + tw - 1) / tw;
       const long long grid = xcd_grid(nmat, tps);
@@ -1036,16 +1033,9 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
       gemm_batch(b, db, n64, dl64, 1, b.Tm.p, b.Ct.p, b.Fm.p, nullptr, b.gemm_gflop_sym(a64), 1, 1);
     }
     if (split_ok && cap < 1e299) {
-      const unsigned lds_rot = jacobi_rot_layout(b.max_nao, jp.elt).total;
+      const RotShape rs = rot_shape(b, db, dl, na, jp, cap, log_stride, timed);
       int ev = timed ? timers.begin(stream) : -1;
-      if (jp.elt == 8)
-        hipLaunchKernelGGL(k_jacobi_rot<double>, dim3(na), dim3(jp.threads), lds_rot, stream, db, dl,
-                           jacobi_max_sweeps, jacobi_tol, jacobi_thr_scale, cap, b.sweeps.p, b.rotlog.p, log_stride,
-                           jacobi_max_log, b.nlog.p);
-      else
-        hipLaunchKernelGGL(k_jacobi_rot<float>, dim3(na), dim3(jp.threads), lds_rot, stream, db, dl,
-                           jacobi_max_sweeps, jacobi_tol, jacobi_thr_scale, cap, b.sweeps.p, b.rotlog.p, log_stride,
-                           jacobi_max_log, b.nlog.p);
+      launch_rot(b, db, dl, na, jp.elt, cap, rs, log_stride);
       if (timed) timers.end(stream, ev, kt_rot, 0.0);
       const int tw = apply_rot_tile(b.max_nao);
       const int tps = (b.max_nao + tw - 1) / tw;
@@ -1324,6 +1314,82 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
   }
   if (iters_out) *iters_out += iters;
   return single ? 0 : failed;
+}
+
+// The rotation kernel over the na systems listed in dl, one work-group per
+// system or a persistent grid over a work queue (rs.persistent: as many
+// work-groups as fit on the device at once, fed by an atomic counter)
+void Ctx::launch_rot(const Batch& b, const DevBatch& db, const int* dl, int na, int elt, double cap,
+                     const RotShape& rs, long long log_stride) {
+  const unsigned lds_rot = jacobi_rot_layout(b.max_nao, elt).total;
+  const void* fn = elt == 8 ? reinterpret_cast<const void*>(k_jacobi_rot<double>)
+                            : reinterpret_cast<const void*>(k_jacobi_rot<float>);
+  int grid = na, nl = 0;
+  int* queue = nullptr;
+  if (rs.persistent) {
+    int per_cu = 0;
+    check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, rs.threads, lds_rot), "occupancy query");
+    grid = std::min(na, std::max(1, per_cu) * std::max(1, n_cu));
+    if (rot_queue.n < 1) rot_queue.alloc(1);
+    queue = rot_queue.p;
+    nl = na;
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, stream, queue);
+  }
+  if (elt == 8)
+    hipLaunchKernelGGL(k_jacobi_rot<double>, dim3(grid), dim3(rs.threads), lds_rot, stream, db, dl, jacobi_max_sweeps,
+                       jacobi_tol, jacobi_thr_scale, cap, b.sweeps.p, b.rotlog.p, log_stride, jacobi_max_log,
+                       b.nlog.p, queue, nl);
+  else
+    hipLaunchKernelGGL(k_jacobi_rot<float>, dim3(grid), dim3(rs.threads), lds_rot, stream, db, dl, jacobi_max_sweeps,
+                       jacobi_tol, jacobi_thr_scale, cap, b.sweeps.p, b.rotlog.p, log_stride, jacobi_max_log,
+                       b.nlog.p, queue, nl);
+  check(hipGetLastError(), "k_jacobi_rot");
+}
+
+// Launch shape of the rotation kernel for this size bucket: forced by the
+// environment, tuned once per bucket by timing every candidate on the
+// current iteration's input (the kernel only reads the working matrix, and
+// every shape writes bitwise the same log and eigenvalues, so the timing
+// launches change nothing), or the plan's default when tuning is off
+Ctx::RotShape Ctx::rot_shape(Batch& b, const DevBatch& db, const int* dl, int na, const JacobiPlan& jp, double cap,
+                             long long log_stride, bool may_tune) {
+  RotShape def{jp.threads, false};
+  if (force_rot_threads > 0 || force_rot_persistent >= 0) {
+    RotShape f = def;
+    if (force_rot_threads > 0) f.threads = force_rot_threads;
+    if (force_rot_persistent >= 0) f.persistent = force_rot_persistent != 0;
+    return f;
+  }
+  const long long key = jp_key(b.max_nao, jp.elt);
+  auto it = tuned_rot.find(key);
+  if (it != tuned_rot.end()) return it->second;
+  if (!autotune || !may_tune || capturing) return def;
+  hipEvent_t e0, e1;
+  check(hipEventCreate(&e0), "event");
+  check(hipEventCreate(&e1), "event");
+  RotShape best = def;
+  float best_ms = 1e30f;
+  for (int t : {256, 512, 768, 1024})
+    for (int p = 0; p < 2; ++p) {
+      const RotShape c{t, p != 0};
+      check(hipEventRecord(e0, stream), "event");
+      launch_rot(b, db, dl, na, jp.elt, cap, c, log_stride);
+      check(hipEventRecord(e1, stream), "event");
+      check(hipEventSynchronize(e1), "event");
+      float ms = 0.0f;
+      check(hipEventElapsedTime(&ms, e0, e1), "event");
+      if (verbose)
+        std::fprintf(stderr, "[fx] autotune rotation kernel n<=%d: %d threads%s: %.3f ms\n", b.max_nao, t,
+                     p ? " persistent" : "", ms);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  tuned_rot[key] = best;
+  return best;
 }
 
 void Ctx::count_ring_init() {

@@ -479,6 +479,23 @@ struct Ctx {
   int jacobi_max_log = std::getenv("FX_JACOBI_MAX_LOG") ? std::atoi(std::getenv("FX_JACOBI_MAX_LOG")) : 2;
   std::map<long long, JacobiPlan> tuned;
   static long long jp_key(int n, int elt) { return (long long)n * 16 + elt; }
+  // launch shape of the rotation kernel per size bucket: work-group size and
+  // the persistent work-queue form (FX_JACOBI_ROT_THREADS and
+  // FX_JACOBI_ROT_PERSISTENT force one; otherwise tuned by timing)
+  struct RotShape {
+    int threads = 0;
+    bool persistent = false;
+  };
+  std::map<long long, RotShape> tuned_rot;
+  int force_rot_threads = std::getenv("FX_JACOBI_ROT_THREADS") ? std::atoi(std::getenv("FX_JACOBI_ROT_THREADS")) : 0;
+  int force_rot_persistent =
+      std::getenv("FX_JACOBI_ROT_PERSISTENT") ? std::atoi(std::getenv("FX_JACOBI_ROT_PERSISTENT")) : -1;
+  DevBuf<int> rot_queue;
+  int n_cu = 1;
+  void launch_rot(const Batch& b, const DevBatch& db, const int* dl, int na, int elt, double cap, const RotShape& rs,
+                  long long log_stride);
+  RotShape rot_shape(Batch& b, const DevBatch& db, const int* dl, int na, const JacobiPlan& jp, double cap,
+                     long long log_stride, bool may_tune);
   JacobiPlan autotune_jacobi(Batch& b, const int* dl, int na, const JacobiPlan& base, double cap);
   void gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlist, int mode, const double* A,
                   const double* B, double* C, const double* w, double gflop, int skip_done = 0, int sym = 0,

@@ -124,7 +124,8 @@ constexpr int CHOL_THREADS_HOST = 1024;
 template <typename T>
 __global__ void k_jacobi_rot(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale,
                              double cap_err, int* sweeps_out, double2* logbuf, long long log_stride, int max_log,
-                             int* nlog);
+                             int* nlog, int* queue, int nl);
+__global__ void k_queue_reset(int* queue);
 __global__ void k_apply_rot(DevBatch bt, const int* list, int nl, int tiles_per_sys, int tile_w,
                             const double2* logbuf, long long log_stride, const int* nlog);
 template <typename T>

@@ -1947,14 +1947,14 @@ __device__ inline void jq_block(int a, int b, int nq, int bf, typename JtVec<T>:
   jt_offdiag<T>(At, qa, qb, ra, rb, wa, wb);
 }
 
+// The sweeps of one system by the whole work-group (k_jacobi_rot).
 template <typename T>
-__global__ void __launch_bounds__(1024)
-    k_jacobi_rot(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale, double cap_err,
-                 int* sweeps_out, double2* logbuf, long long log_stride, int max_log, int* nlog) {
+__device__ inline void jacobi_rot_system(const DevBatch& bt, int si, int max_sweeps, double rel_tol, double thr_scale,
+                                         double cap_err, int* sweeps_out, double2* logbuf, long long log_stride,
+                                         int max_log, int* nlog) {
   typedef typename JtVec<T>::type V4;
   extern __shared__ double2 lds_raw[];
   unsigned char* lds = reinterpret_cast<unsigned char*>(lds_raw);
-  const int si = list[blockIdx.x];
   if (bt.status[si] != 0) return;
   const SysDesc d = bt.desc[si];
   const int n = d.nao;
@@ -2110,10 +2110,41 @@ __global__ void __launch_bounds__(1024)
   }
 }
 
+// One work-group per listed system (queue == nullptr), or a persistent grid
+// whose work-groups take list slots from the work queue *queue (zeroed by
+// k_queue_reset before the launch) until all nl are taken.  Either way each
+// system is swept by one work-group from start to end, so the results do
+// not depend on the form or on the work-group size.
+template <typename T>
+__global__ void __launch_bounds__(1024)
+    k_jacobi_rot(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale, double cap_err,
+                 int* sweeps_out, double2* logbuf, long long log_stride, int max_log, int* nlog, int* queue,
+                 int nl) {
+  if (queue == nullptr) {
+    jacobi_rot_system<T>(bt, list[blockIdx.x], max_sweeps, rel_tol, thr_scale, cap_err, sweeps_out, logbuf,
+                         log_stride, max_log, nlog);
+    return;
+  }
+  __shared__ int slot_sh;
+  for (;;) {
+    __syncthreads();  // the previous system's LDS is no longer read
+    if (threadIdx.x == 0) slot_sh = atomicAdd(queue, 1);
+    __syncthreads();
+    const int slot = slot_sh;
+    if (slot >= nl) break;
+    jacobi_rot_system<T>(bt, list[slot], max_sweeps, rel_tol, thr_scale, cap_err, sweeps_out, logbuf, log_stride,
+                         max_log, nlog);
+  }
+}
+
+__global__ void k_queue_reset(int* queue) {
+  if (threadIdx.x == 0) *queue = 0;
+}
+
 template __global__ void k_jacobi_rot<double>(DevBatch, const int*, int, double, double, double, int*, double2*,
-                                              long long, int, int*);
+                                              long long, int, int*, int*, int);
 template __global__ void k_jacobi_rot<float>(DevBatch, const int*, int, double, double, double, int*, double2*,
-                                             long long, int, int*);
+                                             long long, int, int*, int*, int);
 
 // Apply the logged rotations to the rows of C^T, one 64-column tile per
 // work-group and four columns per wave.  Lane q holds, for the wave's four

@@ -282,6 +282,42 @@ def test_device_driven_matches_host_sync(lib, which):
             assert r1[k] == r0[k], k
 
 
+def test_rotation_kernel_shapes_bitwise(lib):
+    """The rotation kernel's launch shapes (work-group size; one work-group
+    per system or the persistent work-queue grid) that the tuner chooses
+    among give bitwise identical energies, charges and gradients (six
+    pentacenes: 232-AO dimers with the FP32 working matrix, 116-AO monomers
+    with the FP64 one)."""
+    import os
+    s = w.pentacene_crystal(reps=(2, 2, 1)).subset([0, 1, 2, 3, 4, 5])
+    out = {}
+    for t, p in [(0, -1), (256, 0), (512, 1), (768, 0), (1024, 1)]:
+        _say(f"rotation kernel {t} threads, persistent {p}")
+        env = {"FX_JACOBI_ROT_THREADS": str(t), "FX_JACOBI_ROT_PERSISTENT": str(p)} if t else {}
+        old = {k: os.environ.get(k) for k in ("FX_JACOBI_ROT_THREADS", "FX_JACOBI_ROT_PERSISTENT")}
+        os.environ.update(env)
+        try:
+            c = lib()
+        finally:
+            for k, v in old.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+        c.set_system(s.Z, s.xyz, s.frag, s.frag_charge)
+        c.set_options(want_gradient=1)
+        r = c.run()
+        out[(t, p)] = (r["e_total"], c.energies(), c.charges(), c.gradient(), r["iters_dimer"])
+    ref = out[(0, -1)]
+    for k, v in out.items():
+        assert v[0] == ref[0], k
+        for a, b in zip(v[1], ref[1]):
+            assert np.array_equal(a, b), k
+        assert np.array_equal(v[2], ref[2]), k
+        assert np.array_equal(v[3], ref[3]), k
+        assert v[4] == ref[4], k
+
+
 @pytest.mark.parametrize("which", ["c1", "pentacene6"])
 def test_mixed_precision_matches_fp64(lib, which):
     """FX_MIXED (FP32 Fock build and FP32 matrix-core products while an SCC
