@@ -1335,14 +1335,17 @@ void Ctx::launch_rot(const Batch& b, const DevBatch& db, const int* dl, int na, 
     nl = na;
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, stream, queue);
   }
+  // (monomers start each solve from exact eigenvectors: one sweep)
+  const int es = std::min(jacobi_early_sweeps, jacobi_max_log);
+  const double ee = b.init_from_mono ? jacobi_early_err : 1e300;
   if (elt == 8)
     hipLaunchKernelGGL(k_jacobi_rot<double>, dim3(grid), dim3(rs.threads), lds_rot, stream, db, dl, jacobi_max_sweeps,
-                       jacobi_tol, jacobi_thr_scale, cap, b.sweeps.p, b.rotlog.p, log_stride, jacobi_max_log,
-                       b.nlog.p, queue, nl);
+                       jacobi_tol, jacobi_thr_scale, cap, ee, es, b.sweeps.p, b.rotlog.p, log_stride,
+                       jacobi_max_log, b.nlog.p, queue, nl);
   else
     hipLaunchKernelGGL(k_jacobi_rot<float>, dim3(grid), dim3(rs.threads), lds_rot, stream, db, dl, jacobi_max_sweeps,
-                       jacobi_tol, jacobi_thr_scale, cap, b.sweeps.p, b.rotlog.p, log_stride, jacobi_max_log,
-                       b.nlog.p, queue, nl);
+                       jacobi_tol, jacobi_thr_scale, cap, ee, es, b.sweeps.p, b.rotlog.p, log_stride,
+                       jacobi_max_log, b.nlog.p, queue, nl);
   check(hipGetLastError(), "k_jacobi_rot");
 }
 

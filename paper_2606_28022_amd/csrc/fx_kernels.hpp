@@ -123,8 +123,8 @@ size_t cholinv_block2_lds_bytes(int n1, int n2);
 constexpr int CHOL_THREADS_HOST = 1024;
 template <typename T>
 __global__ void k_jacobi_rot(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale,
-                             double cap_err, int* sweeps_out, double2* logbuf, long long log_stride, int max_log,
-                             int* nlog, int* queue, int nl);
+                             double cap_err, double early_err, int early_sweeps, int* sweeps_out, double2* logbuf,
+                             long long log_stride, int max_log, int* nlog, int* queue, int nl);
 __global__ void k_queue_reset(int* queue);
 __global__ void k_apply_rot(DevBatch bt, const int* list, int nl, int tiles_per_sys, int tile_w,
                             const double2* logbuf, long long log_stride, const int* nlog);

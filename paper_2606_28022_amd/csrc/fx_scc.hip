@@ -1236,6 +1236,9 @@ __global__ void k_charges_mix(DevSystem sys, DevBatch bt, const int* list, doubl
   int m = nh < HIST ? nh : HIST;
   __syncthreads();
   if (m == 1) {
+    // first step: plain, on the raw residual (a first step along the Newton
+    // direction converged the C4 dimers no faster: 40,252 iterations against
+    // 38,555; the plain step adds a second direction to the history)
     double* qn = bt.q_in + d.sh_off;
     for (int s = threadIdx.x; s < ns; s += blockDim.x) qn[s] = qi[s] + beta * (qo[s] - qi[s]);
   } else {
@@ -1719,16 +1722,30 @@ __device__ inline void tri_pair(int idx, int N, int& a, int& b) {
 }
 
 // Jacobi rotation zeroing a_pq of a symmetric matrix: (c, s, t), identity if
-// |a_pq| is below the threshold
+// |a_pq| is below the threshold.  t is the smaller root of
+// t^2 + 2 theta t - 1 = 0, theta = (a_qq - a_pp) / (2 a_pq), written as
+// t = sign(theta) |y| / (|tau| + sqrt(tau^2 + y^2)) with tau = a_qq - a_pp and
+// y = 2 a_pq, so that no quotient by a_pq is formed.  The reciprocal and the
+// reciprocal square roots are hardware estimates refined by Newton steps
+// (full FP64 precision).  An error in t would only turn the angle slightly;
+// c = (1 + t^2)^(-1/2) and s = t c keep c^2 + s^2 = 1 to rounding whatever t
+// is, so the basis stays orthonormal.
 __device__ inline void jq_angle(double app, double aqq, double apq, double thr, double rel_tol, double& c, double& s,
                                 double& t) {
   c = 1.0;
   s = 0.0;
   t = 0.0;
   if (fabs(apq) > fmax(thr, rel_tol * fmax(fabs(app), fabs(aqq)))) {
-    const double theta = (aqq - app) / (2.0 * apq);
-    t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-    c = 1.0 / sqrt(t * t + 1.0);
+    const double tau = aqq - app, y = 2.0 * apq;
+    const double h = fma(tau, tau, y * y);  // > 0, since y != 0
+    const double dd = fabs(tau) + h * rsqrt_pos(h);
+    double r = __builtin_amdgcn_rcp(dd);
+    r = r * fma(-dd, r, 2.0);
+    r = r * fma(-dd, r, 2.0);
+    // sign(theta), theta = tau / y; +1 when tau is zero
+    const bool pos = tau == 0.0 || ((tau > 0.0) == (y > 0.0));
+    t = (pos ? fabs(y) : -fabs(y)) * r;
+    c = rsqrt_pos(fma(t, t, 1.0));
     s = t * c;
   }
 }
@@ -1776,14 +1793,24 @@ __device__ inline void jq_cols(T (&B)[4][4], T c, T s) {
 }
 
 // The working matrix is held as 2 x 2 tiles of the upper block triangle
-// (blocks {2k, 2k+1}): tile (a, b), a <= b, at jt_index(a, b) holds
-// A(2a + i, 2b + j) in component 2 i + j (x, y, z, w); a diagonal tile keeps
-// only its y component, A(2a, 2a + 1) (the diagonal itself is held in FP64
-// apart).  Padded rows and columns are stored as zeros and stay zero, since
-// every rotation that involves a padded index is the identity, so no access
-// needs a padding test.  A 4 x 4 block between two quartets is four tiles:
-// four 16-byte (FP32) or 32-byte (FP64) LDS accesses each way.
-__device__ inline int jt_index(int a, int b) { return b * (b + 1) / 2 + a; }
+// (N blocks {2k, 2k+1}, N even): tile (a, b), a <= b, at jt_index(a, b, N)
+// holds A(2a + i, 2b + j) in component 2 i + j (x, y, z, w); a diagonal tile
+// keeps only its y component, A(2a, 2a + 1) (the diagonal itself is held in
+// FP64 apart).  Padded rows and columns are stored as zeros and stay zero,
+// since every rotation that involves a padded index is the identity, so no
+// access needs a padding test.  A 4 x 4 block between two quartets is four
+// tiles: four 16-byte (FP32) or 32-byte (FP64) LDS accesses each way.
+// The triangle is stored in rectangular full packed order: N / 2 rows of
+// R = N + 1 tiles, row k holding column b = N / 2 + k forwards (tiles
+// a = 0..b from the row's start) and column N / 2 - 1 - k backwards (tile a
+// at R - 1 - a).  Neighbouring a, or neighbouring b, are then 1 or R (odd)
+// tiles apart, so the lanes of a quarter-wave that step either index reach
+// distinct LDS banks; the column-major triangle (b (b + 1) / 2 + a) put
+// lanes that step b at triangular-number offsets that collided.
+__device__ inline int jt_index(int a, int b, int N) {
+  const int h = N >> 1, R = N + 1;
+  return b >= h ? (b - h) * R + a : (h - 1 - b) * R + (R - 1 - a);
+}
 
 template <typename T>
 struct JtVec;
@@ -1798,36 +1825,39 @@ struct JtVec<double> {
 
 // 2 x 2 block of rows of block rb and columns of block cb, rb != cb
 template <typename T>
-__device__ inline void jt_get(const typename JtVec<T>::type* At, int rb, int cb, T& e00, T& e01, T& e10, T& e11) {
+__device__ inline void jt_get(const typename JtVec<T>::type* At, int rb, int cb, int N, T& e00, T& e01, T& e10,
+                              T& e11) {
   const bool tr = rb > cb;
-  const typename JtVec<T>::type v = At[jt_index(min(rb, cb), max(rb, cb))];
+  const typename JtVec<T>::type v = At[jt_index(min(rb, cb), max(rb, cb), N)];
   e00 = v.x;
   e11 = v.w;
   e01 = tr ? v.z : v.y;
   e10 = tr ? v.y : v.z;
 }
 template <typename T>
-__device__ inline void jt_put(typename JtVec<T>::type* At, int rb, int cb, T e00, T e01, T e10, T e11) {
+__device__ inline void jt_put(typename JtVec<T>::type* At, int rb, int cb, int N, T e00, T e01, T e10, T e11) {
   const bool tr = rb > cb;
   typename JtVec<T>::type v;
   v.x = e00;
   v.w = e11;
   v.y = tr ? e10 : e01;
   v.z = tr ? e01 : e10;
-  At[jt_index(min(rb, cb), max(rb, cb))] = v;
+  At[jt_index(min(rb, cb), max(rb, cb), N)] = v;
 }
 
 // the four (c, s) of quartet q in the working precision: FP32 from the packed
-// float copy (two 16-byte reads), FP64 from the double2 entries
+// float copy (two 16-byte reads, the halves of all quartets stored apart so
+// that neighbouring quartets are 16 bytes apart), FP64 from the double2
+// entries
 template <typename T>
-__device__ inline void jq_params(const double2* cs, const float4* csf, int q, T (&w)[8]);
+__device__ inline void jq_params(const double2* cs, const float4* csf, int q, int nq, T (&w)[8]);
 template <>
-__device__ inline void jq_params<float>(const double2*, const float4* csf, int q, float (&w)[8]) {
-  const float4 u = csf[2 * q], v = csf[2 * q + 1];
+__device__ inline void jq_params<float>(const double2*, const float4* csf, int q, int nq, float (&w)[8]) {
+  const float4 u = csf[q], v = csf[nq + q];
   w[0] = u.x, w[1] = u.y, w[2] = u.z, w[3] = u.w, w[4] = v.x, w[5] = v.y, w[6] = v.z, w[7] = v.w;
 }
 template <>
-__device__ inline void jq_params<double>(const double2* cs, const float4*, int q, double (&w)[8]) {
+__device__ inline void jq_params<double>(const double2* cs, const float4*, int q, int, double (&w)[8]) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const double2 u = cs[4 * q + k];
@@ -1840,14 +1870,14 @@ __device__ inline void jq_params<double>(const double2* cs, const float4*, int q
 // qa (X | Y << 16), columns of the quartet qb; rows take that quartet's two
 // steps (x1 y1, x2 y2, then x1 y2, x2 y1), columns the other's.
 template <typename T>
-__device__ inline void jt_offdiag(typename JtVec<T>::type* At, int qa, int qb, bool ra, bool rb, const T (&wa)[8],
-                                  const T (&wb)[8]) {
+__device__ inline void jt_offdiag(typename JtVec<T>::type* At, int N, int qa, int qb, bool ra, bool rb,
+                                  const T (&wa)[8], const T (&wb)[8]) {
   const int Xa = qa & 0xffff, Ya = (qa >> 16) & 0x7fff, Xb = qb & 0xffff, Yb = (qb >> 16) & 0x7fff;
   T B[4][4];
-  jt_get<T>(At, Xa, Xb, B[0][0], B[0][1], B[1][0], B[1][1]);
-  jt_get<T>(At, Xa, Yb, B[0][2], B[0][3], B[1][2], B[1][3]);
-  jt_get<T>(At, Ya, Xb, B[2][0], B[2][1], B[3][0], B[3][1]);
-  jt_get<T>(At, Ya, Yb, B[2][2], B[2][3], B[3][2], B[3][3]);
+  jt_get<T>(At, Xa, Xb, N, B[0][0], B[0][1], B[1][0], B[1][1]);
+  jt_get<T>(At, Xa, Yb, N, B[0][2], B[0][3], B[1][2], B[1][3]);
+  jt_get<T>(At, Ya, Xb, N, B[2][0], B[2][1], B[3][0], B[3][1]);
+  jt_get<T>(At, Ya, Yb, N, B[2][2], B[2][3], B[3][2], B[3][3]);
   if (ra) {
     jq_rows<0, 2>(B, wa[0], wa[1]);
     jq_rows<1, 3>(B, wa[2], wa[3]);
@@ -1860,10 +1890,10 @@ __device__ inline void jt_offdiag(typename JtVec<T>::type* At, int qa, int qb, b
     jq_cols<0, 3>(B, wb[4], wb[5]);
     jq_cols<1, 2>(B, wb[6], wb[7]);
   }
-  jt_put<T>(At, Xa, Xb, B[0][0], B[0][1], B[1][0], B[1][1]);
-  jt_put<T>(At, Xa, Yb, B[0][2], B[0][3], B[1][2], B[1][3]);
-  jt_put<T>(At, Ya, Xb, B[2][0], B[2][1], B[3][0], B[3][1]);
-  jt_put<T>(At, Ya, Yb, B[2][2], B[2][3], B[3][2], B[3][3]);
+  jt_put<T>(At, Xa, Xb, N, B[0][0], B[0][1], B[1][0], B[1][1]);
+  jt_put<T>(At, Xa, Yb, N, B[0][2], B[0][3], B[1][2], B[1][3]);
+  jt_put<T>(At, Ya, Xb, N, B[2][0], B[2][1], B[3][0], B[3][1]);
+  jt_put<T>(At, Ya, Yb, N, B[2][2], B[2][3], B[3][2], B[3][3]);
 }
 
 // The two steps of round rd on quartet qd's own 4 x 4 block (rotation angles
@@ -1875,10 +1905,10 @@ __device__ inline bool jq_quartet(int qd, int rd, int n, int nb2, int nq, int b,
                                   double2* lr) {
   const int X = rr_fast(qd, rd, nb2), Y = rr_fast(nb2 - 1 - qd, rd, nb2);
   const int ix[4] = {2 * X, 2 * X + 1, 2 * Y, 2 * Y + 1};
-  T* ex = Ae + 4 * jt_index(X, X) + 1;
-  T* ey = Ae + 4 * jt_index(Y, Y) + 1;
+  T* ex = Ae + 4 * jt_index(X, X, nb2) + 1;
+  T* ey = Ae + 4 * jt_index(Y, Y, nb2) + 1;
   T e00, e01, e10, e11;
-  jt_get<T>(At, X, Y, e00, e01, e10, e11);
+  jt_get<T>(At, X, Y, nb2, e00, e01, e10, e11);
   double M[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) M[i][i] = dg[ix[i]];
@@ -1911,14 +1941,14 @@ __device__ inline bool jq_quartet(int qd, int rd, int n, int nb2, int nq, int b,
     for (int i = 0; i < 4; ++i) dg[ix[i]] = M[i][i];
     *ex = (T)M[0][1];
     *ey = (T)M[2][3];
-    jt_put<T>(At, X, Y, (T)M[0][2], (T)M[0][3], (T)M[1][2], (T)M[1][3]);
+    jt_put<T>(At, X, Y, nb2, (T)M[0][2], (T)M[0][3], (T)M[1][2], (T)M[1][3]);
   }
   qr[b * nq + qd] = X | (Y << 16) | (rot ? (int)0x80000000u : 0);
   const double2 w0 = make_double2(c0, s0), w1 = make_double2(c1, s1), w2 = make_double2(c2, s2),
                 w3 = make_double2(c3, s3);
   if (sizeof(T) == 4) {
-    csf[2 * (b * nq + qd)] = make_float4((float)c0, (float)s0, (float)c1, (float)s1);
-    csf[2 * (b * nq + qd) + 1] = make_float4((float)c2, (float)s2, (float)c3, (float)s3);
+    csf[2 * b * nq + qd] = make_float4((float)c0, (float)s0, (float)c1, (float)s1);
+    csf[2 * b * nq + nq + qd] = make_float4((float)c2, (float)s2, (float)c3, (float)s3);
   } else {
     double2* cb = cs + 4 * (b * nq + qd);
     cb[0] = w0;
@@ -1942,16 +1972,16 @@ __device__ inline void jq_block(int a, int b, int nq, int bf, typename JtVec<T>:
   const bool ra = qa < 0, rb = qb < 0;
   if (!ra && !rb) return;
   T wa[8], wb[8];
-  jq_params<T>(cs + 4 * bf * nq, csf + 2 * bf * nq, a, wa);
-  jq_params<T>(cs + 4 * bf * nq, csf + 2 * bf * nq, b, wb);
-  jt_offdiag<T>(At, qa, qb, ra, rb, wa, wb);
+  jq_params<T>(cs + 4 * bf * nq, csf + 2 * bf * nq, a, nq, wa);
+  jq_params<T>(cs + 4 * bf * nq, csf + 2 * bf * nq, b, nq, wb);
+  jt_offdiag<T>(At, 2 * nq, qa, qb, ra, rb, wa, wb);
 }
 
 // The sweeps of one system by the whole work-group (k_jacobi_rot).
 template <typename T>
 __device__ inline void jacobi_rot_system(const DevBatch& bt, int si, int max_sweeps, double rel_tol, double thr_scale,
-                                         double cap_err, int* sweeps_out, double2* logbuf, long long log_stride,
-                                         int max_log, int* nlog) {
+                                         double cap_err, double early_err, int early_sweeps, int* sweeps_out,
+                                         double2* logbuf, long long log_stride, int max_log, int* nlog) {
   typedef typename JtVec<T>::type V4;
   extern __shared__ double2 lds_raw[];
   unsigned char* lds = reinterpret_cast<unsigned char*>(lds_raw);
@@ -1991,7 +2021,7 @@ __device__ inline void jacobi_rot_system(const DevBatch& bt, int si, int max_swe
     if (i == j)
       dg[i] = v;
     else
-      Ae[4 * jt_index(i >> 1, j >> 1) + 2 * (i & 1) + (j & 1)] = (T)v;
+      Ae[4 * jt_index(i >> 1, j >> 1, nb2) + 2 * (i & 1) + (j & 1)] = (T)v;
   }
   for (int i = threadIdx.x; i < n; i += nt) {
     double r = 0.0;
@@ -2011,7 +2041,11 @@ __device__ inline void jacobi_rot_system(const DevBatch& bt, int si, int max_swe
   const double fro = red[0];
   const double err = bt.err[si];
   const double thr = fmax(rel_tol * (fro > 0.0 ? fro : 1.0), thr_scale * err);
-  const int msw = min(max_log, err > cap_err ? 1 : max_sweeps);
+  // sweeps of this SCC iteration: early_sweeps while the SCC residual
+  // exceeds early_err (the first iterations, where the working matrix still
+  // carries large couplings), then one, and to convergence once the residual
+  // is below cap_err
+  const int msw = min(max_log, err > early_err ? early_sweeps : err > cap_err ? 1 : max_sweeps);
   const long long swe = jq_sweep_entries(m);
   const int nblk = nb2 * (nb2 - 1) / 2, nqp = nq * (nq - 1) / 2;
   int sweep = 0;
@@ -2024,7 +2058,7 @@ __device__ inline void jacobi_rot_system(const DevBatch& bt, int si, int max_swe
       const int p = 2 * k, q = p + 1;
       double c = 1.0, s = 0.0, t = 0.0;
       if (q < n) {
-        T* e01 = Ae + 4 * jt_index(k, k) + 1;
+        T* e01 = Ae + 4 * jt_index(k, k, nb2) + 1;
         const double apq = (double)*e01, app = dg[p], aqq = dg[q];
         jq_angle(app, aqq, apq, thr, rel_tol, c, s, t);
         if (s != 0.0) {
@@ -2046,14 +2080,14 @@ __device__ inline void jacobi_rot_system(const DevBatch& bt, int si, int max_swe
       const double2 wa = cs[a], wb = cs[b];
       if (wa.y == 0.0 && wb.y == 0.0) continue;
       const T ca = (T)wa.x, sa = (T)wa.y, cb = (T)wb.x, sb = (T)wb.y;
-      V4 v = At[jt_index(a, b)];
+      V4 v = At[jt_index(a, b, nb2)];
       const T tpr = ca * v.x - sa * v.z, tpu = ca * v.y - sa * v.w;
       const T tqr = sa * v.x + ca * v.z, tqu = sa * v.y + ca * v.w;
       v.x = cb * tpr - sb * tpu;
       v.y = sb * tpr + cb * tpu;
       v.z = cb * tqr - sb * tqu;
       v.w = sb * tqr + cb * tqu;
-      At[jt_index(a, b)] = v;
+      At[jt_index(a, b, nb2)] = v;
     }
     __syncthreads();
     // Rounds.  Round rd's quartet solves use parameter buffer rd & 1.  In
@@ -2118,11 +2152,11 @@ __device__ inline void jacobi_rot_system(const DevBatch& bt, int si, int max_swe
 template <typename T>
 __global__ void __launch_bounds__(1024)
     k_jacobi_rot(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale, double cap_err,
-                 int* sweeps_out, double2* logbuf, long long log_stride, int max_log, int* nlog, int* queue,
-                 int nl) {
+                 double early_err, int early_sweeps, int* sweeps_out, double2* logbuf, long long log_stride,
+                 int max_log, int* nlog, int* queue, int nl) {
   if (queue == nullptr) {
-    jacobi_rot_system<T>(bt, list[blockIdx.x], max_sweeps, rel_tol, thr_scale, cap_err, sweeps_out, logbuf,
-                         log_stride, max_log, nlog);
+    jacobi_rot_system<T>(bt, list[blockIdx.x], max_sweeps, rel_tol, thr_scale, cap_err, early_err, early_sweeps,
+                         sweeps_out, logbuf, log_stride, max_log, nlog);
     return;
   }
   __shared__ int slot_sh;
@@ -2132,8 +2166,8 @@ __global__ void __launch_bounds__(1024)
     __syncthreads();
     const int slot = slot_sh;
     if (slot >= nl) break;
-    jacobi_rot_system<T>(bt, list[slot], max_sweeps, rel_tol, thr_scale, cap_err, sweeps_out, logbuf, log_stride,
-                         max_log, nlog);
+    jacobi_rot_system<T>(bt, list[slot], max_sweeps, rel_tol, thr_scale, cap_err, early_err, early_sweeps,
+                         sweeps_out, logbuf, log_stride, max_log, nlog);
   }
 }
 
@@ -2141,10 +2175,10 @@ __global__ void k_queue_reset(int* queue) {
   if (threadIdx.x == 0) *queue = 0;
 }
 
-template __global__ void k_jacobi_rot<double>(DevBatch, const int*, int, double, double, double, int*, double2*,
-                                              long long, int, int*, int*, int);
-template __global__ void k_jacobi_rot<float>(DevBatch, const int*, int, double, double, double, int*, double2*,
-                                             long long, int, int*, int*, int);
+template __global__ void k_jacobi_rot<double>(DevBatch, const int*, int, double, double, double, double, int, int*,
+                                              double2*, long long, int, int*, int*, int);
+template __global__ void k_jacobi_rot<float>(DevBatch, const int*, int, double, double, double, double, int, int*,
+                                             double2*, long long, int, int*, int*, int);
 
 // Apply the logged rotations to the rows of C^T, one 64-column tile per
 // work-group and four columns per wave.  Lane q holds, for the wave's four
