@@ -340,6 +340,7 @@ void Ctx::build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters,
   b.d_atom_ao0.upload(atom_ao0);
   b.d_atom_sh0.upload(atom_sh0);
   b.d_sh_global.upload(sh_global);
+  b.h_sh_global = sh_global;
   b.d_sh_atom.upload(sh_atom);
   b.d_ao_sh.upload(ao_sh);
   b.S.alloc(mat);
@@ -1096,6 +1097,22 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     d_act.alloc(nl);
     check(hipMemcpyAsync(d_act.p, b.d_list.p, sizeof(int) * nl, hipMemcpyDeviceToDevice, stream), "copy");
   }
+  // launch shape of the fused LDS eigensolver, tuned once per size bucket on
+  // the first iteration that runs it (the cold iteration of a solve from the
+  // Cholesky basis when the split form is on, else the second iteration):
+  // this iteration's A is formed once and every shape is timed on copies of
+  // (A, C^T); all shapes give bitwise identical results
+  auto want_tune = [&](int it) {
+    if (!autotune || capturing || jp.elt == 0 || tuned.count(jp_key(b.max_nao, jp.elt))) return false;
+    return split_ok ? (it == 0 && cold && !b.init_from_mono) : it == 1;
+  };
+  auto tune_fused = [&](const int* dl, int na, double cap) {
+    hipLaunchKernelGGL(k_fock, dim3(na), dim3(256), 0, stream, ds, db, dl);
+    gemm_batch(b, db, na, dl, 0, b.Ct.p, b.Fm.p, b.Tm.p, nullptr, 0.0, 1);
+    gemm_batch(b, db, na, dl, 1, b.Tm.p, b.Ct.p, b.Fm.p, nullptr, 0.0, 1);
+    jp = autotune_jacobi(b, dl, na, jp, cap);
+    tuned[jp_key(b.max_nao, jp.elt)] = jp;
+  };
   for (int it = 0; it < max_it && !active.empty(); ++it) {
     const double cap = (cold && it == 0 && !b.init_from_mono) ? 1e300 : jacobi_cap_err;
     if (graph_mode && it >= 1) {
@@ -1127,6 +1144,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
       continue;
     }
     if (async) {
+      if (want_tune(it)) tune_fused(d_act.p, ub, cap);
       launch_iteration(no_list, d_act.p, ub, 0, cap, true);
       if (first_solve && it == 0) {
         // median first-iteration residual over the batch (all listed systems
@@ -1191,16 +1209,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
                          (const int*)d_switched.p, (int)switched.size());
       switched.clear();
     }
-    if (it == 1 && autotune && !split_ok && jp.elt != 0 && !tuned.count(jp_key(b.max_nao, jp.elt))) {
-      // form this iteration's A once, time the eigensolver's launch shapes
-      // on copies of (A, C^T) and keep the fastest for this size bucket; all
-      // shapes give bitwise identical results
-      hipLaunchKernelGGL(k_fock, dim3(na), dim3(256), 0, stream, ds, db, d_act.p);
-      gemm_batch(b, db, na, d_act.p, 0, b.Ct.p, b.Fm.p, b.Tm.p, nullptr, b.gemm_gflop(active), 1);
-      gemm_batch(b, db, na, d_act.p, 1, b.Tm.p, b.Ct.p, b.Fm.p, nullptr, b.gemm_gflop(active), 1);
-      jp = autotune_jacobi(b, d_act.p, na, jp, cap);
-      tuned[jp_key(b.max_nao, jp.elt)] = jp;
-    }
+    if (want_tune(it)) tune_fused(d_act.p, na, cap);
     launch_iteration(active, d_act.p, na, n32, cap, true);
     res.iters_fp32 += n32;
     if (first_solve && it == 0) {
@@ -2218,6 +2227,7 @@ int fx_set_workspace(fx_ctx* ctx, void* dev_ptr, size_t bytes) {
     ctx->c.~Ctx();
     new (&ctx->c) fx::Ctx();
     if (!ctx->mem.live.empty()) throw fx::FxError(FX_E_STATE, "device buffers outlived the context reset");
+    ctx->mem.release_cache();
     ctx->mem.base = static_cast<char*>(dev_ptr);
     ctx->mem.size = bytes;
     ctx->mem.top = 0;

@@ -51,20 +51,17 @@ void explicit_terms(Ctx& c, Batch& b, const double* wsys, DevBuf<double>& g_sys,
   Ctx::check(hipGetLastError(), "explicit gradient terms");
 }
 
-// CSR map global shell -> local shell slots of a cluster batch, in batch order
+// CSR map global shell -> local shell slots of a cluster batch, in batch
+// order (a counting sort of the batch's host shell map)
 void cluster_csr(Ctx& c, Batch& b, DevBuf<int>& ptr, DevBuf<int>& ent) {
-  std::vector<int> cnt(c.Nsh + 1, 0), e;
-  std::vector<std::vector<int>> rows(c.Nsh);
-  std::vector<int> shg;
-  b.d_sh_global.download(shg, c.stream);
-  c.sync();
-  for (int k = 0; k < (int)shg.size(); ++k) rows[shg[k]].push_back(k);
-  for (int s = 0; s < c.Nsh; ++s) {
-    cnt[s + 1] = cnt[s] + (int)rows[s].size();
-    for (int x : rows[s]) e.push_back(x);
-  }
+  const std::vector<int>& shg = b.h_sh_global;
+  std::vector<int> cnt(c.Nsh + 1, 0), e(std::max<size_t>(1, shg.size()));
+  for (int g : shg) ++cnt[g + 1];
+  for (int s = 0; s < c.Nsh; ++s) cnt[s + 1] += cnt[s];
+  std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+  for (int k = 0; k < (int)shg.size(); ++k) e[pos[shg[k]]++] = k;
   ptr.upload(cnt);
-  ent.upload(e.empty() ? std::vector<int>{0} : e);
+  ent.upload(e);
 }
 
 }  // namespace

@@ -28,12 +28,16 @@ struct FxError : std::runtime_error {
 };
 
 // Device memory of one context.  Without a workspace every block comes from
-// hipMalloc; with a caller-owned workspace every block is carved from it (first
-// fit over 256-byte granules, freed neighbours merged) and hipMalloc is never
-// called.  The first-fit layout is kept in both modes (in the first only as
-// offsets), so the workspace size a sequence of calls needs is known from a
-// run without one: replaying the same calls into a workspace of `peak` bytes
-// reproduces the same layout.
+// hipMalloc, and a freed block is kept in a cache keyed by its size and
+// handed out again to a request it fits within 1/8 (repeated runs then call
+// neither hipMalloc nor the synchronising hipFree); the cache is released
+// when the context ends or takes a workspace.  With a caller-owned
+// workspace every block is carved from it (first fit over 256-byte granules,
+// freed neighbours merged) and hipMalloc is never called.  The first-fit
+// layout is kept in both modes (in the first only as offsets), so the
+// workspace size a sequence of calls needs is known from a run without one:
+// replaying the same calls into a workspace of `peak` bytes reproduces the
+// same layout.
 struct DevMem {
   static constexpr size_t kAlign = 256;
   char* base = nullptr;  // workspace, or nullptr
@@ -43,6 +47,19 @@ struct DevMem {
   long long hip_allocs = 0;
   std::map<size_t, size_t> free_;                                 // offset -> bytes below top
   std::unordered_map<void*, std::pair<size_t, size_t>> live;      // block -> (offset, bytes)
+  std::multimap<size_t, void*> cache_;                             // freed hipMalloc blocks by size
+  std::unordered_map<void*, size_t> hip_size_;                     // size of every hipMalloc block
+  DevMem() = default;
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  ~DevMem() { release_cache(); }
+  void release_cache() {
+    for (auto& kv : cache_) {
+      (void)hipFree(kv.second);
+      hip_size_.erase(kv.second);
+    }
+    cache_.clear();
+  }
 
   void* alloc(size_t bytes) {
     bytes = (bytes + kAlign - 1) / kAlign * kAlign;
@@ -66,11 +83,18 @@ struct DevMem {
     if (base) {
       p = base + off;
     } else {
-      if (hipMalloc(&p, bytes) != hipSuccess) {
-        if (from_free) give_back(off, bytes);
-        throw FxError(FX_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+      auto c = cache_.lower_bound(bytes);
+      if (c != cache_.end() && c->first - bytes <= bytes / 8) {
+        p = c->second;
+        cache_.erase(c);
+      } else {
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+          if (from_free) give_back(off, bytes);
+          throw FxError(FX_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        }
+        ++hip_allocs;
+        hip_size_[p] = bytes;
       }
-      ++hip_allocs;
     }
     if (!from_free) top += bytes;
     peak = std::max(peak, top);
@@ -82,7 +106,13 @@ struct DevMem {
     if (it == live.end()) return;
     const size_t off = it->second.first, bytes = it->second.second;
     live.erase(it);
-    if (!base) (void)hipFree(p);
+    if (!base) {
+      auto hs = hip_size_.find(p);
+      if (hs != hip_size_.end())
+        cache_.emplace(hs->second, p);
+      else
+        (void)hipFree(p);
+    }
     give_back(off, bytes);
   }
   void give_back(size_t off, size_t bytes) {
@@ -245,6 +275,7 @@ struct Batch {
   DevBuf<int> hop_off, hop_atom, hop_kind, hop_bond, healed_off, healed_sh, sh_mono;
   int n_hop = 0;  // boundary entries of the batch
   std::vector<int> h_hop_off, h_hop_bond, h_healed_off, h_healed_sh;  // host copies
+  std::vector<int> h_sh_global;  // host copy of d_sh_global
   long long tot_gam = 0;
   DevBatch dev();
   // algorithmic work of one n x n product (2 n^3) summed over listed systems

@@ -46,6 +46,9 @@ def test_workspace_runs_allocate_nothing():
     c = _ctx(s, want_gradient=1)
     r0 = c.run()
     assert r0["device_allocs"] > 0
+    # a second run reuses the blocks the first one freed
+    r1 = c.run()
+    assert r1["device_allocs"] < r0["device_allocs"], (r1["device_allocs"], r0["device_allocs"])
     em0, ds0, de0, _ = c.energies()
     g0 = c.gradient()
     need = c.workspace_size()
