@@ -183,8 +183,34 @@ DevSystem Ctx::dev_system() const {
 
 // Build a batch of fragment systems (each a tuple of 1..3 fragments).
 void Ctx::build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters, int nfrag_each) {
-  b.max_nao = 0;
   b.init_from_mono = false;
+  if (b.h_system_gen == system_gen && b.h_nfrag == nfrag_each && b.h_clusters == clusters) {
+    // the same clusters of the same system as the last build: the tables
+    // (atoms, shells, offsets, boundary charges) stand and the pools keep
+    // their layout; only the projector bond directions follow the
+    // coordinates
+    if (b.has_hop) {
+      std::vector<double> hb(3 * (size_t)b.n_hop);
+      for (int e = 0; e < b.n_hop; ++e) {
+        const int kb = b.h_hop_bond[e], a = bonds[2 * kb], bb = bonds[2 * kb + 1];
+        double v[3], r2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+          v[c] = xyz_h[3 * bb + c] - xyz_h[3 * a + c];
+          r2 += v[c] * v[c];
+        }
+        const double r = std::sqrt(r2);
+        for (int c = 0; c < 3; ++c) hb[3 * e + c] = v[c] / r;
+      }
+      b.hop_b.upload(hb);
+    }
+    b.has_pre = false;
+    check(hipMemsetAsync(b.phi.p, 0, sizeof(double) * std::max(1, b.tot_sh), stream), "memset");
+    return;
+  }
+  b.max_nao = 0;
+  b.h_clusters = clusters;
+  b.h_nfrag = nfrag_each;
+  b.h_system_gen = -1;  // set once the build has completed
   const int ns = (int)clusters.size();
   b.nsys = ns;
   std::vector<SysDesc> desc(ns);
@@ -337,6 +363,7 @@ void Ctx::build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters,
   b.has_pre = false;
   b.d_desc.upload(desc);
   b.d_atoms.upload(atoms);
+  b.h_atoms = atoms;
   b.d_atom_ao0.upload(atom_ao0);
   b.d_atom_sh0.upload(atom_sh0);
   b.d_sh_global.upload(sh_global);
@@ -373,6 +400,7 @@ void Ctx::build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters,
   for (int k = 0; k < ns; ++k) all[k] = k;
   b.d_all.upload(all);
   check(hipMemsetAsync(b.phi.p, 0, sizeof(double) * std::max(1, sh_off), stream), "memset");
+  b.h_system_gen = system_gen;
 }
 
 DevBatch Batch::dev() {
@@ -1562,6 +1590,7 @@ void Ctx::set_system(int32_t n_atoms, const int32_t* Z, const double* xyz, int32
   if (n_atoms <= 0 || n_frag <= 0 || !Z || !xyz || !atom_frag || !fchg) throw FxError(FX_E_INVALID, "bad system");
   if (n_bonds < 0 || (n_bonds > 0 && !bonds_in)) throw FxError(FX_E_INVALID, "bad bond list");
   has_system = false;
+  ++system_gen;
   N = n_atoms;
   F = n_frag;
   elem.assign(N, 0);

@@ -349,16 +349,21 @@ void Ctx::gradient() {
   std::vector<long long> ent_o;
   {
     // a ghost (extended atom N + k) sits on the detached atom of bond k: its
-    // forces and CN sensitivity go to that atom's row
+    // forces and CN sensitivity go to that atom's row.  Entries are listed
+    // in a fixed order and then sorted stably by row (a counting sort), so
+    // each row keeps that order and its sums are deterministic.
     auto row_of = [&](int A) { return A < N ? A : bonds[2 * (A - N)]; };
-    std::vector<std::vector<std::pair<int, long long>>> rows(N);
+    struct Ent {
+      int row, b;
+      long long o;
+    };
+    std::vector<Ent> ents;
+    auto add = [&](int row, int id, long long o) { ents.push_back({row, id, o}); };
     auto add_batch = [&](Batch& b, int id) {
-      std::vector<int> at;
-      b.d_atoms.download(at, stream);
-      sync();
+      const std::vector<int>& at = b.h_atoms;
       for (int k = 0; k < b.nsys; ++k) {
         const SysDesc& d = b.h_desc[k];
-        for (int a = 0; a < d.nat; ++a) rows[row_of(at[d.atom_off + a])].push_back({id, d.atom_off + a});
+        for (int a = 0; a < d.nat; ++a) add(row_of(at[d.atom_off + a]), id, d.atom_off + a);
       }
     };
     add_batch(mb, 0);
@@ -368,25 +373,28 @@ void Ctx::gradient() {
     for (long long e = 0; e < n_healed; ++e) {
       const int t = db_.h_healed_sh[e];
       const int G = (int)(std::upper_bound(atom_sh0_g.begin(), atom_sh0_g.end(), t) - atom_sh0_g.begin()) - 1;
-      rows[row_of(G)].push_back({3, e});
+      add(row_of(G), 3, e);
     }
     // projector hybrid-coefficient forces (batch 4): attached atom, detached atom
     auto add_hop = [&](const Batch& b, long long base) {
       for (int e = 0; e < b.n_hop; ++e) {
         const int kb = b.h_hop_bond[e];
-        rows[bonds[2 * kb + 1]].push_back({4, 2 * (base + e)});
-        rows[bonds[2 * kb]].push_back({4, 2 * (base + e) + 1});
+        add(bonds[2 * kb + 1], 4, 2 * (base + e));
+        add(bonds[2 * kb], 4, 2 * (base + e) + 1);
       }
     };
     add_hop(mb, 0);
     if (nscc > 0) add_hop(db_, n_hop_m);
     if (opt.want_response && (nscc > 0 || ntri > 0)) add_hop(mb, n_hop_m + n_hop_d);
-    for (int A = 0; A < N; ++A) {
-      rowptr[A + 1] = rowptr[A] + (int)rows[A].size();
-      for (auto& e : rows[A]) {
-        ent_b.push_back(e.first);
-        ent_o.push_back(e.second);
-      }
+    for (const Ent& e : ents) ++rowptr[e.row + 1];
+    for (int A = 0; A < N; ++A) rowptr[A + 1] += rowptr[A];
+    std::vector<int> pos(rowptr.begin(), rowptr.end() - 1);
+    ent_b.resize(ents.size());
+    ent_o.resize(ents.size());
+    for (const Ent& e : ents) {
+      const int k = pos[e.row]++;
+      ent_b[k] = e.b;
+      ent_o[k] = e.o;
     }
   }
   DevBuf<int> d_rp, d_eb;

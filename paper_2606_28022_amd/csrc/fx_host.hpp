@@ -243,6 +243,11 @@ HostParams load_params(const std::string& path);
 struct Batch {
   int nsys = 0;
   int max_nao = 0;
+  // what the tables were last built for (build_batch keeps them when the
+  // same clusters of the same system come again)
+  std::vector<std::array<int, 3>> h_clusters;
+  int h_nfrag = 0;
+  long long h_system_gen = -1;
   bool init_from_mono = false;  // first basis from the monomers' eigenvectors
   bool has_warm = false;        // some systems start from the previous run (warm_off >= 0)
   DevBuf<long long> warm_off;   // per system: C^T offset in the previous run's layout, or -1
@@ -276,6 +281,7 @@ struct Batch {
   int n_hop = 0;  // boundary entries of the batch
   std::vector<int> h_hop_off, h_hop_bond, h_healed_off, h_healed_sh;  // host copies
   std::vector<int> h_sh_global;  // host copy of d_sh_global
+  std::vector<int> h_atoms;      // host copy of d_atoms
   long long tot_gam = 0;
   DevBatch dev();
   // algorithmic work of one n x n product (2 n^3) summed over listed systems
@@ -364,6 +370,7 @@ struct Ctx {
   // selects the global-memory kernel everywhere
   bool jacobi_lds = !(std::getenv("FX_JACOBI_LDS") && std::atoi(std::getenv("FX_JACOBI_LDS")) == 0);
   int lds_max = 65536;  // bytes of LDS one workgroup may allocate (queried)
+  long long system_gen = 0;  // counts fx_set_system calls (batch tables depend on it)
   double mix_beta = 0.5;
   double macro_beta = 0.5;
   double scc_tol_cur = -1.0, etol_cur = -1.0;
