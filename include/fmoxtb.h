@@ -142,6 +142,16 @@ typedef struct fx_options {
                              gradient (default 400); a run whose response
                              has not reached its tolerance by then returns
                              FX_E_NOCONV (gradient still readable) */
+  int32_t scc_retry;      /* 1 (default): an SCC dimer or trimer that has not
+                             converged within max_iter is solved again from
+                             where it stopped, first with plain Anderson
+                             mixing without the Newton preconditioner and a
+                             damping of 0.2 (FP64 products), then, if still
+                             unconverged, at a tenfold electronic temperature
+                             followed by a warm solve at the nominal one; each
+                             stage allows max(max_iter, 200) iterations.  The
+                             fixed point is the same.  0: none (the run then
+                             returns FX_E_NOCONV). */
 } fx_options;
 
 typedef struct fx_counts {
@@ -189,6 +199,8 @@ typedef struct fx_result {
                              the same system and options already exist) */
   int64_t iters_fp32;     /* FX_MIXED: SCC iterations (summed over systems)
                              that ran the FP32 Fock build and products */
+  int64_t scc_retries;    /* SCC dimers and trimers solved again by the
+                             automatic retry (scc_retry) */
 } fx_result;
 
 /* Caller-owned device memory (the PyTorch wrapper passes a uint8 tensor).

@@ -1440,6 +1440,48 @@ void Ctx::count_ring_init() {
   check(hipHostMalloc((void**)&cnt_host, sizeof(int) * CNT_RING, hipHostMallocDefault), "hipHostMalloc");
 }
 
+// Automatic retry of the systems of a cluster batch whose SCC did not
+// converge: from where each solve stopped, first with plain Anderson mixing
+// of the raw residual (no Newton preconditioner) and a damping of 0.2, then,
+// for those still unconverged, at a tenfold electronic temperature followed
+// by a warm solve at the nominal one.  Products in FP64 throughout (the
+// caller has left the mixed form).  Returns the number still unconverged.
+int Ctx::retry_failed(Batch& b, long long* iters_out) {
+  auto unconverged = [&]() {
+    std::vector<int> st, l;
+    b.status.download(st, stream);
+    sync();
+    for (int s = 0; s < b.nsys; ++s)
+      if (st[s] != 1) l.push_back(s);
+    return l;
+  };
+  std::vector<int> fail = unconverged();
+  if (fail.empty()) return 0;
+  res.scc_retries += (long long)fail.size();
+  const int max_iter0 = opt.max_iter;
+  const int cap = std::max(opt.max_iter, 200);
+  opt.max_iter = retry_damped_iters > 0 ? retry_damped_iters : cap;
+  const bool pre = b.has_pre;
+  const double beta = mix_beta;
+  b.has_pre = false;
+  mix_beta = 0.2;
+  int left = run_scc(b, fail, false, iters_out);
+  b.has_pre = pre;
+  mix_beta = beta;
+  opt.max_iter = cap;
+  if (left) {
+    fail = unconverged();
+    const double kT = P.g.kT;
+    P.g.kT = 10.0 * kT;
+    (void)run_scc(b, fail, false, iters_out);
+    P.g.kT = kT;
+    left = run_scc(b, fail, false, iters_out);
+  }
+  opt.max_iter = max_iter0;
+  if (verbose) std::fprintf(stderr, "[fx] scc retry: %d systems still unconverged\n", left);
+  return left;
+}
+
 // solve a batch either all at once or one system at a time
 int Ctx::solve_batch(Batch& b, bool cold, long long* iters_out) {
   int failed = 0;
@@ -2006,6 +2048,7 @@ void Ctx::run(fx_result* out) {
     prod_mode = mixed ? 1 : 0;
     int failed = solve_batch(db_, true, &itd);
     prod_mode = 0;
+    if (failed && opt.scc_retry) failed = retry_failed(db_, &itd);
     if (failed) all_conv = false;
     res.solves_dimer = nscc;
     res.iters_dimer = itd;
@@ -2055,6 +2098,7 @@ void Ctx::run(fx_result* out) {
     prod_mode = mixed ? 1 : 0;
     int failed = solve_batch(tb_, true, &itt);
     prod_mode = 0;
+    if (failed && opt.scc_retry) failed = retry_failed(tb_, &itt);
     if (failed) all_conv = false;
     res.solves_trimer = ntri;
     res.iters_trimer = itt;
@@ -2303,6 +2347,7 @@ int fx_default_options(fx_options* o) {
   o->vdw_trimer = 1.5;
   o->warm_clusters = 0;
   o->max_response = 400;
+  o->scc_retry = 1;
   return FX_OK;
 }
 
@@ -2326,6 +2371,7 @@ int fx_set_options(fx_ctx* ctx, const fx_options* o) {
       throw fx::FxError(FX_E_INVALID, "van der Waals scaling factors must be positive");
     if (o->warm_clusters != 0 && o->warm_clusters != 1) throw fx::FxError(FX_E_INVALID, "warm_clusters must be 0 or 1");
     if (o->max_response < 1) throw fx::FxError(FX_E_INVALID, "max_response must be positive");
+    if (o->scc_retry != 0 && o->scc_retry != 1) throw fx::FxError(FX_E_INVALID, "scc_retry must be 0 or 1");
     const fx_options& c = ctx->c.opt;
     bool cutoff_changed = o->cutoff_bohr != c.cutoff_bohr || o->order != c.order || o->selection != c.selection ||
                           o->vdw_dimer != c.vdw_dimer || o->vdw_trimer != c.vdw_trimer;

@@ -566,6 +566,10 @@ struct Ctx {
   void count_ring_init();
   int run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* iters_out, bool single = false);
   int solve_batch(Batch& b, bool cold, long long* iters_out);
+  int retry_failed(Batch& b, long long* iters_out);
+  // iteration cap of the damped retry stage (0: max(max_iter, 200));
+  // FX_RETRY_DAMPED_ITERS lets a test force the second stage
+  int retry_damped_iters = std::getenv("FX_RETRY_DAMPED_ITERS") ? std::atoi(std::getenv("FX_RETRY_DAMPED_ITERS")) : 0;
   void run(fx_result* out);
   void set_coordinates(const double* xyz);
   void md_verlet(int n_steps, double dt, const double* mass, double* xyz, double* vel, double* e_pot,

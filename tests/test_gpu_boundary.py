@@ -148,3 +148,41 @@ def test_fp32_field_pass_vs_oracle(params):
     # and the FP64 pass of the same entry point to 1e-12
     c.set_options(precision=0)
     assert np.max(np.abs(c.embedding_field(dq) - ref)) < 1e-12 * np.max(scale)
+
+
+def test_scc_retry_recovers_unconverged_dimers():
+    """Automatic retry of unconverged SCC dimers: with a first-attempt cap of
+    four iterations every pentacene dimer stops unconverged; the damped
+    retry (and, with its own cap forced to two iterations from the host,
+    the tenfold-temperature stage) brings each to the same fixed point as a
+    normal run.  Without the retry the run reports FX_E_NOCONV."""
+    import os
+    from paper_2606_28022_amd.binding import FX_E_NOCONV, FxError
+    _say("scc retry: pentacene 6 molecules")
+    s = w.pentacene_crystal(reps=(2, 2, 1)).subset(list(range(6)))
+    ref = _ctx(s, want_gradient=1)
+    r0 = ref.run()
+    assert r0["scc_retries"] == 0
+    em0, ds0, _, _ = ref.energies()
+    g0 = ref.gradient()
+    for stage2 in (False, True):
+        old = os.environ.get("FX_RETRY_DAMPED_ITERS")
+        if stage2:
+            os.environ["FX_RETRY_DAMPED_ITERS"] = "2"
+        try:
+            c = _ctx(s, want_gradient=1, max_iter=4)
+        finally:
+            if old is None:
+                os.environ.pop("FX_RETRY_DAMPED_ITERS", None)
+            else:
+                os.environ["FX_RETRY_DAMPED_ITERS"] = old
+        r = c.run()
+        assert r["scc_retries"] > 0
+        em, ds, _, _ = c.energies()
+        assert abs(r["e_total"] - r0["e_total"]) < 1e-8
+        assert np.max(np.abs(ds - ds0)) < 1e-9
+        assert np.max(np.abs(c.gradient() - g0)) < 1e-7
+    c = _ctx(s, want_gradient=0, max_iter=4, scc_retry=0)
+    with pytest.raises(FxError) as e:
+        c.run()
+    assert e.value.code == FX_E_NOCONV

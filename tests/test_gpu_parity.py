@@ -220,10 +220,13 @@ def test_error_paths(lib, c1):
         c.set_system(c1.Z, xyz, c1.frag, c1.frag_charge)
     assert e.value.code == FX_E_INVALID
     c.set_system(c1.Z, c1.xyz, c1.frag, c1.frag_charge)
-    c.set_options(max_iter=1, want_gradient=0)
+    c.set_options(max_iter=1, want_gradient=0, scc_retry=0)
     with pytest.raises(FxError) as e:
         c.run()
     assert e.value.code == FX_E_NOCONV
+    with pytest.raises(FxError) as e:
+        c.set_options(scc_retry=2)
+    assert e.value.code == FX_E_INVALID
 
 
 @pytest.mark.parametrize("which", ["c1", "pentacene4"])
