@@ -79,6 +79,11 @@ _lib = None
 
 
 def lib_path():
+    """The in-tree library; FX_LIBRARY=ubsan selects the build whose host
+    code carries the undefined-behaviour sanitizer (python -m
+    paper_2606_28022_amd.build --ubsan)."""
+    if os.environ.get("FX_LIBRARY") == "ubsan":
+        return os.path.join(HERE, "libfmoxtb_ubsan.so")
     return os.path.join(HERE, "libfmoxtb.so")
 
 
