@@ -479,6 +479,7 @@ void Ctx::init_device() {
   for (const void* k : {reinterpret_cast<const void*>(k_jacobi_rot<double>),
                         reinterpret_cast<const void*>(k_jacobi_rot<float>),
                         reinterpret_cast<const void*>(k_apply_rot),
+                        reinterpret_cast<const void*>(k_apply_rot_dual),
                         reinterpret_cast<const void*>(k_cholinv_lds<double>),
                         reinterpret_cast<const void*>(k_cholinv_lds<float>),
                         reinterpret_cast<const void*>(k_cholinv_block2)})
@@ -856,12 +857,7 @@ void Ctx::eigh_hot(const std::vector<int>& nv, const double* A, double* w, doubl
       const unsigned lds_rot = jacobi_rot_layout(b.max_nao, jp.elt).total;
       (void)lds_rot;
       launch_rot(b, db, b.d_list.p, nmat, jp.elt, jacobi_cap_err, RotShape{jp.threads, false}, log_stride);
-      const int tw = apply_rot_tile(b.max_nao);
-      const int tps = (b.max_nao + tw - 1) / tw;
-      const long long grid = xcd_grid(nmat, tps);
-      hipLaunchKernelGGL(k_apply_rot, dim3((unsigned)grid), dim3(64 * apply_rot_waves(b.max_nao)),
-                         (unsigned)apply_rot_lds_bytes(b.max_nao), stream, db, b.d_list.p, nmat, tps, tw,
-                         (const double2*)b.rotlog.p, log_stride, (const int*)b.nlog.p);
+      launch_apply(b, db, b.d_list.p, nmat, log_stride);
     } else if (jp.elt == 8) {
       hipLaunchKernelGGL(k_jacobi_lds<double>, dim3(nmat), dim3(jp.threads), jp.lds, stream, db, b.d_list.p,
                          jacobi_max_sweeps, jacobi_tol, jacobi_thr_scale, jacobi_cap_err, b.sweeps.p, jp.chunk);
@@ -1028,7 +1024,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     b.nlog.alloc(b.nsys);
   }
   KernelTimer* kt_rot = kt(jp.elt == 8 ? "fx::k_jacobi_rot<double>" : "fx::k_jacobi_rot<float>");
-  KernelTimer* kt_app = kt("fx::k_apply_rot");
+  KernelTimer* kt_app = kt(apply_dual(b.max_nao) ? "fx::k_apply_rot_dual" : "fx::k_apply_rot");
   // mixed precision: FP32 Fock build and FP32 matrix-core products for this
   // iteration (the basis, the rotation angles, the charges and the
   // convergence test stay FP64; a final solve's tolerance lies far below the
@@ -1066,13 +1062,8 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
       int ev = timed ? timers.begin(stream) : -1;
       launch_rot(b, db, dl, na, jp.elt, cap, rs, log_stride);
       if (timed) timers.end(stream, ev, kt_rot, 0.0);
-      const int tw = apply_rot_tile(b.max_nao);
-      const int tps = (b.max_nao + tw - 1) / tw;
-      const long long grid = xcd_grid(na, tps);
       ev = timed ? timers.begin(stream) : -1;
-      const unsigned lds_app = (unsigned)apply_rot_lds_bytes(b.max_nao);
-      hipLaunchKernelGGL(k_apply_rot, dim3((unsigned)grid), dim3(64 * apply_rot_waves(b.max_nao)), lds_app, stream,
-                         db, dl, na, tps, tw, (const double2*)b.rotlog.p, log_stride, (const int*)b.nlog.p);
+      launch_apply(b, db, dl, na, log_stride);
       if (timed) timers.end(stream, ev, kt_app, 0.0);
       last_split = true;
     } else {
@@ -1384,6 +1375,25 @@ void Ctx::launch_rot(const Batch& b, const DevBatch& db, const int* dl, int na, 
                        jacobi_tol, jacobi_thr_scale, cap, ee, es, b.sweeps.p, b.rotlog.p, log_stride,
                        jacobi_max_log, b.nlog.p, queue, nl);
   check(hipGetLastError(), "k_jacobi_rot");
+}
+
+// The apply kernel over the na systems listed in dl: two quartets per lane
+// for systems of 129 to 256 AOs, one otherwise
+void Ctx::launch_apply(const Batch& b, const DevBatch& db, const int* dl, int na, long long log_stride) {
+  if (apply_dual(b.max_nao)) {
+    const int tps = (b.max_nao + 63) / 64;
+    const long long grid = xcd_grid(na, tps);
+    hipLaunchKernelGGL(k_apply_rot_dual, dim3((unsigned)grid), dim3(512), (unsigned)apply_rot_dual_lds_bytes(b.max_nao),
+                       stream, db, dl, na, tps, (const double2*)b.rotlog.p, log_stride, (const int*)b.nlog.p);
+  } else {
+    const int tw = apply_rot_tile(b.max_nao);
+    const int tps = (b.max_nao + tw - 1) / tw;
+    const long long grid = xcd_grid(na, tps);
+    hipLaunchKernelGGL(k_apply_rot, dim3((unsigned)grid), dim3(64 * apply_rot_waves(b.max_nao)),
+                       (unsigned)apply_rot_lds_bytes(b.max_nao), stream, db, dl, na, tps, tw,
+                       (const double2*)b.rotlog.p, log_stride, (const int*)b.nlog.p);
+  }
+  check(hipGetLastError(), "apply kernel");
 }
 
 // Launch shape of the rotation kernel for this size bucket: forced by the

@@ -541,6 +541,11 @@ struct Ctx {
   int n_cu = 1;
   void launch_rot(const Batch& b, const DevBatch& db, const int* dl, int na, int elt, double cap, const RotShape& rs,
                   long long log_stride);
+  // apply kernel with two quartets per lane for systems of 129 to 256 AOs
+  // (FX_APPLY_DUAL=0: the one-quartet kernel everywhere)
+  bool apply_dual_on = !(std::getenv("FX_APPLY_DUAL") && std::atoi(std::getenv("FX_APPLY_DUAL")) == 0);
+  bool apply_dual(int max_nao) const { return apply_dual_on && max_nao > 128 && max_nao <= 256; }
+  void launch_apply(const Batch& b, const DevBatch& db, const int* dl, int na, long long log_stride);
   RotShape rot_shape(Batch& b, const DevBatch& db, const int* dl, int na, const JacobiPlan& jp, double cap,
                      long long log_stride, bool may_tune);
   JacobiPlan autotune_jacobi(Batch& b, const int* dl, int na, const JacobiPlan& base, double cap);

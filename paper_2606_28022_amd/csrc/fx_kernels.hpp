@@ -128,6 +128,10 @@ __global__ void k_jacobi_rot(DevBatch bt, const int* list, int max_sweeps, doubl
 __global__ void k_queue_reset(int* queue);
 __global__ void k_apply_rot(DevBatch bt, const int* list, int nl, int tiles_per_sys, int tile_w,
                             const double2* logbuf, long long log_stride, const int* nlog);
+// two quartets per lane, for systems of 129 to 256 AOs: 512 threads, 64-column tiles
+__global__ void k_apply_rot_dual(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double2* logbuf,
+                                 long long log_stride, const int* nlog);
+size_t apply_rot_dual_lds_bytes(int n);
 template <typename T>
 __global__ void k_jacobi_lds(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale,
                              double cap_err, int* sweeps_out, int chunk);

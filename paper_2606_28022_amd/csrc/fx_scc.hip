@@ -2371,6 +2371,225 @@ __global__ void __launch_bounds__(1024)
   }
 }
 
+// Apply kernel for systems of 33 to 64 quartets (129 to 256 AOs): each lane
+// holds two quartets, 2p and 2p + 1, of its half-wave's four columns (a wave
+// takes eight columns, a work-group of eight waves a 64-column tile).  Of
+// the ring moves from one round to the next (X to quartet q - 1, Y to
+// q + 1) those between a lane's own two quartets stay in the lane: the block
+// in X of quartet 2p + 1 becomes quartet 2p's, the block in Y of quartet 2p
+// becomes quartet 2p + 1's.  Only the X of quartet 2p + 2 (from the next
+// lane) and the Y of quartet 2p - 1 (from the previous lane) move by DPP, so
+// a round moves half as much data per quartet as in k_apply_rot.  The
+// boundary rules are those of k_apply_rot: quartet 0 keeps block 0 in X and
+// takes quartet 1's X as its Y; the last quartet L takes its own Y as its X.
+// Rotation parameters are staged per round as [rotation k][parity of q]
+// [q / 2], so that each lane reads consecutive 16-byte entries.
+constexpr int APPLY2_WAVES = 8;
+// rows per LDS band of the dual kernel's tile: half the padded rows
+__host__ __device__ inline int apply_dual_band(int m) { return ((m / 2) + 3) & ~3; }
+__global__ void __launch_bounds__(64 * APPLY2_WAVES)
+    k_apply_rot_dual(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double2* __restrict__ logbuf,
+                     long long log_stride, const int* nlog) {
+  extern __shared__ double2 lds_raw[];
+  constexpr int TW = 64;  // tile columns
+  int sl, tcol;
+  xcd_slot_tile(blockIdx.x, tiles_per_sys, sl, tcol);
+  if (sl >= nl) return;
+  const int si = list[sl];
+  if (bt.status[si] != 0) return;
+  const int nsw = nlog[si];
+  if (nsw <= 0) return;
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao, nv = d.nao;
+  const int c0 = tcol * TW;
+  if (c0 >= nv) return;
+  const int m = (n + 3) & ~3, nb2 = m / 2, nq = m / 4, nrd = nb2 - 1, L = nq - 1;
+  const int P2 = (nq + 1) / 2;  // lane pairs of quartets
+  const int S = 8 * P2;         // staged entries per round
+  const int NT = blockDim.x;
+  double2* lgs = lds_raw;  // [APPLY_RCH][4][2][P2]
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool wact = c0 + 2 * APPLY_COLS * wave < nv;  // uniform in the wave
+  const int p = lane & 31;
+  const int cw = c0 + 2 * APPLY_COLS * wave + APPLY_COLS * (lane >> 5);  // the lane's first column
+  const int qa = 2 * p, qb = 2 * p + 1;
+  const bool acta = qa < nq, actb = qb < nq;
+  const bool first = p == 0, lastA = qa == L, lastB = qb == L;
+  const bool Lodd = (L & 1) != 0;  // uniform: the last quartet is some lane's second
+  double* V = bt.Ct + d.mat_off;
+  const int qac = min(qa, nq - 1), qbc = min(qb, nq - 1);
+  const int rxa = 2 * qac, rya = 2 * (nb2 - 1 - qac), rxb = 2 * qbc, ryb = 2 * (nb2 - 1 - qbc);
+  double* st = reinterpret_cast<double*>(lds_raw);
+  const int ld = TW + 1;
+  const int ccol = cw - c0;
+  // the tile passes through LDS in two bands of rows (half the LDS of a
+  // whole tile, so that two work-groups share a CU)
+  const int band = apply_dual_band(m);
+  double xa1[APPLY_COLS], xa2[APPLY_COLS], ya1[APPLY_COLS], ya2[APPLY_COLS];
+  double xb1[APPLY_COLS], xb2[APPLY_COLS], yb1[APPLY_COLS], yb2[APPLY_COLS];
+#pragma unroll
+  for (int c = 0; c < APPLY_COLS; ++c)
+    xa1[c] = xa2[c] = ya1[c] = ya2[c] = xb1[c] = xb2[c] = yb1[c] = yb2[c] = 0.0;
+  for (int b0 = 0; b0 < m; b0 += band) {
+    const int nr = min(band, m - b0);
+    if (b0 > 0) __syncthreads();  // the previous band has been read
+    for (int e = threadIdx.x; e < nr * TW; e += NT) {
+      const int r = e / TW, cc = e - r * TW, col = c0 + cc;
+      st[r * ld + cc] = (b0 + r < n && col < nv) ? V[(long long)(b0 + r) * nv + col] : 0.0;
+    }
+    __syncthreads();
+    // (a row outside this band reads nothing; every row lies in one band)
+    auto pick = [&](int row, bool act, double& v, int col) {
+      const int r = row - b0;
+      if (act && r >= 0 && r < nr) v = st[r * ld + col];
+    };
+#pragma unroll
+    for (int c = 0; c < APPLY_COLS; ++c) {
+      const int col = ccol + c;
+      pick(rxa, acta, xa1[c], col);
+      pick(rxa + 1, acta, xa2[c], col);
+      pick(rya, acta, ya1[c], col);
+      pick(rya + 1, acta, ya2[c], col);
+      pick(rxb, actb, xb1[c], col);
+      pick(rxb + 1, actb, xb2[c], col);
+      pick(ryb, actb, yb1[c], col);
+      pick(ryb + 1, actb, yb2[c], col);
+    }
+  }
+  __syncthreads();  // the area is reused for the rotation parameters
+  const double2* lg = logbuf + (long long)si * log_stride;
+  const long long swe = jq_sweep_entries(m);
+  const int CE = APPLY_RCH * m;        // log entries per chunk
+  const int per = (CE + NT - 1) / NT;  // <= 4 for m <= 256 and NT = 512
+  double2 rg[4];
+  auto fetch = [&](int sw, int r0) {
+    const double2* src = lg + (long long)sw * swe + nb2 + (long long)r0 * m;
+    const int lim = min(APPLY_RCH, nrd - r0) * m;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = threadIdx.x + NT * r;
+      rg[r] = (r < per && e < lim) ? src[e] : make_double2(1.0, 0.0);
+    }
+  };
+  for (int sw = 0; sw < nsw; ++sw) {
+    const double2* ls = lg + (long long)sw * swe;
+    fetch(sw, 0);
+    // block step: pairs (2k, 2k+1) of the lane's four blocks
+    if (wact) {
+      const double2 wxa = ls[qac], wya = ls[nb2 - 1 - qac], wxb = ls[qbc], wyb = ls[nb2 - 1 - qbc];
+#pragma unroll
+      for (int c = 0; c < APPLY_COLS; ++c) {
+        jq_apply2(xa1[c], xa2[c], wxa);
+        jq_apply2(ya1[c], ya2[c], wya);
+        jq_apply2(xb1[c], xb2[c], wxb);
+        jq_apply2(yb1[c], yb2[c], wyb);
+      }
+    }
+    for (int r0 = 0; r0 < nrd; r0 += APPLY_RCH) {
+      __syncthreads();  // the previous chunk's parameters are no longer read
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int e = threadIdx.x + NT * r;
+        if (r < per && e < CE) {
+          const int j = e / m, i = e - j * m;  // round j of the chunk, entry 4 quartet + k
+          const int qq = i >> 2, k = i & 3;
+          lgs[j * S + (2 * k + (qq & 1)) * P2 + (qq >> 1)] = rg[r];
+        }
+      }
+      if (r0 + APPLY_RCH < nrd) fetch(sw, r0 + APPLY_RCH);
+      __syncthreads();  // staged parameters visible
+      const int r1 = min(nrd, r0 + APPLY_RCH);
+      if (!wact) continue;
+      for (int rd = r0; rd < r1; ++rd) {
+        const double2* lr = lgs + (rd - r0) * S + min(p, P2 - 1);
+        const double2 a0 = lr[0], b0 = lr[P2], a1 = lr[2 * P2], b1 = lr[3 * P2];
+        const double2 a2 = lr[4 * P2], b2 = lr[5 * P2], a3 = lr[6 * P2], b3 = lr[7 * P2];
+#pragma unroll
+        for (int c = 0; c < APPLY_COLS; ++c) {
+          jq_apply2(xa1[c], ya1[c], a0);
+          jq_apply2(xa2[c], ya2[c], a1);
+          jq_apply2(xa1[c], ya2[c], a2);
+          jq_apply2(xa2[c], ya1[c], a3);
+          jq_apply2(xb1[c], yb1[c], b0);
+          jq_apply2(xb2[c], yb2[c], b1);
+          jq_apply2(xb1[c], yb2[c], b2);
+          jq_apply2(xb2[c], yb1[c], b3);
+        }
+        // ring move: X(2p) <- X(2p+1), X(2p+1) <- X(2p+2) (next lane),
+        // Y(2p) <- Y(2p-1) (previous lane), Y(2p+1) <- Y(2p); quartet 0
+        // keeps its X and takes X(1) as its Y; the last quartet takes its Y
+        if (Lodd) {
+#pragma unroll
+          for (int c = 0; c < APPLY_COLS; ++c) {
+            const double nx1 = lane_from_next(xa1[c]), nx2 = lane_from_next(xa2[c]);
+            const double py1 = lane_from_prev(yb1[c]), py2 = lane_from_prev(yb2[c]);
+            const double oxa1 = xa1[c], oxa2 = xa2[c];
+            xa1[c] = first ? oxa1 : xb1[c];
+            xa2[c] = first ? oxa2 : xb2[c];
+            const double nyb1 = ya1[c], nyb2 = ya2[c];
+            ya1[c] = first ? xb1[c] : py1;
+            ya2[c] = first ? xb2[c] : py2;
+            xb1[c] = lastB ? yb1[c] : nx1;
+            xb2[c] = lastB ? yb2[c] : nx2;
+            yb1[c] = nyb1;
+            yb2[c] = nyb2;
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < APPLY_COLS; ++c) {
+            const double nx1 = lane_from_next(xa1[c]), nx2 = lane_from_next(xa2[c]);
+            const double py1 = lane_from_prev(yb1[c]), py2 = lane_from_prev(yb2[c]);
+            const double oxa1 = xa1[c], oxa2 = xa2[c];
+            xa1[c] = first ? oxa1 : (lastA ? ya1[c] : xb1[c]);
+            xa2[c] = first ? oxa2 : (lastA ? ya2[c] : xb2[c]);
+            const double nyb1 = ya1[c], nyb2 = ya2[c];
+            ya1[c] = first ? xb1[c] : py1;
+            ya2[c] = first ? xb2[c] : py2;
+            xb1[c] = nx1;
+            xb2[c] = nx2;
+            yb1[c] = nyb1;
+            yb2[c] = nyb2;
+          }
+        }
+      }
+    }
+  }
+  // store the tile through LDS in whole-row writes, band by band
+  for (int b0 = 0; b0 < n; b0 += band) {
+    const int nr = min(band, n - b0);
+    __syncthreads();  // the area is free (parameters read / previous band written)
+    auto put = [&](int row, bool act, double v, int col) {
+      const int r = row - b0;
+      if (act && r >= 0 && r < nr) st[r * ld + col] = v;
+    };
+    if (wact) {
+#pragma unroll
+      for (int c = 0; c < APPLY_COLS; ++c) {
+        const int col = ccol + c;
+        put(rxa, acta, xa1[c], col);
+        put(rxa + 1, acta, xa2[c], col);
+        put(rya, acta, ya1[c], col);
+        put(rya + 1, acta, ya2[c], col);
+        put(rxb, actb, xb1[c], col);
+        put(rxb + 1, actb, xb2[c], col);
+        put(ryb, actb, yb1[c], col);
+        put(ryb + 1, actb, yb2[c], col);
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * TW; e += NT) {
+      const int r = e / TW, cc = e - r * TW, col = c0 + cc;
+      if (col < nv) V[(long long)(b0 + r) * nv + col] = st[r * ld + cc];
+    }
+  }
+}
+
+size_t apply_rot_dual_lds_bytes(int n) {
+  const int m = (n + 3) & ~3, nq = m / 4, P2 = (nq + 1) / 2;
+  return std::max((size_t)APPLY_RCH * 8 * P2 * 16, (size_t)apply_dual_band(m) * 65 * 8);
+}
+
 int apply_rot_tile(int n) { return ((n + 3) & ~3) <= 128 ? 128 : 64; }
 size_t apply_rot_lds_bytes(int n) {
   const size_t m = (size_t)((n + 3) & ~3);
