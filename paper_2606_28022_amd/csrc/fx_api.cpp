@@ -600,17 +600,16 @@ void Ctx::build_precond(Batch& b) {
   if (!precond || !resp_ok || b.nsys == 0) return;
   int nsmax = 0;
   for (const auto& d : b.h_desc) nsmax = std::max(nsmax, d.nsh);
-  int ncmax = 1;  // largest component (monomer) of any system, in shells
-  for (const auto& d : mb.h_desc) ncmax = std::max(ncmax, d.nsh);
-  const unsigned kb = (unsigned)nsmax * (unsigned)nsmax * 4u, mrow = 16u * 8u * (unsigned)ncmax + 8u;
-  if ((int)(kb + mrow) > lds_max - 16384 || nsmax > MAXN) return;
-  const unsigned bytes = kb + mrow;
+  // K in FP32, and the operand chunks of its product (two KC x ns FP64
+  // blocks, KC = min(16, max(1, ns / 4))) in the same bytes
+  const unsigned bytes = std::max(4u * (unsigned)nsmax * (unsigned)nsmax, 16u * (unsigned)nsmax);
+  if ((int)bytes > lds_max - 16384 || nsmax > PRE_MAXSH) return;
   b.pre.alloc(std::max(1LL, b.tot_gam));
   DevBuf<int> ok;
   ok.alloc(b.nsys);
   DevBatch db = b.dev();
-  hipLaunchKernelGGL(k_precond_build, dim3(b.nsys), dim3(1024), bytes, stream, dev_system(), db, b.d_all.p, mb.dev(),
-                     (const double*)resp_M.p, b.pre.p, ok.p, ncmax);
+  hipLaunchKernelGGL(k_precond_build, dim3(b.nsys), dim3(PRE_THREADS), bytes, stream, dev_system(), db, b.d_all.p,
+                     mb.dev(), (const double*)resp_M.p, b.pre.p, ok.p);
   check(hipGetLastError(), "k_precond_build");
   std::vector<int> h;
   ok.download(h, stream);

@@ -44,8 +44,12 @@ __global__ void k_to_f32(const double* src, float* dst, long long n);
 template <int MODE, typename TA, typename TB, typename TC>
 __global__ void k_gemm_f32(DevBatch bt, const int* list, int nl, int tiles_per_sys, const TA* Abase, const TB* Bbase,
                            TC* Cbase, const double* wbase, int skip_done, int sym, int occ_list);
+// k_precond_build runs 1024 threads (16 waves); each thread holds PRE_ROWS x
+// PRE_COLS elements of K, so systems of up to 192 shells
+constexpr int PRE_ROWS = 12, PRE_COLS = 3, PRE_THREADS = 1024;
+constexpr int PRE_MAXSH = 16 * PRE_ROWS < 64 * PRE_COLS ? 16 * PRE_ROWS : 64 * PRE_COLS;
 __global__ void k_precond_build(DevSystem sys, DevBatch bt, const int* list, DevBatch mono, const double* Mmono,
-                                float* pre, int* ok, int ncmax);
+                                float* pre, int* ok);
 template <int MODE>
 __global__ void k_gemm_mfma(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double* Abase,
                             const double* Bbase, double* Cbase, const double* wbase, int skip_done, int sym,

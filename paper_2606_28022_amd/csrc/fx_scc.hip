@@ -519,9 +519,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
     for (int k = tid; k < nk; k += 256) kxs[k] = kg[k];
     __syncthreads();
   }
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wi = wave >> 1, wj = wave & 1;
   const int i0 = ti * 64, j0 = tj * 64;
+  // 16 x 16 output blocks of this wave that hold a real element: the others
+  // lie wholly in the padding and are neither computed nor stored
+  bool blk[2][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) blk[u][v] = i0 + wi * 32 + 16 * u < n && j0 + wj * 32 + 16 * v < n;
+  const bool all4 = blk[1][1];
   v4d acc[2][2];
 #pragma unroll
   for (int u = 0; u < 2; ++u)
@@ -608,15 +616,29 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
     }
     __syncthreads();
     if (k0 + KS < nk) fetch(k0 + KS);
+    if (all4 && k0 + KS <= nk) {
 #pragma unroll
-    for (int kk = 0; kk < KS; kk += 4) {
-      const int krow = kk + (lane >> 4), c = lane & 15;
-      const double a0 = As[krow][wi * 32 + c], a1 = As[krow][wi * 32 + 16 + c];
-      const double b0 = Bs[krow][wj * 32 + c], b1 = Bs[krow][wj * 32 + 16 + c];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      for (int kk = 0; kk < KS; kk += 4) {
+        const int krow = kk + (lane >> 4), c = lane & 15;
+        const double a0 = As[krow][wi * 32 + c], a1 = As[krow][wi * 32 + 16 + c];
+        const double b0 = Bs[krow][wj * 32 + c], b1 = Bs[krow][wj * 32 + 16 + c];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      }
+    } else {
+      // a wave with padding blocks, or the last slab: the steps past nk
+      // (zero padding) and the padding blocks are left out
+      for (int kk = 0; kk < KS && k0 + kk < nk; kk += 4) {
+        const int krow = kk + (lane >> 4), c = lane & 15;
+        const double a0 = As[krow][wi * 32 + c], a1 = As[krow][wi * 32 + 16 + c];
+        const double b0 = Bs[krow][wj * 32 + c], b1 = Bs[krow][wj * 32 + 16 + c];
+        if (blk[0][0]) acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        if (blk[0][1]) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        if (blk[1][0]) acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        if (blk[1][1]) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
@@ -1526,14 +1548,15 @@ namespace fx {
 // the identity are written when a pivot vanishes.
 __global__ void __launch_bounds__(1024)
     k_precond_build(DevSystem sys, DevBatch bt, const int* list, DevBatch mono, const double* Mmono, float* pre,
-                    int* ok, int ncmax) {
-  // LDS: K (ns x ns, FP32), then one row of the monomer susceptibility per
-  // wave (ncmax doubles each)
+                    int* ok) {
+  // LDS: K (ns x ns, FP32); while K is formed, the same bytes stage the
+  // operands of the product M G' in chunks of KC contraction indices
   extern __shared__ float Kf[];
-  __shared__ double qa[MAXN];
+  __shared__ double qa[MAXN];  // atom charges, then 2 Gamma_A dq_A per atom
   __shared__ float colk[MAXN], rowk[MAXN];
-  __shared__ int perm[MAXN];
-  __shared__ int comp_off[4], comp_frag[3];
+  __shared__ int perm[MAXN];   // local atom of each shell while K is formed
+  __shared__ int comp_off[4], comp_mnsh[3];
+  __shared__ long long comp_moff[3];
   __shared__ int pivrow;
   __shared__ float pivval;
   const int si = list[blockIdx.x];
@@ -1544,8 +1567,10 @@ __global__ void __launch_bounds__(1024)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   if (threadIdx.x == 0) {
     for (int c = 0; c < d.nfrag; ++c) {
-      comp_frag[c] = d.frag[c];
+      const SysDesc md = mono.desc[d.frag[c]];
       comp_off[c] = d.comp_sh[c];
+      comp_moff[c] = md.gam_off;
+      comp_mnsh[c] = md.nsh;
     }
     comp_off[d.nfrag] = d.comp_sh[d.nfrag];
   }
@@ -1554,37 +1579,67 @@ __global__ void __launch_bounds__(1024)
     const int s1 = (a + 1 < d.nat) ? bt.sys_atom_sh0[d.atom_off + a + 1] : ns;
     double v = 0.0;
     for (int s = s0; s < s1; ++s) v += q[s];
-    qa[a] = v;
+    qa[a] = 2.0 * sys.elems[sys.elem[bt.sys_atoms[d.atom_off + a]]].Gamma * v;
   }
-  __syncthreads();
-  // K = 1 + M G' (a wave per row, lanes over columns): the row of M is
-  // gathered once per row into the wave's LDS slot (instead of two dependent
-  // loads per term)
+  for (int t = threadIdx.x; t < ns; t += blockDim.x) perm[t] = bt.sys_sh_atom[d.sh_off + t];
+  // K = 1 + M G', M block diagonal (the monomers' susceptibilities): each
+  // thread accumulates rows s = wave + nw r and columns t = lane + 64 j in
+  // FP64 registers, the contraction index u ascending (terms from another
+  // fragment's block are exact zeros), so every element is summed in the same
+  // order as the plain row-by-row product; G' and the block-diagonal M are
+  // staged KC rows / columns at a time (each element read from HBM once)
   const int* smap = bt.sh_mono + d.sh_off;
-  double* mrow = reinterpret_cast<double*>(Kf + ((ns * ns + 1) & ~1)) + wave * ncmax;
-  for (int s = wave; s < ns; s += nw) {
-    int c = 0;
-    while (c + 1 < d.nfrag && s >= comp_off[c + 1]) ++c;
-    const int k0 = comp_off[c], nc = comp_off[c + 1] - k0;
-    const SysDesc md = mono.desc[comp_frag[c]];
-    const double* Mr = Mmono + md.gam_off + (long long)smap[s] * md.nsh;
-    for (int k = lane; k < nc; k += 64) mrow[k] = Mr[smap[k0 + k]];
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    for (int t = lane; t < ns; t += 64) {
-      const int at = bt.sys_sh_atom[d.sh_off + t];
-      const double g3 = 2.0 * sys.elems[sys.elem[bt.sys_atoms[d.atom_off + at]]].Gamma * qa[at];
-      double v = (s == t) ? 1.0 : 0.0;
-      for (int k = 0; k < nc; ++k) {
-        double g = G[(long long)(k0 + k) * ns + t];
-        if (bt.sys_sh_atom[d.sh_off + k0 + k] == at) g -= g3;
-        v += mrow[k] * g;
-      }
-      Kf[s * ns + t] = (float)v;
+  const int KC = min(16, max(1, ns / 4));
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  double* Gs = reinterpret_cast<double*>(Kf);  // [KC][ns]
+  double* Ms = Gs + KC * ns;                    // [ns][KC]
+  double acc[PRE_ROWS][PRE_COLS];
+#pragma unroll
+  for (int r = 0; r < PRE_ROWS; ++r)
+#pragma unroll
+    for (int j = 0; j < PRE_COLS; ++j) acc[r][j] = (wave + nw * r == lane + 64 * j) ? 1.0 : 0.0;
+  for (int u0 = 0; u0 < ns; u0 += KC) {
+    const int kc = min(KC, ns - u0);
+    __syncthreads();  // the previous chunk is consumed (first pass: the tables above are written)
+    for (int e = threadIdx.x; e < kc * ns; e += blockDim.x) {
+      const int uu = e / ns, t = e - uu * ns, u = u0 + uu;
+      double g = G[(long long)u * ns + t];
+      if (perm[u] == perm[t]) g -= qa[perm[t]];
+      Gs[uu * ns + t] = g;
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();  // the slot is rewritten for the next row
+    for (int e = threadIdx.x; e < ns * kc; e += blockDim.x) {
+      const int s = e / kc, uu = e - s * kc, u = u0 + uu;
+      int cs = 0, cu = 0;
+      for (int c = 1; c < d.nfrag; ++c) {
+        cs += s >= comp_off[c];
+        cu += u >= comp_off[c];
+      }
+      Ms[s * kc + uu] =
+          cs == cu ? Mmono[comp_moff[cs] + (long long)smap[s] * comp_mnsh[cs] + smap[u]] : 0.0;
+    }
+    __syncthreads();
+    // (rows and columns beyond ns repeat the last one: no branches in the
+    // loop, and their sums are never stored)
+    for (int uu = 0; uu < kc; ++uu) {
+      double g[PRE_COLS];
+#pragma unroll
+      for (int j = 0; j < PRE_COLS; ++j) g[j] = Gs[uu * ns + min(lane + 64 * j, ns - 1)];
+#pragma unroll
+      for (int r = 0; r < PRE_ROWS; ++r) {
+        const double m = Ms[min(wave_u + nw * r, ns - 1) * kc + uu];
+#pragma unroll
+        for (int j = 0; j < PRE_COLS; ++j) acc[r][j] = fma(m, g[j], acc[r][j]);
+      }
+    }
   }
+  __syncthreads();  // the staging area becomes K
+#pragma unroll
+  for (int r = 0; r < PRE_ROWS; ++r)
+#pragma unroll
+    for (int j = 0; j < PRE_COLS; ++j) {
+      const int s = wave + nw * r, t = lane + 64 * j;
+      if (s < ns && t < ns) Kf[s * ns + t] = (float)acc[r][j];
+    }
   __syncthreads();
   // Gauss-Jordan with partial pivoting (largest |K[i][k]|, i >= k, lowest
   // index on ties), in place
