@@ -1018,8 +1018,13 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
   const bool split_ok = jacobi_split && jp.elt != 0 && (long long)apply_rot_lds_bytes(b.max_nao) <= lds_max &&
                         (int)jacobi_rot_layout(b.max_nao, jp.elt).total <= lds_max &&
                         8 * m4 <= 2 * 64 * apply_rot_waves(b.max_nao);
+  // cold solve by the split form (not in the mixed-precision form, whose
+  // cold iteration builds only the FP32 Fock matrix)
+  const bool cold_split = split_ok && jacobi_cold_log > 0 && cold && !b.init_from_mono && !(b.has_f32 && prod_mode != 0);
+  const long long cold_stride = (long long)jacobi_cold_log * jacobi_rot_log_entries(b.max_nao);
+  DevBuf<int> cold_list;
   if (split_ok) {
-    b.rotlog.alloc((long long)b.nsys * log_stride);
+    b.rotlog.alloc((long long)b.nsys * (cold_split ? std::max(log_stride, cold_stride) : log_stride));
     b.nlog.alloc(b.nsys);
   }
   KernelTimer* kt_rot = kt(jp.elt == 8 ? "fx::k_jacobi_rot<double>" : "fx::k_jacobi_rot<float>");
@@ -1064,6 +1069,40 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
       ev = timed ? timers.begin(stream) : -1;
       launch_apply(b, db, dl, na, log_stride);
       if (timed) timers.end(stream, ev, kt_app, 0.0);
+      last_split = true;
+    } else if (cold_split) {
+      // passes of up to jacobi_cold_log sweeps; a system whose pass ended on
+      // a sweep without rotations (fewer logged sweeps than the pass allows)
+      // is done, the others start the next pass from C^T F C in the basis
+      // this pass left (the Fock matrix is rebuilt: the products overwrite
+      // it).  The launch shape is not tuned here but on a warm iteration.
+      const RotShape rs = rot_shape(b, db, dl, na, jp, cap, cold_stride, false);
+      std::vector<int> todo(na), nlog;
+      check(hipMemcpyAsync(todo.data(), dl, sizeof(int) * na, hipMemcpyDeviceToHost, stream), "list copy");
+      const int* dt = dl;
+      const int max_pass = (jacobi_max_sweeps + jacobi_cold_log - 1) / jacobi_cold_log;
+      for (int pass = 0; pass < max_pass && !todo.empty(); ++pass) {
+        const int nt = (int)todo.size();
+        if (pass > 0) {
+          cold_list.upload(todo);
+          dt = cold_list.p;
+          hipLaunchKernelGGL(k_fock, dim3(nt), dim3(256), 0, stream, ds, db, dt);
+          gemm_batch(b, db, nt, dt, 0, b.Ct.p, b.Fm.p, b.Tm.p, nullptr, 0.0, 1);
+          gemm_batch(b, db, nt, dt, 1, b.Tm.p, b.Ct.p, b.Fm.p, nullptr, 0.0, 1, 1);
+        }
+        int ev = timed ? timers.begin(stream) : -1;
+        launch_rot(b, db, dt, nt, jp.elt, cap, rs, cold_stride, jacobi_cold_log);
+        if (timed) timers.end(stream, ev, kt_rot, 0.0);
+        ev = timed ? timers.begin(stream) : -1;
+        launch_apply(b, db, dt, nt, cold_stride);
+        if (timed) timers.end(stream, ev, kt_app, 0.0);
+        b.nlog.download(nlog, stream);
+        sync();
+        std::vector<int> next;
+        for (int s : todo)
+          if (nlog[s] >= jacobi_cold_log) next.push_back(s);
+        todo.swap(next);
+      }
       last_split = true;
     } else {
       last_split = false;
@@ -1122,7 +1161,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
   // (A, C^T); all shapes give bitwise identical results
   auto want_tune = [&](int it) {
     if (!autotune || capturing || jp.elt == 0 || tuned.count(jp_key(b.max_nao, jp.elt))) return false;
-    return split_ok ? (it == 0 && cold && !b.init_from_mono) : it == 1;
+    return split_ok ? (it == 0 && cold && !b.init_from_mono && !cold_split) : it == 1;
   };
   auto tune_fused = [&](const int* dl, int na, double cap) {
     hipLaunchKernelGGL(k_fock, dim3(na), dim3(256), 0, stream, ds, db, dl);
@@ -1347,7 +1386,8 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
 // system or a persistent grid over a work queue (rs.persistent: as many
 // work-groups as fit on the device at once, fed by an atomic counter)
 void Ctx::launch_rot(const Batch& b, const DevBatch& db, const int* dl, int na, int elt, double cap,
-                     const RotShape& rs, long long log_stride) {
+                     const RotShape& rs, long long log_stride, int max_log) {
+  const int ml = max_log > 0 ? max_log : jacobi_max_log;
   const unsigned lds_rot = jacobi_rot_layout(b.max_nao, elt).total;
   const void* fn = elt == 8 ? reinterpret_cast<const void*>(k_jacobi_rot<double>)
                             : reinterpret_cast<const void*>(k_jacobi_rot<float>);
@@ -1363,16 +1403,16 @@ void Ctx::launch_rot(const Batch& b, const DevBatch& db, const int* dl, int na, 
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, stream, queue);
   }
   // (monomers start each solve from exact eigenvectors: one sweep)
-  const int es = std::min(jacobi_early_sweeps, jacobi_max_log);
+  const int es = std::min(jacobi_early_sweeps, ml);
   const double ee = b.init_from_mono ? jacobi_early_err : 1e300;
   if (elt == 8)
     hipLaunchKernelGGL(k_jacobi_rot<double>, dim3(grid), dim3(rs.threads), lds_rot, stream, db, dl, jacobi_max_sweeps,
-                       jacobi_tol, jacobi_thr_scale, cap, ee, es, b.sweeps.p, b.rotlog.p, log_stride,
-                       jacobi_max_log, b.nlog.p, queue, nl);
+                       jacobi_tol, jacobi_thr_scale, cap, ee, es, b.sweeps.p, b.rotlog.p, log_stride, ml, b.nlog.p,
+                       queue, nl);
   else
     hipLaunchKernelGGL(k_jacobi_rot<float>, dim3(grid), dim3(rs.threads), lds_rot, stream, db, dl, jacobi_max_sweeps,
-                       jacobi_tol, jacobi_thr_scale, cap, ee, es, b.sweeps.p, b.rotlog.p, log_stride,
-                       jacobi_max_log, b.nlog.p, queue, nl);
+                       jacobi_tol, jacobi_thr_scale, cap, ee, es, b.sweeps.p, b.rotlog.p, log_stride, ml, b.nlog.p,
+                       queue, nl);
   check(hipGetLastError(), "k_jacobi_rot");
 }
 

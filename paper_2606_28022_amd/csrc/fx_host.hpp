@@ -524,6 +524,11 @@ struct Ctx {
   // iterations; FX_JACOBI_SPLIT=0 keeps the fused kernel everywhere
   bool jacobi_split = !(std::getenv("FX_JACOBI_SPLIT") && std::atoi(std::getenv("FX_JACOBI_SPLIT")) == 0);
   int jacobi_max_log = std::getenv("FX_JACOBI_MAX_LOG") ? std::atoi(std::getenv("FX_JACOBI_MAX_LOG")) : 2;
+  // the cold eigensolve of a solve from the orthogonalised basis by the split
+  // form too: passes of up to this many logged sweeps, each from a fresh
+  // C^T F C, until every system has had a sweep without rotations
+  // (FX_JACOBI_COLD_LOG=0: the fused kernel)
+  int jacobi_cold_log = std::getenv("FX_JACOBI_COLD_LOG") ? std::atoi(std::getenv("FX_JACOBI_COLD_LOG")) : 8;
   std::map<long long, JacobiPlan> tuned;
   static long long jp_key(int n, int elt) { return (long long)n * 16 + elt; }
   // launch shape of the rotation kernel per size bucket: work-group size and
@@ -539,8 +544,9 @@ struct Ctx {
       std::getenv("FX_JACOBI_ROT_PERSISTENT") ? std::atoi(std::getenv("FX_JACOBI_ROT_PERSISTENT")) : -1;
   DevBuf<int> rot_queue;
   int n_cu = 1;
+  // (max_log: sweeps the log holds per system; 0: jacobi_max_log)
   void launch_rot(const Batch& b, const DevBatch& db, const int* dl, int na, int elt, double cap, const RotShape& rs,
-                  long long log_stride);
+                  long long log_stride, int max_log = 0);
   // apply kernel with two quartets per lane for systems of 129 to 256 AOs
   // (FX_APPLY_DUAL=0: the one-quartet kernel everywhere)
   bool apply_dual_on = !(std::getenv("FX_APPLY_DUAL") && std::atoi(std::getenv("FX_APPLY_DUAL")) == 0);

