@@ -1863,8 +1863,12 @@ __device__ inline void jq_cols(T (&B)[4][4], T c, T s) {
 // distinct LDS banks; the column-major triangle (b (b + 1) / 2 + a) put
 // lanes that step b at triangular-number offsets that collided.
 __device__ inline int jt_index(int a, int b, int N) {
+  // (row and column selected first, then one 24-bit multiply-add: no branch)
   const int h = N >> 1, R = N + 1;
-  return b >= h ? (b - h) * R + a : (h - 1 - b) * R + (R - 1 - a);
+  const bool fwd = b >= h;
+  const int row = fwd ? b - h : h - 1 - b;
+  const int col = fwd ? a : R - 1 - a;
+  return __umul24(row, R) + col;
 }
 
 template <typename T>
