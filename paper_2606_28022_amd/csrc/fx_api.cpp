@@ -480,7 +480,6 @@ void Ctx::init_device() {
                         reinterpret_cast<const void*>(k_jacobi_rot<float>),
                         reinterpret_cast<const void*>(k_apply_rot),
                         reinterpret_cast<const void*>(k_apply_rot_dual),
-                        reinterpret_cast<const void*>(k_apply_sb),
                         reinterpret_cast<const void*>(k_cholinv_lds<double>),
                         reinterpret_cast<const void*>(k_cholinv_lds<float>),
                         reinterpret_cast<const void*>(k_cholinv_block2)})
@@ -847,14 +846,15 @@ void Ctx::eigh_hot(const std::vector<int>& nv, const double* A, double* w, doubl
     gemm_batch(b, db, nmat, b.d_list.p, 0, b.Ct.p, b.Pm.p, b.Tm.p, nullptr, b.gemm_gflop(all), 0);
     gemm_batch(b, db, nmat, b.d_list.p, 1, b.Tm.p, b.Ct.p, b.Fm.p, nullptr, b.gemm_gflop_sym(all), 0, 1);
     const int m4 = (b.max_nao + 3) & ~3;
-    b.rot_sb = sb_order_fits(b.max_nao, jp.elt);
-    const bool split_ok = b.rot_sb || ((long long)apply_rot_lds_bytes(b.max_nao) <= lds_max &&
-                                       (int)jacobi_rot_layout(b.max_nao, jp.elt).total <= lds_max &&
-                                       8 * m4 <= 2 * 64 * apply_rot_waves(b.max_nao));
+    const bool split_ok = (long long)apply_rot_lds_bytes(b.max_nao) <= lds_max &&
+                          (int)jacobi_rot_layout(b.max_nao, jp.elt).total <= lds_max &&
+                          8 * m4 <= 2 * 64 * apply_rot_waves(b.max_nao);
     if (split_ok) {
-      const long long log_stride = (long long)jacobi_max_log * jacobi_rot_log_entries(rot_m(b));
+      const long long log_stride = (long long)jacobi_max_log * jacobi_rot_log_entries(b.max_nao);
       b.rotlog.alloc((long long)nmat * log_stride);
       b.nlog.alloc(nmat);
+      const unsigned lds_rot = jacobi_rot_layout(b.max_nao, jp.elt).total;
+      (void)lds_rot;
       launch_rot(b, db, b.d_list.p, nmat, jp.elt, jacobi_cap_err, RotShape{jp.threads, false}, log_stride);
       launch_apply(b, db, b.d_list.p, nmat, log_stride);
     } else if (jp.elt == 8) {
@@ -1012,27 +1012,23 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
   // listed there return at once (device-side status)
   bool last_split = false;
   // split eigensolver: rotation log of up to jacobi_max_log sweeps per system
-  b.rot_sb = jacobi_split && sb_order_fits(b.max_nao, jp.elt);
-  const long long log_stride = (long long)jacobi_max_log * jacobi_rot_log_entries(rot_m(b));
+  const long long log_stride = (long long)jacobi_max_log * jacobi_rot_log_entries(b.max_nao);
   // (the apply kernel stages 8 rounds of (c, s), at most two entries per thread)
   const int m4 = (b.max_nao + 3) & ~3;
-  const bool split_ok = jacobi_split && jp.elt != 0 &&
-                        (b.rot_sb || ((long long)apply_rot_lds_bytes(b.max_nao) <= lds_max &&
-                                      (int)jacobi_rot_layout(b.max_nao, jp.elt).total <= lds_max &&
-                                      8 * m4 <= 2 * 64 * apply_rot_waves(b.max_nao)));
+  const bool split_ok = jacobi_split && jp.elt != 0 && (long long)apply_rot_lds_bytes(b.max_nao) <= lds_max &&
+                        (int)jacobi_rot_layout(b.max_nao, jp.elt).total <= lds_max &&
+                        8 * m4 <= 2 * 64 * apply_rot_waves(b.max_nao);
   // cold solve by the split form (not in the mixed-precision form, whose
   // cold iteration builds only the FP32 Fock matrix)
   const bool cold_split = split_ok && jacobi_cold_log > 0 && cold && !b.init_from_mono && !(b.has_f32 && prod_mode != 0);
-  const long long cold_stride = (long long)jacobi_cold_log * jacobi_rot_log_entries(rot_m(b));
+  const long long cold_stride = (long long)jacobi_cold_log * jacobi_rot_log_entries(b.max_nao);
   DevBuf<int> cold_list;
   if (split_ok) {
     b.rotlog.alloc((long long)b.nsys * (cold_split ? std::max(log_stride, cold_stride) : log_stride));
     b.nlog.alloc(b.nsys);
   }
   KernelTimer* kt_rot = kt(jp.elt == 8 ? "fx::k_jacobi_rot<double>" : "fx::k_jacobi_rot<float>");
-  KernelTimer* kt_app = kt(b.rot_sb                  ? "fx::k_apply_sb"
-                           : apply_dual(b.max_nao) ? "fx::k_apply_rot_dual"
-                                                   : "fx::k_apply_rot");
+  KernelTimer* kt_app = kt(apply_dual(b.max_nao) ? "fx::k_apply_rot_dual" : "fx::k_apply_rot");
   // mixed precision: FP32 Fock build and FP32 matrix-core products for this
   // iteration (the basis, the rotation angles, the charges and the
   // convergence test stay FP64; a final solve's tolerance lies far below the
@@ -1392,7 +1388,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
 void Ctx::launch_rot(const Batch& b, const DevBatch& db, const int* dl, int na, int elt, double cap,
                      const RotShape& rs, long long log_stride, int max_log) {
   const int ml = max_log > 0 ? max_log : jacobi_max_log;
-  const unsigned lds_rot = jacobi_rot_layout(rot_m(b), elt).total;
+  const unsigned lds_rot = jacobi_rot_layout(b.max_nao, elt).total;
   const void* fn = elt == 8 ? reinterpret_cast<const void*>(k_jacobi_rot<double>)
                             : reinterpret_cast<const void*>(k_jacobi_rot<float>);
   int grid = na, nl = 0;
@@ -1412,31 +1408,18 @@ void Ctx::launch_rot(const Batch& b, const DevBatch& db, const int* dl, int na, 
   if (elt == 8)
     hipLaunchKernelGGL(k_jacobi_rot<double>, dim3(grid), dim3(rs.threads), lds_rot, stream, db, dl, jacobi_max_sweeps,
                        jacobi_tol, jacobi_thr_scale, cap, ee, es, b.sweeps.p, b.rotlog.p, log_stride, ml, b.nlog.p,
-                       queue, nl, b.rot_sb ? 1 : 0);
+                       queue, nl);
   else
     hipLaunchKernelGGL(k_jacobi_rot<float>, dim3(grid), dim3(rs.threads), lds_rot, stream, db, dl, jacobi_max_sweeps,
                        jacobi_tol, jacobi_thr_scale, cap, ee, es, b.sweeps.p, b.rotlog.p, log_stride, ml, b.nlog.p,
-                       queue, nl, b.rot_sb ? 1 : 0);
+                       queue, nl);
   check(hipGetLastError(), "k_jacobi_rot");
-}
-
-// whether the super-block ordering is on and both of its kernels fit a
-// batch of systems of at most max_nao AOs (at most 64 quartets)
-bool Ctx::sb_order_fits(int max_nao, int elt) const {
-  const int m = (max_nao + 15) & ~15;
-  return jacobi_order == 1 && elt != 0 && m <= 256 && (long long)apply_sb_lds_bytes(max_nao) <= lds_max &&
-         (int)jacobi_rot_layout(m, elt).total <= lds_max;
 }
 
 // The apply kernel over the na systems listed in dl: two quartets per lane
 // for systems of 129 to 256 AOs, one otherwise
 void Ctx::launch_apply(const Batch& b, const DevBatch& db, const int* dl, int na, long long log_stride) {
-  if (b.rot_sb) {
-    const int tps = (b.max_nao + 63) / 64;
-    const long long grid = xcd_grid(na, tps);
-    hipLaunchKernelGGL(k_apply_sb, dim3((unsigned)grid), dim3(SBA_THREADS_HOST), (unsigned)apply_sb_lds_bytes(b.max_nao),
-                       stream, db, dl, na, tps, (const double2*)b.rotlog.p, log_stride, (const int*)b.nlog.p);
-  } else if (apply_dual(b.max_nao)) {
+  if (apply_dual(b.max_nao)) {
     const int tps = (b.max_nao + 63) / 64;
     const long long grid = xcd_grid(na, tps);
     hipLaunchKernelGGL(k_apply_rot_dual, dim3((unsigned)grid), dim3(512), (unsigned)apply_rot_dual_lds_bytes(b.max_nao),

@@ -243,9 +243,6 @@ HostParams load_params(const std::string& path);
 struct Batch {
   int nsys = 0;
   int max_nao = 0;
-  // split eigensolver of the last solve in the super-block ordering
-  // (rotation log padded to a multiple of 16, k_apply_sb)
-  bool rot_sb = false;
   // what the tables were last built for (build_batch keeps them when the
   // same clusters of the same system come again)
   std::vector<std::array<int, 3>> h_clusters;
@@ -554,13 +551,6 @@ struct Ctx {
   // (FX_APPLY_DUAL=0: the one-quartet kernel everywhere)
   bool apply_dual_on = !(std::getenv("FX_APPLY_DUAL") && std::atoi(std::getenv("FX_APPLY_DUAL")) == 0);
   bool apply_dual(int max_nao) const { return apply_dual_on && max_nao > 128 && max_nao <= 256; }
-  // Jacobi ordering of the split eigensolver: 0 the circle method over the
-  // blocks (lane-ring apply kernels), 1 the super-block ordering (apply on
-  // the FP64 matrix cores); FX_JACOBI_ORDER
-  int jacobi_order = std::getenv("FX_JACOBI_ORDER") ? std::atoi(std::getenv("FX_JACOBI_ORDER")) : 0;
-  bool sb_order_fits(int max_nao, int elt) const;
-  // the size the rotation layout and log are computed for
-  static int rot_m(const Batch& b) { return b.rot_sb ? (b.max_nao + 15) & ~15 : b.max_nao; }
   void launch_apply(const Batch& b, const DevBatch& db, const int* dl, int na, long long log_stride);
   RotShape rot_shape(Batch& b, const DevBatch& db, const int* dl, int na, const JacobiPlan& jp, double cap,
                      long long log_stride, bool may_tune);

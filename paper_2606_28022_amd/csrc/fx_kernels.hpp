@@ -91,7 +91,7 @@ __host__ __device__ inline JacobiLdsLayout jacobi_lds_layout(int n, int elt, int
 // quartet), the quartets' blocks of two rounds, the table of quartet pairs,
 // a reduction slot
 struct JacobiRotLayout {
-  unsigned ap, dg, cs, csf, qr, pt, red, cb, total;
+  unsigned ap, dg, cs, csf, qr, pt, red, total;
 };
 __host__ __device__ inline JacobiRotLayout jacobi_rot_layout(int n, int elt) {
   const unsigned m = (unsigned)(n + 3) & ~3u, nb2 = m / 2u;
@@ -111,16 +111,10 @@ __host__ __device__ inline JacobiRotLayout jacobi_rot_layout(int n, int elt) {
   o = jl_align(o + 4u * (m / 4u) * (m / 4u - 1u) / 2u);
   L.red = o;
   o = jl_align(o + 8u * 64u);
-  L.cb = o;  // super-block ordering: two sets of 4096 bits
-  o = jl_align(o + 1024u);
   L.total = o;
   return L;
 }
 size_t apply_rot_lds_bytes(int n);
-size_t apply_sb_lds_bytes(int n);  // LDS of k_apply_sb (the tile and the M_p of one super-round)
-constexpr int SBA_THREADS_HOST = 512;
-__global__ void k_apply_sb(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double2* logbuf,
-                           long long log_stride, const int* nlog);
 int apply_rot_tile(int n);  // columns per work-group of k_apply_rot (64 or 128)
 int apply_rot_waves(int n);
 long long jacobi_rot_log_entries(int n);  // rotation log entries per sweep
@@ -134,7 +128,7 @@ constexpr int CHOL_THREADS_HOST = 1024;
 template <typename T>
 __global__ void k_jacobi_rot(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale,
                              double cap_err, double early_err, int early_sweeps, int* sweeps_out, double2* logbuf,
-                             long long log_stride, int max_log, int* nlog, int* queue, int nl, int sb);
+                             long long log_stride, int max_log, int* nlog, int* queue, int nl);
 __global__ void k_queue_reset(int* queue);
 __global__ void k_apply_rot(DevBatch bt, const int* list, int nl, int tiles_per_sys, int tile_w,
                             const double2* logbuf, long long log_stride, const int* nlog);

@@ -1757,62 +1757,6 @@ __device__ inline int rr_fast(int pos, int step, int M) {
 
 __device__ inline long long jq_sweep_entries(int m) { return (long long)m / 2 + (long long)(m / 2 - 1) * m; }
 
-// Super-block ordering (the alternative to the circle method above).  The
-// nb2 blocks (nb2 a multiple of 8) form G = nb2 / 4 super-blocks of four
-// consecutive blocks; the circle method over the super-blocks gives, in
-// outer round o, G / 2 disjoint super-pairs (I, J).  A sweep is: the block
-// step; three intra rounds in which the four blocks of each super-block meet
-// each other (circle method over four, super-pairs of outer round 0); then
-// for o = 0 .. G - 2 four cross rounds k = 0 .. 3 in which block j of I meets
-// block (j + k) mod 4 of J.  That is nb2 - 1 rounds of nb2 / 2 quartets,
-// every pair of blocks meeting once, as in the circle method; quartet
-// q = 4 p + j belongs to super-pair p.  Between consecutive super-rounds
-// (the block step with the intra rounds, then each outer round) the
-// rotations of a super-pair act only on its 16 rows, so their product is a
-// 16 x 16 orthogonal matrix that the apply kernel multiplies onto C^T with
-// the FP64 matrix cores.
-constexpr int SB_G = 4;
-__device__ inline int sb_circ(int pos, int o, int N) { return pos == 0 ? 0 : 1 + (pos - 1 + o) % (N - 1); }
-__device__ inline int sb_circ_inv(int x, int o, int N) {
-  return x == 0 ? 0 : 1 + ((x - 1 - o) % (N - 1) + (N - 1)) % (N - 1);
-}
-// blocks X, Y of quartet q in round rd
-__device__ inline void sb_sched(int q, int rd, int nb2, int& X, int& Y) {
-  const int G = nb2 / SB_G, p = q / SB_G, j = q % SB_G;
-  if (rd < SB_G - 1) {
-    const int I = sb_circ(p, 0, G), J = sb_circ(G - 1 - p, 0, G);
-    const int S = j < SB_G / 2 ? I : J, jj = j < SB_G / 2 ? j : j - SB_G / 2;
-    X = S * SB_G + sb_circ(jj, rd, SB_G);
-    Y = S * SB_G + sb_circ(SB_G - 1 - jj, rd, SB_G);
-    return;
-  }
-  const int t = rd - (SB_G - 1), o = t / SB_G, k = t % SB_G;
-  X = sb_circ(p, o, G) * SB_G + j;
-  Y = sb_circ(G - 1 - p, o, G) * SB_G + (j + k) % SB_G;
-}
-// quartet holding block u in round rd, and u's partner block in it
-__device__ inline void sb_quartet_of(int u, int rd, int nb2, int& q, int& partner) {
-  const int G = nb2 / SB_G, sb = u / SB_G, i = u % SB_G;
-  if (rd < SB_G - 1) {
-    const int pos = sb_circ_inv(sb, 0, G);
-    const int side = pos < G / 2 ? 0 : 1, p = side ? G - 1 - pos : pos;
-    const int pg = sb_circ_inv(i, rd, SB_G);
-    q = p * SB_G + min(pg, SB_G - 1 - pg) + side * (SB_G / 2);
-    partner = sb * SB_G + sb_circ(SB_G - 1 - pg, rd, SB_G);
-    return;
-  }
-  const int t = rd - (SB_G - 1), o = t / SB_G, k = t % SB_G;
-  const int pos = sb_circ_inv(sb, o, G);
-  if (pos < G / 2) {
-    q = pos * SB_G + i;
-    partner = sb_circ(G - 1 - pos, o, G) * SB_G + (i + k) % SB_G;
-  } else {
-    const int p = G - 1 - pos, j = (i - k + SB_G) % SB_G;
-    q = p * SB_G + j;
-    partner = sb_circ(p, o, G) * SB_G + j;
-  }
-}
-
 // (a, b), a < b, of the idx-th unordered pair of N items (rows folded so that
 // every row of the enumeration has N entries)
 __device__ inline void tri_pair(int idx, int N, int& a, int& b) {
@@ -2014,17 +1958,11 @@ __device__ inline void jt_offdiag(typename JtVec<T>::type* At, int N, int qa, in
 // The two steps of round rd on quartet qd's own 4 x 4 block (rotation angles
 // in FP64): the rotated block back to LDS, the four (c, s) to the round's
 // parameter slots (buffer b) and to the log.  Returns whether it rotated.
-template <typename T, bool SB>
+template <typename T>
 __device__ inline bool jq_quartet(int qd, int rd, int n, int nb2, int nq, int b, double thr, double rel_tol,
                                   typename JtVec<T>::type* At, T* Ae, double* dg, double2* cs, float4* csf, int* qr,
                                   double2* lr) {
-  int X, Y;
-  if (SB) {
-    sb_sched(qd, rd, nb2, X, Y);
-  } else {
-    X = rr_fast(qd, rd, nb2);
-    Y = rr_fast(nb2 - 1 - qd, rd, nb2);
-  }
+  const int X = rr_fast(qd, rd, nb2), Y = rr_fast(nb2 - 1 - qd, rd, nb2);
   const int ix[4] = {2 * X, 2 * X + 1, 2 * Y, 2 * Y + 1};
   T* ex = Ae + 4 * jt_index(X, X, nb2) + 1;
   T* ey = Ae + 4 * jt_index(Y, Y, nb2) + 1;
@@ -2099,7 +2037,7 @@ __device__ inline void jq_block(int a, int b, int nq, int bf, typename JtVec<T>:
 }
 
 // The sweeps of one system by the whole work-group (k_jacobi_rot).
-template <typename T, bool SB>
+template <typename T>
 __device__ inline void jacobi_rot_system(const DevBatch& bt, int si, int max_sweeps, double rel_tol, double thr_scale,
                                          double cap_err, double early_err, int early_sweeps, int* sweeps_out,
                                          double2* logbuf, long long log_stride, int max_log, int* nlog) {
@@ -2109,11 +2047,9 @@ __device__ inline void jacobi_rot_system(const DevBatch& bt, int si, int max_swe
   if (bt.status[si] != 0) return;
   const SysDesc d = bt.desc[si];
   const int n = d.nao;
-  // (the super-block ordering pads to a multiple of 16: an even number of
-  // four-block super-blocks)
-  const int m = SB ? (n + 15) & ~15 : (n + 3) & ~3, nb2 = m / 2, nq = m / 4;
+  const int m = (n + 3) & ~3, nb2 = m / 2, nq = m / 4;
   const int nt = blockDim.x;
-  const JacobiRotLayout L = jacobi_rot_layout(m, (int)sizeof(T));
+  const JacobiRotLayout L = jacobi_rot_layout(n, (int)sizeof(T));
   V4* At = reinterpret_cast<V4*>(lds + L.ap);
   T* Ae = reinterpret_cast<T*>(lds + L.ap);
   double* dg = reinterpret_cast<double*>(lds + L.dg);
@@ -2122,9 +2058,6 @@ __device__ inline void jacobi_rot_system(const DevBatch& bt, int si, int max_swe
   int* qr = reinterpret_cast<int*>(lds + L.qr);          // [2][nq] X | Y << 16, sign bit: rotates
   int* pt = reinterpret_cast<int*>(lds + L.pt);          // [nq (nq - 1) / 2] quartet pairs
   double* red = reinterpret_cast<double*>(lds + L.red);
-  // super-block ordering: per round parity, a bit per quartet pair (a, b)
-  // (bit a * 64 + b) marking the blocks that wave 0 rotates first
-  unsigned* cbits = reinterpret_cast<unsigned*>(lds + L.cb);
   double* rows = reinterpret_cast<double*>(cs);  // row sums before the sweeps (16 m >= 8 n bytes)
   const double* __restrict__ A = bt.F + d.mat_off;
   double2* lg = logbuf + (long long)si * log_stride;
@@ -2136,7 +2069,7 @@ __device__ inline void jacobi_rot_system(const DevBatch& bt, int si, int max_swe
   for (int idx = threadIdx.x; idx < nq * (nq - 1) / 2; idx += nt) {
     int a, b;
     tri_pair(idx, nq, a, b);
-    const bool crit = !SB && (b == a + 2 || (a == 0 && b == 1) || (a == nq - 2 && b == nq - 1));
+    const bool crit = b == a + 2 || (a == 0 && b == 1) || (a == nq - 2 && b == nq - 1);
     pt[idx] = a | (b << 8) | (crit ? 1 << 16 : 0);
   }
   __syncthreads();
@@ -2228,46 +2161,13 @@ __device__ inline void jacobi_rot_system(const DevBatch& bt, int si, int max_swe
     const int nrd = nb2 - 1;
     const int ncrit = nq >= 3 ? nq : (nq == 2 ? 1 : 0);
     for (int qd = threadIdx.x; qd < nq; qd += nt)
-      if (jq_quartet<T, SB>(qd, 0, n, nb2, nq, 0, thr, rel_tol, At, Ae, dg, cs, csf, qr, ls + nb2)) rot_sweep = 1;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // Super-block ordering: the blocks of round rd that hold round rd + 1's
-    // quartets follow from the schedule (one per next quartet at most, a
-    // block shared by two next quartets taken by the lower one).  Wave 0
-    // finds them one round ahead, keeps each lane's block in (ca, cb) and
-    // marks it in the bit set of the round's parity, which the other waves
-    // skip.
-    int ca = -1, cb = -1;
-    auto sb_crit = [&](int r) {
-      ca = -1;
-      cb = -1;
-      for (int w = lane; w < 128; w += 64) cbits[(r & 1) * 128 + w] = 0u;
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      if (lane < nq && r + 1 < nrd) {
-        int Xn, Yn, q1, p1, q2, p2;
-        sb_sched(lane, r + 1, nb2, Xn, Yn);
-        sb_quartet_of(Xn, r, nb2, q1, p1);
-        sb_quartet_of(Yn, r, nb2, q2, p2);
-        if (q1 != q2) {
-          int qo, po;
-          sb_quartet_of(p1, r + 1, nb2, qo, po);
-          if (!(po == p2 && qo < lane)) {
-            ca = min(q1, q2);
-            cb = max(q1, q2);
-            const int bit = ca * 64 + cb;
-            atomicOr(&cbits[(r & 1) * 128 + (bit >> 5)], 1u << (bit & 31));
-          }
-        }
-      }
-    };
-    if (SB && wave == 0) sb_crit(0);
+      if (jq_quartet<T>(qd, 0, n, nb2, nq, 0, thr, rel_tol, At, Ae, dg, cs, csf, qr, ls + nb2)) rot_sweep = 1;
     __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int rd = 0; rd < nrd; ++rd) {
       const int bf = rd & 1;
       if (wave == 0) {
-        if (SB) {
-          if (ca >= 0) jq_block<T>(ca, cb, nq, bf, At, cs, csf, qr);
-        } else if (lane < ncrit) {
+        if (lane < ncrit) {
           const int a = lane == 0 ? 0 : (lane == nq - 1 ? nq - 2 : lane - 1);
           const int b = lane == 0 ? 1 : (lane == nq - 1 ? nq - 1 : lane + 1);
           jq_block<T>(a, b, nq, bf, At, cs, csf, qr);
@@ -2275,10 +2175,9 @@ __device__ inline void jacobi_rot_system(const DevBatch& bt, int si, int max_swe
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         if (rd + 1 < nrd && lane < nq)
-          if (jq_quartet<T, SB>(lane, rd + 1, n, nb2, nq, bf ^ 1, thr, rel_tol, At, Ae, dg, cs, csf, qr,
-                                ls + nb2 + (long long)(rd + 1) * m))
+          if (jq_quartet<T>(lane, rd + 1, n, nb2, nq, bf ^ 1, thr, rel_tol, At, Ae, dg, cs, csf, qr,
+                            ls + nb2 + (long long)(rd + 1) * m))
             rot_sweep = 1;
-        if (SB && rd + 1 < nrd) sb_crit(rd + 1);
       }
       // the remaining blocks: the other waves (wave 0 itself in a one-wave
       // work-group)
@@ -2286,14 +2185,8 @@ __device__ inline void jacobi_rot_system(const DevBatch& bt, int si, int max_swe
       if ((int)threadIdx.x >= t0)
         for (int idx = threadIdx.x - t0; idx < nqp; idx += nt - t0) {
           const int e = pt[idx];
-          const int a = e & 255, b = (e >> 8) & 255;
-          if (SB) {
-            const int bit = a * 64 + b;
-            if ((cbits[bf * 128 + (bit >> 5)] >> (bit & 31)) & 1u) continue;  // wave 0's
-          } else if (e >> 16) {
-            continue;  // wave 0's
-          }
-          jq_block<T>(a, b, nq, bf, At, cs, csf, qr);
+          if (e >> 16) continue;  // wave 0's
+          jq_block<T>(e & 255, (e >> 8) & 255, nq, bf, At, cs, csf, qr);
         }
       __syncthreads();
     }
@@ -2319,17 +2212,10 @@ template <typename T>
 __global__ void __launch_bounds__(1024)
     k_jacobi_rot(DevBatch bt, const int* list, int max_sweeps, double rel_tol, double thr_scale, double cap_err,
                  double early_err, int early_sweeps, int* sweeps_out, double2* logbuf, long long log_stride,
-                 int max_log, int* nlog, int* queue, int nl, int sb) {
-  auto one = [&](int si) {
-    if (sb)
-      jacobi_rot_system<T, true>(bt, si, max_sweeps, rel_tol, thr_scale, cap_err, early_err, early_sweeps, sweeps_out,
-                                 logbuf, log_stride, max_log, nlog);
-    else
-      jacobi_rot_system<T, false>(bt, si, max_sweeps, rel_tol, thr_scale, cap_err, early_err, early_sweeps,
-                                  sweeps_out, logbuf, log_stride, max_log, nlog);
-  };
+                 int max_log, int* nlog, int* queue, int nl) {
   if (queue == nullptr) {
-    one(list[blockIdx.x]);
+    jacobi_rot_system<T>(bt, list[blockIdx.x], max_sweeps, rel_tol, thr_scale, cap_err, early_err, early_sweeps,
+                         sweeps_out, logbuf, log_stride, max_log, nlog);
     return;
   }
   __shared__ int slot_sh;
@@ -2339,7 +2225,8 @@ __global__ void __launch_bounds__(1024)
     __syncthreads();
     const int slot = slot_sh;
     if (slot >= nl) break;
-    one(list[slot]);
+    jacobi_rot_system<T>(bt, list[slot], max_sweeps, rel_tol, thr_scale, cap_err, early_err, early_sweeps,
+                         sweeps_out, logbuf, log_stride, max_log, nlog);
   }
 }
 
@@ -2348,9 +2235,9 @@ __global__ void k_queue_reset(int* queue) {
 }
 
 template __global__ void k_jacobi_rot<double>(DevBatch, const int*, int, double, double, double, double, int, int*,
-                                              double2*, long long, int, int*, int*, int, int);
+                                              double2*, long long, int, int*, int*, int);
 template __global__ void k_jacobi_rot<float>(DevBatch, const int*, int, double, double, double, double, int, int*,
-                                             double2*, long long, int, int*, int*, int, int);
+                                             double2*, long long, int, int*, int*, int);
 
 // Apply the logged rotations to the rows of C^T, one 64-column tile per
 // work-group and four columns per wave.  Lane q holds, for the wave's four
@@ -2540,141 +2427,6 @@ __global__ void __launch_bounds__(1024)
       const int r = e / tile_w, cc = e - r * tile_w, col = c0 + cc;
       if (col < nv) V[(long long)(r0 + r) * nv + col] = st[r * ld + cc];
     }
-  }
-}
-
-// Apply kernel of the super-block ordering: per super-round, the product M_p
-// of super-pair p's logged rotations (a 16 x 16 orthogonal matrix on its
-// rows: 8 of super-block I, then 8 of J) is formed and multiplied onto those
-// rows of the C^T tile with v_mfma_f64_16x16x4.  One 64-column tile per
-// work-group of eight waves, held in LDS for the whole launch.
-//  * Waves 0-3 form the M_p: lane 16 (p mod 4) + c holds column c of M_p in
-//    registers, starts from the identity and applies the super-round's
-//    rotations as row operations in their logged order (for super-round 0
-//    the block step, then the three intra rounds; for the others the four
-//    cross rounds), every row index a compile-time constant; then M_p goes
-//    to LDS in the operand order of the matrix instruction.
-//  * All waves then take (super-pair, 16-column block) units: rows_new =
-//    M_p rows_old as four v_mfma_f64_16x16x4 steps over the 16 rows.
-// Super-pairs are disjoint, so the units of a super-round touch disjoint
-// parts of the tile; two barriers per super-round.
-constexpr int SBA_THREADS = 512;
-constexpr int SB_INTRA[3][2][2] = {{{0, 3}, {1, 2}}, {{0, 1}, {2, 3}}, {{0, 2}, {3, 1}}};
-
-__device__ inline void sb_rows4(double (&M)[16], int bx, int by, const double2* w) {
-  jq_apply2(M[2 * bx], M[2 * by], w[0]);
-  jq_apply2(M[2 * bx + 1], M[2 * by + 1], w[1]);
-  jq_apply2(M[2 * bx], M[2 * by + 1], w[2]);
-  jq_apply2(M[2 * bx + 1], M[2 * by], w[3]);
-}
-
-size_t apply_sb_lds_bytes(int n) {
-  const size_t m = (size_t)((n + 15) & ~15);
-  return (m * 64 + (m / 16) * 256) * sizeof(double);
-}
-
-__global__ void __launch_bounds__(SBA_THREADS)
-    k_apply_sb(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double2* __restrict__ logbuf,
-               long long log_stride, const int* nlog) {
-  extern __shared__ double2 lds_raw[];
-  int sl, tcol;
-  xcd_slot_tile(blockIdx.x, tiles_per_sys, sl, tcol);
-  if (sl >= nl) return;
-  const int si = list[sl];
-  if (bt.status[si] != 0) return;
-  const int nsw = nlog[si];
-  if (nsw <= 0) return;
-  const SysDesc d = bt.desc[si];
-  const int n = d.nao;
-  const int c0 = tcol * 64;
-  if (c0 >= n) return;
-  const int m = (n + 15) & ~15, nb2 = m / 2, G = nb2 / SB_G, NP = G / 2;
-  double* st = reinterpret_cast<double*>(lds_raw);  // [m][64] tile
-  double* ms = st + m * 64;                          // [NP][4][64] M_p, operand order
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  double* V = bt.Ct + d.mat_off;
-  for (int e = tid; e < m * 64; e += SBA_THREADS) {
-    const int r = e >> 6, col = c0 + (e & 63);
-    st[e] = (r < n && col < n) ? V[(long long)r * n + col] : 0.0;
-  }
-  const double2* lg = logbuf + (long long)si * log_stride;
-  const long long swe = jq_sweep_entries(m);
-  for (int sw = 0; sw < nsw; ++sw) {
-    const double2* ls = lg + (long long)sw * swe;
-    for (int s = 0; s < G; ++s) {
-      const int o = s == 0 ? 0 : s - 1;
-      if (wave < 4) {
-        const int p = 4 * wave + (lane >> 4), c = lane & 15;
-        if (p < NP) {
-          double M[16];
-#pragma unroll
-          for (int i = 0; i < 16; ++i) M[i] = i == c ? 1.0 : 0.0;
-          const int I = sb_circ(p, o, G), J = sb_circ(G - 1 - p, o, G);
-          double2 w[4];
-          if (s == 0) {
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-              const double2 wb = ls[b < 4 ? I * SB_G + b : J * SB_G + b - 4];
-              jq_apply2(M[2 * b], M[2 * b + 1], wb);
-            }
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-              const double2* lr = ls + nb2 + (long long)r * m + 4 * (p * SB_G);
-#pragma unroll
-              for (int j = 0; j < 4; ++j) {
-#pragma unroll
-                for (int t = 0; t < 4; ++t) w[t] = lr[4 * j + t];
-                const int side = j < 2 ? 0 : 4, jj = j & 1;
-                sb_rows4(M, side + SB_INTRA[r][jj][0], side + SB_INTRA[r][jj][1], w);
-              }
-            }
-          } else {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const int rd = SB_G - 1 + SB_G * (s - 1) + k;
-              const double2* lr = ls + nb2 + (long long)rd * m + 4 * (p * SB_G);
-#pragma unroll
-              for (int j = 0; j < 4; ++j) {
-#pragma unroll
-                for (int t = 0; t < 4; ++t) w[t] = lr[4 * j + t];
-                sb_rows4(M, j, 4 + ((j + k) & 3), w);
-              }
-            }
-          }
-          // element (i, c) of M_p feeds k-step c / 4 at lane i + 16 (c mod 4)
-          double* mp = ms + (p * 4 + (c >> 2)) * 64 + 16 * (c & 3);
-#pragma unroll
-          for (int i = 0; i < 16; ++i) mp[i] = M[i];
-        }
-      }
-      __syncthreads();  // M_p in LDS (and, before the first super-round, the tile)
-      for (int u = wave; u < 4 * NP; u += SBA_THREADS / 64) {
-        const int p = u >> 2, cb = u & 3;
-        const int I = sb_circ(p, o, G), J = sb_circ(G - 1 - p, o, G);
-        const int col = 16 * cb + (lane & 15);
-        v4d acc = (v4d){0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int lr = 4 * t + (lane >> 4);
-          const int gr = lr < 8 ? 8 * I + lr : 8 * J + lr - 8;
-          const double a = ms[(p * 4 + t) * 64 + lane];
-          const double b = st[gr * 64 + col];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int lr = (lane >> 4) + 4 * r;
-          const int gr = lr < 8 ? 8 * I + lr : 8 * J + lr - 8;
-          st[gr * 64 + col] = acc[r];
-        }
-      }
-      __syncthreads();  // rows updated before the next super-round reads them
-    }
-  }
-  for (int e = tid; e < n * 64; e += SBA_THREADS) {
-    const int r = e >> 6, col = c0 + (e & 63);
-    if (col < n) V[(long long)r * n + col] = st[e];
   }
 }
 
