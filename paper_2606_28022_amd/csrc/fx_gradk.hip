@@ -45,80 +45,125 @@ __device__ inline double gamma_and_deriv(const DevGlobals& g, double R, double e
   return gam;
 }
 
-// overlap block and its derivative with respect to R = A - B
-__device__ void atom_pair_overlap_deriv(const DevElem& ea, const DevElem& eb, const double Rv[3],
-                                        double S[MAXAO_EL][MAXAO_EL], double dS[3][MAXAO_EL][MAXAO_EL]) {
+// The overlap block of an atom pair, R = A - B (STO-6G s and p shells; a
+// second s shell orthogonalised against the first, |s2'> = N (|s2> - S12 |s1>))
+// and the contraction sum_ij W_ij dS_ij / dR of its
+// derivative with a weight block W, added to g, without forming dS.  The
+// orthogonalisation of a second s shell is a fixed linear map T on the AO
+// index (S' = T_a S T_b^T), so the weights are moved through it once
+// (W' = T_a^T W T_b) and contracted with the raw derivatives.  Per shell pair
+// every primitive term has the form s00 times a polynomial in R with
+// primitive-dependent coefficients fa = -b / (a + b), fb = a / (a + b),
+// h = 1 / (2 (a + b)) and d s00 / dR_k = -2 mu R_k s00, so the primitive sums
+// reduce to at most four scalars, and the block and the contraction follow
+// from them and from R:
+//   s s:  S = sum s00;                 g_k += W R_k sum(-2 mu s00)
+//   p s:  S_u = R_u sum(fa s00);       g_k += W_k sum(fa s00) + (W.R) R_k sum(-2 mu fa s00)
+//   s p:  likewise with fb and the columns of W
+//   p p:  S_uv = R_u R_v sum(fa fb s00) + delta_uv sum(h s00);
+//         g_k += ((W R)_k + (W^T R)_k) sum(fa fb s00)
+//                + R_k (R.W.R sum(-2 mu fa fb s00) + tr W sum(-2 mu h s00))
+__device__ void atom_pair_overlap_contract(const DevElem& ea, const DevElem& eb, const double Rv[3],
+                                           double (&W)[MAXAO_EL][MAXAO_EL], double S[MAXAO_EL][MAXAO_EL],
+                                           double g[3]) {
   const double PI = 3.14159265358979323846;
-  double R2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
-  for (int i = 0; i < MAXAO_EL; ++i)
+  const double R2 = Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2];
+  if (ea.orth) {
+#pragma unroll
     for (int j = 0; j < MAXAO_EL; ++j) {
-      S[i][j] = 0.0;
-      for (int k = 0; k < 3; ++k) dS[k][i][j] = 0.0;
+      W[0][j] -= ea.orthN * ea.orthS12 * W[1][j];
+      W[1][j] *= ea.orthN;
     }
-  // shell 0 is an s shell at AO 0 and shell 1 (if any) starts at AO 1 (the
-  // parameter loader checks this), so every array index below is a
-  // compile-time constant and the blocks stay in registers
+  }
+  if (eb.orth) {
+#pragma unroll
+    for (int i = 0; i < MAXAO_EL; ++i) {
+      W[i][0] -= eb.orthN * eb.orthS12 * W[i][1];
+      W[i][1] *= eb.orthN;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < MAXAO_EL; ++i)
+#pragma unroll
+    for (int j = 0; j < MAXAO_EL; ++j) S[i][j] = 0.0;
 #pragma unroll
   for (int sa = 0; sa < MAXSH_EL; ++sa)
 #pragma unroll
     for (int sb = 0; sb < MAXSH_EL; ++sb) {
       if (sa >= ea.nsh || sb >= eb.nsh) continue;
       const int la = ea.l[sa], lb = eb.l[sb];
-      const int oa = sa, ob = sb;
+      const int kind = 2 * la + lb;  // 0 s s, 1 s p, 2 p s, 3 p p
+      // shell-pair sums over the primitives
+      double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+#pragma unroll 1
       for (int i = 0; i < NPRIM; ++i) {
-        double a = ea.alpha[sa][i];
+        const double a = ea.alpha[sa][i];
         for (int j = 0; j < NPRIM; ++j) {
-          double b = eb.alpha[sb][j];
-          double ip = 1.0 / (a + b);
-          double mu = a * b * ip;
-          double s00 = ea.coef[sa][i] * eb.coef[sb][j] * PI * ip * sqrt(PI * ip) * exp(-mu * R2);
-          double ds00[3];
-          for (int k = 0; k < 3; ++k) ds00[k] = -2.0 * mu * Rv[k] * s00;
-          double fa = -b * ip, fb = a * ip;
-          if (la == 0 && lb == 0) {
-            S[oa][ob] += s00;
-            for (int k = 0; k < 3; ++k) dS[k][oa][ob] += ds00[k];
-          } else if (la == 1 && lb == 0) {
-            for (int u = 0; u < 3; ++u) {
-              S[oa + u][ob] += fa * Rv[u] * s00;
-              for (int k = 0; k < 3; ++k) dS[k][oa + u][ob] += (u == k ? fa * s00 : 0.0) + fa * Rv[u] * ds00[k];
-            }
-          } else if (la == 0 && lb == 1) {
-            for (int v = 0; v < 3; ++v) {
-              S[oa][ob + v] += fb * Rv[v] * s00;
-              for (int k = 0; k < 3; ++k) dS[k][oa][ob + v] += (v == k ? fb * s00 : 0.0) + fb * Rv[v] * ds00[k];
-            }
+          const double b = eb.alpha[sb][j];
+          const double ip = 1.0 / (a + b);
+          const double mu = a * b * ip;
+          const double s00 = ea.coef[sa][i] * eb.coef[sb][j] * PI * ip * sqrt(PI * ip) * exp(-mu * R2);
+          const double d00 = -2.0 * mu * s00;
+          const double fa = -b * ip, fb = a * ip;
+          if (kind == 0) {
+            t0 += s00;
+            t1 += d00;
+          } else if (kind == 2) {
+            t0 += fa * s00;
+            t1 += fa * d00;
+          } else if (kind == 1) {
+            t0 += fb * s00;
+            t1 += fb * d00;
           } else {
-            double h = 0.5 * ip;
-            for (int u = 0; u < 3; ++u)
-              for (int v = 0; v < 3; ++v) {
-                double core = fa * Rv[u] * fb * Rv[v] + (u == v ? h : 0.0);
-                S[oa + u][ob + v] += core * s00;
-                for (int k = 0; k < 3; ++k) {
-                  double dcore = (u == k ? fa * fb * Rv[v] : 0.0) + (v == k ? fa * Rv[u] * fb : 0.0);
-                  dS[k][oa + u][ob + v] += dcore * s00 + core * ds00[k];
-                }
-              }
+            const double ff = fa * fb, h = 0.5 * ip;
+            t0 += ff * s00;
+            t1 += ff * d00;
+            t2 += h * s00;
+            t3 += h * d00;
           }
         }
       }
+      const int oa = sa, ob = sb;
+      if (kind == 0) {
+        S[oa][ob] = t0;
+        for (int k = 0; k < 3; ++k) g[k] += W[oa][ob] * Rv[k] * t1;
+      } else if (kind == 2) {
+        double wr = 0.0;
+        for (int u = 0; u < 3; ++u) {
+          S[oa + u][ob] = Rv[u] * t0;
+          wr += W[oa + u][ob] * Rv[u];
+        }
+        for (int k = 0; k < 3; ++k) g[k] += W[oa + k][ob] * t0 + wr * Rv[k] * t1;
+      } else if (kind == 1) {
+        double wc = 0.0;
+        for (int v = 0; v < 3; ++v) {
+          S[oa][ob + v] = Rv[v] * t0;
+          wc += W[oa][ob + v] * Rv[v];
+        }
+        for (int k = 0; k < 3; ++k) g[k] += W[oa][ob + k] * t0 + wc * Rv[k] * t1;
+      } else {
+        double rw = 0.0, tr = 0.0, wr[3], wc[3];
+        for (int u = 0; u < 3; ++u) {
+          wr[u] = 0.0;
+          wc[u] = 0.0;
+          for (int v = 0; v < 3; ++v) {
+            S[oa + u][ob + v] = Rv[u] * Rv[v] * t0 + (u == v ? t2 : 0.0);
+            wr[u] += W[oa + u][ob + v] * Rv[v];
+            wc[u] += W[oa + v][ob + u] * Rv[v];
+          }
+          rw += wr[u] * Rv[u];
+          tr += W[oa + u][ob + u];
+        }
+        for (int k = 0; k < 3; ++k) g[k] += (wr[k] + wc[k]) * t0 + Rv[k] * (rw * t1 + tr * t3);
+      }
     }
-  // second s shell orthogonalised against the first (AOs 0 and 1)
   if (ea.orth) {
 #pragma unroll
-    for (int j = 0; j < MAXAO_EL; ++j) {
-      S[1][j] = ea.orthN * (S[1][j] - ea.orthS12 * S[0][j]);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) dS[k][1][j] = ea.orthN * (dS[k][1][j] - ea.orthS12 * dS[k][0][j]);
-    }
+    for (int j = 0; j < MAXAO_EL; ++j) S[1][j] = ea.orthN * (S[1][j] - ea.orthS12 * S[0][j]);
   }
   if (eb.orth) {
 #pragma unroll
-    for (int i = 0; i < MAXAO_EL; ++i) {
-      S[i][1] = eb.orthN * (S[i][1] - eb.orthS12 * S[i][0]);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) dS[k][i][1] = eb.orthN * (dS[k][i][1] - eb.orthS12 * dS[k][i][0]);
-    }
+    for (int i = 0; i < MAXAO_EL; ++i) S[i][1] = eb.orthN * (S[i][1] - eb.orthS12 * S[i][0]);
   }
 }
 
@@ -128,7 +173,7 @@ __device__ void atom_pair_overlap_deriv(const DevElem& ea, const DevElem& eb, co
 // at fixed CN, for every atom a of the system, and the CN sensitivity
 // F_a = d/dCN_a of the D_H term.  Results are multiplied by the system weight
 // and written (or added) to the per-system atom arrays.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
     k_grad_contract(DevSystem sys, DevBatch bt, const int* list, const double* DHp, const double* DSp,
                                 const double* gx, const double* gy, const double* wsys, int with_rep, int accumulate,
                                 double* g_out, double* F_out, double* scratch) {
@@ -165,8 +210,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
                     sys.xyz[3 * A + 2] - sys.xyz[3 * B + 2]};
     double R = sqrt(Rv[0] * Rv[0] + Rv[1] * Rv[1] + Rv[2] * Rv[2]);
     double uR[3] = {Rv[0] / R, Rv[1] / R, Rv[2] / R};
-    double S[MAXAO_EL][MAXAO_EL], dS[3][MAXAO_EL][MAXAO_EL];
-    atom_pair_overlap_deriv(ea, eb, Rv, S, dS);
     double den = ea.EN - eb.EN;
     double enf = 1.0 + sys.g.kEN * den * den;
     double rcov = ea.rcov + eb.rcov;
@@ -187,17 +230,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
         const double pa = 1.0 + ea.kpoly[sa] * x, pbb = 1.0 + eb.kpoly[sb] * x;
         fac[sa][sb] = sys.g.KAB * kll * enf * 0.5 * (ha + hb) * pa * pbb;
       }
+    // d/dR of sum (D_H H0 + D_S S) over the pair's overlap block: weights
+    // 2 (fac D_H + D_S) (both triangles) contracted with dS / dR
+    double W[MAXAO_EL][MAXAO_EL], S[MAXAO_EL][MAXAO_EL];
+#pragma unroll
+    for (int i = 0; i < MAXAO_EL; ++i)
+#pragma unroll
+      for (int j = 0; j < MAXAO_EL; ++j) {
+        W[i][j] = 0.0;
+        if (i >= ea.nao || j >= eb.nao) continue;
+        const int sa = i == 0 ? 0 : 1, sb = j == 0 ? 0 : 1;
+        const long long mn = (long long)(oa + i) * n + ob + j;
+        W[i][j] = 2.0 * (fac[sa][sb] * DH[mn] + DS[mn]);
+      }
+    atom_pair_overlap_contract(ea, eb, Rv, W, S, g);
 #pragma unroll
     for (int i = 0; i < MAXAO_EL; ++i)
 #pragma unroll
       for (int j = 0; j < MAXAO_EL; ++j) {
         if (i >= ea.nao || j >= eb.nao) continue;
         const int sa = i == 0 ? 0 : 1, sb = j == 0 ? 0 : 1;
-        const long long mn = (long long)(oa + i) * n + ob + j;
-        const double dh = DH[mn], ds = DS[mn];
-        const double w = fac[sa][sb] * dh + ds;
-        for (int k = 0; k < 3; ++k) g[k] += 2.0 * w * dS[k][i][j];
-        sumDHS[sa][sb] += dh * S[i][j];
+        sumDHS[sa][sb] += DH[(long long)(oa + i) * n + ob + j] * S[i][j];
       }
 #pragma unroll
     for (int sa = 0; sa < MAXSH_EL; ++sa)
