@@ -116,6 +116,11 @@ __global__ void k_pair_contacts(DevSystem sys, const int* frag_atoms, const int*
 // ---------------------------------------------------------------------------
 // overlap block between two atoms (raw contracted shells, then the on-site
 // orthogonalisation), R = A - B.  out is nao_a x nao_b, row-major, ld = 4.
+// Every primitive term of a shell pair is s00 times a polynomial in R whose
+// coefficients depend on the primitive pair only through fa = -b / (a + b),
+// fb = a / (a + b) and h = 1 / (2 (a + b)): s s sum s00; p s R_u sum(fa s00);
+// s p R_v sum(fb s00); p p R_u R_v sum(fa fb s00) + delta_uv sum(h s00).  So
+// the primitive loop accumulates at most two scalars per shell pair.
 __device__ void atom_pair_overlap(const DevElem& ea, const DevElem& eb, double Rx, double Ry,
                                   double Rz, double out[MAXAO_EL][MAXAO_EL]) {
   const double PI = 3.14159265358979323846;
@@ -131,31 +136,38 @@ __device__ void atom_pair_overlap(const DevElem& ea, const DevElem& eb, double R
 #pragma unroll
     for (int sb = 0; sb < MAXSH_EL; ++sb) {
       if (sa >= ea.nsh || sb >= eb.nsh) continue;
-      const int la = ea.l[sa], lb = eb.l[sb];
-      const int oa = sa, ob = sb;
+      const int kind = 2 * ea.l[sa] + eb.l[sb];  // 0 s s, 1 s p, 2 p s, 3 p p
+      double t0 = 0.0, t2 = 0.0;
+#pragma unroll 1
       for (int i = 0; i < NPRIM; ++i) {
-        double a = ea.alpha[sa][i];
+        const double a = ea.alpha[sa][i];
         for (int j = 0; j < NPRIM; ++j) {
-          double b = eb.alpha[sb][j];
-          double p = a + b;
-          double ip = 1.0 / p;
-          double mu = a * b * ip;
-          double s00 = ea.coef[sa][i] * eb.coef[sb][j] * PI * ip * sqrt(PI * ip) * exp(-mu * R2);
-          if (la == 0 && lb == 0) {
-            out[oa][ob] += s00;
-          } else if (la == 1 && lb == 0) {
-            double f = -b * ip * s00;
-            for (int k = 0; k < 3; ++k) out[oa + k][ob] += f * Rv[k];
-          } else if (la == 0 && lb == 1) {
-            double f = a * ip * s00;
-            for (int k = 0; k < 3; ++k) out[oa][ob + k] += f * Rv[k];
+          const double b = eb.alpha[sb][j];
+          const double ip = 1.0 / (a + b);
+          const double mu = a * b * ip;
+          const double s00 = ea.coef[sa][i] * eb.coef[sb][j] * PI * ip * sqrt(PI * ip) * exp(-mu * R2);
+          if (kind == 0) {
+            t0 += s00;
+          } else if (kind == 2) {
+            t0 += -b * ip * s00;
+          } else if (kind == 1) {
+            t0 += a * ip * s00;
           } else {
-            double fa = -b * ip, fb = a * ip, h = 0.5 * ip;
-            for (int u = 0; u < 3; ++u)
-              for (int v = 0; v < 3; ++v)
-                out[oa + u][ob + v] += (fa * Rv[u] * fb * Rv[v] + (u == v ? h : 0.0)) * s00;
+            t0 += (-b * ip) * (a * ip) * s00;
+            t2 += 0.5 * ip * s00;
           }
         }
+      }
+      const int oa = sa, ob = sb;
+      if (kind == 0) {
+        out[oa][ob] = t0;
+      } else if (kind == 2) {
+        for (int k = 0; k < 3; ++k) out[oa + k][ob] = Rv[k] * t0;
+      } else if (kind == 1) {
+        for (int k = 0; k < 3; ++k) out[oa][ob + k] = Rv[k] * t0;
+      } else {
+        for (int u = 0; u < 3; ++u)
+          for (int v = 0; v < 3; ++v) out[oa + u][ob + v] = Rv[u] * Rv[v] * t0 + (u == v ? t2 : 0.0);
       }
     }
   }
@@ -183,7 +195,7 @@ __device__ inline double h0_prefactor(const DevGlobals& g, const DevElem& ea, in
 
 // ---------------------------------------------------------------------------
 // per-system S, H0, gamma and repulsion; one work-group per system.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
     k_build_system(DevSystem sys, DevBatch bt, const int* list) {
   int si = list ? list[blockIdx.x] : blockIdx.x;
   const SysDesc d = bt.desc[si];
@@ -209,11 +221,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
       for (int k = 0; k < e.nao_sh[s]; ++k) H[(long long)(o + e.ao0[s] + k) * n + o + e.ao0[s] + k] = h;
     }
   }
-  // off-diagonal atom blocks
-  const int np = d.nat * d.nat;
+  // off-diagonal atom blocks: the unordered pairs a < b, row a holding
+  // pairs off(a) = a nat - a (a + 1) / 2 .. off(a + 1) - 1
+  const int nat = d.nat, np = nat * (nat - 1) / 2;
   for (int idx = threadIdx.x; idx < np; idx += blockDim.x) {
-    int a = idx / d.nat, b = idx - a * d.nat;
-    if (b <= a) continue;
+    const double c = 2.0 * nat - 1.0;
+    int a = (int)floor(0.5 * (c - sqrt(c * c - 8.0 * idx)));
+    a = max(0, min(a, nat - 2));
+    while (a > 0 && a * nat - a * (a + 1) / 2 > idx) --a;
+    while ((a + 1) * nat - (a + 1) * (a + 2) / 2 <= idx) ++a;
+    const int b = idx - (a * nat - a * (a + 1) / 2) + a + 1;
     int A = atoms[a], B = atoms[b];
     const DevElem& ea = sys.elems[sys.elem[A]];
     const DevElem& eb = sys.elems[sys.elem[B]];
