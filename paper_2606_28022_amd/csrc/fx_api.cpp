@@ -472,6 +472,8 @@ void Ctx::init_device() {
   for (const void* k : {reinterpret_cast<const void*>(k_jacobi_lds<double>),
                         reinterpret_cast<const void*>(k_jacobi_lds<float>)})
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_resp_Q), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds_max);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_resp_M), hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds_max);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_precond_build),
@@ -571,6 +573,7 @@ bool Ctx::monomer_response_setup() {
     int nsh = 0;
     for (const auto& d : b.h_desc) nsh = std::max(nsh, d.nsh);
     if ((long long)resp_M_lds_bytes(nsh) > (long long)lds_max) return false;
+    if ((long long)resp_Q_lds_bytes(b.max_nao) > (long long)lds_max) return false;
   }
   DevBatch dmb = b.dev();
   resp_nocc.upload(nocc);
@@ -584,7 +587,8 @@ bool Ctx::monomer_response_setup() {
   hipLaunchKernelGGL(k_mo_order, dim3(b.nsys), dim3(256), 0, stream, dmb, resp_nocc.p, resp_order.p);
   // (S C)^T = Ct S into the GEMM scratch
   gemm_batch(b, dmb, b.nsys, b.d_list.p, 0, b.Ct.p, b.S.p, b.Tm.p, (const double*)nullptr, b.gemm_gflop_all());
-  hipLaunchKernelGGL(k_resp_Q, dim3(b.nsys), dim3(256), 0, stream, dev_system(), dmb, b.Tm.p, resp_order.p,
+  hipLaunchKernelGGL(k_resp_Q, dim3(b.nsys), dim3(256), (unsigned)resp_Q_lds_bytes(b.max_nao), stream, dev_system(),
+                     dmb, b.Tm.p, resp_order.p,
                      resp_nocc.p, resp_qoff.p, resp_Q.p);
   hipLaunchKernelGGL(k_resp_M, dim3(b.nsys), dim3(256), resp_M_lds(b), stream, dmb, resp_order.p, resp_nocc.p, resp_qoff.p,
                      resp_Q.p, resp_M.p);

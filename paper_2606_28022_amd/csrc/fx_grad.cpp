@@ -244,8 +244,8 @@ void Ctx::gradient() {
       // (SC)^T = Ct S into G1
       gemm_batch(b, dmb, (int)b.nsys, b.d_list.p, 0, b.Ct.p, b.S.p, G1.p, (const double*)nullptr,
                  b.gemm_gflop_all());
-      hipLaunchKernelGGL(k_resp_Q, dim3(b.nsys), dim3(256), 0, stream, ds, dmb, G1.p, order.p, d_nocc.p, d_qoff.p,
-                         Q.p);
+      hipLaunchKernelGGL(k_resp_Q, dim3(b.nsys), dim3(256), (unsigned)resp_Q_lds_bytes(b.max_nao), stream, ds, dmb,
+                         G1.p, order.p, d_nocc.p, d_qoff.p, Q.p);
       hipLaunchKernelGGL(k_resp_M, dim3(b.nsys), dim3(256), resp_M_lds(b), stream, dmb, order.p, d_nocc.p, d_qoff.p, Q.p, M.p);
     }
     hipLaunchKernelGGL(k_resp_R, dim3(b.nsys), dim3(256), 0, stream, ds, dmb, p_M, Wk.p, R.p);

@@ -166,6 +166,8 @@ __global__ void k_resp_Q(DevSystem sys, DevBatch bt, const double* SCt, const in
 __global__ void k_resp_M(DevBatch bt, const int* order, const int* nocc, const long long* qoff, const double* Q,
                          double* M);
 size_t resp_M_lds_bytes(int nsh);
+constexpr int RQ_CH = 16;        // AOs per staged run of k_resp_Q
+size_t resp_Q_lds_bytes(int n);  // dynamic LDS of k_resp_Q for systems of up to n AOs
 __global__ void k_resp_R(DevSystem sys, DevBatch bt, const double* M, double* Wk, double* R);
 __global__ void k_resp_apply(DevBatch bt, const double* R, const double* M, const double* y, double* w, double* u);
 __global__ void k_resp_Z(DevBatch bt, const int* order, const int* nocc, const long long* qoff, const double* Q,

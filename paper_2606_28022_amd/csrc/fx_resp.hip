@@ -34,42 +34,81 @@ __global__ void k_mo_order(DevBatch bt, const int* nocc, int* order) {
   (void)nocc;
 }
 
+// AO range of local shell s of a system: first AO and count
+__device__ inline void shell_aos(const DevSystem& sys, const DevBatch& bt, const SysDesc& d, int s, int& mu0,
+                                 int& nao) {
+  const int la = bt.sys_sh_atom[d.sh_off + s];
+  const DevElem& el = sys.elems[sys.elem[bt.sys_atoms[d.atom_off + la]]];
+  const int ls = s - bt.sys_atom_sh0[d.atom_off + la];
+  mu0 = bt.sys_atom_ao0[d.atom_off + la] + el.ao0[ls];
+  nao = el.nao_sh[ls];
+}
+
 // Q[s][a'][i'] = sum_{mu in s} (C_mu,a (SC)_mu,i + C_mu,i (SC)_mu,a)
-// (Ct rows are MOs; SCt = Ct S holds (SC)^T).
-__global__ void k_resp_Q(DevSystem sys, DevBatch bt, const double* SCt, const int* order, const int* nocc,
-                         const long long* qoff, double* Q) {
+// (Ct rows are MOs; SCt = Ct S holds (SC)^T).  The shells are taken in runs
+// of at most RQ_CH consecutive AOs; the run's columns of Ct and SCt (every
+// MO) are staged in LDS with coalesced row-segment reads, then each shell's
+// nv x no block of Q is written with consecutive addresses.
+size_t resp_Q_lds_bytes(int n) { return (size_t)2 * RQ_CH * n * sizeof(double) + (size_t)n * sizeof(int); }
+
+__global__ void __launch_bounds__(256) k_resp_Q(DevSystem sys, DevBatch bt, const double* SCt, const int* order,
+                                                const int* nocc, const long long* qoff, double* Q) {
   const int si = blockIdx.x;
   const SysDesc d = bt.desc[si];
   const int n = d.nao, no = nocc[si], nv = n - no, ns = d.nsh;
   const double* Ct = bt.Ct + d.mat_off;
   const double* T = SCt + d.mat_off;
-  const int* ord = order + d.ao_off;
-  const long long tot = (long long)ns * nv * no;
-  for (long long idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-    int s = (int)(idx / ((long long)nv * no));
-    int r = (int)(idx % ((long long)nv * no));
-    int ap = r / no, ip = r % no;
-    int a = ord[no + ap], i = ord[ip];
-    int la = bt.sys_sh_atom[d.sh_off + s];
-    int A = bt.sys_atoms[d.atom_off + la];
-    const DevElem& el = sys.elems[sys.elem[A]];
-    int ls = s - bt.sys_atom_sh0[d.atom_off + la];
-    int mu0 = bt.sys_atom_ao0[d.atom_off + la] + el.ao0[ls];
-    double v = 0.0;
-    for (int u = 0; u < el.nao_sh[ls]; ++u) {
-      int mu = mu0 + u;
-      v += Ct[(long long)a * n + mu] * T[(long long)i * n + mu] + Ct[(long long)i * n + mu] * T[(long long)a * n + mu];
+  extern __shared__ double rq_lds[];
+  double* cs = rq_lds;                                  // [RQ_CH][n]: C of the run's AOs, every MO
+  double* ts = cs + RQ_CH * n;                          // [RQ_CH][n]: SC likewise
+  int* ord = reinterpret_cast<int*>(ts + RQ_CH * n);    // [n]
+  for (int k = threadIdx.x; k < n; k += blockDim.x) ord[k] = order[d.ao_off + k];
+  const int K = nv * no;
+  double* Qs = Q + qoff[si];
+  for (int s = 0; s < ns;) {
+    int mua, na;
+    shell_aos(sys, bt, d, s, mua, na);
+    int s1 = s + 1, mub = mua + na;
+    while (s1 < ns) {
+      int m1, n1;
+      shell_aos(sys, bt, d, s1, m1, n1);
+      if (m1 + n1 - mua > RQ_CH) break;
+      mub = m1 + n1;
+      ++s1;
     }
-    Q[qoff[si] + idx] = v;
+    const int w = mub - mua;
+    __syncthreads();  // the previous run is consumed (and ord written)
+    for (int e = threadIdx.x; e < n * w; e += blockDim.x) {
+      const int r = e / w, u = e - r * w;
+      cs[u * n + r] = Ct[(long long)r * n + mua + u];
+      ts[u * n + r] = T[(long long)r * n + mua + u];
+    }
+    __syncthreads();
+    for (int t = s; t < s1; ++t) {
+      int m0, nu;
+      shell_aos(sys, bt, d, t, m0, nu);
+      const int u0 = m0 - mua;
+      double* Qt = Qs + (long long)t * K;
+      for (int idx = threadIdx.x; idx < K; idx += blockDim.x) {
+        const int ap = idx / no, ip = idx - ap * no;
+        const int a = ord[no + ap], i = ord[ip];
+        double v = 0.0;
+        for (int u = u0; u < u0 + nu; ++u) v += cs[u * n + a] * ts[u * n + i] + cs[u * n + i] * ts[u * n + a];
+        Qt[idx] = v;
+      }
+    }
+    s = s1;
   }
 }
 
-// M_st = sum_{a'i'} Q_s,a'i' Q_t,a'i' / (eps_a - eps_i)   (into the nsh^2 pool)
-// M = sum_ai Q_ai Q_ai^T / (eps_a - eps_i), per system: the (a, i) index is
-// staged through LDS 64 columns at a time together with the inverse gaps;
-// each thread accumulates a fixed set of upper-triangle entries (s <= t) in
-// registers over all chunks in order, then mirrors them.
-constexpr int RM_KC = 64, RM_LD = RM_KC + 1, RM_MAXP = 20;
+// M = sum_ai Q_ai Q_ai^T / (eps_a - eps_i), per system (into the nsh^2
+// pool): the (a, i) index is staged through LDS 64 columns at a time
+// together with the inverse gaps; each thread accumulates a 4 x 4 block of
+// the upper block triangle in registers over all chunks in order (eight LDS
+// reads per sixteen products), then writes it and its mirror (on the
+// diagonal blocks the upper entries, mirrored, so that M is exactly
+// symmetric).
+constexpr int RM_KC = 64, RM_LD = RM_KC + 1;
 __global__ void __launch_bounds__(256) k_resp_M(DevBatch bt, const int* order, const int* nocc, const long long* qoff,
                                                 const double* Q, double* M) {
   const int si = blockIdx.x;
@@ -80,37 +119,34 @@ __global__ void __launch_bounds__(256) k_resp_M(DevBatch bt, const int* order, c
   const long long K = (long long)nv * no;
   const double* Qs = Q + qoff[si];
   extern __shared__ double rm_lds[];
-  double* qt = rm_lds;                   // [ns][RM_LD]
-  double* idn = rm_lds + ns * RM_LD;     // [RM_KC]
-  const int npairs = ns * (ns + 1) / 2;
+  const int nb = (ns + 3) / 4, nrow = 4 * nb;
+  double* qt = rm_lds;                   // [4 nb][RM_LD] (rows past ns zero)
+  double* idn = rm_lds + nrow * RM_LD;   // [RM_KC]
+  const int nblk = nb * (nb + 1) / 2;
   double* Mo = M + d.gam_off;
-  // pairs in groups of RM_MAXP per thread; Q is streamed once per group
-  for (int g0 = 0; g0 < npairs; g0 += RM_MAXP * (int)blockDim.x) {
-    double acc[RM_MAXP];
-    int ps[RM_MAXP], pt[RM_MAXP];
-#pragma unroll
-    for (int r = 0; r < RM_MAXP; ++r) {
-      acc[r] = 0.0;
-      const int idx = g0 + threadIdx.x + r * blockDim.x;
-      int s = 0, t = 0;
-      if (idx < npairs) {
-        // upper-triangle pair number idx -> (s, t), s <= t
-        int rem = idx;
-        while (rem >= ns - s) {
-          rem -= ns - s;
-          ++s;
-        }
-        t = s + rem;
+  for (int g0 = 0; g0 < nblk; g0 += (int)blockDim.x) {
+    const int blk = g0 + (int)threadIdx.x;
+    int bs = 0, bb = 0;
+    if (blk < nblk) {
+      // upper-triangle block number -> (bs, bb), bs <= bb
+      int rem = blk;
+      while (rem >= nb - bs) {
+        rem -= nb - bs;
+        ++bs;
       }
-      ps[r] = s;
-      pt[r] = t;
+      bb = bs + rem;
     }
+    double acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
     for (long long k0 = 0; k0 < K; k0 += RM_KC) {
       const int kn = (int)((K - k0) < RM_KC ? (K - k0) : RM_KC);
       __syncthreads();
-      for (int x = threadIdx.x; x < ns * RM_KC; x += blockDim.x) {
+      for (int x = threadIdx.x; x < nrow * RM_KC; x += blockDim.x) {
         const int sh = x / RM_KC, k = x - sh * RM_KC;
-        qt[sh * RM_LD + k] = k < kn ? Qs[(long long)sh * K + k0 + k] : 0.0;
+        qt[sh * RM_LD + k] = (k < kn && sh < ns) ? Qs[(long long)sh * K + k0 + k] : 0.0;
       }
       for (int k = threadIdx.x; k < RM_KC; k += blockDim.x) {
         double v = 0.0;
@@ -122,29 +158,40 @@ __global__ void __launch_bounds__(256) k_resp_M(DevBatch bt, const int* order, c
         idn[k] = v;
       }
       __syncthreads();
+      if (blk < nblk) {
+        const double* qa = qt + 4 * bs * RM_LD;
+        const double* qb = qt + 4 * bb * RM_LD;
+        for (int k = 0; k < kn; ++k) {
+          const double w = idn[k];
+          double a[4], b[4];
 #pragma unroll
-      for (int r = 0; r < RM_MAXP; ++r) {
-        const int idx = g0 + threadIdx.x + r * blockDim.x;
-        if (idx >= npairs) continue;
-        const double* qa = qt + ps[r] * RM_LD;
-        const double* qb = qt + pt[r] * RM_LD;
-        double v = 0.0;
-        for (int k = 0; k < kn; ++k) v += qa[k] * qb[k] * idn[k];
-        acc[r] += v;
+          for (int u = 0; u < 4; ++u) {
+            a[u] = qa[u * RM_LD + k] * w;
+            b[u] = qb[u * RM_LD + k];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+        }
       }
     }
+    if (blk < nblk) {
 #pragma unroll
-    for (int r = 0; r < RM_MAXP; ++r) {
-      const int idx = g0 + threadIdx.x + r * blockDim.x;
-      if (idx >= npairs) continue;
-      Mo[(long long)ps[r] * ns + pt[r]] = acc[r];
-      Mo[(long long)pt[r] * ns + ps[r]] = acc[r];
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int s = 4 * bs + u, t = 4 * bb + v;
+          if (s >= ns || t >= ns || (bs == bb && v < u)) continue;
+          Mo[(long long)s * ns + t] = acc[u][v];
+          Mo[(long long)t * ns + s] = acc[u][v];
+        }
     }
   }
 }
 
 // dynamic LDS of k_resp_M for systems of up to nsh shells
-size_t resp_M_lds_bytes(int nsh) { return ((size_t)nsh * RM_LD + RM_KC) * sizeof(double); }
+size_t resp_M_lds_bytes(int nsh) { return ((size_t)(4 * ((nsh + 3) / 4)) * RM_LD + RM_KC) * sizeof(double); }
 
 // R = (1 + G M)^-1 with G = gamma - 2 Gamma_A dq_A on same-atom shell blocks
 // (Gauss-Jordan with partial pivoting on a work copy in Wk; one work-group).
