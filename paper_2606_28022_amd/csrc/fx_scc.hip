@@ -59,6 +59,18 @@ __device__ inline double block_max(double v, double* red) {
   return r;
 }
 
+// maximum over the work-group in the same way as block_sum_waves
+__device__ inline double block_max_waves(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  __syncthreads();  // red may still be read by a previous reduction
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = red[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) t = fmax(t, red[w]);
+  return t;
+}
+
 // ---------------------------------------------------------------------------
 // start of a solve: clear the iteration state of the listed systems
 // (keep_err: the residual of the previous pass stays, so the eigensolver's
@@ -1170,20 +1182,19 @@ __global__ void k_charges_mix(DevSystem sys, DevBatch bt, const int* list, doubl
         __syncthreads();
       }
   }
-  eh = block_sum(eh, red);
+  eh = block_sum_waves(eh, red);
   // shell charges
   double* qo = bt.q_out + d.sh_off;
   const double* qi = bt.q_in + d.sh_off;
-  const int* aosh = bt.sys_ao_sh + d.ao_off;
   for (int s = threadIdx.x; s < ns; s += blockDim.x) {
-    double v = 0.0;
-#pragma unroll 8
-    for (int i = 0; i < n; ++i)
-      if (aosh[i] == s) v += pop[i];
     int a = bt.sys_sh_atom[d.sh_off + s];
     int A = bt.sys_atoms[d.atom_off + a];
     const DevElem& el = sys.elems[sys.elem[A]];
     int ls = s - bt.sys_atom_sh0[d.atom_off + a];
+    // the shell's AOs are consecutive
+    const int mu0 = bt.sys_atom_ao0[d.atom_off + a] + el.ao0[ls];
+    double v = 0.0;
+    for (int i = mu0; i < mu0 + el.nao_sh[ls]; ++i) v += pop[i];
     qo[s] = v - (bt.sh_q0 ? bt.sh_q0[d.sh_off + s] : el.q0[ls]);
   }
   __syncthreads();
@@ -1211,9 +1222,9 @@ __global__ void k_charges_mix(DevSystem sys, DevBatch bt, const int* list, doubl
     int A = bt.sys_atoms[d.atom_off + a];
     e3 -= sys.elems[sys.elem[A]].Gamma * qa[a] * qa[a] * qa[a] / 3.0;
   }
-  e2 = block_sum(e2, red);
-  e3 = block_sum(e3, red);
-  err = block_max(err, red);
+  e2 = block_sum_waves(e2, red);
+  e3 = block_sum_waves(e3, red);
+  err = block_max_waves(err, red);
   double e = eh + e2 + e3 + bt.mts[si] + bt.erep[si];
   int it = bt.niter[si] + 1;
   double de = fabs(e - bt.e_prev[si]);
@@ -1264,19 +1275,43 @@ __global__ void k_charges_mix(DevSystem sys, DevBatch bt, const int* list, doubl
     double* qn = bt.q_in + d.sh_off;
     for (int s = threadIdx.x; s < ns; s += blockDim.x) qn[s] = qi[s] + beta * (qo[s] - qi[s]);
   } else {
-    // B_ij = r_i . r_j (slots ordered oldest..newest)
+    // B_ij = r_i . r_j (slots ordered oldest..newest): every thread
+    // accumulates its part of all m (m + 1) / 2 products in one pass over the
+    // history, then a butterfly within each wave and the wave totals in order
     __shared__ double Bm[(HIST + 1) * (HIST + 1)];
     __shared__ double rhs[HIST + 1];
-    for (int pr = 0; pr < m * m; ++pr) {
-      int i = pr / m, j = pr % m;
-      int si_ = (nh - m + i) % HIST, sj_ = (nh - m + j) % HIST;
-      double loc = 0.0;
-      for (int s = threadIdx.x; s < ns; s += blockDim.x)
-        loc += hr[(long long)si_ * ns + s] * hr[(long long)sj_ * ns + s];
-      double v = block_sum(loc, red);
-      if (threadIdx.x == 0) Bm[i * (m + 1) + j] = v;
+    __shared__ double wsum[16][HIST * (HIST + 1) / 2];
+    constexpr int NPR = HIST * (HIST + 1) / 2;
+    double loc[NPR];
+#pragma unroll
+    for (int k = 0; k < NPR; ++k) loc[k] = 0.0;
+    for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+      double r[HIST];
+#pragma unroll
+      for (int i = 0; i < HIST; ++i) r[i] = i < m ? hr[(long long)((nh - m + i) % HIST) * ns + s] : 0.0;
+#pragma unroll
+      for (int i = 0, k = 0; i < HIST; ++i)
+#pragma unroll
+        for (int j = i; j < HIST; ++j, ++k) loc[k] = fma(r[i], r[j], loc[k]);
     }
+    const int wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NPR; ++k) {
+      double v = loc[k];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if ((threadIdx.x & 63) == 0) wsum[wv][k] = v;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+      for (int i = 0, k = 0; i < HIST; ++i)
+        for (int j = i; j < HIST; ++j, ++k) {
+          if (i >= m || j >= m) continue;
+          double v = 0.0;
+          for (int w = 0; w < nwv; ++w) v += wsum[w][k];
+          Bm[i * (m + 1) + j] = v;
+          Bm[j * (m + 1) + i] = v;
+        }
       int M = m + 1;
       double tr = 0.0;
       for (int i = 0; i < m; ++i) tr += Bm[i * M + i];
