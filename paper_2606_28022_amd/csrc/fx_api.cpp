@@ -604,9 +604,9 @@ void Ctx::build_precond(Batch& b) {
   if (!precond || !resp_ok || b.nsys == 0) return;
   int nsmax = 0;
   for (const auto& d : b.h_desc) nsmax = std::max(nsmax, d.nsh);
-  // the operand chunks of the product M G' (two KC x ns FP64 blocks,
-  // KC = min(16, max(1, ns / 4)), largest for the largest system)
-  const unsigned bytes = 16u * (unsigned)std::min(16, std::max(1, nsmax / 4)) * (unsigned)nsmax;
+  // K in FP32, and the operand chunks of its product (two KC x ns FP64
+  // blocks, KC = min(16, max(1, ns / 4))) in the same bytes
+  const unsigned bytes = std::max(4u * (unsigned)nsmax * (unsigned)nsmax, 16u * (unsigned)nsmax);
   if ((int)bytes > lds_max - 16384 || nsmax > PRE_MAXSH) return;
   b.pre.alloc(std::max(1LL, b.tot_gam));
   DevBuf<int> ok;

@@ -1578,24 +1578,22 @@ namespace fx {
 // susceptibilities M_I = sum_ai Q_ai Q_ai^T / (eps_a - eps_i) (the orbital
 // response of the response section, shell-summed) and G_X = gamma_XX minus
 // 2 Gamma_A dq_A on same-atom shell blocks at the system's input charges.
-// K is formed in FP64 and inverted by Gauss-Jordan with partial pivoting in
-// FP32 registers (the preconditioner only steers the mixer; the fixed point
-// does not depend on it).  ok[si] = 0 and the identity are written when a
-// pivot vanishes.
+// Gauss-Jordan inversion in place, in FP32 in LDS (the preconditioner only
+// steers the mixer; the fixed point does not depend on it).  ok[si] = 0 and
+// the identity are written when a pivot vanishes.
 __global__ void __launch_bounds__(1024)
     k_precond_build(DevSystem sys, DevBatch bt, const int* list, DevBatch mono, const double* Mmono, float* pre,
                     int* ok) {
-  // dynamic LDS: the operands of the product M G', staged in chunks of KC
-  // contraction indices
-  extern __shared__ double stage[];
+  // LDS: K (ns x ns, FP32); while K is formed, the same bytes stage the
+  // operands of the product M G' in chunks of KC contraction indices
+  extern __shared__ float Kf[];
   __shared__ double qa[MAXN];  // atom charges, then 2 Gamma_A dq_A per atom
-  __shared__ float rowp[MAXN];  // the pivot row of the current step
-  __shared__ int perm[MAXN];    // local atom of each shell while K is formed, then the pivot rows
-  __shared__ int inv[MAXN];
-  __shared__ float slot_a[16], slot_v[16];
-  __shared__ int slot_i[16];
+  __shared__ float colk[MAXN], rowk[MAXN];
+  __shared__ int perm[MAXN];   // local atom of each shell while K is formed
   __shared__ int comp_off[4], comp_mnsh[3];
   __shared__ long long comp_moff[3];
+  __shared__ int pivrow;
+  __shared__ float pivval;
   const int si = list[blockIdx.x];
   const SysDesc d = bt.desc[si];
   const int ns = d.nsh;
@@ -1628,7 +1626,7 @@ __global__ void __launch_bounds__(1024)
   const int* smap = bt.sh_mono + d.sh_off;
   const int KC = min(16, max(1, ns / 4));
   const int wave_u = __builtin_amdgcn_readfirstlane(wave);
-  double* Gs = stage;                          // [KC][ns]
+  double* Gs = reinterpret_cast<double*>(Kf);  // [KC][ns]
   double* Ms = Gs + KC * ns;                    // [ns][KC]
   double acc[PRE_ROWS][PRE_COLS];
 #pragma unroll
@@ -1669,106 +1667,92 @@ __global__ void __launch_bounds__(1024)
       }
     }
   }
-  // Gauss-Jordan inversion in place, K kept in FP32 registers in the same
-  // layout (rows s = wave + 16 r, columns t = lane + 64 c).  Partial
-  // pivoting without moving rows: the pivot of column k is the largest
-  // |K[i][k]| among the rows not yet used (lowest index on ties), row piv[k].
-  // Per step: each wave's lane holding column k proposes its best unused row
-  // (slot per wave), barrier; all threads take the best proposal, the owner
-  // wave publishes the pivot row, barrier; every thread updates its elements
-  // with the pivot row and the multipliers K[i][k] of its rows, read from the
-  // lane that holds column k.  At the end element (i, j) of the array is
-  // element (inv[i], piv[j]) of K^-1 (inv the inverse of piv).
-  float kf[PRE_ROWS][PRE_COLS];
+  __syncthreads();  // the staging area becomes K
 #pragma unroll
   for (int r = 0; r < PRE_ROWS; ++r)
 #pragma unroll
-    for (int c = 0; c < PRE_COLS; ++c) kf[r][c] = (float)acc[r][c];
-  unsigned used = 0u;  // rows r of this wave already taken as pivots (uniform in the wave)
+    for (int j = 0; j < PRE_COLS; ++j) {
+      const int s = wave + nw * r, t = lane + 64 * j;
+      if (s < ns && t < ns) Kf[s * ns + t] = (float)acc[r][j];
+    }
+  __syncthreads();
+  // Gauss-Jordan with partial pivoting (largest |K[i][k]|, i >= k, lowest
+  // index on ties), in place
   bool good = true;
   for (int k = 0; k < ns; ++k) {
-    const int lk = k & 63, ck = k >> 6;
-    if (lane == lk) {
-      float best = -1.0f, bv = 0.0f;
-      int bi = ns;
-#pragma unroll
-      for (int r = 0; r < PRE_ROWS; ++r) {
-        const int i = wave_u + nw * r;
-        const float v = ck == 0 ? kf[r][0] : ck == 1 ? kf[r][1] : kf[r][2];
-        if (i < ns && !((used >> r) & 1u) && fabsf(v) > best) {
-          best = fabsf(v);
-          bv = v;
+    if (wave == 0) {
+      float best = -1.0f;
+      int bi = k;
+      for (int i = k + lane; i < ns; i += 64) {
+        const float v = fabsf(Kf[i * ns + k]);
+        if (v > best) {
+          best = v;
           bi = i;
         }
       }
-      slot_a[wave_u] = best;
-      slot_v[wave_u] = bv;
-      slot_i[wave_u] = bi;
-    }
-    __syncthreads();
-    float best = -1.0f, pv = 0.0f;
-    int p = ns;
-    for (int w = 0; w < nw; ++w) {
-      const float a = slot_a[w];
-      const int i = slot_i[w];
-      if (a > best || (a == best && i < p)) {
-        best = a;
-        pv = slot_v[w];
-        p = i;
+      for (int off = 32; off >= 1; off >>= 1) {
+        const float ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        pivrow = bi;
+        perm[k] = bi;
+        pivval = best;
       }
     }
-    if (best < 1e-20f) {  // same value in every thread: uniform exit
+    __syncthreads();
+    const int p = pivrow;
+    if (pivval < 1e-20f) {  // same value in every thread: uniform exit
       good = false;
       break;
     }
-    const int wp = p % nw, rp = p / nw;
-    if (wave_u == wp) {
-#pragma unroll
-      for (int r = 0; r < PRE_ROWS; ++r)
-        if (r == rp) {
-#pragma unroll
-          for (int c = 0; c < PRE_COLS; ++c)
-            if (lane + 64 * c < ns) rowp[lane + 64 * c] = kf[r][c];
-        }
-      used |= 1u << rp;
+    if (p != k) {
+      for (int j = threadIdx.x; j < ns; j += blockDim.x) {
+        const float t = Kf[k * ns + j];
+        Kf[k * ns + j] = Kf[p * ns + j];
+        Kf[p * ns + j] = t;
+      }
+      __syncthreads();
     }
-    if (threadIdx.x == 0) perm[k] = p;
+    const float piv = Kf[k * ns + k];
+    for (int x = threadIdx.x; x < ns; x += blockDim.x) {
+      rowk[x] = (x == k ? 1.0f : Kf[k * ns + x]) / piv;
+      colk[x] = (x == k) ? 0.0f : Kf[x * ns + k];
+    }
     __syncthreads();
-    float rk[PRE_COLS];
-#pragma unroll
-    for (int c = 0; c < PRE_COLS; ++c) {
-      const int j = min(lane + 64 * c, ns - 1);
-      rk[c] = (j == k ? 1.0f : rowp[j]) / pv;
-    }
-#pragma unroll
-    for (int r = 0; r < PRE_ROWS; ++r) {
-      const float own = ck == 0 ? kf[r][0] : ck == 1 ? kf[r][1] : kf[r][2];
-      const float ci = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(own), lk));
-      const bool piv_row = wave_u + nw * r == p;
-#pragma unroll
-      for (int c = 0; c < PRE_COLS; ++c) {
-        const int j = lane + 64 * c;
-        kf[r][c] = piv_row ? rk[c] : (j == k ? 0.0f : kf[r][c]) - ci * rk[c];
+    for (int i = wave; i < ns; i += nw) {
+      float* row = Kf + i * ns;
+      if (i == k) {
+        for (int j = lane; j < ns; j += 64) row[j] = rowk[j];
+      } else {
+        const float ci = colk[i];
+        for (int j = lane; j < ns; j += 64) row[j] = (j == k ? 0.0f : row[j]) - ci * rowk[j];
       }
     }
+    __syncthreads();
   }
-  // stored transposed (element (s, t) of K^-1 at t ns + s), so that the
-  // products with it read consecutive addresses across threads
-  float* out = pre + d.gam_off;
   if (good) {
-    for (int k = threadIdx.x; k < ns; k += blockDim.x) inv[perm[k]] = k;
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < PRE_ROWS; ++r)
-#pragma unroll
-      for (int c = 0; c < PRE_COLS; ++c) {
-        const int i = wave_u + nw * r, j = lane + 64 * c;
-        if (i < ns && j < ns) out[perm[j] * ns + inv[i]] = kf[r][c];
-      }
-  } else {
-    for (int t = wave; t < ns; t += nw)
-      for (int s2 = lane; s2 < ns; s2 += 64) out[t * ns + s2] = s2 == t ? 1.0f : 0.0f;
+    // undo the row interchanges as column interchanges, last first
+    for (int k = ns - 1; k >= 0; --k) {
+      const int p = perm[k];
+      if (p != k)
+        for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+          const float t = Kf[i * ns + k];
+          Kf[i * ns + k] = Kf[i * ns + p];
+          Kf[i * ns + p] = t;
+        }
+      __syncthreads();
+    }
   }
+  // stored transposed (element (s, t) at t ns + s), so that the products
+  // with it read consecutive addresses across threads
+  float* out = pre + d.gam_off;
+  for (int t = wave; t < ns; t += nw)
+    for (int s = lane; s < ns; s += 64) out[t * ns + s] = good ? Kf[s * ns + t] : (s == t ? 1.0f : 0.0f);
   if (threadIdx.x == 0) ok[si] = good ? 1 : 0;
 }
 
