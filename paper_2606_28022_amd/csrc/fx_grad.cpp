@@ -190,6 +190,64 @@ void Ctx::gradient() {
     check(hipGetLastError(), "lagrangian potential");
   }
 
+  // ---- per-atom gather map (host side; built while the response kernels
+  // run when there is a response phase)
+  std::vector<int> rowptr, ent_b;
+  std::vector<long long> ent_o;
+  bool force_map_built = false;
+  auto build_force_map = [&]() {
+    rowptr.assign(N + 1, 0);
+    // a ghost (extended atom N + k) sits on the detached atom of bond k: its
+    // forces and CN sensitivity go to that atom's row.  Entries are listed
+    // in a fixed order and then sorted stably by row (a counting sort), so
+    // each row keeps that order and its sums are deterministic.
+    auto row_of = [&](int A) { return A < N ? A : bonds[2 * (A - N)]; };
+    struct Ent {
+      int row, b;
+      long long o;
+    };
+    std::vector<Ent> ents;
+    auto add = [&](int row, int id, long long o) { ents.push_back({row, id, o}); };
+    auto add_batch = [&](Batch& b, int id) {
+      const std::vector<int>& at = b.h_atoms;
+      for (int k = 0; k < b.nsys; ++k) {
+        const SysDesc& d = b.h_desc[k];
+        for (int a = 0; a < d.nat; ++a) add(row_of(at[d.atom_off + a]), id, d.atom_off + a);
+      }
+    };
+    add_batch(mb, 0);
+    if (nscc > 0) add_batch(db_, 1);
+    if (ntri > 0) add_batch(tb_, 2);
+    // opposite forces on the ghosts healed in the SCC dimers (batch 3)
+    for (long long e = 0; e < n_healed; ++e) {
+      const int t = db_.h_healed_sh[e];
+      const int G = (int)(std::upper_bound(atom_sh0_g.begin(), atom_sh0_g.end(), t) - atom_sh0_g.begin()) - 1;
+      add(row_of(G), 3, e);
+    }
+    // projector hybrid-coefficient forces (batch 4): attached atom, detached atom
+    auto add_hop = [&](const Batch& b, long long base) {
+      for (int e = 0; e < b.n_hop; ++e) {
+        const int kb = b.h_hop_bond[e];
+        add(bonds[2 * kb + 1], 4, 2 * (base + e));
+        add(bonds[2 * kb], 4, 2 * (base + e) + 1);
+      }
+    };
+    add_hop(mb, 0);
+    if (nscc > 0) add_hop(db_, n_hop_m);
+    if (opt.want_response && (nscc > 0 || ntri > 0)) add_hop(mb, n_hop_m + n_hop_d);
+    for (const Ent& e : ents) ++rowptr[e.row + 1];
+    for (int A = 0; A < N; ++A) rowptr[A + 1] += rowptr[A];
+    std::vector<int> pos(rowptr.begin(), rowptr.end() - 1);
+    ent_b.resize(ents.size());
+    ent_o.resize(ents.size());
+    for (const Ent& e : ents) {
+      const int k = pos[e.row]++;
+      ent_b[k] = e.b;
+      ent_o[k] = e.o;
+    }
+    force_map_built = true;
+  };
+
   // ---- response of the monomer charges (adjoint of the self-consistency)
   if (opt.want_response && (nscc > 0 || ntri > 0)) {
     const double tr = now_ms();
@@ -340,63 +398,13 @@ void Ctx::gradient() {
     hipLaunchKernelGGL(k_grad_contract, dim3(b.nsys), dim3(256), 0, stream, ds, dmb, b.d_list.p, G1.p, b.Fm.p, gx.p,
                        b.q_out.p, (const double*)nullptr, 0, 1, gm.p, Fm_.p, b.Tm.p);
     check(hipGetLastError(), "response gradient terms");
+    build_force_map();  // host work while the queued kernels run
     sync();
     res.ms_response = now_ms() - tr;
   }
 
   // ---- per-atom gather: F, CN chain, inter-fragment forces, fragment terms
-  std::vector<int> rowptr(N + 1, 0), ent_b;
-  std::vector<long long> ent_o;
-  {
-    // a ghost (extended atom N + k) sits on the detached atom of bond k: its
-    // forces and CN sensitivity go to that atom's row.  Entries are listed
-    // in a fixed order and then sorted stably by row (a counting sort), so
-    // each row keeps that order and its sums are deterministic.
-    auto row_of = [&](int A) { return A < N ? A : bonds[2 * (A - N)]; };
-    struct Ent {
-      int row, b;
-      long long o;
-    };
-    std::vector<Ent> ents;
-    auto add = [&](int row, int id, long long o) { ents.push_back({row, id, o}); };
-    auto add_batch = [&](Batch& b, int id) {
-      const std::vector<int>& at = b.h_atoms;
-      for (int k = 0; k < b.nsys; ++k) {
-        const SysDesc& d = b.h_desc[k];
-        for (int a = 0; a < d.nat; ++a) add(row_of(at[d.atom_off + a]), id, d.atom_off + a);
-      }
-    };
-    add_batch(mb, 0);
-    if (nscc > 0) add_batch(db_, 1);
-    if (ntri > 0) add_batch(tb_, 2);
-    // opposite forces on the ghosts healed in the SCC dimers (batch 3)
-    for (long long e = 0; e < n_healed; ++e) {
-      const int t = db_.h_healed_sh[e];
-      const int G = (int)(std::upper_bound(atom_sh0_g.begin(), atom_sh0_g.end(), t) - atom_sh0_g.begin()) - 1;
-      add(row_of(G), 3, e);
-    }
-    // projector hybrid-coefficient forces (batch 4): attached atom, detached atom
-    auto add_hop = [&](const Batch& b, long long base) {
-      for (int e = 0; e < b.n_hop; ++e) {
-        const int kb = b.h_hop_bond[e];
-        add(bonds[2 * kb + 1], 4, 2 * (base + e));
-        add(bonds[2 * kb], 4, 2 * (base + e) + 1);
-      }
-    };
-    add_hop(mb, 0);
-    if (nscc > 0) add_hop(db_, n_hop_m);
-    if (opt.want_response && (nscc > 0 || ntri > 0)) add_hop(mb, n_hop_m + n_hop_d);
-    for (const Ent& e : ents) ++rowptr[e.row + 1];
-    for (int A = 0; A < N; ++A) rowptr[A + 1] += rowptr[A];
-    std::vector<int> pos(rowptr.begin(), rowptr.end() - 1);
-    ent_b.resize(ents.size());
-    ent_o.resize(ents.size());
-    for (const Ent& e : ents) {
-      const int k = pos[e.row]++;
-      ent_b[k] = e.b;
-      ent_o[k] = e.o;
-    }
-  }
+  if (!force_map_built) build_force_map();
   DevBuf<int> d_rp, d_eb;
   DevBuf<long long> d_eo;
   d_rp.upload(rowptr);
