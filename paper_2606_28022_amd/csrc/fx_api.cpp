@@ -1032,6 +1032,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     b.nlog.alloc(b.nsys);
   }
   KernelTimer* kt_rot = kt(jp.elt == 8 ? "fx::k_jacobi_rot<double>" : "fx::k_jacobi_rot<float>");
+  const int sym_A = jp.elt != 0 ? 2 : 1;
   KernelTimer* kt_app = kt(apply_dual(b.max_nao) ? "fx::k_apply_rot_dual" : "fx::k_apply_rot");
   // mixed precision: FP32 Fock build and FP32 matrix-core products for this
   // iteration (the basis, the rotation angles, the charges and the
@@ -1062,8 +1063,9 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
       hipLaunchKernelGGL(k_fock, dim3(n64), dim3(256), 0, stream, ds, db, dl64);
       // A = C^T F C in the current basis, then Jacobi rotations
       gemm_batch(b, db, n64, dl64, 0, b.Ct.p, b.Fm.p, b.Tm.p, nullptr, b.gemm_gflop(a64), 1);
-      // A = (C^T F) C is symmetric: upper tiles only, mirrored
-      gemm_batch(b, db, n64, dl64, 1, b.Tm.p, b.Ct.p, b.Fm.p, nullptr, b.gemm_gflop_sym(a64), 1, 1);
+      // A = (C^T F) C is symmetric: upper tiles only, mirrored unless the
+      // eigensolver is an LDS kernel (those read the upper triangle only)
+      gemm_batch(b, db, n64, dl64, 1, b.Tm.p, b.Ct.p, b.Fm.p, nullptr, b.gemm_gflop_sym(a64), 1, sym_A);
     }
     if (split_ok && cap < 1e299) {
       const RotShape rs = rot_shape(b, db, dl, na, jp, cap, log_stride, timed);
@@ -1092,7 +1094,7 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
           dt = cold_list.p;
           hipLaunchKernelGGL(k_fock, dim3(nt), dim3(256), 0, stream, ds, db, dt);
           gemm_batch(b, db, nt, dt, 0, b.Ct.p, b.Fm.p, b.Tm.p, nullptr, 0.0, 1);
-          gemm_batch(b, db, nt, dt, 1, b.Tm.p, b.Ct.p, b.Fm.p, nullptr, 0.0, 1, 1);
+          gemm_batch(b, db, nt, dt, 1, b.Tm.p, b.Ct.p, b.Fm.p, nullptr, 0.0, 1, sym_A);
         }
         int ev = timed ? timers.begin(stream) : -1;
         launch_rot(b, db, dt, nt, jp.elt, cap, rs, cold_stride, jacobi_cold_log);

@@ -511,7 +511,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
   const int nt = (n + 63) / 64;
   if (tile >= nt * nt) return;
   const int ti = tile / nt, tj = tile - ti * nt;
-  // symmetric product: only the upper tiles, mirrored on store
+  // symmetric product: only the upper tiles, mirrored on store (sym 1) or
+  // not (sym 2: the consumer reads the upper triangle only)
   if (sym && ti > tj) return;
   const double* A = Abase + d.mat_off;
   const double* B = Bbase + d.mat_off;
@@ -664,7 +665,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
         const int gj = j0 + wj * 32 + v * 16 + (lane & 15);
         if (gi < n && gj < n) {
           C[(long long)gi * n + gj] = acc[u][v][r];
-          if (sym && ti < tj) C[(long long)gj * n + gi] = acc[u][v][r];
+          if (sym == 1 && ti < tj) C[(long long)gj * n + gi] = acc[u][v][r];
         }
       }
 }
