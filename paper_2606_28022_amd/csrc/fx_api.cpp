@@ -1128,7 +1128,9 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
     if (n32 > 0)
       gemm_batch_f32(b, db, n32, dl, 2, b.Ct.p, b.Ct.p, b.Pm.p, b.occ.p, b.gemm_gflop_occ(a32), 1, 1, true);
     if (n64 > 0)
-      gemm_batch(b, db, n64, dl64, 2, b.Ct.p, b.Ct.p, b.Pm.p, b.occ.p, b.gemm_gflop_occ(a64), 1, 1, true);
+      // (the upper tiles only: the mixer reads those; the lower ones are
+      // filled once the solve ends)
+      gemm_batch(b, db, n64, dl64, 2, b.Ct.p, b.Ct.p, b.Pm.p, b.occ.p, b.gemm_gflop_occ(a64), 1, 2, true);
     // a system converges only in an FP64 iteration
     const double beta = b.has_pre ? precond_beta : mix_beta;
     if (n32 > 0)
@@ -1343,6 +1345,11 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
   }
   if (gexec) (void)hipGraphExecDestroy(gexec);
   if (graph) (void)hipGraphDestroy(graph);
+  // the density's lower tiles (the iterations write the upper ones)
+  if (b.max_nao > 64) {
+    hipLaunchKernelGGL(k_mirror_tiles, dim3(nl), dim3(256), 0, stream, db, (const int*)b.d_list.p, b.Pm.p);
+    check(hipGetLastError(), "k_mirror_tiles");
+  }
   b.status.download(status, stream);
   b.niter.download(niter, stream);
   sync();

@@ -50,6 +50,7 @@ constexpr int PRE_ROWS = 12, PRE_COLS = 3, PRE_THREADS = 1024;
 constexpr int PRE_MAXSH = 16 * PRE_ROWS < 64 * PRE_COLS ? 16 * PRE_ROWS : 64 * PRE_COLS;
 __global__ void k_precond_build(DevSystem sys, DevBatch bt, const int* list, DevBatch mono, const double* Mmono,
                                 float* pre, int* ok);
+__global__ void k_mirror_tiles(DevBatch bt, const int* list, double* Abase);
 template <int MODE>
 __global__ void k_gemm_mfma(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double* Abase,
                             const double* Bbase, double* Cbase, const double* wbase, int skip_done, int sym,

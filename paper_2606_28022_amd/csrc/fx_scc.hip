@@ -677,6 +677,39 @@ template __global__ void k_gemm_mfma<1>(DevBatch, const int*, int, int, const do
 template __global__ void k_gemm_mfma<2>(DevBatch, const int*, int, int, const double*, const double*, double*,
                                         const double*, int, int, int);
 
+// Lower triangle of the listed systems' symmetric matrices from the upper
+// one, for the parts that a product with sym 2 leaves out: every element of
+// a 64 x 64 tile below the diagonal tiles (the diagonal tiles were computed
+// whole).  32 x 32 pieces pass through LDS so that reads and writes are
+// whole rows.
+__global__ void __launch_bounds__(256) k_mirror_tiles(DevBatch bt, const int* list, double* Abase) {
+  const int si = list[blockIdx.x];
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao;
+  double* A = Abase + d.mat_off;
+  __shared__ double tr[32][33];
+  const int nt = (n + 31) / 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int I = 0; I < nt; ++I)
+    for (int J = I + 1; J < nt; ++J) {
+      if ((I >> 1) == (J >> 1)) continue;  // inside one 64 x 64 diagonal tile
+      const int j = 32 * J + tx;
+#pragma unroll
+      for (int r = 0; r < 32; r += 8) {
+        const int i = 32 * I + r + ty;
+        if (i < n && j < n) tr[r + ty][tx] = A[(long long)i * n + j];
+      }
+      __syncthreads();
+      const int ic = 32 * I + tx;
+#pragma unroll
+      for (int r = 0; r < 32; r += 8) {
+        const int jr = 32 * J + r + ty;
+        if (jr < n && ic < n) A[(long long)jr * n + ic] = tr[tx][r + ty];
+      }
+      __syncthreads();  // before the next piece overwrites tr
+    }
+}
+
 // ---------------------------------------------------------------------------
 // The batched products of the mixed-precision form (early SCC iterations) on
 // the FP32 matrix cores: operands read in their storage precision (FP64
