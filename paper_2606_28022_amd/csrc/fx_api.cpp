@@ -476,8 +476,9 @@ void Ctx::init_device() {
                             lds_max);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_resp_M), hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds_max);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_precond_build),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_max - 16384);
+  for (const void* k : {reinterpret_cast<const void*>(k_precond_build<PRE_ROWS_SMALL>),
+                        reinterpret_cast<const void*>(k_precond_build<PRE_ROWS>)})
+    (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max - 16384);
   for (const void* k : {reinterpret_cast<const void*>(k_jacobi_rot<double>),
                         reinterpret_cast<const void*>(k_jacobi_rot<float>),
                         reinterpret_cast<const void*>(k_apply_rot),
@@ -606,14 +607,19 @@ void Ctx::build_precond(Batch& b) {
   for (const auto& d : b.h_desc) nsmax = std::max(nsmax, d.nsh);
   // K in FP32, and the operand chunks of its product (two KC x ns FP64
   // blocks, KC = min(16, max(1, ns / 4))) in the same bytes
-  const unsigned bytes = std::max(4u * (unsigned)nsmax * (unsigned)nsmax, 16u * (unsigned)nsmax);
+  const unsigned ldk = ((unsigned)nsmax + 3u) & ~3u;  // K rows padded to whole float4s
+  const unsigned bytes = std::max(4u * (unsigned)nsmax * ldk, 16u * (unsigned)nsmax);
   if ((int)bytes > lds_max - 16384 || nsmax > PRE_MAXSH) return;
   b.pre.alloc(std::max(1LL, b.tot_gam));
   DevBuf<int> ok;
   ok.alloc(b.nsys);
   DevBatch db = b.dev();
-  hipLaunchKernelGGL(k_precond_build, dim3(b.nsys), dim3(PRE_THREADS), bytes, stream, dev_system(), db, b.d_all.p,
-                     mb.dev(), (const double*)resp_M.p, b.pre.p, ok.p);
+  if (nsmax <= 16 * PRE_ROWS_SMALL)
+    hipLaunchKernelGGL(k_precond_build<PRE_ROWS_SMALL>, dim3(b.nsys), dim3(PRE_THREADS), bytes, stream, dev_system(),
+                       db, b.d_all.p, mb.dev(), (const double*)resp_M.p, b.pre.p, ok.p);
+  else
+    hipLaunchKernelGGL(k_precond_build<PRE_ROWS>, dim3(b.nsys), dim3(PRE_THREADS), bytes, stream, dev_system(), db,
+                       b.d_all.p, mb.dev(), (const double*)resp_M.p, b.pre.p, ok.p);
   check(hipGetLastError(), "k_precond_build");
   std::vector<int> h;
   ok.download(h, stream);

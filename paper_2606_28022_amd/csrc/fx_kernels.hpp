@@ -46,8 +46,11 @@ __global__ void k_gemm_f32(DevBatch bt, const int* list, int nl, int tiles_per_s
                            TC* Cbase, const double* wbase, int skip_done, int sym, int occ_list);
 // k_precond_build runs 1024 threads (16 waves); each thread holds PRE_ROWS x
 // PRE_COLS elements of K, so systems of up to 192 shells
-constexpr int PRE_ROWS = 12, PRE_COLS = 3, PRE_THREADS = 1024;
+// (ROWS = PRE_ROWS_SMALL for up to 16 PRE_ROWS_SMALL shells: fewer
+// accumulators, no register spills)
+constexpr int PRE_ROWS = 12, PRE_ROWS_SMALL = 9, PRE_COLS = 3, PRE_THREADS = 1024;
 constexpr int PRE_MAXSH = 16 * PRE_ROWS < 64 * PRE_COLS ? 16 * PRE_ROWS : 64 * PRE_COLS;
+template <int ROWS>
 __global__ void k_precond_build(DevSystem sys, DevBatch bt, const int* list, DevBatch mono, const double* Mmono,
                                 float* pre, int* ok);
 __global__ void k_mirror_tiles(DevBatch bt, const int* list, double* Abase);

@@ -1609,6 +1609,41 @@ template __global__ void k_jacobi_lds<float>(DevBatch, const int*, int, double, 
 
 namespace fx {
 
+// Maximum (minimum) over the wave, in every lane: DPP row shifts build the
+// row maxima in lane 15 of each row, row broadcasts carry them to lane 63.
+__device__ inline float wave_max_f32(float v) {
+#define FX_DPP_MAX(ctrl, rmask) \
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), ctrl, rmask, 0xf, false)))
+  FX_DPP_MAX(0x111, 0xf);
+  FX_DPP_MAX(0x112, 0xf);
+  FX_DPP_MAX(0x114, 0xf);
+  FX_DPP_MAX(0x118, 0xf);
+  FX_DPP_MAX(0x142, 0xa);
+  FX_DPP_MAX(0x143, 0xc);
+#undef FX_DPP_MAX
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+__device__ inline int wave_min_i32(int v) {
+#define FX_DPP_MIN(ctrl, rmask) v = min(v, __builtin_amdgcn_update_dpp(v, v, ctrl, rmask, 0xf, false))
+  FX_DPP_MIN(0x111, 0xf);
+  FX_DPP_MIN(0x112, 0xf);
+  FX_DPP_MIN(0x114, 0xf);
+  FX_DPP_MIN(0x118, 0xf);
+  FX_DPP_MIN(0x142, 0xa);
+  FX_DPP_MIN(0x143, 0xc);
+#undef FX_DPP_MIN
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+__device__ inline float f4_get(const float4& v, int c) { return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w; }
+__device__ inline void f4_set(float4& v, int c, float x) {
+  v.x = c == 0 ? x : v.x;
+  v.y = c == 1 ? x : v.y;
+  v.z = c == 2 ? x : v.z;
+  v.w = c == 3 ? x : v.w;
+}
+
 // ---------------------------------------------------------------------------
 // Mixing preconditioner of a cluster system X (1 to 3 fragments): the inverse
 // of K = 1 + M_X G_X, where M_X is block diagonal with the monomers' charge
@@ -1618,19 +1653,20 @@ namespace fx {
 // Gauss-Jordan inversion in place, in FP32 in LDS (the preconditioner only
 // steers the mixer; the fixed point does not depend on it).  ok[si] = 0 and
 // the identity are written when a pivot vanishes.
+template <int ROWS>
 __global__ void __launch_bounds__(1024)
     k_precond_build(DevSystem sys, DevBatch bt, const int* list, DevBatch mono, const double* Mmono, float* pre,
                     int* ok) {
   // LDS: K (ns x ns, FP32); while K is formed, the same bytes stage the
   // operands of the product M G' in chunks of KC contraction indices
-  extern __shared__ float Kf[];
+  extern __shared__ float4 Kf4_lds[];
+  float* Kf = reinterpret_cast<float*>(Kf4_lds);
   __shared__ double qa[MAXN];  // atom charges, then 2 Gamma_A dq_A per atom
-  __shared__ float colk[MAXN], rowk[MAXN];
+  __shared__ float4 rowk4[MAXN / 4];
+  __shared__ float colA[MAXN], colB[MAXN];
   __shared__ int perm[MAXN];   // local atom of each shell while K is formed
   __shared__ int comp_off[4], comp_mnsh[3];
   __shared__ long long comp_moff[3];
-  __shared__ int pivrow;
-  __shared__ float pivval;
   const int si = list[blockIdx.x];
   const SysDesc d = bt.desc[si];
   const int ns = d.nsh;
@@ -1665,9 +1701,9 @@ __global__ void __launch_bounds__(1024)
   const int wave_u = __builtin_amdgcn_readfirstlane(wave);
   double* Gs = reinterpret_cast<double*>(Kf);  // [KC][ns]
   double* Ms = Gs + KC * ns;                    // [ns][KC]
-  double acc[PRE_ROWS][PRE_COLS];
+  double acc[ROWS][PRE_COLS];
 #pragma unroll
-  for (int r = 0; r < PRE_ROWS; ++r)
+  for (int r = 0; r < ROWS; ++r)
 #pragma unroll
     for (int j = 0; j < PRE_COLS; ++j) acc[r][j] = (wave + nw * r == lane + 64 * j) ? 1.0 : 0.0;
   for (int u0 = 0; u0 < ns; u0 += KC) {
@@ -1697,7 +1733,7 @@ __global__ void __launch_bounds__(1024)
 #pragma unroll
       for (int j = 0; j < PRE_COLS; ++j) g[j] = Gs[uu * ns + min(lane + 64 * j, ns - 1)];
 #pragma unroll
-      for (int r = 0; r < PRE_ROWS; ++r) {
+      for (int r = 0; r < ROWS; ++r) {
         const double m = Ms[min(wave_u + nw * r, ns - 1) * kc + uu];
 #pragma unroll
         for (int j = 0; j < PRE_COLS; ++j) acc[r][j] = fma(m, g[j], acc[r][j]);
@@ -1705,69 +1741,98 @@ __global__ void __launch_bounds__(1024)
     }
   }
   __syncthreads();  // the staging area becomes K
+  // K rows padded to ldk (a multiple of 4, zeros beyond ns): whole float4s
+  const int ldk = (ns + 3) & ~3, ld4 = ldk >> 2;
+  float4* K4 = Kf4_lds;
 #pragma unroll
-  for (int r = 0; r < PRE_ROWS; ++r)
+  for (int r = 0; r < ROWS; ++r)
 #pragma unroll
     for (int j = 0; j < PRE_COLS; ++j) {
       const int s = wave + nw * r, t = lane + 64 * j;
-      if (s < ns && t < ns) Kf[s * ns + t] = (float)acc[r][j];
+      if (s < ns && t < ldk) Kf[s * ldk + t] = t < ns ? (float)acc[r][j] : 0.0f;
     }
   __syncthreads();
+  // the first pivot column, taken out of K (a pivot column is kept outside
+  // K and zero inside it: the update then leaves -c_i / pivot there)
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+    colA[i] = Kf[i * ldk];
+    Kf[i * ldk] = 0.0f;
+  }
+  __syncthreads();
   // Gauss-Jordan with partial pivoting (largest |K[i][k]|, i >= k, lowest
-  // index on ties), in place
+  // index on ties), in place.  Every wave finds the pivot itself from the
+  // pivot column (consecutive LDS words, wave reductions); the first ld4
+  // threads form the scaled pivot row and make the row interchange; then
+  // thread (cg, rg) updates float4 column group cg of rows rg, rg + ng, ...
+  // and collects column k + 1 of them, the next pivot column.  Two barriers
+  // per pivot.
+  constexpr int NG = PRE_THREADS / (4 * ROWS);    // fewest row groups (ns <= 16 ROWS)
+  constexpr int GJR = (16 * ROWS + NG - 1) / NG;  // most rows per thread
+  const int ng = blockDim.x / ld4;
+  const int cg = threadIdx.x % ld4, rg = threadIdx.x / ld4;
   bool good = true;
   for (int k = 0; k < ns; ++k) {
-    if (wave == 0) {
-      float best = -1.0f;
-      int bi = k;
-      for (int i = k + lane; i < ns; i += 64) {
-        const float v = fabsf(Kf[i * ns + k]);
-        if (v > best) {
-          best = v;
-          bi = i;
-        }
-      }
-      for (int off = 32; off >= 1; off >>= 1) {
-        const float ob = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
-      if (lane == 0) {
-        pivrow = bi;
-        perm[k] = bi;
-        pivval = best;
+    const float* colc = (k & 1) ? colB : colA;
+    float* coln = (k & 1) ? colA : colB;
+    float best = -1.0f;
+    int bi = 0x7fffffff;
+    for (int i = k + lane; i < ns; i += 64) {
+      const float v = fabsf(colc[i]);
+      if (v > best) {
+        best = v;
+        bi = i;
       }
     }
-    __syncthreads();
-    const int p = pivrow;
-    if (pivval < 1e-20f) {  // same value in every thread: uniform exit
+    const float pv = wave_max_f32(best);
+    const int p = wave_min_i32(best == pv ? bi : 0x7fffffff);
+    if (pv < 1e-20f) {  // same value in every wave: uniform exit
       good = false;
       break;
     }
-    if (p != k) {
-      for (int j = threadIdx.x; j < ns; j += blockDim.x) {
-        const float t = Kf[k * ns + j];
-        Kf[k * ns + j] = Kf[p * ns + j];
-        Kf[p * ns + j] = t;
-      }
-      __syncthreads();
-    }
-    const float piv = Kf[k * ns + k];
-    for (int x = threadIdx.x; x < ns; x += blockDim.x) {
-      rowk[x] = (x == k ? 1.0f : Kf[k * ns + x]) / piv;
-      colk[x] = (x == k) ? 0.0f : Kf[x * ns + k];
+    if ((int)threadIdx.x < ld4) {
+      const int c = threadIdx.x;
+      const float piv = colc[p];
+      float4 xp = K4[p * ld4 + c];
+      if (c == (k >> 2)) f4_set(xp, k & 3, 1.0f);
+      rowk4[c] = make_float4(xp.x / piv, xp.y / piv, xp.z / piv, xp.w / piv);
+      if (p != k) K4[p * ld4 + c] = K4[k * ld4 + c];
+      if (c == 0) perm[k] = p;
     }
     __syncthreads();
-    for (int i = wave; i < ns; i += nw) {
-      float* row = Kf + i * ns;
-      if (i == k) {
-        for (int j = lane; j < ns; j += 64) row[j] = rowk[j];
-      } else {
-        const float ci = colk[i];
-        for (int j = lane; j < ns; j += 64) row[j] = (j == k ? 0.0f : row[j]) - ci * rowk[j];
+    if (rg < ng) {
+      const float4 rk = rowk4[cg];
+      const float ck = colc[k];  // row p holds the former row k from now on
+      const int k1 = k + 1;
+      const bool collect = cg == (k1 >> 2);
+      float4 x[GJR];
+      float cr[GJR];
+#pragma unroll
+      for (int r = 0; r < GJR; ++r) {
+        const int i = rg + ng * r;
+        if (i < ns) {
+          x[r] = K4[i * ld4 + cg];
+          cr[r] = colc[i];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < GJR; ++r) {
+        const int i = rg + ng * r;
+        if (i < ns) {
+          float4 v = rk;
+          if (i != k) {
+            const float ci = i == p ? ck : cr[r];
+            v = x[r];
+            v.x = v.x - ci * rk.x;
+            v.y = v.y - ci * rk.y;
+            v.z = v.z - ci * rk.z;
+            v.w = v.w - ci * rk.w;
+          }
+          if (collect) {
+            coln[i] = f4_get(v, k1 & 3);
+            f4_set(v, k1 & 3, 0.0f);
+          }
+          K4[i * ld4 + cg] = v;
+        }
       }
     }
     __syncthreads();
@@ -1776,22 +1841,28 @@ __global__ void __launch_bounds__(1024)
     // undo the row interchanges as column interchanges, last first
     for (int k = ns - 1; k >= 0; --k) {
       const int p = perm[k];
-      if (p != k)
+      if (p != k) {  // (perm is shared: a uniform branch)
         for (int i = threadIdx.x; i < ns; i += blockDim.x) {
-          const float t = Kf[i * ns + k];
-          Kf[i * ns + k] = Kf[i * ns + p];
-          Kf[i * ns + p] = t;
+          const float t = Kf[i * ldk + k];
+          Kf[i * ldk + k] = Kf[i * ldk + p];
+          Kf[i * ldk + p] = t;
         }
-      __syncthreads();
+        __syncthreads();
+      }
     }
   }
   // stored transposed (element (s, t) at t ns + s), so that the products
   // with it read consecutive addresses across threads
   float* out = pre + d.gam_off;
   for (int t = wave; t < ns; t += nw)
-    for (int s = lane; s < ns; s += 64) out[t * ns + s] = good ? Kf[s * ns + t] : (s == t ? 1.0f : 0.0f);
+    for (int s = lane; s < ns; s += 64) out[t * ns + s] = good ? Kf[s * ldk + t] : (s == t ? 1.0f : 0.0f);
   if (threadIdx.x == 0) ok[si] = good ? 1 : 0;
 }
+
+template __global__ void k_precond_build<PRE_ROWS_SMALL>(DevSystem, DevBatch, const int*, DevBatch, const double*,
+                                                         float*, int*);
+template __global__ void k_precond_build<PRE_ROWS>(DevSystem, DevBatch, const int*, DevBatch, const double*, float*,
+                                                   int*);
 
 }  // namespace fx
 
