@@ -120,11 +120,6 @@ struct DevBatch {
 // rounding of any element that matters
 constexpr double OCC_MIN = 1e-30;
 
-// 1/sqrt(x) for positive finite x (the damped Coulomb kernels, where
-// x = R^2 + c^2 with c > 0): the hardware estimate y followed by one step of
-// the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ..., e = 1 - x y^2, which
-// triples the number of correct bits; no handling of zero, infinite or NaN
-// arguments, which these callers never pass.
 // gamma_st at distance R (Klopman-Ohno form, eta_st the harmonic mean)
 __device__ inline double gamma_pair(const DevGlobals& g, double R, double eta_s, double eta_t) {
   const double ie = 0.5 * (1.0 / eta_s + 1.0 / eta_t);
@@ -132,12 +127,47 @@ __device__ inline double gamma_pair(const DevGlobals& g, double R, double eta_s,
   return pow(pow(R, g.kg) + pow(ie, g.kg), -1.0 / g.kg);
 }
 
+// 1/sqrt(x) for positive finite x (the damped Coulomb kernels, where
+// x = R^2 + c^2 with c > 0): the hardware estimate y followed by one step of
+// the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ..., e = 1 - x y^2, which
+// triples the number of correct bits; no handling of zero, infinite or NaN
+// arguments, which these callers never pass.
 __device__ inline double rsqrt_pos(double x) {
   const double y = __builtin_amdgcn_rsq(x);
   const double e = fma(-x * y, y, 1.0);
   return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
+
+// Maximum (minimum) over a whole wave (every lane active), returned in every
+// lane: DPP row shifts leave each row's extreme in its lane 15, row
+// broadcasts carry those to lane 63.
+#define FX_WAVE_REDUCE(op, ctrl, rmask) v = op(v, dpp_as(v, __builtin_amdgcn_update_dpp(dpp_bits(v), dpp_bits(v), ctrl, rmask, 0xf, false)))
+#define FX_WAVE_REDUCE_ALL(op) \
+  FX_WAVE_REDUCE(op, 0x111, 0xf); \
+  FX_WAVE_REDUCE(op, 0x112, 0xf); \
+  FX_WAVE_REDUCE(op, 0x114, 0xf); \
+  FX_WAVE_REDUCE(op, 0x118, 0xf); \
+  FX_WAVE_REDUCE(op, 0x142, 0xa); \
+  FX_WAVE_REDUCE(op, 0x143, 0xc)
+__device__ inline int dpp_bits(int v) { return v; }
+__device__ inline int dpp_bits(float v) { return __float_as_int(v); }
+__device__ inline int dpp_as(int, int b) { return b; }
+__device__ inline float dpp_as(float, int b) { return __int_as_float(b); }
+__device__ inline float wave_max_f32(float v) {
+  FX_WAVE_REDUCE_ALL(fmaxf);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ inline int wave_min_i32(int v) {
+  FX_WAVE_REDUCE_ALL(min);
+  return __builtin_amdgcn_readlane(v, 63);
+}
+__device__ inline int wave_max_i32(int v) {
+  FX_WAVE_REDUCE_ALL(max);
+  return __builtin_amdgcn_readlane(v, 63);
+}
+#undef FX_WAVE_REDUCE_ALL
+#undef FX_WAVE_REDUCE
 
 // List slot and tile of work-group L in a launch of xcd_grid(nl, tps)
 // work-groups over nl systems of tps tiles each.  The dispatcher deals

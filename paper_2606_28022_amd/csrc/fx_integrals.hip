@@ -451,6 +451,37 @@ __device__ inline double wave_rol1(double v) {
                           __builtin_amdgcn_mov_dpp(lo, 0x134, 0xf, 0xf, true));
 }
 
+// One off-diagonal block pair (64 steps); OWN: some target and source atom
+// may share a fragment (such pairs add exactly +0)
+template <bool OWN>
+__device__ inline void field_block_pair(const double4* sa, const double4* sb, int lane, double xa, double ya, double za,
+                                        double ia0, double ia1, double qa0, double qa1, double fa, double& r0,
+                                        double& r1, double& c0, double& c1) {
+  for (int r = 0; r < 64; ++r) {
+    const int k = (lane + r) & 63;
+    const double4 a = sa[k], b = sb[k];
+    const double dx = xa - a.x, dy = ya - a.y, dz = za - a.z;
+    const double R2 = dx * dx + dy * dy + dz * dz;
+    const double t00 = ia0 + a.w, t01 = ia0 + b.x, t10 = ia1 + a.w, t11 = ia1 + b.x;
+    const double x00 = rsqrt_pos(R2 + t00 * t00), x01 = rsqrt_pos(R2 + t01 * t01);
+    const double x10 = rsqrt_pos(R2 + t10 * t10), x11 = rsqrt_pos(R2 + t11 * t11);
+    const double g0 = x00 * b.y + x01 * b.z, g1 = x10 * b.y + x11 * b.z;
+    const double h0 = x00 * qa0 + x10 * qa1, h1 = x01 * qa0 + x11 * qa1;
+    if (OWN) {
+      const bool own = b.w == fa;
+      r0 += own ? 0.0 : g0;
+      r1 += own ? 0.0 : g1;
+      c0 = wave_rol1(c0 + (own ? 0.0 : h0));
+      c1 = wave_rol1(c1 + (own ? 0.0 : h1));
+    } else {
+      r0 += g0;
+      r1 += g1;
+      c0 = wave_rol1(c0 + h0);
+      c1 = wave_rol1(c1 + h1);
+    }
+  }
+}
+
 __global__ void __launch_bounds__(64) k_field_sym(DevSystem sys, const double* q, int group, int ngmax,
                                                   double* rowpart, double* colpart) {
   const int N = sys.natoms;
@@ -480,9 +511,13 @@ __global__ void __launch_bounds__(64) k_field_sym(DevSystem sys, const double* q
       }
     }
   }
+  // fragments of the target block (absent atoms excluded)
+  const int fmin_t = wave_min_i32(fa >= 0.0 ? (int)fa : 0x7fffffff);
+  const int fmax_t = wave_max_i32(fa >= 0.0 ? (int)fa : -1);
   double r0 = 0.0, r1 = 0.0;
   for (int J = J0; J < J1; ++J) {
     __syncthreads();
+    int fmin_s, fmax_s;
     {
       const int B = 64 * J + lane;
       double4 a = make_double4(0.0, 0.0, 0.0, 0.5), b = make_double4(0.5, 0.0, 0.0, -2.0);
@@ -501,6 +536,8 @@ __global__ void __launch_bounds__(64) k_field_sym(DevSystem sys, const double* q
       }
       sa[lane] = a;
       sb[lane] = b;
+      fmin_s = wave_min_i32(b.w >= 0.0 ? (int)b.w : 0x7fffffff);
+      fmax_s = wave_max_i32(b.w >= 0.0 ? (int)b.w : -1);
     }
     __syncthreads();
     if (J == I) {
@@ -518,22 +555,11 @@ __global__ void __launch_bounds__(64) k_field_sym(DevSystem sys, const double* q
       }
     } else {
       double c0 = 0.0, c1 = 0.0;  // column sums of source atom (lane + r) mod 64
-      for (int r = 0; r < 64; ++r) {
-        const int k = (lane + r) & 63;
-        const double4 a = sa[k], b = sb[k];
-        const double dx = xa - a.x, dy = ya - a.y, dz = za - a.z;
-        const double R2 = dx * dx + dy * dy + dz * dz;
-        const double t00 = ia0 + a.w, t01 = ia0 + b.x, t10 = ia1 + a.w, t11 = ia1 + b.x;
-        const double x00 = rsqrt_pos(R2 + t00 * t00), x01 = rsqrt_pos(R2 + t01 * t01);
-        const double x10 = rsqrt_pos(R2 + t10 * t10), x11 = rsqrt_pos(R2 + t11 * t11);
-        const bool own = b.w == fa;
-        const double g0 = x00 * b.y + x01 * b.z, g1 = x10 * b.y + x11 * b.z;
-        const double h0 = x00 * qa0 + x10 * qa1, h1 = x01 * qa0 + x11 * qa1;
-        r0 += own ? 0.0 : g0;
-        r1 += own ? 0.0 : g1;
-        c0 = wave_rol1(c0 + (own ? 0.0 : h0));
-        c1 = wave_rol1(c1 + (own ? 0.0 : h1));
-      }
+      // blocks whose fragment ranges are disjoint share no fragment: no test
+      if (fmax_t < fmin_s || fmax_s < fmin_t)
+        field_block_pair<false>(sa, sb, lane, xa, ya, za, ia0, ia1, qa0, qa1, fa, r0, r1, c0, c1);
+      else
+        field_block_pair<true>(sa, sb, lane, xa, ya, za, ia0, ia1, qa0, qa1, fa, r0, r1, c0, c1);
       // lane holds the column sums of its own source atom 64 J + lane
       double* cp = colpart + ((long long)J * (J - 1) / 2 + I) * 128;
       cp[2 * lane] = c0;
