@@ -169,6 +169,25 @@ __device__ inline int wave_max_i32(int v) {
 #undef FX_WAVE_REDUCE_ALL
 #undef FX_WAVE_REDUCE
 
+// Sum over a whole wave (every lane active), returned in every lane: the same
+// tree, lanes without a source adding zero; a fixed order (deterministic)
+template <int CTRL, int RMASK>
+__device__ inline double dpp_or_zero(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, RMASK, 0xf, false),
+                          __builtin_amdgcn_update_dpp(0, lo, CTRL, RMASK, 0xf, false));
+}
+__device__ inline double wave_sum_f64(double v) {
+  v += dpp_or_zero<0x111, 0xf>(v);
+  v += dpp_or_zero<0x112, 0xf>(v);
+  v += dpp_or_zero<0x114, 0xf>(v);
+  v += dpp_or_zero<0x118, 0xf>(v);
+  v += dpp_or_zero<0x142, 0xa>(v);
+  v += dpp_or_zero<0x143, 0xc>(v);
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                          __builtin_amdgcn_readlane(__double2loint(v), 63));
+}
+
 // List slot and tile of work-group L in a launch of xcd_grid(nl, tps)
 // work-groups over nl systems of tps tiles each.  The dispatcher deals
 // consecutive work-group ids to the 8 XCDs in turn; slot s runs on XCD s % 8

@@ -322,6 +322,25 @@ __global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst
     dst[i] = (float)src[i];
 }
 
+// part[w ns + s] = the sum over wave w's share of t of M[t ns + s] x[t], for
+// s < ns (lanes: consecutive s, consecutive addresses; a wave's loads are
+// independent, so many are in flight).  The caller adds the shares in wave
+// order after a barrier.
+template <typename T, typename X>
+__device__ inline void matvec_wave_part(const T* M, const X* x, int ns, double* part) {
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, nwv = blockDim.x >> 6;
+  const int tq = (ns + nwv - 1) / nwv, t0 = wv * tq, t1 = min(ns, t0 + tq);
+  for (int s0 = 0; s0 < ns; s0 += 64) {
+    const int s = s0 + ln;
+    if (s < ns) {
+      double v = 0.0;
+#pragma unroll 8
+      for (int t = t0; t < t1; ++t) v += (double)M[(long long)t * ns + s] * x[t];
+      part[wv * ns + s] = v;
+    }
+  }
+}
+
 __global__ void k_fock(DevSystem sys, DevBatch bt, const int* list) {
   int si = list[blockIdx.x];
   if (bt.status[si] != 0) return;  // converged or failed: nothing to do
@@ -339,14 +358,19 @@ __global__ void k_fock(DevSystem sys, DevBatch bt, const int* list) {
     for (int k = 0; k < nsa; ++k) v += q[s0 + k];
     qa_s[a] = v;
   }
-  __syncthreads();
+  // per-wave transposition tiles of the F build; first the partial sums of
+  // the shell shifts
+  __shared__ double trw[4][32][33];
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, nwv = blockDim.x >> 6;
   const double* G = bt.gam + d.gam_off;
+  // (G q)_s = sum_t G_ts q_t (G stored exactly symmetric), by the waves'
+  // shares of t, added in order
+  matvec_wave_part(G, q, ns, &trw[0][0][0]);
+  __syncthreads();
   for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+    const double* part = &trw[0][0][0];
     double v = 0.0;
-    // G is stored exactly symmetric: column s is read (consecutive threads,
-    // consecutive addresses), several loads in flight
-#pragma unroll 8
-    for (int t = 0; t < ns; ++t) v += G[(long long)t * ns + s] * q[t];
+    for (int w = 0; w < nwv; ++w) v += part[w * ns + s];
     int a = bt.sys_sh_atom[d.sh_off + s];
     int A = bt.sys_atoms[d.atom_off + a];
     double Gam = sys.elems[sys.elem[A]].Gamma;
@@ -367,15 +391,20 @@ __global__ void k_fock(DevSystem sys, DevBatch bt, const int* list) {
   if (!Vh && blockDim.x == 256) {
     // H0 and S are stored exactly symmetric, so F is: only the upper 32 x 32
     // tiles are read, and each is written as itself and, through LDS, as its
-    // mirror tile (2 n^2 instead of 3 n^2 elements of HBM traffic)
-    __shared__ double tr[32][33];
+    // mirror tile (2 n^2 instead of 3 n^2 elements of HBM traffic).  The
+    // tiles are dealt to the waves in turn; a wave transposes its tile in its
+    // own LDS tile, so the waves never wait for each other (a tile's 32 loads
+    // per lane are in flight together)
+    double (*tr)[33] = trw[wv];
     const int nt = (n + 31) / 32;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 8 rows of a tile per pass
+    const int tx = ln & 31, ty = ln >> 5;  // 2 rows of a tile per pass
+    int tile = 0;
     for (int I = 0; I < nt; ++I)
-      for (int J = I; J < nt; ++J) {
+      for (int J = I; J < nt; ++J, ++tile) {
+        if ((tile & 3) != wv) continue;
         const int j = 32 * J + tx;
-#pragma unroll
-        for (int r = 0; r < 32; r += 8) {
+#pragma unroll 8
+        for (int r = 0; r < 32; r += 2) {
           const int i = 32 * I + r + ty;
           if (i < n && j < n) {
             const long long e = (long long)i * n + j;
@@ -385,14 +414,19 @@ __global__ void k_fock(DevSystem sys, DevBatch bt, const int* list) {
           }
         }
         if (I == J) continue;
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const int ic = 32 * I + tx;
-#pragma unroll
-        for (int r = 0; r < 32; r += 8) {
+#pragma unroll 8
+        for (int r = 0; r < 32; r += 2) {
           const int jr = 32 * J + r + ty;
           if (jr < n) Fm[(long long)jr * n + ic] = tr[tx][r + ty];
         }
-        __syncthreads();  // before the next tile overwrites tr
+        // (before the wave's next tile overwrites its LDS tile)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     return;
   }
@@ -1162,59 +1196,59 @@ __global__ void k_charges_mix(DevSystem sys, DevBatch bt, const int* list, doubl
   const double* P = bt.P + d.mat_off;
   const double* H = bt.H0 + d.mat_off;
   // AO populations (P S)_mu,mu = sum_nu P_mu,nu S_mu,nu and Tr(P H0).  P, S
-  // and H0 are symmetric: only the upper 32 x 32 tiles are read.  A diagonal
-  // tile adds its row sums to the populations of its rows; an off-diagonal
-  // tile (I, J) adds its row sums to those of the rows in I and its column
-  // sums to those of the columns in J, and counts twice in Tr(P H0).  Every
-  // sum is taken in a fixed order (deterministic).
+  // and H0 are symmetric: only the upper triangle is read, by rows (wave w
+  // takes rows w, w + 4, ...; lanes consecutive columns j >= i).  Element
+  // (i, j) adds to population i (a wave sum per row) and, off the diagonal,
+  // to population j (per-lane column sums, added over the waves in order at
+  // the end) and counts twice in Tr(P H0).  Every sum is taken in a fixed
+  // order (deterministic); no barrier inside the loop, so the loads of many
+  // rows are in flight together.
+  __shared__ double cpart[4 * MAXN];  // per-wave column sums, then matrix-vector partials
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63, nwv = blockDim.x >> 6;
   double eh = 0.0;
   {
-    __shared__ double colp[8][33];
-    for (int i = threadIdx.x; i < n; i += blockDim.x) pop[i] = 0.0;
-    __syncthreads();
-    const int nt = (n + 31) / 32;
-    // (256 threads: a half-wave per tile row, 8 rows per pass)
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    for (int I = 0; I < nt; ++I)
-      for (int J = I; J < nt; ++J) {
-        const int j = 32 * J + tx;
-        const double wh = I == J ? 1.0 : 2.0;
-        double rs[4], cs = 0.0;
+    constexpr int NC = MAXN / 64;
+    double colacc[NC];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int i = 32 * I + 8 * k + ty;
-          double x = 0.0;
-          if (i < n && j < n) {
-            const long long e = (long long)i * n + j;
-            const double pv = P[e];
-            x = pv * S[e];
-            eh += wh * (pv * H[e]);
-          }
-          rs[k] = x;
-          cs += x;
-        }
+    for (int c = 0; c < NC; ++c) colacc[c] = 0.0;
+    const int ncn = (n + 63) >> 6;
+    for (int i = wv; i < n; i += nwv) {
+      const long long ro = (long long)i * n;
+      const int c0 = i >> 6;
+      double rs = 0.0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-          for (int off = 16; off > 0; off >>= 1) rs[k] += __shfl_xor(rs[k], off, 32);
-        if (tx == 0)
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int i = 32 * I + 8 * k + ty;
-            if (i < n) pop[i] += rs[k];
-          }
-        if (I != J) {
-          colp[ty][tx] = cs;
-          __syncthreads();
-          if (ty == 0 && j < n) {
-            double c = 0.0;
-#pragma unroll
-            for (int t = 0; t < 8; ++t) c += colp[t][tx];
-            pop[j] += c;
+      for (int c = 0; c < NC; ++c) {
+        if (c >= c0 && c < ncn) {
+          const int j = 64 * c + ln;
+          if (j >= i && j < n) {
+            const double pv = P[ro + j];
+            const double x = pv * S[ro + j];
+            const double ph = pv * H[ro + j];
+            rs += x;
+            if (j == i) {
+              eh += ph;
+            } else {
+              eh += 2.0 * ph;
+              colacc[c] += x;
+            }
           }
         }
-        __syncthreads();
       }
+      rs = wave_sum_f64(rs);
+      if (ln == 0) pop[i] = rs;
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int j = 64 * c + ln;
+      if (j < n) cpart[wv * n + j] = colacc[c];
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      double v = pop[j];
+      for (int w = 0; w < nwv; ++w) v += cpart[w * n + j];
+      pop[j] = v;
+    }
+    __syncthreads();
   }
   eh = block_sum_waves(eh, red);
   // shell charges
@@ -1242,13 +1276,13 @@ __global__ void k_charges_mix(DevSystem sys, DevBatch bt, const int* list, doubl
   __syncthreads();
   // energy
   const double* G = bt.gam + d.gam_off;
+  // (G q)_s, G stored exactly symmetric: the waves' shares of t, added in order
+  matvec_wave_part(G, qo, ns, cpart);
+  __syncthreads();
   double e2 = 0.0, e3 = 0.0, err = 0.0;
   for (int s = threadIdx.x; s < ns; s += blockDim.x) {
     double v = 0.0;
-    // G is stored exactly symmetric: column s is read (consecutive threads,
-    // consecutive addresses), several loads in flight
-#pragma unroll 8
-    for (int t = 0; t < ns; ++t) v += G[(long long)t * ns + s] * qo[t];
+    for (int w = 0; w < nwv; ++w) v += cpart[w * ns + s];
     e2 += 0.5 * qo[s] * v;
     err = fmax(err, fabs(qo[s] - qi[s]));
   }
@@ -1286,10 +1320,11 @@ __global__ void k_charges_mix(DevSystem sys, DevBatch bt, const int* list, doubl
     const float* Pr = bt.pre + d.gam_off;
     for (int s = threadIdx.x; s < ns; s += blockDim.x) pop[s] = qo[s] - qi[s];
     __syncthreads();
+    matvec_wave_part(Pr, pop, ns, cpart);  // (stored transposed)
+    __syncthreads();
     for (int s = threadIdx.x; s < ns; s += blockDim.x) {
       double v = 0.0;
-#pragma unroll 8
-      for (int t = 0; t < ns; ++t) v += (double)Pr[(long long)t * ns + s] * pop[t];  // stored transposed
+      for (int w = 0; w < nwv; ++w) v += cpart[w * ns + s];
       hx[(long long)slot * ns + s] = qi[s];
       hr[(long long)slot * ns + s] = v;
     }
