@@ -881,10 +881,13 @@ void Ctx::eigh_hot(const std::vector<int>& nv, const double* A, double* w, doubl
   sync();
 }
 
-void Ctx::build_matrices(Batch& b) {
+void Ctx::build_matrices(Batch& b, bool from_mono) {
   if (b.has_hop) b.Vh.alloc(std::max(1LL, b.tot_mat));
   DevBatch db = b.dev();
-  hipLaunchKernelGGL(k_build_system, dim3(b.nsys), dim3(256), 0, stream, dev_system(), db, nullptr);
+  // clusters of a system without cut bonds copy their monomers' blocks (the
+  // monomer batch holds this geometry's matrices)
+  const int copy = from_mono && bonds.empty() && b.h_nfrag > 1 ? 1 : 0;
+  hipLaunchKernelGGL(k_build_system, dim3(b.nsys), dim3(256), 0, stream, dev_system(), db, nullptr, mb.dev(), copy);
   if (b.has_hop) hipLaunchKernelGGL(k_vhop, dim3(b.nsys), dim3(256), 0, stream, db, P.g.VHOP);
   check(hipGetLastError(), "k_build_system");
   // mixed precision: FP32 copies of H0 and S for the FP32 Fock builds
@@ -2083,7 +2086,7 @@ void Ctx::run(fx_result* out) {
     for (long long k = 0; k < nscc; ++k) cl[k] = {scc_pairs[2 * k], scc_pairs[2 * k + 1], -1};
     build_batch(db_, cl, 2);
     db_.init_from_mono = !db_.has_healed;
-    build_matrices(db_);
+    build_matrices(db_, true);
     DevBatch ddb = db_.dev();
     hipLaunchKernelGGL(k_cluster_phi, dim3(db_.nsys), dim3(128), 0, stream, dev_system(), ddb, d_phi.p, d_q.p);
     hipLaunchKernelGGL(k_gather_shell, dim3(db_.nsys), dim3(64), 0, stream, ddb, d_q.p, db_.q_in.p);
@@ -2157,7 +2160,7 @@ void Ctx::run(fx_result* out) {
     for (long long k = 0; k < ntri; ++k) cl[k] = {trimers[3 * k], trimers[3 * k + 1], trimers[3 * k + 2]};
     build_batch(tb_, cl, 3);
     tb_.init_from_mono = !tb_.has_healed;
-    build_matrices(tb_);
+    build_matrices(tb_, true);
     DevBatch dtb = tb_.dev();
     hipLaunchKernelGGL(k_cluster_phi, dim3(tb_.nsys), dim3(128), 0, stream, dev_system(), dtb, d_phi.p, d_q.p);
     hipLaunchKernelGGL(k_gather_shell, dim3(tb_.nsys), dim3(64), 0, stream, dtb, d_q.p, tb_.q_in.p);

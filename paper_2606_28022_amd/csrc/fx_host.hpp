@@ -511,7 +511,7 @@ struct Ctx {
   void hist_coef(const double* R, long long n, const Slots& sl, double* coef);
   void field(const double* d_q, double* d_phi, bool fp32 = false);
   void build_batch(Batch& b, const std::vector<std::array<int, 3>>& clusters, int nfrag_each);
-  void build_matrices(Batch& b);
+  void build_matrices(Batch& b, bool from_mono = false);
   void eigh_hot(const std::vector<int>& nv, const double* A, double* w, double* V, bool global_kernel = false);
   void init_device();
   // embedding field through the chunked pass into caller-given device

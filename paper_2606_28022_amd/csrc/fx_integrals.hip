@@ -193,10 +193,53 @@ __device__ inline double h0_prefactor(const DevGlobals& g, const DevElem& ea, in
   return g.KAB * kll * 0.5 * (ha + hb) * (1.0 + g.kEN * den * den) * Pi;
 }
 
+// S and H0 blocks of the atom pair (a, b), a != b, written in both
+// triangles; returns the pair's repulsion energy
+__device__ inline double pair_block(const DevSystem& sys, const DevBatch& bt, const SysDesc& d, int n,
+                                    const int* atoms, const int* aao, int a, int b, double* S, double* H) {
+  const int A = atoms[a], B = atoms[b];
+  const DevElem& ea = sys.elems[sys.elem[A]];
+  const DevElem& eb = sys.elems[sys.elem[B]];
+  const double Rx = sys.xyz[3 * A] - sys.xyz[3 * B];
+  const double Ry = sys.xyz[3 * A + 1] - sys.xyz[3 * B + 1];
+  const double Rz = sys.xyz[3 * A + 2] - sys.xyz[3 * B + 2];
+  const double R = sqrt(Rx * Rx + Ry * Ry + Rz * Rz);
+  double blk[MAXAO_EL][MAXAO_EL];
+  atom_pair_overlap(ea, eb, Rx, Ry, Rz, blk);
+  const int oa = aao[a], ob = aao[b];
+  double f[MAXSH_EL][MAXSH_EL];
+#pragma unroll
+  for (int sa = 0; sa < MAXSH_EL; ++sa)
+#pragma unroll
+    for (int sb = 0; sb < MAXSH_EL; ++sb)
+      f[sa][sb] =
+          (sa < ea.nsh && sb < eb.nsh) ? h0_prefactor(sys.g, ea, sa, sys.cn[A], eb, sb, sys.cn[B], R) : 0.0;
+#pragma unroll
+  for (int i = 0; i < MAXAO_EL; ++i)
+#pragma unroll
+    for (int j = 0; j < MAXAO_EL; ++j) {
+      if (i >= ea.nao || j >= eb.nao) continue;
+      const double sv = blk[i][j];
+      const double hv = f[i == 0 ? 0 : 1][j == 0 ? 0 : 1] * sv;
+      S[(long long)(oa + i) * n + ob + j] = sv;
+      S[(long long)(ob + j) * n + oa + i] = sv;
+      H[(long long)(oa + i) * n + ob + j] = hv;
+      H[(long long)(ob + j) * n + oa + i] = hv;
+    }
+  const double al = sqrt(ea.arep * eb.arep);
+  const double zs = bt.atom_zs ? bt.atom_zs[d.atom_off + a] * bt.atom_zs[d.atom_off + b] : 1.0;
+  return zs * ea.zeff * eb.zeff / R * exp(-al * pow(R, sys.g.kf));
+}
+
 // ---------------------------------------------------------------------------
 // per-system S, H0, gamma and repulsion; one work-group per system.
+// from_mono (clusters of fragments without cut bonds, whose components are
+// their monomers' atoms in the monomers' order): every block within one
+// component equals the monomer's (the same atom pairs, CN and shells), so it
+// is copied from the monomer batch, and only the pairs between components
+// are evaluated; the repulsion adds the monomers' own.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
-    k_build_system(DevSystem sys, DevBatch bt, const int* list) {
+    k_build_system(DevSystem sys, DevBatch bt, const int* list, DevBatch mono, int from_mono) {
   int si = list ? list[blockIdx.x] : blockIdx.x;
   const SysDesc d = bt.desc[si];
   const int n = d.nao;
@@ -206,69 +249,106 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
   const int* aao = bt.sys_atom_ao0 + d.atom_off;
   __shared__ double red[256];
   double erep = 0.0;
-  // diagonal atom blocks
-  for (int a = threadIdx.x; a < d.nat; a += blockDim.x) {
-    int A = atoms[a];
-    const DevElem& e = sys.elems[sys.elem[A]];
-    int o = aao[a];
-    for (int i = 0; i < e.nao; ++i)
-      for (int j = 0; j < e.nao; ++j) {
-        S[(long long)(o + i) * n + o + j] = (i == j) ? 1.0 : 0.0;
-        H[(long long)(o + i) * n + o + j] = 0.0;
+  const int nc = d.nfrag;
+  const bool copy = from_mono && nc > 1;
+  // component c: atoms ca[c] .., AOs co[c] .., shells csh[c] ..; the atom
+  // pairs between components as rectangles (rc1, rc2), c1 < c2, at pair
+  // offsets roff
+  __shared__ int ca[4], co[4], roff[4], rc1[3], rc2[3], nrect, cfrag[3], csh[4];
+  if (copy) {
+    if (threadIdx.x == 0) {
+      ca[0] = co[0] = 0;
+      const SysDesc* dp = bt.desc + si;  // (indexed in memory, not copied)
+      for (int c = 0; c < nc; ++c) {
+        cfrag[c] = dp->frag[c];
+        csh[c] = dp->comp_sh[c];
+        ca[c + 1] = ca[c] + mono.desc[cfrag[c]].nat;
+        co[c + 1] = co[c] + mono.desc[cfrag[c]].nao;
       }
-    for (int s = 0; s < e.nsh; ++s) {
-      double h = e.level[s] * (1.0 + e.kcn[s] * sys.cn[A]);
-      for (int k = 0; k < e.nao_sh[s]; ++k) H[(long long)(o + e.ao0[s] + k) * n + o + e.ao0[s] + k] = h;
+      csh[nc] = dp->comp_sh[nc];
+      int nr = 0;
+      roff[0] = 0;
+      for (int c1 = 0; c1 < nc; ++c1)
+        for (int c2 = c1 + 1; c2 < nc; ++c2) {
+          rc1[nr] = c1;
+          rc2[nr] = c2;
+          roff[nr + 1] = roff[nr] + (ca[c1 + 1] - ca[c1]) * (ca[c2 + 1] - ca[c2]);
+          ++nr;
+        }
+      nrect = nr;
+    }
+    __syncthreads();
+    for (int c = 0; c < nc; ++c) {
+      const SysDesc* md = mono.desc + cfrag[c];
+      const int m = md->nao, msh = md->nsh;
+      const double* mS = mono.S + md->mat_off;
+      const double* mH = mono.H0 + md->mat_off;
+      for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+        const int i = e / m, j = e - i * m;
+        const long long o = (long long)(co[c] + i) * n + co[c] + j;
+        S[o] = mS[e];
+        H[o] = mH[e];
+      }
+      const double* mG = mono.gam + md->gam_off;
+      double* G = bt.gam + d.gam_off;
+      const int s0 = csh[c];
+      for (int e = threadIdx.x; e < msh * msh; e += blockDim.x) {
+        const int i = e / msh, j = e - i * msh;
+        G[(long long)(s0 + i) * d.nsh + s0 + j] = mG[e];
+      }
+    }
+  } else {
+    // diagonal atom blocks
+    for (int a = threadIdx.x; a < d.nat; a += blockDim.x) {
+      int A = atoms[a];
+      const DevElem& e = sys.elems[sys.elem[A]];
+      int o = aao[a];
+      for (int i = 0; i < e.nao; ++i)
+        for (int j = 0; j < e.nao; ++j) {
+          S[(long long)(o + i) * n + o + j] = (i == j) ? 1.0 : 0.0;
+          H[(long long)(o + i) * n + o + j] = 0.0;
+        }
+      for (int s = 0; s < e.nsh; ++s) {
+        double h = e.level[s] * (1.0 + e.kcn[s] * sys.cn[A]);
+        for (int k = 0; k < e.nao_sh[s]; ++k) H[(long long)(o + e.ao0[s] + k) * n + o + e.ao0[s] + k] = h;
+      }
     }
   }
   // off-diagonal atom blocks: the unordered pairs a < b, row a holding
-  // pairs off(a) = a nat - a (a + 1) / 2 .. off(a + 1) - 1
-  const int nat = d.nat, np = nat * (nat - 1) / 2;
+  // pairs off(a) = a nat - a (a + 1) / 2 .. off(a + 1) - 1; with copied
+  // components, the pairs between components only
+  const int nat = d.nat, np = copy ? roff[nrect] : nat * (nat - 1) / 2;
   for (int idx = threadIdx.x; idx < np; idx += blockDim.x) {
-    const double c = 2.0 * nat - 1.0;
-    int a = (int)floor(0.5 * (c - sqrt(c * c - 8.0 * idx)));
-    a = max(0, min(a, nat - 2));
-    while (a > 0 && a * nat - a * (a + 1) / 2 > idx) --a;
-    while ((a + 1) * nat - (a + 1) * (a + 2) / 2 <= idx) ++a;
-    const int b = idx - (a * nat - a * (a + 1) / 2) + a + 1;
-    int A = atoms[a], B = atoms[b];
-    const DevElem& ea = sys.elems[sys.elem[A]];
-    const DevElem& eb = sys.elems[sys.elem[B]];
-    double Rx = sys.xyz[3 * A] - sys.xyz[3 * B];
-    double Ry = sys.xyz[3 * A + 1] - sys.xyz[3 * B + 1];
-    double Rz = sys.xyz[3 * A + 2] - sys.xyz[3 * B + 2];
-    double R = sqrt(Rx * Rx + Ry * Ry + Rz * Rz);
-    double blk[MAXAO_EL][MAXAO_EL];
-    atom_pair_overlap(ea, eb, Rx, Ry, Rz, blk);
-    int oa = aao[a], ob = aao[b];
-    double f[MAXSH_EL][MAXSH_EL];
-#pragma unroll
-    for (int sa = 0; sa < MAXSH_EL; ++sa)
-#pragma unroll
-      for (int sb = 0; sb < MAXSH_EL; ++sb)
-        f[sa][sb] = (sa < ea.nsh && sb < eb.nsh) ? h0_prefactor(sys.g, ea, sa, sys.cn[A], eb, sb, sys.cn[B], R)
-                                                  : 0.0;
-#pragma unroll
-    for (int i = 0; i < MAXAO_EL; ++i)
-#pragma unroll
-      for (int j = 0; j < MAXAO_EL; ++j) {
-        if (i >= ea.nao || j >= eb.nao) continue;
-        const double sv = blk[i][j];
-        const double hv = f[i == 0 ? 0 : 1][j == 0 ? 0 : 1] * sv;
-        S[(long long)(oa + i) * n + ob + j] = sv;
-        S[(long long)(ob + j) * n + oa + i] = sv;
-        H[(long long)(oa + i) * n + ob + j] = hv;
-        H[(long long)(ob + j) * n + oa + i] = hv;
-      }
-    double al = sqrt(ea.arep * eb.arep);
-    const double zs = bt.atom_zs ? bt.atom_zs[d.atom_off + a] * bt.atom_zs[d.atom_off + b] : 1.0;
-    erep += zs * ea.zeff * eb.zeff / R * exp(-al * pow(R, sys.g.kf));
+    int a, b;
+    if (copy) {
+      int k = 0;
+      while (idx >= roff[k + 1]) ++k;
+      const int w = ca[rc2[k] + 1] - ca[rc2[k]], loc = idx - roff[k];
+      a = ca[rc1[k]] + loc / w;
+      b = ca[rc2[k]] + loc % w;
+    } else {
+      const double c = 2.0 * nat - 1.0;
+      a = (int)floor(0.5 * (c - sqrt(c * c - 8.0 * idx)));
+      a = max(0, min(a, nat - 2));
+      while (a > 0 && a * nat - a * (a + 1) / 2 > idx) --a;
+      while ((a + 1) * nat - (a + 1) * (a + 2) / 2 <= idx) ++a;
+      b = idx - (a * nat - a * (a + 1) / 2) + a + 1;
+    }
+    erep += pair_block(sys, bt, d, n, atoms, aao, a, b, S, H);
   }
-  // gamma of the system's shells
+  // gamma of the system's shells (with copied components: between them)
   double* G = bt.gam + d.gam_off;
   const int* shg = bt.sys_sh_global + d.sh_off;
   for (int idx = threadIdx.x; idx < d.nsh * d.nsh; idx += blockDim.x) {
     int s = idx / d.nsh, t = idx - s * d.nsh;
+    if (copy) {
+      int cs = 0, ct = 0;
+      for (int c = 1; c < nc; ++c) {
+        cs += s >= csh[c];
+        ct += t >= csh[c];
+      }
+      if (cs == ct) continue;
+    }
     int gs = shg[s], gt = shg[t];
     int As = sys.sh_atom[gs], At = sys.sh_atom[gt];
     double dx = sys.xyz[3 * As] - sys.xyz[3 * At];
@@ -276,14 +356,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
     double dz = sys.xyz[3 * As + 2] - sys.xyz[3 * At + 2];
     G[idx] = gamma_fn(sys.g, dx * dx + dy * dy + dz * dz, sys.sh_eta[gs], sys.sh_eta[gt]);
   }
-  // deterministic reduction of the repulsion energy
+  // deterministic reduction of the repulsion energy (plus the copied
+  // components' own)
   red[threadIdx.x] = erep;
   __syncthreads();
   for (int w = blockDim.x / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) bt.erep[si] = red[0];
+  if (threadIdx.x == 0) {
+    double e = red[0];
+    if (copy)
+      for (int c = 0; c < nc; ++c) e += mono.erep[cfrag[c]];
+    bt.erep[si] = e;
+  }
 }
 
 // ---------------------------------------------------------------------------

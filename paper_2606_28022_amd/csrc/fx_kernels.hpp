@@ -11,7 +11,7 @@ namespace fx {
 __global__ void k_cn(DevSystem sys, int nchunk, double* part);
 __global__ void k_pair_contacts(DevSystem sys, const int* frag_atoms, const int* frag_off, int rule, double cut2,
                                 double lam2, double lam3, int8_t* flag);
-__global__ void k_build_system(DevSystem sys, DevBatch bt, const int* list);
+__global__ void k_build_system(DevSystem sys, DevBatch bt, const int* list, DevBatch mono, int from_mono);
 __global__ void k_field_partial(DevSystem sys, const double* q, int nchunk, double* part);
 __global__ void k_field_partial_f32(DevSystem sys, const double* q, int nchunk, double* part);
 __global__ void k_field_reduce(int nshells, int nchunk, const double* part, double* phi);
