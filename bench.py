@@ -25,9 +25,10 @@ MI355X_FP64_PEAK_TFLOPS = 78.6
 
 # HBM traffic of the dominant kernel on this workload, from two rocprofv3 PMC
 # passes (FETCH_SIZE scaled by 2 and WRITE_SIZE by 1, the factors a 1 GiB
-# device copy gives), bytes per launch; valid while the kernel is unchanged
-# (profiles/k_apply_rot_dual_pentacene_fmo2.md gives the commands)
-PMC_TRAFFIC_BYTES = {"fx::k_apply_rot_dual": 2.26e9 + 0.94e9, "fx::k_apply_rot": 0.12e9 + 0.06e9}
+# device copy gives), bytes per launch averaged over the launches of the
+# warm-up and the timed step; valid while the kernel and the SCC schedule are
+# unchanged (profiles/k_apply_rot_dual_pentacene_fmo2.md gives the commands)
+PMC_TRAFFIC_BYTES = {"fx::k_apply_rot_dual": 2.14e9 + 0.90e9, "fx::k_apply_rot": 0.14e9 + 0.06e9}
 
 
 def scc_iteration_work(n, n_occ):
