@@ -476,6 +476,8 @@ void Ctx::init_device() {
                             lds_max);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_resp_M), hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds_max);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_resp_R_lds), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds_max - 24576);
   for (const void* k : {reinterpret_cast<const void*>(k_precond_build<PRE_ROWS_SMALL>),
                         reinterpret_cast<const void*>(k_precond_build<PRE_ROWS>)})
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max - 16384);

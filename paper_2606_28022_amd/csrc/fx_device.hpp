@@ -177,6 +177,22 @@ __device__ inline double dpp_or_zero(double v) {
   return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, RMASK, 0xf, false),
                           __builtin_amdgcn_update_dpp(0, lo, CTRL, RMASK, 0xf, false));
 }
+template <int CTRL, int RMASK>
+__device__ inline double dpp_or_self(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, CTRL, RMASK, 0xf, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, CTRL, RMASK, 0xf, false));
+}
+__device__ inline double wave_max_f64(double v) {
+  v = fmax(v, dpp_or_self<0x111, 0xf>(v));
+  v = fmax(v, dpp_or_self<0x112, 0xf>(v));
+  v = fmax(v, dpp_or_self<0x114, 0xf>(v));
+  v = fmax(v, dpp_or_self<0x118, 0xf>(v));
+  v = fmax(v, dpp_or_self<0x142, 0xa>(v));
+  v = fmax(v, dpp_or_self<0x143, 0xc>(v));
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                          __builtin_amdgcn_readlane(__double2loint(v), 63));
+}
 __device__ inline double wave_sum_f64(double v) {
   v += dpp_or_zero<0x111, 0xf>(v);
   v += dpp_or_zero<0x112, 0xf>(v);

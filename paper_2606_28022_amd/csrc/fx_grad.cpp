@@ -306,7 +306,13 @@ void Ctx::gradient() {
                          G1.p, order.p, d_nocc.p, d_qoff.p, Q.p);
       hipLaunchKernelGGL(k_resp_M, dim3(b.nsys), dim3(256), resp_M_lds(b), stream, dmb, order.p, d_nocc.p, d_qoff.p, Q.p, M.p);
     }
-    hipLaunchKernelGGL(k_resp_R, dim3(b.nsys), dim3(256), 0, stream, ds, dmb, p_M, Wk.p, R.p);
+    int nsmax = 0;
+    for (const auto& dd : b.h_desc) nsmax = std::max(nsmax, dd.nsh);
+    const size_t rr_bytes = (size_t)nsmax * (size_t)((nsmax + 1) & ~1) * sizeof(double);
+    if (nsmax <= MAXN_RESP_LDS && (long long)rr_bytes <= lds_max - 24576)
+      hipLaunchKernelGGL(k_resp_R_lds, dim3(b.nsys), dim3(RR_THREADS), rr_bytes, stream, ds, dmb, p_M, R.p);
+    else
+      hipLaunchKernelGGL(k_resp_R, dim3(b.nsys), dim3(256), 0, stream, ds, dmb, p_M, Wk.p, R.p);
     check(hipGetLastError(), "response setup");
     // adjoint sweeps y = v + field_excl(u(y)), Anderson-accelerated
     DevBuf<double> yg, yng, hX, hR, hC, fu;

@@ -173,6 +173,9 @@ size_t resp_M_lds_bytes(int nsh);
 constexpr int RQ_CH = 16;        // AOs per staged run of k_resp_Q
 size_t resp_Q_lds_bytes(int n);  // dynamic LDS of k_resp_Q for systems of up to n AOs
 __global__ void k_resp_R(DevSystem sys, DevBatch bt, const double* M, double* Wk, double* R);
+// k_resp_R_lds: systems of at most MAXN_RESP_LDS shells (the matrix in LDS)
+constexpr int MAXN_RESP_LDS = 96, RR_THREADS = 512;
+__global__ void k_resp_R_lds(DevSystem sys, DevBatch bt, const double* M, double* R);
 __global__ void k_resp_apply(DevBatch bt, const double* R, const double* M, const double* y, double* w, double* u);
 __global__ void k_resp_Z(DevBatch bt, const int* order, const int* nocc, const long long* qoff, const double* Q,
                          const double* w, double* Zm, double* Ze);

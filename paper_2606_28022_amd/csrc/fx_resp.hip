@@ -282,6 +282,184 @@ __global__ void k_resp_R(DevSystem sys, DevBatch bt, const double* M, double* Wk
   }
 }
 
+// The same R for systems whose ns x ns matrix fits in LDS (ns even-padded
+// rows of double2): A = I + G' M with M read by column from HBM (consecutive
+// threads, consecutive t) and G' rows from LDS, then Gauss-Jordan in place
+// with partial pivoting (largest |A_ik|, i >= k, lowest index on ties), as
+// the mixing preconditioner's: every wave finds the pivot itself from the
+// pivot column, which is kept outside A (zero inside it, so the update leaves
+// -c_i / pivot there), the first ld2 threads form the scaled pivot row and
+// make the row interchange, thread (cg, rg) updates column pair cg of rows
+// rg, rg + ng, ... and collects the next pivot column; two barriers per pivot.
+// A singular A (pivot below 1e-300) leaves the identity.
+__global__ void __launch_bounds__(RR_THREADS) k_resp_R_lds(DevSystem sys, DevBatch bt, const double* M, double* R) {
+  extern __shared__ double2 A2[];  // [ns][ld2]
+  double* A = reinterpret_cast<double*>(A2);
+  __shared__ double gcor[MAXN];    // 2 Gamma_A dq_A of each shell's atom
+  __shared__ int shat[MAXN];       // local atom of each shell
+  __shared__ double colA[MAXN], colB[MAXN];
+  __shared__ double2 rowk2[MAXN / 2];
+  __shared__ int perm[MAXN];
+  const int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const int ns = d.nsh, ldk = (ns + 1) & ~1, ld2 = ldk >> 1;
+  const int lane = threadIdx.x & 63;
+  const double* G = bt.gam + d.gam_off;
+  const double* Mm = M + d.gam_off;
+  const double* q = bt.q_out + d.sh_off;
+  for (int a = threadIdx.x; a < d.nat; a += blockDim.x) {
+    const int s0 = bt.sys_atom_sh0[d.atom_off + a];
+    const int s1 = (a + 1 < d.nat) ? bt.sys_atom_sh0[d.atom_off + a + 1] : ns;
+    double v = 0.0;
+    for (int s = s0; s < s1; ++s) v += q[s];
+    const double c = 2.0 * sys.elems[sys.elem[bt.sys_atoms[d.atom_off + a]]].Gamma * v;
+    for (int s = s0; s < s1; ++s) {
+      gcor[s] = c;
+      shat[s] = a;
+    }
+  }
+  __syncthreads();
+  // G' into LDS (row-major, ldk)
+  for (int e = threadIdx.x; e < ns * ns; e += blockDim.x) {
+    const int s = e / ns, k = e - s * ns;
+    double g = G[e];
+    if (shat[s] == shat[k]) g -= gcor[s];
+    A[s * ldk + k] = g;
+  }
+  __syncthreads();
+  // A = I + G' M, each thread's elements in registers, then over G'
+  constexpr int EPT = (MAXN_RESP_LDS * MAXN_RESP_LDS + RR_THREADS - 1) / RR_THREADS;
+  double av[EPT];
+  const int ne = ns * ns;
+#pragma unroll
+  for (int r = 0; r < EPT; ++r) {
+    const int e = threadIdx.x + RR_THREADS * r;
+    double v = 0.0;
+    if (e < ne) {
+      const int s = e / ns, t = e - s * ns;
+      v = s == t ? 1.0 : 0.0;
+      const double* gr = A + s * ldk;
+#pragma unroll 8
+      for (int k = 0; k < ns; ++k) v += gr[k] * Mm[(long long)k * ns + t];
+    }
+    av[r] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < EPT; ++r) {
+    const int e = threadIdx.x + RR_THREADS * r;
+    if (e < ne) {
+      const int s = e / ns, t = e - s * ns;
+      A[s * ldk + t] = av[r];
+    }
+  }
+  for (int s = threadIdx.x; s < ns; s += blockDim.x)
+    if (ldk > ns) A[s * ldk + ns] = 0.0;  // the padding column
+  __syncthreads();
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+    colA[i] = A[i * ldk];
+    A[i * ldk] = 0.0;
+  }
+  __syncthreads();
+  // (fewest row groups: RR_THREADS / (MAXN_RESP_LDS / 2); most rows per thread)
+  constexpr int NGMIN = RR_THREADS / (MAXN_RESP_LDS / 2);
+  constexpr int RPT = (MAXN_RESP_LDS + NGMIN - 1) / NGMIN;
+  const int ng = blockDim.x / ld2;
+  const int cg = threadIdx.x % ld2, rg = threadIdx.x / ld2;
+  bool good = true;
+  for (int k = 0; k < ns; ++k) {
+    const double* colc = (k & 1) ? colB : colA;
+    double* coln = (k & 1) ? colA : colB;
+    double best = -1.0;
+    int bi = 0x7fffffff;
+    for (int i = k + lane; i < ns; i += 64) {
+      const double v = fabs(colc[i]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    const double pvv = wave_max_f64(best);
+    const int p = wave_min_i32(best == pvv ? bi : 0x7fffffff);
+    if (!(pvv >= 1e-300)) {  // same value in every wave: uniform exit
+      good = false;
+      break;
+    }
+    if ((int)threadIdx.x < ld2) {
+      const int c = threadIdx.x;
+      const double piv = colc[p];
+      double2 xp = A2[p * ld2 + c];
+      if (c == (k >> 1)) {
+        if (k & 1) xp.y = 1.0;
+        else xp.x = 1.0;
+      }
+      rowk2[c] = make_double2(xp.x / piv, xp.y / piv);
+      if (p != k) A2[p * ld2 + c] = A2[k * ld2 + c];
+      if (c == 0) perm[k] = p;
+    }
+    __syncthreads();
+    if (rg < ng) {
+      const double2 rk = rowk2[cg];
+      const double ck = colc[k];  // row p holds the former row k from now on
+      const int k1 = k + 1;
+      const bool collect = cg == (k1 >> 1);
+      double2 x[RPT];
+      double cr[RPT];
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int i = rg + ng * r;
+        if (i < ns) {
+          x[r] = A2[i * ld2 + cg];
+          cr[r] = colc[i];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int i = rg + ng * r;
+        if (i < ns) {
+          double2 v = rk;
+          if (i != k) {
+            const double ci = i == p ? ck : cr[r];
+            v = x[r];
+            v.x = v.x - ci * rk.x;
+            v.y = v.y - ci * rk.y;
+          }
+          if (collect) {
+            if (k1 & 1) {
+              coln[i] = v.y;
+              v.y = 0.0;
+            } else {
+              coln[i] = v.x;
+              v.x = 0.0;
+            }
+          }
+          A2[i * ld2 + cg] = v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (good) {
+    // undo the row interchanges as column interchanges, last first
+    for (int k = ns - 1; k >= 0; --k) {
+      const int p = perm[k];
+      if (p != k) {  // (perm is shared: a uniform branch)
+        for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+          const double t = A[i * ldk + k];
+          A[i * ldk + k] = A[i * ldk + p];
+          A[i * ldk + p] = t;
+        }
+        __syncthreads();
+      }
+    }
+  }
+  double* X = R + d.gam_off;
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    const int s = e / ns, t = e - s * ns;
+    X[e] = good ? A[s * ldk + t] : (s == t ? 1.0 : 0.0);
+  }
+}
+
 // w = R y,  u = -M w   (local shell vectors)
 __global__ void k_resp_apply(DevBatch bt, const double* R, const double* M, const double* y, double* w, double* u) {
   const int si = blockIdx.x;
