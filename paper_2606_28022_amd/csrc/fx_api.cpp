@@ -476,6 +476,8 @@ void Ctx::init_device() {
                             lds_max);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_resp_M), hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds_max);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_resp_M_mfma), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds_max);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_resp_R_lds), hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds_max - 24576);
   for (const void* k : {reinterpret_cast<const void*>(k_precond_build<PRE_ROWS_SMALL>),
@@ -556,6 +558,19 @@ unsigned Ctx::resp_M_lds(const Batch& b) const {
   return (unsigned)by;
 }
 
+// M = sum_ai Q_ai Q_ai^T / (eps_a - eps_i) of every system of the batch: on
+// the matrix cores where the shells fit, else the register-blocked kernel
+void Ctx::launch_resp_M(const Batch& b, const DevBatch& db, const int* order, const int* nocc, const long long* qoff,
+                        const double* Q, double* M) {
+  int nsh = 0;
+  for (const auto& d : b.h_desc) nsh = std::max(nsh, d.nsh);
+  const size_t bm = resp_M_mfma_lds_bytes(nsh);
+  if (nsh <= 16 * RMM_MAXB && (long long)bm <= (long long)lds_max)
+    hipLaunchKernelGGL(k_resp_M_mfma, dim3(b.nsys), dim3(256), (unsigned)bm, stream, db, order, nocc, qoff, Q, M);
+  else
+    hipLaunchKernelGGL(k_resp_M, dim3(b.nsys), dim3(256), resp_M_lds(b), stream, db, order, nocc, qoff, Q, M);
+}
+
 // Charge susceptibilities of the monomers from their current orbitals
 // (shell-summed transition charges Q and M = sum_ai Q Q^T / (eps_a - eps_i));
 // closed-shell monomers only (returns false otherwise).
@@ -593,8 +608,7 @@ bool Ctx::monomer_response_setup() {
   hipLaunchKernelGGL(k_resp_Q, dim3(b.nsys), dim3(256), (unsigned)resp_Q_lds_bytes(b.max_nao), stream, dev_system(),
                      dmb, b.Tm.p, resp_order.p,
                      resp_nocc.p, resp_qoff.p, resp_Q.p);
-  hipLaunchKernelGGL(k_resp_M, dim3(b.nsys), dim3(256), resp_M_lds(b), stream, dmb, resp_order.p, resp_nocc.p, resp_qoff.p,
-                     resp_Q.p, resp_M.p);
+  launch_resp_M(b, dmb, resp_order.p, resp_nocc.p, resp_qoff.p, resp_Q.p, resp_M.p);
   check(hipGetLastError(), "monomer susceptibilities");
   resp_ok = true;
   return true;

@@ -304,7 +304,7 @@ void Ctx::gradient() {
                  b.gemm_gflop_all());
       hipLaunchKernelGGL(k_resp_Q, dim3(b.nsys), dim3(256), (unsigned)resp_Q_lds_bytes(b.max_nao), stream, ds, dmb,
                          G1.p, order.p, d_nocc.p, d_qoff.p, Q.p);
-      hipLaunchKernelGGL(k_resp_M, dim3(b.nsys), dim3(256), resp_M_lds(b), stream, dmb, order.p, d_nocc.p, d_qoff.p, Q.p, M.p);
+      launch_resp_M(b, dmb, order.p, d_nocc.p, d_qoff.p, Q.p, M.p);
     }
     int nsmax = 0;
     for (const auto& dd : b.h_desc) nsmax = std::max(nsmax, dd.nsh);

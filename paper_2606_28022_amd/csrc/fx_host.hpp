@@ -436,6 +436,8 @@ struct Ctx {
   bool monomer_response_setup();
   // dynamic LDS of k_resp_M for a batch (throws when a system is too large)
   unsigned resp_M_lds(const Batch& b) const;
+  void launch_resp_M(const Batch& b, const DevBatch& db, const int* order, const int* nocc, const long long* qoff,
+                     const double* Q, double* M);
   void build_precond(Batch& b);
   // learned initial guess: FP32 master weights, Adam moments, bfloat16-rounded copy
   DevBuf<float> mlp_master, mlp_m, mlp_v, mlp_wr, mlp_grad, mlp_part, mlp_feat, mlp_out;

@@ -170,6 +170,11 @@ __global__ void k_resp_Q(DevSystem sys, DevBatch bt, const double* SCt, const in
 __global__ void k_resp_M(DevBatch bt, const int* order, const int* nocc, const long long* qoff, const double* Q,
                          double* M);
 size_t resp_M_lds_bytes(int nsh);
+// k_resp_M_mfma: systems of at most 16 RMM_MAXB shells
+constexpr int RMM_MAXB = 8;
+__global__ void k_resp_M_mfma(DevBatch bt, const int* order, const int* nocc, const long long* qoff, const double* Q,
+                              double* M);
+size_t resp_M_mfma_lds_bytes(int nsh);
 constexpr int RQ_CH = 16;        // AOs per staged run of k_resp_Q
 size_t resp_Q_lds_bytes(int n);  // dynamic LDS of k_resp_Q for systems of up to n AOs
 __global__ void k_resp_R(DevSystem sys, DevBatch bt, const double* M, double* Wk, double* R);

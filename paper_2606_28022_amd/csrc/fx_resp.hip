@@ -190,6 +190,94 @@ __global__ void __launch_bounds__(256) k_resp_M(DevBatch bt, const int* order, c
   }
 }
 
+// The same M on the FP64 matrix cores for systems of up to 16 RMM_MAXB
+// shells: the upper 16 x 16 blocks of M = (Q diag(w)) Q^T, dealt to the four
+// waves in turn, each accumulated with v_mfma_f64_16x16x4 over the staged
+// (a, i) chunks (rows padded to whole blocks with zeros, the chunk's tail
+// steps with zero weights), then written with their mirrors (on the
+// diagonal blocks the upper entries, so that M is exactly symmetric).
+typedef double rm_v4d __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_resp_M_mfma(DevBatch bt, const int* order, const int* nocc,
+                                                     const long long* qoff, const double* Q, double* M) {
+  const int si = blockIdx.x;
+  const SysDesc d = bt.desc[si];
+  const int n = d.nao, no = nocc[si], nv = n - no, ns = d.nsh;
+  const int* ord = order + d.ao_off;
+  const double* e = bt.eps + d.ao_off;
+  const long long K = (long long)nv * no;
+  const double* Qs = Q + qoff[si];
+  extern __shared__ double rm_lds[];
+  const int nb = (ns + 15) / 16, nrow = 16 * nb;
+  double* qt = rm_lds;                  // [nrow][RM_LD] (rows past ns zero)
+  double* idn = rm_lds + nrow * RM_LD;  // [RM_KC]
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nblk = nb * (nb + 1) / 2;
+  constexpr int QB = (RMM_MAXB * (RMM_MAXB + 1) / 2 + 3) / 4;  // blocks per wave, at most
+  int bsr[QB], bbr[QB];
+  rm_v4d acc[QB];
+  int nmine = 0;
+#pragma unroll
+  for (int q = 0; q < QB; ++q) {
+    acc[q] = (rm_v4d){0.0, 0.0, 0.0, 0.0};
+    const int blk = wave + 4 * q;
+    int bs = 0, rem = blk < nblk ? blk : 0;
+    while (rem >= nb - bs) {
+      rem -= nb - bs;
+      ++bs;
+    }
+    bsr[q] = bs;
+    bbr[q] = bs + rem;
+    nmine += blk < nblk;
+  }
+  const int i16 = lane & 15, kq = lane >> 4;
+  for (long long k0 = 0; k0 < K; k0 += RM_KC) {
+    const int kn = (int)((K - k0) < RM_KC ? (K - k0) : RM_KC);
+    __syncthreads();
+    for (int x = threadIdx.x; x < nrow * RM_KC; x += blockDim.x) {
+      const int sh = x / RM_KC, k = x - sh * RM_KC;
+      qt[sh * RM_LD + k] = (k < kn && sh < ns) ? Qs[(long long)sh * K + k0 + k] : 0.0;
+    }
+    for (int k = threadIdx.x; k < RM_KC; k += blockDim.x) {
+      double v = 0.0;
+      if (k < kn) {
+        const long long kk = k0 + k;
+        const int ap = (int)(kk / no), ip = (int)(kk - (long long)ap * no);
+        v = 1.0 / (e[ord[no + ap]] - e[ord[ip]]);
+      }
+      idn[k] = v;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < kn; kk += 4) {
+      const int k = kk + kq;
+      const double w = idn[k];
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        if (q < nmine) {
+          const double a = qt[(16 * bsr[q] + i16) * RM_LD + k] * w;
+          const double b = qt[(16 * bbr[q] + i16) * RM_LD + k];
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+        }
+      }
+    }
+  }
+  double* Mo = M + d.gam_off;
+#pragma unroll
+  for (int q = 0; q < QB; ++q) {
+    if (q >= nmine) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int s = 16 * bsr[q] + kq + 4 * r, t = 16 * bbr[q] + i16;
+      if (s >= ns || t >= ns || (bsr[q] == bbr[q] && t < s)) continue;
+      Mo[(long long)s * ns + t] = acc[q][r];
+      Mo[(long long)t * ns + s] = acc[q][r];
+    }
+  }
+}
+
+size_t resp_M_mfma_lds_bytes(int nsh) {
+  return ((size_t)(16 * ((nsh + 15) / 16)) * RM_LD + RM_KC) * sizeof(double);
+}
+
 // dynamic LDS of k_resp_M for systems of up to nsh shells
 size_t resp_M_lds_bytes(int nsh) { return ((size_t)(4 * ((nsh + 3) / 4)) * RM_LD + RM_KC) * sizeof(double); }
 
