@@ -501,7 +501,7 @@ void Ctx::init_device() {
 // the matrix-core kernel once a system spans more than one 32 x 32 tile.
 void Ctx::gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlist, int mode, const double* A,
                      const double* B, double* C, const double* w, double gflop, int skip_done, int sym,
-                     bool occ_list) {
+                     bool occ_list, int win) {
   if (nl <= 0) return;
   const bool timed = !capturing;
   if (b.max_nao <= 32) {
@@ -513,15 +513,21 @@ void Ctx::gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlis
     const long long grid = xcd_grid(nl, nt * nt);
     if (grid > 0x7fffffffLL) throw FxError(FX_E_INVALID, "batched product grid too large");
     const int ev = timed ? timers.begin(stream) : -1;
-    if (mode == 0)
-      hipLaunchKernelGGL(k_gemm_mfma<0>, dim3((unsigned)grid), dim3(256), 0, stream, db, dlist, nl, nt * nt, A, B, C,
-                         w, skip_done, sym, occ_list ? 1 : 0);
+    if (win && mode == 0)
+      hipLaunchKernelGGL((k_gemm_mfma<0, 1>), dim3((unsigned)grid), dim3(256), 0, stream, db, dlist, nl, nt * nt, A, B,
+                         C, w, skip_done, 0, 0);
+    else if (win && mode == 1)
+      hipLaunchKernelGGL((k_gemm_mfma<1, 1>), dim3((unsigned)grid), dim3(256), 0, stream, db, dlist, nl, nt * nt, A, B,
+                         C, w, skip_done, 0, 0);
+    else if (mode == 0)
+      hipLaunchKernelGGL((k_gemm_mfma<0, 0>), dim3((unsigned)grid), dim3(256), 0, stream, db, dlist, nl, nt * nt, A, B,
+                         C, w, skip_done, sym, occ_list ? 1 : 0);
     else if (mode == 1)
-      hipLaunchKernelGGL(k_gemm_mfma<1>, dim3((unsigned)grid), dim3(256), 0, stream, db, dlist, nl, nt * nt, A, B, C,
-                         w, skip_done, sym, occ_list ? 1 : 0);
+      hipLaunchKernelGGL((k_gemm_mfma<1, 0>), dim3((unsigned)grid), dim3(256), 0, stream, db, dlist, nl, nt * nt, A, B,
+                         C, w, skip_done, sym, occ_list ? 1 : 0);
     else
-      hipLaunchKernelGGL(k_gemm_mfma<2>, dim3((unsigned)grid), dim3(256), 0, stream, db, dlist, nl, nt * nt, A, B, C,
-                         w, skip_done, sym, occ_list ? 1 : 0);
+      hipLaunchKernelGGL((k_gemm_mfma<2, 0>), dim3((unsigned)grid), dim3(256), 0, stream, db, dlist, nl, nt * nt, A, B,
+                         C, w, skip_done, sym, occ_list ? 1 : 0);
     if (timed) timers.end(stream, ev, kt("fx::k_gemm_mfma"), gflop);
   }
   check(hipGetLastError(), "batched product");
@@ -977,28 +983,32 @@ int Ctx::run_scc(Batch& b, const std::vector<int>& list, bool cold, long long* i
       // C0 = blockdiag(monomer C); G = C0^T S C0 = L L^T; C = C0 L^-T
       hipLaunchKernelGGL(k_cluster_init_ct, dim3(nl), dim3(256), 0, stream, db, b.d_list.p, mb.dev(),
                          b.has_warm ? (const long long*)b.warm_off.p : nullptr);
-      gemm_batch(b, db, nl, b.d_list.p, 0, b.Ct.p, b.S.p, b.Tm.p, (const double*)nullptr, gf);
-      gemm_batch(b, db, nl, b.d_list.p, 1, b.Tm.p, b.Ct.p, b.Fm.p, (const double*)nullptr, gf, 0, 1);
+      // two-fragment clusters all started from their monomers: the factor
+      // of I - X^T X (half the order) gives the same inverse factor, and
+      // only the fragment-pair block X^T of G is formed
+      bool block2 = chol_elt == 4 && !b.has_warm;
+      int n1max = 0, n2max = 0;
+      for (int k = 0; block2 && k < nl; ++k) {
+        const SysDesc& sd = b.h_desc[list[k]];
+        if (sd.nfrag != 2) {
+          block2 = false;
+          break;
+        }
+        const int n1 = mb.h_desc[sd.frag[0]].nao;
+        n1max = std::max(n1max, n1);
+        n2max = std::max(n2max, sd.nao - n1);
+      }
+      block2 = block2 && (long long)cholinv_block2_lds_bytes(n1max, n2max) <= lds_max;
+      gemm_batch(b, db, nl, b.d_list.p, 0, b.Ct.p, b.S.p, b.Tm.p, (const double*)nullptr, gf, 0, 0, false,
+                 block2 ? 1 : 0);
+      gemm_batch(b, db, nl, b.d_list.p, 1, b.Tm.p, b.Ct.p, b.Fm.p, (const double*)nullptr, gf, 0, 1, false,
+                 block2 ? 1 : 0);
       if (chol_elt == 0) {
         cholinv(b.Fm.p, b.Tm.p);  // (k_cholinv uses Pm as its workspace)
         gemm_batch(b, db, nl, b.d_list.p, 0, b.Tm.p, b.Ct.p, b.Fm.p, (const double*)nullptr, gf);
         check(hipMemcpyAsync(b.Ct.p, b.Fm.p, sizeof(double) * b.tot_mat, hipMemcpyDeviceToDevice, stream), "copy");
       } else {
-        // two-fragment clusters all started from their monomers: the factor
-        // of I - X^T X (half the order) gives the same inverse factor
-        bool block2 = chol_elt == 4 && !b.has_warm;
-        int n1max = 0, n2max = 0;
-        for (int k = 0; block2 && k < nl; ++k) {
-          const SysDesc& sd = b.h_desc[list[k]];
-          if (sd.nfrag != 2) {
-            block2 = false;
-            break;
-          }
-          const int n1 = mb.h_desc[sd.frag[0]].nao;
-          n1max = std::max(n1max, n1);
-          n2max = std::max(n2max, sd.nao - n1);
-        }
-        if (block2 && (long long)cholinv_block2_lds_bytes(n1max, n2max) <= lds_max) {
+        if (block2) {
           const int ev = capturing ? -1 : timers.begin(stream);
           hipLaunchKernelGGL(k_cholinv_block2, dim3(nl), dim3(CHOL_THREADS_HOST),
                              (unsigned)cholinv_block2_lds_bytes(n1max, n2max), stream, db, b.d_list.p, mb.dev(),

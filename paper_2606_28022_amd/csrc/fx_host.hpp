@@ -559,7 +559,7 @@ struct Ctx {
   JacobiPlan autotune_jacobi(Batch& b, const int* dl, int na, const JacobiPlan& base, double cap);
   void gemm_batch(const Batch& b, const DevBatch& db, int nl, const int* dlist, int mode, const double* A,
                   const double* B, double* C, const double* w, double gflop, int skip_done = 0, int sym = 0,
-                  bool occ_list = false);
+                  bool occ_list = false, int win = 0);
   // the FP32 products of the mixed form (mode 0: double A, float B and C;
   // mode 1: float A, double B and C; mode 2: double A, B and C)
   void gemm_batch_f32(const Batch& b, const DevBatch& db, int nl, const int* dlist, int mode, const void* A,

@@ -54,7 +54,7 @@ template <int ROWS>
 __global__ void k_precond_build(DevSystem sys, DevBatch bt, const int* list, DevBatch mono, const double* Mmono,
                                 float* pre, int* ok);
 __global__ void k_mirror_tiles(DevBatch bt, const int* list, double* Abase);
-template <int MODE>
+template <int MODE, int WIN>
 __global__ void k_gemm_mfma(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double* Abase,
                             const double* Bbase, double* Cbase, const double* wbase, int skip_done, int sym,
                             int occ_list);

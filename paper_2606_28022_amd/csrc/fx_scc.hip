@@ -530,7 +530,14 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // only its own addressing, and every thread keeps 32-bit element offsets that
 // advance by one K slab per step (few registers, so several work-groups share
 // a CU and hide each other's load latency).
-template <int MODE>
+// WIN = 1 (modes 0 and 1, a two-fragment cluster whose basis rows are its
+// monomers' orbitals, block diagonal, the first fragment's AOs 0 .. n1 - 1):
+// only the output rows >= n1 and columns < n1 are needed (the fragment-pair
+// block of C0^T S C0), so the tiles without such elements are skipped, and K
+// runs over the second fragment's AOs in mode 0 (C0^T S: the other terms
+// are zeros of C0) and over the first fragment's in mode 1 ((C0^T S) C0^T^T,
+// the columns of the first factor that mode 0 formed).
+template <int MODE, int WIN>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
     k_gemm_mfma(DevBatch bt, const int* list, int nl, int tiles_per_sys, const double* __restrict__ Abase,
                 const double* __restrict__ Bbase, double* __restrict__ Cbase, const double* __restrict__ wbase,
@@ -548,6 +555,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
   // symmetric product: only the upper tiles, mirrored on store (sym 1) or
   // not (sym 2: the consumer reads the upper triangle only)
   if (sym && ti > tj) return;
+  int kbeg = 0, kend = n;
+  if (WIN) {
+    const int a1 = bt.sys_sh_atom[d.sh_off + d.comp_sh[1]];
+    const int n1 = bt.sys_atom_ao0[d.atom_off + a1];
+    if (ti * 64 + 64 <= n1 || tj * 64 >= n1) return;
+    if (MODE == 0) kbeg = (n1 / 32) * 32;
+    else kend = min(n, (n1 + 31) / 32 * 32);
+  }
   const double* A = Abase + d.mat_off;
   const double* B = Bbase + d.mat_off;
   double* C = Cbase + d.mat_off;
@@ -555,7 +570,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
   // mode 2 with occ_list: the sum runs over the orbitals listed by k_fermi
   // (occupation above OCC_MIN) instead of all n
   const bool use_list = MODE == 2 && occ_list;
-  const int nk = use_list ? bt.occ_cnt[si] : n;
+  if (use_list) kend = bt.occ_cnt[si];
+  const int nk = kend;
   constexpr int KS = 32, LD = 66;
   __shared__ double As[KS][LD];  // [k][i]
   __shared__ double Bs[KS][LD];  // [k][j]
@@ -612,6 +628,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
     b_step = KS * n;
     b_fix = j0 + kr < n;
   }
+  if (WIN) {  // start at K = kbeg (row-major operands: + kbeg, k-major: + kbeg rows)
+    a_off += MODE == 2 ? kbeg * n : kbeg;
+    b_off += MODE == 1 ? kbeg : kbeg * n;
+  }
   double ra[8], rb[8];
   auto fetch = [&](int k0) {
     if (MODE == 2 && use_list) {
@@ -632,24 +652,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
     for (int h = 0; h < 8; ++h) {
       if (MODE == 2) {
         const int gk = k0 + kk_ + 4 * h;
-        ra[h] = (a_fix && gk < n) ? A[a_off + h * a_hstep] * (w ? w[gk] : 1.0) : 0.0;
+        ra[h] = (a_fix && gk < nk) ? A[a_off + h * a_hstep] * (w ? w[gk] : 1.0) : 0.0;
       } else {
         const int gi = i0 + rr + 8 * h, gk = k0 + rk;
-        ra[h] = (gi < n && gk < n) ? A[a_off + h * a_hstep] : 0.0;
+        ra[h] = (gi < n && gk < nk) ? A[a_off + h * a_hstep] : 0.0;
       }
       if (MODE == 1) {
         const int gj = j0 + rr + 8 * h, gk = k0 + rk;
-        rb[h] = (gj < n && gk < n) ? B[b_off + h * b_hstep] : 0.0;
+        rb[h] = (gj < n && gk < nk) ? B[b_off + h * b_hstep] : 0.0;
       } else {
         const int gk = k0 + kk_ + 4 * h;
-        rb[h] = (b_fix && gk < n) ? B[b_off + h * b_hstep] : 0.0;
+        rb[h] = (b_fix && gk < nk) ? B[b_off + h * b_hstep] : 0.0;
       }
     }
     a_off += a_step;
     b_off += b_step;
   };
-  fetch(0);
-  for (int k0 = 0; k0 < nk; k0 += KS) {
+  fetch(kbeg);
+  for (int k0 = kbeg; k0 < nk; k0 += KS) {
 #pragma unroll
     for (int h = 0; h < 8; ++h) {
       if (MODE == 2)
@@ -704,12 +724,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
       }
 }
 
-template __global__ void k_gemm_mfma<0>(DevBatch, const int*, int, int, const double*, const double*, double*,
-                                        const double*, int, int, int);
-template __global__ void k_gemm_mfma<1>(DevBatch, const int*, int, int, const double*, const double*, double*,
-                                        const double*, int, int, int);
-template __global__ void k_gemm_mfma<2>(DevBatch, const int*, int, int, const double*, const double*, double*,
-                                        const double*, int, int, int);
+template __global__ void k_gemm_mfma<0, 0>(DevBatch, const int*, int, int, const double*, const double*, double*,
+                                           const double*, int, int, int);
+template __global__ void k_gemm_mfma<1, 0>(DevBatch, const int*, int, int, const double*, const double*, double*,
+                                           const double*, int, int, int);
+template __global__ void k_gemm_mfma<2, 0>(DevBatch, const int*, int, int, const double*, const double*, double*,
+                                           const double*, int, int, int);
+template __global__ void k_gemm_mfma<0, 1>(DevBatch, const int*, int, int, const double*, const double*, double*,
+                                           const double*, int, int, int);
+template __global__ void k_gemm_mfma<1, 1>(DevBatch, const int*, int, int, const double*, const double*, double*,
+                                           const double*, int, int, int);
 
 // Lower triangle of the listed systems' symmetric matrices from the upper
 // one, for the parts that a product with sym 2 leaves out: every element of
