@@ -155,18 +155,23 @@ __global__ void k_cluster_init_ct(DevBatch bt, const int* list, DevBatch mono, c
   const SysDesc d = bt.desc[si];
   const int n = d.nao;
   double* C = bt.Ct + d.mat_off;
-  for (long long i = threadIdx.x; i < (long long)n * n; i += blockDim.x) C[i] = 0.0;
-  __syncthreads();
-  int off = 0;
+  // fragment f's rows and columns: co[f] .. co[f + 1] - 1 (its monomer's C^T
+  // there, zeros elsewhere); a wave per row, lanes along it (every element
+  // written once, row segments coalesced)
+  int co[4] = {0, 0, 0, 0};
+  const double* Cm[3] = {nullptr, nullptr, nullptr};
   for (int f = 0; f < d.nfrag; ++f) {
-    const SysDesc m = mono.desc[d.frag[f]];
-    const double* Cm = mono.Ct + m.mat_off;
-    const int nm = m.nao;
-    for (long long idx = threadIdx.x; idx < (long long)nm * nm; idx += blockDim.x) {
-      int i = (int)(idx / nm), j = (int)(idx % nm);
-      C[(long long)(off + i) * n + off + j] = Cm[idx];
-    }
-    off += nm;
+    const SysDesc* m = mono.desc + d.frag[f];
+    Cm[f] = mono.Ct + m->mat_off;
+    co[f + 1] = co[f] + m->nao;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+  for (int i = wave; i < n; i += nwv) {
+    const int fi = (i >= co[1]) + (d.nfrag > 2 && i >= co[2]);
+    const int a = co[fi], nm = co[fi + 1] - a;
+    const double* src = Cm[fi] + (long long)(i - a) * nm;
+    double* dst = C + (long long)i * n;
+    for (int j = lane; j < n; j += 64) dst[j] = (j >= a && j < a + nm) ? src[j - a] : 0.0;
   }
 }
 
