@@ -577,7 +577,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
   const bool use_list = MODE == 2 && occ_list;
   if (use_list) kend = bt.occ_cnt[si];
   const int nk = kend;
-  constexpr int KS = 32, LD = 66;
+  constexpr int KS = 32, LD = 65;
   __shared__ double As[KS][LD];  // [k][i]
   __shared__ double Bs[KS][LD];  // [k][j]
   __shared__ int kxs[MODE == 2 ? MAXN : 1];  // the listed orbitals, staged once
